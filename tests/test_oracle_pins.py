@@ -1,0 +1,374 @@
+"""Pins of the CPU oracle against things other than itself.
+
+Each test names the fact it checks: a dense Kronecker construction, a
+textbook closed form, an exact invariant of the method, or a mathematical
+identity of the ansatz (Eqs. 2-5).  A plausible slip in the oracle (a
+dropped term, a wrong sign or index, a transposed operand) breaks at least
+one of them.
+"""
+import math
+
+import numpy as np
+import pytest
+import scipy.linalg
+
+from oracle import ansatz, closed_forms, dense, fermion, hamiltonian
+from paper_2402_17993_amd.inputs import make_integrals, make_thetas, uccsd_excitations
+
+
+def system(ns, ne, seed=0, order="interleaved"):
+    h1, h2 = make_integrals(ns, seed)
+    h, g = hamiltonian.spin_orbital_integrals(h1, h2, order)
+    return h1, h2, h, g
+
+
+def hf_mask(ne):
+    return (1 << ne) - 1
+
+
+def rand_state(n, seed):
+    r = np.random.default_rng(seed)
+    return r.normal(size=1 << n) + 1j * r.normal(size=1 << n)
+
+
+# ---------------------------------------------------------------- inputs
+
+def test_integrals_have_eq2_symmetries():
+    h1, h2 = make_integrals(5, 3)
+    assert np.array_equal(h1, h1.T)
+    for perm in [(1, 0, 2, 3), (0, 1, 3, 2), (2, 3, 0, 1), (3, 2, 1, 0)]:
+        np.testing.assert_allclose(h2, h2.transpose(perm), atol=1e-15)
+    for p in range(5):
+        for q in range(5):
+            assert h2[p, q, p, q] >= 0
+
+
+@pytest.mark.parametrize("n,ne,k", [(8, 4, 26), (12, 8, 92), (16, 8, 360), (18, 10, 560),
+                                    (24, 14, 1715), (26, 14, 2478)])
+def test_excitation_counts(n, ne, k):
+    exc = uccsd_excitations(n, ne)
+    assert exc.shape == (k, 4)
+    singles = exc[exc[:, 1] < 0]
+    assert np.all(singles[:, 0] < ne) and np.all(singles[:, 2] >= ne)
+    d = exc[exc[:, 1] >= 0]
+    assert np.all(d[:, 0] < d[:, 1]) and np.all(d[:, 2] < d[:, 3])
+
+
+# ---------------------------------------------------------------- ladder operators
+
+def test_ladder_matches_kronecker_construction():
+    n = 5
+    a, ad = dense.ladder_ops(n)
+    rng = np.random.default_rng(1)
+    psi = rand_state(n, 2)
+    for _ in range(20):
+        m = int(rng.integers(1, 5))
+        ops = [(int(rng.integers(0, n)), bool(rng.integers(0, 2))) for _ in range(m)]
+        M = np.eye(1 << n, dtype=complex)
+        for q, dag in ops:
+            M = M @ (ad[q] if dag else a[q])
+        got = fermion.apply_product(n, ops, psi)
+        np.testing.assert_allclose(got, M @ psi, atol=1e-13)
+
+
+def test_canonical_anticommutation():
+    n = 4
+    psi = rand_state(n, 5)
+    for p in range(n):
+        for q in range(n):
+            x = fermion.apply_product(n, [(p, False), (q, True)], psi)
+            x = fermion.apply_product(n, [(q, True), (p, False)], psi, 1.0, x)
+            np.testing.assert_allclose(x, psi if p == q else 0 * psi, atol=1e-14)
+            y = fermion.apply_product(n, [(p, False), (q, False)], psi)
+            y = fermion.apply_product(n, [(q, False), (p, False)], psi, 1.0, y)
+            np.testing.assert_allclose(y, 0 * psi, atol=1e-14)
+
+
+# ---------------------------------------------------------------- Hamiltonian (Eq. 2)
+
+def test_apply_h_matches_dense_and_literal():
+    _, _, h, g = system(3, 2, seed=4)
+    H = dense.hamiltonian_dense(h, g)
+    assert np.allclose(H, H.conj().T, atol=1e-13)
+    assert np.max(np.abs(H.imag)) == 0.0
+    psi = rand_state(6, 7)
+    ref = H @ psi
+    np.testing.assert_allclose(hamiltonian.apply_h_literal(h, g, psi), ref, atol=1e-12)
+    np.testing.assert_allclose(hamiltonian.apply_h(h, g, psi), ref, atol=1e-12)
+
+
+def test_one_electron_limit_is_orbital_energy_sum():
+    # With h2 = 0 and h1 diagonal, H|x> = (sum of occupied h_pp) |x>.
+    ns = 4
+    h1 = np.diag([-2.0, -1.0, 0.5, 1.25])
+    h, g = hamiltonian.spin_orbital_integrals(h1, np.zeros((ns,) * 4))
+    psi = rand_state(8, 3)
+    out = hamiltonian.apply_h(h, g, psi)
+    occ = (np.arange(256)[:, None] >> np.arange(8)) & 1
+    diag = occ @ np.repeat(np.diag(h1), 2)
+    np.testing.assert_allclose(out, diag * psi, atol=1e-13)
+
+
+# ---------------------------------------------------------------- P1: theta = 0
+
+@pytest.mark.parametrize("ns,ne", [(4, 4), (5, 6), (6, 4)])
+def test_p1_theta_zero_energy_and_gradient(ns, ne):
+    h1, h2, h, g = system(ns, ne, seed=ns)
+    n = 2 * ns
+    exc = uccsd_excitations(n, ne)
+    e, grad = ansatz.energy_and_gradient(h, g, n, hf_mask(ne), exc, np.zeros(len(exc)))
+    assert abs(e - closed_forms.hf_energy_spatial(h1, h2, ne)) < 1e-12
+    np.testing.assert_allclose(grad, closed_forms.gradient_at_zero(h, g, range(ne), exc),
+                               atol=1e-12)
+
+
+# ---------------------------------------------------------------- P2: variational bound
+
+def test_p2_energy_above_fci():
+    ns, ne = 4, 4
+    _, _, h, g = system(ns, ne)
+    n = 2 * ns
+    exc = uccsd_excitations(n, ne)
+    efci = dense.fci_energy(dense.hamiltonian_dense(h, g), n, ne)
+    for s in range(5):
+        th = make_thetas(len(exc), s, 0.8)
+        assert ansatz.energy(h, g, n, hf_mask(ne), exc, th) >= efci - 1e-12
+
+
+def test_p2_two_electron_ucc_reaches_fci():
+    ns, ne = 2, 2
+    _, _, h, g = system(ns, ne, seed=11)
+    n = 4
+    exc = uccsd_excitations(n, ne)
+    efci = dense.fci_energy(dense.hamiltonian_dense(h, g), n, ne)
+    best = np.inf
+    for s in range(8):
+        th = make_thetas(len(exc), 100 + s, 1.5)
+        for _ in range(400):
+            e, gr = ansatz.energy_and_gradient(h, g, n, hf_mask(ne), exc, th)
+            th = th - 0.3 * gr
+        best = min(best, e)
+    assert abs(best - efci) < 1e-9
+
+
+# ---------------------------------------------------------------- P3: one factor = expm
+
+def test_p3_factor_equals_dense_expm():
+    n, ne = 8, 4
+    exc = uccsd_excitations(n, ne)
+    psi = rand_state(n, 9)
+    for row in exc[[0, 3, 7, 8, 15, 25]]:
+        G = dense.generator_dense(n, row)
+        assert np.allclose(G @ G @ G, -G, atol=1e-14)
+        for t in (0.3, -1.1):
+            ref = scipy.linalg.expm(t * G) @ psi
+            got = ansatz.apply_factor(psi, ansatz.excitation_pairs(n, row), t)
+            np.testing.assert_allclose(got, ref, atol=1e-14)
+        np.testing.assert_allclose(ansatz.apply_generator(psi, ansatz.excitation_pairs(n, row)),
+                                   G @ psi, atol=1e-14)
+
+
+def test_trotter_state_matches_dense_product():
+    n, ne = 8, 4
+    exc = uccsd_excitations(n, ne)
+    th = make_thetas(len(exc), 1, 0.4)
+    np.testing.assert_allclose(ansatz.trotter_state(n, hf_mask(ne), exc, th),
+                               dense.trotter_state_dense(n, hf_mask(ne), exc, th), atol=1e-13)
+
+
+# ---------------------------------------------------------------- P4: Pauli form of a factor
+
+def test_p4_factor_is_product_of_commuting_pauli_exponentials():
+    n = 6
+    rows = [(0, -1, 4, -1), (1, -1, 5, -1), (0, 1, 4, 5), (0, 3, 4, 5), (0, 2, 3, 5)]
+    t = 0.37
+    for row in rows:
+        G = dense.generator_dense(n, row)
+        terms = dense.pauli_decompose(G)
+        nw = 2 if row[1] < 0 else 8
+        assert len(terms) == nw
+        mats = [dense.pauli_matrix(lab) for lab in terms]
+        for A in mats:
+            for B in mats:
+                assert np.allclose(A @ B, B @ A)
+        for c in terms.values():
+            assert abs(c.real) < 1e-15  # G anti-Hermitian: c = i t_k, t_k real
+        prod = np.eye(1 << n, dtype=complex)
+        for lab, c in terms.items():
+            prod = scipy.linalg.expm(t * c * dense.pauli_matrix(lab)) @ prod
+        np.testing.assert_allclose(prod, scipy.linalg.expm(t * G), atol=1e-13)
+
+
+# ---------------------------------------------------------------- P5: invariants
+
+def test_p5_invariants():
+    ns, ne = 5, 6
+    _, _, h, g = system(ns, ne)
+    n = 2 * ns
+    exc = uccsd_excitations(n, ne)
+    th = make_thetas(len(exc), 1, 0.3)
+    e, grad, st = ansatz.energy_and_gradient(h, g, n, hf_mask(ne), exc, th, return_states=True)
+    psi = st["psi"]
+    assert abs(np.linalg.norm(psi) - 1.0) < 1e-13
+    assert np.all(psi.imag == 0.0)
+    assert st["im_e"] == 0.0
+    ntot, two_sz = dense.number_and_sz(n)
+    outside = (ntot != ne) | (two_sz != 0)
+    assert np.all(psi[outside] == 0.0)
+    assert abs(np.sum(np.abs(psi) ** 2 * ntot) - ne) < 1e-12
+    back = st["psi_back"]
+    ref = ansatz.hf_state(n, hf_mask(ne))
+    assert np.max(np.abs(back - ref)) < 1e-13
+
+
+# ---------------------------------------------------------------- P6: orbital ordering
+
+def test_p6_blocked_ordering_same_energy():
+    ns, ne = 4, 4
+    h1, h2 = make_integrals(ns, 2)
+    n = 2 * ns
+    exc = uccsd_excitations(n, ne)
+    th = make_thetas(len(exc), 3, 0.3)
+    h, g = hamiltonian.spin_orbital_integrals(h1, h2, "interleaved")
+    e_int, g_int = ansatz.energy_and_gradient(h, g, n, hf_mask(ne), exc, th)
+    hb, gb = hamiltonian.spin_orbital_integrals(h1, h2, "blocked")
+    relabel = np.array([(q // 2) + (q % 2) * ns for q in range(n)])
+    exc_b = np.where(exc >= 0, relabel[np.maximum(exc, 0)], -1)
+    occ_b = sum(1 << int(relabel[q]) for q in range(ne))
+    e_blk, g_blk = ansatz.energy_and_gradient(hb, gb, n, occ_b, exc_b, th)
+    assert abs(e_int - e_blk) < 1e-12
+    np.testing.assert_allclose(g_int, g_blk, atol=1e-12)
+
+
+# ---------------------------------------------------------------- P7: orbital phase gauge
+
+def test_p7_orbital_sign_flip_is_a_gauge():
+    ns, ne = 4, 4
+    h1, h2 = make_integrals(ns, 5)
+    n = 2 * ns
+    exc = uccsd_excitations(n, ne)
+    th = make_thetas(len(exc), 6, 0.3)
+    h, g = hamiltonian.spin_orbital_integrals(h1, h2)
+    e0 = ansatz.energy(h, g, n, hf_mask(ne), exc, th)
+    for p in range(ns):
+        d = np.ones(ns)
+        d[p] = -1.0
+        h1f = d[:, None] * h1 * d[None, :]
+        h2f = np.einsum("a,b,c,d,abcd->abcd", d, d, d, d, h2)
+        hf_, gf_ = hamiltonian.spin_orbital_integrals(h1f, h2f)
+        touches = np.array([sum(1 for x in row if x >= 0 and x // 2 == p) for row in exc])
+        thf = th * np.where(touches % 2 == 1, -1.0, 1.0)
+        assert abs(ansatz.energy(hf_, gf_, n, hf_mask(ne), exc, thf) - e0) < 1e-12
+        # and a flip without the matching amplitude sign change does move E
+    assert abs(ansatz.energy(hf_, gf_, n, hf_mask(ne), exc, th) - e0) > 1e-8
+
+
+# ---------------------------------------------------------------- P8: size consistency
+
+def test_p8_non_interacting_fragments_add():
+    # Fragment A = spatial {0, 1}, fragment B = spatial {2, 3}; 2 electrons each.
+    r = np.random.default_rng(8)
+    ns = 4
+    h1 = np.zeros((ns, ns))
+    h2 = np.zeros((ns,) * 4)
+    blocks = [(0, 1), (2, 3)]
+    sub = []
+    for blk in blocks:
+        a1, a2 = make_integrals(2, int(r.integers(1000)))
+        ix = np.array(blk)
+        h1[np.ix_(ix, ix)] = a1
+        h2[np.ix_(ix, ix, ix, ix)] = a2
+        sub.append((a1, a2))
+    h, g = hamiltonian.spin_orbital_integrals(h1, h2)
+    exc_a = np.array([(0, -1, 2, -1), (1, -1, 3, -1), (0, 1, 2, 3)], dtype=np.int32)
+    exc_b = exc_a + 4 * (exc_a >= 0)
+    exc = np.concatenate([exc_a, exc_b])
+    th = make_thetas(6, 9, 0.5)
+    occ = 0b00110011
+    e_ab, g_ab = ansatz.energy_and_gradient(h, g, 8, occ, exc, th)
+    parts = []
+    for (a1, a2), t in zip(sub, (th[:3], th[3:])):
+        hs, gs = hamiltonian.spin_orbital_integrals(a1, a2)
+        parts.append(ansatz.energy_and_gradient(hs, gs, 4, 0b0011, exc_a, t))
+    assert abs(e_ab - (parts[0][0] + parts[1][0])) < 1e-12
+    np.testing.assert_allclose(g_ab, np.concatenate([parts[0][1], parts[1][1]]), atol=1e-12)
+
+
+# ---------------------------------------------------------------- P9: order is respected
+
+def test_p9_trotter_order():
+    ns, ne = 4, 4
+    _, _, h, g = system(ns, ne, seed=3)
+    n = 2 * ns
+    exc = uccsd_excitations(n, ne)
+    th = make_thetas(len(exc), 4, 0.5)
+    e0 = ansatz.energy(h, g, n, hf_mask(ne), exc, th)
+    supp = [set(int(x) for x in row if x >= 0) for row in exc]
+    disjoint = next(k for k in range(len(exc) - 1) if not (supp[k] & supp[k + 1]))
+    overlap = next(k for k in range(len(exc) - 1) if supp[k] & supp[k + 1])
+    for k, expect_same in ((disjoint, True), (overlap, False)):
+        perm = np.arange(len(exc))
+        perm[[k, k + 1]] = perm[[k + 1, k]]
+        e = ansatz.energy(h, g, n, hf_mask(ne), exc[perm], th[perm])
+        if expect_same:
+            assert abs(e - e0) < 1e-14
+        else:
+            assert abs(e - e0) > 1e-8
+
+
+# ---------------------------------------------------------------- P10, P11: gradient, shape
+
+def test_p10_gradient_shift_rule_and_finite_difference():
+    ns, ne = 4, 4
+    _, _, h, g = system(ns, ne, seed=1)
+    n = 2 * ns
+    exc = uccsd_excitations(n, ne)
+    pairs = ansatz.all_pairs(n, exc)
+    th = make_thetas(len(exc), 2, 0.3)
+    _, grad = ansatz.energy_and_gradient(h, g, n, hf_mask(ne), exc, th, pairs)
+
+    def E(t):
+        return ansatz.energy(h, g, n, hf_mask(ne), exc, t, pairs)
+
+    c = (math.sqrt(2.0) - 1.0) / 2.0
+    for k in range(len(exc)):
+        def sh(d):
+            t = th.copy()
+            t[k] += d
+            return E(t)
+        shift = (sh(math.pi / 4) - sh(-math.pi / 4)) - c * (sh(math.pi / 2) - sh(-math.pi / 2))
+        assert abs(shift - grad[k]) < 1e-12
+        fd = (sh(1e-4) - sh(-1e-4)) / 2e-4
+        assert abs(fd - grad[k]) < 1e-7
+
+
+def test_p11_energy_is_degree_two_trig_polynomial():
+    ns, ne = 4, 4
+    _, _, h, g = system(ns, ne, seed=2)
+    n = 2 * ns
+    exc = uccsd_excitations(n, ne)
+    pairs = ansatz.all_pairs(n, exc)
+    th = make_thetas(len(exc), 5, 0.3)
+    k = 17
+    xs = np.array([-1.3, -0.4, 0.2, 0.9, 1.7, 2.6])
+    es = []
+    for x in xs:
+        t = th.copy()
+        t[k] = x
+        es.append(ansatz.energy(h, g, n, hf_mask(ne), exc, t, pairs))
+    A = np.stack([np.ones_like(xs), np.cos(xs), np.sin(xs), np.cos(2 * xs), np.sin(2 * xs)], 1)
+    coef = np.linalg.solve(A[:5], np.array(es[:5]))
+    assert abs(A[5] @ coef - es[5]) < 1e-12
+
+
+# ---------------------------------------------------------------- steepest descent driver
+
+def test_steepest_descent_lowers_energy():
+    ns, ne = 4, 4
+    _, _, h, g = system(ns, ne)
+    n = 2 * ns
+    exc = uccsd_excitations(n, ne)
+    th0 = make_thetas(len(exc), 1, 0.1)
+    es, _ = ansatz.steepest_descent(h, g, n, hf_mask(ne), exc, th0, 20, 0.1)
+    assert es.shape == (21,)
+    assert np.all(np.diff(es) < 1e-12)
