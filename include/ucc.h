@@ -1,0 +1,240 @@
+/*
+ * ucc.h -- C ABI of the MI355X state-vector library for Trotterized UCCSD.
+ *
+ * What it computes (arXiv 2402.17993, Sec. 2.3):
+ *   H     = sum_pq h_pq a_p^dag a_q + 1/2 sum_pqrs g_pqrs a_p^dag a_q^dag a_s a_r   (Eq. 2)
+ *   |Psi> = U_K ... U_1 |HF>,  U_k = exp(theta_k (T_k - T_k^dag))                  (Eqs. 3-5, M = 1)
+ *   E     = <Psi|H|Psi>         (the VQE cost evaluated once per function evaluation)
+ *   dE/dtheta_k                 (adjoint reverse sweep; not in the paper, which uses
+ *                                gradient-free optimizers)
+ * with T_k = a_a^dag a_i (single) or a_a^dag a_b^dag a_j a_i (double, Eq. 4), mapped to
+ * qubits by Jordan-Wigner, state vector complex128 of 2^n amplitudes, all arithmetic FP64.
+ *
+ * Conventions
+ *   spin orbital q = 2p + sigma (sigma 0 = alpha, 1 = beta), p = spatial orbital;
+ *   Hartree-Fock reference occupies spin orbitals 0 .. n_elec-1;
+ *   g_pqrs = <pq|rs> = (pr|qs); h2 is passed in chemist order (pq|rs);
+ *   no constant energy (nuclear repulsion, frozen core) is added.
+ *
+ * Errors: every function returning ucc_status returns UCC_OK (0) or a negative code;
+ * a human-readable message for the last failure on the calling thread is returned by
+ * ucc_last_error().  Nothing aborts the process.
+ *
+ * Threading: a ucc_ctx is not thread-safe (one caller at a time); a ucc_server is.
+ */
+#ifndef UCC_H
+#define UCC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t ucc_status;
+
+enum {
+  UCC_OK = 0,
+  UCC_EINVAL = -1,    /* invalid argument or input that violates the stated contract */
+  UCC_ENOMEM = -2,    /* device allocation failed, or a footprint exceeds a budget */
+  UCC_EDEVICE = -3,   /* a HIP runtime call or a kernel reported an error */
+  UCC_EBUSY = -4,     /* serving queue is full */
+  UCC_ECANCELED = -5, /* job was cancelled */
+  UCC_ENOTFOUND = -6  /* unknown ticket */
+};
+
+typedef struct ucc_ctx ucc_ctx;       /* opaque: one Hamiltonian + excitation list + buffers */
+typedef struct ucc_server ucc_server; /* opaque: continuous-batching VQE server */
+
+/* Build options.  Zero means "choose automatically" unless stated otherwise. */
+typedef struct {
+  int32_t trotter_steps;     /* M of Eq. 5; only 1 is supported (0 is read as 1) */
+  int32_t tile_qubits;       /* k: local qubits per tile for one-vector passes (4..13) */
+  int32_t tile_qubits_rev;   /* k for two-vector passes (reverse sweep) (4..12) */
+  int32_t contiguous_qubits; /* lowest physical bits kept inside every tile (2..k-4) */
+  int32_t block_threads;     /* threads per workgroup: 256, 512 or 1024 */
+  int32_t max_batch;         /* theta vectors allocated up front (grows on demand) */
+  int32_t launch_mode;       /* 0 auto, 1 one kernel launch per pass, 2 persistent work queue */
+  int32_t host_only;         /* 1: plan on the host only (no device memory, no evaluation);
+                                for introspection and tests on machines without a GPU */
+  int32_t device;            /* HIP device ordinal; -1 = current device */
+  int32_t reserved[7];
+} ucc_options;
+
+/* Fill *opt with defaults (all automatic, launch_mode 0, max_batch 1). */
+void ucc_default_options(ucc_options* opt);
+
+/*
+ * ucc_build -- validate the inputs, map Eq. 2 to a Jordan-Wigner Pauli sum, group it by
+ * x-mask, compile the excitation list, plan fused passes, and (unless host_only) copy the
+ * tables to the device and allocate state buffers.
+ *
+ *   n_qubits  even, 4 <= n_qubits <= 30 (n_spatial = n_qubits / 2)
+ *   n_elec    even (closed shell), 2 <= n_elec < n_qubits
+ *   h1        host, [n_spatial * n_spatial] row-major, symmetric within 1e-12
+ *   h2        host, [n_spatial^4] row-major chemist (pq|rs), 8-fold symmetric within 1e-12
+ *   exc       host, [n_exc * 4] int32 rows (i, j, a, b) of spin-orbital indices in Trotter
+ *             order (Eq. 5); a single is (i, -1, a, -1); a double needs i < j occupied,
+ *             a < b virtual; every excitation must conserve S_z; no duplicate rows
+ *   n_exc     1 <= n_exc <= 65535
+ *   opt       nullable (defaults)
+ *   out       receives the new context; the caller owns it (ucc_destroy)
+ *
+ * Inputs are copied; the caller may free them on return.
+ * Errors: UCC_EINVAL (any violated condition above), UCC_ENOMEM, UCC_EDEVICE.
+ */
+ucc_status ucc_build(int32_t n_qubits, int32_t n_elec, const double* h1, const double* h2,
+                     const int32_t* exc, int32_t n_exc, const ucc_options* opt, ucc_ctx** out);
+
+/*
+ * ucc_energy -- E_b = <Psi(theta_b)|H|Psi(theta_b)> for b = 0..B-1 (Eqs. 2-5).
+ *
+ *   theta   [B * n_exc] float64, row b = amplitudes of vector b; host or device pointer
+ *   B       1 <= B <= 65535; buffers grow if B exceeds what the context holds
+ *   energy  [B] float64, host or device pointer (written when the call returns for host
+ *           pointers; stream-ordered for device pointers)
+ *   stream  hipStream_t to run on; NULL = the default stream
+ * After the call the context holds Psi(theta_b) (see ucc_get_state).
+ */
+ucc_status ucc_energy(ucc_ctx* ctx, const double* theta, int32_t B, double* energy, void* stream);
+
+/*
+ * ucc_energy_grad -- energies and gradients dE_b/dtheta_{b,k} by the adjoint method.
+ *
+ *   grad    [B * n_exc] float64, host or device pointer
+ * Other arguments as ucc_energy.  The reverse sweep returns the state buffer to |HF>, so
+ * after this call ucc_get_state reports |HF> (to rounding).
+ */
+ucc_status ucc_energy_grad(ucc_ctx* ctx, const double* theta, int32_t B, double* energy,
+                           double* grad, void* stream);
+
+/*
+ * ucc_get_state -- copy state vector b held by the context to the host, in the logical
+ * qubit order of this header (qubit q = bit q), as interleaved (re, im) pairs.
+ *   re_im  host, [2 * 2^n_qubits] float64
+ * Synchronizes the device.  Test and inspection hook.
+ */
+ucc_status ucc_get_state(ucc_ctx* ctx, int32_t b, double* re_im);
+
+/* Release everything the context owns.  NULL is accepted. */
+void ucc_destroy(ucc_ctx* ctx);
+
+/* Message for the last error on the calling thread ("" if none). */
+const char* ucc_last_error(void);
+
+/* ---------------------------------------------------------------- introspection */
+
+typedef struct {
+  int32_t n_qubits, n_elec, n_exc;
+  int32_t n_pauli;           /* Pauli strings of the JW Hamiltonian (after exact cancellation) */
+  int32_t n_groups;          /* distinct x-masks, the diagonal group included */
+  int32_t n_fwd_passes;      /* one-vector excitation passes (forward sweep) */
+  int32_t n_exp_passes;      /* expectation / apply-H passes */
+  int32_t n_rev_passes;      /* two-vector reverse-sweep passes */
+  int32_t tile_qubits, tile_qubits_rev;
+  int32_t contiguous_fwd, contiguous_exp, contiguous_rev;
+  int32_t block_threads, launch_mode;
+  int32_t perm[32];          /* physical bit of logical qubit q (q < n_qubits) */
+} ucc_plan_info;
+
+/* Sizes and choices made by ucc_build. */
+ucc_status ucc_get_plan_info(const ucc_ctx* ctx, ucc_plan_info* info);
+
+/*
+ * ucc_get_pauli_terms -- the Jordan-Wigner Pauli sum H = sum_t c_t P_t built from Eq. 2.
+ * P_t has X on the bits of x[t] & ~z[t], Y on x[t] & z[t], Z on z[t] & ~x[t] (logical
+ * qubits); c_t is real.  Arrays hold n_pauli entries (see ucc_get_plan_info); any may be NULL.
+ */
+ucc_status ucc_get_pauli_terms(const ucc_ctx* ctx, uint64_t* x, uint64_t* z, double* coef);
+
+/*
+ * ucc_get_group_table -- the compiled form of each x-group, used by the expectation kernels.
+ * For group g with x-mask x_g != 0 (physical bits), support pattern P of a basis state v
+ * (bit j of P = bit of v at the j-th lowest set bit of x_g),
+ *   <v ^ x_g| H |v> = (-1)^popcount(v & m_g) * (A_g[P] + sum_{r not in x_g} B_g[P][r] * n_r(v))
+ * for patterns P in valid_g, and 0 for all other patterns.  The diagonal group (x = 0) is
+ *   <v|H|v> = c0 + sum_r a_r n_r(v) + sum_{r<s} b_rs n_r(v) n_s(v).
+ *   xm, m      [n_groups] physical masks (group 0 is the diagonal group, xm = 0)
+ *   valid      [n_groups] 16-bit pattern masks
+ *   A          [n_groups * 16]
+ *   B          [n_groups * 16 * n_qubits]  (zeros where a group has no occupation terms)
+ *   diag       [1 + n_qubits + n_qubits * n_qubits] = c0, a[r], b[r * n + s] (physical)
+ * Any pointer may be NULL.
+ */
+ucc_status ucc_get_group_table(const ucc_ctx* ctx, uint32_t* xm, uint32_t* m, uint32_t* valid,
+                               double* A, double* B, double* diag);
+
+/*
+ * ucc_get_excitation_table -- per excitation k (physical bits): support mask, the pattern
+ * u & supp that T_k acts on, parity mask m_k and constant sign sigma_k, such that
+ * T_k|u> = sigma_k (-1)^popcount(u & m_k) |u ^ supp> whenever u & supp == from.
+ * Arrays of n_exc entries; any may be NULL.
+ */
+ucc_status ucc_get_excitation_table(const ucc_ctx* ctx, uint32_t* supp, uint32_t* from,
+                                    uint32_t* m, int32_t* sigma);
+
+/*
+ * ucc_get_pass_table -- the pass plan.  kind[p] 0 = forward, 1 = expectation/apply-H,
+ * 2 = reverse; local[p] = physical mask of the tile's local qubits; first/count index the
+ * excitation order (kinds 0 and 2, count items in application order) or the group list
+ * (kind 1) through items[].  Arrays sized n_fwd + n_exp + n_rev passes; items sized
+ * 2 * n_exc + n_groups.  Any pointer may be NULL.
+ */
+ucc_status ucc_get_pass_table(const ucc_ctx* ctx, int32_t* kind, uint32_t* local, int32_t* first,
+                              int32_t* count, int32_t* items);
+
+/* ---------------------------------------------------------------- serving */
+
+/*
+ * Continuous-batching server for steepest-descent VQE jobs (theta <- theta - lr * grad).
+ * A job is admitted when its device footprint (two complex128 state vectors of 2^n
+ * amplitudes plus partial-sum buffers) fits in hbm_budget_bytes and a slot is free; jobs
+ * that arrive while others run join the next device round.  Each round evaluates E and
+ * dE/dtheta for every active job in one batched launch sequence on the server's stream.
+ *
+ *   hbm_budget_bytes  device memory the server may hold for job state (0 = 64 GiB)
+ *   slots             maximum concurrently active jobs (1..4096)
+ *   max_queue         maximum queued (not yet admitted) jobs; beyond it ucc_submit
+ *                     returns UCC_EBUSY (0 = unlimited)
+ */
+ucc_status ucc_server_create(size_t hbm_budget_bytes, int32_t slots, int32_t max_queue,
+                             ucc_server** out);
+
+/*
+ * ucc_submit -- enqueue a VQE job on a built context (not host_only).  The server uses the
+ * context's plan and tables but its own state buffers; the context must outlive the job
+ * and must not be evaluated by the caller while the job runs.
+ *   theta0  host [n_exc] initial amplitudes (copied)
+ *   iters   steepest-descent steps (>= 0); the job records iters + 1 energies
+ *   lr      step size
+ *   flags   reserved, pass 0
+ *   ticket  receives the job id
+ */
+ucc_status ucc_submit(ucc_server* s, ucc_ctx* job, const double* theta0, int32_t iters, double lr,
+                      uint32_t flags, uint64_t* ticket);
+
+/*
+ * ucc_poll / ucc_wait -- job results.  energy_traj [iters + 1] and theta_out [n_exc] (host,
+ * nullable) are filled once the job is done (*done = 1).  timing (nullable, host [4]):
+ * submit->admit seconds, submit->done seconds, number of device rounds, 0.
+ * ucc_wait blocks until the job is done; both return the job's own status
+ * (e.g. UCC_ECANCELED) once it has finished.  A finished job is forgotten after a
+ * successful ucc_wait.
+ */
+ucc_status ucc_poll(ucc_server* s, uint64_t ticket, int32_t* done, double* energy_traj,
+                    double* theta_out, double* timing);
+ucc_status ucc_wait(ucc_server* s, uint64_t ticket, double* energy_traj, double* theta_out,
+                    double* timing);
+
+/* Cancel a queued or running job (it finishes with UCC_ECANCELED at the next round). */
+ucc_status ucc_cancel(ucc_server* s, uint64_t ticket);
+
+/* Stop the server thread after the running round and free its buffers. */
+void ucc_server_destroy(ucc_server* s);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* UCC_H */

@@ -1,0 +1,439 @@
+// C ABI of the UCCSD state-vector library (include/ucc.h): context lifetime, device
+// tables and buffers, and the launch sequence of one energy or energy+gradient call.
+#include <hip/hip_runtime_api.h>
+
+#include <algorithm>
+#include <cstring>
+#include <new>
+#include <string>
+
+#include "api_internal.h"
+#include "kernels.h"
+#include "ucc.h"
+
+namespace ucc {
+
+thread_local std::string g_last_error;
+
+ucc_status fail(ucc_status code, const std::string& msg) {
+  g_last_error = msg;
+  return code;
+}
+
+ucc_status hip_fail(hipError_t e, const char* what) {
+  g_last_error = std::string(what) + ": " + hipGetErrorString(e);
+  (void)hipGetLastError();
+  return e == hipErrorOutOfMemory ? UCC_ENOMEM : UCC_EDEVICE;
+}
+
+bool is_device_ptr(const void* p) {
+  hipPointerAttribute_t attr;
+  std::memset(&attr, 0, sizeof(attr));
+  const hipError_t e = hipPointerGetAttributes(&attr, p);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    return false;
+  }
+  return attr.type == hipMemoryTypeDevice || attr.type == hipMemoryTypeManaged ||
+         attr.type == hipMemoryTypeUnified;
+}
+
+namespace {
+
+template <typename T>
+hipError_t upload(T** dst, const std::vector<T>& src) {
+  *dst = nullptr;
+  const size_t bytes = std::max<size_t>(src.size(), 1) * sizeof(T);
+  hipError_t e = hipMalloc(reinterpret_cast<void**>(dst), bytes);
+  if (e != hipSuccess) return e;
+  if (!src.empty()) e = hipMemcpy(*dst, src.data(), src.size() * sizeof(T), hipMemcpyHostToDevice);
+  return e;
+}
+
+void free_ptr(void* p) {
+  if (p) (void)hipFree(p);
+}
+
+}  // namespace
+
+void free_buffers(Buffers& b) {
+  free_ptr(b.psi);
+  free_ptr(b.lam);
+  free_ptr(b.theta);
+  free_ptr(b.cs);
+  free_ptr(b.epart);
+  free_ptr(b.gpart);
+  free_ptr(b.E);
+  free_ptr(b.G);
+  b = Buffers();
+}
+
+ucc_status ensure_buffers(const ucc_ctx* c, Buffers& b, int B, bool need_lam) {
+  const Plan& p = c->plan;
+  const size_t S = size_t(1) << p.n;
+  if (B <= b.cap && (!need_lam || b.lam)) return UCC_OK;
+  hipError_t e = hipDeviceSynchronize();
+  if (e != hipSuccess) return hip_fail(e, "hipDeviceSynchronize");
+  const int cap = std::max(B, b.cap);
+  const bool lam = need_lam || b.lam != nullptr;
+  free_buffers(b);
+  b.cap = cap;
+  const size_t nte = size_t(1) << (p.n - p.kf);
+  const size_t ntr = size_t(1) << (p.n - p.kr);
+  struct Req {
+    void** ptr;
+    size_t bytes;
+  } reqs[] = {
+      {reinterpret_cast<void**>(&b.psi), cap * S * 16},
+      {reinterpret_cast<void**>(&b.theta), cap * size_t(p.K) * 8},
+      {reinterpret_cast<void**>(&b.cs), cap * size_t(p.K) * 16},
+      {reinterpret_cast<void**>(&b.epart), cap * size_t(p.nexp) * nte * 8},
+      {reinterpret_cast<void**>(&b.E), cap * size_t(8)},
+      {reinterpret_cast<void**>(&b.G), cap * size_t(p.K) * 8},
+      {reinterpret_cast<void**>(&b.lam), lam ? cap * S * 16 : 0},
+      {reinterpret_cast<void**>(&b.gpart), lam ? cap * size_t(p.K) * ntr * 8 : 0},
+  };
+  for (auto& r : reqs) {
+    if (r.bytes == 0) continue;
+    e = hipMalloc(r.ptr, r.bytes);
+    if (e != hipSuccess) {
+      free_buffers(b);
+      return hip_fail(e, "hipMalloc(state buffers)");
+    }
+  }
+  // psi is fully rewritten by the first forward pass; lambda relies on zeros outside the
+  // N / S_z sector, which no kernel writes.
+  e = hipMemset(b.psi, 0, cap * S * 16);
+  if (e == hipSuccess && b.lam) e = hipMemset(b.lam, 0, cap * S * 16);
+  if (e != hipSuccess) {
+    free_buffers(b);
+    return hip_fail(e, "hipMemset(state buffers)");
+  }
+  return UCC_OK;
+}
+
+LaunchArgs make_args(const ucc_ctx* c, const Buffers& b, int B, hipStream_t st) {
+  const Plan& p = c->plan;
+  LaunchArgs a;
+  a.stream = st;
+  a.n = p.n;
+  a.K = p.K;
+  a.B = B;
+  a.threads = p.threads;
+  a.hf = p.hf;
+  a.amask = p.amask;
+  a.bmask = p.bmask;
+  a.passes = c->d_passes;
+  a.exc = c->d_exc;
+  a.groups = c->d_groups;
+  a.occ = c->d_occ;
+  a.diag = c->d_diag;
+  a.cls = reinterpret_cast<const int2*>(c->d_cls);
+  a.list = reinterpret_cast<const uint2*>(c->d_list);
+  a.psi = b.psi;
+  a.lam = b.lam;
+  a.cs = b.cs;
+  a.epart = b.epart;
+  a.estride = p.nexp << (p.n - p.kf);
+  a.gpart = b.gpart;
+  a.E = b.E;
+  a.G = b.G;
+  return a;
+}
+
+// The launch sequence of one call: cos/sin, forward passes (the first synthesizes |HF>),
+// expectation or apply-H passes, reverse passes (gradient), fixed-order reduction.
+ucc_status enqueue_eval(const ucc_ctx* c, Buffers& b, const double* d_theta, int B, bool grad,
+                        hipStream_t st) {
+  const Plan& p = c->plan;
+  LaunchArgs a = make_args(c, b, B, st);
+  hipError_t e = launch_trig(a, d_theta);
+  if (e != hipSuccess) return hip_fail(e, "launch k_trig");
+  for (int i = 0; i < p.nfwd; ++i) {
+    e = launch_fwd(a, i, p.kf, i == 0);
+    if (e != hipSuccess) return hip_fail(e, "launch k_fwd");
+  }
+  const int nte = 1 << (p.n - p.kf);
+  for (int j = 0; j < p.nexp; ++j) {
+    e = launch_exp(a, p.nfwd + j, p.kf, j * nte, j == 0, grad);
+    if (e != hipSuccess) return hip_fail(e, "launch k_exp");
+  }
+  if (grad)
+    for (int j = 0; j < p.nrev; ++j) {
+      e = launch_rev(a, p.nfwd + p.nexp + j, p.kr);
+      if (e != hipSuccess) return hip_fail(e, "launch k_rev");
+    }
+  e = launch_reduce(a, p.nexp * nte, grad, 1 << (p.n - p.kr));
+  if (e != hipSuccess) return hip_fail(e, "launch k_reduce");
+  return UCC_OK;
+}
+
+}  // namespace ucc
+
+using namespace ucc;
+
+extern "C" {
+
+void ucc_default_options(ucc_options* opt) {
+  if (!opt) return;
+  std::memset(opt, 0, sizeof(*opt));
+  opt->trotter_steps = 1;
+  opt->max_batch = 1;
+  opt->device = -1;
+}
+
+const char* ucc_last_error(void) { return g_last_error.c_str(); }
+
+ucc_status ucc_build(int32_t n_qubits, int32_t n_elec, const double* h1, const double* h2,
+                     const int32_t* exc, int32_t n_exc, const ucc_options* opt, ucc_ctx** out) {
+  g_last_error.clear();
+  if (!out) return fail(UCC_EINVAL, "out is NULL");
+  *out = nullptr;
+  ucc_options o;
+  ucc_default_options(&o);
+  if (opt) o = *opt;
+  if (o.trotter_steps > 1 || o.trotter_steps < 0)
+    return fail(UCC_EINVAL, "only one Trotter slice (M = 1) is supported");
+  std::string msg = validate_inputs(n_qubits, n_elec, h1, h2, exc, n_exc);
+  if (!msg.empty()) return fail(UCC_EINVAL, msg);
+  // one complex128 tile of 2^k amplitudes (two for the reverse sweep) must fit in 160 KB of LDS
+  if (o.tile_qubits && (o.tile_qubits < 4 || o.tile_qubits > 13))
+    return fail(UCC_EINVAL, "tile_qubits must be 0 or in [4, 13]");
+  if (o.tile_qubits_rev && (o.tile_qubits_rev < 4 || o.tile_qubits_rev > 12))
+    return fail(UCC_EINVAL, "tile_qubits_rev must be 0 or in [4, 12]");
+  if (o.block_threads && o.block_threads != 256 && o.block_threads != 512 &&
+      o.block_threads != 1024)
+    return fail(UCC_EINVAL, "block_threads must be 0, 256, 512 or 1024");
+  if (o.launch_mode < 0 || o.launch_mode > 2) return fail(UCC_EINVAL, "launch_mode must be 0..2");
+  if (o.max_batch < 0) return fail(UCC_EINVAL, "max_batch must be >= 0");
+
+  ucc_ctx* c = new (std::nothrow) ucc_ctx();
+  if (!c) return fail(UCC_ENOMEM, "host allocation failed");
+  c->opt = o;
+  c->host_only = o.host_only != 0;
+  Tuning tu = choose_tuning(n_qubits, n_exc, std::max(1, o.max_batch), o);
+  msg = build_plan(c->plan, n_qubits, n_elec, h1, h2, exc, n_exc, tu.kf, tu.kr,
+                   o.contiguous_qubits, tu.threads);
+  if (!msg.empty()) {
+    delete c;
+    return fail(UCC_EINVAL, msg);
+  }
+  c->plan.launch_mode = tu.launch_mode;
+  build_tables(c->plan, c->tab);
+  if (c->host_only) {
+    *out = c;
+    return UCC_OK;
+  }
+  hipError_t e;
+  if (o.device >= 0) {
+    e = hipSetDevice(o.device);
+    if (e != hipSuccess) {
+      delete c;
+      return hip_fail(e, "hipSetDevice");
+    }
+  }
+  e = hipGetDevice(&c->device);
+  if (e != hipSuccess) {
+    delete c;
+    return hip_fail(e, "hipGetDevice (no GPU?)");
+  }
+  const Tables& t = c->tab;
+  if ((e = upload(&c->d_passes, t.passes)) != hipSuccess ||
+      (e = upload(&c->d_exc, t.exc)) != hipSuccess ||
+      (e = upload(&c->d_groups, t.groups)) != hipSuccess ||
+      (e = upload(&c->d_occ, t.occ)) != hipSuccess ||
+      (e = upload(&c->d_diag, t.diag)) != hipSuccess ||
+      (e = upload(&c->d_cls, t.cls)) != hipSuccess ||
+      (e = upload(&c->d_list, t.list)) != hipSuccess) {
+    ucc_status s = hip_fail(e, "device table upload");
+    ucc_destroy(c);
+    return s;
+  }
+  ucc_status s = ensure_buffers(c, c->buf, std::max(1, o.max_batch), false);
+  if (s != UCC_OK) {
+    ucc_destroy(c);
+    return s;
+  }
+  *out = c;
+  return UCC_OK;
+}
+
+static ucc_status eval_call(ucc_ctx* c, const double* theta, int32_t B, double* energy,
+                            double* grad, bool want_grad, void* stream) {
+  g_last_error.clear();
+  if (!c) return fail(UCC_EINVAL, "ctx is NULL");
+  if (c->host_only) return fail(UCC_EINVAL, "context was built host_only");
+  if (B < 1 || B > 65535) return fail(UCC_EINVAL, "B must be in [1, 65535]");
+  if (!theta || !energy || (want_grad && !grad)) return fail(UCC_EINVAL, "NULL output or input");
+  if (c->busy) return fail(UCC_EBUSY, "context is in use by a server job");
+  hipError_t e = hipSetDevice(c->device);
+  if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
+  ucc_status s = ensure_buffers(c, c->buf, B, want_grad);
+  if (s != UCC_OK) return s;
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  const size_t tb = size_t(B) * c->plan.K * sizeof(double);
+  const double* d_theta = theta;
+  if (!is_device_ptr(theta)) {
+    e = hipMemcpyAsync(c->buf.theta, theta, tb, hipMemcpyHostToDevice, st);
+    if (e != hipSuccess) return hip_fail(e, "copy theta");
+    d_theta = c->buf.theta;
+  }
+  s = enqueue_eval(c, c->buf, d_theta, B, want_grad, st);
+  if (s != UCC_OK) return s;
+  const bool host_e = !is_device_ptr(energy);
+  e = hipMemcpyAsync(energy, c->buf.E, B * sizeof(double),
+                     host_e ? hipMemcpyDeviceToHost : hipMemcpyDeviceToDevice, st);
+  if (e != hipSuccess) return hip_fail(e, "copy energy");
+  bool host_g = false;
+  if (want_grad) {
+    host_g = !is_device_ptr(grad);
+    e = hipMemcpyAsync(grad, c->buf.G, tb, host_g ? hipMemcpyDeviceToHost : hipMemcpyDeviceToDevice,
+                       st);
+    if (e != hipSuccess) return hip_fail(e, "copy gradient");
+  }
+  if (host_e || host_g) {
+    e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+  }
+  c->last_B = B;
+  return UCC_OK;
+}
+
+ucc_status ucc_energy(ucc_ctx* c, const double* theta, int32_t B, double* energy, void* stream) {
+  return eval_call(c, theta, B, energy, nullptr, false, stream);
+}
+
+ucc_status ucc_energy_grad(ucc_ctx* c, const double* theta, int32_t B, double* energy,
+                           double* grad, void* stream) {
+  return eval_call(c, theta, B, energy, grad, true, stream);
+}
+
+ucc_status ucc_get_state(ucc_ctx* c, int32_t b, double* re_im) {
+  g_last_error.clear();
+  if (!c || !re_im) return fail(UCC_EINVAL, "NULL argument");
+  if (c->host_only) return fail(UCC_EINVAL, "context was built host_only");
+  if (b < 0 || b >= c->buf.cap) return fail(UCC_EINVAL, "b out of range");
+  const int n = c->plan.n, ne = c->plan.ne;
+  const size_t S = size_t(1) << n;
+  std::vector<double> tmp(2 * S);
+  hipError_t e = hipSetDevice(c->device);
+  if (e == hipSuccess) e = hipDeviceSynchronize();
+  if (e == hipSuccess)
+    e = hipMemcpy(tmp.data(), c->buf.psi + b * S, S * 16, hipMemcpyDeviceToHost);
+  if (e != hipSuccess) return hip_fail(e, "copy state");
+  // logical index L -> physical: occupied bits (low n_elec) move to the top
+  const uint64_t lowm = (uint64_t(1) << ne) - 1;
+  for (uint64_t L = 0; L < S; ++L) {
+    const uint64_t P = (L >> ne) | ((L & lowm) << (n - ne));
+    re_im[2 * L] = tmp[2 * P];
+    re_im[2 * L + 1] = tmp[2 * P + 1];
+  }
+  return UCC_OK;
+}
+
+void ucc_destroy(ucc_ctx* c) {
+  if (!c) return;
+  if (!c->host_only) {
+    (void)hipSetDevice(c->device);
+    (void)hipDeviceSynchronize();
+    free_buffers(c->buf);
+    free_ptr(c->d_passes);
+    free_ptr(c->d_exc);
+    free_ptr(c->d_groups);
+    free_ptr(c->d_occ);
+    free_ptr(c->d_diag);
+    free_ptr(c->d_cls);
+    free_ptr(c->d_list);
+  }
+  delete c;
+}
+
+ucc_status ucc_get_plan_info(const ucc_ctx* c, ucc_plan_info* info) {
+  if (!c || !info) return fail(UCC_EINVAL, "NULL argument");
+  const Plan& p = c->plan;
+  std::memset(info, 0, sizeof(*info));
+  info->n_qubits = p.n;
+  info->n_elec = p.ne;
+  info->n_exc = p.K;
+  info->n_pauli = (int32_t)p.pc.size();
+  info->n_groups = (int32_t)p.groups.size();
+  info->n_fwd_passes = p.nfwd;
+  info->n_exp_passes = p.nexp;
+  info->n_rev_passes = p.nrev;
+  info->tile_qubits = p.kf;
+  info->tile_qubits_rev = p.kr;
+  info->contiguous_fwd = p.c0f;
+  info->contiguous_exp = p.c0e;
+  info->contiguous_rev = p.c0r;
+  info->block_threads = p.threads;
+  info->launch_mode = p.launch_mode;
+  for (int q = 0; q < p.n; ++q) info->perm[q] = p.perm[q];
+  return UCC_OK;
+}
+
+ucc_status ucc_get_pauli_terms(const ucc_ctx* c, uint64_t* x, uint64_t* z, double* coef) {
+  if (!c) return fail(UCC_EINVAL, "NULL ctx");
+  const Plan& p = c->plan;
+  for (size_t t = 0; t < p.pc.size(); ++t) {
+    if (x) x[t] = p.px[t];
+    if (z) z[t] = p.pz[t];
+    if (coef) coef[t] = p.pc[t];
+  }
+  return UCC_OK;
+}
+
+ucc_status ucc_get_group_table(const ucc_ctx* c, uint32_t* xm, uint32_t* m, uint32_t* valid,
+                               double* A, double* B, double* diag) {
+  if (!c) return fail(UCC_EINVAL, "NULL ctx");
+  const Plan& p = c->plan;
+  const int n = p.n;
+  for (size_t g = 0; g < p.groups.size(); ++g) {
+    const auto& G = p.groups[g];
+    if (xm) xm[g] = G.x;
+    if (m) m[g] = G.m;
+    if (valid) valid[g] = G.valid;
+    if (A)
+      for (int P = 0; P < 16; ++P) A[g * 16 + P] = G.A[P];
+    if (B)
+      for (int i = 0; i < 16 * n; ++i) B[g * 16 * n + i] = G.has_occ ? G.B[i] : 0.0;
+  }
+  if (diag) {
+    diag[0] = p.diag_c0;
+    for (int r = 0; r < n; ++r) diag[1 + r] = p.diag_a[r];
+    for (int i = 0; i < n * n; ++i) diag[1 + n + i] = p.diag_b[i];
+  }
+  return UCC_OK;
+}
+
+ucc_status ucc_get_excitation_table(const ucc_ctx* c, uint32_t* supp, uint32_t* from, uint32_t* m,
+                                    int32_t* sigma) {
+  if (!c) return fail(UCC_EINVAL, "NULL ctx");
+  const Plan& p = c->plan;
+  for (int k = 0; k < p.K; ++k) {
+    if (supp) supp[k] = p.ex[k].supp;
+    if (from) from[k] = p.ex[k].from;
+    if (m) m[k] = p.ex[k].m;
+    if (sigma) sigma[k] = p.ex[k].sigma;
+  }
+  return UCC_OK;
+}
+
+ucc_status ucc_get_pass_table(const ucc_ctx* c, int32_t* kind, uint32_t* local, int32_t* first,
+                              int32_t* count, int32_t* items) {
+  if (!c) return fail(UCC_EINVAL, "NULL ctx");
+  const Plan& p = c->plan;
+  int off = 0;
+  for (size_t i = 0; i < p.passes.size(); ++i) {
+    const auto& ps = p.passes[i];
+    if (kind) kind[i] = ps.kind;
+    if (local) local[i] = ps.lmask;
+    if (first) first[i] = off;
+    if (count) count[i] = (int32_t)ps.items.size();
+    if (items)
+      for (size_t j = 0; j < ps.items.size(); ++j) items[off + j] = ps.items[j];
+    off += (int)ps.items.size();
+  }
+  return UCC_OK;
+}
+
+}  // extern "C"

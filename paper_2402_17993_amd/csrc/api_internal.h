@@ -1,0 +1,66 @@
+// Internal pieces shared by the C ABI (api.cpp), the tuner (tuning.cpp) and the server
+// (server.cpp).
+#pragma once
+
+#include <hip/hip_runtime_api.h>
+
+#include <atomic>
+#include <string>
+
+#include "kernels.h"
+#include "ucc.h"
+#include "ucc_internal.h"
+
+namespace ucc {
+
+// Device buffers for up to `cap` state vectors of one plan.
+struct Buffers {
+  int cap = 0;
+  double2* psi = nullptr;  // [cap][2^n]
+  double2* lam = nullptr;  // [cap][2^n] (gradient calls only)
+  double* theta = nullptr; // [cap][K]
+  double2* cs = nullptr;   // [cap][K] (cos, sin)
+  double* epart = nullptr; // [cap][n_exp_passes * tiles]
+  double* gpart = nullptr; // [cap][K][reverse tiles]
+  double* E = nullptr;     // [cap]
+  double* G = nullptr;     // [cap][K]
+};
+
+struct Tuning {
+  int kf = 13, kr = 12, threads = 512, launch_mode = 1;
+};
+
+}  // namespace ucc
+
+struct ucc_ctx {
+  ucc_options opt{};
+  bool host_only = false;
+  int device = 0;
+  ucc::Plan plan;
+  ucc::Tables tab;
+  ucc::DevPass* d_passes = nullptr;
+  ucc::DevExc* d_exc = nullptr;
+  ucc::DevGroup* d_groups = nullptr;
+  double* d_occ = nullptr;
+  double* d_diag = nullptr;
+  int32_t* d_cls = nullptr;
+  uint32_t* d_list = nullptr;
+  ucc::Buffers buf;
+  int last_B = 0;
+  std::atomic<int> busy{0};  // held by a server job
+};
+
+namespace ucc {
+
+extern thread_local std::string g_last_error;
+ucc_status fail(ucc_status code, const std::string& msg);
+ucc_status hip_fail(hipError_t e, const char* what);
+bool is_device_ptr(const void* p);
+void free_buffers(Buffers& b);
+ucc_status ensure_buffers(const ucc_ctx* c, Buffers& b, int B, bool need_lam);
+LaunchArgs make_args(const ucc_ctx* c, const Buffers& b, int B, hipStream_t st);
+ucc_status enqueue_eval(const ucc_ctx* c, Buffers& b, const double* d_theta, int B, bool grad,
+                        hipStream_t st);
+Tuning choose_tuning(int n, int K, int batch, const ucc_options& o);
+
+}  // namespace ucc

@@ -1,0 +1,37 @@
+// Launchers of the HIP kernels (kernels.hip).  Host code only sees these.
+#pragma once
+
+#include <hip/hip_runtime_api.h>
+
+#include "ucc_internal.h"
+
+namespace ucc {
+
+struct LaunchArgs {
+  hipStream_t stream = nullptr;
+  int n = 0, K = 0, B = 0, threads = 512;
+  uint32_t hf = 0, amask = 0, bmask = 0;
+  const DevPass* passes = nullptr;
+  const DevExc* exc = nullptr;
+  const DevGroup* groups = nullptr;
+  const double* occ = nullptr;
+  const double* diag = nullptr;
+  const int2* cls = nullptr;
+  const uint2* list = nullptr;
+  double2* psi = nullptr;
+  double2* lam = nullptr;
+  double2* cs = nullptr;
+  double* epart = nullptr;  // [B][estride]
+  int estride = 0;
+  double* gpart = nullptr;  // [B][K][tiles of a reverse pass]
+  double* E = nullptr;
+  double* G = nullptr;
+};
+
+hipError_t launch_trig(const LaunchArgs& a, const double* theta);
+hipError_t launch_fwd(const LaunchArgs& a, int pidx, int k, int init);
+hipError_t launch_exp(const LaunchArgs& a, int pidx, int k, int eslot, int first, bool apply);
+hipError_t launch_rev(const LaunchArgs& a, int pidx, int k);
+hipError_t launch_reduce(const LaunchArgs& a, int ne, bool grad, int nt);
+
+}  // namespace ucc

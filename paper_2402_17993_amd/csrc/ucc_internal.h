@@ -1,0 +1,131 @@
+// Internal data structures of the UCCSD state-vector library.
+//
+// Host planner (planner.cpp) -> device tables (kernels.hip) -> C ABI (api.cpp).
+//
+// Physical layout.  Logical qubit q (spin orbital, Jordan-Wigner order) is stored at
+// physical bit perm[q] of the state index: virtual orbitals occupy the low physical bits
+// and occupied orbitals the high ones, so that every excitation (which always touches
+// virtual orbitals) and every tile keeps its busiest bits contiguous in memory.  All
+// parity masks are computed in logical order and then moved to physical bits; a parity is
+// a popcount over a set of bits, so the relabeling does not change any sign.
+//
+// Tiles.  A pass fixes a set L of k physical bits ("local"); the other n-k bits ("global")
+// index 2^(n-k) tiles of 2^k amplitudes each.  Compact index c in [0, 2^k) enumerates the
+// local bits in ascending physical order.  A workgroup stages one tile in LDS, applies
+// everything the pass holds, and writes the tile back.
+#pragma once
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+namespace ucc {
+
+constexpr int kMaxQubits = 30;
+
+enum PassKind : int32_t { kFwd = 0, kExp = 1, kRev = 2 };
+
+// One excitation inside one forward or reverse pass, in compact tile coordinates.
+struct DevExc {
+  uint32_t supp_c;  // compact support (2 or 4 bits)
+  uint32_t from_c;  // compact pattern u & supp on which T_k acts (its occupied orbitals)
+  uint32_t mloc_c;  // compact part of the JW parity mask m_k
+  uint32_t mglob;   // physical global part of m_k (constant over a tile)
+  uint32_t ins;     // ascending compact support positions, 5 bits each
+  int32_t nsup;     // 2 (single) or 4 (double)
+  int32_t k;        // amplitude index
+  int32_t sigma;    // constant sign of T_k on its from-pattern (+1 or -1)
+};
+
+// One x-group inside one expectation pass.
+struct DevGroup {
+  uint32_t xc;     // compact x-mask (LDS partner offset); 0 for the diagonal group
+  uint32_t xphys;  // physical x-mask
+  uint32_t m;      // physical parity mask (outside the support)
+  uint32_t valid;  // bit P set when support pattern P conserves N and S_z
+  uint32_t spos;   // ascending physical support positions, 5 bits each
+  int32_t nsup;    // 0 (diagonal), 2 or 4
+  int32_t occ;     // offset (doubles) of the B[16][n] table, or -1
+  int32_t pad;
+  double A[16];    // constant part per support pattern
+};
+
+struct DevPass {
+  uint32_t lmask;   // physical local bits
+  uint32_t gmask;   // physical global bits
+  int32_t k;        // popcount(lmask)
+  int32_t kind;     // PassKind
+  int32_t first;    // first record in DevExc[] (fwd/rev) or DevGroup[] (exp)
+  int32_t count;    // records in this pass
+  int32_t cls_base; // exp: first class entry (int2 offset,count) of this pass
+  int32_t nbeta_g;  // exp: number of beta bits among the global bits
+};
+
+// Host-side plan: everything ucc_build derives from the inputs.
+struct Plan {
+  int n = 0, ne = 0, ns = 0, K = 0;
+  int nalpha = 0, nbeta = 0;
+  std::vector<double> h1, h2;
+  std::vector<int32_t> exc;  // [K*4]
+  int perm[32] = {0};        // logical -> physical
+  int iperm[32] = {0};       // physical -> logical
+  uint32_t amask = 0, bmask = 0, hf = 0;  // physical
+
+  // Jordan-Wigner Pauli sum (logical qubits), Hermitian coefficients.
+  std::vector<uint64_t> px, pz;
+  std::vector<double> pc;
+
+  // Compiled groups (physical).  groups[0] is the diagonal group.
+  struct Group {
+    uint32_t x = 0, m = 0;
+    uint32_t valid = 0;
+    double A[16] = {0};
+    bool has_occ = false;
+    std::vector<double> B;  // [16 * n] when has_occ
+  };
+  std::vector<Group> groups;
+  double diag_c0 = 0.0;
+  std::vector<double> diag_a, diag_b;  // [n], [n*n] (b[r*n+s], r<s)
+
+  // Compiled excitations (physical).
+  struct Exc {
+    uint32_t supp = 0, from = 0, m = 0;
+    int sigma = 1, nsup = 0;
+  };
+  std::vector<Exc> ex;
+
+  struct Pass {
+    int kind = 0;
+    uint32_t lmask = 0;
+    std::vector<int> items;
+  };
+  std::vector<Pass> passes;  // forward, then expectation, then reverse
+  int nfwd = 0, nexp = 0, nrev = 0;
+  int kf = 0, kr = 0;
+  int c0f = 0, c0e = 0, c0r = 0;
+  int threads = 512;
+  int launch_mode = 1;
+};
+
+// Device-ready flattened tables built from a Plan.
+struct Tables {
+  std::vector<DevPass> passes;
+  std::vector<DevExc> exc;
+  std::vector<DevGroup> groups;
+  std::vector<double> occ;      // B tables
+  std::vector<double> diag;     // c0, a[n], b[n*n]
+  std::vector<int32_t> cls;     // pairs (offset, count)
+  std::vector<uint32_t> list;   // pairs (compact c, physical local offset)
+};
+
+// planner.cpp
+// Returns "" on success, otherwise an error message (inputs invalid).
+std::string validate_inputs(int n, int ne, const double* h1, const double* h2, const int32_t* exc,
+                            int K);
+std::string build_plan(Plan& p, int n, int ne, const double* h1, const double* h2,
+                       const int32_t* exc, int K, int kf, int kr, int c0, int threads);
+void build_tables(const Plan& p, Tables& t);
+uint32_t deposit_bits(uint32_t v, uint32_t mask);
+int count_plan_passes(const Plan& p, int kind);
+
+}  // namespace ucc

@@ -1,0 +1,276 @@
+"""ctypes binding of libucc.so (include/ucc.h).
+
+Argument marshalling only: every step of the computation runs in the HIP library.  With
+torch CUDA tensors the device pointers and torch's current stream are passed through; with
+numpy arrays the library copies to and from the host itself.  There is no CPU fallback:
+if libucc.so is missing every call raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libucc.so")
+
+_i32, _u32, _u64, _dbl, _vp = ctypes.c_int32, ctypes.c_uint32, ctypes.c_uint64, ctypes.c_double, ctypes.c_void_p
+_P = ctypes.POINTER
+
+STATUS = {0: "UCC_OK", -1: "UCC_EINVAL", -2: "UCC_ENOMEM", -3: "UCC_EDEVICE", -4: "UCC_EBUSY",
+          -5: "UCC_ECANCELED", -6: "UCC_ENOTFOUND"}
+
+EXPORTED = [
+    "ucc_default_options", "ucc_build", "ucc_energy", "ucc_energy_grad", "ucc_get_state",
+    "ucc_destroy", "ucc_last_error", "ucc_get_plan_info", "ucc_get_pauli_terms",
+    "ucc_get_group_table", "ucc_get_excitation_table", "ucc_get_pass_table",
+    "ucc_server_create", "ucc_submit", "ucc_poll", "ucc_wait", "ucc_cancel", "ucc_server_destroy",
+]
+
+
+class Options(ctypes.Structure):
+    _fields_ = [("trotter_steps", _i32), ("tile_qubits", _i32), ("tile_qubits_rev", _i32),
+                ("contiguous_qubits", _i32), ("block_threads", _i32), ("max_batch", _i32),
+                ("launch_mode", _i32), ("host_only", _i32), ("device", _i32),
+                ("reserved", _i32 * 7)]
+
+
+class PlanInfo(ctypes.Structure):
+    _fields_ = [("n_qubits", _i32), ("n_elec", _i32), ("n_exc", _i32), ("n_pauli", _i32),
+                ("n_groups", _i32), ("n_fwd_passes", _i32), ("n_exp_passes", _i32),
+                ("n_rev_passes", _i32), ("tile_qubits", _i32), ("tile_qubits_rev", _i32),
+                ("contiguous_fwd", _i32), ("contiguous_exp", _i32), ("contiguous_rev", _i32),
+                ("block_threads", _i32), ("launch_mode", _i32), ("perm", _i32 * 32)]
+
+
+class UCCError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+_lib = None
+
+
+def lib():
+    """The loaded library (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with "
+                           "`python -m paper_2402_17993_amd.build` (or __graft_entry__.build())")
+    L = ctypes.CDLL(LIB_PATH)
+    sig = {
+        "ucc_default_options": (None, [_P(Options)]),
+        "ucc_build": (_i32, [_i32, _i32, _vp, _vp, _vp, _i32, _P(Options), _P(_vp)]),
+        "ucc_energy": (_i32, [_vp, _vp, _i32, _vp, _vp]),
+        "ucc_energy_grad": (_i32, [_vp, _vp, _i32, _vp, _vp, _vp]),
+        "ucc_get_state": (_i32, [_vp, _i32, _vp]),
+        "ucc_destroy": (None, [_vp]),
+        "ucc_last_error": (ctypes.c_char_p, []),
+        "ucc_get_plan_info": (_i32, [_vp, _P(PlanInfo)]),
+        "ucc_get_pauli_terms": (_i32, [_vp, _vp, _vp, _vp]),
+        "ucc_get_group_table": (_i32, [_vp, _vp, _vp, _vp, _vp, _vp, _vp]),
+        "ucc_get_excitation_table": (_i32, [_vp, _vp, _vp, _vp, _vp]),
+        "ucc_get_pass_table": (_i32, [_vp, _vp, _vp, _vp, _vp, _vp]),
+        "ucc_server_create": (_i32, [ctypes.c_size_t, _i32, _i32, _P(_vp)]),
+        "ucc_submit": (_i32, [_vp, _vp, _vp, _i32, _dbl, _u32, _P(_u64)]),
+        "ucc_poll": (_i32, [_vp, _u64, _P(_i32), _vp, _vp, _vp]),
+        "ucc_wait": (_i32, [_vp, _u64, _vp, _vp, _vp]),
+        "ucc_cancel": (_i32, [_vp, _u64]),
+        "ucc_server_destroy": (None, [_vp]),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(L, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = L
+    return L
+
+
+def check(status, what=""):
+    if status != 0:
+        msg = lib().ucc_last_error().decode(errors="replace")
+        raise UCCError(status, f"{what}: {msg}" if what else msg)
+
+
+def _ptr(a):
+    return ctypes.c_void_p(a.ctypes.data) if a is not None else None
+
+
+def _is_torch_cuda(x):
+    try:
+        import torch
+    except ImportError:
+        return False
+    return isinstance(x, torch.Tensor) and x.is_cuda
+
+
+class Context:
+    """One Hamiltonian (Eq. 2) + excitation list (Eqs. 4-5) + device buffers."""
+
+    def __init__(self, n_qubits, n_elec, h1, h2, exc, *, tile_qubits=0, tile_qubits_rev=0,
+                 contiguous_qubits=0, block_threads=0, max_batch=1, launch_mode=0,
+                 host_only=False, device=-1):
+        L = lib()
+        self._h = None
+        self.n_qubits, self.n_elec = int(n_qubits), int(n_elec)
+        h1 = np.ascontiguousarray(h1, dtype=np.float64)
+        h2 = np.ascontiguousarray(h2, dtype=np.float64)
+        exc = np.ascontiguousarray(exc, dtype=np.int32).reshape(-1, 4)
+        self.n_exc = exc.shape[0]
+        o = Options()
+        L.ucc_default_options(ctypes.byref(o))
+        o.tile_qubits, o.tile_qubits_rev = tile_qubits, tile_qubits_rev
+        o.contiguous_qubits, o.block_threads = contiguous_qubits, block_threads
+        o.max_batch, o.launch_mode = max_batch, launch_mode
+        o.host_only, o.device = int(bool(host_only)), device
+        h = _vp()
+        check(L.ucc_build(self.n_qubits, self.n_elec, _ptr(h1), _ptr(h2), _ptr(exc),
+                          self.n_exc, ctypes.byref(o), ctypes.byref(h)), "ucc_build")
+        self._h = h
+
+    # ------------------------------------------------------------ evaluation
+    def _run(self, theta, grad, stream):
+        L = lib()
+        if _is_torch_cuda(theta):
+            import torch
+            th = theta.detach().to(torch.float64).contiguous()
+            B = th.numel() // self.n_exc
+            if th.numel() != B * self.n_exc or B < 1:
+                raise ValueError("theta must hold B * n_exc amplitudes")
+            E = torch.empty(B, dtype=torch.float64, device=th.device)
+            G = torch.empty(B, self.n_exc, dtype=torch.float64, device=th.device) if grad else None
+            st = stream if stream is not None else torch.cuda.current_stream(th.device).cuda_stream
+            if grad:
+                check(L.ucc_energy_grad(self._h, _vp(th.data_ptr()), B, _vp(E.data_ptr()),
+                                        _vp(G.data_ptr()), _vp(st)), "ucc_energy_grad")
+            else:
+                check(L.ucc_energy(self._h, _vp(th.data_ptr()), B, _vp(E.data_ptr()), _vp(st)),
+                      "ucc_energy")
+            return E, G
+        th = np.ascontiguousarray(theta, dtype=np.float64)
+        B = th.size // self.n_exc
+        if th.size != B * self.n_exc or B < 1:
+            raise ValueError("theta must hold B * n_exc amplitudes")
+        E = np.empty(B)
+        G = np.empty((B, self.n_exc)) if grad else None
+        st = _vp(stream) if stream is not None else None
+        if grad:
+            check(L.ucc_energy_grad(self._h, _ptr(th), B, _ptr(E), _ptr(G), st), "ucc_energy_grad")
+        else:
+            check(L.ucc_energy(self._h, _ptr(th), B, _ptr(E), st), "ucc_energy")
+        return E, G
+
+    def energy(self, theta, stream=None):
+        """E for theta [K] or [B, K] (numpy -> numpy, torch CUDA -> torch CUDA)."""
+        return self._run(theta, False, stream)[0]
+
+    def energy_grad(self, theta, stream=None):
+        """(E [B], dE/dtheta [B, K])."""
+        return self._run(theta, True, stream)
+
+    def state(self, b=0):
+        out = np.empty(2 << self.n_qubits)
+        check(lib().ucc_get_state(self._h, int(b), _ptr(out)), "ucc_get_state")
+        return out[0::2] + 1j * out[1::2]
+
+    # ------------------------------------------------------------ introspection
+    def plan_info(self):
+        info = PlanInfo()
+        check(lib().ucc_get_plan_info(self._h, ctypes.byref(info)), "ucc_get_plan_info")
+        d = {f: getattr(info, f) for f, _ in PlanInfo._fields_ if f != "perm"}
+        d["perm"] = list(info.perm)[: info.n_qubits]
+        return d
+
+    def pauli_terms(self):
+        n = self.plan_info()["n_pauli"]
+        x, z, c = np.empty(n, np.uint64), np.empty(n, np.uint64), np.empty(n)
+        check(lib().ucc_get_pauli_terms(self._h, _ptr(x), _ptr(z), _ptr(c)))
+        return x, z, c
+
+    def group_table(self):
+        info = self.plan_info()
+        G, n = info["n_groups"], self.n_qubits
+        xm, m, valid = (np.empty(G, np.uint32) for _ in range(3))
+        A = np.empty((G, 16))
+        B = np.empty((G, 16, n))
+        diag = np.empty(1 + n + n * n)
+        check(lib().ucc_get_group_table(self._h, _ptr(xm), _ptr(m), _ptr(valid), _ptr(A), _ptr(B),
+                                        _ptr(diag)))
+        return dict(x=xm, m=m, valid=valid, A=A, B=B, c0=diag[0], a=diag[1:1 + n],
+                    b=diag[1 + n:].reshape(n, n))
+
+    def excitation_table(self):
+        K = self.n_exc
+        supp, frm, m = (np.empty(K, np.uint32) for _ in range(3))
+        sig = np.empty(K, np.int32)
+        check(lib().ucc_get_excitation_table(self._h, _ptr(supp), _ptr(frm), _ptr(m), _ptr(sig)))
+        return dict(supp=supp, frm=frm, m=m, sigma=sig)
+
+    def pass_table(self):
+        info = self.plan_info()
+        P = info["n_fwd_passes"] + info["n_exp_passes"] + info["n_rev_passes"]
+        kind, first, count = (np.empty(P, np.int32) for _ in range(3))
+        local = np.empty(P, np.uint32)
+        items = np.empty(2 * self.n_exc + info["n_groups"], np.int32)
+        check(lib().ucc_get_pass_table(self._h, _ptr(kind), _ptr(local), _ptr(first), _ptr(count),
+                                       _ptr(items)))
+        return [dict(kind=int(kind[i]), local=int(local[i]),
+                     items=items[first[i]:first[i] + count[i]].copy()) for i in range(P)]
+
+    # ------------------------------------------------------------ lifetime
+    def close(self):
+        if self._h:
+            lib().ucc_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+
+def _autograd():
+    import torch
+
+    class UCCEnergy(torch.autograd.Function):
+        """E(theta) with dE/dtheta from the library's adjoint sweep.
+
+        forward(theta [B, K] or [K] float64 CUDA tensor, ctx: Context) -> E [B] or scalar.
+        """
+
+        @staticmethod
+        def forward(fctx, theta, ctx):
+            E, G = ctx.energy_grad(theta)
+            fctx.save_for_backward(G)
+            fctx.scalar = theta.dim() == 1
+            return E[0] if fctx.scalar else E
+
+        @staticmethod
+        def backward(fctx, gE):
+            (G,) = fctx.saved_tensors
+            if fctx.scalar:
+                return gE * G[0], None
+            return gE.unsqueeze(-1) * G, None
+
+    return UCCEnergy
+
+
+_UCCEnergy = None
+
+
+def ucc_energy_fn(theta, ctx):
+    """Differentiable energy: torch autograd through the HIP adjoint gradient."""
+    global _UCCEnergy
+    if _UCCEnergy is None:
+        _UCCEnergy = _autograd()
+    return _UCCEnergy.apply(theta, ctx)

@@ -1,0 +1,63 @@
+"""Write stored expected values for the GPU parity tests.
+
+Calls only oracle/ (and the seeded input generators).  Output: one JSON file per case in
+this directory.  Run from the repository root:
+
+    python tests/golden/make_golden.py [case ...]
+"""
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+sys.path.insert(0, ROOT)
+
+from oracle import ansatz, closed_forms, hamiltonian  # noqa: E402
+from paper_2402_17993_amd.inputs import make_integrals, make_thetas, uccsd_excitations  # noqa: E402
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+def case_dimer_18q():
+    """18 qubits, 10 electrons, integrals seed 0, batch of 64 thetas U(-0.05, 0.05) from seeds
+    1..64: oracle energy and gradient of batch entries 0, 1 and 63."""
+    n, ne = 18, 10
+    h1, h2 = make_integrals(n // 2, 0)
+    h, g = hamiltonian.spin_orbital_integrals(h1, h2)
+    exc = uccsd_excitations(n, ne)
+    thetas = make_thetas(len(exc), 1, 0.05, batch=64)
+    pairs = ansatz.all_pairs(n, exc)
+    out = {"n": n, "ne": ne, "integral_seed": 0, "theta_seed": 1, "theta_scale": 0.05,
+           "batch": 64, "entries": {}}
+    for b in (0, 1, 63):
+        e, gr = ansatz.energy_and_gradient(h, g, n, (1 << ne) - 1, exc, thetas[b], pairs)
+        out["entries"][str(b)] = {"energy": e, "grad": gr.tolist()}
+    return out
+
+
+def case_large_26q_theta0():
+    """26 qubits, 14 electrons, integrals seed 0, theta = 0: closed-form Hartree-Fock energy
+    and Slater-Condon gradient (the oracle's closed forms; no state vector needed)."""
+    n, ne = 26, 14
+    h1, h2 = make_integrals(n // 2, 0)
+    h, g = hamiltonian.spin_orbital_integrals(h1, h2)
+    exc = uccsd_excitations(n, ne)
+    return {"n": n, "ne": ne, "integral_seed": 0,
+            "energy": closed_forms.hf_energy_spatial(h1, h2, ne),
+            "grad": closed_forms.gradient_at_zero(h, g, range(ne), exc).tolist()}
+
+
+CASES = {"dimer_18q": case_dimer_18q, "large_26q_theta0": case_large_26q_theta0}
+
+if __name__ == "__main__":
+    names = sys.argv[1:] or list(CASES)
+    for name in names:
+        t = time.time()
+        data = CASES[name]()
+        data["generator"] = "tests/golden/make_golden.py (oracle/)"
+        with open(os.path.join(HERE, f"{name}.json"), "w") as f:
+            json.dump(data, f, indent=1)
+        print(f"{name}: {time.time() - t:.1f}s")

@@ -1,0 +1,207 @@
+"""GPU parity: the HIP path through the C ABI against the CPU oracle.
+
+Tolerances (stated for the method): |dE| <= 1e-10 Ha, max_k |dg_k| <= 1e-9.
+"""
+import json
+import os
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import ansatz, closed_forms, hamiltonian
+from paper_2402_17993_amd.inputs import make_integrals, make_thetas, uccsd_excitations
+
+pytestmark = pytest.mark.gpu
+
+E_TOL = 1e-10
+G_TOL = 1e-9
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+def say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def ucc():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_2402_17993_amd import ucc as u
+    u.lib()
+    return u
+
+
+def system(n, ne, seed=0):
+    h1, h2 = make_integrals(n // 2, seed)
+    h, g = hamiltonian.spin_orbital_integrals(h1, h2)
+    return h1, h2, h, g, uccsd_excitations(n, ne)
+
+
+def oracle_eg(n, ne, h, g, exc, th):
+    return ansatz.energy_and_gradient(h, g, n, (1 << ne) - 1, exc, th)
+
+
+def sector_mask(n, ne):
+    v = np.arange(1 << n)
+    return (np.bitwise_count(v & 0x5555_5555) == ne // 2) & (np.bitwise_count(v & 0xAAAA_AAAA) == ne // 2)
+
+
+def test_8q_energy_gradient(ucc):
+    say("case: 8q/4e seed 0 energy+grad")
+    n, ne = 8, 4
+    h1, h2, h, g, exc = system(n, ne)
+    th = make_thetas(len(exc), 1, 0.1)
+    ctx = ucc.Context(n, ne, h1, h2, exc)
+    e_ref, g_ref = oracle_eg(n, ne, h, g, exc, th)
+    e1 = ctx.energy(th)
+    e2, gr = ctx.energy_grad(th)
+    assert abs(e1[0] - e_ref) <= E_TOL
+    assert abs(e2[0] - e_ref) <= E_TOL
+    assert np.max(np.abs(gr[0] - g_ref)) <= G_TOL
+
+
+def test_8q_steepest_descent_trajectory(ucc):
+    say("case: 8q/4e 20 steepest-descent steps")
+    n, ne = 8, 4
+    h1, h2, h, g, exc = system(n, ne)
+    th0 = make_thetas(len(exc), 1, 0.1)
+    es_ref, th_ref = ansatz.steepest_descent(h, g, n, (1 << ne) - 1, exc, th0, 20, 0.1)
+    ctx = ucc.Context(n, ne, h1, h2, exc)
+    th = th0.copy()
+    es = []
+    for _ in range(20):
+        e, gr = ctx.energy_grad(th)
+        es.append(e[0])
+        th = th - 0.1 * gr[0]
+    es.append(ctx.energy(th)[0])
+    assert np.max(np.abs(np.array(es) - es_ref)) <= E_TOL
+    assert np.max(np.abs(th - th_ref)) <= 1e-9
+
+
+@pytest.mark.parametrize("kf,kr,c0,threads", [
+    (6, 5, 2, 256), (7, 6, 3, 512), (8, 8, 4, 1024), (10, 9, 0, 512), (12, 12, 0, 0), (5, 4, 1, 256)])
+def test_12q_tilings(ucc, kf, kr, c0, threads):
+    say(f"case: 12q/4e tiling kf={kf} kr={kr} c0={c0} threads={threads}")
+    n, ne = 12, 4
+    h1, h2, h, g, exc = system(n, ne, seed=3)
+    th = make_thetas(len(exc), 5, 0.2)
+    e_ref, g_ref = oracle_eg(n, ne, h, g, exc, th)
+    ctx = ucc.Context(n, ne, h1, h2, exc, tile_qubits=kf, tile_qubits_rev=kr, contiguous_qubits=c0,
+                      block_threads=threads)
+    info = ctx.plan_info()
+    assert info["n_fwd_passes"] >= 1
+    e, gr = ctx.energy_grad(th)
+    assert abs(e[0] - e_ref) <= E_TOL
+    assert np.max(np.abs(gr[0] - g_ref)) <= G_TOL
+    assert abs(ctx.energy(th)[0] - e_ref) <= E_TOL
+
+
+def test_minimal_system_and_single_excitation(ucc):
+    say("case: 4q/2e full list, and a one-excitation list")
+    n, ne = 4, 2
+    h1, h2, h, g, exc = system(n, ne, seed=7)
+    th = np.array([0.3, -0.2, 0.5])
+    e_ref, g_ref = oracle_eg(n, ne, h, g, exc, th)
+    ctx = ucc.Context(n, ne, h1, h2, exc)
+    e, gr = ctx.energy_grad(th)
+    assert abs(e[0] - e_ref) <= E_TOL and np.max(np.abs(gr[0] - g_ref)) <= G_TOL
+    one = exc[-1:].copy()
+    e_ref, g_ref = oracle_eg(n, ne, h, g, one, th[-1:])
+    ctx1 = ucc.Context(n, ne, h1, h2, one)
+    e, gr = ctx1.energy_grad(th[-1:])
+    assert abs(e[0] - e_ref) <= E_TOL and np.max(np.abs(gr[0] - g_ref)) <= G_TOL
+
+
+def test_state_invariants_and_reverse_sweep(ucc):
+    say("case: 12q/6e state invariants")
+    n, ne = 12, 6
+    h1, h2, h, g, exc = system(n, ne, seed=2)
+    th = make_thetas(len(exc), 3, 0.3)
+    ctx = ucc.Context(n, ne, h1, h2, exc, tile_qubits=8, tile_qubits_rev=7)
+    ctx.energy(th)
+    psi = ctx.state(0)
+    ref = ansatz.trotter_state(n, (1 << ne) - 1, exc, th)
+    assert np.max(np.abs(psi - ref)) <= 1e-12
+    assert abs(np.linalg.norm(psi) - 1.0) <= 1e-13
+    assert np.all(psi.imag == 0.0)
+    assert np.all(psi[~sector_mask(n, ne)] == 0.0)
+    ctx.energy_grad(th)
+    back = ctx.state(0)
+    hf = np.zeros(1 << n, complex)
+    hf[(1 << ne) - 1] = 1.0
+    assert np.max(np.abs(back - hf)) <= 1e-13
+
+
+def test_16q_energy_gradient(ucc):
+    say("case: 16q/8e seed 0 energy+grad")
+    n, ne = 16, 8
+    h1, h2, h, g, exc = system(n, ne)
+    th = make_thetas(len(exc), 1, 0.05)
+    ctx = ucc.Context(n, ne, h1, h2, exc)
+    e, gr = ctx.energy_grad(th)
+    e_ref, g_ref = oracle_eg(n, ne, h, g, exc, th)
+    assert abs(e[0] - e_ref) <= E_TOL
+    assert np.max(np.abs(gr[0] - g_ref)) <= G_TOL
+    assert abs(ctx.energy(th)[0] - e_ref) <= E_TOL
+
+
+def test_18q_batch64_against_stored_oracle_values(ucc):
+    say("case: 18q/10e batch 64 energy+grad (stored oracle values for entries 0, 1, 63)")
+    gold = json.load(open(os.path.join(HERE, "golden", "dimer_18q.json")))
+    n, ne = gold["n"], gold["ne"]
+    h1, h2 = make_integrals(n // 2, gold["integral_seed"])
+    exc = uccsd_excitations(n, ne)
+    th = make_thetas(len(exc), gold["theta_seed"], gold["theta_scale"], batch=gold["batch"])
+    ctx = ucc.Context(n, ne, h1, h2, exc, max_batch=64)
+    e, gr = ctx.energy_grad(th)
+    for b, ent in gold["entries"].items():
+        b = int(b)
+        assert abs(e[b] - ent["energy"]) <= E_TOL, b
+        assert np.max(np.abs(gr[b] - np.array(ent["grad"]))) <= G_TOL, b
+    # every entry returned the state to |HF> (the reverse sweep undoes the forward one)
+    hf = (1 << ne) - 1
+    for b in (0, 31, 63):
+        s = ctx.state(b)
+        assert abs(s[hf] - 1.0) <= 1e-12 and np.max(np.abs(np.delete(s, hf))) <= 1e-12
+    # batch entry == solo run, bitwise
+    solo = ucc.Context(n, ne, h1, h2, exc)
+    e1, g1 = solo.energy_grad(th[1])
+    assert e1[0] == e[1] and np.array_equal(g1[0], gr[1])
+    e_only = ctx.energy(th)
+    assert np.max(np.abs(e_only - e)) <= 1e-12
+
+
+def test_26q_theta_zero_closed_forms(ucc):
+    say("case: 26q/14e theta = 0 energy+grad vs closed forms")
+    gold = json.load(open(os.path.join(HERE, "golden", "large_26q_theta0.json")))
+    n, ne = gold["n"], gold["ne"]
+    h1, h2 = make_integrals(n // 2, gold["integral_seed"])
+    exc = uccsd_excitations(n, ne)
+    ctx = ucc.Context(n, ne, h1, h2, exc)
+    e, gr = ctx.energy_grad(np.zeros(len(exc)))
+    assert abs(e[0] - gold["energy"]) <= E_TOL
+    assert np.max(np.abs(gr[0] - np.array(gold["grad"]))) <= G_TOL
+
+
+def test_determinism_and_device_pointers(ucc):
+    import torch
+    say("case: 12q/8e determinism, torch device pointers, autograd")
+    n, ne = 12, 8
+    h1, h2, h, g, exc = system(n, ne, seed=1)
+    th = make_thetas(len(exc), 2, 0.1, batch=3)
+    ctx = ucc.Context(n, ne, h1, h2, exc, tile_qubits=9, tile_qubits_rev=8)
+    e_a, g_a = ctx.energy_grad(th)
+    e_b, g_b = ctx.energy_grad(th)
+    assert np.array_equal(e_a, e_b) and np.array_equal(g_a, g_b)
+    td = torch.tensor(th, device="cuda", dtype=torch.float64)
+    e_d, g_d = ctx.energy_grad(td)
+    torch.cuda.synchronize()
+    assert np.array_equal(e_d.cpu().numpy(), e_a) and np.array_equal(g_d.cpu().numpy(), g_a)
+    tr = td.clone().requires_grad_(True)
+    E = ucc.ucc_energy_fn(tr, ctx)
+    E.sum().backward()
+    assert np.array_equal(tr.grad.cpu().numpy(), g_a)
+    e_ref, g_ref = oracle_eg(n, ne, h, g, exc, th[2])
+    assert abs(e_a[2] - e_ref) <= E_TOL and np.max(np.abs(g_a[2] - g_ref)) <= G_TOL

@@ -1,0 +1,189 @@
+"""Host-side tests of the C ABI (no GPU): symbol exports, input validation, and the
+planner's tables (JW Pauli sum, compiled x-groups, excitation signs, pass plan) checked
+against the oracle's dense and ladder-operator constructions."""
+import re
+import os
+import ctypes
+
+import numpy as np
+import pytest
+
+from oracle import dense, hamiltonian, fermion, ansatz
+from paper_2402_17993_amd import ucc
+from paper_2402_17993_amd.inputs import make_integrals, uccsd_excitations
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+pytestmark = pytest.mark.skipif(not os.path.exists(ucc.LIB_PATH), reason="libucc.so not built")
+
+
+def host_ctx(n, ne, seed=0, exc=None, **kw):
+    h1, h2 = make_integrals(n // 2, seed)
+    if exc is None:
+        exc = uccsd_excitations(n, ne)
+    return ucc.Context(n, ne, h1, h2, exc, host_only=True, **kw), h1, h2, exc
+
+
+def logical_to_phys(n, ne):
+    idx = np.arange(1 << n)
+    return (idx >> ne) | ((idx & ((1 << ne) - 1)) << (n - ne))
+
+
+# ---------------------------------------------------------------- ABI surface
+
+def test_library_exports_every_declared_symbol():
+    header = open(os.path.join(ROOT, "include", "ucc.h")).read()
+    declared = set(re.findall(r"\b(ucc_[a-z_]+)\s*\(", header))
+    declared -= {"ucc_status"}
+    L = ctypes.CDLL(ucc.LIB_PATH)
+    for name in sorted(declared):
+        assert hasattr(L, name), name
+    assert declared == set(ucc.EXPORTED)
+
+
+@pytest.mark.parametrize("bad", [
+    dict(n=7), dict(n=32), dict(ne=3), dict(ne=8),
+    dict(exc=[[0, -1, 1, -1]]),            # occupied -> occupied
+    dict(exc=[[0, -1, 5, -1]]),            # spin flip (alpha -> beta)
+    dict(exc=[[1, 0, 4, 5]]),              # i > j
+    dict(exc=[[0, 1, 4, 5], [0, 1, 4, 5]]),  # duplicate
+    dict(h1_asym=True), dict(h2_asym=True), dict(tile_qubits=20), dict(block_threads=300),
+])
+def test_invalid_inputs_are_rejected(bad):
+    n, ne = bad.get("n", 8), bad.get("ne", 4)
+    h1, h2 = make_integrals(4, 0)
+    if bad.get("h1_asym"):
+        h1 = h1.copy()
+        h1[0, 1] += 1e-6
+    if bad.get("h2_asym"):
+        h2 = h2.copy()
+        h2[0, 1, 2, 3] += 1e-6
+    exc = np.array(bad.get("exc", uccsd_excitations(8, 4)), dtype=np.int32)
+    kw = {k: bad[k] for k in ("tile_qubits", "block_threads") if k in bad}
+    with pytest.raises(ucc.UCCError) as ei:
+        ucc.Context(n, ne, h1[: n // 2, : n // 2] if n <= 8 else np.zeros((n // 2,) * 2),
+                    h2 if n == 8 else np.zeros((n // 2,) * 4), exc, host_only=True, **kw)
+    assert ei.value.status == -1
+
+
+def test_host_only_context_refuses_evaluation():
+    ctx, *_ = host_ctx(8, 4)
+    with pytest.raises(ucc.UCCError):
+        ctx.energy(np.zeros(ctx.n_exc))
+
+
+# ---------------------------------------------------------------- JW Pauli sum
+
+@pytest.mark.parametrize("ns,ne,seed", [(3, 2, 1), (4, 4, 0)])
+def test_pauli_sum_reconstructs_dense_hamiltonian(ns, ne, seed):
+    n = 2 * ns
+    ctx, h1, h2, _ = host_ctx(n, ne, seed)
+    x, z, c = ctx.pauli_terms()
+    H = np.zeros((1 << n, 1 << n), dtype=complex)
+    for xi, zi, ci in zip(x, z, c):
+        lab = "".join("I" if not (xi >> q) & 1 and not (zi >> q) & 1 else
+                      "X" if (xi >> q) & 1 and not (zi >> q) & 1 else
+                      "Y" if (xi >> q) & 1 else "Z" for q in range(n))
+        H += ci * dense.pauli_matrix(lab)
+    h, g = hamiltonian.spin_orbital_integrals(h1, h2)
+    np.testing.assert_allclose(H, dense.hamiltonian_dense(h, g), atol=1e-12)
+
+
+def test_pauli_string_counts():
+    # counts quoted for the workloads (8 / 12 / 16 qubits)
+    for n, ne, strings, groups in [(8, 4, 361, 51), (12, 8, 1819, 286), (16, 8, 5793, 981)]:
+        ctx, *_ = host_ctx(n, ne)
+        info = ctx.plan_info()
+        assert info["n_pauli"] == strings
+        assert info["n_groups"] == groups
+
+
+# ---------------------------------------------------------------- compiled groups
+
+@pytest.mark.parametrize("ns,ne,seed", [(4, 4, 0), (5, 6, 2), (5, 4, 3)])
+def test_group_table_reproduces_hamiltonian_in_sector(ns, ne, seed):
+    n = 2 * ns
+    ctx, h1, h2, _ = host_ctx(n, ne, seed)
+    tab = ctx.group_table()
+    perm = np.array(ctx.plan_info()["perm"])
+    h, g = hamiltonian.spin_orbital_integrals(h1, h2)
+    N = 1 << n
+    l2p = logical_to_phys(n, ne)
+    # physical matrix Hp[P(a), P(b)] = <a|H|b>, columns b in the N / S_z sector, from the
+    # oracle's ladder-operator H (pinned to the dense Kronecker H in the oracle tests)
+    lv = np.arange(N)
+    lsec = (np.bitwise_count(lv & 0x5555_5555) == ne // 2) & (np.bitwise_count(lv & 0xAAAA_AAAA) == ne // 2)
+    Hp = np.zeros((N, N))
+    for b in np.flatnonzero(lsec):
+        e = np.zeros(N, dtype=complex)
+        e[b] = 1.0
+        Hp[l2p, l2p[b]] = hamiltonian.apply_h(h, g, e).real
+    v = np.arange(N)
+    occ = ((v[:, None] >> np.arange(n)) & 1).astype(float)
+    Hc = np.zeros((N, N))
+    diag = tab["c0"] + occ @ tab["a"] + np.einsum("vr,rs,vs->v", occ, np.triu(tab["b"], 1), occ)
+    Hc[v, v] += diag
+    for gi in range(1, len(tab["x"])):
+        x = int(tab["x"][gi])
+        pos = [q for q in range(n) if (x >> q) & 1]
+        P = sum(((v >> p) & 1) << j for j, p in enumerate(pos))
+        ok = (tab["valid"][gi] >> P) & 1 == 1
+        val = tab["A"][gi][P] + np.einsum("vr,vr->v", occ, tab["B"][gi][P])
+        sgn = np.where(np.bitwise_count(v & int(tab["m"][gi])) & 1, -1.0, 1.0)
+        vv = v[ok]
+        Hc[vv ^ x, vv] += (sgn * val)[ok]
+    amask = sum(1 << int(perm[q]) for q in range(0, n, 2))
+    bmask = sum(1 << int(perm[q]) for q in range(1, n, 2))
+    sec = (np.bitwise_count(v & amask) == ne // 2) & (np.bitwise_count(v & bmask) == ne // 2)
+    S = np.flatnonzero(sec)
+    np.testing.assert_allclose(Hc[np.ix_(S, S)], Hp[np.ix_(S, S)], atol=1e-12)
+    # nothing leaves the sector
+    assert np.max(np.abs(Hc[np.ix_(~sec, S)])) == 0.0
+
+
+# ---------------------------------------------------------------- excitation signs
+
+@pytest.mark.parametrize("n,ne", [(8, 4), (10, 6), (12, 4)])
+def test_excitation_signs_match_ladder_operators(n, ne):
+    ctx, _, _, exc = host_ctx(n, ne)
+    t = ctx.excitation_table()
+    l2p = logical_to_phys(n, ne)
+    for k, row in enumerate(exc):
+        src, dst, s = ansatz.excitation_pairs(n, row)
+        up, vp = l2p[src], l2p[dst]
+        assert np.all((up & int(t["supp"][k])) == int(t["frm"][k]))
+        assert np.all((up ^ vp) == int(t["supp"][k]))
+        pred = t["sigma"][k] * np.where(np.bitwise_count(up & int(t["m"][k])) & 1, -1, 1)
+        assert np.array_equal(pred, s)
+
+
+# ---------------------------------------------------------------- pass plan
+
+@pytest.mark.parametrize("n,ne,kf,kr", [(8, 4, 0, 0), (12, 8, 8, 7), (16, 8, 0, 0), (18, 10, 0, 0),
+                                        (18, 10, 10, 9)])
+def test_pass_plan_covers_everything_in_order(n, ne, kf, kr):
+    ctx, _, _, exc = host_ctx(n, ne, tile_qubits=kf, tile_qubits_rev=kr)
+    info = ctx.plan_info()
+    passes = ctx.pass_table()
+    et = ctx.excitation_table()
+    gt = ctx.group_table()
+    fwd = [p for p in passes if p["kind"] == 0]
+    exp_ = [p for p in passes if p["kind"] == 1]
+    rev = [p for p in passes if p["kind"] == 2]
+    assert len(fwd) == info["n_fwd_passes"] and len(exp_) == info["n_exp_passes"]
+    K = len(exc)
+    assert np.array_equal(np.concatenate([p["items"] for p in fwd]), np.arange(K))
+    assert np.array_equal(np.concatenate([p["items"] for p in rev]), np.arange(K)[::-1])
+    for group, k, c0 in ((fwd, info["tile_qubits"], info["contiguous_fwd"]),
+                         (rev, info["tile_qubits_rev"], info["contiguous_rev"])):
+        for p in group:
+            assert bin(p["local"]).count("1") == k
+            assert p["local"] & ((1 << c0) - 1) == (1 << c0) - 1
+            for e in p["items"]:
+                assert int(et["supp"][e]) & ~p["local"] == 0
+    seen = np.concatenate([p["items"] for p in exp_])
+    assert np.array_equal(np.sort(seen), np.arange(info["n_groups"]))
+    for p in exp_:
+        assert bin(p["local"]).count("1") == info["tile_qubits"]
+        for gi in p["items"]:
+            assert int(gt["x"][gi]) & ~p["local"] == 0
