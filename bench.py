@@ -1,0 +1,180 @@
+"""Throughput of the UCCSD energy + adjoint-gradient hot path on one MI355X.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+
+Workload: 18 qubits (9 spatial orbitals), 10 electrons, integrals from seed 0, the full
+spin-conserving UCCSD list (K = 560) in singles-then-doubles Trotter order, a batch of 64
+theta vectors U(-0.05, 0.05) from seeds 1..64; one step = E and dE/dtheta for all 64
+vectors (forward sweep, apply-H, reverse sweep, reductions), inputs resident in HBM.
+
+Prints one JSON line (rank 0).  `roofline` reports the kernel kind with the largest summed
+HIP-event time over the timed steps: algorithmic bytes per launch / average launch time.
+`cpu_baseline` times the CPU oracle on one theta vector of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "UCCSD energy+grad evals/sec at 18 qubits (FP64, ≤1e-10 Ha); HBM GB/s; p50/p99"
+HBM_PEAK_GBS = 8000.0
+N, NE, BATCH, SCALE, ISEED, TSEED = 18, 10, 64, 0.05, 0, 1
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_dimer_18q_b64.json")
+
+
+def cpu_baseline():
+    """The oracle, unchanged, on theta vector 0 of the workload (one E + gradient)."""
+    from threadpoolctl import threadpool_limits
+
+    from oracle import ansatz, hamiltonian
+    from paper_2402_17993_amd.inputs import make_integrals, make_thetas, uccsd_excitations
+
+    h1, h2 = make_integrals(N // 2, ISEED)
+    exc = uccsd_excitations(N, NE)
+    th = make_thetas(len(exc), TSEED, SCALE, batch=1)[0]
+    with threadpool_limits(limits=1):
+        t0 = time.perf_counter()
+        h, g = hamiltonian.spin_orbital_integrals(h1, h2)
+        ansatz.energy_and_gradient(h, g, N, (1 << NE) - 1, exc, th)
+        dt = time.perf_counter() - t0
+    return {"value": 1.0 / dt, "unit": "evals/s", "cores": 1, "kind": "oracle",
+            "sample": f"1 energy+gradient evaluation (theta vector 0 of the batch), "
+                      f"{dt:.1f} s, numpy/BLAS limited to 1 thread"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--launch-mode", type=int, default=0)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU: the workload shards by independent theta vectors and "
+              "fragment jobs, and this build runs on a single MI355X; use --gpus 1.",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from paper_2402_17993_amd import ucc
+    from paper_2402_17993_amd.inputs import make_integrals, make_thetas, uccsd_excitations
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    dev = torch.device("cuda:0")
+    h1, h2 = make_integrals(N // 2, ISEED)
+    exc = uccsd_excitations(N, NE)
+    K = len(exc)
+    thetas = make_thetas(K, TSEED, SCALE, batch=BATCH)
+    ctx = ucc.Context(N, NE, h1, h2, exc, max_batch=BATCH, device=0, launch_mode=args.launch_mode)
+    info = ctx.plan_info()
+    td = torch.tensor(thetas, device=dev, dtype=torch.float64)
+
+    # parity guard on the benchmarked configuration (stored oracle values)
+    gold = json.load(open(os.path.join(ROOT, "tests", "golden", "dimer_18q.json")))
+    E, G = ctx.energy_grad(td)
+    torch.cuda.synchronize()
+    En, Gn = E.cpu().numpy(), G.cpu().numpy()
+    de = max(abs(En[int(b)] - v["energy"]) for b, v in gold["entries"].items())
+    dg = max(float(np.max(np.abs(Gn[int(b)] - np.array(v["grad"])))) for b, v in gold["entries"].items())
+    if de > 1e-10 or dg > 1e-9:
+        print(f"parity guard failed: max|dE| {de:.3e} max|dg| {dg:.3e}", file=sys.stderr)
+        sys.exit(1)
+
+    for _ in range(args.warmup):
+        ctx.energy_grad(td)
+    torch.cuda.synchronize()
+
+    # timed region: K steps, HIP events around every kernel launch on the launch stream
+    ctx.profile(True)
+    ctx.profile_read(reset=True)
+    starts = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
+    ends = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        starts[i].record()
+        ctx.energy_grad(td)
+        ends[i].record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    stats = ctx.profile_read(reset=True)
+    ctx.profile(False)
+    step_ms = np.array([s.elapsed_time(e) for s, e in zip(starts, ends)])
+
+    # untimed-by-events throughput run (no per-launch event records)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    for _ in range(args.steps):
+        ctx.energy_grad(td)
+    torch.cuda.synchronize()
+    wall_plain = time.perf_counter() - t1
+
+    ms_per_step = 1e3 * wall_plain / args.steps
+    value = BATCH * args.steps / wall_plain
+
+    dom = max((k for k in stats if stats[k]["launches"]), key=lambda k: stats[k]["ms"])
+    d = stats[dom]
+    avg_ms = d["ms"] / d["launches"]
+    bytes_per_launch = d["bytes"] / d["launches"]
+    achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
+    traffic = None
+    if os.path.exists(TRAFFIC_FILE):
+        tr = json.load(open(TRAFFIC_FILE))
+        if tr.get("kernel") == dom and tr.get("source_hash") == kernel_source_hash():
+            traffic = tr.get("bytes_per_launch")
+
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "evals/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "dimer_18q_b64", "n_qubits": N, "n_elec": NE, "batch": BATCH,
+                   "n_exc": K, "n_pauli": info["n_pauli"], "n_groups": info["n_groups"],
+                   "passes_fwd_exp_rev": [info["n_fwd_passes"], info["n_exp_passes"],
+                                          info["n_rev_passes"]],
+                   "tile_qubits": [info["tile_qubits"], info["tile_qubits_rev"]],
+                   "block_threads": info["block_threads"], "launch_mode": info["launch_mode"],
+                   "integral_seed": ISEED, "theta_seeds": "1..64", "theta_scale": SCALE},
+        "p50_ms": float(np.percentile(step_ms, 50)),
+        "p99_ms": float(np.percentile(step_ms, 99)),
+        "ms_per_step_with_event_probes": 1e3 * wall / args.steps,
+        "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                     "avg_launch_ms": avg_ms, "algorithmic_bytes_per_launch": bytes_per_launch},
+        "kernels": {k: {"launches": v["launches"], "ms": v["ms"],
+                        "GBps": (v["bytes"] / (v["ms"] * 1e-3) / 1e9) if v["ms"] else None}
+                    for k, v in stats.items() if v["launches"]},
+        "parity": {"max_abs_dE": de, "max_abs_dgrad": dg, "entries": sorted(gold["entries"])},
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline()
+    print(json.dumps(out))
+
+
+def kernel_source_hash():
+    import hashlib
+
+    p = os.path.join(ROOT, "paper_2402_17993_amd", "csrc", "kernels.hip")
+    return hashlib.sha256(open(p, "rb").read()).hexdigest()[:16]
+
+
+if __name__ == "__main__":
+    main()

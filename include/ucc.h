@@ -184,6 +184,43 @@ ucc_status ucc_get_excitation_table(const ucc_ctx* ctx, uint32_t* supp, uint32_t
 ucc_status ucc_get_pass_table(const ucc_ctx* ctx, int32_t* kind, uint32_t* local, int32_t* first,
                               int32_t* count, int32_t* items);
 
+/* ---------------------------------------------------------------- profiling */
+
+/* Kernel kinds reported by ucc_profile_read. */
+enum {
+  UCC_KERNEL_TRIG = 0,   /* cos/sin of the amplitudes */
+  UCC_KERNEL_FWD = 1,    /* forward excitation pass (one vector) */
+  UCC_KERNEL_EXP = 2,    /* expectation pass (energy only) */
+  UCC_KERNEL_APPLYH = 3, /* apply-H pass (lambda = H psi, energy as a by-product) */
+  UCC_KERNEL_REV = 4,    /* reverse-sweep pass (two vectors, gradient partials) */
+  UCC_KERNEL_REDUCE = 5, /* fixed-order reduction of partials */
+  UCC_KERNEL_KINDS = 8
+};
+
+typedef struct {
+  int32_t launches; /* kernel launches recorded since the last reset */
+  int32_t reserved;
+  double ms;        /* summed HIP-event durations of those launches (ms) */
+  double bytes;     /* algorithmic HBM bytes of those launches: every amplitude a pass must
+                       read or write, 16 B each (per-kind model: fwd 2S per vector (S = 16 * 2^n;
+                       the first pass writes only, S), exp S, apply-H S + 32 B per N/S_z-sector
+                       amplitude (16 B on the first pass), rev 4S, trig 24 B per amplitude) */
+} ucc_kernel_stat;
+
+/*
+ * ucc_profile -- enable (1) or disable (0) per-launch timing: every kernel launch of later
+ * ucc_energy / ucc_energy_grad calls on this context is bracketed by HIP events recorded on
+ * the call's stream.  Adds two event records per launch; off by default.
+ */
+ucc_status ucc_profile(ucc_ctx* ctx, int32_t enable);
+
+/*
+ * ucc_profile_read -- wait for the recorded events, add their durations into
+ * stats[UCC_KERNEL_KINDS] (host, caller-allocated; zeroed first) and, if reset != 0,
+ * forget them.
+ */
+ucc_status ucc_profile_read(ucc_ctx* ctx, ucc_kernel_stat* stats, int32_t reset);
+
 /* ---------------------------------------------------------------- serving */
 
 /*

@@ -125,9 +125,9 @@ LaunchArgs make_args(const ucc_ctx* c, const Buffers& b, int B, hipStream_t st) 
   a.bmask = p.bmask;
   a.passes = c->d_passes;
   a.exc = c->d_exc;
-  a.groups = c->d_groups;
-  a.occ = c->d_occ;
-  a.diag = c->d_diag;
+  a.hpasses = c->tab.passes.data();
+  a.pairs = c->d_pairs;
+  a.blobs = reinterpret_cast<const uint4*>(c->d_blob);
   a.cls = reinterpret_cast<const int2*>(c->d_cls);
   a.list = reinterpret_cast<const uint2*>(c->d_list);
   a.psi = b.psi;
@@ -141,29 +141,70 @@ LaunchArgs make_args(const ucc_ctx* c, const Buffers& b, int B, hipStream_t st) 
   return a;
 }
 
+hipEvent_t Profiler::get() {
+  if (!pool.empty()) {
+    hipEvent_t e = pool.back();
+    pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+void Profiler::release_all() {
+  for (auto& r : recs) {
+    pool.push_back(r.a);
+    pool.push_back(r.b);
+  }
+  recs.clear();
+}
+
+Profiler::~Profiler() {
+  release_all();
+  for (hipEvent_t e : pool)
+    if (e) (void)hipEventDestroy(e);
+}
+
 // The launch sequence of one call: cos/sin, forward passes (the first synthesizes |HF>),
 // expectation or apply-H passes, reverse passes (gradient), fixed-order reduction.
 ucc_status enqueue_eval(const ucc_ctx* c, Buffers& b, const double* d_theta, int B, bool grad,
-                        hipStream_t st) {
+                        hipStream_t st, Profiler* prof) {
   const Plan& p = c->plan;
   LaunchArgs a = make_args(c, b, B, st);
-  hipError_t e = launch_trig(a, d_theta);
+  const double S = 16.0 * double(size_t(1) << p.n) * B;
+  const double sec = 16.0 * double(p.nsec) * B;
+  auto timed = [&](int kind, double bytes, auto&& fn) -> hipError_t {
+    if (!prof) return fn();
+    Profiler::Rec r{kind, prof->get(), prof->get(), bytes};
+    if (!r.a || !r.b) return hipErrorOutOfMemory;
+    hipError_t e = hipEventRecord(r.a, st);
+    if (e == hipSuccess) e = fn();
+    if (e == hipSuccess) e = hipEventRecord(r.b, st);
+    prof->recs.push_back(r);
+    return e;
+  };
+  hipError_t e = timed(UCC_KERNEL_TRIG, 24.0 * B * p.K, [&] { return launch_trig(a, d_theta); });
   if (e != hipSuccess) return hip_fail(e, "launch k_trig");
   for (int i = 0; i < p.nfwd; ++i) {
-    e = launch_fwd(a, i, p.kf, i == 0);
+    e = timed(UCC_KERNEL_FWD, i == 0 ? S : 2 * S, [&] { return launch_fwd(a, i, i == 0); });
     if (e != hipSuccess) return hip_fail(e, "launch k_fwd");
   }
   const int nte = 1 << (p.n - p.kf);
   for (int j = 0; j < p.nexp; ++j) {
-    e = launch_exp(a, p.nfwd + j, p.kf, j * nte, j == 0, grad);
+    const double bytes = grad ? S + (j == 0 ? sec : 2 * sec) : S;
+    e = timed(grad ? UCC_KERNEL_APPLYH : UCC_KERNEL_EXP, bytes,
+              [&] { return launch_exp(a, p.nfwd + j, j * nte, j == 0, grad); });
     if (e != hipSuccess) return hip_fail(e, "launch k_exp");
   }
   if (grad)
     for (int j = 0; j < p.nrev; ++j) {
-      e = launch_rev(a, p.nfwd + p.nexp + j, p.kr);
+      e = timed(UCC_KERNEL_REV, 4 * S, [&] { return launch_rev(a, p.nfwd + p.nexp + j); });
       if (e != hipSuccess) return hip_fail(e, "launch k_rev");
     }
-  e = launch_reduce(a, p.nexp * nte, grad, 1 << (p.n - p.kr));
+  const double rb = 8.0 * B * (double(p.nexp) * nte + (grad ? double(p.K) * (1 << (p.n - p.kr)) : 0.0));
+  e = timed(UCC_KERNEL_REDUCE, rb,
+            [&] { return launch_reduce(a, p.nexp * nte, grad, 1 << (p.n - p.kr)); });
   if (e != hipSuccess) return hip_fail(e, "launch k_reduce");
   return UCC_OK;
 }
@@ -240,9 +281,8 @@ ucc_status ucc_build(int32_t n_qubits, int32_t n_elec, const double* h1, const d
   const Tables& t = c->tab;
   if ((e = upload(&c->d_passes, t.passes)) != hipSuccess ||
       (e = upload(&c->d_exc, t.exc)) != hipSuccess ||
-      (e = upload(&c->d_groups, t.groups)) != hipSuccess ||
-      (e = upload(&c->d_occ, t.occ)) != hipSuccess ||
-      (e = upload(&c->d_diag, t.diag)) != hipSuccess ||
+      (e = upload(&c->d_pairs, t.pairs)) != hipSuccess ||
+      (e = upload(&c->d_blob, t.blob)) != hipSuccess ||
       (e = upload(&c->d_cls, t.cls)) != hipSuccess ||
       (e = upload(&c->d_list, t.list)) != hipSuccess) {
     ucc_status s = hip_fail(e, "device table upload");
@@ -278,7 +318,7 @@ static ucc_status eval_call(ucc_ctx* c, const double* theta, int32_t B, double* 
     if (e != hipSuccess) return hip_fail(e, "copy theta");
     d_theta = c->buf.theta;
   }
-  s = enqueue_eval(c, c->buf, d_theta, B, want_grad, st);
+  s = enqueue_eval(c, c->buf, d_theta, B, want_grad, st, c->prof.get());
   if (s != UCC_OK) return s;
   const bool host_e = !is_device_ptr(energy);
   e = hipMemcpyAsync(energy, c->buf.E, B * sizeof(double),
@@ -339,9 +379,8 @@ void ucc_destroy(ucc_ctx* c) {
     free_buffers(c->buf);
     free_ptr(c->d_passes);
     free_ptr(c->d_exc);
-    free_ptr(c->d_groups);
-    free_ptr(c->d_occ);
-    free_ptr(c->d_diag);
+    free_ptr(c->d_pairs);
+    free_ptr(c->d_blob);
     free_ptr(c->d_cls);
     free_ptr(c->d_list);
   }
@@ -433,6 +472,38 @@ ucc_status ucc_get_pass_table(const ucc_ctx* c, int32_t* kind, uint32_t* local, 
       for (size_t j = 0; j < ps.items.size(); ++j) items[off + j] = ps.items[j];
     off += (int)ps.items.size();
   }
+  return UCC_OK;
+}
+
+ucc_status ucc_profile(ucc_ctx* c, int32_t enable) {
+  if (!c) return fail(UCC_EINVAL, "NULL ctx");
+  if (c->host_only) return fail(UCC_EINVAL, "context was built host_only");
+  if (enable && !c->prof) c->prof.reset(new (std::nothrow) Profiler());
+  if (!enable && c->prof) {
+    (void)hipSetDevice(c->device);
+    (void)hipDeviceSynchronize();
+    c->prof.reset();
+  }
+  if (enable && !c->prof) return fail(UCC_ENOMEM, "host allocation failed");
+  return UCC_OK;
+}
+
+ucc_status ucc_profile_read(ucc_ctx* c, ucc_kernel_stat* stats, int32_t reset) {
+  if (!c || !stats) return fail(UCC_EINVAL, "NULL argument");
+  std::memset(stats, 0, sizeof(ucc_kernel_stat) * UCC_KERNEL_KINDS);
+  if (!c->prof) return UCC_OK;
+  hipError_t e = hipSetDevice(c->device);
+  for (auto& r : c->prof->recs) {
+    if (e == hipSuccess) e = hipEventSynchronize(r.b);
+    float ms = 0.f;
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, r.a, r.b);
+    if (e != hipSuccess) return hip_fail(e, "profile events");
+    auto& st = stats[r.kind];
+    st.launches += 1;
+    st.ms += ms;
+    st.bytes += r.bytes;
+  }
+  if (reset) c->prof->release_all();
   return UCC_OK;
 }
 

@@ -5,7 +5,9 @@
 #include <hip/hip_runtime_api.h>
 
 #include <atomic>
+#include <memory>
 #include <string>
+#include <vector>
 
 #include "kernels.h"
 #include "ucc.h"
@@ -26,6 +28,20 @@ struct Buffers {
   double* G = nullptr;     // [cap][K]
 };
 
+// Per-launch HIP-event timing (ucc_profile).
+struct Profiler {
+  struct Rec {
+    int kind;
+    hipEvent_t a, b;
+    double bytes;
+  };
+  std::vector<Rec> recs;
+  std::vector<hipEvent_t> pool;
+  hipEvent_t get();
+  void release_all();
+  ~Profiler();
+};
+
 struct Tuning {
   int kf = 13, kr = 12, threads = 512, launch_mode = 1;
 };
@@ -40,14 +56,14 @@ struct ucc_ctx {
   ucc::Tables tab;
   ucc::DevPass* d_passes = nullptr;
   ucc::DevExc* d_exc = nullptr;
-  ucc::DevGroup* d_groups = nullptr;
-  double* d_occ = nullptr;
-  double* d_diag = nullptr;
+  uint32_t* d_pairs = nullptr;
+  uint32_t* d_blob = nullptr;
   int32_t* d_cls = nullptr;
   uint32_t* d_list = nullptr;
   ucc::Buffers buf;
   int last_B = 0;
   std::atomic<int> busy{0};  // held by a server job
+  std::unique_ptr<ucc::Profiler> prof;
 };
 
 namespace ucc {
@@ -60,7 +76,7 @@ void free_buffers(Buffers& b);
 ucc_status ensure_buffers(const ucc_ctx* c, Buffers& b, int B, bool need_lam);
 LaunchArgs make_args(const ucc_ctx* c, const Buffers& b, int B, hipStream_t st);
 ucc_status enqueue_eval(const ucc_ctx* c, Buffers& b, const double* d_theta, int B, bool grad,
-                        hipStream_t st);
+                        hipStream_t st, Profiler* prof);
 Tuning choose_tuning(int n, int K, int batch, const ucc_options& o);
 
 }  // namespace ucc

@@ -13,9 +13,9 @@ struct LaunchArgs {
   uint32_t hf = 0, amask = 0, bmask = 0;
   const DevPass* passes = nullptr;
   const DevExc* exc = nullptr;
-  const DevGroup* groups = nullptr;
-  const double* occ = nullptr;
-  const double* diag = nullptr;
+  const DevPass* hpasses = nullptr;  // host copy of the pass table (sizes for launches)
+  const uint32_t* pairs = nullptr;
+  const uint4* blobs = nullptr;
   const int2* cls = nullptr;
   const uint2* list = nullptr;
   double2* psi = nullptr;
@@ -29,9 +29,9 @@ struct LaunchArgs {
 };
 
 hipError_t launch_trig(const LaunchArgs& a, const double* theta);
-hipError_t launch_fwd(const LaunchArgs& a, int pidx, int k, int init);
-hipError_t launch_exp(const LaunchArgs& a, int pidx, int k, int eslot, int first, bool apply);
-hipError_t launch_rev(const LaunchArgs& a, int pidx, int k);
+hipError_t launch_fwd(const LaunchArgs& a, int pidx, int init);
+hipError_t launch_exp(const LaunchArgs& a, int pidx, int eslot, int first, bool apply);
+hipError_t launch_rev(const LaunchArgs& a, int pidx);
 hipError_t launch_reduce(const LaunchArgs& a, int ne, bool grad, int nt);
 
 }  // namespace ucc

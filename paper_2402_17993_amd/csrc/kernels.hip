@@ -3,8 +3,9 @@
 // Every kernel works on one tile of one state vector per workgroup: the 2^k amplitudes
 // whose global bits equal the tile index.  blockIdx.x = tile, blockIdx.y = batch entry.
 // The tile is staged in LDS with coalesced 16-byte loads (the lowest physical bits are
-// always local, so consecutive lanes read consecutive addresses), all of the pass's work is
-// applied in LDS, and the tile is written back.
+// always local, so consecutive lanes read consecutive addresses; every load of a thread is
+// issued before the first one is waited on), all of the pass's work is applied in LDS, and
+// the tile is written back.
 //
 //   k_trig      cos/sin of every amplitude of every batch entry
 //   k_fwd       forward excitation pass: U_k = exp(theta_k G_k) for the pass's excitations
@@ -13,6 +14,10 @@
 //   k_rev       reverse pass over (psi, lambda): gradient partials, then U_k^dag on both
 //   k_reduce    fixed-order sums of the per-tile partials
 #include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <map>
+#include <mutex>
 
 #include "kernels.h"
 
@@ -33,19 +38,39 @@ __device__ __forceinline__ uint32_t dep(uint32_t v, uint32_t mask) {
 
 __device__ __forceinline__ int parity(uint32_t v) { return __popc(v) & 1; }
 
-template <int T>
-__device__ __forceinline__ double wave_sum(double v) {
-  // fixed butterfly over the 64 lanes of a wavefront
-#pragma unroll
-  for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+// One DPP move of a double (two 32-bit halves); lanes the pattern does not write read 0.
+template <int CTRL, int ROWMASK = 0xf>
+__device__ __forceinline__ double dpp(double v) {
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, ROWMASK, 0xf, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, ROWMASK, 0xf, false);
+  return __hiloint2double(hi, lo);
+}
+
+// Sum over the 4 lanes of a quad (fixed order); every lane of the quad gets the sum.
+__device__ __forceinline__ double quad_sum(double v) {
+  v += dpp<0xb1>(v);  // quad_perm [1,0,3,2]
+  v += dpp<0x4e>(v);  // quad_perm [2,3,0,1]
   return v;
+}
+
+// Sum over the 64 lanes of a wavefront in a fixed order (quads, row_shr 4 and 8 within each
+// row of 16, then row_bcast 15 and 31 across rows); every lane gets the result.
+__device__ __forceinline__ double wave_sum(double v) {
+  v = quad_sum(v);
+  v += dpp<0x114>(v);       // row_shr:4
+  v += dpp<0x118>(v);       // row_shr:8
+  v += dpp<0x142, 0xa>(v);  // row_bcast:15 into rows 1 and 3
+  v += dpp<0x143, 0xc>(v);  // row_bcast:31 into rows 2 and 3
+  const int lo = __builtin_amdgcn_readlane(__double2loint(v), 63);
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), 63);
+  return __hiloint2double(hi, lo);
 }
 
 // Sum of one double per thread over the workgroup in a fixed order; result valid in thread 0.
 template <int T>
 __device__ __forceinline__ double block_sum(double v, double* red) {
   constexpr int NW = T / 64;
-  v = wave_sum<T>(v);
+  v = wave_sum(v);
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   __syncthreads();
   if (lane == 0) red[w] = v;
@@ -56,40 +81,127 @@ __device__ __forceinline__ double block_sum(double v, double* red) {
   return s;
 }
 
-// Load (or synthesize |HF>) / store one tile between HBM and LDS.
 template <int T>
-__device__ __forceinline__ void tile_load(double2* lds, const double2* __restrict__ v, uint32_t base,
-                                          uint32_t lmask, uint32_t tileN, uint32_t hf, bool init) {
-  const uint32_t dt = dep(threadIdx.x, lmask);
-  for (uint32_t j = 0; j * T < tileN; ++j) {
-    const uint32_t c = threadIdx.x + j * T;
-    if (c < tileN) {
-      const uint32_t a = base | dt | dep(j * T, lmask);
-      lds[c] = init ? make_double2(a == hf ? 1.0 : 0.0, 0.0) : v[a];
+constexpr int log2i() {
+  return T == 256 ? 8 : T == 512 ? 9 : 10;
+}
+
+// Native 2 x double vector: copies of it are plain 16-byte loads and stores.
+typedef double dvec2 __attribute__((ext_vector_type(2)));
+
+__device__ __forceinline__ dvec2 ld16(const double2* p) { return *reinterpret_cast<const dvec2*>(p); }
+__device__ __forceinline__ void st16(double2* p, dvec2 v) { *reinterpret_cast<dvec2*>(p) = v; }
+
+// Fixed-size register buffer of N complex values addressed by compile-time index (a nest
+// of structs rather than an array, so it always lives in VGPRs).
+template <int N>
+struct RegBuf {
+  dvec2 head;
+  RegBuf<N - 1> tail;
+};
+template <>
+struct RegBuf<1> {
+  dvec2 head;
+};
+template <int J, int N>
+__device__ __forceinline__ dvec2& rget(RegBuf<N>& r) {
+  if constexpr (J == 0)
+    return r.head;
+  else
+    return rget<J - 1, N - 1>(r.tail);
+}
+template <int J, int N>
+__device__ __forceinline__ const dvec2& rget(const RegBuf<N>& r) {
+  if constexpr (J == 0)
+    return r.head;
+  else
+    return rget<J - 1, N - 1>(r.tail);
+}
+
+// Element c = threadIdx.x + j*T of a tile sits at base | dt | dj: dt deposits the thread's
+// low compact bits into the local mask, dj the bits of j into the next local bits (uniform).
+// KT = log2 of the tile size for the unrolled register-staged path (12 or 13); KT = 0 is a
+// plain loop for small tiles.
+template <int T, int KT>
+struct Tile {
+  static constexpr int L2T = log2i<T>();
+  static constexpr int EPT = KT ? (1 << KT) / T : 1;
+  static constexpr int JB = KT ? KT - L2T : 0;
+  static_assert(JB <= 5, "tile too large for the workgroup");
+  using Buf = RegBuf<EPT>;
+  uint32_t lmask, dt;
+  uint32_t h0 = 0, h1 = 0, h2 = 0, h3 = 0, h4 = 0;  // physical bits of j's bits 0..4
+  __device__ __forceinline__ explicit Tile(uint32_t lm) : lmask(lm) {
+    dt = dep(threadIdx.x, lm);
+    uint32_t mm = lm;
+#pragma unroll
+    for (int i = 0; i < L2T; ++i) mm &= mm - 1;
+    auto low = [&mm]() {
+      const uint32_t b = mm & (~mm + 1u);
+      mm &= mm - 1;
+      return b;
+    };
+    if (JB > 0) h0 = low();
+    if (JB > 1) h1 = low();
+    if (JB > 2) h2 = low();
+    if (JB > 3) h3 = low();
+    if (JB > 4) h4 = low();
+  }
+  template <int J>
+  __device__ __forceinline__ uint32_t off() const {
+    return dt | ((J & 1) ? h0 : 0u) | ((J & 2) ? h1 : 0u) | ((J & 4) ? h2 : 0u) |
+           ((J & 8) ? h3 : 0u) | ((J & 16) ? h4 : 0u);
+  }
+  // fetch issues every load of the thread into registers; put waits and writes into LDS
+  template <int J = 0>
+  __device__ __forceinline__ void fetch(Buf& r, const double2* __restrict__ v, uint32_t base) const {
+    rget<J, EPT>(r) = ld16(v + (base | off<J>()));
+    if constexpr (J + 1 < EPT) fetch<J + 1>(r, v, base);
+  }
+  template <int J = 0>
+  __device__ __forceinline__ void put(const Buf& r, double2* lds) const {
+    st16(lds + threadIdx.x + J * T, rget<J, EPT>(r));
+    if constexpr (J + 1 < EPT) put<J + 1>(r, lds);
+  }
+  template <int J = 0>
+  __device__ __forceinline__ void store_j(const double2* lds, double2* __restrict__ v,
+                                          uint32_t base) const {
+    st16(v + (base | off<J>()), ld16(lds + threadIdx.x + J * T));
+    if constexpr (J + 1 < EPT) store_j<J + 1>(lds, v, base);
+  }
+  template <int J = 0>
+  __device__ __forceinline__ void init_j(double2* lds, uint32_t base, uint32_t hf) const {
+    lds[threadIdx.x + J * T] = make_double2((base | off<J>()) == hf ? 1.0 : 0.0, 0.0);
+    if constexpr (J + 1 < EPT) init_j<J + 1>(lds, base, hf);
+  }
+  __device__ __forceinline__ void load(double2* lds, const double2* __restrict__ v, uint32_t base,
+                                       uint32_t tileN) const {
+    if constexpr (KT == 0) {
+      for (uint32_t c = threadIdx.x; c < tileN; c += T) lds[c] = v[base | dep(c, lmask)];
+    } else {
+      Buf r;
+      fetch(r, v, base);
+      put(r, lds);
     }
   }
-}
-
-template <int T>
-__device__ __forceinline__ void tile_store(const double2* lds, double2* __restrict__ v, uint32_t base,
-                                           uint32_t lmask, uint32_t tileN) {
-  const uint32_t dt = dep(threadIdx.x, lmask);
-  for (uint32_t j = 0; j * T < tileN; ++j) {
-    const uint32_t c = threadIdx.x + j * T;
-    if (c < tileN) v[base | dt | dep(j * T, lmask)] = lds[c];
+  __device__ __forceinline__ void init_hf(double2* lds, uint32_t base, uint32_t tileN,
+                                          uint32_t hf) const {
+    if constexpr (KT == 0) {
+      for (uint32_t c = threadIdx.x; c < tileN; c += T)
+        lds[c] = make_double2((base | dep(c, lmask)) == hf ? 1.0 : 0.0, 0.0);
+    } else {
+      init_j(lds, base, hf);
+    }
   }
-}
-
-// Compact index of the pi-th pair of an excitation: zero bits inserted at the support
-// positions, then the from-pattern set.
-__device__ __forceinline__ uint32_t pair_index(uint32_t pi, const DevExc& x) {
-  uint32_t u = pi;
-  for (int q = 0; q < x.nsup; ++q) {
-    const uint32_t pos = (x.ins >> (5 * q)) & 31u;
-    u = ((u >> pos) << (pos + 1)) | (u & ((1u << pos) - 1u));
+  __device__ __forceinline__ void store(const double2* lds, double2* __restrict__ v, uint32_t base,
+                                        uint32_t tileN) const {
+    if constexpr (KT == 0) {
+      for (uint32_t c = threadIdx.x; c < tileN; c += T) v[base | dep(c, lmask)] = lds[c];
+    } else {
+      store_j(lds, v, base);
+    }
   }
-  return u | x.from_c;
-}
+};
 
 }  // namespace
 
@@ -102,183 +214,369 @@ __global__ void k_trig(const double* __restrict__ theta, double2* __restrict__ c
   }
 }
 
+// Shared-memory staging of a forward/reverse pass: its excitation records and their
+// (cos, sin) for the current batch entry.
+struct PassStage {
+  DevExc x[kMaxPassExc];
+  double2 cs[kMaxPassExc];
+};
+
 template <int T>
-__global__ __launch_bounds__(T) void k_fwd(const DevPass* __restrict__ passes, int pidx,
-                                           const DevExc* __restrict__ exc,
-                                           const double2* __restrict__ cs, int K,
-                                           double2* __restrict__ psi, int n, uint32_t hf, int init) {
+__device__ __forceinline__ void stage_records(PassStage& st, const DevPass& ps,
+                                              const DevExc* __restrict__ exc) {
+  for (int i = threadIdx.x; i < ps.count; i += T) st.x[i] = exc[ps.first + i];
+}
+
+template <int T>
+__device__ __forceinline__ void stage_cs(PassStage& st, const DevPass& ps,
+                                         const double2* __restrict__ cs, int K, int b) {
+  for (int i = threadIdx.x; i < ps.count; i += T) st.cs[i] = cs[(size_t)b * K + st.x[i].k];
+}
+
+// Copy `words` uint32 from global to LDS.
+template <int T>
+__device__ __forceinline__ void stage_words(uint32_t* dst, const uint32_t* __restrict__ src, int words) {
+  for (int i = threadIdx.x; i < words; i += T) dst[i] = src[i];
+}
+
+// Class of the tile with global-bit offset base (its pair-list block / in-sector list).
+__device__ __forceinline__ int tile_class(uint32_t base, uint32_t amask, uint32_t bmask, int nbg) {
+  return __popc(base & amask) * (nbg + 1) + __popc(base & bmask);
+}
+
+// The pass kernels hold one or two workgroups per CU (their LDS tile decides), i.e. T/256
+// waves per SIMD each: let the register allocator use the VGPRs that occupancy leaves.
+#define LDS_BOUND_OCCUPANCY __attribute__((amdgpu_waves_per_eu(T / 256, 2 * T / 256)))
+
+// The pass kernels are persistent over tiles: the grid holds as many workgroups as fit on
+// the device and each walks items (batch entry, tile) with stride gridDim.x (a multiple of
+// the tile count where possible, so a workgroup keeps one tile index and one class).  With
+// KT != 0 the next item's tile is fetched into registers while the current one is processed.
+//
+// Forward pass: for each excitation of the pass in Trotter order, a Givens rotation on the
+// tile's in-sector pairs (u, u ^ supp) listed in the class's pair block.
+template <int T, int KT, bool INIT>
+__global__ __launch_bounds__(T) LDS_BOUND_OCCUPANCY void k_fwd(
+    const DevPass* __restrict__ passes, int pidx, const DevExc* __restrict__ exc,
+    const int2* __restrict__ pcls, const uint32_t* __restrict__ pairs,
+    const double2* __restrict__ cs, int K, double2* __restrict__ psi, int n, uint32_t hf,
+    uint32_t amask, uint32_t bmask, int total) {
   extern __shared__ double2 lds[];
+  __shared__ PassStage st;
+  using TL = Tile<T, KT>;
   const DevPass ps = passes[pidx];
-  const int b = blockIdx.y;
-  const uint32_t base = dep(blockIdx.x, ps.gmask);
-  double2* __restrict__ v = psi + ((size_t)b << n);
   const uint32_t tileN = 1u << ps.k;
-  tile_load<T>(lds, v, base, ps.lmask, tileN, hf, init != 0);
-  __syncthreads();
-  for (int e = 0; e < ps.count; ++e) {
-    const DevExc x = exc[ps.first + e];
-    const double2 t = cs[(size_t)b * K + x.k];
-    const double c = t.x;
-    const double s = (parity(base & x.mglob) ? -t.y : t.y) * (double)x.sigma;
-    const uint32_t np = tileN >> x.nsup;
-    for (uint32_t pi = threadIdx.x; pi < np; pi += T) {
-      const uint32_t u = pair_index(pi, x);
-      const uint32_t w = u ^ x.supp_c;
-      const double sg = parity(u & x.mloc_c) ? -s : s;
-      const double2 a = lds[u], bb = lds[w];
-      lds[u] = make_double2(c * a.x - sg * bb.x, c * a.y - sg * bb.y);
-      lds[w] = make_double2(c * bb.x + sg * a.x, c * bb.y + sg * a.y);
+  const int tb = n - ps.k;
+  const uint32_t tmask = (1u << tb) - 1u;
+  uint32_t* blk = reinterpret_cast<uint32_t*>(lds + tileN);
+  const uint16_t* ent = reinterpret_cast<const uint16_t*>(blk + ps.count + 1);
+  const TL tm(ps.lmask);
+  stage_records<T>(st, ps, exc);
+  constexpr bool PF = KT != 0 && !INIT;  // register prefetch of the next tile
+  typename TL::Buf r;
+  int staged = -1;
+  int item = blockIdx.x;
+  if (PF && item < total) tm.fetch(r, psi + ((size_t)(item >> tb) << n), dep(item & tmask, ps.gmask));
+  for (; item < total; item += gridDim.x) {
+    const int b = item >> tb;
+    const uint32_t base = dep(item & tmask, ps.gmask);
+    double2* __restrict__ v = psi + ((size_t)b << n);
+    __syncthreads();  // LDS free: the previous item's store has read it
+    if (INIT)
+      tm.init_hf(lds, base, tileN, hf);
+    else if (PF)
+      tm.put(r, lds);
+    else
+      tm.load(lds, v, base, tileN);
+    const int next = item + gridDim.x;
+    if (PF) {  // the last item re-fetches itself (in bounds, unused) so r is written on every path
+      const int nf = next < total ? next : item;
+      tm.fetch(r, psi + ((size_t)(nf >> tb) << n), dep(nf & tmask, ps.gmask));
     }
+    const int cl = tile_class(base, amask, bmask, ps.nbeta_g);
+    if (cl != staged) {
+      const int2 bl = pcls[ps.cls_base + cl];
+      stage_words<T>(blk, pairs + bl.x, bl.y);
+      staged = cl;
+    }
+    stage_cs<T>(st, ps, cs, K, b);
     __syncthreads();
+    for (int e = 0; e < ps.count; ++e) {
+      const DevExc x = st.x[e];
+      const double2 t = st.cs[e];
+      const double c = t.x;
+      const double s = (parity(base & x.mglob) ? -t.y : t.y) * (double)x.sigma;
+      const int i1 = (int)blk[e + 1];
+      for (int i = (int)blk[e] + threadIdx.x; i < i1; i += T) {
+        const uint32_t u = ent[i];
+        const uint32_t w = u ^ x.supp_c;
+        const double sg = parity(u & x.mloc_c) ? -s : s;
+        const double2 a = lds[u], bb = lds[w];
+        lds[u] = make_double2(c * a.x - sg * bb.x, c * a.y - sg * bb.y);
+        lds[w] = make_double2(c * bb.x + sg * a.x, c * bb.y + sg * a.y);
+      }
+      __syncthreads();
+    }
+    tm.store(lds, v, base, tileN);
   }
-  tile_store<T>(lds, v, base, ps.lmask, tileN);
 }
 
 // Reverse pass: for each excitation (descending k) the partial of <lambda|G_k|psi> over the
-// tile, then psi, lambda <- exp(-theta_k G_k) (psi, lambda).
-template <int T>
-__global__ __launch_bounds__(T) void k_rev(const DevPass* __restrict__ passes, int pidx,
-                                           const DevExc* __restrict__ exc,
-                                           const double2* __restrict__ cs, int K,
-                                           double2* __restrict__ psi, double2* __restrict__ lam,
-                                           int n, double* __restrict__ gpart, int ntiles) {
+// tile's in-sector pairs, then psi, lambda <- exp(-theta_k G_k) (psi, lambda).
+template <int T, int KT>
+__global__ __launch_bounds__(T) LDS_BOUND_OCCUPANCY void k_rev(
+    const DevPass* __restrict__ passes, int pidx, const DevExc* __restrict__ exc,
+    const int2* __restrict__ pcls, const uint32_t* __restrict__ pairs,
+    const double2* __restrict__ cs, int K, double2* __restrict__ psi, double2* __restrict__ lam,
+    int n, uint32_t amask, uint32_t bmask, double* __restrict__ gpart, int total) {
   extern __shared__ double2 lds[];
   constexpr int NW = T / 64;
+  __shared__ PassStage st;
+  __shared__ double red[2][NW];
+  using TL = Tile<T, KT>;
   const DevPass ps = passes[pidx];
-  const int b = blockIdx.y;
-  const uint32_t base = dep(blockIdx.x, ps.gmask);
   const uint32_t tileN = 1u << ps.k;
+  const int tb = n - ps.k;
+  const uint32_t tmask = (1u << tb) - 1u;
+  const int ntiles = 1 << tb;
   double2* lp = lds;
   double2* ll = lds + tileN;
-  double* red = reinterpret_cast<double*>(lds + 2 * tileN);  // [2][NW]
-  double2* __restrict__ vp = psi + ((size_t)b << n);
-  double2* __restrict__ vl = lam + ((size_t)b << n);
-  tile_load<T>(lp, vp, base, ps.lmask, tileN, 0, false);
-  tile_load<T>(ll, vl, base, ps.lmask, tileN, 0, false);
-  __syncthreads();
+  uint32_t* blk = reinterpret_cast<uint32_t*>(lds + 2 * tileN);
+  const uint16_t* ent = reinterpret_cast<const uint16_t*>(blk + ps.count + 1);
+  const TL tm(ps.lmask);
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  int prev_k = -1;
-  for (int e = 0; e < ps.count; ++e) {
-    const DevExc x = exc[ps.first + e];
-    const double2 t = cs[(size_t)b * K + x.k];
-    const double c = t.x;
-    const double sgn0 = (parity(base & x.mglob) ? -1.0 : 1.0) * (double)x.sigma;
-    const uint32_t np = tileN >> x.nsup;
-    double g = 0.0;
-    for (uint32_t pi = threadIdx.x; pi < np; pi += T) {
-      const uint32_t u = pair_index(pi, x);
-      const uint32_t w = u ^ x.supp_c;
-      const double sg = parity(u & x.mloc_c) ? -sgn0 : sgn0;
-      const double2 pu = lp[u], pw = lp[w], lu = ll[u], lw = ll[w];
-      g += sg * ((lw.x * pu.x + lw.y * pu.y) - (lu.x * pw.x + lu.y * pw.y));
-      const double s = sg * t.y;
-      lp[u] = make_double2(c * pu.x + s * pw.x, c * pu.y + s * pw.y);
-      lp[w] = make_double2(c * pw.x - s * pu.x, c * pw.y - s * pu.y);
-      ll[u] = make_double2(c * lu.x + s * lw.x, c * lu.y + s * lw.y);
-      ll[w] = make_double2(c * lw.x - s * lu.x, c * lw.y - s * lu.y);
-    }
-    g = wave_sum<T>(g);
-    if (lane == 0) red[(e & 1) * NW + wv] = g;
-    // thread 0 folds the previous excitation's wave sums while the others proceed
-    if (threadIdx.x == 0 && prev_k >= 0) {
-      double s = 0.0;
-      for (int i = 0; i < NW; ++i) s += red[((e - 1) & 1) * NW + i];
-      gpart[((size_t)b * K + prev_k) * ntiles + blockIdx.x] = s;
-    }
-    prev_k = x.k;
+  stage_records<T>(st, ps, exc);
+  typename TL::Buf rp, rl;
+  int staged = -1;
+  int item = blockIdx.x;
+  if (KT && item < total) {
+    const size_t vo = (size_t)(item >> tb) << n;
+    const uint32_t bs = dep(item & tmask, ps.gmask);
+    tm.fetch(rp, psi + vo, bs);
+    tm.fetch(rl, lam + vo, bs);
+  }
+  for (; item < total; item += gridDim.x) {
+    const int b = item >> tb;
+    const uint32_t t = item & tmask;
+    const uint32_t base = dep(t, ps.gmask);
+    double2* __restrict__ vp = psi + ((size_t)b << n);
+    double2* __restrict__ vl = lam + ((size_t)b << n);
     __syncthreads();
+    if (KT) {
+      tm.put(rp, lp);
+      tm.put(rl, ll);
+    } else {
+      tm.load(lp, vp, base, tileN);
+      tm.load(ll, vl, base, tileN);
+    }
+    const int next = item + gridDim.x;
+    if (KT) {  // the last item re-fetches itself (in bounds, unused) so rp/rl are always written
+      const int nf = next < total ? next : item;
+      const size_t vo = (size_t)(nf >> tb) << n;
+      const uint32_t bs = dep(nf & tmask, ps.gmask);
+      tm.fetch(rp, psi + vo, bs);
+      tm.fetch(rl, lam + vo, bs);
+    }
+    const int cl = tile_class(base, amask, bmask, ps.nbeta_g);
+    if (cl != staged) {
+      const int2 bl = pcls[ps.cls_base + cl];
+      stage_words<T>(blk, pairs + bl.x, bl.y);
+      staged = cl;
+    }
+    stage_cs<T>(st, ps, cs, K, b);
+    __syncthreads();
+    int prev_k = -1, prev_e = 0;
+    for (int e = 0; e < ps.count; ++e) {
+      const DevExc x = st.x[e];
+      const double2 tt = st.cs[e];
+      const double c = tt.x;
+      const double sgn0 = (parity(base & x.mglob) ? -1.0 : 1.0) * (double)x.sigma;
+      const int i0 = (int)blk[e], i1 = (int)blk[e + 1];
+      double g = 0.0;
+      if (i0 + wv * 64 < i1) {  // this wave has pairs of this excitation
+        for (int i = i0 + threadIdx.x; i < i1; i += T) {
+          const uint32_t u = ent[i];
+          const uint32_t w = u ^ x.supp_c;
+          const double sg = parity(u & x.mloc_c) ? -sgn0 : sgn0;
+          const double2 pu = lp[u], pw = lp[w], lu = ll[u], lw = ll[w];
+          g += sg * ((lw.x * pu.x + lw.y * pu.y) - (lu.x * pw.x + lu.y * pw.y));
+          const double s = sg * tt.y;
+          lp[u] = make_double2(c * pu.x + s * pw.x, c * pu.y + s * pw.y);
+          lp[w] = make_double2(c * pw.x - s * pu.x, c * pw.y - s * pu.y);
+          ll[u] = make_double2(c * lu.x + s * lw.x, c * lu.y + s * lw.y);
+          ll[w] = make_double2(c * lw.x - s * lu.x, c * lw.y - s * lu.y);
+        }
+        g = wave_sum(g);
+      }
+      if (lane == 0) red[e & 1][wv] = g;
+      // thread 0 folds the previous excitation's wave sums while the others proceed
+      if (threadIdx.x == 0 && prev_k >= 0) {
+        double sum = 0.0;
+        for (int i = 0; i < NW; ++i) sum += red[prev_e & 1][i];
+        gpart[((size_t)b * K + prev_k) * ntiles + t] = sum;
+      }
+      prev_k = x.k;
+      prev_e = e;
+      __syncthreads();
+    }
+    if (threadIdx.x == 0 && prev_k >= 0) {
+      double sum = 0.0;
+      for (int i = 0; i < NW; ++i) sum += red[prev_e & 1][i];
+      gpart[((size_t)b * K + prev_k) * ntiles + t] = sum;
+    }
+    tm.store(lp, vp, base, tileN);
+    tm.store(ll, vl, base, tileN);
   }
-  if (threadIdx.x == 0 && prev_k >= 0) {
-    double s = 0.0;
-    for (int i = 0; i < NW; ++i) s += red[((ps.count - 1) & 1) * NW + i];
-    gpart[((size_t)b * K + prev_k) * ntiles + blockIdx.x] = s;
-  }
-  tile_store<T>(lp, vp, base, ps.lmask, tileN);
-  tile_store<T>(ll, vl, base, ps.lmask, tileN);
 }
 
-// Expectation / apply-H pass.  Each thread takes in-sector basis states u of the tile (only
-// those can be non-zero: the HF state has N = n_elec, S_z = 0 and every factor and every
-// Hamiltonian term conserves both) and gathers
+// Expectation / apply-H pass.  Only in-sector basis states u of a tile can be non-zero (the
+// HF state has N = n_elec, S_z = 0 and every factor and every Hamiltonian term conserves
+// both).  Each in-sector u is handled by a quad of lanes; lane s of the quad gathers
 //     (H psi)[u] += <u|H_g|u ^ x_g> psi[u ^ x_g]
-// over the groups of the pass, with the matrix element evaluated at the source state
-// v = u ^ x_g from the compiled group table.  The energy partial is
-// sum_u Re(conj(psi[u]) (H psi)[u]).  With APPLY the gathered values are added into lambda
-// (first pass: written).
-template <int T, bool APPLY>
-__global__ __launch_bounds__(T) void k_exp(const DevPass* __restrict__ passes, int pidx,
-                                           const DevGroup* __restrict__ groups,
-                                           const double* __restrict__ occ,
-                                           const double* __restrict__ diag,
+// over every fourth group of the pass (matrix element evaluated at the source state
+// v = u ^ x_g from the compiled group table), and the quad adds its four partial sums in a
+// fixed order.  The energy partial is sum_u Re(conj(psi[u]) (H psi)[u]).  With APPLY the
+// gathered values are added into lambda (first pass: written).
+//
+// The pass's group tables arrive as one blob (layout: ExpBlob in ucc_internal.h) that each
+// workgroup copies into LDS behind the tile once.
+template <int T, int KT, bool APPLY>
+__global__ __launch_bounds__(T) LDS_BOUND_OCCUPANCY void k_exp(const DevPass* __restrict__ passes, int pidx,
+                                           const uint4* __restrict__ blobs,
                                            const int2* __restrict__ cls,
                                            const uint2* __restrict__ list,
                                            const double2* __restrict__ psi,
                                            double2* __restrict__ lam, int n, uint32_t amask,
                                            uint32_t bmask, double* __restrict__ epart,
-                                           int estride, int first) {
+                                           int estride, int first, int total) {
   extern __shared__ double2 lds[];
+  using TL = Tile<T, KT>;
   const DevPass ps = passes[pidx];
-  const int b = blockIdx.y;
-  const uint32_t base = dep(blockIdx.x, ps.gmask);
   const uint32_t tileN = 1u << ps.k;
-  double* red = reinterpret_cast<double*>(lds + tileN);
-  const double2* __restrict__ vp = psi + ((size_t)b << n);
-  double2* __restrict__ vl = lam + ((size_t)b << n);
-  tile_load<T>(lds, vp, base, ps.lmask, tileN, 0, false);
-  const int ag = __popc(base & amask), bg = __popc(base & bmask);
-  const int2 cl = cls[ps.cls_base + ag * (ps.nbeta_g + 1) + bg];
-  __syncthreads();
-  double eacc = 0.0;
-  for (int it = threadIdx.x; it < cl.y; it += T) {
-    const uint2 ent = list[cl.x + it];
-    const uint32_t c = ent.x;
-    const uint32_t u = base | ent.y;
-    const double2 pu = lds[c];
-    double ax = 0.0, ay = 0.0;
-    for (int gi = 0; gi < ps.count; ++gi) {
-      const DevGroup& G = groups[ps.first + gi];
-      if (G.nsup == 0) {
-        double f = diag[0];
+  const int tb = n - ps.k;
+  const uint32_t tmask = (1u << tb) - 1u;
+  uint4* lb = reinterpret_cast<uint4*>(lds + tileN);
+  const uint4* __restrict__ gb = blobs + ps.blob_off;
+  for (int i = threadIdx.x; i < ps.blob_len; i += T) lb[i] = gb[i];
+  uint2* lst = reinterpret_cast<uint2*>(lb + ps.blob_len);  // the class's in-sector list
+  double* red = reinterpret_cast<double*>(lst + ps.stage_len);
+  int staged = -1, nlist = 0;
+  const uint32_t* bw = reinterpret_cast<const uint32_t*>(lb);
+  const TL tm(ps.lmask);
+  const int sub = threadIdx.x & 3;
+  typename TL::Buf r;
+  int item = blockIdx.x;
+  if (KT && item < total) tm.fetch(r, psi + ((size_t)(item >> tb) << n), dep(item & tmask, ps.gmask));
+  for (; item < total; item += gridDim.x) {
+    const int b = item >> tb;
+    const uint32_t t = item & tmask;
+    const uint32_t base = dep(t, ps.gmask);
+    const double2* __restrict__ vp = psi + ((size_t)b << n);
+    __syncthreads();
+    if (KT)
+      tm.put(r, lds);
+    else
+      tm.load(lds, vp, base, tileN);
+    const int next = item + gridDim.x;
+    if (KT) {  // the last item re-fetches itself (in bounds, unused) so r is always written
+      const int nf = next < total ? next : item;
+      tm.fetch(r, psi + ((size_t)(nf >> tb) << n), dep(nf & tmask, ps.gmask));
+    }
+    const int cli = tile_class(base, amask, bmask, ps.nbeta_g);
+    if (cli != staged) {
+      const int2 cl = cls[ps.cls_base + cli];
+      for (int i = threadIdx.x; i < cl.y; i += T) lst[i] = list[cl.x + i];
+      nlist = cl.y;
+      staged = cli;
+    }
+    __syncthreads();
+    const int nd = (int)bw[0], no = (int)bw[1], npl = (int)bw[2];
+    const uint4* occr = reinterpret_cast<const uint4*>(bw + bw[3]);
+    const uint4* plr = reinterpret_cast<const uint4*>(bw + bw[4]);
+    const double* dg = reinterpret_cast<const double*>(bw + bw[5]);
+    const double* dw = reinterpret_cast<const double*>(bw);  // double view of the blob
+    double eacc = 0.0;
+    for (int it = threadIdx.x >> 2; it < nlist; it += T / 4) {
+      const uint2 ent = lst[it];
+      const uint32_t c = ent.x;
+      const uint32_t u = base | ent.y;
+      const double2 pu = lds[c];
+      double2 old = make_double2(0.0, 0.0);
+      if (APPLY && !first && sub == 0) old = lam[((size_t)b << n) + u];  // in flight meanwhile
+      double ax = 0.0, ay = 0.0;
+      if (nd) {  // diagonal c0 + sum_r a_r n_r + sum_{r<s} b_rs n_r n_s; set bits split by rank
+        double f = sub == 0 ? dg[0] : 0.0;
         uint32_t rem = u;
+        int rank = 0;
         while (rem) {
           const int q = __ffs(rem) - 1;
           rem &= rem - 1;
-          f += diag[1 + q];
-          const double* brow = diag + 1 + n + q * n;
-          for (uint32_t r2 = rem; r2; r2 &= r2 - 1) f += brow[__ffs(r2) - 1];
+          if ((rank++ & 3) == sub) {
+            f += dg[1 + q];
+            const double* brow = dg + 1 + n + q * n;
+            for (uint32_t r2 = rem; r2; r2 &= r2 - 1) f += brow[__ffs(r2) - 1];
+          }
         }
         ax += f * pu.x;
         ay += f * pu.y;
-        continue;
       }
-      uint32_t P = 0;
-      for (int q = 0; q < G.nsup; ++q) P |= ((u >> ((G.spos >> (5 * q)) & 31u)) & 1u) << q;
-      if ((G.valid >> P) & 1u) {
-        const uint32_t Pv = P ^ ((1u << G.nsup) - 1u);
-        double val = G.A[Pv];
-        if (G.occ >= 0) {
-          const double* Bt = occ + G.occ + Pv * n;
-          for (uint32_t r = u & ~G.xphys; r; r &= r - 1) val += Bt[__ffs(r) - 1];
+      // groups with occupation-number terms: lane `sub` of the quad takes every fourth one
+      for (int gb = 0; gb < no; gb += 4) {
+        const int g = gb + sub;
+        if (g < no) {
+          const uint4 ha = occr[2 * g], hb = occr[2 * g + 1];  // {xc, xphys, m, valid}, {spos, nsup, occ, a}
+          const uint32_t spos = hb.x, nsup = hb.y;
+          uint32_t P = ((u >> (spos & 31u)) & 1u) | (((u >> ((spos >> 5) & 31u)) & 1u) << 1);
+          if (nsup == 4)
+            P |= (((u >> ((spos >> 10) & 31u)) & 1u) << 2) | (((u >> ((spos >> 15) & 31u)) & 1u) << 3);
+          if ((ha.w >> P) & 1u) {
+            const uint32_t Pv = P ^ ((1u << nsup) - 1u);
+            const uint32_t slot = __popc(ha.w & ((1u << Pv) - 1u));
+            double val = dw[(hb.w >> 1) + slot];
+            const double* Bt = dw + (hb.z >> 1) + slot * n;
+            for (uint32_t rr = u & ~ha.y; rr; rr &= rr - 1) val += Bt[__ffs(rr) - 1];
+            if (parity(u & ha.z)) val = -val;
+            const double2 pw = lds[c ^ ha.x];
+            ax += val * pw.x;
+            ay += val * pw.y;
+          }
         }
-        if (parity(u & G.m)) val = -val;
-        const double2 pw = lds[c ^ G.xc];
-        ax += val * pw.x;
-        ay += val * pw.y;
+      }
+      // plain groups (+-A[pattern]); the next record is fetched while this one is used
+      uint4 hn = sub < npl ? plr[sub] : make_uint4(0u, 0u, 0u, 0u);
+      for (int gb = 0; gb < npl; gb += 4) {
+        const int g = gb + sub;
+        const uint4 h = hn;  // {xc | size4 << 31, spos, m, valid | a << 16}
+        if (g + 4 < npl) hn = plr[g + 4];
+        if (g < npl) {
+          const uint32_t spos = h.y;
+          uint32_t P = ((u >> (spos & 31u)) & 1u) | (((u >> ((spos >> 5) & 31u)) & 1u) << 1);
+          uint32_t full = 3u;
+          if (h.x >> 31) {
+            P |= (((u >> ((spos >> 10) & 31u)) & 1u) << 2) | (((u >> ((spos >> 15) & 31u)) & 1u) << 3);
+            full = 15u;
+          }
+          const uint32_t valid = h.w & 0xffffu;
+          if ((valid >> P) & 1u) {
+            const uint32_t Pv = P ^ full;
+            double val = dw[(h.w >> 17) + __popc(valid & ((1u << Pv) - 1u))];
+            if (parity(u & h.z)) val = -val;
+            const double2 pw = lds[c ^ (h.x & 0x7fffffffu)];
+            ax += val * pw.x;
+            ay += val * pw.y;
+          }
+        }
+      }
+      ax = quad_sum(ax);
+      ay = quad_sum(ay);
+      if (sub == 0) {
+        eacc += pu.x * ax + pu.y * ay;
+        if (APPLY) lam[((size_t)b << n) + u] = make_double2(old.x + ax, old.y + ay);
       }
     }
-    eacc += pu.x * ax + pu.y * ay;
-    if (APPLY) {
-      double2 o = make_double2(ax, ay);
-      if (!first) {
-        const double2 old = vl[u];
-        o.x += old.x;
-        o.y += old.y;
-      }
-      vl[u] = o;
-    }
+    const double s = block_sum<T>(eacc, red);
+    if (threadIdx.x == 0) epart[(size_t)b * estride + t] = s;
   }
-  const double s = block_sum<T>(eacc, red);
-  if (threadIdx.x == 0) epart[(size_t)b * estride + blockIdx.x] = s;
 }
 
 // Fixed-order reductions.  epart: [B][ne] energy partials; gpart: [B][K][nt] gradient partials.
@@ -312,39 +610,113 @@ hipError_t set_lds(F kernel, size_t bytes) {
                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
 }
 
-template <int T>
-hipError_t fwd_t(const LaunchArgs& a, int pidx, int k, int init) {
-  const size_t lds = sizeof(double2) << k;
-  hipError_t e = set_lds(k_fwd<T>, lds);
+// Workgroups that fit on the device at once for this kernel and LDS size (cached).
+template <typename F>
+int resident_grid(F kernel, int threads, size_t lds) {
+  static std::mutex mu;
+  static std::map<std::pair<const void*, size_t>, int> cache;
+  static int cus = 0;
+  const auto key = std::make_pair(reinterpret_cast<const void*>(kernel), lds);
+  std::lock_guard<std::mutex> lock(mu);
+  auto it = cache.find(key);
+  if (it != cache.end()) return it->second;
+  if (cus == 0) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0)
+      cus = 256;
+  }
+  int per = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, reinterpret_cast<const void*>(kernel),
+                                                   threads, lds) != hipSuccess || per <= 0)
+    per = 1;
+  (void)hipGetLastError();
+  const int g = per * cus;
+  cache[key] = g;
+  return g;
+}
+
+// Grid of a persistent pass: resident workgroups, rounded down to a multiple of the tile
+// count when at least one full round of tiles fits (then each workgroup keeps one tile).
+inline int pass_grid(int total, int resident, int ntiles) {
+  int g = std::min(total, resident);
+  if (g >= ntiles) g -= g % ntiles;
+  return std::max(g, 1);
+}
+
+template <int T, int KT, bool INIT>
+hipError_t fwd_ti(const LaunchArgs& a, int pidx) {
+  const DevPass& hp = a.hpasses[pidx];
+  const int k = hp.k;
+  const size_t lds = (sizeof(double2) << k) + 4 * size_t(hp.stage_len);
+  hipError_t e = set_lds(k_fwd<T, KT, INIT>, lds);
   if (e != hipSuccess) return e;
-  dim3 grid(1u << (a.n - k), a.B);
-  hipLaunchKernelGGL(k_fwd<T>, grid, dim3(T), lds, a.stream, a.passes, pidx, a.exc, a.cs, a.K,
-                     a.psi, a.n, a.hf, init);
+  const int total = a.B << (a.n - k);
+  const int grid = KT ? pass_grid(total, resident_grid(k_fwd<T, KT, INIT>, T, lds), 1 << (a.n - k))
+                      : total;
+  hipLaunchKernelGGL((k_fwd<T, KT, INIT>), dim3(grid), dim3(T), lds, a.stream, a.passes, pidx,
+                     a.exc, a.cls, a.pairs, a.cs, a.K, a.psi, a.n, a.hf, a.amask, a.bmask, total);
   return hipGetLastError();
 }
 
-template <int T>
-hipError_t rev_t(const LaunchArgs& a, int pidx, int k) {
-  const size_t lds = (2 * sizeof(double2) << k) + 2 * (T / 64) * sizeof(double);
-  hipError_t e = set_lds(k_rev<T>, lds);
+template <int T, int KT>
+hipError_t fwd_t(const LaunchArgs& a, int pidx, int init) {
+  return init ? fwd_ti<T, KT, true>(a, pidx) : fwd_ti<T, KT, false>(a, pidx);
+}
+
+template <int T, int KT>
+hipError_t rev_t(const LaunchArgs& a, int pidx) {
+  const DevPass& hp = a.hpasses[pidx];
+  const int k = hp.k;
+  const size_t lds = (2 * sizeof(double2) << k) + 4 * size_t(hp.stage_len);
+  hipError_t e = set_lds(k_rev<T, KT>, lds);
   if (e != hipSuccess) return e;
-  dim3 grid(1u << (a.n - k), a.B);
-  hipLaunchKernelGGL(k_rev<T>, grid, dim3(T), lds, a.stream, a.passes, pidx, a.exc, a.cs, a.K,
-                     a.psi, a.lam, a.n, a.gpart, 1 << (a.n - k));
+  const int total = a.B << (a.n - k);
+  const int grid = KT ? pass_grid(total, resident_grid(k_rev<T, KT>, T, lds), 1 << (a.n - k)) : total;
+  hipLaunchKernelGGL((k_rev<T, KT>), dim3(grid), dim3(T), lds, a.stream, a.passes, pidx, a.exc,
+                     a.cls, a.pairs, a.cs, a.K, a.psi, a.lam, a.n, a.amask, a.bmask, a.gpart,
+                     total);
   return hipGetLastError();
+}
+
+template <int T, int KT, bool APPLY>
+hipError_t exp_t(const LaunchArgs& a, int pidx, int eslot, int first) {
+  const DevPass& hp = a.hpasses[pidx];
+  const int k = hp.k;
+  const size_t lds = (sizeof(double2) << k) + 16 * size_t(hp.blob_len) + 8 * size_t(hp.stage_len) +
+                     (T / 64) * sizeof(double);
+  hipError_t e = set_lds(k_exp<T, KT, APPLY>, lds);
+  if (e != hipSuccess) return e;
+  const int total = a.B << (a.n - k);
+  const int grid =
+      KT ? pass_grid(total, resident_grid(k_exp<T, KT, APPLY>, T, lds), 1 << (a.n - k)) : total;
+  hipLaunchKernelGGL((k_exp<T, KT, APPLY>), dim3(grid), dim3(T), lds, a.stream, a.passes, pidx,
+                     a.blobs, a.cls, a.list, a.psi, a.lam, a.n, a.amask, a.bmask,
+                     a.epart + (size_t)eslot, a.estride, first, total);
+  return hipGetLastError();
+}
+
+// Tile-size dispatch: unrolled register staging for k = 12 and 13, a loop otherwise.
+template <int T>
+hipError_t fwd_k(const LaunchArgs& a, int pidx, int init) {
+  const int k = a.hpasses[pidx].k;
+  if (k == 13) return fwd_t<T, 13>(a, pidx, init);
+  if (k == 12) return fwd_t<T, 12>(a, pidx, init);
+  return fwd_t<T, 0>(a, pidx, init);
+}
+
+template <int T>
+hipError_t rev_k(const LaunchArgs& a, int pidx) {
+  if (a.hpasses[pidx].k == 12) return rev_t<T, 12>(a, pidx);
+  return rev_t<T, 0>(a, pidx);
 }
 
 template <int T, bool APPLY>
-hipError_t exp_t(const LaunchArgs& a, int pidx, int k, int eslot, int first) {
-  const size_t lds = (sizeof(double2) << k) + (T / 64) * sizeof(double);
-  hipError_t e = set_lds(k_exp<T, APPLY>, lds);
-  if (e != hipSuccess) return e;
-  const int nt = 1 << (a.n - k);
-  dim3 grid(nt, a.B);
-  hipLaunchKernelGGL((k_exp<T, APPLY>), grid, dim3(T), lds, a.stream, a.passes, pidx, a.groups,
-                     a.occ, a.diag, a.cls, a.list, a.psi, a.lam, a.n, a.amask, a.bmask,
-                     a.epart + (size_t)eslot, a.estride, first);
-  return hipGetLastError();
+hipError_t exp_k(const LaunchArgs& a, int pidx, int eslot, int first) {
+  const int k = a.hpasses[pidx].k;
+  if (k == 13) return exp_t<T, 13, APPLY>(a, pidx, eslot, first);
+  if (k == 12) return exp_t<T, 12, APPLY>(a, pidx, eslot, first);
+  return exp_t<T, 0, APPLY>(a, pidx, eslot, first);
 }
 
 }  // namespace
@@ -355,34 +727,34 @@ hipError_t launch_trig(const LaunchArgs& a, const double* theta) {
   return hipGetLastError();
 }
 
-hipError_t launch_fwd(const LaunchArgs& a, int pidx, int k, int init) {
+hipError_t launch_fwd(const LaunchArgs& a, int pidx, int init) {
   switch (a.threads) {
-    case 256: return fwd_t<256>(a, pidx, k, init);
-    case 1024: return fwd_t<1024>(a, pidx, k, init);
-    default: return fwd_t<512>(a, pidx, k, init);
+    case 256: return fwd_k<256>(a, pidx, init);
+    case 1024: return fwd_k<1024>(a, pidx, init);
+    default: return fwd_k<512>(a, pidx, init);
   }
 }
 
-hipError_t launch_rev(const LaunchArgs& a, int pidx, int k) {
+hipError_t launch_rev(const LaunchArgs& a, int pidx) {
   switch (a.threads) {
-    case 256: return rev_t<256>(a, pidx, k);
-    case 1024: return rev_t<1024>(a, pidx, k);
-    default: return rev_t<512>(a, pidx, k);
+    case 256: return rev_k<256>(a, pidx);
+    case 1024: return rev_k<1024>(a, pidx);
+    default: return rev_k<512>(a, pidx);
   }
 }
 
-hipError_t launch_exp(const LaunchArgs& a, int pidx, int k, int eslot, int first, bool apply) {
+hipError_t launch_exp(const LaunchArgs& a, int pidx, int eslot, int first, bool apply) {
   if (apply) {
     switch (a.threads) {
-      case 256: return exp_t<256, true>(a, pidx, k, eslot, first);
-      case 1024: return exp_t<1024, true>(a, pidx, k, eslot, first);
-      default: return exp_t<512, true>(a, pidx, k, eslot, first);
+      case 256: return exp_k<256, true>(a, pidx, eslot, first);
+      case 1024: return exp_k<1024, true>(a, pidx, eslot, first);
+      default: return exp_k<512, true>(a, pidx, eslot, first);
     }
   }
   switch (a.threads) {
-    case 256: return exp_t<256, false>(a, pidx, k, eslot, first);
-    case 1024: return exp_t<1024, false>(a, pidx, k, eslot, first);
-    default: return exp_t<512, false>(a, pidx, k, eslot, first);
+    case 256: return exp_k<256, false>(a, pidx, eslot, first);
+    case 1024: return exp_k<1024, false>(a, pidx, eslot, first);
+    default: return exp_k<512, false>(a, pidx, eslot, first);
   }
 }
 

@@ -4,6 +4,7 @@
 // Nothing here runs per evaluation; ucc_build calls it once per Hamiltonian.
 #include <algorithm>
 #include <cmath>
+#include <cstring>
 #include <map>
 #include <set>
 #include <sstream>
@@ -96,7 +97,7 @@ std::vector<Plan::Pass> plan_windows(const Plan& p, int kind, int k, int c0) {
   for (int t = 0; t < p.K; ++t) {
     const int e = (kind == kRev) ? p.K - 1 - t : t;
     const uint32_t s = p.ex[e].supp;
-    if (!cur.items.empty() && pc32(cur.lmask | s) > k) {
+    if (!cur.items.empty() && (pc32(cur.lmask | s) > k || (int)cur.items.size() >= kMaxPassExc)) {
       close();
       cur.items.clear();
       cur.lmask = F;
@@ -239,6 +240,11 @@ std::string build_plan(Plan& p, int n, int ne, const double* h1, const double* h
   p.K = K;
   p.nalpha = p.nbeta = ne / 2;
   const int ns = p.ns;
+  {
+    uint64_t cnk = 1;  // C(ns, nalpha)
+    for (int i = 0; i < p.nalpha; ++i) cnk = cnk * (ns - i) / (i + 1);
+    p.nsec = cnk * cnk;
+  }
   p.h1.assign(h1, h1 + ns * ns);
   p.h2.assign(h2, h2 + ns * ns * ns * ns);
   p.exc.assign(exc, exc + 4 * K);
@@ -449,6 +455,54 @@ std::string build_plan(Plan& p, int n, int ne, const double* h1, const double* h
       }
     }
   }
+  {
+    // keep tile + blob + staged class list + reduction slots inside one workgroup's LDS:
+    // split passes whose group tables would not fit (same local set, groups in order)
+    std::vector<Plan::Pass> split;
+    for (auto& ps : ex) {
+      const int budget = kLdsBytes - (16 << p.kf) - 8 * max_class_size(p, ps.lmask) - 256;
+      Plan::Pass cur;
+      cur.kind = kExp;
+      cur.lmask = ps.lmask;
+      for (int g : ps.items) {
+        cur.items.push_back(g);
+        if (cur.items.size() > 1 && exp_blob_bytes(p, cur.items) > budget) {
+          cur.items.pop_back();
+          split.push_back(cur);
+          cur.items.assign(1, g);
+        }
+      }
+      if (exp_blob_bytes(p, cur.items) > budget) return "tile too large for the expectation tables";
+      split.push_back(cur);
+    }
+    ex.swap(split);
+  }
+  // forward/reverse windows whose largest pair-list block would not fit next to the tile(s)
+  // are halved (same local set, order kept)
+  auto fit_blocks = [&](std::vector<Plan::Pass>& ws, int tile_bytes) -> bool {
+    const int budget_words = (kLdsBytes - tile_bytes - kStageBytes - 1024) / 4;
+    std::vector<Plan::Pass> out;
+    std::vector<Plan::Pass> todo(ws.rbegin(), ws.rend());
+    while (!todo.empty()) {
+      Plan::Pass w = todo.back();
+      todo.pop_back();
+      if (max_pair_block_words(p, w.lmask, w.items) <= budget_words) {
+        out.push_back(w);
+        continue;
+      }
+      if (w.items.size() < 2) return false;
+      Plan::Pass a = w, b = w;
+      const size_t h = w.items.size() / 2;
+      a.items.assign(w.items.begin(), w.items.begin() + h);
+      b.items.assign(w.items.begin() + h, w.items.end());
+      todo.push_back(b);
+      todo.push_back(a);
+    }
+    ws.swap(out);
+    return true;
+  };
+  if (!fit_blocks(fw, 16 << p.kf) || !fit_blocks(rv, 32 << p.kr))
+    return "tile too large for the pair lists of one excitation";
   p.nfwd = (int)fw.size();
   p.nexp = (int)ex.size();
   p.nrev = (int)rv.size();
@@ -459,19 +513,100 @@ std::string build_plan(Plan& p, int n, int ne, const double* h1, const double* h
   return "";
 }
 
+namespace {
+
+// Order of groups inside an expectation blob: diagonal, occupation-term groups, plain.
+std::vector<int> blob_order(const Plan& p, const std::vector<int>& items) {
+  std::vector<int> out;
+  for (int g : items)
+    if (g == 0) out.push_back(g);
+  for (int g : items)
+    if (g != 0 && p.groups[g].has_occ) out.push_back(g);
+  for (int g : items)
+    if (g != 0 && !p.groups[g].has_occ) out.push_back(g);
+  return out;
+}
+
+// Words of a blob: header, group headers, one double per valid pattern (plus n per valid
+// pattern for occupation rows), the diagonal table.
+size_t blob_words(const Plan& p, const std::vector<int>& items) {
+  size_t w = ExpBlob::kHeaderWords;
+  for (int g : items) {
+    if (g == 0) {
+      w += 2 * (1 + p.n + p.n * p.n);
+    } else {
+      const size_t nv = __builtin_popcount(p.groups[g].valid);
+      w += 2 * nv;
+      if (p.groups[g].has_occ)
+        w += ExpBlob::kOccWords + 2 * nv * p.n;
+      else
+        w += ExpBlob::kPlainWords;
+    }
+  }
+  return ((w + 3) & ~size_t(3)) + 4;  // slack for the 16-byte alignment of the plain records
+}
+
+// In-sector local compact indices of a tile with local bits lmask, bucketed by the class
+// (alpha, beta electron counts of the global bits): bucket ag * (nbg + 1) + bg.
+std::vector<std::vector<std::pair<uint32_t, uint32_t>>> class_buckets(const Plan& p, uint32_t lmask,
+                                                                      int* nbg_out = nullptr) {
+  const uint32_t full = (p.n >= 32) ? 0xffffffffu : ((1u << p.n) - 1u);
+  const uint32_t gmask = full & ~lmask;
+  const int nag = pc32(gmask & p.amask), nbg = pc32(gmask & p.bmask);
+  if (nbg_out) *nbg_out = nbg;
+  std::vector<std::vector<std::pair<uint32_t, uint32_t>>> buckets((nag + 1) * (nbg + 1));
+  const uint32_t tile = 1u << pc32(lmask);
+  for (uint32_t c = 0; c < tile; ++c) {
+    const uint32_t ph = deposit_bits(c, lmask);
+    const int ag = p.nalpha - pc32(ph & p.amask);
+    const int bg = p.nbeta - pc32(ph & p.bmask);
+    if (ag < 0 || bg < 0 || ag > nag || bg > nbg) continue;
+    buckets[ag * (nbg + 1) + bg].push_back({c, ph});
+  }
+  return buckets;
+}
+
+// Pair-list block (see ucc_internal.h) of excitations `items` for one class bucket.
+std::vector<uint32_t> pair_block(const Plan& p, uint32_t lmask, const std::vector<int>& items,
+                                 const std::vector<std::pair<uint32_t, uint32_t>>& bucket) {
+  const size_t m = items.size();
+  std::vector<uint32_t> off(m + 1, 0);
+  std::vector<uint16_t> ent;
+  for (size_t j = 0; j < m; ++j) {
+    const auto& e = p.ex[items[j]];
+    const uint32_t sc = compact_bits(e.supp, lmask), fc = compact_bits(e.from, lmask);
+    for (auto& cp : bucket)
+      if ((cp.first & sc) == fc) ent.push_back((uint16_t)cp.first);
+    off[j + 1] = (uint32_t)ent.size();
+  }
+  std::vector<uint32_t> w(off);
+  for (size_t i = 0; i < ent.size(); i += 2)
+    w.push_back(uint32_t(ent[i]) | (i + 1 < ent.size() ? uint32_t(ent[i + 1]) << 16 : 0u));
+  return w;
+}
+
+}  // namespace
+
+int exp_blob_bytes(const Plan& p, const std::vector<int>& groups) {
+  return (int)(4 * blob_words(p, groups));
+}
+
+int max_class_size(const Plan& p, uint32_t lmask) {
+  size_t mx = 0;
+  for (auto& b : class_buckets(p, lmask)) mx = std::max(mx, b.size());
+  return (int)mx;
+}
+
+int max_pair_block_words(const Plan& p, uint32_t lmask, const std::vector<int>& items) {
+  size_t mx = 0;
+  for (auto& b : class_buckets(p, lmask)) mx = std::max(mx, pair_block(p, lmask, items, b).size());
+  return (int)mx;
+}
+
 void build_tables(const Plan& p, Tables& t) {
   t = Tables();
   const int n = p.n;
   const uint32_t full = (n >= 32) ? 0xffffffffu : ((1u << n) - 1u);
-  t.diag.push_back(p.diag_c0);
-  t.diag.insert(t.diag.end(), p.diag_a.begin(), p.diag_a.end());
-  t.diag.insert(t.diag.end(), p.diag_b.begin(), p.diag_b.end());
-  std::vector<int> occ_off(p.groups.size(), -1);
-  for (size_t g = 0; g < p.groups.size(); ++g)
-    if (p.groups[g].has_occ) {
-      occ_off[g] = (int)t.occ.size();
-      t.occ.insert(t.occ.end(), p.groups[g].B.begin(), p.groups[g].B.end());
-    }
   for (const auto& ps : p.passes) {
     DevPass dp{};
     dp.lmask = ps.lmask;
@@ -479,36 +614,79 @@ void build_tables(const Plan& p, Tables& t) {
     dp.k = pc32(ps.lmask);
     dp.kind = ps.kind;
     if (ps.kind == kExp) {
-      dp.first = (int)t.groups.size();
-      dp.count = (int)ps.items.size();
-      for (int gi : ps.items) {
+      const std::vector<int> order = blob_order(p, ps.items);
+      const size_t words = blob_words(p, order);
+      std::vector<uint32_t> b(words, 0u);
+      auto put_double = [&](size_t w, double v) { std::memcpy(&b[w], &v, sizeof(double)); };
+      int nd = 0, no = 0, npl = 0;
+      for (int g : order) (g == 0 ? nd : p.groups[g].has_occ ? no : npl)++;
+      size_t w = ExpBlob::kHeaderWords;
+      const size_t occ_rec = w;
+      w += ExpBlob::kOccWords * no;
+      w = (w + 3) & ~size_t(3);
+      const size_t plain_rec = w;
+      w += ExpBlob::kPlainWords * npl;
+      b[0] = nd;
+      b[1] = no;
+      b[2] = npl;
+      b[3] = (uint32_t)occ_rec;
+      b[4] = (uint32_t)plain_rec;
+      b[6] = n;
+      int io = 0, ip = 0;
+      for (size_t i = 0; i < order.size(); ++i) {
+        const int gi = order[i];
+        if (gi == 0) continue;
         const auto& g = p.groups[gi];
-        DevGroup d{};
-        d.xc = compact_bits(g.x, ps.lmask);
-        d.xphys = g.x;
-        d.m = g.m;
-        d.valid = g.valid;
-        d.spos = pack_positions(g.x);
-        d.nsup = pc32(g.x);
-        d.occ = occ_off[gi];
-        for (int P = 0; P < 16; ++P) d.A[P] = g.A[P];
-        t.groups.push_back(d);
+        const size_t a_off = w;
+        int slot = 0;
+        for (int P = 0; P < 16; ++P)
+          if ((g.valid >> P) & 1u) put_double(w + 2 * slot++, g.A[P]);
+        w += 2 * slot;
+        const uint32_t xc = compact_bits(g.x, ps.lmask);
+        if (g.has_occ) {
+          uint32_t* h = &b[occ_rec + ExpBlob::kOccWords * io++];
+          h[0] = xc;
+          h[1] = g.x;
+          h[2] = g.m;
+          h[3] = g.valid;
+          h[4] = pack_positions(g.x);
+          h[5] = pc32(g.x);
+          h[6] = (uint32_t)w;
+          h[7] = (uint32_t)a_off;
+          slot = 0;
+          for (int P = 0; P < 16; ++P)
+            if ((g.valid >> P) & 1u) {
+              for (int r = 0; r < n; ++r) put_double(w + 2 * (slot * n + r), g.B[P * n + r]);
+              ++slot;
+            }
+          w += 2 * slot * n;
+        } else {
+          uint32_t* h = &b[plain_rec + ExpBlob::kPlainWords * ip++];
+          h[0] = xc | (pc32(g.x) == 4 ? 0x80000000u : 0u);
+          h[1] = pack_positions(g.x);
+          h[2] = g.m;
+          h[3] = g.valid | ((uint32_t)a_off << 16);
+        }
       }
+      b[5] = (uint32_t)w;
+      if (nd) {
+        put_double(w, p.diag_c0);
+        for (int r = 0; r < n; ++r) put_double(w + 2 * (1 + r), p.diag_a[r]);
+        for (int i = 0; i < n * n; ++i) put_double(w + 2 * (1 + n + i), p.diag_b[i]);
+      }
+      dp.first = 0;
+      dp.count = (int)order.size();
+      dp.blob_off = (int)(t.blob.size() / 4);
+      dp.blob_len = (int)(words / 4);
+      t.blob.insert(t.blob.end(), b.begin(), b.end());
       // in-sector tile lists, bucketed by the (alpha, beta) electron count of the global bits
-      const int nag = pc32(dp.gmask & p.amask), nbg = pc32(dp.gmask & p.bmask);
+      int nbg = 0;
+      auto buckets = class_buckets(p, ps.lmask, &nbg);
       dp.cls_base = (int)t.cls.size() / 2;
       dp.nbeta_g = nbg;
-      const int ncls = (nag + 1) * (nbg + 1);
-      std::vector<std::vector<std::pair<uint32_t, uint32_t>>> buckets(ncls);
-      const uint32_t tile = 1u << dp.k;
-      for (uint32_t c = 0; c < tile; ++c) {
-        const uint32_t ph = deposit_bits(c, ps.lmask);
-        const int ag = p.nalpha - pc32(ph & p.amask);
-        const int bg = p.nbeta - pc32(ph & p.bmask);
-        if (ag < 0 || bg < 0 || ag > nag || bg > nbg) continue;
-        buckets[ag * (nbg + 1) + bg].push_back({c, ph});
-      }
+      dp.stage_len = 0;
       for (auto& bk : buckets) {
+        dp.stage_len = std::max(dp.stage_len, (int)bk.size());
         t.cls.push_back((int32_t)(t.list.size() / 2));
         t.cls.push_back((int32_t)bk.size());
         for (auto& e : bk) {
@@ -526,11 +704,23 @@ void build_tables(const Plan& p, Tables& t) {
         d.from_c = compact_bits(e.from, ps.lmask);
         d.mloc_c = compact_bits(e.m & ps.lmask, ps.lmask);
         d.mglob = e.m & ~ps.lmask;
-        d.ins = pack_positions(d.supp_c);
         d.nsup = e.nsup;
         d.k = k;
         d.sigma = e.sigma;
         t.exc.push_back(d);
+      }
+      int nbg = 0;
+      auto buckets = class_buckets(p, ps.lmask, &nbg);
+      dp.cls_base = (int)t.cls.size() / 2;
+      dp.nbeta_g = nbg;
+      dp.stage_len = 0;
+      for (auto& bk : buckets) {
+        std::vector<uint32_t> blk = pair_block(p, ps.lmask, ps.items, bk);
+        while (t.pairs.size() % 4) t.pairs.push_back(0u);  // 16-byte aligned blocks
+        t.cls.push_back((int32_t)t.pairs.size());
+        t.cls.push_back((int32_t)blk.size());
+        dp.stage_len = std::max(dp.stage_len, (int)blk.size());
+        t.pairs.insert(t.pairs.end(), blk.begin(), blk.end());
       }
     }
     t.passes.push_back(dp);

@@ -31,23 +31,42 @@ struct DevExc {
   uint32_t from_c;  // compact pattern u & supp on which T_k acts (its occupied orbitals)
   uint32_t mloc_c;  // compact part of the JW parity mask m_k
   uint32_t mglob;   // physical global part of m_k (constant over a tile)
-  uint32_t ins;     // ascending compact support positions, 5 bits each
   int32_t nsup;     // 2 (single) or 4 (double)
   int32_t k;        // amplitude index
   int32_t sigma;    // constant sign of T_k on its from-pattern (+1 or -1)
+  int32_t pad;
 };
 
-// One x-group inside one expectation pass.
-struct DevGroup {
-  uint32_t xc;     // compact x-mask (LDS partner offset); 0 for the diagonal group
-  uint32_t xphys;  // physical x-mask
-  uint32_t m;      // physical parity mask (outside the support)
-  uint32_t valid;  // bit P set when support pattern P conserves N and S_z
-  uint32_t spos;   // ascending physical support positions, 5 bits each
-  int32_t nsup;    // 0 (diagonal), 2 or 4
-  int32_t occ;     // offset (doubles) of the B[16][n] table, or -1
-  int32_t pad;
-  double A[16];    // constant part per support pattern
+constexpr int kMaxPassExc = 256;  // excitations per forward/reverse pass (staged in LDS)
+
+// Pair-list block of one forward/reverse pass for one tile class (the alpha and beta
+// electron counts of the tile's global bits): uint32 words
+//   [0 .. m]  prefix offsets: the pairs of the pass's j-th excitation are entries
+//             off[j] .. off[j+1]-1
+//   then the entries, two uint16 per word: compact index u of each in-sector basis state
+//   with u & supp == from (its partner is u ^ supp, also in-sector).
+// Only in-sector amplitudes can be non-zero, so only these pairs change anything.
+
+// Blob of one expectation pass: uint32 words, copied into LDS behind the tile; every
+// double sits at an even word offset and every record at a 16-byte boundary.
+//   [0] n_diag (0 or 1)  [1] n_occ  [2] n_plain  [3] word offset of the occ records
+//   [4] word offset of the plain records  [5] word offset of the diagonal table
+//   [6] n_qubits  [7] 0
+//   occ records (groups with occupation-number terms), 8 words each:
+//     {compact x, physical x, physical parity mask m, valid-pattern mask,
+//      ascending physical support positions (5 bits each), support size,
+//      word offset of the occupation rows, word offset of the A values}
+//   plain records (groups without them), 4 words each:
+//     {compact x | (support size == 4) << 31, support positions, parity mask m,
+//      valid-pattern mask | word offset of the A values << 16}
+//   A values: one double per valid support pattern, in pattern order, so the value of a
+//     valid source pattern P sits at slot popcount(valid & ((1 << P) - 1))
+//   occupation rows: n doubles per valid pattern of an occ group (same slots)
+//   diagonal: c0, a[n], b[n*n] (if n_diag)
+struct ExpBlob {
+  static constexpr int kHeaderWords = 8;
+  static constexpr int kOccWords = 8;
+  static constexpr int kPlainWords = 4;
 };
 
 struct DevPass {
@@ -57,14 +76,20 @@ struct DevPass {
   int32_t kind;     // PassKind
   int32_t first;    // first record in DevExc[] (fwd/rev) or DevGroup[] (exp)
   int32_t count;    // records in this pass
-  int32_t cls_base; // exp: first class entry (int2 offset,count) of this pass
-  int32_t nbeta_g;  // exp: number of beta bits among the global bits
+  int32_t cls_base; // first class entry of this pass (int2): exp -> (list offset, count),
+                    // fwd/rev -> (pair-block word offset, word count)
+  int32_t nbeta_g;  // number of beta bits among the global bits (class index stride - 1)
+  int32_t blob_off; // exp: first uint4 of the pass's blob
+  int32_t blob_len; // exp: blob length in uint4
+  int32_t stage_len; // exp: largest class list (entries); fwd/rev: largest block (words)
+  int32_t pad;
 };
 
 // Host-side plan: everything ucc_build derives from the inputs.
 struct Plan {
   int n = 0, ne = 0, ns = 0, K = 0;
   int nalpha = 0, nbeta = 0;
+  uint64_t nsec = 0;  // basis states with N = ne, S_z = 0
   std::vector<double> h1, h2;
   std::vector<int32_t> exc;  // [K*4]
   int perm[32] = {0};        // logical -> physical
@@ -111,12 +136,18 @@ struct Plan {
 struct Tables {
   std::vector<DevPass> passes;
   std::vector<DevExc> exc;
-  std::vector<DevGroup> groups;
-  std::vector<double> occ;      // B tables
-  std::vector<double> diag;     // c0, a[n], b[n*n]
+  std::vector<uint32_t> pairs;  // forward/reverse pair-list blocks
+  std::vector<uint32_t> blob;   // expectation-pass blobs (multiple of 4 words each)
   std::vector<int32_t> cls;     // pairs (offset, count)
   std::vector<uint32_t> list;   // pairs (compact c, physical local offset)
 };
+
+// LDS limit of one workgroup on gfx950 and what an expectation pass may spend on its blob.
+constexpr int kLdsBytes = 163840;
+constexpr int kStageBytes = 12288;  // static LDS of a forward/reverse pass (records, cos/sin)
+int exp_blob_bytes(const Plan& p, const std::vector<int>& groups);
+int max_class_size(const Plan& p, uint32_t lmask);
+int max_pair_block_words(const Plan& p, uint32_t lmask, const std::vector<int>& items);
 
 // planner.cpp
 // Returns "" on success, otherwise an error message (inputs invalid).

@@ -24,8 +24,11 @@ EXPORTED = [
     "ucc_default_options", "ucc_build", "ucc_energy", "ucc_energy_grad", "ucc_get_state",
     "ucc_destroy", "ucc_last_error", "ucc_get_plan_info", "ucc_get_pauli_terms",
     "ucc_get_group_table", "ucc_get_excitation_table", "ucc_get_pass_table",
+    "ucc_profile", "ucc_profile_read",
     "ucc_server_create", "ucc_submit", "ucc_poll", "ucc_wait", "ucc_cancel", "ucc_server_destroy",
 ]
+
+KERNEL_KINDS = ["trig", "fwd", "exp", "applyh", "rev", "reduce"]
 
 
 class Options(ctypes.Structure):
@@ -41,6 +44,10 @@ class PlanInfo(ctypes.Structure):
                 ("n_rev_passes", _i32), ("tile_qubits", _i32), ("tile_qubits_rev", _i32),
                 ("contiguous_fwd", _i32), ("contiguous_exp", _i32), ("contiguous_rev", _i32),
                 ("block_threads", _i32), ("launch_mode", _i32), ("perm", _i32 * 32)]
+
+
+class KernelStat(ctypes.Structure):
+    _fields_ = [("launches", _i32), ("reserved", _i32), ("ms", _dbl), ("bytes", _dbl)]
 
 
 class UCCError(RuntimeError):
@@ -74,6 +81,8 @@ def lib():
         "ucc_get_group_table": (_i32, [_vp, _vp, _vp, _vp, _vp, _vp, _vp]),
         "ucc_get_excitation_table": (_i32, [_vp, _vp, _vp, _vp, _vp]),
         "ucc_get_pass_table": (_i32, [_vp, _vp, _vp, _vp, _vp, _vp]),
+        "ucc_profile": (_i32, [_vp, _i32]),
+        "ucc_profile_read": (_i32, [_vp, _P(KernelStat), _i32]),
         "ucc_server_create": (_i32, [ctypes.c_size_t, _i32, _i32, _P(_vp)]),
         "ucc_submit": (_i32, [_vp, _vp, _vp, _i32, _dbl, _u32, _P(_u64)]),
         "ucc_poll": (_i32, [_vp, _u64, _P(_i32), _vp, _vp, _vp]),
@@ -175,6 +184,18 @@ class Context:
         out = np.empty(2 << self.n_qubits)
         check(lib().ucc_get_state(self._h, int(b), _ptr(out)), "ucc_get_state")
         return out[0::2] + 1j * out[1::2]
+
+    # ------------------------------------------------------------ profiling
+    def profile(self, enable=True):
+        """Bracket every later kernel launch with HIP events on the call's stream."""
+        check(lib().ucc_profile(self._h, int(bool(enable))), "ucc_profile")
+
+    def profile_read(self, reset=True):
+        """{kind: dict(launches, ms, bytes)} accumulated since the last reset."""
+        st = (KernelStat * 8)()
+        check(lib().ucc_profile_read(self._h, st, int(bool(reset))), "ucc_profile_read")
+        return {name: dict(launches=st[i].launches, ms=st[i].ms, bytes=st[i].bytes)
+                for i, name in enumerate(KERNEL_KINDS)}
 
     # ------------------------------------------------------------ introspection
     def plan_info(self):
