@@ -163,6 +163,23 @@ struct Tile {
     st16(lds + threadIdx.x + J * T, rget<J, EPT>(r));
     if constexpr (J + 1 < EPT) put<J + 1>(r, lds);
   }
+  // rs <- the thread's own tile elements in LDS, then those elements <- r (the next tile)
+  template <int J = 0>
+  __device__ __forceinline__ void swap(Buf& rs, const Buf& r, double2* lds) const {
+    rget<J, EPT>(rs) = ld16(lds + threadIdx.x + J * T);
+    st16(lds + threadIdx.x + J * T, rget<J, EPT>(r));
+    if constexpr (J + 1 < EPT) swap<J + 1>(rs, r, lds);
+  }
+  template <int J = 0>
+  __device__ __forceinline__ void save(Buf& rs, const double2* lds) const {
+    rget<J, EPT>(rs) = ld16(lds + threadIdx.x + J * T);
+    if constexpr (J + 1 < EPT) save<J + 1>(rs, lds);
+  }
+  template <int J = 0>
+  __device__ __forceinline__ void store_regs(const Buf& rs, double2* __restrict__ v, uint32_t base) const {
+    st16(v + (base | off<J>()), rget<J, EPT>(rs));
+    if constexpr (J + 1 < EPT) store_regs<J + 1>(rs, v, base);
+  }
   template <int J = 0>
   __device__ __forceinline__ void store_j(const double2* lds, double2* __restrict__ v,
                                           uint32_t base) const {
@@ -227,11 +244,23 @@ __device__ __forceinline__ void stage_records(PassStage& st, const DevPass& ps,
   for (int i = threadIdx.x; i < ps.count; i += T) st.x[i] = exc[ps.first + i];
 }
 
-template <int T>
-__device__ __forceinline__ void stage_cs(PassStage& st, const DevPass& ps,
-                                         const double2* __restrict__ cs, int K, int b) {
-  for (int i = threadIdx.x; i < ps.count; i += T) st.cs[i] = cs[(size_t)b * K + st.x[i].k];
-}
+// Everything excitation e needs before its amplitudes: record, (cos, sin), the range of
+// its pairs in the pair block and the thread's first pair entry.
+struct ExcAhead {
+  DevExc x;
+  double2 t;
+  int i0, i1;
+  uint32_t u0;
+  __device__ __forceinline__ void load(const DevExc* sx, const double2* scs, const uint32_t* blk,
+                                       const uint16_t* ent, int e, int count) {
+    x = sx[e];
+    t = scs[e];
+    i0 = (int)blk[e];
+    i1 = (int)blk[e + 1];
+    const int i = i0 + (int)threadIdx.x;
+    u0 = i < i1 ? (uint32_t)ent[i] : 0u;
+  }
+};
 
 // Copy `words` uint32 from global to LDS.
 template <int T>
@@ -250,8 +279,13 @@ __device__ __forceinline__ int tile_class(uint32_t base, uint32_t amask, uint32_
 
 // The pass kernels are persistent over tiles: the grid holds as many workgroups as fit on
 // the device and each walks items (batch entry, tile) with stride gridDim.x (a multiple of
-// the tile count where possible, so a workgroup keeps one tile index and one class).  With
-// KT != 0 the next item's tile is fetched into registers while the current one is processed.
+// the tile count where possible, so a workgroup keeps one tile index and one class).
+//
+// Pipelining (KT != 0).  Vector-memory counters retire loads and stores in issue order, so
+// no wait may follow fresh stores.  At the end of an item each thread swaps its own tile
+// elements (LDS -> registers, prefetched next tile -> LDS), writes this item's (cos, sin)
+// stage, and only then issues the item's stores and the prefetch of the item after next:
+// both are in flight during the next item's compute.
 //
 // Forward pass: for each excitation of the pass in Trotter order, a Givens rotation on the
 // tile's in-sector pairs (u, u ^ supp) listed in the class's pair block.
@@ -264,6 +298,7 @@ __global__ __launch_bounds__(T) LDS_BOUND_OCCUPANCY void k_fwd(
   extern __shared__ double2 lds[];
   __shared__ PassStage st;
   using TL = Tile<T, KT>;
+  constexpr bool RP = KT != 0;  // register-staged tiles
   const DevPass ps = passes[pidx];
   const uint32_t tileN = 1u << ps.k;
   const int tb = n - ps.k;
@@ -271,44 +306,62 @@ __global__ __launch_bounds__(T) LDS_BOUND_OCCUPANCY void k_fwd(
   uint32_t* blk = reinterpret_cast<uint32_t*>(lds + tileN);
   const uint16_t* ent = reinterpret_cast<const uint16_t*>(blk + ps.count + 1);
   const TL tm(ps.lmask);
-  stage_records<T>(st, ps, exc);
-  constexpr bool PF = KT != 0 && !INIT;  // register prefetch of the next tile
-  typename TL::Buf r;
-  int staged = -1;
+  const bool cst = (int)threadIdx.x < ps.count;
   int item = blockIdx.x;
-  if (PF && item < total) tm.fetch(r, psi + ((size_t)(item >> tb) << n), dep(item & tmask, ps.gmask));
-  for (; item < total; item += gridDim.x) {
-    const int b = item >> tb;
-    const uint32_t base = dep(item & tmask, ps.gmask);
-    double2* __restrict__ v = psi + ((size_t)b << n);
-    __syncthreads();  // LDS free: the previous item's store has read it
-    if (INIT)
-      tm.init_hf(lds, base, tileN, hf);
-    else if (PF)
-      tm.put(r, lds);
-    else
-      tm.load(lds, v, base, tileN);
-    const int next = item + gridDim.x;
-    if (PF) {  // the last item re-fetches itself (in bounds, unused) so r is written on every path
-      const int nf = next < total ? next : item;
-      tm.fetch(r, psi + ((size_t)(nf >> tb) << n), dep(nf & tmask, ps.gmask));
-    }
+  if (item >= total) return;
+  stage_records<T>(st, ps, exc);
+  __syncthreads();
+  typename TL::Buf r, rs;
+  int staged = -1;
+  auto cs_of = [&](int it) { return cs[(size_t)(it >> tb) * K + st.x[threadIdx.x].k]; };
+  auto base_of = [&](int it) { return dep(it & tmask, ps.gmask); };
+  auto vec_of = [&](int it) { return psi + ((size_t)(it >> tb) << n); };
+  auto stage_class = [&](uint32_t base) {
     const int cl = tile_class(base, amask, bmask, ps.nbeta_g);
     if (cl != staged) {
       const int2 bl = pcls[ps.cls_base + cl];
       stage_words<T>(blk, pairs + bl.x, bl.y);
       staged = cl;
     }
-    stage_cs<T>(st, ps, cs, K, b);
-    __syncthreads();
+  };
+  // prologue: first tile in LDS, the next one in flight
+  {
+    const uint32_t base = base_of(item);
+    double2 c0 = make_double2(1.0, 0.0);
+    if (cst) c0 = cs_of(item);
+    if (INIT)
+      tm.init_hf(lds, base, tileN, hf);
+    else
+      tm.load(lds, vec_of(item), base, tileN);
+    stage_class(base);
+    if (cst) st.cs[threadIdx.x] = c0;
+  }
+  double2 csv = make_double2(1.0, 0.0);
+  {
+    const int next = item + gridDim.x;
+    if (next < total) {
+      if (RP && !INIT) tm.fetch(r, vec_of(next), base_of(next));
+      if (cst) csv = cs_of(next);
+    }
+  }
+  __syncthreads();
+  for (;;) {
+    const uint32_t base = base_of(item);
+    double2* __restrict__ v = vec_of(item);
+    // The records, (cos, sin), list offsets and first pair entry of excitation e+1 do not
+    // change during the pass: they are read while excitation e is applied, leaving only the
+    // amplitude reads on the dependency chain between barriers.
+    ExcAhead ah;
+    ah.load(st.x, st.cs, blk, ent, 0, ps.count);
     for (int e = 0; e < ps.count; ++e) {
-      const DevExc x = st.x[e];
-      const double2 t = st.cs[e];
-      const double c = t.x;
-      const double s = (parity(base & x.mglob) ? -t.y : t.y) * (double)x.sigma;
-      const int i1 = (int)blk[e + 1];
-      for (int i = (int)blk[e] + threadIdx.x; i < i1; i += T) {
-        const uint32_t u = ent[i];
+      const ExcAhead cur = ah;
+      if (e + 1 < ps.count) ah.load(st.x, st.cs, blk, ent, e + 1, ps.count);
+      const DevExc& x = cur.x;
+      const double c = cur.t.x;
+      const double s = (parity(base & x.mglob) ? -cur.t.y : cur.t.y) * (double)x.sigma;
+      uint32_t u = cur.u0;
+      for (int i = cur.i0 + threadIdx.x; i < cur.i1; i += T) {
+        if (i != cur.i0 + (int)threadIdx.x) u = ent[i];
         const uint32_t w = u ^ x.supp_c;
         const double sg = parity(u & x.mloc_c) ? -s : s;
         const double2 a = lds[u], bb = lds[w];
@@ -317,12 +370,43 @@ __global__ __launch_bounds__(T) LDS_BOUND_OCCUPANCY void k_fwd(
       }
       __syncthreads();
     }
-    tm.store(lds, v, base, tileN);
+    const int next = item + gridDim.x;
+    if (next >= total) {
+      tm.store(lds, v, base, tileN);
+      break;
+    }
+    const uint32_t nbase = base_of(next);
+    if (RP) {
+      if (INIT) {
+        tm.save(rs, lds);
+        tm.init_hf(lds, nbase, tileN, hf);
+      } else {
+        tm.swap(rs, r, lds);
+      }
+      if (cst) st.cs[threadIdx.x] = csv;
+      tm.store_regs(rs, v, base);
+    } else {
+      tm.store(lds, v, base, tileN);
+      if (INIT)
+        tm.init_hf(lds, nbase, tileN, hf);
+      else
+        tm.load(lds, vec_of(next), nbase, tileN);
+      if (cst) st.cs[threadIdx.x] = csv;
+    }
+    stage_class(nbase);
+    const int next2 = next + gridDim.x;
+    if (next2 < total) {
+      if (RP && !INIT) tm.fetch(r, vec_of(next2), base_of(next2));
+      if (cst) csv = cs_of(next2);
+    }
+    __syncthreads();
+    item = next;
   }
 }
 
 // Reverse pass: for each excitation (descending k) the partial of <lambda|G_k|psi> over the
-// tile's in-sector pairs, then psi, lambda <- exp(-theta_k G_k) (psi, lambda).
+// tile's in-sector pairs, then psi, lambda <- exp(-theta_k G_k) (psi, lambda).  Per-item
+// gradient partials collect in LDS and are stored with the tiles.
 template <int T, int KT>
 __global__ __launch_bounds__(T) LDS_BOUND_OCCUPANCY void k_rev(
     const DevPass* __restrict__ passes, int pidx, const DevExc* __restrict__ exc,
@@ -333,7 +417,9 @@ __global__ __launch_bounds__(T) LDS_BOUND_OCCUPANCY void k_rev(
   constexpr int NW = T / 64;
   __shared__ PassStage st;
   __shared__ double red[2][NW];
+  __shared__ double gsum[kMaxPassExc];
   using TL = Tile<T, KT>;
+  constexpr bool RP = KT != 0;
   const DevPass ps = passes[pidx];
   const uint32_t tileN = 1u << ps.k;
   const int tb = n - ps.k;
@@ -345,57 +431,66 @@ __global__ __launch_bounds__(T) LDS_BOUND_OCCUPANCY void k_rev(
   const uint16_t* ent = reinterpret_cast<const uint16_t*>(blk + ps.count + 1);
   const TL tm(ps.lmask);
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  stage_records<T>(st, ps, exc);
-  typename TL::Buf rp, rl;
-  int staged = -1;
+  const bool cst = (int)threadIdx.x < ps.count;
   int item = blockIdx.x;
-  if (KT && item < total) {
-    const size_t vo = (size_t)(item >> tb) << n;
-    const uint32_t bs = dep(item & tmask, ps.gmask);
-    tm.fetch(rp, psi + vo, bs);
-    tm.fetch(rl, lam + vo, bs);
-  }
-  for (; item < total; item += gridDim.x) {
-    const int b = item >> tb;
-    const uint32_t t = item & tmask;
-    const uint32_t base = dep(t, ps.gmask);
-    double2* __restrict__ vp = psi + ((size_t)b << n);
-    double2* __restrict__ vl = lam + ((size_t)b << n);
-    __syncthreads();
-    if (KT) {
-      tm.put(rp, lp);
-      tm.put(rl, ll);
-    } else {
-      tm.load(lp, vp, base, tileN);
-      tm.load(ll, vl, base, tileN);
-    }
-    const int next = item + gridDim.x;
-    if (KT) {  // the last item re-fetches itself (in bounds, unused) so rp/rl are always written
-      const int nf = next < total ? next : item;
-      const size_t vo = (size_t)(nf >> tb) << n;
-      const uint32_t bs = dep(nf & tmask, ps.gmask);
-      tm.fetch(rp, psi + vo, bs);
-      tm.fetch(rl, lam + vo, bs);
-    }
+  if (item >= total) return;
+  stage_records<T>(st, ps, exc);
+  __syncthreads();
+  typename TL::Buf rp, rl, rsp, rsl;
+  int staged = -1;
+  auto cs_of = [&](int it) { return cs[(size_t)(it >> tb) * K + st.x[threadIdx.x].k]; };
+  auto base_of = [&](int it) { return dep(it & tmask, ps.gmask); };
+  auto off_of = [&](int it) { return (size_t)(it >> tb) << n; };
+  auto stage_class = [&](uint32_t base) {
     const int cl = tile_class(base, amask, bmask, ps.nbeta_g);
     if (cl != staged) {
       const int2 bl = pcls[ps.cls_base + cl];
       stage_words<T>(blk, pairs + bl.x, bl.y);
       staged = cl;
     }
-    stage_cs<T>(st, ps, cs, K, b);
-    __syncthreads();
-    int prev_k = -1, prev_e = 0;
+  };
+  {
+    const uint32_t base = base_of(item);
+    double2 c0 = make_double2(1.0, 0.0);
+    if (cst) c0 = cs_of(item);
+    tm.load(lp, psi + off_of(item), base, tileN);
+    tm.load(ll, lam + off_of(item), base, tileN);
+    stage_class(base);
+    if (cst) st.cs[threadIdx.x] = c0;
+  }
+  double2 csv = make_double2(1.0, 0.0);
+  {
+    const int next = item + gridDim.x;
+    if (next < total) {
+      if (RP) {
+        tm.fetch(rp, psi + off_of(next), base_of(next));
+        tm.fetch(rl, lam + off_of(next), base_of(next));
+      }
+      if (cst) csv = cs_of(next);
+    }
+  }
+  __syncthreads();
+  for (;;) {
+    const int b = item >> tb;
+    const uint32_t t = item & tmask;
+    const uint32_t base = base_of(item);
+    double2* __restrict__ vp = psi + off_of(item);
+    double2* __restrict__ vl = lam + off_of(item);
+    int prev_e = -1;
+    ExcAhead ah;
+    ah.load(st.x, st.cs, blk, ent, 0, ps.count);
     for (int e = 0; e < ps.count; ++e) {
-      const DevExc x = st.x[e];
-      const double2 tt = st.cs[e];
+      const ExcAhead cur = ah;
+      if (e + 1 < ps.count) ah.load(st.x, st.cs, blk, ent, e + 1, ps.count);
+      const DevExc& x = cur.x;
+      const double2 tt = cur.t;
       const double c = tt.x;
       const double sgn0 = (parity(base & x.mglob) ? -1.0 : 1.0) * (double)x.sigma;
-      const int i0 = (int)blk[e], i1 = (int)blk[e + 1];
+      const int i0 = cur.i0, i1 = cur.i1;
       double g = 0.0;
       if (i0 + wv * 64 < i1) {  // this wave has pairs of this excitation
         for (int i = i0 + threadIdx.x; i < i1; i += T) {
-          const uint32_t u = ent[i];
+          const uint32_t u = i == i0 + (int)threadIdx.x ? cur.u0 : (uint32_t)ent[i];
           const uint32_t w = u ^ x.supp_c;
           const double sg = parity(u & x.mloc_c) ? -sgn0 : sgn0;
           const double2 pu = lp[u], pw = lp[w], lu = ll[u], lw = ll[w];
@@ -409,25 +504,85 @@ __global__ __launch_bounds__(T) LDS_BOUND_OCCUPANCY void k_rev(
         g = wave_sum(g);
       }
       if (lane == 0) red[e & 1][wv] = g;
-      // thread 0 folds the previous excitation's wave sums while the others proceed
-      if (threadIdx.x == 0 && prev_k >= 0) {
+      // the last wave (pairs rarely reach it) folds the previous excitation's wave sums
+      if (threadIdx.x == T - 64 && prev_e >= 0) {
         double sum = 0.0;
         for (int i = 0; i < NW; ++i) sum += red[prev_e & 1][i];
-        gpart[((size_t)b * K + prev_k) * ntiles + t] = sum;
+        gsum[prev_e] = sum;
       }
-      prev_k = x.k;
       prev_e = e;
       __syncthreads();
     }
-    if (threadIdx.x == 0 && prev_k >= 0) {
+    if (threadIdx.x == T - 64 && prev_e >= 0) {
       double sum = 0.0;
       for (int i = 0; i < NW; ++i) sum += red[prev_e & 1][i];
-      gpart[((size_t)b * K + prev_k) * ntiles + t] = sum;
+      gsum[prev_e] = sum;
     }
-    tm.store(lp, vp, base, tileN);
-    tm.store(ll, vl, base, tileN);
+    __syncthreads();  // gsum complete
+    const int next = item + gridDim.x;
+    if (next >= total) {
+      if (cst) gpart[((size_t)b * K + st.x[threadIdx.x].k) * ntiles + t] = gsum[threadIdx.x];
+      tm.store(lp, vp, base, tileN);
+      tm.store(ll, vl, base, tileN);
+      break;
+    }
+    const uint32_t nbase = base_of(next);
+    const double gv = cst ? gsum[threadIdx.x] : 0.0;
+    if (RP) {
+      tm.swap(rsp, rp, lp);
+      tm.swap(rsl, rl, ll);
+      if (cst) st.cs[threadIdx.x] = csv;
+      tm.store_regs(rsp, vp, base);
+      tm.store_regs(rsl, vl, base);
+    } else {
+      tm.store(lp, vp, base, tileN);
+      tm.store(ll, vl, base, tileN);
+      tm.load(lp, psi + off_of(next), nbase, tileN);
+      tm.load(ll, lam + off_of(next), nbase, tileN);
+      if (cst) st.cs[threadIdx.x] = csv;
+    }
+    if (cst) gpart[((size_t)b * K + st.x[threadIdx.x].k) * ntiles + t] = gv;
+    stage_class(nbase);
+    const int next2 = next + gridDim.x;
+    if (next2 < total) {
+      if (RP) {
+        tm.fetch(rp, psi + off_of(next2), base_of(next2));
+        tm.fetch(rl, lam + off_of(next2), base_of(next2));
+      }
+      if (cst) csv = cs_of(next2);
+    }
+    __syncthreads();
+    item = next;
   }
 }
+
+// lambda values of the first J entries (per quad lane 0) of an apply-H item, loaded before
+// the next tile's prefetch is issued; later entries (beyond J * T/4) load on use.
+template <int T>
+struct OldBuf {
+  static constexpr int J = 4096 / T;
+  RegBuf<J> r;
+  template <int I = 0>
+  __device__ __forceinline__ void load(const uint2* lst, const double2* __restrict__ vl, uint32_t base,
+                                       int nlist, bool rmw) {
+    const int it = (threadIdx.x >> 2) + I * (T / 4);
+    rget<I, J>(r) = (rmw && it < nlist) ? ld16(vl + (base | lst[it].y)) : dvec2{0.0, 0.0};
+    if constexpr (I + 1 < J) load<I + 1>(lst, vl, base, nlist, rmw);
+  }
+  template <int I = 0>
+  __device__ __forceinline__ dvec2 pick(int j, dvec2 v) const {
+    v = j == I ? rget<I, J>(r) : v;
+    if constexpr (I + 1 < J)
+      return pick<I + 1>(j, v);
+    else
+      return v;
+  }
+  __device__ __forceinline__ dvec2 get(int j, const double2* __restrict__ vl, uint32_t u,
+                                       bool rmw) const {
+    if (j < J) return pick(j, dvec2{0.0, 0.0});
+    return rmw ? ld16(vl + u) : dvec2{0.0, 0.0};
+  }
+};
 
 // Expectation / apply-H pass.  Only in-sector basis states u of a tile can be non-zero (the
 // HF state has N = n_elec, S_z = 0 and every factor and every Hamiltonian term conserves
@@ -464,45 +619,54 @@ __global__ __launch_bounds__(T) LDS_BOUND_OCCUPANCY void k_exp(const DevPass* __
   const uint32_t* bw = reinterpret_cast<const uint32_t*>(lb);
   const TL tm(ps.lmask);
   const int sub = threadIdx.x & 3;
+  const bool rmw = APPLY && !first && sub == 0;
   typename TL::Buf r;
+  OldBuf<T> olds;
   int item = blockIdx.x;
-  if (KT && item < total) tm.fetch(r, psi + ((size_t)(item >> tb) << n), dep(item & tmask, ps.gmask));
-  for (; item < total; item += gridDim.x) {
-    const int b = item >> tb;
-    const uint32_t t = item & tmask;
-    const uint32_t base = dep(t, ps.gmask);
-    const double2* __restrict__ vp = psi + ((size_t)b << n);
-    __syncthreads();
-    if (KT)
-      tm.put(r, lds);
-    else
-      tm.load(lds, vp, base, tileN);
-    const int next = item + gridDim.x;
-    if (KT) {  // the last item re-fetches itself (in bounds, unused) so r is always written
-      const int nf = next < total ? next : item;
-      tm.fetch(r, psi + ((size_t)(nf >> tb) << n), dep(nf & tmask, ps.gmask));
-    }
+  if (item >= total) return;
+  auto base_of = [&](int it) { return dep(it & tmask, ps.gmask); };
+  auto stage_class = [&](uint32_t base) {
     const int cli = tile_class(base, amask, bmask, ps.nbeta_g);
     if (cli != staged) {
+      __syncthreads();  // the previous list is no longer read
       const int2 cl = cls[ps.cls_base + cli];
       for (int i = threadIdx.x; i < cl.y; i += T) lst[i] = list[cl.x + i];
       nlist = cl.y;
       staged = cli;
+      __syncthreads();
     }
-    __syncthreads();
+  };
+  // prologue: first tile, its class list and lambda values; the next tile in flight.
+  // Loads are issued in the order they are consumed (vector-memory counters retire in
+  // issue order): lambda values of an item before the prefetch of the item after it.
+  {
+    const uint32_t base = base_of(item);
+    stage_class(base);
+    olds.load(lst, APPLY ? lam + ((size_t)(item >> tb) << n) : nullptr, base, nlist, rmw);
+    tm.load(lds, psi + ((size_t)(item >> tb) << n), base, tileN);
+    const int next = item + gridDim.x;
+    if (KT && next < total) tm.fetch(r, psi + ((size_t)(next >> tb) << n), base_of(next));
+  }
+  __syncthreads();
+  for (;;) {
+    const int b = item >> tb;
+    const uint32_t t = item & tmask;
+    const uint32_t base = base_of(item);
+    double2* __restrict__ vl = APPLY ? lam + ((size_t)b << n) : nullptr;
     const int nd = (int)bw[0], no = (int)bw[1], npl = (int)bw[2];
     const uint4* occr = reinterpret_cast<const uint4*>(bw + bw[3]);
     const uint4* plr = reinterpret_cast<const uint4*>(bw + bw[4]);
     const double* dg = reinterpret_cast<const double*>(bw + bw[5]);
     const double* dw = reinterpret_cast<const double*>(bw);  // double view of the blob
     double eacc = 0.0;
-    for (int it = threadIdx.x >> 2; it < nlist; it += T / 4) {
+    for (int j = 0;; ++j) {
+      const int it = (threadIdx.x >> 2) + j * (T / 4);
+      if (it >= nlist) break;
       const uint2 ent = lst[it];
       const uint32_t c = ent.x;
       const uint32_t u = base | ent.y;
       const double2 pu = lds[c];
-      double2 old = make_double2(0.0, 0.0);
-      if (APPLY && !first && sub == 0) old = lam[((size_t)b << n) + u];  // in flight meanwhile
+      const dvec2 old = olds.get(j, vl, u, rmw);
       double ax = 0.0, ay = 0.0;
       if (nd) {  // diagonal c0 + sum_r a_r n_r + sum_{r<s} b_rs n_r n_s; set bits split by rank
         double f = sub == 0 ? dg[0] : 0.0;
@@ -571,11 +735,25 @@ __global__ __launch_bounds__(T) LDS_BOUND_OCCUPANCY void k_exp(const DevPass* __
       ay = quad_sum(ay);
       if (sub == 0) {
         eacc += pu.x * ax + pu.y * ay;
-        if (APPLY) lam[((size_t)b << n) + u] = make_double2(old.x + ax, old.y + ay);
+        if (APPLY) vl[u] = make_double2(old.x + ax, old.y + ay);
       }
     }
     const double s = block_sum<T>(eacc, red);
     if (threadIdx.x == 0) epart[(size_t)b * estride + t] = s;
+    const int next = item + gridDim.x;
+    if (next >= total) break;
+    const uint32_t nbase = base_of(next);
+    __syncthreads();  // the tile and the list are no longer read
+    if (KT)
+      tm.put(r, lds);
+    else
+      tm.load(lds, psi + ((size_t)(next >> tb) << n), nbase, tileN);
+    stage_class(nbase);
+    olds.load(lst, APPLY ? lam + ((size_t)(next >> tb) << n) : nullptr, nbase, nlist, rmw);
+    const int next2 = next + gridDim.x;
+    if (KT && next2 < total) tm.fetch(r, psi + ((size_t)(next2 >> tb) << n), base_of(next2));
+    __syncthreads();
+    item = next;
   }
 }
 
