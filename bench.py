@@ -50,6 +50,21 @@ def cpu_baseline():
                       f"{dt:.1f} s, numpy/BLAS limited to 1 thread"}
 
 
+def copy_calibration(gib):
+    """A plain device copy of known size, for scaling HBM byte counters (FETCH_SIZE,
+    WRITE_SIZE) read under rocprofv3 --pmc: the copy kernel moves exactly `gib` GiB each way."""
+    import torch
+
+    n = int(gib * 2 ** 30) // 8
+    a = torch.ones(n, dtype=torch.float64, device="cuda:0")
+    b = torch.empty_like(a)
+    torch.cuda.synchronize()
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes_read": n * 8, "copy_bytes_written": n * 8, "launches": 3}))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -57,7 +72,14 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--launch-mode", type=int, default=0)
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="use the fixed tuning table instead of timing the candidates")
+    ap.add_argument("--copy-calibration", type=float, default=0.0, metavar="GIB",
+                    help="only run a plain device copy of GIB GiB (counter calibration) and exit")
     args = ap.parse_args()
+    if args.copy_calibration > 0:
+        copy_calibration(args.copy_calibration)
+        return
     if args.gpus != 1:
         print("bench.py measures one GPU: the workload shards by independent theta vectors and "
               "fragment jobs, and this build runs on a single MI355X; use --gpus 1.",
@@ -75,7 +97,8 @@ def main():
     exc = uccsd_excitations(N, NE)
     K = len(exc)
     thetas = make_thetas(K, TSEED, SCALE, batch=BATCH)
-    ctx = ucc.Context(N, NE, h1, h2, exc, max_batch=BATCH, device=0, launch_mode=args.launch_mode)
+    ctx = ucc.Context(N, NE, h1, h2, exc, max_batch=BATCH, device=0, launch_mode=args.launch_mode,
+                      autotune=not args.no_autotune)
     info = ctx.plan_info()
     td = torch.tensor(thetas, device=dev, dtype=torch.float64)
 
@@ -129,9 +152,12 @@ def main():
     achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
     traffic = None
     if os.path.exists(TRAFFIC_FILE):
+        # HBM bytes per launch from rocprofv3 FETCH_SIZE / WRITE_SIZE runs, scaled by what the
+        # same counters read for a plain copy; only valid for the kernel source they measured
         tr = json.load(open(TRAFFIC_FILE))
-        if tr.get("kernel") == dom and tr.get("source_hash") == kernel_source_hash():
-            traffic = tr.get("bytes_per_launch")
+        kt = tr.get("kernels", {}).get(dom)
+        if kt and tr.get("source_hash") == kernel_source_hash():
+            traffic = kt["bytes_per_launch"]
 
     out = {
         "metric": METRIC,
@@ -151,7 +177,10 @@ def main():
                    "passes_fwd_exp_rev": [info["n_fwd_passes"], info["n_exp_passes"],
                                           info["n_rev_passes"]],
                    "tile_qubits": [info["tile_qubits"], info["tile_qubits_rev"]],
-                   "block_threads": info["block_threads"], "launch_mode": info["launch_mode"],
+                   "block_threads_fwd_exp_rev": [info["block_threads_fwd"],
+                                                 info["block_threads_exp"],
+                                                 info["block_threads_rev"]],
+                   "autotuned": bool(info["autotuned"]), "launch_mode": info["launch_mode"],
                    "integral_seed": ISEED, "theta_seeds": "1..64", "theta_scale": SCALE},
         "p50_ms": float(np.percentile(step_ms, 50)),
         "p99_ms": float(np.percentile(step_ms, 99)),

@@ -53,13 +53,20 @@ typedef struct {
   int32_t tile_qubits;       /* k: local qubits per tile for one-vector passes (4..13) */
   int32_t tile_qubits_rev;   /* k for two-vector passes (reverse sweep) (4..12) */
   int32_t contiguous_qubits; /* lowest physical bits kept inside every tile (2..k-4) */
-  int32_t block_threads;     /* threads per workgroup: 256, 512 or 1024 */
+  int32_t block_threads;     /* threads per workgroup of every pass kind: 256, 512 or 1024 */
   int32_t max_batch;         /* theta vectors allocated up front (grows on demand) */
   int32_t launch_mode;       /* 0 auto, 1 one kernel launch per pass, 2 persistent work queue */
   int32_t host_only;         /* 1: plan on the host only (no device memory, no evaluation);
                                 for introspection and tests on machines without a GPU */
   int32_t device;            /* HIP device ordinal; -1 = current device */
-  int32_t reserved[7];
+  int32_t block_threads_fwd; /* per-kind workgroup size (forward, expectation/apply-H, */
+  int32_t block_threads_exp; /* reverse); overrides block_threads for that kind */
+  int32_t block_threads_rev;
+  int32_t autotune;          /* 1: time the candidate tile sizes and workgroup sizes of the
+                                kinds left automatic on this device at batch max(1, max_batch)
+                                during ucc_build and keep the fastest (results are cached per
+                                process by (n_qubits, n_elec, n_exc, batch)); 0: fixed table */
+  int32_t reserved[3];
 } ucc_options;
 
 /* Fill *opt with defaults (all automatic, launch_mode 0, max_batch 1). */
@@ -134,7 +141,8 @@ typedef struct {
   int32_t n_rev_passes;      /* two-vector reverse-sweep passes */
   int32_t tile_qubits, tile_qubits_rev;
   int32_t contiguous_fwd, contiguous_exp, contiguous_rev;
-  int32_t block_threads, launch_mode;
+  int32_t block_threads_fwd, block_threads_exp, block_threads_rev, launch_mode;
+  int32_t autotuned;         /* 1 if the choices above come from measurement */
   int32_t perm[32];          /* physical bit of logical qubit q (q < n_qubits) */
 } ucc_plan_info;
 

@@ -119,7 +119,9 @@ LaunchArgs make_args(const ucc_ctx* c, const Buffers& b, int B, hipStream_t st) 
   a.n = p.n;
   a.K = p.K;
   a.B = B;
-  a.threads = p.threads;
+  a.tf = p.tf;
+  a.te = p.te;
+  a.tr = p.tr;
   a.hf = p.hf;
   a.amask = p.amask;
   a.bmask = p.bmask;
@@ -209,6 +211,85 @@ ucc_status enqueue_eval(const ucc_ctx* c, Buffers& b, const double* d_theta, int
   return UCC_OK;
 }
 
+void free_tables(ucc_ctx* c) {
+  free_ptr(c->d_passes);
+  free_ptr(c->d_exc);
+  free_ptr(c->d_pairs);
+  free_ptr(c->d_blob);
+  free_ptr(c->d_cls);
+  free_ptr(c->d_list);
+  c->d_passes = nullptr;
+  c->d_exc = nullptr;
+  c->d_pairs = nullptr;
+  c->d_blob = nullptr;
+  c->d_cls = nullptr;
+  c->d_list = nullptr;
+}
+
+ucc_status upload_tables(ucc_ctx* c) {
+  const Tables& t = c->tab;
+  hipError_t e;
+  if ((e = upload(&c->d_passes, t.passes)) != hipSuccess ||
+      (e = upload(&c->d_exc, t.exc)) != hipSuccess ||
+      (e = upload(&c->d_pairs, t.pairs)) != hipSuccess ||
+      (e = upload(&c->d_blob, t.blob)) != hipSuccess ||
+      (e = upload(&c->d_cls, t.cls)) != hipSuccess ||
+      (e = upload(&c->d_list, t.list)) != hipSuccess)
+    return hip_fail(e, "device table upload");
+  return UCC_OK;
+}
+
+void apply_tuning(Plan& p, const Tuning& tu) {
+  p.tf = tu.tf;
+  p.te = tu.te;
+  p.tr = tu.tr;
+  p.launch_mode = tu.launch_mode;
+}
+
+ucc_status replan(ucc_ctx* c, int kf, int kr) {
+  Plan& p = c->plan;
+  if (p.kf == kf && p.kr == kr) return UCC_OK;
+  Plan np;
+  const std::string msg = build_plan(np, p.n, p.ne, p.h1.data(), p.h2.data(), p.exc.data(), p.K,
+                                     kf, kr, c->opt.contiguous_qubits);
+  if (!msg.empty()) return fail(UCC_EINVAL, msg);
+  np.tf = p.tf;
+  np.te = p.te;
+  np.tr = p.tr;
+  np.launch_mode = p.launch_mode;
+  np.autotuned = p.autotuned;
+  hipError_t e = hipDeviceSynchronize();
+  if (e != hipSuccess) return hip_fail(e, "hipDeviceSynchronize");
+  const int cap = c->buf.cap;
+  const bool lam = c->buf.lam != nullptr;
+  free_buffers(c->buf);
+  free_tables(c);
+  p = std::move(np);
+  c->tab = Tables();
+  build_tables(p, c->tab);
+  ucc_status s = upload_tables(c);
+  if (s == UCC_OK && cap) s = ensure_buffers(c, c->buf, cap, lam);
+  return s;
+}
+
+void profile_sum(const Profiler& pr, ucc_kernel_stat* stats, hipError_t* err) {
+  std::memset(stats, 0, sizeof(ucc_kernel_stat) * UCC_KERNEL_KINDS);
+  *err = hipSuccess;
+  for (auto& r : pr.recs) {
+    hipError_t e = hipEventSynchronize(r.b);
+    float ms = 0.f;
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, r.a, r.b);
+    if (e != hipSuccess) {
+      *err = e;
+      return;
+    }
+    auto& st = stats[r.kind];
+    st.launches += 1;
+    st.ms += ms;
+    st.bytes += r.bytes;
+  }
+}
+
 }  // namespace ucc
 
 using namespace ucc;
@@ -242,24 +323,24 @@ ucc_status ucc_build(int32_t n_qubits, int32_t n_elec, const double* h1, const d
     return fail(UCC_EINVAL, "tile_qubits must be 0 or in [4, 13]");
   if (o.tile_qubits_rev && (o.tile_qubits_rev < 4 || o.tile_qubits_rev > 12))
     return fail(UCC_EINVAL, "tile_qubits_rev must be 0 or in [4, 12]");
-  if (o.block_threads && o.block_threads != 256 && o.block_threads != 512 &&
-      o.block_threads != 1024)
-    return fail(UCC_EINVAL, "block_threads must be 0, 256, 512 or 1024");
+  for (int t : {o.block_threads, o.block_threads_fwd, o.block_threads_exp, o.block_threads_rev})
+    if (t && t != 256 && t != 512 && t != 1024)
+      return fail(UCC_EINVAL, "block_threads (any kind) must be 0, 256, 512 or 1024");
   if (o.launch_mode < 0 || o.launch_mode > 2) return fail(UCC_EINVAL, "launch_mode must be 0..2");
   if (o.max_batch < 0) return fail(UCC_EINVAL, "max_batch must be >= 0");
+  if (o.autotune && o.host_only) return fail(UCC_EINVAL, "autotune needs a device context");
 
   ucc_ctx* c = new (std::nothrow) ucc_ctx();
   if (!c) return fail(UCC_ENOMEM, "host allocation failed");
   c->opt = o;
   c->host_only = o.host_only != 0;
-  Tuning tu = choose_tuning(n_qubits, n_exc, std::max(1, o.max_batch), o);
-  msg = build_plan(c->plan, n_qubits, n_elec, h1, h2, exc, n_exc, tu.kf, tu.kr,
-                   o.contiguous_qubits, tu.threads);
+  const Tuning tu = choose_tuning(n_qubits, n_exc, std::max(1, o.max_batch), o);
+  msg = build_plan(c->plan, n_qubits, n_elec, h1, h2, exc, n_exc, tu.kf, tu.kr, o.contiguous_qubits);
   if (!msg.empty()) {
     delete c;
     return fail(UCC_EINVAL, msg);
   }
-  c->plan.launch_mode = tu.launch_mode;
+  apply_tuning(c->plan, tu);
   build_tables(c->plan, c->tab);
   if (c->host_only) {
     *out = c;
@@ -278,18 +359,9 @@ ucc_status ucc_build(int32_t n_qubits, int32_t n_elec, const double* h1, const d
     delete c;
     return hip_fail(e, "hipGetDevice (no GPU?)");
   }
-  const Tables& t = c->tab;
-  if ((e = upload(&c->d_passes, t.passes)) != hipSuccess ||
-      (e = upload(&c->d_exc, t.exc)) != hipSuccess ||
-      (e = upload(&c->d_pairs, t.pairs)) != hipSuccess ||
-      (e = upload(&c->d_blob, t.blob)) != hipSuccess ||
-      (e = upload(&c->d_cls, t.cls)) != hipSuccess ||
-      (e = upload(&c->d_list, t.list)) != hipSuccess) {
-    ucc_status s = hip_fail(e, "device table upload");
-    ucc_destroy(c);
-    return s;
-  }
-  ucc_status s = ensure_buffers(c, c->buf, std::max(1, o.max_batch), false);
+  ucc_status s = upload_tables(c);
+  if (s == UCC_OK) s = ensure_buffers(c, c->buf, std::max(1, o.max_batch), false);
+  if (s == UCC_OK && o.autotune) s = autotune(c, std::max(1, o.max_batch));
   if (s != UCC_OK) {
     ucc_destroy(c);
     return s;
@@ -377,12 +449,7 @@ void ucc_destroy(ucc_ctx* c) {
     (void)hipSetDevice(c->device);
     (void)hipDeviceSynchronize();
     free_buffers(c->buf);
-    free_ptr(c->d_passes);
-    free_ptr(c->d_exc);
-    free_ptr(c->d_pairs);
-    free_ptr(c->d_blob);
-    free_ptr(c->d_cls);
-    free_ptr(c->d_list);
+    free_tables(c);
   }
   delete c;
 }
@@ -404,7 +471,10 @@ ucc_status ucc_get_plan_info(const ucc_ctx* c, ucc_plan_info* info) {
   info->contiguous_fwd = p.c0f;
   info->contiguous_exp = p.c0e;
   info->contiguous_rev = p.c0r;
-  info->block_threads = p.threads;
+  info->block_threads_fwd = p.tf;
+  info->block_threads_exp = p.te;
+  info->block_threads_rev = p.tr;
+  info->autotuned = p.autotuned ? 1 : 0;
   info->launch_mode = p.launch_mode;
   for (int q = 0; q < p.n; ++q) info->perm[q] = p.perm[q];
   return UCC_OK;
@@ -493,16 +563,8 @@ ucc_status ucc_profile_read(ucc_ctx* c, ucc_kernel_stat* stats, int32_t reset) {
   std::memset(stats, 0, sizeof(ucc_kernel_stat) * UCC_KERNEL_KINDS);
   if (!c->prof) return UCC_OK;
   hipError_t e = hipSetDevice(c->device);
-  for (auto& r : c->prof->recs) {
-    if (e == hipSuccess) e = hipEventSynchronize(r.b);
-    float ms = 0.f;
-    if (e == hipSuccess) e = hipEventElapsedTime(&ms, r.a, r.b);
-    if (e != hipSuccess) return hip_fail(e, "profile events");
-    auto& st = stats[r.kind];
-    st.launches += 1;
-    st.ms += ms;
-    st.bytes += r.bytes;
-  }
+  if (e == hipSuccess) profile_sum(*c->prof, stats, &e);
+  if (e != hipSuccess) return hip_fail(e, "profile events");
   if (reset) c->prof->release_all();
   return UCC_OK;
 }

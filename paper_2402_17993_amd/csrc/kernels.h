@@ -9,7 +9,8 @@ namespace ucc {
 
 struct LaunchArgs {
   hipStream_t stream = nullptr;
-  int n = 0, K = 0, B = 0, threads = 512;
+  int n = 0, K = 0, B = 0;
+  int tf = 512, te = 1024, tr = 256;  // workgroup size of forward, expectation, reverse passes
   uint32_t hf = 0, amask = 0, bmask = 0;
   const DevPass* passes = nullptr;
   const DevExc* exc = nullptr;

@@ -906,7 +906,7 @@ hipError_t launch_trig(const LaunchArgs& a, const double* theta) {
 }
 
 hipError_t launch_fwd(const LaunchArgs& a, int pidx, int init) {
-  switch (a.threads) {
+  switch (a.tf) {
     case 256: return fwd_k<256>(a, pidx, init);
     case 1024: return fwd_k<1024>(a, pidx, init);
     default: return fwd_k<512>(a, pidx, init);
@@ -914,7 +914,7 @@ hipError_t launch_fwd(const LaunchArgs& a, int pidx, int init) {
 }
 
 hipError_t launch_rev(const LaunchArgs& a, int pidx) {
-  switch (a.threads) {
+  switch (a.tr) {
     case 256: return rev_k<256>(a, pidx);
     case 1024: return rev_k<1024>(a, pidx);
     default: return rev_k<512>(a, pidx);
@@ -923,13 +923,13 @@ hipError_t launch_rev(const LaunchArgs& a, int pidx) {
 
 hipError_t launch_exp(const LaunchArgs& a, int pidx, int eslot, int first, bool apply) {
   if (apply) {
-    switch (a.threads) {
+    switch (a.te) {
       case 256: return exp_k<256, true>(a, pidx, eslot, first);
       case 1024: return exp_k<1024, true>(a, pidx, eslot, first);
       default: return exp_k<512, true>(a, pidx, eslot, first);
     }
   }
-  switch (a.threads) {
+  switch (a.te) {
     case 256: return exp_k<256, false>(a, pidx, eslot, first);
     case 1024: return exp_k<1024, false>(a, pidx, eslot, first);
     default: return exp_k<512, false>(a, pidx, eslot, first);

@@ -232,7 +232,7 @@ std::string validate_inputs(int n, int ne, const double* h1, const double* h2, c
 }
 
 std::string build_plan(Plan& p, int n, int ne, const double* h1, const double* h2,
-                       const int32_t* exc, int K, int kf, int kr, int c0, int threads) {
+                       const int32_t* exc, int K, int kf, int kr, int c0) {
   p = Plan();
   p.n = n;
   p.ne = ne;
@@ -425,7 +425,6 @@ std::string build_plan(Plan& p, int n, int ne, const double* h1, const double* h
   // ---- pass plan.
   p.kf = std::min(kf, n);
   p.kr = std::min(kr, n);
-  p.threads = threads;
   auto best_windows = [&](int kind, int k, int& c0_out) {
     std::vector<Plan::Pass> best;
     const int req = pick_c0(k, c0);

@@ -128,7 +128,8 @@ struct Plan {
   int nfwd = 0, nexp = 0, nrev = 0;
   int kf = 0, kr = 0;
   int c0f = 0, c0e = 0, c0r = 0;
-  int threads = 512;
+  int tf = 512, te = 1024, tr = 256;  // workgroup sizes per pass kind
+  bool autotuned = false;
   int launch_mode = 1;
 };
 
@@ -154,7 +155,7 @@ int max_pair_block_words(const Plan& p, uint32_t lmask, const std::vector<int>& 
 std::string validate_inputs(int n, int ne, const double* h1, const double* h2, const int32_t* exc,
                             int K);
 std::string build_plan(Plan& p, int n, int ne, const double* h1, const double* h2,
-                       const int32_t* exc, int K, int kf, int kr, int c0, int threads);
+                       const int32_t* exc, int K, int kf, int kr, int c0);
 void build_tables(const Plan& p, Tables& t);
 uint32_t deposit_bits(uint32_t v, uint32_t mask);
 int count_plan_passes(const Plan& p, int kind);

@@ -35,7 +35,8 @@ class Options(ctypes.Structure):
     _fields_ = [("trotter_steps", _i32), ("tile_qubits", _i32), ("tile_qubits_rev", _i32),
                 ("contiguous_qubits", _i32), ("block_threads", _i32), ("max_batch", _i32),
                 ("launch_mode", _i32), ("host_only", _i32), ("device", _i32),
-                ("reserved", _i32 * 7)]
+                ("block_threads_fwd", _i32), ("block_threads_exp", _i32),
+                ("block_threads_rev", _i32), ("autotune", _i32), ("reserved", _i32 * 3)]
 
 
 class PlanInfo(ctypes.Structure):
@@ -43,7 +44,9 @@ class PlanInfo(ctypes.Structure):
                 ("n_groups", _i32), ("n_fwd_passes", _i32), ("n_exp_passes", _i32),
                 ("n_rev_passes", _i32), ("tile_qubits", _i32), ("tile_qubits_rev", _i32),
                 ("contiguous_fwd", _i32), ("contiguous_exp", _i32), ("contiguous_rev", _i32),
-                ("block_threads", _i32), ("launch_mode", _i32), ("perm", _i32 * 32)]
+                ("block_threads_fwd", _i32), ("block_threads_exp", _i32),
+                ("block_threads_rev", _i32), ("launch_mode", _i32), ("autotuned", _i32),
+                ("perm", _i32 * 32)]
 
 
 class KernelStat(ctypes.Structure):
@@ -120,8 +123,9 @@ class Context:
     """One Hamiltonian (Eq. 2) + excitation list (Eqs. 4-5) + device buffers."""
 
     def __init__(self, n_qubits, n_elec, h1, h2, exc, *, tile_qubits=0, tile_qubits_rev=0,
-                 contiguous_qubits=0, block_threads=0, max_batch=1, launch_mode=0,
-                 host_only=False, device=-1):
+                 contiguous_qubits=0, block_threads=0, block_threads_fwd=0,
+                 block_threads_exp=0, block_threads_rev=0, max_batch=1, launch_mode=0,
+                 autotune=False, host_only=False, device=-1):
         L = lib()
         self._h = None
         self.n_qubits, self.n_elec = int(n_qubits), int(n_elec)
@@ -133,6 +137,8 @@ class Context:
         L.ucc_default_options(ctypes.byref(o))
         o.tile_qubits, o.tile_qubits_rev = tile_qubits, tile_qubits_rev
         o.contiguous_qubits, o.block_threads = contiguous_qubits, block_threads
+        o.block_threads_fwd, o.block_threads_exp = block_threads_fwd, block_threads_exp
+        o.block_threads_rev, o.autotune = block_threads_rev, int(bool(autotune))
         o.max_batch, o.launch_mode = max_batch, launch_mode
         o.host_only, o.device = int(bool(host_only)), device
         h = _vp()

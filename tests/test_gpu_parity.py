@@ -147,6 +147,45 @@ def test_16q_energy_gradient(ucc):
     assert abs(ctx.energy(th)[0] - e_ref) <= E_TOL
 
 
+@pytest.mark.parametrize("tf,te,tr", [(256, 1024, 512), (1024, 256, 1024), (512, 512, 256)])
+def test_16q_per_kind_workgroup_sizes(ucc, tf, te, tr):
+    say(f"case: 16q/8e workgroup sizes fwd {tf} exp {te} rev {tr}, batch 2")
+    n, ne = 16, 8
+    h1, h2, h, g, exc = system(n, ne, seed=4)
+    th = make_thetas(len(exc), 9, 0.1, batch=2)
+    ctx = ucc.Context(n, ne, h1, h2, exc, block_threads_fwd=tf, block_threads_exp=te,
+                      block_threads_rev=tr, max_batch=2)
+    info = ctx.plan_info()
+    assert (info["block_threads_fwd"], info["block_threads_exp"], info["block_threads_rev"]) == (tf, te, tr)
+    e, gr = ctx.energy_grad(th)
+    e_ref, g_ref = oracle_eg(n, ne, h, g, exc, th[1])
+    assert abs(e[1] - e_ref) <= E_TOL
+    assert np.max(np.abs(gr[1] - g_ref)) <= G_TOL
+
+
+def test_16q_autotuned_context(ucc):
+    say("case: 16q/8e autotune at batch 4, then parity")
+    n, ne = 16, 8
+    h1, h2, h, g, exc = system(n, ne, seed=5)
+    th = make_thetas(len(exc), 11, 0.1, batch=4)
+    ctx = ucc.Context(n, ne, h1, h2, exc, max_batch=4, autotune=True)
+    info = ctx.plan_info()
+    assert info["autotuned"] == 1
+    assert info["tile_qubits"] in (12, 13) and info["tile_qubits_rev"] in (11, 12)
+    e, gr = ctx.energy_grad(th)
+    e_ref, g_ref = oracle_eg(n, ne, h, g, exc, th[3])
+    assert abs(e[3] - e_ref) <= E_TOL
+    assert np.max(np.abs(gr[3] - g_ref)) <= G_TOL
+    # a second context of the same shape takes the cached choice
+    ctx2 = ucc.Context(n, ne, h1, h2, exc, max_batch=4, autotune=True)
+    info2 = ctx2.plan_info()
+    for key in ("tile_qubits", "tile_qubits_rev", "block_threads_fwd", "block_threads_exp",
+                "block_threads_rev"):
+        assert info2[key] == info[key]
+    e2, g2 = ctx2.energy_grad(th)
+    assert np.array_equal(e2, e) and np.array_equal(g2, gr)
+
+
 def test_18q_batch64_against_stored_oracle_values(ucc):
     say("case: 18q/10e batch 64 energy+grad (stored oracle values for entries 0, 1, 63)")
     gold = json.load(open(os.path.join(HERE, "golden", "dimer_18q.json")))

@@ -48,6 +48,7 @@ def test_library_exports_every_declared_symbol():
     dict(exc=[[1, 0, 4, 5]]),              # i > j
     dict(exc=[[0, 1, 4, 5], [0, 1, 4, 5]]),  # duplicate
     dict(h1_asym=True), dict(h2_asym=True), dict(tile_qubits=20), dict(block_threads=300),
+    dict(block_threads_rev=128), dict(block_threads_exp=768), dict(autotune=True),
 ])
 def test_invalid_inputs_are_rejected(bad):
     n, ne = bad.get("n", 8), bad.get("ne", 4)
@@ -59,7 +60,8 @@ def test_invalid_inputs_are_rejected(bad):
         h2 = h2.copy()
         h2[0, 1, 2, 3] += 1e-6
     exc = np.array(bad.get("exc", uccsd_excitations(8, 4)), dtype=np.int32)
-    kw = {k: bad[k] for k in ("tile_qubits", "block_threads") if k in bad}
+    kw = {k: bad[k] for k in ("tile_qubits", "block_threads", "block_threads_rev",
+                              "block_threads_exp", "autotune") if k in bad}
     with pytest.raises(ucc.UCCError) as ei:
         ucc.Context(n, ne, h1[: n // 2, : n // 2] if n <= 8 else np.zeros((n // 2,) * 2),
                     h2 if n == 8 else np.zeros((n // 2,) * 4), exc, host_only=True, **kw)
