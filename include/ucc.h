@@ -54,7 +54,9 @@ typedef struct {
   int32_t tile_qubits_rev;   /* k for two-vector passes (reverse sweep) (4..12) */
   int32_t contiguous_qubits; /* lowest physical bits kept inside every tile (2..k-4) */
   int32_t block_threads;     /* threads per workgroup of every pass kind: 256, 512 or 1024 */
-  int32_t max_batch;         /* theta vectors allocated up front (grows on demand) */
+  int32_t max_batch;         /* theta vectors allocated up front (grows on demand); 0 =
+                                none until the first evaluation (contexts that are only
+                                evaluated through a server) */
   int32_t launch_mode;       /* 0 auto, 1 one kernel launch per pass, 2 persistent work queue */
   int32_t host_only;         /* 1: plan on the host only (no device memory, no evaluation);
                                 for introspection and tests on machines without a GPU */
@@ -144,10 +146,18 @@ typedef struct {
   int32_t block_threads_fwd, block_threads_exp, block_threads_rev, launch_mode;
   int32_t autotuned;         /* 1 if the choices above come from measurement */
   int32_t perm[32];          /* physical bit of logical qubit q (q < n_qubits) */
+  int64_t job_footprint;     /* device bytes one server job on this context holds */
 } ucc_plan_info;
 
 /* Sizes and choices made by ucc_build. */
 ucc_status ucc_get_plan_info(const ucc_ctx* ctx, ucc_plan_info* info);
+
+/*
+ * ucc_batch_compatible -- *out = 1 if server jobs on contexts a and b can share one batched
+ * launch sequence (their tables agree in everything but the Hamiltonian's values), else 0.
+ * Works on host_only contexts too.
+ */
+ucc_status ucc_batch_compatible(const ucc_ctx* a, const ucc_ctx* b, int32_t* out);
 
 /*
  * ucc_get_pauli_terms -- the Jordan-Wigner Pauli sum H = sum_t c_t P_t built from Eq. 2.
@@ -233,23 +243,35 @@ ucc_status ucc_profile_read(ucc_ctx* ctx, ucc_kernel_stat* stats, int32_t reset)
 
 /*
  * Continuous-batching server for steepest-descent VQE jobs (theta <- theta - lr * grad).
- * A job is admitted when its device footprint (two complex128 state vectors of 2^n
- * amplitudes plus partial-sum buffers) fits in hbm_budget_bytes and a slot is free; jobs
- * that arrive while others run join the next device round.  Each round evaluates E and
- * dE/dtheta for every active job in one batched launch sequence on the server's stream.
+ * A worker thread runs rounds: it admits queued jobs (first fit) while a slot is free and
+ * the job's device footprint fits in what the budget leaves, evaluates E and dE/dtheta once
+ * for every active job, applies the update on the host and retires finished jobs.  Jobs that
+ * arrive while others run join at the next round.
+ *
+ * Batching: active jobs whose contexts agree in everything but the Hamiltonian's values
+ * (same n_qubits, n_elec, excitation list, x-group structure and tuning -- e.g. fragments of
+ * one size with their own integrals) run as one batched launch sequence, each entry with its
+ * own expectation tables; other jobs form other batches, which run on up to four streams.
+ * A job's result does not depend on what else runs (bitwise).
+ *
+ * Footprint of one job: two complex128 state vectors of 2^n amplitudes (psi, lambda), its
+ * per-tile partial sums, theta/cos-sin/gradient rows and one row of expectation tables.
  *
  *   hbm_budget_bytes  device memory the server may hold for job state (0 = 64 GiB)
  *   slots             maximum concurrently active jobs (1..4096)
  *   max_queue         maximum queued (not yet admitted) jobs; beyond it ucc_submit
  *                     returns UCC_EBUSY (0 = unlimited)
+ * The server runs on the device current at creation.
  */
 ucc_status ucc_server_create(size_t hbm_budget_bytes, int32_t slots, int32_t max_queue,
                              ucc_server** out);
 
 /*
- * ucc_submit -- enqueue a VQE job on a built context (not host_only).  The server uses the
- * context's plan and tables but its own state buffers; the context must outlive the job
- * and must not be evaluated by the caller while the job runs.
+ * ucc_submit -- enqueue a VQE job on a built context (not host_only, same device as the
+ * server).  The server uses the context's plan and tables but its own state buffers (build
+ * such contexts with max_batch = 0); the context must outlive the job, and ucc_energy /
+ * ucc_energy_grad on it return UCC_EBUSY while any of its jobs is queued or running.
+ * Errors: UCC_EINVAL, UCC_ENOMEM (footprint above the whole budget), UCC_EBUSY (queue full).
  *   theta0  host [n_exc] initial amplitudes (copied)
  *   iters   steepest-descent steps (>= 0); the job records iters + 1 energies
  *   lr      step size

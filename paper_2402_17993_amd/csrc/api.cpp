@@ -171,9 +171,13 @@ Profiler::~Profiler() {
 // The launch sequence of one call: cos/sin, forward passes (the first synthesizes |HF>),
 // expectation or apply-H passes, reverse passes (gradient), fixed-order reduction.
 ucc_status enqueue_eval(const ucc_ctx* c, Buffers& b, const double* d_theta, int B, bool grad,
-                        hipStream_t st, Profiler* prof) {
+                        hipStream_t st, Profiler* prof, const uint32_t* blob_bank) {
   const Plan& p = c->plan;
   LaunchArgs a = make_args(c, b, B, st);
+  if (blob_bank) {
+    a.blobs = reinterpret_cast<const uint4*>(blob_bank);
+    a.blob_stride = (int)(c->tab.blob.size() / 4);
+  }
   const double S = 16.0 * double(size_t(1) << p.n) * B;
   const double sec = 16.0 * double(p.nsec) * B;
   auto timed = [&](int kind, double bytes, auto&& fn) -> hipError_t {
@@ -360,7 +364,7 @@ ucc_status ucc_build(int32_t n_qubits, int32_t n_elec, const double* h1, const d
     return hip_fail(e, "hipGetDevice (no GPU?)");
   }
   ucc_status s = upload_tables(c);
-  if (s == UCC_OK) s = ensure_buffers(c, c->buf, std::max(1, o.max_batch), false);
+  if (s == UCC_OK && o.max_batch > 0) s = ensure_buffers(c, c->buf, o.max_batch, false);
   if (s == UCC_OK && o.autotune) s = autotune(c, std::max(1, o.max_batch));
   if (s != UCC_OK) {
     ucc_destroy(c);
@@ -477,6 +481,13 @@ ucc_status ucc_get_plan_info(const ucc_ctx* c, ucc_plan_info* info) {
   info->autotuned = p.autotuned ? 1 : 0;
   info->launch_mode = p.launch_mode;
   for (int q = 0; q < p.n; ++q) info->perm[q] = p.perm[q];
+  info->job_footprint = (int64_t)entry_footprint(c);
+  return UCC_OK;
+}
+
+ucc_status ucc_batch_compatible(const ucc_ctx* a, const ucc_ctx* b, int32_t* out) {
+  if (!a || !b || !out) return fail(UCC_EINVAL, "NULL argument");
+  *out = batch_compatible(a, b) ? 1 : 0;
   return UCC_OK;
 }
 

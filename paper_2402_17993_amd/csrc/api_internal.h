@@ -75,8 +75,16 @@ bool is_device_ptr(const void* p);
 void free_buffers(Buffers& b);
 ucc_status ensure_buffers(const ucc_ctx* c, Buffers& b, int B, bool need_lam);
 LaunchArgs make_args(const ucc_ctx* c, const Buffers& b, int B, hipStream_t st);
+// Launch sequence of one call on stream st.  blob_bank (optional): the expectation tables of
+// each batch entry, [B][tab.blob.size()] words, for entries with their own Hamiltonian of the
+// same structure as c (see batch_compatible); NULL = c's own tables for every entry.
 ucc_status enqueue_eval(const ucc_ctx* c, Buffers& b, const double* d_theta, int B, bool grad,
-                        hipStream_t st, Profiler* prof);
+                        hipStream_t st, Profiler* prof, const uint32_t* blob_bank = nullptr);
+// True if b's tables equal a's in everything but the expectation values, so entries built
+// from b can run in a batch launched with a's tables and a per-entry blob bank.
+bool batch_compatible(const ucc_ctx* a, const ucc_ctx* b);
+// Device bytes one batch entry of this context occupies in a server group.
+size_t entry_footprint(const ucc_ctx* c);
 Tuning choose_tuning(int n, int K, int batch, const ucc_options& o);
 void apply_tuning(Plan& p, const Tuning& tu);
 void free_tables(ucc_ctx* c);

@@ -17,6 +17,7 @@ struct LaunchArgs {
   const DevPass* hpasses = nullptr;  // host copy of the pass table (sizes for launches)
   const uint32_t* pairs = nullptr;
   const uint4* blobs = nullptr;
+  int blob_stride = 0;  // uint4 per batch entry when entries have their own Hamiltonian
   const int2* cls = nullptr;
   const uint2* list = nullptr;
   double2* psi = nullptr;

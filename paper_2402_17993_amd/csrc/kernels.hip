@@ -603,7 +603,7 @@ __global__ __launch_bounds__(T) LDS_BOUND_OCCUPANCY void k_exp(const DevPass* __
                                            const double2* __restrict__ psi,
                                            double2* __restrict__ lam, int n, uint32_t amask,
                                            uint32_t bmask, double* __restrict__ epart,
-                                           int estride, int first, int total) {
+                                           int estride, int first, int total, int bstride) {
   extern __shared__ double2 lds[];
   using TL = Tile<T, KT>;
   const DevPass ps = passes[pidx];
@@ -611,8 +611,16 @@ __global__ __launch_bounds__(T) LDS_BOUND_OCCUPANCY void k_exp(const DevPass* __
   const int tb = n - ps.k;
   const uint32_t tmask = (1u << tb) - 1u;
   uint4* lb = reinterpret_cast<uint4*>(lds + tileN);
-  const uint4* __restrict__ gb = blobs + ps.blob_off;
-  for (int i = threadIdx.x; i < ps.blob_len; i += T) lb[i] = gb[i];
+  // The blob of batch entry b sits at blobs + b * bstride (bstride 0: one Hamiltonian for
+  // the whole batch, copied once; otherwise re-staged whenever the entry changes).
+  int blob_b = -1;
+  auto stage_blob = [&](int b) {
+    const int key = bstride ? b : 0;
+    if (key == blob_b) return;
+    const uint4* __restrict__ gb = blobs + (size_t)key * bstride + ps.blob_off;
+    for (int i = threadIdx.x; i < ps.blob_len; i += T) lb[i] = gb[i];
+    blob_b = key;
+  };
   uint2* lst = reinterpret_cast<uint2*>(lb + ps.blob_len);  // the class's in-sector list
   double* red = reinterpret_cast<double*>(lst + ps.stage_len);
   int staged = -1, nlist = 0;
@@ -641,6 +649,7 @@ __global__ __launch_bounds__(T) LDS_BOUND_OCCUPANCY void k_exp(const DevPass* __
   // issue order): lambda values of an item before the prefetch of the item after it.
   {
     const uint32_t base = base_of(item);
+    stage_blob(item >> tb);
     stage_class(base);
     olds.load(lst, APPLY ? lam + ((size_t)(item >> tb) << n) : nullptr, base, nlist, rmw);
     tm.load(lds, psi + ((size_t)(item >> tb) << n), base, tileN);
@@ -748,6 +757,7 @@ __global__ __launch_bounds__(T) LDS_BOUND_OCCUPANCY void k_exp(const DevPass* __
       tm.put(r, lds);
     else
       tm.load(lds, psi + ((size_t)(next >> tb) << n), nbase, tileN);
+    stage_blob(next >> tb);  // visible to the next item after the barrier below
     stage_class(nbase);
     olds.load(lst, APPLY ? lam + ((size_t)(next >> tb) << n) : nullptr, nbase, nlist, rmw);
     const int next2 = next + gridDim.x;
@@ -870,7 +880,7 @@ hipError_t exp_t(const LaunchArgs& a, int pidx, int eslot, int first) {
       KT ? pass_grid(total, resident_grid(k_exp<T, KT, APPLY>, T, lds), 1 << (a.n - k)) : total;
   hipLaunchKernelGGL((k_exp<T, KT, APPLY>), dim3(grid), dim3(T), lds, a.stream, a.passes, pidx,
                      a.blobs, a.cls, a.list, a.psi, a.lam, a.n, a.amask, a.bmask,
-                     a.epart + (size_t)eslot, a.estride, first, total);
+                     a.epart + (size_t)eslot, a.estride, first, total, a.blob_stride);
   return hipGetLastError();
 }
 

@@ -1,26 +1,540 @@
-// Continuous-batching VQE server (include/ucc.h, "serving").
+// Continuous-batching steepest-descent VQE server (include/ucc.h, "serving").
+//
+// One worker thread runs rounds.  A round (1) admits queued jobs, first fit, while slots and
+// the device-memory budget allow, (2) evaluates E and dE/dtheta once for every active job,
+// and (3) applies theta <- theta - lr * grad on the host, records E, and retires jobs that
+// have their iters + 1 energies (or were cancelled).  Jobs join and leave between rounds, so
+// a job that arrives while others run starts at the next round instead of waiting for them.
+//
+// Batching: active jobs are partitioned into groups whose contexts share every table except
+// the expectation values (same qubit and electron count, excitation list, x-group structure
+// and tuning; batch_compatible).  A group runs as one batched launch sequence; when its
+// members come from different contexts (e.g. fragments with their own integrals), each
+// entry's expectation tables are copied into a per-group bank and the apply-H kernel reads
+// the entry's row.  Groups run on up to four streams, so unlike groups overlap on the device.
+//
+// Results do not depend on the mix: every batch entry is computed by the same kernels in the
+// same order whatever else is in the batch, and the host update is plain IEEE arithmetic.
+#include <chrono>
+#include <cmath>
+#include <condition_variable>
+#include <cstring>
+#include <deque>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <new>
+#include <thread>
+#include <vector>
+
 #include "api_internal.h"
+
+namespace ucc {
+
+template <typename T>
+static bool same_bytes(const std::vector<T>& a, const std::vector<T>& b) {
+  return a.size() == b.size() && (a.empty() || std::memcmp(a.data(), b.data(), a.size() * sizeof(T)) == 0);
+}
+
+bool batch_compatible(const ucc_ctx* a, const ucc_ctx* b) {
+  if (a == b) return true;
+  const Plan& p = a->plan;
+  const Plan& q = b->plan;
+  if (p.n != q.n || p.ne != q.ne || p.K != q.K || p.kf != q.kf || p.kr != q.kr || p.c0f != q.c0f ||
+      p.c0e != q.c0e || p.c0r != q.c0r || p.tf != q.tf || p.te != q.te || p.tr != q.tr ||
+      p.launch_mode != q.launch_mode || p.nfwd != q.nfwd || p.nexp != q.nexp || p.nrev != q.nrev ||
+      p.hf != q.hf || p.amask != q.amask || p.bmask != q.bmask || a->device != b->device)
+    return false;
+  if (!same_bytes(p.exc, q.exc) || p.groups.size() != q.groups.size() || p.passes.size() != q.passes.size())
+    return false;
+  for (size_t g = 0; g < p.groups.size(); ++g) {
+    const auto& x = p.groups[g];
+    const auto& y = q.groups[g];
+    if (x.x != y.x || x.m != y.m || x.valid != y.valid || x.has_occ != y.has_occ) return false;
+  }
+  for (size_t i = 0; i < p.passes.size(); ++i)
+    if (p.passes[i].kind != q.passes[i].kind || p.passes[i].lmask != q.passes[i].lmask ||
+        p.passes[i].items != q.passes[i].items)
+      return false;
+  const Tables& s = a->tab;
+  const Tables& t = b->tab;
+  return same_bytes(s.passes, t.passes) && same_bytes(s.exc, t.exc) && same_bytes(s.pairs, t.pairs) &&
+         same_bytes(s.cls, t.cls) && same_bytes(s.list, t.list) && s.blob.size() == t.blob.size();
+}
+
+size_t entry_footprint(const ucc_ctx* c) {
+  const Plan& p = c->plan;
+  const size_t S = size_t(16) << p.n;
+  const size_t nte = size_t(1) << (p.n - p.kf), ntr = size_t(1) << (p.n - p.kr);
+  return 2 * S + size_t(p.K) * (8 + 16 + 8) + 8 + 8 * size_t(p.nexp) * nte + 8 * size_t(p.K) * ntr +
+         4 * c->tab.blob.size();
+}
+
+namespace {
+
+using Clock = std::chrono::steady_clock;
+constexpr int kStreams = 4;
+
+struct Job {
+  uint64_t id = 0;
+  ucc_ctx* ctx = nullptr;
+  std::vector<double> theta;
+  std::vector<double> traj;
+  int iters = 0;
+  double lr = 0.0;
+  size_t footprint = 0;
+  Clock::time_point t_submit, t_admit, t_done;
+  int rounds = 0;
+  bool admitted = false, done = false, cancel = false;
+  ucc_status status = UCC_OK;
+  std::string error;
+};
+
+struct Group {
+  ucc_ctx* proto = nullptr;  // its tables drive the launches
+  std::vector<Job*> jobs;    // active members; row r of the batch = jobs[r]
+  Buffers buf;
+  uint32_t* bank = nullptr;  // [bank_cap][blob words] (mixed contexts only)
+  int bank_cap = 0;
+  std::vector<const ucc_ctx*> bank_rows;
+  double* h_theta = nullptr;  // pinned host staging
+  double* h_E = nullptr;
+  double* h_G = nullptr;
+  int h_cap = 0;
+  int stream = 0;
+};
+
+void free_group(Group& g) {
+  free_buffers(g.buf);
+  if (g.bank) (void)hipFree(g.bank);
+  if (g.h_theta) (void)hipHostFree(g.h_theta);
+  if (g.h_E) (void)hipHostFree(g.h_E);
+  if (g.h_G) (void)hipHostFree(g.h_G);
+  g.bank = nullptr;
+  g.h_theta = g.h_E = g.h_G = nullptr;
+  g.bank_cap = g.h_cap = 0;
+  g.bank_rows.clear();
+}
+
+// After members left: the launches must use the tables of a context that still has a job
+// in the group (a context may be destroyed once its own jobs are done), and rows moved.
+void members_changed(Group& g) {
+  std::fill(g.bank_rows.begin(), g.bank_rows.end(), nullptr);
+  if (g.jobs.empty()) return;
+  for (Job* j : g.jobs)
+    if (j->ctx == g.proto) return;
+  g.proto = g.jobs[0]->ctx;
+}
+
+}  // namespace
+}  // namespace ucc
 
 using namespace ucc;
 
+struct ucc_server {
+  size_t budget = 0;
+  int slots = 0, max_queue = 0;
+  int device = 0;
+  hipStream_t streams[kStreams] = {};
+  std::mutex mu;
+  std::condition_variable cv_work, cv_done;
+  std::map<uint64_t, std::unique_ptr<Job>> jobs;
+  std::deque<Job*> queue;
+  std::vector<std::unique_ptr<Group>> groups;
+  int active = 0;
+  size_t used = 0;
+  uint64_t next_id = 1;
+  int next_stream = 0;
+  bool stop = false;
+  std::thread worker;
+
+  void run();
+  void admit_locked();
+  Group* group_for(ucc_ctx* c);
+  void round(std::vector<Group*>& gs);
+  void finish_locked(Job* j, ucc_status st);
+};
+
+void ucc_server::finish_locked(Job* j, ucc_status st) {
+  j->done = true;
+  j->status = st;
+  j->t_done = Clock::now();
+  j->ctx->busy.fetch_sub(1);
+}
+
+Group* ucc_server::group_for(ucc_ctx* c) {
+  for (auto& g : groups)
+    if (g->proto == c) return g.get();
+  for (auto& g : groups)
+    if (batch_compatible(g->proto, c)) return g.get();
+  std::unique_ptr<Group> g(new Group());
+  g->proto = c;
+  g->stream = next_stream++ % kStreams;
+  groups.push_back(std::move(g));
+  return groups.back().get();
+}
+
+void ucc_server::admit_locked() {
+  for (auto it = queue.begin(); it != queue.end() && active < slots;) {
+    Job* j = *it;
+    if (used + j->footprint > budget) {
+      ++it;  // first fit: a smaller job behind it may still fit
+      continue;
+    }
+    it = queue.erase(it);
+    j->admitted = true;
+    j->t_admit = Clock::now();
+    used += j->footprint;
+    ++active;
+    group_for(j->ctx)->jobs.push_back(j);
+  }
+}
+
+// Grow a group's device and pinned buffers to B entries (capacity doubles, capped by the
+// slot count, so a growing group reallocates O(log B) times).
+static ucc_status prepare_group(Group& g, int B, int slots) {
+  const Plan& p = g.proto->plan;
+  const int cap = std::max(B, std::min(2 * std::max(g.buf.cap, 1), slots));
+  if (B > g.buf.cap) {
+    ucc_status s = ensure_buffers(g.proto, g.buf, cap, true);
+    if (s != UCC_OK) return s;
+  }
+  if (B > g.h_cap) {
+    if (g.h_theta) (void)hipHostFree(g.h_theta);
+    if (g.h_E) (void)hipHostFree(g.h_E);
+    if (g.h_G) (void)hipHostFree(g.h_G);
+    g.h_theta = g.h_E = g.h_G = nullptr;
+    g.h_cap = 0;
+    hipError_t e = hipHostMalloc(reinterpret_cast<void**>(&g.h_theta), size_t(cap) * p.K * 8);
+    if (e == hipSuccess) e = hipHostMalloc(reinterpret_cast<void**>(&g.h_E), size_t(cap) * 8);
+    if (e == hipSuccess) e = hipHostMalloc(reinterpret_cast<void**>(&g.h_G), size_t(cap) * p.K * 8);
+    if (e != hipSuccess) return hip_fail(e, "hipHostMalloc(server staging)");
+    g.h_cap = cap;
+  }
+  bool mixed = false;
+  for (Job* j : g.jobs) mixed |= j->ctx != g.proto;
+  if (mixed && B > g.bank_cap) {
+    if (g.bank) (void)hipFree(g.bank);
+    g.bank = nullptr;
+    g.bank_cap = 0;
+    g.bank_rows.clear();
+    hipError_t e = hipMalloc(reinterpret_cast<void**>(&g.bank), size_t(cap) * g.proto->tab.blob.size() * 4);
+    if (e != hipSuccess) return hip_fail(e, "hipMalloc(server blob bank)");
+    g.bank_cap = cap;
+    g.bank_rows.assign(cap, nullptr);
+  }
+  return UCC_OK;
+}
+
+// One device round: every group evaluated once (E and grad), then the host update.
+void ucc_server::round(std::vector<Group*>& gs) {
+  std::vector<ucc_status> st(gs.size(), UCC_OK);
+  std::vector<std::string> err(gs.size());
+  bool used_stream[kStreams] = {false, false, false, false};
+  for (size_t gi = 0; gi < gs.size(); ++gi) {
+    Group& g = *gs[gi];
+    const int B = (int)g.jobs.size();
+    const int K = g.proto->plan.K;
+    hipStream_t stream = streams[g.stream];
+    ucc_status s = prepare_group(g, B, slots);
+    bool mixed = false;
+    for (Job* j : g.jobs) mixed |= j->ctx != g.proto;
+    for (int r = 0; r < B && s == UCC_OK; ++r)
+      std::memcpy(g.h_theta + size_t(r) * K, g.jobs[r]->theta.data(), size_t(K) * 8);
+    hipError_t e = hipSuccess;
+    if (s == UCC_OK)
+      e = hipMemcpyAsync(g.buf.theta, g.h_theta, size_t(B) * K * 8, hipMemcpyHostToDevice, stream);
+    if (s == UCC_OK && e == hipSuccess && mixed) {
+      const size_t words = g.proto->tab.blob.size();
+      for (int r = 0; r < B && e == hipSuccess; ++r) {
+        const ucc_ctx* c = g.jobs[r]->ctx;
+        if (g.bank_rows[r] == c) continue;
+        e = hipMemcpyAsync(g.bank + size_t(r) * words, c->d_blob, words * 4, hipMemcpyDeviceToDevice, stream);
+        g.bank_rows[r] = c;
+      }
+    }
+    if (s == UCC_OK && e != hipSuccess) s = hip_fail(e, "server copies");
+    if (s == UCC_OK)
+      s = enqueue_eval(g.proto, g.buf, g.buf.theta, B, true, stream, nullptr, mixed ? g.bank : nullptr);
+    if (s == UCC_OK) {
+      e = hipMemcpyAsync(g.h_E, g.buf.E, size_t(B) * 8, hipMemcpyDeviceToHost, stream);
+      if (e == hipSuccess)
+        e = hipMemcpyAsync(g.h_G, g.buf.G, size_t(B) * K * 8, hipMemcpyDeviceToHost, stream);
+      if (e != hipSuccess) s = hip_fail(e, "server result copies");
+    }
+    if (s != UCC_OK) {
+      st[gi] = s;
+      err[gi] = g_last_error;
+      // a failed copy may leave bank rows stale
+      std::fill(g.bank_rows.begin(), g.bank_rows.end(), nullptr);
+    }
+    used_stream[g.stream] = true;
+  }
+  for (int i = 0; i < kStreams; ++i)
+    if (used_stream[i]) {
+      const hipError_t e = hipStreamSynchronize(streams[i]);
+      if (e != hipSuccess)
+        for (size_t gi = 0; gi < gs.size(); ++gi)
+          if (gs[gi]->stream == i && st[gi] == UCC_OK) {
+            st[gi] = hip_fail(e, "server round");
+            err[gi] = g_last_error;
+          }
+    }
+  std::lock_guard<std::mutex> lock(mu);
+  bool any_done = false;
+  for (size_t gi = 0; gi < gs.size(); ++gi) {
+    Group& g = *gs[gi];
+    const int K = g.proto->plan.K;
+    std::vector<Job*> keep;
+    for (size_t r = 0; r < g.jobs.size(); ++r) {
+      Job* j = g.jobs[r];
+      bool fin = false;
+      if (st[gi] != UCC_OK) {
+        j->error = err[gi];
+        finish_locked(j, st[gi]);
+        fin = true;
+      } else {
+        j->rounds += 1;
+        j->traj.push_back(g.h_E[r]);
+        if ((int)j->traj.size() == j->iters + 1) {
+          finish_locked(j, UCC_OK);
+          fin = true;
+        } else {
+          const double* gr = g.h_G + r * size_t(K);
+          for (int k = 0; k < K; ++k) {
+            const double step = j->lr * gr[k];  // rounded product, then the difference
+            j->theta[k] = j->theta[k] - step;
+          }
+          if (j->cancel) {
+            finish_locked(j, UCC_ECANCELED);
+            fin = true;
+          }
+        }
+      }
+      if (fin) {
+        used -= j->footprint;
+        --active;
+        any_done = true;
+      } else {
+        keep.push_back(j);
+      }
+    }
+    const bool changed = keep.size() != g.jobs.size();
+    g.jobs.swap(keep);
+    if (changed) members_changed(g);
+  }
+  // empty groups give their memory back
+  for (auto it = groups.begin(); it != groups.end();) {
+    if ((*it)->jobs.empty()) {
+      free_group(**it);
+      it = groups.erase(it);
+    } else {
+      ++it;
+    }
+  }
+  if (any_done) cv_done.notify_all();
+}
+
+void ucc_server::run() {
+  (void)hipSetDevice(device);
+  std::unique_lock<std::mutex> lk(mu);
+  for (;;) {
+    cv_work.wait(lk, [&] { return stop || !queue.empty() || active > 0; });
+    if (stop) break;
+    admit_locked();
+    // cancelled active jobs leave before their next evaluation
+    bool any_done = false;
+    for (auto& g : groups) {
+      std::vector<Job*> keep;
+      for (Job* j : g->jobs) {
+        if (j->cancel) {
+          finish_locked(j, UCC_ECANCELED);
+          used -= j->footprint;
+          --active;
+          any_done = true;
+        } else {
+          keep.push_back(j);
+        }
+      }
+      const bool changed = keep.size() != g->jobs.size();
+      g->jobs.swap(keep);
+      if (changed) members_changed(*g);
+    }
+    if (any_done) cv_done.notify_all();
+    std::vector<Group*> gs;
+    for (auto& g : groups)
+      if (!g->jobs.empty()) gs.push_back(g.get());
+    if (gs.empty()) {
+      // nothing fits right now (queued jobs larger than the free budget cannot occur: the
+      // budget check at submit guarantees each job fits an empty server)
+      continue;
+    }
+    lk.unlock();
+    round(gs);
+    lk.lock();
+  }
+}
+
 extern "C" {
 
-ucc_status ucc_server_create(size_t, int32_t, int32_t, ucc_server** out) {
-  if (out) *out = nullptr;
-  return fail(UCC_EINVAL, "server not available in this build");
+ucc_status ucc_server_create(size_t hbm_budget_bytes, int32_t slots, int32_t max_queue,
+                             ucc_server** out) {
+  g_last_error.clear();
+  if (!out) return fail(UCC_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (slots < 1 || slots > 4096) return fail(UCC_EINVAL, "slots must be in [1, 4096]");
+  if (max_queue < 0) return fail(UCC_EINVAL, "max_queue must be >= 0");
+  ucc_server* s = new (std::nothrow) ucc_server();
+  if (!s) return fail(UCC_ENOMEM, "host allocation failed");
+  s->budget = hbm_budget_bytes ? hbm_budget_bytes : (size_t(64) << 30);
+  s->slots = slots;
+  s->max_queue = max_queue;
+  hipError_t e = hipGetDevice(&s->device);
+  for (int i = 0; i < kStreams && e == hipSuccess; ++i)
+    e = hipStreamCreateWithFlags(&s->streams[i], hipStreamNonBlocking);
+  if (e != hipSuccess) {
+    for (auto& st : s->streams)
+      if (st) (void)hipStreamDestroy(st);
+    delete s;
+    return hip_fail(e, "server streams (no GPU?)");
+  }
+  try {
+    s->worker = std::thread([s] { s->run(); });
+  } catch (...) {
+    for (auto& st : s->streams) (void)hipStreamDestroy(st);
+    delete s;
+    return fail(UCC_ENOMEM, "cannot start the server thread");
+  }
+  *out = s;
+  return UCC_OK;
 }
-ucc_status ucc_submit(ucc_server*, ucc_ctx*, const double*, int32_t, double, uint32_t, uint64_t*) {
-  return fail(UCC_EINVAL, "server not available in this build");
+
+ucc_status ucc_submit(ucc_server* s, ucc_ctx* job, const double* theta0, int32_t iters, double lr,
+                      uint32_t flags, uint64_t* ticket) {
+  g_last_error.clear();
+  if (!s || !job || !theta0 || !ticket) return fail(UCC_EINVAL, "NULL argument");
+  if (job->host_only) return fail(UCC_EINVAL, "context was built host_only");
+  if (iters < 0) return fail(UCC_EINVAL, "iters must be >= 0");
+  if (!std::isfinite(lr)) return fail(UCC_EINVAL, "lr must be finite");
+  if (flags != 0) return fail(UCC_EINVAL, "flags must be 0");
+  if (job->device != s->device) return fail(UCC_EINVAL, "context lives on another device");
+  std::unique_ptr<Job> j(new (std::nothrow) Job());
+  if (!j) return fail(UCC_ENOMEM, "host allocation failed");
+  j->ctx = job;
+  j->theta.assign(theta0, theta0 + job->plan.K);
+  j->traj.reserve(size_t(iters) + 1);
+  j->iters = iters;
+  j->lr = lr;
+  j->footprint = entry_footprint(job);
+  j->t_submit = Clock::now();
+  if (j->footprint > s->budget)
+    return fail(UCC_ENOMEM, "job footprint exceeds the server's device-memory budget");
+  {
+    std::lock_guard<std::mutex> lock(s->mu);
+    if (s->stop) return fail(UCC_EINVAL, "server is stopping");
+    if (s->max_queue && (int)s->queue.size() >= s->max_queue)
+      return fail(UCC_EBUSY, "server queue is full");
+    j->id = s->next_id++;
+    *ticket = j->id;
+    job->busy.fetch_add(1);
+    s->queue.push_back(j.get());
+    s->jobs[j->id] = std::move(j);
+  }
+  s->cv_work.notify_one();
+  return UCC_OK;
 }
-ucc_status ucc_poll(ucc_server*, uint64_t, int32_t*, double*, double*, double*) {
-  return fail(UCC_EINVAL, "server not available in this build");
+
+static void copy_out(const Job& j, double* energy_traj, double* theta_out, double* timing) {
+  if (energy_traj) std::memcpy(energy_traj, j.traj.data(), j.traj.size() * sizeof(double));
+  if (theta_out) std::memcpy(theta_out, j.theta.data(), j.theta.size() * sizeof(double));
+  if (timing) {
+    using sec = std::chrono::duration<double>;
+    timing[0] = j.admitted ? sec(j.t_admit - j.t_submit).count() : -1.0;
+    timing[1] = sec(j.t_done - j.t_submit).count();
+    timing[2] = j.rounds;
+    timing[3] = 0.0;
+  }
 }
-ucc_status ucc_wait(ucc_server*, uint64_t, double*, double*, double*) {
-  return fail(UCC_EINVAL, "server not available in this build");
+
+ucc_status ucc_poll(ucc_server* s, uint64_t ticket, int32_t* done, double* energy_traj,
+                    double* theta_out, double* timing) {
+  g_last_error.clear();
+  if (!s || !done) return fail(UCC_EINVAL, "NULL argument");
+  std::lock_guard<std::mutex> lock(s->mu);
+  auto it = s->jobs.find(ticket);
+  if (it == s->jobs.end()) return fail(UCC_ENOTFOUND, "unknown ticket");
+  const Job& j = *it->second;
+  *done = j.done ? 1 : 0;
+  if (!j.done) return UCC_OK;
+  copy_out(j, energy_traj, theta_out, timing);
+  if (j.status != UCC_OK) g_last_error = j.error.empty() ? "job did not complete" : j.error;
+  return j.status;
 }
-ucc_status ucc_cancel(ucc_server*, uint64_t) {
-  return fail(UCC_EINVAL, "server not available in this build");
+
+ucc_status ucc_wait(ucc_server* s, uint64_t ticket, double* energy_traj, double* theta_out,
+                    double* timing) {
+  g_last_error.clear();
+  if (!s) return fail(UCC_EINVAL, "NULL argument");
+  std::unique_lock<std::mutex> lk(s->mu);
+  auto it = s->jobs.find(ticket);
+  if (it == s->jobs.end()) return fail(UCC_ENOTFOUND, "unknown ticket");
+  Job* j = it->second.get();
+  s->cv_done.wait(lk, [&] { return j->done; });
+  copy_out(*j, energy_traj, theta_out, timing);
+  const ucc_status st = j->status;
+  if (st != UCC_OK) g_last_error = j->error.empty() ? "job did not complete" : j->error;
+  s->jobs.erase(ticket);
+  return st;
 }
-void ucc_server_destroy(ucc_server*) {}
+
+ucc_status ucc_cancel(ucc_server* s, uint64_t ticket) {
+  g_last_error.clear();
+  if (!s) return fail(UCC_EINVAL, "NULL argument");
+  std::lock_guard<std::mutex> lock(s->mu);
+  auto it = s->jobs.find(ticket);
+  if (it == s->jobs.end()) return fail(UCC_ENOTFOUND, "unknown ticket");
+  Job* j = it->second.get();
+  if (j->done) return UCC_OK;
+  if (!j->admitted) {
+    for (auto q = s->queue.begin(); q != s->queue.end(); ++q)
+      if (*q == j) {
+        s->queue.erase(q);
+        break;
+      }
+    j->error = "cancelled";
+    s->finish_locked(j, UCC_ECANCELED);
+    s->cv_done.notify_all();
+  } else {
+    j->cancel = true;
+    j->error = "cancelled";
+  }
+  return UCC_OK;
+}
+
+void ucc_server_destroy(ucc_server* s) {
+  if (!s) return;
+  {
+    std::lock_guard<std::mutex> lock(s->mu);
+    s->stop = true;
+  }
+  s->cv_work.notify_all();
+  if (s->worker.joinable()) s->worker.join();
+  (void)hipSetDevice(s->device);
+  for (auto& st : s->streams)
+    if (st) (void)hipStreamSynchronize(st);
+  {
+    std::lock_guard<std::mutex> lock(s->mu);
+    for (auto& kv : s->jobs)
+      if (!kv.second->done) {
+        kv.second->error = "server destroyed";
+        s->finish_locked(kv.second.get(), UCC_ECANCELED);
+      }
+    s->cv_done.notify_all();
+  }
+  for (auto& g : s->groups) free_group(*g);
+  for (auto& st : s->streams)
+    if (st) (void)hipStreamDestroy(st);
+  delete s;
+}
 
 }  // extern "C"

@@ -19,10 +19,12 @@ _P = ctypes.POINTER
 
 STATUS = {0: "UCC_OK", -1: "UCC_EINVAL", -2: "UCC_ENOMEM", -3: "UCC_EDEVICE", -4: "UCC_EBUSY",
           -5: "UCC_ECANCELED", -6: "UCC_ENOTFOUND"}
+STATUS_CODES = {v: k for k, v in STATUS.items()}
 
 EXPORTED = [
     "ucc_default_options", "ucc_build", "ucc_energy", "ucc_energy_grad", "ucc_get_state",
-    "ucc_destroy", "ucc_last_error", "ucc_get_plan_info", "ucc_get_pauli_terms",
+    "ucc_destroy", "ucc_last_error", "ucc_get_plan_info", "ucc_batch_compatible",
+    "ucc_get_pauli_terms",
     "ucc_get_group_table", "ucc_get_excitation_table", "ucc_get_pass_table",
     "ucc_profile", "ucc_profile_read",
     "ucc_server_create", "ucc_submit", "ucc_poll", "ucc_wait", "ucc_cancel", "ucc_server_destroy",
@@ -46,7 +48,7 @@ class PlanInfo(ctypes.Structure):
                 ("contiguous_fwd", _i32), ("contiguous_exp", _i32), ("contiguous_rev", _i32),
                 ("block_threads_fwd", _i32), ("block_threads_exp", _i32),
                 ("block_threads_rev", _i32), ("launch_mode", _i32), ("autotuned", _i32),
-                ("perm", _i32 * 32)]
+                ("perm", _i32 * 32), ("job_footprint", ctypes.c_int64)]
 
 
 class KernelStat(ctypes.Structure):
@@ -80,6 +82,7 @@ def lib():
         "ucc_destroy": (None, [_vp]),
         "ucc_last_error": (ctypes.c_char_p, []),
         "ucc_get_plan_info": (_i32, [_vp, _P(PlanInfo)]),
+        "ucc_batch_compatible": (_i32, [_vp, _vp, _P(_i32)]),
         "ucc_get_pauli_terms": (_i32, [_vp, _vp, _vp, _vp]),
         "ucc_get_group_table": (_i32, [_vp, _vp, _vp, _vp, _vp, _vp, _vp]),
         "ucc_get_excitation_table": (_i32, [_vp, _vp, _vp, _vp, _vp]),
@@ -211,6 +214,13 @@ class Context:
         d["perm"] = list(info.perm)[: info.n_qubits]
         return d
 
+    def batch_compatible(self, other):
+        """True if server jobs on this context and `other` share batched launches."""
+        out = ctypes.c_int32()
+        check(lib().ucc_batch_compatible(self._h, other._h, ctypes.byref(out)),
+              "ucc_batch_compatible")
+        return bool(out.value)
+
     def pauli_terms(self):
         n = self.plan_info()["n_pauli"]
         x, z, c = np.empty(n, np.uint64), np.empty(n, np.uint64), np.empty(n)
@@ -251,6 +261,83 @@ class Context:
     def close(self):
         if self._h:
             lib().ucc_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+
+class Server:
+    """Continuous-batching steepest-descent VQE server (ucc_server_* calls).
+
+    submit(ctx, theta0, iters, lr) -> ticket; poll(ticket) -> None while running, else the
+    result; wait(ticket) -> result.  A result is dict(status, energies [iters + 1],
+    theta [n_exc], admit_s, done_s, rounds); a cancelled job has status UCC_ECANCELED.
+    """
+
+    def __init__(self, hbm_budget=0, slots=64, max_queue=0):
+        h = _vp()
+        check(lib().ucc_server_create(int(hbm_budget), int(slots), int(max_queue), ctypes.byref(h)),
+              "ucc_server_create")
+        self._h = h
+        self._meta = {}
+
+    def submit(self, ctx, theta0, iters, lr):
+        th = np.ascontiguousarray(theta0, dtype=np.float64).reshape(-1)
+        if th.size != ctx.n_exc:
+            raise ValueError("theta0 must hold n_exc amplitudes")
+        t = ctypes.c_uint64()
+        check(lib().ucc_submit(self._h, ctx._h, _ptr(th), int(iters), float(lr), 0,
+                               ctypes.byref(t)), "ucc_submit")
+        self._meta[t.value] = (int(iters), ctx.n_exc)
+        return t.value
+
+    def _bufs(self, ticket):
+        if ticket not in self._meta:  # not submitted here: the library reports the status
+            return None, None, np.zeros(4)
+        iters, K = self._meta[ticket]
+        return np.empty(iters + 1), np.empty(K), np.empty(4)
+
+    @staticmethod
+    def _result(status, e, th, tm):
+        rounds = int(tm[2])
+        return dict(status=int(status), energies=e[:rounds].copy() if status else e, theta=th,
+                    admit_s=float(tm[0]), done_s=float(tm[1]), rounds=rounds)
+
+    def poll(self, ticket):
+        done = ctypes.c_int32()
+        e, th, tm = self._bufs(ticket)
+        st = lib().ucc_poll(self._h, ticket, ctypes.byref(done), _ptr(e), _ptr(th), _ptr(tm))
+        if not done.value:
+            check(st, "ucc_poll")
+            return None
+        if st not in (0, STATUS_CODES["UCC_ECANCELED"]):
+            check(st, "ucc_poll")
+        return self._result(st, e, th, tm)
+
+    def wait(self, ticket):
+        e, th, tm = self._bufs(ticket)
+        st = lib().ucc_wait(self._h, ticket, _ptr(e), _ptr(th), _ptr(tm))
+        self._meta.pop(ticket, None)
+        if st not in (0, STATUS_CODES["UCC_ECANCELED"]):
+            check(st, "ucc_wait")
+        return self._result(st, e, th, tm)
+
+    def cancel(self, ticket):
+        check(lib().ucc_cancel(self._h, ticket), "ucc_cancel")
+
+    def close(self):
+        if self._h:
+            lib().ucc_server_destroy(self._h)
             self._h = None
 
     def __del__(self):

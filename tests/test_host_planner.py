@@ -189,3 +189,37 @@ def test_pass_plan_covers_everything_in_order(n, ne, kf, kr):
         assert bin(p["local"]).count("1") == info["tile_qubits"]
         for gi in p["items"]:
             assert int(gt["x"][gi]) & ~p["local"] == 0
+
+
+# ---------------------------------------------------------------- serving (host side)
+
+def test_batch_compatibility_and_job_footprint():
+    exc = uccsd_excitations(12, 8)
+    a = ucc.Context(12, 8, *make_integrals(6, 1), exc, host_only=True)
+    b = ucc.Context(12, 8, *make_integrals(6, 2), exc, host_only=True)
+    assert a.batch_compatible(b) and b.batch_compatible(a) and a.batch_compatible(a)
+    # another size, another excitation list, another tiling: separate batches
+    c = ucc.Context(16, 8, *make_integrals(8, 1), uccsd_excitations(16, 8), host_only=True)
+    d = ucc.Context(12, 8, *make_integrals(6, 2), exc[:-1], host_only=True)
+    e = ucc.Context(12, 8, *make_integrals(6, 2), exc, host_only=True, tile_qubits=10)
+    assert not a.batch_compatible(c) and not a.batch_compatible(d) and not a.batch_compatible(e)
+    # footprint: two complex128 vectors plus partial sums, rows and one table row
+    info = a.plan_info()
+    S = 16 << 12
+    assert 2 * S < info["job_footprint"] < 2 * S + (1 << 20)
+
+
+def test_server_argument_errors():
+    with pytest.raises(ucc.UCCError) as ei:
+        ucc.Server(slots=0)
+    assert ei.value.status == -1
+    with pytest.raises(ucc.UCCError) as ei:
+        ucc.Server(slots=8, max_queue=-1)
+    assert ei.value.status == -1
+    L = ucc.lib()
+    t = ucc.ctypes.c_uint64()
+    assert L.ucc_submit(None, None, None, 1, 0.1, 0, ucc.ctypes.byref(t)) == -1
+    done = ucc.ctypes.c_int32()
+    assert L.ucc_poll(None, 1, ucc.ctypes.byref(done), None, None, None) == -1
+    assert L.ucc_cancel(None, 1) == -1
+    L.ucc_server_destroy(None)  # accepted
