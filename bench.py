@@ -65,6 +65,94 @@ def copy_calibration(gib):
     print(json.dumps({"copy_bytes_read": n * 8, "copy_bytes_written": n * 8, "launches": 3}))
 
 
+def one_at_a_time(ctx, td):
+    """The plain path: one ucc_energy_grad call per theta vector (B = 1), device-resident."""
+    import torch
+
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for b in range(td.shape[0]):
+        ctx.energy_grad(td[b])
+    torch.cuda.synchronize()
+    return td.shape[0] / (time.perf_counter() - t0)
+
+
+def served_same_workload(ucc, h1, h2, exc, thetas, iters=4):
+    """The workload's 64 theta vectors as 64 steepest-descent jobs on the server."""
+    ctx = ucc.Context(N, NE, h1, h2, exc, max_batch=0, device=0, autotune=True)
+    with ucc.Server(slots=BATCH) as srv:
+        t0 = time.perf_counter()
+        tickets = [srv.submit(ctx, thetas[b], iters, 0.1) for b in range(BATCH)]
+        res = [srv.wait(t) for t in tickets]
+        wall = time.perf_counter() - t0
+    assert all(r["status"] == 0 for r in res)
+    return BATCH * (iters + 1) / wall
+
+
+MIX = {"monomer": (12, 8), "dimer": (18, 10), "trimer": (24, 14)}
+
+
+def serving_mix(ucc, n_arrivals, rate=200.0, iters=30, lr=0.1, seed=0):
+    """FMO-like serving trace: Poisson arrivals at `rate`/s of monomer / dimer / trimer VQE
+    jobs in ratio 3:3:1, job i with integrals from seed 1000 + i and theta0 ~ U(-0.05, 0.05)
+    from seed 2000 + i, `iters` steepest-descent steps each.  Contexts are built before the
+    clock starts; latency runs from submission to the last energy."""
+    from paper_2402_17993_amd.inputs import make_integrals, make_thetas, uccsd_excitations
+
+    rng = np.random.default_rng(seed)
+    arrive = np.cumsum(rng.exponential(1.0 / rate, n_arrivals))
+    kinds = [("monomer", "dimer", "trimer")[min(2, int(k) // 3)] for k in rng.integers(0, 7, n_arrivals)]
+    t0 = time.perf_counter()
+    jobs = []
+    for i, kind in enumerate(kinds):
+        n, ne = MIX[kind]
+        h1, h2 = make_integrals(n // 2, 1000 + i)
+        exc = uccsd_excitations(n, ne)
+        ctx = ucc.Context(n, ne, h1, h2, exc, max_batch=0, device=0)
+        jobs.append((kind, ctx, make_thetas(len(exc), 2000 + i, 0.05)))
+    build_s = time.perf_counter() - t0
+    res = []
+    with ucc.Server(slots=256) as srv:
+        start = time.perf_counter()
+        tickets = []
+        for i, (kind, ctx, th) in enumerate(jobs):
+            delay = start + arrive[i] - time.perf_counter()
+            if delay > 0:
+                time.sleep(delay)
+            tickets.append(srv.submit(ctx, th, iters, lr))
+        for t in tickets:
+            res.append(srv.wait(t))
+        makespan = time.perf_counter() - start
+    assert all(r["status"] == 0 for r in res)
+    lat = np.array([r["done_s"] for r in res])
+    per_it = np.array([(r["done_s"] - r["admit_s"]) / r["rounds"] for r in res])
+    out = {"arrivals": n_arrivals, "trace_s": float(arrive[-1]), "rate_per_s": rate,
+           "iters": iters, "jobs": {k: kinds.count(k) for k in MIX},
+           "makespan_s": makespan, "evals_per_s": len(res) * (iters + 1) / makespan,
+           "latency_p50_s": float(np.percentile(lat, 50)), "latency_p99_s": float(np.percentile(lat, 99)),
+           "per_iteration_p50_ms": 1e3 * float(np.percentile(per_it, 50)),
+           "per_iteration_p99_ms": 1e3 * float(np.percentile(per_it, 99)),
+           "context_build_s": build_s, "by_kind": {}}
+    for k in MIX:
+        sel = [j for j, kind in enumerate(kinds) if kind == k]
+        if sel:
+            out["by_kind"][k] = {"latency_p50_s": float(np.percentile(lat[sel], 50)),
+                                 "latency_p99_s": float(np.percentile(lat[sel], 99)),
+                                 "per_iteration_p50_ms": 1e3 * float(np.percentile(per_it[sel], 50))}
+    # alone vs in the mix: the first monomer and dimer jobs again, alone
+    same = True
+    for k in ("monomer", "dimer"):
+        sel = [j for j, kind in enumerate(kinds) if kind == k]
+        if sel:
+            j = sel[0]
+            with ucc.Server(slots=4) as srv:
+                r = srv.wait(srv.submit(jobs[j][1], jobs[j][2], iters, lr))
+            same &= bool(np.array_equal(r["energies"], res[j]["energies"]) and
+                         np.array_equal(r["theta"], res[j]["theta"]))
+    out["alone_equals_mix_bitwise"] = same
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -74,6 +162,8 @@ def main():
     ap.add_argument("--launch-mode", type=int, default=0)
     ap.add_argument("--no-autotune", action="store_true",
                     help="use the fixed tuning table instead of timing the candidates")
+    ap.add_argument("--serve-arrivals", type=int, default=70,
+                    help="arrivals of the serving trace (0 = skip the serving legs)")
     ap.add_argument("--copy-calibration", type=float, default=0.0, metavar="GIB",
                     help="only run a plain device copy of GIB GiB (counter calibration) and exit")
     args = ap.parse_args()
@@ -144,6 +234,7 @@ def main():
 
     ms_per_step = 1e3 * wall_plain / args.steps
     value = BATCH * args.steps / wall_plain
+    plain = one_at_a_time(ctx, td)
 
     dom = max((k for k in stats if stats[k]["launches"]), key=lambda k: stats[k]["ms"])
     d = stats[dom]
@@ -193,6 +284,10 @@ def main():
                     for k, v in stats.items() if v["launches"]},
         "parity": {"max_abs_dE": de, "max_abs_dgrad": dg, "entries": sorted(gold["entries"])},
     }
+    out["one_at_a_time_evals_per_s"] = plain
+    if args.serve_arrivals > 0:
+        out["served_evals_per_s"] = served_same_workload(ucc, h1, h2, exc, thetas)
+        out["serving_mix"] = serving_mix(ucc, args.serve_arrivals)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline()
     print(json.dumps(out))

@@ -243,16 +243,15 @@ ucc_status ucc_profile_read(ucc_ctx* ctx, ucc_kernel_stat* stats, int32_t reset)
 
 /*
  * Continuous-batching server for steepest-descent VQE jobs (theta <- theta - lr * grad).
- * A worker thread runs rounds: it admits queued jobs (first fit) while a slot is free and
- * the job's device footprint fits in what the budget leaves, evaluates E and dE/dtheta once
- * for every active job, applies the update on the host and retires finished jobs.  Jobs that
- * arrive while others run join at the next round.
- *
- * Batching: active jobs whose contexts agree in everything but the Hamiltonian's values
- * (same n_qubits, n_elec, excitation list, x-group structure and tuning -- e.g. fragments of
- * one size with their own integrals) run as one batched launch sequence, each entry with its
- * own expectation tables; other jobs form other batches, which run on up to four streams.
- * A job's result does not depend on what else runs (bitwise).
+ * Queued jobs are admitted (first fit) while a slot is free and the job's device footprint
+ * fits in what the budget leaves.  Admitted jobs whose contexts agree in everything but the
+ * Hamiltonian's values (same n_qubits, n_elec, excitation list, x-group structure and tuning
+ * -- e.g. fragments of one size with their own integrals) form a batch group; each entry
+ * keeps its own expectation tables.  Every group iterates on its own stream at its own pace:
+ * a round evaluates E and dE/dtheta for all members in one batched launch sequence, then
+ * applies the update on the host and retires finished jobs; jobs that arrive while the group
+ * runs join at its next round.  Groups' kernels overlap on the device.  A job's result does
+ * not depend on what else runs (bitwise).
  *
  * Footprint of one job: two complex128 state vectors of 2^n amplitudes (psi, lambda), its
  * per-tile partial sums, theta/cos-sin/gradient rows and one row of expectation tables.

@@ -171,9 +171,10 @@ Profiler::~Profiler() {
 // The launch sequence of one call: cos/sin, forward passes (the first synthesizes |HF>),
 // expectation or apply-H passes, reverse passes (gradient), fixed-order reduction.
 ucc_status enqueue_eval(const ucc_ctx* c, Buffers& b, const double* d_theta, int B, bool grad,
-                        hipStream_t st, Profiler* prof, const uint32_t* blob_bank) {
+                        hipStream_t st, Profiler* prof, const uint32_t* blob_bank, int cu_share) {
   const Plan& p = c->plan;
   LaunchArgs a = make_args(c, b, B, st);
+  a.cu_share = cu_share;
   if (blob_bank) {
     a.blobs = reinterpret_cast<const uint4*>(blob_bank);
     a.blob_stride = (int)(c->tab.blob.size() / 4);

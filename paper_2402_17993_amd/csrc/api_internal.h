@@ -78,8 +78,10 @@ LaunchArgs make_args(const ucc_ctx* c, const Buffers& b, int B, hipStream_t st);
 // Launch sequence of one call on stream st.  blob_bank (optional): the expectation tables of
 // each batch entry, [B][tab.blob.size()] words, for entries with their own Hamiltonian of the
 // same structure as c (see batch_compatible); NULL = c's own tables for every entry.
+// cu_share: compute units the persistent pass kernels may fill (0 = the whole device).
 ucc_status enqueue_eval(const ucc_ctx* c, Buffers& b, const double* d_theta, int B, bool grad,
-                        hipStream_t st, Profiler* prof, const uint32_t* blob_bank = nullptr);
+                        hipStream_t st, Profiler* prof, const uint32_t* blob_bank = nullptr,
+                        int cu_share = 0);
 // True if b's tables equal a's in everything but the expectation values, so entries built
 // from b can run in a batch launched with a's tables and a per-entry blob bank.
 bool batch_compatible(const ucc_ctx* a, const ucc_ctx* b);

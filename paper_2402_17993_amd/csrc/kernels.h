@@ -18,6 +18,7 @@ struct LaunchArgs {
   const uint32_t* pairs = nullptr;
   const uint4* blobs = nullptr;
   int blob_stride = 0;  // uint4 per batch entry when entries have their own Hamiltonian
+  int cu_share = 0;     // compute units the persistent pass kernels may fill (0 = all)
   const int2* cls = nullptr;
   const uint2* list = nullptr;
   double2* psi = nullptr;
@@ -29,6 +30,9 @@ struct LaunchArgs {
   double* E = nullptr;
   double* G = nullptr;
 };
+
+// Compute units of the current device.
+int device_cus();
 
 hipError_t launch_trig(const LaunchArgs& a, const double* theta);
 hipError_t launch_fwd(const LaunchArgs& a, int pidx, int init);

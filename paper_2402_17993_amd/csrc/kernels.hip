@@ -790,6 +790,20 @@ __global__ __launch_bounds__(T) void k_reduce(const double* __restrict__ epart, 
 
 // ---------------------------------------------------------------- launchers
 
+int device_cus() {
+  static int g_cus = 0;
+  static std::once_flag once;
+  std::call_once(once, [] {
+    int dev = 0, c = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&c, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || c <= 0)
+      c = 256;
+    (void)hipGetLastError();
+    g_cus = c;
+  });
+  return g_cus;
+}
+
 namespace {
 
 template <typename F>
@@ -798,22 +812,21 @@ hipError_t set_lds(F kernel, size_t bytes) {
                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
 }
 
-// Workgroups that fit on the device at once for this kernel and LDS size (cached).
+// Workgroups that fit on the device at once for this kernel and LDS size (cached), scaled to
+// the launch's share of the compute units (cu_share 0 = all of them).
 template <typename F>
-int resident_grid(F kernel, int threads, size_t lds) {
+int resident_grid(F kernel, int threads, size_t lds, int cu_share) {
   static std::mutex mu;
   static std::map<std::pair<const void*, size_t>, int> cache;
-  static int cus = 0;
+  const int cus = device_cus();
   const auto key = std::make_pair(reinterpret_cast<const void*>(kernel), lds);
+  auto scaled = [&](int g) {
+    if (cu_share <= 0 || cu_share >= cus) return g;
+    return std::max(1, (int)((long long)g * cu_share / cus));
+  };
   std::lock_guard<std::mutex> lock(mu);
   auto it = cache.find(key);
-  if (it != cache.end()) return it->second;
-  if (cus == 0) {
-    int dev = 0;
-    if (hipGetDevice(&dev) != hipSuccess ||
-        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0)
-      cus = 256;
-  }
+  if (it != cache.end()) return scaled(it->second);
   int per = 0;
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, reinterpret_cast<const void*>(kernel),
                                                    threads, lds) != hipSuccess || per <= 0)
@@ -821,7 +834,7 @@ int resident_grid(F kernel, int threads, size_t lds) {
   (void)hipGetLastError();
   const int g = per * cus;
   cache[key] = g;
-  return g;
+  return scaled(g);
 }
 
 // Grid of a persistent pass: resident workgroups, rounded down to a multiple of the tile
@@ -840,7 +853,7 @@ hipError_t fwd_ti(const LaunchArgs& a, int pidx) {
   hipError_t e = set_lds(k_fwd<T, KT, INIT>, lds);
   if (e != hipSuccess) return e;
   const int total = a.B << (a.n - k);
-  const int grid = KT ? pass_grid(total, resident_grid(k_fwd<T, KT, INIT>, T, lds), 1 << (a.n - k))
+  const int grid = KT ? pass_grid(total, resident_grid(k_fwd<T, KT, INIT>, T, lds, a.cu_share), 1 << (a.n - k))
                       : total;
   hipLaunchKernelGGL((k_fwd<T, KT, INIT>), dim3(grid), dim3(T), lds, a.stream, a.passes, pidx,
                      a.exc, a.cls, a.pairs, a.cs, a.K, a.psi, a.n, a.hf, a.amask, a.bmask, total);
@@ -860,7 +873,7 @@ hipError_t rev_t(const LaunchArgs& a, int pidx) {
   hipError_t e = set_lds(k_rev<T, KT>, lds);
   if (e != hipSuccess) return e;
   const int total = a.B << (a.n - k);
-  const int grid = KT ? pass_grid(total, resident_grid(k_rev<T, KT>, T, lds), 1 << (a.n - k)) : total;
+  const int grid = KT ? pass_grid(total, resident_grid(k_rev<T, KT>, T, lds, a.cu_share), 1 << (a.n - k)) : total;
   hipLaunchKernelGGL((k_rev<T, KT>), dim3(grid), dim3(T), lds, a.stream, a.passes, pidx, a.exc,
                      a.cls, a.pairs, a.cs, a.K, a.psi, a.lam, a.n, a.amask, a.bmask, a.gpart,
                      total);
@@ -877,7 +890,7 @@ hipError_t exp_t(const LaunchArgs& a, int pidx, int eslot, int first) {
   if (e != hipSuccess) return e;
   const int total = a.B << (a.n - k);
   const int grid =
-      KT ? pass_grid(total, resident_grid(k_exp<T, KT, APPLY>, T, lds), 1 << (a.n - k)) : total;
+      KT ? pass_grid(total, resident_grid(k_exp<T, KT, APPLY>, T, lds, a.cu_share), 1 << (a.n - k)) : total;
   hipLaunchKernelGGL((k_exp<T, KT, APPLY>), dim3(grid), dim3(T), lds, a.stream, a.passes, pidx,
                      a.blobs, a.cls, a.list, a.psi, a.lam, a.n, a.amask, a.bmask,
                      a.epart + (size_t)eslot, a.estride, first, total, a.blob_stride);

@@ -1,17 +1,20 @@
 // Continuous-batching steepest-descent VQE server (include/ucc.h, "serving").
 //
-// One worker thread runs rounds.  A round (1) admits queued jobs, first fit, while slots and
-// the device-memory budget allow, (2) evaluates E and dE/dtheta once for every active job,
-// and (3) applies theta <- theta - lr * grad on the host, records E, and retires jobs that
-// have their iters + 1 energies (or were cancelled).  Jobs join and leave between rounds, so
-// a job that arrives while others run starts at the next round instead of waiting for them.
+// Admission: queued jobs are admitted first fit while a slot is free and the job's device
+// footprint fits in what the budget leaves.
 //
-// Batching: active jobs are partitioned into groups whose contexts share every table except
+// Batching: admitted jobs are partitioned into groups whose contexts share every table except
 // the expectation values (same qubit and electron count, excitation list, x-group structure
-// and tuning; batch_compatible).  A group runs as one batched launch sequence; when its
+// and tuning; batch_compatible).  A group runs one batched launch sequence per round; when its
 // members come from different contexts (e.g. fragments with their own integrals), each
 // entry's expectation tables are copied into a per-group bank and the apply-H kernel reads
-// the entry's row.  Groups run on up to four streams, so unlike groups overlap on the device.
+// the entry's row.
+//
+// Rounds are per group: each group has its own stream and iterates at its own pace (one
+// round = E and dE/dtheta for every member, then theta <- theta - lr * grad on the host), so
+// small fragments are not held back by large ones, and the groups' kernels overlap on the
+// device.  One worker thread launches idle groups and polls the in-flight ones; jobs join
+// and leave a group between its rounds.
 //
 // Results do not depend on the mix: every batch entry is computed by the same kernels in the
 // same order whatever else is in the batch, and the host update is plain IEEE arithmetic.
@@ -73,7 +76,6 @@ size_t entry_footprint(const ucc_ctx* c) {
 namespace {
 
 using Clock = std::chrono::steady_clock;
-constexpr int kStreams = 4;
 
 struct Job {
   uint64_t id = 0;
@@ -91,29 +93,32 @@ struct Job {
 };
 
 struct Group {
-  ucc_ctx* proto = nullptr;  // its tables drive the launches
-  std::vector<Job*> jobs;    // active members; row r of the batch = jobs[r]
+  ucc_ctx* proto = nullptr;   // its tables drive the launches
+  std::vector<Job*> jobs;     // members of the current round; row r = jobs[r]
+  std::vector<Job*> joining;  // admitted, enter at the next round
   Buffers buf;
-  uint32_t* bank = nullptr;  // [bank_cap][blob words] (mixed contexts only)
+  uint32_t* bank = nullptr;   // [bank_cap][blob words] (mixed contexts only)
   int bank_cap = 0;
   std::vector<const ucc_ctx*> bank_rows;
   double* h_theta = nullptr;  // pinned host staging
   double* h_E = nullptr;
   double* h_G = nullptr;
   int h_cap = 0;
-  int stream = 0;
+  hipStream_t stream = nullptr;
+  hipEvent_t done_ev = nullptr;
+  bool in_flight = false;
 };
 
 void free_group(Group& g) {
+  if (g.stream) (void)hipStreamSynchronize(g.stream);
   free_buffers(g.buf);
   if (g.bank) (void)hipFree(g.bank);
   if (g.h_theta) (void)hipHostFree(g.h_theta);
   if (g.h_E) (void)hipHostFree(g.h_E);
   if (g.h_G) (void)hipHostFree(g.h_G);
-  g.bank = nullptr;
-  g.h_theta = g.h_E = g.h_G = nullptr;
-  g.bank_cap = g.h_cap = 0;
-  g.bank_rows.clear();
+  if (g.done_ev) (void)hipEventDestroy(g.done_ev);
+  if (g.stream) (void)hipStreamDestroy(g.stream);
+  g = Group();
 }
 
 // After members left: the launches must use the tables of a context that still has a job
@@ -126,73 +131,9 @@ void members_changed(Group& g) {
   g.proto = g.jobs[0]->ctx;
 }
 
-}  // namespace
-}  // namespace ucc
-
-using namespace ucc;
-
-struct ucc_server {
-  size_t budget = 0;
-  int slots = 0, max_queue = 0;
-  int device = 0;
-  hipStream_t streams[kStreams] = {};
-  std::mutex mu;
-  std::condition_variable cv_work, cv_done;
-  std::map<uint64_t, std::unique_ptr<Job>> jobs;
-  std::deque<Job*> queue;
-  std::vector<std::unique_ptr<Group>> groups;
-  int active = 0;
-  size_t used = 0;
-  uint64_t next_id = 1;
-  int next_stream = 0;
-  bool stop = false;
-  std::thread worker;
-
-  void run();
-  void admit_locked();
-  Group* group_for(ucc_ctx* c);
-  void round(std::vector<Group*>& gs);
-  void finish_locked(Job* j, ucc_status st);
-};
-
-void ucc_server::finish_locked(Job* j, ucc_status st) {
-  j->done = true;
-  j->status = st;
-  j->t_done = Clock::now();
-  j->ctx->busy.fetch_sub(1);
-}
-
-Group* ucc_server::group_for(ucc_ctx* c) {
-  for (auto& g : groups)
-    if (g->proto == c) return g.get();
-  for (auto& g : groups)
-    if (batch_compatible(g->proto, c)) return g.get();
-  std::unique_ptr<Group> g(new Group());
-  g->proto = c;
-  g->stream = next_stream++ % kStreams;
-  groups.push_back(std::move(g));
-  return groups.back().get();
-}
-
-void ucc_server::admit_locked() {
-  for (auto it = queue.begin(); it != queue.end() && active < slots;) {
-    Job* j = *it;
-    if (used + j->footprint > budget) {
-      ++it;  // first fit: a smaller job behind it may still fit
-      continue;
-    }
-    it = queue.erase(it);
-    j->admitted = true;
-    j->t_admit = Clock::now();
-    used += j->footprint;
-    ++active;
-    group_for(j->ctx)->jobs.push_back(j);
-  }
-}
-
 // Grow a group's device and pinned buffers to B entries (capacity doubles, capped by the
 // slot count, so a growing group reallocates O(log B) times).
-static ucc_status prepare_group(Group& g, int B, int slots) {
+ucc_status prepare_group(Group& g, int B, int slots, bool mixed) {
   const Plan& p = g.proto->plan;
   const int cap = std::max(B, std::min(2 * std::max(g.buf.cap, 1), slots));
   if (B > g.buf.cap) {
@@ -211,8 +152,6 @@ static ucc_status prepare_group(Group& g, int B, int slots) {
     if (e != hipSuccess) return hip_fail(e, "hipHostMalloc(server staging)");
     g.h_cap = cap;
   }
-  bool mixed = false;
-  for (Job* j : g.jobs) mixed |= j->ctx != g.proto;
   if (mixed && B > g.bank_cap) {
     if (g.bank) (void)hipFree(g.bank);
     g.bank = nullptr;
@@ -226,152 +165,257 @@ static ucc_status prepare_group(Group& g, int B, int slots) {
   return UCC_OK;
 }
 
-// One device round: every group evaluated once (E and grad), then the host update.
-void ucc_server::round(std::vector<Group*>& gs) {
-  std::vector<ucc_status> st(gs.size(), UCC_OK);
-  std::vector<std::string> err(gs.size());
-  bool used_stream[kStreams] = {false, false, false, false};
-  for (size_t gi = 0; gi < gs.size(); ++gi) {
-    Group& g = *gs[gi];
-    const int B = (int)g.jobs.size();
-    const int K = g.proto->plan.K;
-    hipStream_t stream = streams[g.stream];
-    ucc_status s = prepare_group(g, B, slots);
-    bool mixed = false;
-    for (Job* j : g.jobs) mixed |= j->ctx != g.proto;
-    for (int r = 0; r < B && s == UCC_OK; ++r)
-      std::memcpy(g.h_theta + size_t(r) * K, g.jobs[r]->theta.data(), size_t(K) * 8);
-    hipError_t e = hipSuccess;
-    if (s == UCC_OK)
-      e = hipMemcpyAsync(g.buf.theta, g.h_theta, size_t(B) * K * 8, hipMemcpyHostToDevice, stream);
-    if (s == UCC_OK && e == hipSuccess && mixed) {
-      const size_t words = g.proto->tab.blob.size();
-      for (int r = 0; r < B && e == hipSuccess; ++r) {
-        const ucc_ctx* c = g.jobs[r]->ctx;
-        if (g.bank_rows[r] == c) continue;
-        e = hipMemcpyAsync(g.bank + size_t(r) * words, c->d_blob, words * 4, hipMemcpyDeviceToDevice, stream);
-        g.bank_rows[r] = c;
-      }
-    }
-    if (s == UCC_OK && e != hipSuccess) s = hip_fail(e, "server copies");
-    if (s == UCC_OK)
-      s = enqueue_eval(g.proto, g.buf, g.buf.theta, B, true, stream, nullptr, mixed ? g.bank : nullptr);
-    if (s == UCC_OK) {
-      e = hipMemcpyAsync(g.h_E, g.buf.E, size_t(B) * 8, hipMemcpyDeviceToHost, stream);
-      if (e == hipSuccess)
-        e = hipMemcpyAsync(g.h_G, g.buf.G, size_t(B) * K * 8, hipMemcpyDeviceToHost, stream);
-      if (e != hipSuccess) s = hip_fail(e, "server result copies");
-    }
-    if (s != UCC_OK) {
-      st[gi] = s;
-      err[gi] = g_last_error;
-      // a failed copy may leave bank rows stale
-      std::fill(g.bank_rows.begin(), g.bank_rows.end(), nullptr);
-    }
-    used_stream[g.stream] = true;
-  }
-  for (int i = 0; i < kStreams; ++i)
-    if (used_stream[i]) {
-      const hipError_t e = hipStreamSynchronize(streams[i]);
-      if (e != hipSuccess)
-        for (size_t gi = 0; gi < gs.size(); ++gi)
-          if (gs[gi]->stream == i && st[gi] == UCC_OK) {
-            st[gi] = hip_fail(e, "server round");
-            err[gi] = g_last_error;
-          }
-    }
-  std::lock_guard<std::mutex> lock(mu);
-  bool any_done = false;
-  for (size_t gi = 0; gi < gs.size(); ++gi) {
-    Group& g = *gs[gi];
-    const int K = g.proto->plan.K;
-    std::vector<Job*> keep;
-    for (size_t r = 0; r < g.jobs.size(); ++r) {
-      Job* j = g.jobs[r];
-      bool fin = false;
-      if (st[gi] != UCC_OK) {
-        j->error = err[gi];
-        finish_locked(j, st[gi]);
-        fin = true;
-      } else {
-        j->rounds += 1;
-        j->traj.push_back(g.h_E[r]);
-        if ((int)j->traj.size() == j->iters + 1) {
-          finish_locked(j, UCC_OK);
-          fin = true;
-        } else {
-          const double* gr = g.h_G + r * size_t(K);
-          for (int k = 0; k < K; ++k) {
-            const double step = j->lr * gr[k];  // rounded product, then the difference
-            j->theta[k] = j->theta[k] - step;
-          }
-          if (j->cancel) {
-            finish_locked(j, UCC_ECANCELED);
-            fin = true;
-          }
-        }
-      }
-      if (fin) {
-        used -= j->footprint;
-        --active;
-        any_done = true;
-      } else {
-        keep.push_back(j);
-      }
-    }
-    const bool changed = keep.size() != g.jobs.size();
-    g.jobs.swap(keep);
-    if (changed) members_changed(g);
-  }
-  // empty groups give their memory back
-  for (auto it = groups.begin(); it != groups.end();) {
-    if ((*it)->jobs.empty()) {
-      free_group(**it);
-      it = groups.erase(it);
-    } else {
-      ++it;
+// Enqueue one round of group g on its stream: theta rows in, E and grad out.  The pass
+// kernels fill at most cu_share compute units (0 = all).
+ucc_status launch_round(Group& g, int slots, int cu_share) {
+  const int B = (int)g.jobs.size();
+  const int K = g.proto->plan.K;
+  bool mixed = false;
+  for (Job* j : g.jobs) mixed |= j->ctx != g.proto;
+  ucc_status s = prepare_group(g, B, slots, mixed);
+  if (s != UCC_OK) return s;
+  for (int r = 0; r < B; ++r) std::memcpy(g.h_theta + size_t(r) * K, g.jobs[r]->theta.data(), size_t(K) * 8);
+  hipError_t e = hipMemcpyAsync(g.buf.theta, g.h_theta, size_t(B) * K * 8, hipMemcpyHostToDevice, g.stream);
+  if (e == hipSuccess && mixed) {
+    const size_t words = g.proto->tab.blob.size();
+    for (int r = 0; r < B && e == hipSuccess; ++r) {
+      const ucc_ctx* c = g.jobs[r]->ctx;
+      if (g.bank_rows[r] == c) continue;
+      e = hipMemcpyAsync(g.bank + size_t(r) * words, c->d_blob, words * 4, hipMemcpyDeviceToDevice, g.stream);
+      g.bank_rows[r] = c;
     }
   }
-  if (any_done) cv_done.notify_all();
+  if (e != hipSuccess) {
+    std::fill(g.bank_rows.begin(), g.bank_rows.end(), nullptr);
+    return hip_fail(e, "server copies");
+  }
+  s = enqueue_eval(g.proto, g.buf, g.buf.theta, B, true, g.stream, nullptr, mixed ? g.bank : nullptr,
+                   cu_share);
+  if (s != UCC_OK) return s;
+  e = hipMemcpyAsync(g.h_E, g.buf.E, size_t(B) * 8, hipMemcpyDeviceToHost, g.stream);
+  if (e == hipSuccess) e = hipMemcpyAsync(g.h_G, g.buf.G, size_t(B) * K * 8, hipMemcpyDeviceToHost, g.stream);
+  if (e == hipSuccess) e = hipEventRecord(g.done_ev, g.stream);
+  if (e != hipSuccess) return hip_fail(e, "server result copies");
+  return UCC_OK;
+}
+
+}  // namespace
+}  // namespace ucc
+
+using namespace ucc;
+
+struct ucc_server {
+  size_t budget = 0;
+  int slots = 0, max_queue = 0;
+  int device = 0;
+  std::mutex mu;
+  std::condition_variable cv_work, cv_done;
+  std::map<uint64_t, std::unique_ptr<Job>> jobs;
+  std::deque<Job*> queue;
+  std::vector<std::unique_ptr<Group>> groups;
+  int active = 0;
+  size_t used = 0;
+  uint64_t next_id = 1;
+  bool stop = false;
+  std::thread worker;
+
+  void run();
+  int cu_share_for(const Group& g) const;
+  void admit_locked();
+  Group* group_for(ucc_ctx* c);
+  void retire_locked(Job* j, ucc_status st);
+  void finish_round_locked(Group& g, ucc_status st, const std::string& err);
+};
+
+// Job leaves: done, its slot and memory free.
+void ucc_server::retire_locked(Job* j, ucc_status st) {
+  j->done = true;
+  j->status = st;
+  j->t_done = Clock::now();
+  j->ctx->busy.fetch_sub(1);
+  if (j->admitted) {
+    used -= j->footprint;
+    --active;
+  }
+}
+
+Group* ucc_server::group_for(ucc_ctx* c) {
+  for (auto& g : groups)
+    if (g->proto == c) return g.get();
+  for (auto& g : groups)
+    if (batch_compatible(g->proto, c)) return g.get();
+  std::unique_ptr<Group> g(new (std::nothrow) Group());
+  if (!g) return nullptr;
+  if (hipStreamCreateWithFlags(&g->stream, hipStreamNonBlocking) != hipSuccess ||
+      hipEventCreateWithFlags(&g->done_ev, hipEventDisableTiming) != hipSuccess) {
+    (void)hipGetLastError();
+    free_group(*g);
+    return nullptr;
+  }
+  g->proto = c;
+  groups.push_back(std::move(g));
+  return groups.back().get();
+}
+
+void ucc_server::admit_locked() {
+  for (auto it = queue.begin(); it != queue.end() && active < slots;) {
+    Job* j = *it;
+    if (used + j->footprint > budget) {
+      ++it;  // first fit: a smaller job behind it may still fit
+      continue;
+    }
+    Group* g = group_for(j->ctx);
+    if (!g) break;  // no stream could be made: try again later
+    it = queue.erase(it);
+    j->admitted = true;
+    j->t_admit = Clock::now();
+    used += j->footprint;
+    ++active;
+    g->joining.push_back(j);
+  }
+}
+
+// Space sharing.  Persistent pass kernels fill every compute unit they are given and hold
+// it until the kernel ends, so a long round of a large group would make small groups wait for
+// each of its kernels.  When several groups are active, the group with the most work per
+// round takes what the others leave (at least a quarter of the device) and every other group
+// gets the units it can use (one per tile of a forward pass), at most a quarter each.
+int ucc_server::cu_share_for(const Group& g) const {
+  const int cus = device_cus();
+  auto members = [](const Group& h) { return h.jobs.size() + h.joining.size(); };
+  auto work = [&](const Group& h) {
+    const Plan& p = h.proto->plan;
+    return double(members(h)) * double(2 * p.nfwd + p.nexp + 4 * p.nrev) * double(size_t(1) << p.n);
+  };
+  auto demand = [&](const Group& h) {
+    const Plan& p = h.proto->plan;
+    const double tiles = double(members(h)) * double(size_t(1) << (p.n - p.kf));
+    return (int)std::min<double>(tiles, cus / 4);
+  };
+  const Group* big = nullptr;
+  int busy = 0;
+  for (const auto& h : groups)
+    if (members(*h)) {
+      ++busy;
+      if (!big || work(*h) > work(*big)) big = h.get();
+    }
+  if (busy <= 1) return 0;
+  if (&g != big) return std::max(1, demand(g));
+  int others = 0;
+  for (const auto& h : groups)
+    if (members(*h) && h.get() != big) others += std::max(1, demand(*h));
+  return std::max(cus / 4, cus - others);
+}
+
+// Results of a finished round: record E, update theta, retire completed/cancelled jobs.
+void ucc_server::finish_round_locked(Group& g, ucc_status st, const std::string& err) {
+  const int K = g.proto->plan.K;
+  std::vector<Job*> keep;
+  for (size_t r = 0; r < g.jobs.size(); ++r) {
+    Job* j = g.jobs[r];
+    if (st != UCC_OK) {
+      j->error = err;
+      retire_locked(j, st);
+      continue;
+    }
+    j->rounds += 1;
+    j->traj.push_back(g.h_E[r]);
+    if ((int)j->traj.size() == j->iters + 1) {
+      retire_locked(j, UCC_OK);
+      continue;
+    }
+    const double* gr = g.h_G + r * size_t(K);
+    for (int k = 0; k < K; ++k) {
+      const double step = j->lr * gr[k];  // rounded product, then the difference
+      j->theta[k] = j->theta[k] - step;
+    }
+    keep.push_back(j);
+  }
+  g.jobs.swap(keep);
 }
 
 void ucc_server::run() {
   (void)hipSetDevice(device);
   std::unique_lock<std::mutex> lk(mu);
   for (;;) {
-    cv_work.wait(lk, [&] { return stop || !queue.empty() || active > 0; });
     if (stop) break;
     admit_locked();
-    // cancelled active jobs leave before their next evaluation
-    bool any_done = false;
-    for (auto& g : groups) {
+    bool progress = false, any_done = false, in_flight = false;
+    // rounds that finished
+    for (auto& gp : groups) {
+      Group& g = *gp;
+      if (!g.in_flight) continue;
+      const hipError_t e = hipEventQuery(g.done_ev);
+      if (e == hipErrorNotReady) {
+        in_flight = true;
+        continue;
+      }
+      g.in_flight = false;
+      progress = true;
+      const ucc_status st = e == hipSuccess ? UCC_OK : hip_fail(e, "server round");
+      const size_t before = g.jobs.size();
+      finish_round_locked(g, st, g_last_error);
+      any_done |= g.jobs.size() != before;
+      if (g.jobs.size() != before) members_changed(g);
+    }
+    // idle groups: membership changes, then the next round
+    for (auto& gp : groups) {
+      Group& g = *gp;
+      if (g.in_flight) continue;
       std::vector<Job*> keep;
-      for (Job* j : g->jobs) {
+      for (Job* j : g.jobs) {
         if (j->cancel) {
-          finish_locked(j, UCC_ECANCELED);
-          used -= j->footprint;
-          --active;
+          retire_locked(j, UCC_ECANCELED);
           any_done = true;
         } else {
           keep.push_back(j);
         }
       }
-      const bool changed = keep.size() != g->jobs.size();
-      g->jobs.swap(keep);
-      if (changed) members_changed(*g);
+      for (Job* j : g.joining) {
+        if (j->cancel) {
+          retire_locked(j, UCC_ECANCELED);
+          any_done = true;
+        } else {
+          keep.push_back(j);
+        }
+      }
+      const bool changed = keep.size() != g.jobs.size() || !g.joining.empty();
+      g.joining.clear();
+      g.jobs.swap(keep);
+      if (changed) members_changed(g);
+      if (g.jobs.empty()) continue;
+      const ucc_status st = launch_round(g, slots, cu_share_for(g));
+      progress = true;
+      if (st != UCC_OK) {
+        const size_t before = g.jobs.size();
+        // nothing of this round may still be running on the stream before rows are reused
+        (void)hipStreamSynchronize(g.stream);
+        finish_round_locked(g, st, g_last_error);
+        any_done |= g.jobs.size() != before;
+        members_changed(g);
+      } else {
+        g.in_flight = true;
+        in_flight = true;
+      }
+    }
+    // empty groups give their memory back
+    for (auto it = groups.begin(); it != groups.end();) {
+      Group& g = **it;
+      if (!g.in_flight && g.jobs.empty() && g.joining.empty()) {
+        free_group(g);
+        it = groups.erase(it);
+      } else {
+        ++it;
+      }
     }
     if (any_done) cv_done.notify_all();
-    std::vector<Group*> gs;
-    for (auto& g : groups)
-      if (!g->jobs.empty()) gs.push_back(g.get());
-    if (gs.empty()) {
-      // nothing fits right now (queued jobs larger than the free budget cannot occur: the
-      // budget check at submit guarantees each job fits an empty server)
-      continue;
+    if (progress) continue;
+    if (in_flight) {
+      // device rounds in flight: poll again shortly (a submission wakes the loop early)
+      cv_work.wait_for(lk, std::chrono::microseconds(20));
+    } else {
+      cv_work.wait(lk, [&] { return stop || !queue.empty(); });
     }
-    lk.unlock();
-    round(gs);
-    lk.lock();
   }
 }
 
@@ -389,19 +433,17 @@ ucc_status ucc_server_create(size_t hbm_budget_bytes, int32_t slots, int32_t max
   s->budget = hbm_budget_bytes ? hbm_budget_bytes : (size_t(64) << 30);
   s->slots = slots;
   s->max_queue = max_queue;
-  hipError_t e = hipGetDevice(&s->device);
-  for (int i = 0; i < kStreams && e == hipSuccess; ++i)
-    e = hipStreamCreateWithFlags(&s->streams[i], hipStreamNonBlocking);
+  int ndev = 0;
+  hipError_t e = hipGetDeviceCount(&ndev);
+  if (e == hipSuccess && ndev < 1) e = hipErrorNoDevice;
+  if (e == hipSuccess) e = hipGetDevice(&s->device);
   if (e != hipSuccess) {
-    for (auto& st : s->streams)
-      if (st) (void)hipStreamDestroy(st);
     delete s;
-    return hip_fail(e, "server streams (no GPU?)");
+    return hip_fail(e, "server device (no GPU?)");
   }
   try {
     s->worker = std::thread([s] { s->run(); });
   } catch (...) {
-    for (auto& st : s->streams) (void)hipStreamDestroy(st);
     delete s;
     return fail(UCC_ENOMEM, "cannot start the server thread");
   }
@@ -502,7 +544,7 @@ ucc_status ucc_cancel(ucc_server* s, uint64_t ticket) {
         break;
       }
     j->error = "cancelled";
-    s->finish_locked(j, UCC_ECANCELED);
+    s->retire_locked(j, UCC_ECANCELED);
     s->cv_done.notify_all();
   } else {
     j->cancel = true;
@@ -520,20 +562,16 @@ void ucc_server_destroy(ucc_server* s) {
   s->cv_work.notify_all();
   if (s->worker.joinable()) s->worker.join();
   (void)hipSetDevice(s->device);
-  for (auto& st : s->streams)
-    if (st) (void)hipStreamSynchronize(st);
+  for (auto& g : s->groups) free_group(*g);  // waits for rounds in flight
   {
     std::lock_guard<std::mutex> lock(s->mu);
     for (auto& kv : s->jobs)
       if (!kv.second->done) {
         kv.second->error = "server destroyed";
-        s->finish_locked(kv.second.get(), UCC_ECANCELED);
+        s->retire_locked(kv.second.get(), UCC_ECANCELED);
       }
     s->cv_done.notify_all();
   }
-  for (auto& g : s->groups) free_group(*g);
-  for (auto& st : s->streams)
-    if (st) (void)hipStreamDestroy(st);
   delete s;
 }
 
