@@ -50,8 +50,8 @@ typedef struct ucc_server ucc_server; /* opaque: continuous-batching VQE server 
 /* Build options.  Zero means "choose automatically" unless stated otherwise. */
 typedef struct {
   int32_t trotter_steps;     /* M of Eq. 5; only 1 is supported (0 is read as 1) */
-  int32_t tile_qubits;       /* k: local qubits per tile for one-vector passes (4..13) */
-  int32_t tile_qubits_rev;   /* k for two-vector passes (reverse sweep) (4..12) */
+  int32_t tile_qubits;       /* k: local qubits per tile of forward passes (4..14) */
+  int32_t tile_qubits_rev;   /* k of reverse-sweep passes (4..13) */
   int32_t contiguous_qubits; /* lowest physical bits kept inside every tile (2..k-4) */
   int32_t block_threads;     /* threads per workgroup of every pass kind: 256, 512 or 1024 */
   int32_t max_batch;         /* theta vectors allocated up front (grows on demand); 0 =
@@ -64,11 +64,12 @@ typedef struct {
   int32_t block_threads_fwd; /* per-kind workgroup size (forward, expectation/apply-H, */
   int32_t block_threads_exp; /* reverse); overrides block_threads for that kind */
   int32_t block_threads_rev;
+  int32_t tile_qubits_exp;   /* k of expectation / apply-H passes (4..13) */
   int32_t autotune;          /* 1: time the candidate tile sizes and workgroup sizes of the
                                 kinds left automatic on this device at batch max(1, max_batch)
                                 during ucc_build and keep the fastest (results are cached per
                                 process by (n_qubits, n_elec, n_exc, batch)); 0: fixed table */
-  int32_t reserved[3];
+  int32_t reserved[2];
 } ucc_options;
 
 /* Fill *opt with defaults (all automatic, launch_mode 0, max_batch 1). */
@@ -141,7 +142,7 @@ typedef struct {
   int32_t n_fwd_passes;      /* one-vector excitation passes (forward sweep) */
   int32_t n_exp_passes;      /* expectation / apply-H passes */
   int32_t n_rev_passes;      /* two-vector reverse-sweep passes */
-  int32_t tile_qubits, tile_qubits_rev;
+  int32_t tile_qubits, tile_qubits_exp, tile_qubits_rev;
   int32_t contiguous_fwd, contiguous_exp, contiguous_rev;
   int32_t block_threads_fwd, block_threads_exp, block_threads_rev, launch_mode;
   int32_t autotuned;         /* 1 if the choices above come from measurement */

@@ -78,7 +78,7 @@ ucc_status ensure_buffers(const ucc_ctx* c, Buffers& b, int B, bool need_lam) {
   const bool lam = need_lam || b.lam != nullptr;
   free_buffers(b);
   b.cap = cap;
-  const size_t nte = size_t(1) << (p.n - p.kf);
+  const size_t nte = size_t(1) << (p.n - p.ke);
   const size_t ntr = size_t(1) << (p.n - p.kr);
   struct Req {
     void** ptr;
@@ -136,7 +136,7 @@ LaunchArgs make_args(const ucc_ctx* c, const Buffers& b, int B, hipStream_t st) 
   a.lam = b.lam;
   a.cs = b.cs;
   a.epart = b.epart;
-  a.estride = p.nexp << (p.n - p.kf);
+  a.estride = p.nexp << (p.n - p.ke);
   a.gpart = b.gpart;
   a.E = b.E;
   a.G = b.G;
@@ -197,7 +197,7 @@ ucc_status enqueue_eval(const ucc_ctx* c, Buffers& b, const double* d_theta, int
     e = timed(UCC_KERNEL_FWD, i == 0 ? S : 2 * S, [&] { return launch_fwd(a, i, i == 0); });
     if (e != hipSuccess) return hip_fail(e, "launch k_fwd");
   }
-  const int nte = 1 << (p.n - p.kf);
+  const int nte = 1 << (p.n - p.ke);
   for (int j = 0; j < p.nexp; ++j) {
     const double bytes = grad ? S + (j == 0 ? sec : 2 * sec) : S;
     e = timed(grad ? UCC_KERNEL_APPLYH : UCC_KERNEL_EXP, bytes,
@@ -251,12 +251,12 @@ void apply_tuning(Plan& p, const Tuning& tu) {
   p.launch_mode = tu.launch_mode;
 }
 
-ucc_status replan(ucc_ctx* c, int kf, int kr) {
+ucc_status replan(ucc_ctx* c, int kf, int ke, int kr) {
   Plan& p = c->plan;
-  if (p.kf == kf && p.kr == kr) return UCC_OK;
+  if (p.kf == kf && p.ke == ke && p.kr == kr) return UCC_OK;
   Plan np;
   const std::string msg = build_plan(np, p.n, p.ne, p.h1.data(), p.h2.data(), p.exc.data(), p.K,
-                                     kf, kr, c->opt.contiguous_qubits);
+                                     kf, ke, kr, c->opt.contiguous_qubits);
   if (!msg.empty()) return fail(UCC_EINVAL, msg);
   np.tf = p.tf;
   np.te = p.te;
@@ -324,10 +324,12 @@ ucc_status ucc_build(int32_t n_qubits, int32_t n_elec, const double* h1, const d
   std::string msg = validate_inputs(n_qubits, n_elec, h1, h2, exc, n_exc);
   if (!msg.empty()) return fail(UCC_EINVAL, msg);
   // one complex128 tile of 2^k amplitudes (two for the reverse sweep) must fit in 160 KB of LDS
-  if (o.tile_qubits && (o.tile_qubits < 4 || o.tile_qubits > 13))
-    return fail(UCC_EINVAL, "tile_qubits must be 0 or in [4, 13]");
-  if (o.tile_qubits_rev && (o.tile_qubits_rev < 4 || o.tile_qubits_rev > 12))
-    return fail(UCC_EINVAL, "tile_qubits_rev must be 0 or in [4, 12]");
+  if (o.tile_qubits && (o.tile_qubits < 4 || o.tile_qubits > 14))
+    return fail(UCC_EINVAL, "tile_qubits must be 0 or in [4, 14]");
+  if (o.tile_qubits_exp && (o.tile_qubits_exp < 4 || o.tile_qubits_exp > 13))
+    return fail(UCC_EINVAL, "tile_qubits_exp must be 0 or in [4, 13]");
+  if (o.tile_qubits_rev && (o.tile_qubits_rev < 4 || o.tile_qubits_rev > 13))
+    return fail(UCC_EINVAL, "tile_qubits_rev must be 0 or in [4, 13]");
   for (int t : {o.block_threads, o.block_threads_fwd, o.block_threads_exp, o.block_threads_rev})
     if (t && t != 256 && t != 512 && t != 1024)
       return fail(UCC_EINVAL, "block_threads (any kind) must be 0, 256, 512 or 1024");
@@ -340,7 +342,8 @@ ucc_status ucc_build(int32_t n_qubits, int32_t n_elec, const double* h1, const d
   c->opt = o;
   c->host_only = o.host_only != 0;
   const Tuning tu = choose_tuning(n_qubits, n_exc, std::max(1, o.max_batch), o);
-  msg = build_plan(c->plan, n_qubits, n_elec, h1, h2, exc, n_exc, tu.kf, tu.kr, o.contiguous_qubits);
+  msg = build_plan(c->plan, n_qubits, n_elec, h1, h2, exc, n_exc, tu.kf, tu.ke, tu.kr,
+                   o.contiguous_qubits);
   if (!msg.empty()) {
     delete c;
     return fail(UCC_EINVAL, msg);
@@ -472,6 +475,7 @@ ucc_status ucc_get_plan_info(const ucc_ctx* c, ucc_plan_info* info) {
   info->n_exp_passes = p.nexp;
   info->n_rev_passes = p.nrev;
   info->tile_qubits = p.kf;
+  info->tile_qubits_exp = p.ke;
   info->tile_qubits_rev = p.kr;
   info->contiguous_fwd = p.c0f;
   info->contiguous_exp = p.c0e;

@@ -43,7 +43,7 @@ struct Profiler {
 };
 
 struct Tuning {
-  int kf = 13, kr = 12, tf = 512, te = 1024, tr = 256, launch_mode = 1;
+  int kf = 14, ke = 13, kr = 13, tf = 1024, te = 1024, tr = 512, launch_mode = 1;
 };
 
 }  // namespace ucc
@@ -91,8 +91,8 @@ Tuning choose_tuning(int n, int K, int batch, const ucc_options& o);
 void apply_tuning(Plan& p, const Tuning& tu);
 void free_tables(ucc_ctx* c);
 ucc_status upload_tables(ucc_ctx* c);
-// Re-plan for tile sizes (kf, kr): new host and device tables, buffers re-allocated.
-ucc_status replan(ucc_ctx* c, int kf, int kr);
+// Re-plan for tile sizes (kf, ke, kr): new host and device tables, buffers re-allocated.
+ucc_status replan(ucc_ctx* c, int kf, int ke, int kr);
 void profile_sum(const Profiler& pr, ucc_kernel_stat* stats, hipError_t* err);
 // Time the automatic choices at batch B on this context's device and keep the fastest.
 ucc_status autotune(ucc_ctx* c, int B);

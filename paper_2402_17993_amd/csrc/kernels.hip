@@ -129,7 +129,8 @@ struct Tile {
   static constexpr int JB = KT ? KT - L2T : 0;
   static_assert(JB <= 5, "tile too large for the workgroup");
   using Buf = RegBuf<EPT>;
-  uint32_t lmask, dt;
+  uint32_t lmask;
+  mutable uint32_t dt;
   uint32_t h0 = 0, h1 = 0, h2 = 0, h3 = 0, h4 = 0;  // physical bits of j's bits 0..4
   __device__ __forceinline__ explicit Tile(uint32_t lm) : lmask(lm) {
     dt = dep(threadIdx.x, lm);
@@ -147,6 +148,9 @@ struct Tile {
     if (JB > 3) h3 = low();
     if (JB > 4) h4 = low();
   }
+  // Make the per-element offsets look fresh to the compiler, so they are recomputed (one OR
+  // each) where used instead of being hoisted and held in registers across a whole pass.
+  __device__ __forceinline__ void refresh() const { asm volatile("" : "+v"(dt)); }
   template <int J>
   __device__ __forceinline__ uint32_t off() const {
     return dt | ((J & 1) ? h0 : 0u) | ((J & 2) ? h1 : 0u) | ((J & 4) ? h2 : 0u) |
@@ -244,51 +248,151 @@ __device__ __forceinline__ void stage_records(PassStage& st, const DevPass& ps,
   for (int i = threadIdx.x; i < ps.count; i += T) st.x[i] = exc[ps.first + i];
 }
 
-// Everything excitation e needs before its amplitudes: record, (cos, sin), the range of
-// its pairs in the pair block and the thread's first pair entry.
-struct ExcAhead {
-  DevExc x;
-  double2 t;
-  int i0, i1;
-  uint32_t u0;
-  __device__ __forceinline__ void load(const DevExc* sx, const double2* scs, const uint32_t* blk,
-                                       const uint16_t* ent, int e, int count) {
-    x = sx[e];
-    t = scs[e];
-    i0 = (int)blk[e];
-    i1 = (int)blk[e + 1];
-    const int i = i0 + (int)threadIdx.x;
-    u0 = i < i1 ? (uint32_t)ent[i] : 0u;
-  }
-};
-
 // Copy `words` uint32 from global to LDS.
 template <int T>
 __device__ __forceinline__ void stage_words(uint32_t* dst, const uint32_t* __restrict__ src, int words) {
   for (int i = threadIdx.x; i < words; i += T) dst[i] = src[i];
 }
 
-// Class of the tile with global-bit offset base (its pair-list block / in-sector list).
+// Class of the tile with global-bit offset base (its class block / in-sector list).
 __device__ __forceinline__ int tile_class(uint32_t base, uint32_t amask, uint32_t bmask, int nbg) {
   return __popc(base & amask) * (nbg + 1) + __popc(base & bmask);
 }
 
-// The pass kernels hold one or two workgroups per CU (their LDS tile decides), i.e. T/256
-// waves per SIMD each: let the register allocator use the VGPRs that occupancy leaves.
+constexpr uint32_t kNoRank = 0xffffu;
+
+// Stage the class block of a forward/reverse pass (layout: ucc_internal.h) and build the rank
+// table rtab[c] = rank of in-sector compact index c, kNoRank elsewhere.
+template <int T>
+__device__ __forceinline__ void stage_sc_class(uint32_t* blk, uint16_t* rtab,
+                                               const uint32_t* __restrict__ src, int words,
+                                               uint32_t tileN) {
+  __syncthreads();  // the previous block and table are no longer read
+  stage_words<T>(blk, src, words);
+  uint32_t* rt2 = reinterpret_cast<uint32_t*>(rtab);
+  for (uint32_t c = threadIdx.x; c < tileN / 2; c += T) rt2[c] = 0xffffffffu;
+  __syncthreads();
+  const int ns = (int)blk[0], m = (int)blk[1];
+  const uint16_t* sl = reinterpret_cast<const uint16_t*>(blk + 3 + m);
+  for (int i = threadIdx.x; i < ns; i += T) rtab[sl[i]] = (uint16_t)i;
+  __syncthreads();
+}
+
+// Wave-uniform values in scalar registers.
+__device__ __forceinline__ int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
+__device__ __forceinline__ double uniform(double v) {
+  const int lo = __builtin_amdgcn_readfirstlane(__double2loint(v));
+  const int hi = __builtin_amdgcn_readfirstlane(__double2hiint(v));
+  return __hiloint2double(hi, lo);
+}
+
+// Everything excitation e needs before its amplitudes (all wave-uniform but e0): cos, sin,
+// the sign sigma_k (-1)^popcount(base & m_global) common to the tile, the range of its pairs in
+// the class block, and the thread's first pair entry.
+struct ExcAhead {
+  double c, sn, sgn;
+  int i0, i1;
+  uint32_t e0;
+  __device__ __forceinline__ void load(const DevExc* sx, const double2* scs, const uint32_t* off,
+                                       const uint32_t* ent, int e, uint32_t base) {
+    const double2 t = scs[e];
+    c = uniform(t.x);
+    sn = uniform(t.y);
+    const int sig = parity(base & (uint32_t)uniform((int)sx[e].mglob)) ? -sx[e].sigma : sx[e].sigma;
+    sgn = (double)uniform(sig);
+    i0 = uniform((int)off[e]);
+    i1 = uniform((int)off[e + 1]);
+    const int i = i0 + (int)threadIdx.x;
+    e0 = i < i1 ? ent[i] : 0u;
+  }
+};
+
+// Tile elements of the thread in registers <-> in-sector amplitudes in LDS by rank.
+// scatter: in-sector values go to cv[rank]; the others are written straight back to HBM
+// (unchanged; the whole tile is streamed).  gather_store: in-sector values from cv to HBM.
+template <int T, int KT>
+struct Sector {
+  using TL = Tile<T, KT>;
+  static constexpr int EPT = TL::EPT;
+  template <int J = 0>
+  static __device__ __forceinline__ void scatter(const TL& tm, const typename TL::Buf& r, double2* cv,
+                                                 const uint16_t* rtab, double2* __restrict__ v,
+                                                 uint32_t base) {
+    const uint32_t rk = rtab[threadIdx.x + J * T];
+    if (rk != kNoRank)
+      st16(cv + rk, rget<J, EPT>(r));
+    else
+      st16(v + (base | tm.template off<J>()), rget<J, EPT>(r));
+    if constexpr (J + 1 < EPT) scatter<J + 1>(tm, r, cv, rtab, v, base);
+  }
+  template <int J = 0>
+  static __device__ __forceinline__ void scatter_hf(const TL& tm, double2* cv, const uint16_t* rtab,
+                                                    double2* __restrict__ v, uint32_t base,
+                                                    uint32_t hf) {
+    const uint32_t ph = base | tm.template off<J>();
+    const dvec2 val = {ph == hf ? 1.0 : 0.0, 0.0};
+    const uint32_t rk = rtab[threadIdx.x + J * T];
+    if (rk != kNoRank)
+      st16(cv + rk, val);
+    else
+      st16(v + ph, val);
+    if constexpr (J + 1 < EPT) scatter_hf<J + 1>(tm, cv, rtab, v, base, hf);
+  }
+  template <int J = 0>
+  static __device__ __forceinline__ void gather_store(const TL& tm, const double2* cv,
+                                                      const uint16_t* rtab,
+                                                      double2* __restrict__ v, uint32_t base) {
+    const uint32_t rk = rtab[threadIdx.x + J * T];
+    if (rk != kNoRank) st16(v + (base | tm.template off<J>()), ld16(cv + rk));
+    if constexpr (J + 1 < EPT) gather_store<J + 1>(tm, cv, rtab, v, base);
+  }
+};
+
+// Loop forms of the same for tiles without a register-staged variant (KT = 0).
+template <int T, bool INIT>
+__device__ __forceinline__ void scatter_loop(uint32_t lmask, uint32_t tileN, double2* cv,
+                                             const uint16_t* rtab, double2* __restrict__ v,
+                                             uint32_t base, uint32_t hf) {
+  for (uint32_t c = threadIdx.x; c < tileN; c += T) {
+    const uint32_t ph = base | dep(c, lmask);
+    const double2 val = INIT ? make_double2(ph == hf ? 1.0 : 0.0, 0.0) : v[ph];
+    const uint32_t rk = rtab[c];
+    if (rk != kNoRank)
+      cv[rk] = val;
+    else
+      v[ph] = val;
+  }
+}
+
+template <int T>
+__device__ __forceinline__ void gather_loop(uint32_t lmask, uint32_t tileN, const double2* cv,
+                                            const uint16_t* rtab, double2* __restrict__ v,
+                                            uint32_t base) {
+  for (uint32_t c = threadIdx.x; c < tileN; c += T) {
+    const uint32_t rk = rtab[c];
+    if (rk != kNoRank) v[base | dep(c, lmask)] = cv[rk];
+  }
+}
+
+// The pass kernels hold one or two workgroups per CU, i.e. T/256 waves per SIMD each: let
+// the register allocator use the VGPRs that occupancy leaves.
 #define LDS_BOUND_OCCUPANCY __attribute__((amdgpu_waves_per_eu(T / 256, 2 * T / 256)))
 
-// The pass kernels are persistent over tiles: the grid holds as many workgroups as fit on
-// the device and each walks items (batch entry, tile) with stride gridDim.x (a multiple of
-// the tile count where possible, so a workgroup keeps one tile index and one class).
+// Forward and reverse passes are persistent over (batch entry, tile) items with stride
+// gridDim.x (a multiple of the tile count where possible, so a workgroup keeps one tile
+// index and one class).  Per item:
+//   1. the tile (prefetched into registers: one 16-byte load per element, consecutive lanes
+//      on consecutive addresses) is split: in-sector amplitudes go to LDS by rank, the rest
+//      is written straight back (the whole state vector is streamed every pass);
+//   2. the next item's tile is requested, so its loads are in flight during step 3;
+//   3. the pass's excitations run in order on the in-sector amplitudes in LDS, one barrier
+//      per excitation;
+//   4. the in-sector amplitudes are written back from LDS.
+// Vector-memory counters retire in issue order, so the loads of step 2 come before the
+// stores of step 4 and step 1 of the next item waits for nothing issued after them.
 //
-// Pipelining (KT != 0).  Vector-memory counters retire loads and stores in issue order, so
-// no wait may follow fresh stores.  At the end of an item each thread swaps its own tile
-// elements (LDS -> registers, prefetched next tile -> LDS), writes this item's (cos, sin)
-// stage, and only then issues the item's stores and the prefetch of the item after next:
-// both are in flight during the next item's compute.
-//
-// Forward pass: for each excitation of the pass in Trotter order, a Givens rotation on the
-// tile's in-sector pairs (u, u ^ supp) listed in the class's pair block.
+// Forward pass: U_k = exp(theta_k G_k) in Trotter order, each a Givens rotation on the
+// tile's in-sector pairs (u, u ^ supp) listed in the class block.
 template <int T, int KT, bool INIT>
 __global__ __launch_bounds__(T) LDS_BOUND_OCCUPANCY void k_fwd(
     const DevPass* __restrict__ passes, int pidx, const DevExc* __restrict__ exc,
@@ -298,20 +402,21 @@ __global__ __launch_bounds__(T) LDS_BOUND_OCCUPANCY void k_fwd(
   extern __shared__ double2 lds[];
   __shared__ PassStage st;
   using TL = Tile<T, KT>;
+  using SC = Sector<T, KT>;
   constexpr bool RP = KT != 0;  // register-staged tiles
   const DevPass ps = passes[pidx];
   const uint32_t tileN = 1u << ps.k;
   const int tb = n - ps.k;
   const uint32_t tmask = (1u << tb) - 1u;
-  uint32_t* blk = reinterpret_cast<uint32_t*>(lds + tileN);
-  const uint16_t* ent = reinterpret_cast<const uint16_t*>(blk + ps.count + 1);
+  double2* cp = lds;  // in-sector amplitudes by rank
+  uint32_t* blk = reinterpret_cast<uint32_t*>(lds + ps.ns_max);
+  uint16_t* rtab = reinterpret_cast<uint16_t*>(blk + ps.stage_len);
   const TL tm(ps.lmask);
   const bool cst = (int)threadIdx.x < ps.count;
   int item = blockIdx.x;
   if (item >= total) return;
   stage_records<T>(st, ps, exc);
-  __syncthreads();
-  typename TL::Buf r, rs;
+  typename TL::Buf r;
   int staged = -1;
   auto cs_of = [&](int it) { return cs[(size_t)(it >> tb) * K + st.x[threadIdx.x].k]; };
   auto base_of = [&](int it) { return dep(it & tmask, ps.gmask); };
@@ -320,86 +425,63 @@ __global__ __launch_bounds__(T) LDS_BOUND_OCCUPANCY void k_fwd(
     const int cl = tile_class(base, amask, bmask, ps.nbeta_g);
     if (cl != staged) {
       const int2 bl = pcls[ps.cls_base + cl];
-      stage_words<T>(blk, pairs + bl.x, bl.y);
+      stage_sc_class<T>(blk, rtab, pairs + bl.x, bl.y, tileN);
       staged = cl;
     }
   };
-  // prologue: first tile in LDS, the next one in flight
-  {
-    const uint32_t base = base_of(item);
-    double2 c0 = make_double2(1.0, 0.0);
-    if (cst) c0 = cs_of(item);
-    if (INIT)
-      tm.init_hf(lds, base, tileN, hf);
-    else
-      tm.load(lds, vec_of(item), base, tileN);
-    stage_class(base);
-    if (cst) st.cs[threadIdx.x] = c0;
-  }
-  double2 csv = make_double2(1.0, 0.0);
-  {
-    const int next = item + gridDim.x;
-    if (next < total) {
-      if (RP && !INIT) tm.fetch(r, vec_of(next), base_of(next));
-      if (cst) csv = cs_of(next);
-    }
-  }
-  __syncthreads();
+  stage_class(base_of(item));
+  if (RP && !INIT) tm.fetch(r, vec_of(item), base_of(item));
+  if (cst) st.cs[threadIdx.x] = cs_of(item);
+  const uint32_t* off = blk + 2;
   for (;;) {
     const uint32_t base = base_of(item);
     double2* __restrict__ v = vec_of(item);
-    // The records, (cos, sin), list offsets and first pair entry of excitation e+1 do not
-    // change during the pass: they are read while excitation e is applied, leaving only the
-    // amplitude reads on the dependency chain between barriers.
+    if constexpr (RP) {
+      tm.refresh();
+      if (INIT)
+        SC::scatter_hf(tm, cp, rtab, v, base, hf);
+      else
+        SC::scatter(tm, r, cp, rtab, v, base);
+    } else {
+      scatter_loop<T, INIT>(ps.lmask, tileN, cp, rtab, v, base, hf);
+    }
+    __syncthreads();
+    const int next = item + gridDim.x;
+    double2 csv = make_double2(1.0, 0.0);
+    if (next < total) {
+      tm.refresh();
+      if (RP && !INIT) tm.fetch(r, vec_of(next), base_of(next));
+      if (cst) csv = cs_of(next);
+    }
+    const int m = (int)blk[1];
+    const uint32_t* ent = blk + 3 + m + (((int)blk[0] + 1) >> 1);
     ExcAhead ah;
-    ah.load(st.x, st.cs, blk, ent, 0, ps.count);
+    ah.load(st.x, st.cs, off, ent, 0, base);
     for (int e = 0; e < ps.count; ++e) {
       const ExcAhead cur = ah;
-      if (e + 1 < ps.count) ah.load(st.x, st.cs, blk, ent, e + 1, ps.count);
-      const DevExc& x = cur.x;
-      const double c = cur.t.x;
-      const double s = (parity(base & x.mglob) ? -cur.t.y : cur.t.y) * (double)x.sigma;
-      uint32_t u = cur.u0;
+      if (e + 1 < ps.count) ah.load(st.x, st.cs, off, ent, e + 1, base);
+      const double c = cur.c;
+      const double s = cur.sgn * cur.sn;
       for (int i = cur.i0 + threadIdx.x; i < cur.i1; i += T) {
-        if (i != cur.i0 + (int)threadIdx.x) u = ent[i];
-        const uint32_t w = u ^ x.supp_c;
-        const double sg = parity(u & x.mloc_c) ? -s : s;
-        const double2 a = lds[u], bb = lds[w];
-        lds[u] = make_double2(c * a.x - sg * bb.x, c * a.y - sg * bb.y);
-        lds[w] = make_double2(c * bb.x + sg * a.x, c * bb.y + sg * a.y);
+        const uint32_t en = i == cur.i0 + (int)threadIdx.x ? cur.e0 : ent[i];
+        const uint32_t ru = en & 0x7fffu, rw = en >> 16;
+        const double sg = (en & 0x8000u) ? -s : s;
+        const double2 a = cp[ru], bb = cp[rw];
+        cp[ru] = make_double2(c * a.x - sg * bb.x, c * a.y - sg * bb.y);
+        cp[rw] = make_double2(c * bb.x + sg * a.x, c * bb.y + sg * a.y);
       }
       __syncthreads();
     }
-    const int next = item + gridDim.x;
-    if (next >= total) {
-      tm.store(lds, v, base, tileN);
-      break;
-    }
-    const uint32_t nbase = base_of(next);
-    if (RP) {
-      if (INIT) {
-        tm.save(rs, lds);
-        tm.init_hf(lds, nbase, tileN, hf);
-      } else {
-        tm.swap(rs, r, lds);
-      }
-      if (cst) st.cs[threadIdx.x] = csv;
-      tm.store_regs(rs, v, base);
+    if constexpr (RP) {
+      tm.refresh();
+      SC::gather_store(tm, cp, rtab, v, base);
     } else {
-      tm.store(lds, v, base, tileN);
-      if (INIT)
-        tm.init_hf(lds, nbase, tileN, hf);
-      else
-        tm.load(lds, vec_of(next), nbase, tileN);
-      if (cst) st.cs[threadIdx.x] = csv;
+      gather_loop<T>(ps.lmask, tileN, cp, rtab, v, base);
     }
-    stage_class(nbase);
-    const int next2 = next + gridDim.x;
-    if (next2 < total) {
-      if (RP && !INIT) tm.fetch(r, vec_of(next2), base_of(next2));
-      if (cst) csv = cs_of(next2);
-    }
-    __syncthreads();
+    if (next >= total) break;
+    __syncthreads();  // cp, the table and the (cos, sin) stage are no longer read
+    stage_class(base_of(next));
+    if (cst) st.cs[threadIdx.x] = csv;
     item = next;
   }
 }
@@ -419,87 +501,92 @@ __global__ __launch_bounds__(T) LDS_BOUND_OCCUPANCY void k_rev(
   __shared__ double red[2][NW];
   __shared__ double gsum[kMaxPassExc];
   using TL = Tile<T, KT>;
+  using SC = Sector<T, KT>;
   constexpr bool RP = KT != 0;
   const DevPass ps = passes[pidx];
   const uint32_t tileN = 1u << ps.k;
   const int tb = n - ps.k;
   const uint32_t tmask = (1u << tb) - 1u;
   const int ntiles = 1 << tb;
-  double2* lp = lds;
-  double2* ll = lds + tileN;
-  uint32_t* blk = reinterpret_cast<uint32_t*>(lds + 2 * tileN);
-  const uint16_t* ent = reinterpret_cast<const uint16_t*>(blk + ps.count + 1);
+  double2* cp = lds;
+  double2* cl = lds + ps.ns_max;
+  uint32_t* blk = reinterpret_cast<uint32_t*>(lds + 2 * ps.ns_max);
+  uint16_t* rtab = reinterpret_cast<uint16_t*>(blk + ps.stage_len);
   const TL tm(ps.lmask);
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const bool cst = (int)threadIdx.x < ps.count;
   int item = blockIdx.x;
   if (item >= total) return;
   stage_records<T>(st, ps, exc);
-  __syncthreads();
-  typename TL::Buf rp, rl, rsp, rsl;
+  typename TL::Buf rp, rl;
   int staged = -1;
   auto cs_of = [&](int it) { return cs[(size_t)(it >> tb) * K + st.x[threadIdx.x].k]; };
   auto base_of = [&](int it) { return dep(it & tmask, ps.gmask); };
   auto off_of = [&](int it) { return (size_t)(it >> tb) << n; };
   auto stage_class = [&](uint32_t base) {
-    const int cl = tile_class(base, amask, bmask, ps.nbeta_g);
-    if (cl != staged) {
-      const int2 bl = pcls[ps.cls_base + cl];
-      stage_words<T>(blk, pairs + bl.x, bl.y);
-      staged = cl;
+    const int c = tile_class(base, amask, bmask, ps.nbeta_g);
+    if (c != staged) {
+      const int2 bl = pcls[ps.cls_base + c];
+      stage_sc_class<T>(blk, rtab, pairs + bl.x, bl.y, tileN);
+      staged = c;
     }
   };
-  {
-    const uint32_t base = base_of(item);
-    double2 c0 = make_double2(1.0, 0.0);
-    if (cst) c0 = cs_of(item);
-    tm.load(lp, psi + off_of(item), base, tileN);
-    tm.load(ll, lam + off_of(item), base, tileN);
-    stage_class(base);
-    if (cst) st.cs[threadIdx.x] = c0;
+  stage_class(base_of(item));
+  if (RP) {
+    tm.fetch(rp, psi + off_of(item), base_of(item));
+    tm.fetch(rl, lam + off_of(item), base_of(item));
   }
-  double2 csv = make_double2(1.0, 0.0);
-  {
-    const int next = item + gridDim.x;
-    if (next < total) {
-      if (RP) {
-        tm.fetch(rp, psi + off_of(next), base_of(next));
-        tm.fetch(rl, lam + off_of(next), base_of(next));
-      }
-      if (cst) csv = cs_of(next);
-    }
-  }
-  __syncthreads();
+  if (cst) st.cs[threadIdx.x] = cs_of(item);
+  const uint32_t* off = blk + 2;
   for (;;) {
     const int b = item >> tb;
     const uint32_t t = item & tmask;
     const uint32_t base = base_of(item);
     double2* __restrict__ vp = psi + off_of(item);
     double2* __restrict__ vl = lam + off_of(item);
+    if constexpr (RP) {
+      tm.refresh();
+      SC::scatter(tm, rp, cp, rtab, vp, base);
+      SC::scatter(tm, rl, cl, rtab, vl, base);
+    } else {
+      scatter_loop<T, false>(ps.lmask, tileN, cp, rtab, vp, base, 0u);
+      scatter_loop<T, false>(ps.lmask, tileN, cl, rtab, vl, base, 0u);
+    }
+    __syncthreads();
+    const int next = item + gridDim.x;
+    double2 csv = make_double2(1.0, 0.0);
+    if (next < total) {
+      if (RP) {
+        tm.refresh();
+        tm.fetch(rp, psi + off_of(next), base_of(next));
+        tm.fetch(rl, lam + off_of(next), base_of(next));
+      }
+      if (cst) csv = cs_of(next);
+    }
+    const int m = (int)blk[1];
+    const uint32_t* ent = blk + 3 + m + (((int)blk[0] + 1) >> 1);
     int prev_e = -1;
     ExcAhead ah;
-    ah.load(st.x, st.cs, blk, ent, 0, ps.count);
+    ah.load(st.x, st.cs, off, ent, 0, base);
     for (int e = 0; e < ps.count; ++e) {
       const ExcAhead cur = ah;
-      if (e + 1 < ps.count) ah.load(st.x, st.cs, blk, ent, e + 1, ps.count);
-      const DevExc& x = cur.x;
-      const double2 tt = cur.t;
-      const double c = tt.x;
-      const double sgn0 = (parity(base & x.mglob) ? -1.0 : 1.0) * (double)x.sigma;
+      if (e + 1 < ps.count) ah.load(st.x, st.cs, off, ent, e + 1, base);
+      const double c = cur.c, sn = cur.sn;
+      const double sgn0 = cur.sgn;
       const int i0 = cur.i0, i1 = cur.i1;
       double g = 0.0;
       if (i0 + wv * 64 < i1) {  // this wave has pairs of this excitation
         for (int i = i0 + threadIdx.x; i < i1; i += T) {
-          const uint32_t u = i == i0 + (int)threadIdx.x ? cur.u0 : (uint32_t)ent[i];
-          const uint32_t w = u ^ x.supp_c;
-          const double sg = parity(u & x.mloc_c) ? -sgn0 : sgn0;
-          const double2 pu = lp[u], pw = lp[w], lu = ll[u], lw = ll[w];
+          const uint32_t en = i == i0 + (int)threadIdx.x ? cur.e0 : ent[i];
+          const uint32_t ru = en & 0x7fffu, rw = en >> 16;
+          const double sg = (en & 0x8000u) ? -sgn0 : sgn0;
+          const double2 pu = cp[ru], pw = cp[rw], lu = cl[ru], lw = cl[rw];
           g += sg * ((lw.x * pu.x + lw.y * pu.y) - (lu.x * pw.x + lu.y * pw.y));
-          const double s = sg * tt.y;
-          lp[u] = make_double2(c * pu.x + s * pw.x, c * pu.y + s * pw.y);
-          lp[w] = make_double2(c * pw.x - s * pu.x, c * pw.y - s * pu.y);
-          ll[u] = make_double2(c * lu.x + s * lw.x, c * lu.y + s * lw.y);
-          ll[w] = make_double2(c * lw.x - s * lu.x, c * lw.y - s * lu.y);
+          const double s = sg * sn;
+          cp[ru] = make_double2(c * pu.x + s * pw.x, c * pu.y + s * pw.y);
+          cp[rw] = make_double2(c * pw.x - s * pu.x, c * pw.y - s * pu.y);
+          cl[ru] = make_double2(c * lu.x + s * lw.x, c * lu.y + s * lw.y);
+          cl[rw] = make_double2(c * lw.x - s * lu.x, c * lw.y - s * lu.y);
         }
         g = wave_sum(g);
       }
@@ -519,39 +606,19 @@ __global__ __launch_bounds__(T) LDS_BOUND_OCCUPANCY void k_rev(
       gsum[prev_e] = sum;
     }
     __syncthreads();  // gsum complete
-    const int next = item + gridDim.x;
-    if (next >= total) {
-      if (cst) gpart[((size_t)b * K + st.x[threadIdx.x].k) * ntiles + t] = gsum[threadIdx.x];
-      tm.store(lp, vp, base, tileN);
-      tm.store(ll, vl, base, tileN);
-      break;
-    }
-    const uint32_t nbase = base_of(next);
-    const double gv = cst ? gsum[threadIdx.x] : 0.0;
-    if (RP) {
-      tm.swap(rsp, rp, lp);
-      tm.swap(rsl, rl, ll);
-      if (cst) st.cs[threadIdx.x] = csv;
-      tm.store_regs(rsp, vp, base);
-      tm.store_regs(rsl, vl, base);
+    if (cst) gpart[((size_t)b * K + st.x[threadIdx.x].k) * ntiles + t] = gsum[threadIdx.x];
+    if constexpr (RP) {
+      tm.refresh();
+      SC::gather_store(tm, cp, rtab, vp, base);
+      SC::gather_store(tm, cl, rtab, vl, base);
     } else {
-      tm.store(lp, vp, base, tileN);
-      tm.store(ll, vl, base, tileN);
-      tm.load(lp, psi + off_of(next), nbase, tileN);
-      tm.load(ll, lam + off_of(next), nbase, tileN);
-      if (cst) st.cs[threadIdx.x] = csv;
+      gather_loop<T>(ps.lmask, tileN, cp, rtab, vp, base);
+      gather_loop<T>(ps.lmask, tileN, cl, rtab, vl, base);
     }
-    if (cst) gpart[((size_t)b * K + st.x[threadIdx.x].k) * ntiles + t] = gv;
-    stage_class(nbase);
-    const int next2 = next + gridDim.x;
-    if (next2 < total) {
-      if (RP) {
-        tm.fetch(rp, psi + off_of(next2), base_of(next2));
-        tm.fetch(rl, lam + off_of(next2), base_of(next2));
-      }
-      if (cst) csv = cs_of(next2);
-    }
-    __syncthreads();
+    if (next >= total) break;
+    __syncthreads();  // cp, cl, the table, gsum and the (cos, sin) stage are no longer read
+    stage_class(base_of(next));
+    if (cst) st.cs[threadIdx.x] = csv;
     item = next;
   }
 }
@@ -845,16 +912,21 @@ inline int pass_grid(int total, int resident, int ntiles) {
   return std::max(g, 1);
 }
 
+// Dynamic LDS of a forward/reverse pass: compact in-sector vector(s), the class block and
+// the rank table (2 bytes per tile element).
+inline size_t sc_lds(const DevPass& hp, int vectors) {
+  return 16 * size_t(vectors) * hp.ns_max + 4 * size_t(hp.stage_len) + (size_t(2) << hp.k);
+}
+
 template <int T, int KT, bool INIT>
 hipError_t fwd_ti(const LaunchArgs& a, int pidx) {
   const DevPass& hp = a.hpasses[pidx];
   const int k = hp.k;
-  const size_t lds = (sizeof(double2) << k) + 4 * size_t(hp.stage_len);
+  const size_t lds = sc_lds(hp, 1);
   hipError_t e = set_lds(k_fwd<T, KT, INIT>, lds);
   if (e != hipSuccess) return e;
   const int total = a.B << (a.n - k);
-  const int grid = KT ? pass_grid(total, resident_grid(k_fwd<T, KT, INIT>, T, lds, a.cu_share), 1 << (a.n - k))
-                      : total;
+  const int grid = pass_grid(total, resident_grid(k_fwd<T, KT, INIT>, T, lds, a.cu_share), 1 << (a.n - k));
   hipLaunchKernelGGL((k_fwd<T, KT, INIT>), dim3(grid), dim3(T), lds, a.stream, a.passes, pidx,
                      a.exc, a.cls, a.pairs, a.cs, a.K, a.psi, a.n, a.hf, a.amask, a.bmask, total);
   return hipGetLastError();
@@ -869,11 +941,11 @@ template <int T, int KT>
 hipError_t rev_t(const LaunchArgs& a, int pidx) {
   const DevPass& hp = a.hpasses[pidx];
   const int k = hp.k;
-  const size_t lds = (2 * sizeof(double2) << k) + 4 * size_t(hp.stage_len);
+  const size_t lds = sc_lds(hp, 2);
   hipError_t e = set_lds(k_rev<T, KT>, lds);
   if (e != hipSuccess) return e;
   const int total = a.B << (a.n - k);
-  const int grid = KT ? pass_grid(total, resident_grid(k_rev<T, KT>, T, lds, a.cu_share), 1 << (a.n - k)) : total;
+  const int grid = pass_grid(total, resident_grid(k_rev<T, KT>, T, lds, a.cu_share), 1 << (a.n - k));
   hipLaunchKernelGGL((k_rev<T, KT>), dim3(grid), dim3(T), lds, a.stream, a.passes, pidx, a.exc,
                      a.cls, a.pairs, a.cs, a.K, a.psi, a.lam, a.n, a.amask, a.bmask, a.gpart,
                      total);
@@ -897,10 +969,13 @@ hipError_t exp_t(const LaunchArgs& a, int pidx, int eslot, int first) {
   return hipGetLastError();
 }
 
-// Tile-size dispatch: unrolled register staging for k = 12 and 13, a loop otherwise.
+// Tile-size dispatch: unrolled register staging where the tile fits in at most 32 elements
+// per thread (16 for the two-vector reverse pass), a loop otherwise.
 template <int T>
 hipError_t fwd_k(const LaunchArgs& a, int pidx, int init) {
   const int k = a.hpasses[pidx].k;
+  if constexpr (T >= 512)
+    if (k == 14) return fwd_t<T, 14>(a, pidx, init);
   if (k == 13) return fwd_t<T, 13>(a, pidx, init);
   if (k == 12) return fwd_t<T, 12>(a, pidx, init);
   return fwd_t<T, 0>(a, pidx, init);
@@ -908,7 +983,10 @@ hipError_t fwd_k(const LaunchArgs& a, int pidx, int init) {
 
 template <int T>
 hipError_t rev_k(const LaunchArgs& a, int pidx) {
-  if (a.hpasses[pidx].k == 12) return rev_t<T, 12>(a, pidx);
+  const int k = a.hpasses[pidx].k;
+  if constexpr (T >= 512)
+    if (k == 13) return rev_t<T, 13>(a, pidx);
+  if (k == 12) return rev_t<T, 12>(a, pidx);
   return rev_t<T, 0>(a, pidx);
 }
 

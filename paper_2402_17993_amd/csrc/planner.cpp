@@ -232,7 +232,7 @@ std::string validate_inputs(int n, int ne, const double* h1, const double* h2, c
 }
 
 std::string build_plan(Plan& p, int n, int ne, const double* h1, const double* h2,
-                       const int32_t* exc, int K, int kf, int kr, int c0) {
+                       const int32_t* exc, int K, int kf, int ke, int kr, int c0) {
   p = Plan();
   p.n = n;
   p.ne = ne;
@@ -424,6 +424,7 @@ std::string build_plan(Plan& p, int n, int ne, const double* h1, const double* h
 
   // ---- pass plan.
   p.kf = std::min(kf, n);
+  p.ke = std::min(ke, n);
   p.kr = std::min(kr, n);
   auto best_windows = [&](int kind, int k, int& c0_out) {
     std::vector<Plan::Pass> best;
@@ -443,11 +444,11 @@ std::string build_plan(Plan& p, int n, int ne, const double* h1, const double* h
   auto rv = best_windows(kRev, p.kr, p.c0r);
   std::vector<Plan::Pass> ex;
   {
-    const int req = pick_c0(p.kf, c0);
-    const int lo = req >= 0 ? req : std::min(4, std::max(0, p.kf - 4));
-    const int hi = req >= 0 ? req : std::max(lo, std::min(8, p.kf - 4));
+    const int req = pick_c0(p.ke, c0);
+    const int lo = req >= 0 ? req : std::min(4, std::max(0, p.ke - 4));
+    const int hi = req >= 0 ? req : std::max(lo, std::min(8, p.ke - 4));
     for (int c = lo; c <= hi; ++c) {
-      auto w = plan_cover(p, p.kf, c);
+      auto w = plan_cover(p, p.ke, c);
       if (ex.empty() || w.size() <= ex.size()) {
         ex = w;
         p.c0e = c;
@@ -459,7 +460,7 @@ std::string build_plan(Plan& p, int n, int ne, const double* h1, const double* h
     // split passes whose group tables would not fit (same local set, groups in order)
     std::vector<Plan::Pass> split;
     for (auto& ps : ex) {
-      const int budget = kLdsBytes - (16 << p.kf) - 8 * max_class_size(p, ps.lmask) - 256;
+      const int budget = kLdsBytes - (16 << p.ke) - 8 * max_class_size(p, ps.lmask) - 256;
       Plan::Pass cur;
       cur.kind = kExp;
       cur.lmask = ps.lmask;
@@ -476,15 +477,18 @@ std::string build_plan(Plan& p, int n, int ne, const double* h1, const double* h
     }
     ex.swap(split);
   }
-  // forward/reverse windows whose largest pair-list block would not fit next to the tile(s)
-  // are halved (same local set, order kept)
-  auto fit_blocks = [&](std::vector<Plan::Pass>& ws, int tile_bytes) -> bool {
-    const int budget_words = (kLdsBytes - tile_bytes - kStageBytes - 1024) / 4;
+  // forward/reverse windows whose largest class block would not fit next to the rank table
+  // and the compact in-sector vector(s) are halved (same local set, order kept)
+  auto fit_blocks = [&](std::vector<Plan::Pass>& ws, int vectors) -> bool {
     std::vector<Plan::Pass> out;
     std::vector<Plan::Pass> todo(ws.rbegin(), ws.rend());
     while (!todo.empty()) {
       Plan::Pass w = todo.back();
       todo.pop_back();
+      const int ns = max_class_size(p, w.lmask);
+      if (ns >= 32768) return false;
+      const int budget_words =
+          (kLdsBytes - (2 << pc32(w.lmask)) - 16 * vectors * ns - kStageBytes - 4096) / 4;
       if (max_pair_block_words(p, w.lmask, w.items) <= budget_words) {
         out.push_back(w);
         continue;
@@ -500,7 +504,7 @@ std::string build_plan(Plan& p, int n, int ne, const double* h1, const double* h
     ws.swap(out);
     return true;
   };
-  if (!fit_blocks(fw, 16 << p.kf) || !fit_blocks(rv, 32 << p.kr))
+  if (!fit_blocks(fw, 1) || !fit_blocks(rv, 2))
     return "tile too large for the pair lists of one excitation";
   p.nfwd = (int)fw.size();
   p.nexp = (int)ex.size();
@@ -565,22 +569,32 @@ std::vector<std::vector<std::pair<uint32_t, uint32_t>>> class_buckets(const Plan
   return buckets;
 }
 
-// Pair-list block (see ucc_internal.h) of excitations `items` for one class bucket.
+// Class block (layout in ucc_internal.h) of excitations `items` for one class bucket (whose
+// entries are in ascending compact order, so an in-sector state's rank is its position).
 std::vector<uint32_t> pair_block(const Plan& p, uint32_t lmask, const std::vector<int>& items,
                                  const std::vector<std::pair<uint32_t, uint32_t>>& bucket) {
-  const size_t m = items.size();
-  std::vector<uint32_t> off(m + 1, 0);
-  std::vector<uint16_t> ent;
+  const size_t m = items.size(), ns = bucket.size();
+  std::vector<uint32_t> cs(ns);
+  for (size_t i = 0; i < ns; ++i) cs[i] = bucket[i].first;
+  auto rank = [&](uint32_t c) { return (uint32_t)(std::lower_bound(cs.begin(), cs.end(), c) - cs.begin()); };
+  std::vector<uint32_t> w(2 + m + 1, 0u);
+  w[0] = (uint32_t)ns;
+  w[1] = (uint32_t)m;
+  for (size_t i = 0; i < ns; i += 2)
+    w.push_back(cs[i] | (i + 1 < ns ? cs[i + 1] << 16 : 0u));
+  const size_t ent0 = w.size();
   for (size_t j = 0; j < m; ++j) {
     const auto& e = p.ex[items[j]];
     const uint32_t sc = compact_bits(e.supp, lmask), fc = compact_bits(e.from, lmask);
-    for (auto& cp : bucket)
-      if ((cp.first & sc) == fc) ent.push_back((uint16_t)cp.first);
-    off[j + 1] = (uint32_t)ent.size();
+    const uint32_t mc = compact_bits(e.m & lmask, lmask);
+    for (size_t i = 0; i < ns; ++i) {
+      const uint32_t c = cs[i];
+      if ((c & sc) != fc) continue;
+      const uint32_t rw = rank(c ^ sc);
+      w.push_back((uint32_t)i | (uint32_t(pc32(c & mc) & 1) << 15) | (rw << 16));
+    }
+    w[2 + j + 1] = (uint32_t)(w.size() - ent0);
   }
-  std::vector<uint32_t> w(off);
-  for (size_t i = 0; i < ent.size(); i += 2)
-    w.push_back(uint32_t(ent[i]) | (i + 1 < ent.size() ? uint32_t(ent[i + 1]) << 16 : 0u));
   return w;
 }
 
@@ -713,14 +727,17 @@ void build_tables(const Plan& p, Tables& t) {
       dp.cls_base = (int)t.cls.size() / 2;
       dp.nbeta_g = nbg;
       dp.stage_len = 0;
+      dp.ns_max = 0;
       for (auto& bk : buckets) {
         std::vector<uint32_t> blk = pair_block(p, ps.lmask, ps.items, bk);
         while (t.pairs.size() % 4) t.pairs.push_back(0u);  // 16-byte aligned blocks
         t.cls.push_back((int32_t)t.pairs.size());
         t.cls.push_back((int32_t)blk.size());
         dp.stage_len = std::max(dp.stage_len, (int)blk.size());
+        dp.ns_max = std::max(dp.ns_max, (int)bk.size());
         t.pairs.insert(t.pairs.end(), blk.begin(), blk.end());
       }
+      dp.stage_len = (dp.stage_len + 3) & ~3;  // keeps the rank table behind it aligned
     }
     t.passes.push_back(dp);
   }

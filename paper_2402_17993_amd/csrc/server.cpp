@@ -43,7 +43,8 @@ bool batch_compatible(const ucc_ctx* a, const ucc_ctx* b) {
   if (a == b) return true;
   const Plan& p = a->plan;
   const Plan& q = b->plan;
-  if (p.n != q.n || p.ne != q.ne || p.K != q.K || p.kf != q.kf || p.kr != q.kr || p.c0f != q.c0f ||
+  if (p.n != q.n || p.ne != q.ne || p.K != q.K || p.kf != q.kf || p.ke != q.ke || p.kr != q.kr ||
+      p.c0f != q.c0f ||
       p.c0e != q.c0e || p.c0r != q.c0r || p.tf != q.tf || p.te != q.te || p.tr != q.tr ||
       p.launch_mode != q.launch_mode || p.nfwd != q.nfwd || p.nexp != q.nexp || p.nrev != q.nrev ||
       p.hf != q.hf || p.amask != q.amask || p.bmask != q.bmask || a->device != b->device)
@@ -68,7 +69,7 @@ bool batch_compatible(const ucc_ctx* a, const ucc_ctx* b) {
 size_t entry_footprint(const ucc_ctx* c) {
   const Plan& p = c->plan;
   const size_t S = size_t(16) << p.n;
-  const size_t nte = size_t(1) << (p.n - p.kf), ntr = size_t(1) << (p.n - p.kr);
+  const size_t nte = size_t(1) << (p.n - p.ke), ntr = size_t(1) << (p.n - p.kr);
   return 2 * S + size_t(p.K) * (8 + 16 + 8) + 8 + 8 * size_t(p.nexp) * nte + 8 * size_t(p.K) * ntr +
          4 * c->tab.blob.size();
 }

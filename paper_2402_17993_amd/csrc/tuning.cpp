@@ -37,23 +37,36 @@ Tuning choose_tuning(int n, int K, int batch, const ucc_options& o) {
   (void)K;
   (void)batch;
   Tuning t;
-  t.kf = o.tile_qubits ? o.tile_qubits : std::min(n, 13);
-  t.kr = o.tile_qubits_rev ? o.tile_qubits_rev : std::min(n, 12);
-  // One-tile states are latency-bound: small workgroups.  Multi-tile states: the forward
-  // pass is bound by its Givens chains (512), the apply-H gather by arithmetic (1024), the
-  // two-vector reverse pass by its per-excitation reductions (256).
+  t.kf = o.tile_qubits ? o.tile_qubits : std::min(n, 14);
+  t.ke = o.tile_qubits_exp ? o.tile_qubits_exp : std::min(n, 13);
+  t.kr = o.tile_qubits_rev ? o.tile_qubits_rev : std::min(n, 13);
+  // One-tile states are latency-bound: small workgroups.  Multi-tile states: large
+  // workgroups keep a 2^14 forward tile in 16 registers per thread and give the apply-H
+  // gather its lanes; the two-vector reverse tile takes 512.
   const bool small = n <= 12;
-  t.tf = pick(o.block_threads_fwd, o.block_threads, small ? 256 : 512);
+  t.tf = pick(o.block_threads_fwd, o.block_threads, small ? 256 : 1024);
   t.te = pick(o.block_threads_exp, o.block_threads, small ? 256 : 1024);
-  t.tr = pick(o.block_threads_rev, o.block_threads, 256);
+  t.tr = pick(o.block_threads_rev, o.block_threads, small ? 256 : 512);
   t.launch_mode = o.launch_mode ? o.launch_mode : 1;
   return t;
 }
 
-// Candidates: the tile sizes and workgroup sizes the options leave automatic.  One plan
-// per tile pair (kf, kr) is built and every workgroup size is timed on it (all kinds at
-// once, the per-kind HIP-event sums kept apart); the forward and expectation kinds share kf,
-// so (kf, tf, te) minimizes their summed time and (kr, tr) the reverse time.
+namespace {
+
+std::vector<int> tile_candidates(int fixed, int n, std::initializer_list<int> ks) {
+  std::vector<int> out;
+  if (fixed) return {fixed};
+  for (int k : ks)
+    if (std::find(out.begin(), out.end(), std::min(n, k)) == out.end()) out.push_back(std::min(n, k));
+  return out;
+}
+
+}  // namespace
+
+// Candidates: the tile sizes and workgroup sizes the options leave automatic.  Plans for a
+// few tile triples (kf, ke, kr) are built and every workgroup size is timed on each (all
+// kinds at once, the per-kind HIP-event sums kept apart); each kind then takes its fastest
+// (tile, workgroup) pair.
 ucc_status autotune(ucc_ctx* c, int B) {
   const ucc_options& o = c->opt;
   Plan& p = c->plan;
@@ -63,50 +76,38 @@ ucc_status autotune(ucc_ctx* c, int B) {
     auto it = g_cache.find(key);
     if (it != g_cache.end()) {
       const Tuning tu = it->second;
-      ucc_status s = replan(c, tu.kf, tu.kr);
+      ucc_status s = replan(c, tu.kf, tu.ke, tu.kr);
       if (s != UCC_OK) return s;
       apply_tuning(p, tu);
       p.autotuned = true;
       return UCC_OK;
     }
   }
-  std::vector<int> kfs, krs, ts;
-  if (o.tile_qubits) {
-    kfs.push_back(o.tile_qubits);
-  } else {
-    for (int k : {13, 12})
-      if (std::find(kfs.begin(), kfs.end(), std::min(p.n, k)) == kfs.end()) kfs.push_back(std::min(p.n, k));
-  }
-  if (o.tile_qubits_rev) {
-    krs.push_back(o.tile_qubits_rev);
-  } else {
-    for (int k : {12, 11})
-      if (std::find(krs.begin(), krs.end(), std::min(p.n, k)) == krs.end()) krs.push_back(std::min(p.n, k));
-  }
-  const bool fixed_all = o.block_threads != 0;
+  const std::vector<int> kfs = tile_candidates(o.tile_qubits, p.n, {14, 13});
+  const std::vector<int> kes = tile_candidates(o.tile_qubits_exp, p.n, {13, 12});
+  const std::vector<int> krs = tile_candidates(o.tile_qubits_rev, p.n, {13, 12});
+  std::vector<int> ts;
   for (int t : {256, 512, 1024})
-    if (!fixed_all || t == o.block_threads) ts.push_back(t);
+    if (!o.block_threads || t == o.block_threads) ts.push_back(t);
   const Tuning base = choose_tuning(p.n, p.K, B, o);
 
   ucc_status s = ensure_buffers(c, c->buf, B, true);
   if (s != UCC_OK) return s;
-  std::vector<double> th(size_t(B) * p.K, 0.01);
-  hipError_t e = hipMemcpy(c->buf.theta, th.data(), th.size() * sizeof(double), hipMemcpyHostToDevice);
-  if (e != hipSuccess) return hip_fail(e, "autotune theta upload");
-
   struct Best {
     double ms = 1e300;
-    int k = 0, t1 = 0, t2 = 0;
+    int k = 0, t = 0;
   };
-  Best bf, br;  // forward + expectation; reverse
-  std::map<std::pair<int, int>, double> fwd_ms, exp_ms;  // (kf, T) -> ms
-  const size_t pairs = std::max(kfs.size(), krs.size());
-  for (size_t i = 0; i < pairs; ++i) {
-    const int kf = kfs[i % kfs.size()], kr = krs[i % krs.size()];
-    s = replan(c, kf, kr);
+  Best bf, be, br;
+  const size_t triples = std::max(kfs.size(), std::max(kes.size(), krs.size()));
+  for (size_t i = 0; i < triples; ++i) {
+    const int kf = kfs[i % kfs.size()], ke = kes[i % kes.size()], kr = krs[i % krs.size()];
+    s = replan(c, kf, ke, kr);
     if (s != UCC_OK) return s;
     s = ensure_buffers(c, c->buf, B, true);
     if (s != UCC_OK) return s;
+    std::vector<double> th(size_t(B) * p.K, 0.01);
+    hipError_t e = hipMemcpy(c->buf.theta, th.data(), th.size() * sizeof(double), hipMemcpyHostToDevice);
+    if (e != hipSuccess) return hip_fail(e, "autotune theta upload");
     for (int T : ts) {
       p.tf = o.block_threads_fwd ? o.block_threads_fwd : T;
       p.te = o.block_threads_exp ? o.block_threads_exp : T;
@@ -119,23 +120,19 @@ ucc_status autotune(ucc_ctx* c, int B) {
       ucc_kernel_stat st[UCC_KERNEL_KINDS];
       profile_sum(pr, st, &e);
       if (e != hipSuccess) return hip_fail(e, "autotune events");
-      fwd_ms[{kf, p.tf}] = st[UCC_KERNEL_FWD].ms;
-      exp_ms[{kf, p.te}] = st[UCC_KERNEL_APPLYH].ms;
-      if (st[UCC_KERNEL_REV].ms < br.ms) br = Best{st[UCC_KERNEL_REV].ms, kr, p.tr, 0};
+      if (st[UCC_KERNEL_FWD].ms < bf.ms) bf = Best{st[UCC_KERNEL_FWD].ms, kf, p.tf};
+      if (st[UCC_KERNEL_APPLYH].ms < be.ms) be = Best{st[UCC_KERNEL_APPLYH].ms, ke, p.te};
+      if (st[UCC_KERNEL_REV].ms < br.ms) br = Best{st[UCC_KERNEL_REV].ms, kr, p.tr};
     }
   }
-  for (const auto& f : fwd_ms)
-    for (const auto& x : exp_ms)
-      if (f.first.first == x.first.first && f.second + x.second < bf.ms)
-        bf = Best{f.second + x.second, f.first.first, f.first.second, x.first.second};
-
   Tuning tu = base;
   tu.kf = bf.k;
-  tu.tf = bf.t1;
-  tu.te = bf.t2;
+  tu.tf = bf.t;
+  tu.ke = be.k;
+  tu.te = be.t;
   tu.kr = br.k;
-  tu.tr = br.t1;
-  s = replan(c, tu.kf, tu.kr);
+  tu.tr = br.t;
+  s = replan(c, tu.kf, tu.ke, tu.kr);
   if (s != UCC_OK) return s;
   apply_tuning(p, tu);
   p.autotuned = true;

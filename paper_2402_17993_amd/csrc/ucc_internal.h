@@ -39,13 +39,18 @@ struct DevExc {
 
 constexpr int kMaxPassExc = 256;  // excitations per forward/reverse pass (staged in LDS)
 
-// Pair-list block of one forward/reverse pass for one tile class (the alpha and beta
-// electron counts of the tile's global bits): uint32 words
-//   [0 .. m]  prefix offsets: the pairs of the pass's j-th excitation are entries
-//             off[j] .. off[j+1]-1
-//   then the entries, two uint16 per word: compact index u of each in-sector basis state
-//   with u & supp == from (its partner is u ^ supp, also in-sector).
-// Only in-sector amplitudes can be non-zero, so only these pairs change anything.
+// Class block of one forward/reverse pass for one tile class (the alpha and beta electron
+// counts of the tile's global bits): uint32 words
+//   [0] ns: in-sector basis states of such a tile   [1] m: excitations of the pass
+//   [2 .. 2+m]  prefix offsets: the pairs of the pass's j-th excitation are entries
+//               off[j] .. off[j+1]-1
+//   then ceil(ns / 2) words: the in-sector compact indices in ascending order, two uint16 per
+//   word (the position of a state in this list is its rank)
+//   then one word per pair of each excitation: rank of u (u & supp == from) in bits 0-14,
+//   the parity of u over the tile-local part of the JW mask in bit 15, rank of u ^ supp in
+//   bits 16-31.
+// Only in-sector amplitudes can be non-zero, so only these pairs change anything; a
+// workgroup holds the in-sector amplitudes of its tile in LDS by rank.
 
 // Blob of one expectation pass: uint32 words, copied into LDS behind the tile; every
 // double sits at an even word offset and every record at a 16-byte boundary.
@@ -82,7 +87,7 @@ struct DevPass {
   int32_t blob_off; // exp: first uint4 of the pass's blob
   int32_t blob_len; // exp: blob length in uint4
   int32_t stage_len; // exp: largest class list (entries); fwd/rev: largest block (words)
-  int32_t pad;
+  int32_t ns_max;    // fwd/rev: largest in-sector count of a tile class
 };
 
 // Host-side plan: everything ucc_build derives from the inputs.
@@ -126,7 +131,7 @@ struct Plan {
   };
   std::vector<Pass> passes;  // forward, then expectation, then reverse
   int nfwd = 0, nexp = 0, nrev = 0;
-  int kf = 0, kr = 0;
+  int kf = 0, ke = 0, kr = 0;  // local qubits of forward, expectation, reverse passes
   int c0f = 0, c0e = 0, c0r = 0;
   int tf = 512, te = 1024, tr = 256;  // workgroup sizes per pass kind
   bool autotuned = false;
@@ -155,7 +160,7 @@ int max_pair_block_words(const Plan& p, uint32_t lmask, const std::vector<int>& 
 std::string validate_inputs(int n, int ne, const double* h1, const double* h2, const int32_t* exc,
                             int K);
 std::string build_plan(Plan& p, int n, int ne, const double* h1, const double* h2,
-                       const int32_t* exc, int K, int kf, int kr, int c0);
+                       const int32_t* exc, int K, int kf, int ke, int kr, int c0);
 void build_tables(const Plan& p, Tables& t);
 uint32_t deposit_bits(uint32_t v, uint32_t mask);
 int count_plan_passes(const Plan& p, int kind);

@@ -38,13 +38,15 @@ class Options(ctypes.Structure):
                 ("contiguous_qubits", _i32), ("block_threads", _i32), ("max_batch", _i32),
                 ("launch_mode", _i32), ("host_only", _i32), ("device", _i32),
                 ("block_threads_fwd", _i32), ("block_threads_exp", _i32),
-                ("block_threads_rev", _i32), ("autotune", _i32), ("reserved", _i32 * 3)]
+                ("block_threads_rev", _i32), ("tile_qubits_exp", _i32), ("autotune", _i32),
+                ("reserved", _i32 * 2)]
 
 
 class PlanInfo(ctypes.Structure):
     _fields_ = [("n_qubits", _i32), ("n_elec", _i32), ("n_exc", _i32), ("n_pauli", _i32),
                 ("n_groups", _i32), ("n_fwd_passes", _i32), ("n_exp_passes", _i32),
-                ("n_rev_passes", _i32), ("tile_qubits", _i32), ("tile_qubits_rev", _i32),
+                ("n_rev_passes", _i32), ("tile_qubits", _i32), ("tile_qubits_exp", _i32),
+                ("tile_qubits_rev", _i32),
                 ("contiguous_fwd", _i32), ("contiguous_exp", _i32), ("contiguous_rev", _i32),
                 ("block_threads_fwd", _i32), ("block_threads_exp", _i32),
                 ("block_threads_rev", _i32), ("launch_mode", _i32), ("autotuned", _i32),
@@ -125,7 +127,8 @@ def _is_torch_cuda(x):
 class Context:
     """One Hamiltonian (Eq. 2) + excitation list (Eqs. 4-5) + device buffers."""
 
-    def __init__(self, n_qubits, n_elec, h1, h2, exc, *, tile_qubits=0, tile_qubits_rev=0,
+    def __init__(self, n_qubits, n_elec, h1, h2, exc, *, tile_qubits=0, tile_qubits_exp=0,
+                 tile_qubits_rev=0,
                  contiguous_qubits=0, block_threads=0, block_threads_fwd=0,
                  block_threads_exp=0, block_threads_rev=0, max_batch=1, launch_mode=0,
                  autotune=False, host_only=False, device=-1):
@@ -139,6 +142,7 @@ class Context:
         o = Options()
         L.ucc_default_options(ctypes.byref(o))
         o.tile_qubits, o.tile_qubits_rev = tile_qubits, tile_qubits_rev
+        o.tile_qubits_exp = tile_qubits_exp
         o.contiguous_qubits, o.block_threads = contiguous_qubits, block_threads
         o.block_threads_fwd, o.block_threads_exp = block_threads_fwd, block_threads_exp
         o.block_threads_rev, o.autotune = block_threads_rev, int(bool(autotune))

@@ -171,7 +171,8 @@ def test_16q_autotuned_context(ucc):
     ctx = ucc.Context(n, ne, h1, h2, exc, max_batch=4, autotune=True)
     info = ctx.plan_info()
     assert info["autotuned"] == 1
-    assert info["tile_qubits"] in (12, 13) and info["tile_qubits_rev"] in (11, 12)
+    assert info["tile_qubits"] in (13, 14) and info["tile_qubits_exp"] in (12, 13)
+    assert info["tile_qubits_rev"] in (12, 13)
     e, gr = ctx.energy_grad(th)
     e_ref, g_ref = oracle_eg(n, ne, h, g, exc, th[3])
     assert abs(e[3] - e_ref) <= E_TOL
@@ -179,8 +180,8 @@ def test_16q_autotuned_context(ucc):
     # a second context of the same shape takes the cached choice
     ctx2 = ucc.Context(n, ne, h1, h2, exc, max_batch=4, autotune=True)
     info2 = ctx2.plan_info()
-    for key in ("tile_qubits", "tile_qubits_rev", "block_threads_fwd", "block_threads_exp",
-                "block_threads_rev"):
+    for key in ("tile_qubits", "tile_qubits_exp", "tile_qubits_rev", "block_threads_fwd",
+                "block_threads_exp", "block_threads_rev"):
         assert info2[key] == info[key]
     e2, g2 = ctx2.energy_grad(th)
     assert np.array_equal(e2, e) and np.array_equal(g2, gr)

@@ -161,10 +161,11 @@ def test_excitation_signs_match_ladder_operators(n, ne):
 
 # ---------------------------------------------------------------- pass plan
 
-@pytest.mark.parametrize("n,ne,kf,kr", [(8, 4, 0, 0), (12, 8, 8, 7), (16, 8, 0, 0), (18, 10, 0, 0),
-                                        (18, 10, 10, 9)])
-def test_pass_plan_covers_everything_in_order(n, ne, kf, kr):
-    ctx, _, _, exc = host_ctx(n, ne, tile_qubits=kf, tile_qubits_rev=kr)
+@pytest.mark.parametrize("n,ne,kf,ke,kr", [(8, 4, 0, 0, 0), (12, 8, 8, 9, 7), (16, 8, 0, 0, 0),
+                                           (18, 10, 0, 0, 0), (18, 10, 10, 11, 9),
+                                           (18, 10, 14, 12, 13)])
+def test_pass_plan_covers_everything_in_order(n, ne, kf, ke, kr):
+    ctx, _, _, exc = host_ctx(n, ne, tile_qubits=kf, tile_qubits_exp=ke, tile_qubits_rev=kr)
     info = ctx.plan_info()
     passes = ctx.pass_table()
     et = ctx.excitation_table()
@@ -186,7 +187,7 @@ def test_pass_plan_covers_everything_in_order(n, ne, kf, kr):
     seen = np.concatenate([p["items"] for p in exp_])
     assert np.array_equal(np.sort(seen), np.arange(info["n_groups"]))
     for p in exp_:
-        assert bin(p["local"]).count("1") == info["tile_qubits"]
+        assert bin(p["local"]).count("1") == info["tile_qubits_exp"]
         for gi in p["items"]:
             assert int(gt["x"][gi]) & ~p["local"] == 0
 
