@@ -286,92 +286,112 @@ __device__ __forceinline__ double uniform(double v) {
   return __hiloint2double(hi, lo);
 }
 
-// Everything excitation e needs before its amplitudes (all wave-uniform but e0): cos, sin,
-// the sign sigma_k (-1)^popcount(base & m_global) common to the tile, the range of its pairs in
-// the class block, and the thread's first pair entry.
+// Everything excitation e needs before its amplitudes: (cos, sin), its record's sign data,
+// the range of its pairs in the class block and the thread's first pair entry.  Loaded one
+// excitation ahead and kept raw (converting to scalar registers at load time would wait for
+// the loads there); cur() turns them into wave-uniform values where they are used.
 struct ExcAhead {
-  double c, sn, sgn;
-  int i0, i1;
+  double2 t;
+  uint32_t mglob;
+  int sigma, i0, i1;
   uint32_t e0;
   __device__ __forceinline__ void load(const DevExc* sx, const double2* scs, const uint32_t* off,
-                                       const uint32_t* ent, int e, uint32_t base) {
-    const double2 t = scs[e];
-    c = uniform(t.x);
-    sn = uniform(t.y);
-    const int sig = parity(base & (uint32_t)uniform((int)sx[e].mglob)) ? -sx[e].sigma : sx[e].sigma;
-    sgn = (double)uniform(sig);
-    i0 = uniform((int)off[e]);
-    i1 = uniform((int)off[e + 1]);
+                                       const uint32_t* ent, int e) {
+    t = scs[e];
+    mglob = sx[e].mglob;
+    sigma = sx[e].sigma;
+    i0 = (int)off[e];
+    i1 = (int)off[e + 1];
     const int i = i0 + (int)threadIdx.x;
     e0 = i < i1 ? ent[i] : 0u;
   }
 };
 
-// Tile elements of the thread in registers <-> in-sector amplitudes in LDS by rank.
-// scatter: in-sector values go to cv[rank]; the others are written straight back to HBM
-// (unchanged; the whole tile is streamed).  gather_store: in-sector values from cv to HBM.
+// Wave-uniform view of an ExcAhead for a tile with global-bit offset base: cos, sin and the
+// sign sigma_k (-1)^popcount(base & m_global) common to the whole tile.
+struct ExcNow {
+  double c, sn, sgn;
+  int i0, i1;
+  uint32_t e0;
+  __device__ __forceinline__ explicit ExcNow(const ExcAhead& a, uint32_t base) {
+    c = uniform(a.t.x);
+    sn = uniform(a.t.y);
+    const int sig = parity(base & (uint32_t)uniform((int)a.mglob)) ? -a.sigma : a.sigma;
+    sgn = (double)uniform(sig);
+    i0 = uniform(a.i0);
+    i1 = uniform(a.i1);
+    e0 = a.e0;
+  }
+};
+
+// Tile elements of the thread (registers) and the tile's in-sector amplitudes (LDS, by rank).
+// Amplitudes outside the N / S_z sector are exactly zero and stay zero (the reference state is
+// in the sector and every factor conserves N and S_z).  A pass reads the whole tile and writes
+// the whole tile: in-sector values by rank list, the others as the constant zero they are,
+// from a register that is never overwritten, so no store ever holds up the next tile's loads
+// (a load into a register that a pending store still reads would wait for that store).
+//   take:      in-sector values -> cv[rank]; bit J of *insec marks in-sector elements
+//   put_zeros: zero stores for the elements outside the sector
+//   put_list:  in-sector values from cv to HBM through the class's physical offsets
 template <int T, int KT>
 struct Sector {
   using TL = Tile<T, KT>;
   static constexpr int EPT = TL::EPT;
   template <int J = 0>
-  static __device__ __forceinline__ void scatter(const TL& tm, const typename TL::Buf& r, double2* cv,
-                                                 const uint16_t* rtab, double2* __restrict__ v,
-                                                 uint32_t base) {
+  static __device__ __forceinline__ void take(const typename TL::Buf& r, double2* cv,
+                                              const uint16_t* rtab, uint32_t& insec) {
     const uint32_t rk = rtab[threadIdx.x + J * T];
-    if (rk != kNoRank)
+    if (rk != kNoRank) {
       st16(cv + rk, rget<J, EPT>(r));
-    else
-      st16(v + (base | tm.template off<J>()), rget<J, EPT>(r));
-    if constexpr (J + 1 < EPT) scatter<J + 1>(tm, r, cv, rtab, v, base);
+      insec |= 1u << J;
+    }
+    if constexpr (J + 1 < EPT) take<J + 1>(r, cv, rtab, insec);
   }
   template <int J = 0>
-  static __device__ __forceinline__ void scatter_hf(const TL& tm, double2* cv, const uint16_t* rtab,
-                                                    double2* __restrict__ v, uint32_t base,
-                                                    uint32_t hf) {
-    const uint32_t ph = base | tm.template off<J>();
-    const dvec2 val = {ph == hf ? 1.0 : 0.0, 0.0};
+  static __device__ __forceinline__ void take_hf(const TL& tm, double2* cv, const uint16_t* rtab,
+                                                 uint32_t base, uint32_t hf, uint32_t& insec) {
     const uint32_t rk = rtab[threadIdx.x + J * T];
-    if (rk != kNoRank)
-      st16(cv + rk, val);
-    else
-      st16(v + ph, val);
-    if constexpr (J + 1 < EPT) scatter_hf<J + 1>(tm, cv, rtab, v, base, hf);
+    if (rk != kNoRank) {
+      const uint32_t ph = base | tm.template off<J>();
+      st16(cv + rk, dvec2{ph == hf ? 1.0 : 0.0, 0.0});
+      insec |= 1u << J;
+    }
+    if constexpr (J + 1 < EPT) take_hf<J + 1>(tm, cv, rtab, base, hf, insec);
   }
   template <int J = 0>
-  static __device__ __forceinline__ void gather_store(const TL& tm, const double2* cv,
-                                                      const uint16_t* rtab,
-                                                      double2* __restrict__ v, uint32_t base) {
-    const uint32_t rk = rtab[threadIdx.x + J * T];
-    if (rk != kNoRank) st16(v + (base | tm.template off<J>()), ld16(cv + rk));
-    if constexpr (J + 1 < EPT) gather_store<J + 1>(tm, cv, rtab, v, base);
+  static __device__ __forceinline__ void put_zeros(const TL& tm, double2* __restrict__ v,
+                                                   uint32_t base, uint32_t insec, dvec2 zero) {
+    if (!((insec >> J) & 1u)) st16(v + (base | tm.template off<J>()), zero);
+    if constexpr (J + 1 < EPT) put_zeros<J + 1>(tm, v, base, insec, zero);
   }
 };
 
-// Loop forms of the same for tiles without a register-staged variant (KT = 0).
+template <int T>
+__device__ __forceinline__ void put_list(const double2* cv, const uint32_t* sphys, int ns,
+                                         double2* __restrict__ v, uint32_t base) {
+  for (int i = threadIdx.x; i < ns; i += T) st16(v + (base | sphys[i]), ld16(cv + i));
+}
+
+// Loop forms for tiles without a register-staged variant (KT = 0).
 template <int T, bool INIT>
-__device__ __forceinline__ void scatter_loop(uint32_t lmask, uint32_t tileN, double2* cv,
-                                             const uint16_t* rtab, double2* __restrict__ v,
-                                             uint32_t base, uint32_t hf) {
+__device__ __forceinline__ void take_loop(uint32_t lmask, uint32_t tileN, double2* cv,
+                                          const uint16_t* rtab, const double2* __restrict__ v,
+                                          uint32_t base, uint32_t hf) {
   for (uint32_t c = threadIdx.x; c < tileN; c += T) {
     const uint32_t ph = base | dep(c, lmask);
     const double2 val = INIT ? make_double2(ph == hf ? 1.0 : 0.0, 0.0) : v[ph];
+    // every amplitude of the tile is read (the load is not sunk into the branch below)
+    if (!INIT) asm volatile("" : : "v"(val.x), "v"(val.y));
     const uint32_t rk = rtab[c];
-    if (rk != kNoRank)
-      cv[rk] = val;
-    else
-      v[ph] = val;
+    if (rk != kNoRank) cv[rk] = val;
   }
 }
 
 template <int T>
-__device__ __forceinline__ void gather_loop(uint32_t lmask, uint32_t tileN, const double2* cv,
-                                            const uint16_t* rtab, double2* __restrict__ v,
-                                            uint32_t base) {
-  for (uint32_t c = threadIdx.x; c < tileN; c += T) {
-    const uint32_t rk = rtab[c];
-    if (rk != kNoRank) v[base | dep(c, lmask)] = cv[rk];
-  }
+__device__ __forceinline__ void zeros_loop(uint32_t lmask, uint32_t tileN, const uint16_t* rtab,
+                                           double2* __restrict__ v, uint32_t base) {
+  for (uint32_t c = threadIdx.x; c < tileN; c += T)
+    if (rtab[c] == kNoRank) v[base | dep(c, lmask)] = make_double2(0.0, 0.0);
 }
 
 // The pass kernels hold one or two workgroups per CU, i.e. T/256 waves per SIMD each: let
@@ -382,12 +402,12 @@ __device__ __forceinline__ void gather_loop(uint32_t lmask, uint32_t tileN, cons
 // gridDim.x (a multiple of the tile count where possible, so a workgroup keeps one tile
 // index and one class).  Per item:
 //   1. the tile (prefetched into registers: one 16-byte load per element, consecutive lanes
-//      on consecutive addresses) is split: in-sector amplitudes go to LDS by rank, the rest
-//      is written straight back (the whole state vector is streamed every pass);
-//   2. the next item's tile is requested, so its loads are in flight during step 3;
+//      on consecutive addresses) gives its in-sector amplitudes to LDS, by rank;
+//   2. the next item's tile is requested into the same registers (their only readers were
+//      LDS writes), so its loads are in flight during step 3;
 //   3. the pass's excitations run in order on the in-sector amplitudes in LDS, one barrier
 //      per excitation;
-//   4. the in-sector amplitudes are written back from LDS.
+//   4. the whole tile is written: zeros outside the sector, in-sector values from LDS.
 // Vector-memory counters retire in issue order, so the loads of step 2 come before the
 // stores of step 4 and step 1 of the next item waits for nothing issued after them.
 //
@@ -433,17 +453,19 @@ __global__ __launch_bounds__(T) LDS_BOUND_OCCUPANCY void k_fwd(
   if (RP && !INIT) tm.fetch(r, vec_of(item), base_of(item));
   if (cst) st.cs[threadIdx.x] = cs_of(item);
   const uint32_t* off = blk + 2;
+  const dvec2 zero = {0.0, 0.0};
   for (;;) {
     const uint32_t base = base_of(item);
     double2* __restrict__ v = vec_of(item);
+    uint32_t insec = 0u;
     if constexpr (RP) {
       tm.refresh();
       if (INIT)
-        SC::scatter_hf(tm, cp, rtab, v, base, hf);
+        SC::take_hf(tm, cp, rtab, base, hf, insec);
       else
-        SC::scatter(tm, r, cp, rtab, v, base);
+        SC::take(r, cp, rtab, insec);
     } else {
-      scatter_loop<T, INIT>(ps.lmask, tileN, cp, rtab, v, base, hf);
+      take_loop<T, INIT>(ps.lmask, tileN, cp, rtab, v, base, hf);
     }
     __syncthreads();
     const int next = item + gridDim.x;
@@ -453,13 +475,14 @@ __global__ __launch_bounds__(T) LDS_BOUND_OCCUPANCY void k_fwd(
       if (RP && !INIT) tm.fetch(r, vec_of(next), base_of(next));
       if (cst) csv = cs_of(next);
     }
-    const int m = (int)blk[1];
-    const uint32_t* ent = blk + 3 + m + (((int)blk[0] + 1) >> 1);
+    const int m = (int)blk[1], ns = (int)blk[0];
+    const uint32_t* sphys = blk + 3 + m + ((ns + 1) >> 1);
+    const uint32_t* ent = sphys + ns;
     ExcAhead ah;
-    ah.load(st.x, st.cs, off, ent, 0, base);
+    ah.load(st.x, st.cs, off, ent, 0);
     for (int e = 0; e < ps.count; ++e) {
-      const ExcAhead cur = ah;
-      if (e + 1 < ps.count) ah.load(st.x, st.cs, off, ent, e + 1, base);
+      const ExcNow cur(ah, base);
+      if (e + 1 < ps.count) ah.load(st.x, st.cs, off, ent, e + 1);
       const double c = cur.c;
       const double s = cur.sgn * cur.sn;
       for (int i = cur.i0 + threadIdx.x; i < cur.i1; i += T) {
@@ -474,10 +497,11 @@ __global__ __launch_bounds__(T) LDS_BOUND_OCCUPANCY void k_fwd(
     }
     if constexpr (RP) {
       tm.refresh();
-      SC::gather_store(tm, cp, rtab, v, base);
+      SC::put_zeros(tm, v, base, insec, zero);
     } else {
-      gather_loop<T>(ps.lmask, tileN, cp, rtab, v, base);
+      zeros_loop<T>(ps.lmask, tileN, rtab, v, base);
     }
+    put_list<T>(cp, sphys, ns, v, base);
     if (next >= total) break;
     __syncthreads();  // cp, the table and the (cos, sin) stage are no longer read
     stage_class(base_of(next));
@@ -498,8 +522,7 @@ __global__ __launch_bounds__(T) LDS_BOUND_OCCUPANCY void k_rev(
   extern __shared__ double2 lds[];
   constexpr int NW = T / 64;
   __shared__ PassStage st;
-  __shared__ double red[2][NW];
-  __shared__ double gsum[kMaxPassExc];
+  __shared__ double red[kMaxPassExc][NW];  // per-wave partials of <lambda|G_k|psi>
   using TL = Tile<T, KT>;
   using SC = Sector<T, KT>;
   constexpr bool RP = KT != 0;
@@ -538,19 +561,20 @@ __global__ __launch_bounds__(T) LDS_BOUND_OCCUPANCY void k_rev(
   }
   if (cst) st.cs[threadIdx.x] = cs_of(item);
   const uint32_t* off = blk + 2;
+  const dvec2 zero = {0.0, 0.0};
   for (;;) {
     const int b = item >> tb;
     const uint32_t t = item & tmask;
     const uint32_t base = base_of(item);
     double2* __restrict__ vp = psi + off_of(item);
     double2* __restrict__ vl = lam + off_of(item);
+    uint32_t insec = 0u;
     if constexpr (RP) {
-      tm.refresh();
-      SC::scatter(tm, rp, cp, rtab, vp, base);
-      SC::scatter(tm, rl, cl, rtab, vl, base);
+      SC::take(rp, cp, rtab, insec);
+      SC::take(rl, cl, rtab, insec);
     } else {
-      scatter_loop<T, false>(ps.lmask, tileN, cp, rtab, vp, base, 0u);
-      scatter_loop<T, false>(ps.lmask, tileN, cl, rtab, vl, base, 0u);
+      take_loop<T, false>(ps.lmask, tileN, cp, rtab, vp, base, 0u);
+      take_loop<T, false>(ps.lmask, tileN, cl, rtab, vl, base, 0u);
     }
     __syncthreads();
     const int next = item + gridDim.x;
@@ -563,60 +587,89 @@ __global__ __launch_bounds__(T) LDS_BOUND_OCCUPANCY void k_rev(
       }
       if (cst) csv = cs_of(next);
     }
-    const int m = (int)blk[1];
-    const uint32_t* ent = blk + 3 + m + (((int)blk[0] + 1) >> 1);
-    int prev_e = -1;
+    const int m = (int)blk[1], ns = (int)blk[0];
+    const uint32_t* sphys = blk + 3 + m + ((ns + 1) >> 1);
+    const uint32_t* ent = sphys + ns;
+    // The wave sum of excitation e's partial runs while excitation e+1's first amplitudes
+    // load (off the barrier-to-barrier chain); lane 0 of each wave keeps it in red[e].  The
+    // sums run in uniform control flow (whole wave), skipped by waves that had no pair.
+    double gprev = 0.0;
+    bool had_prev = false;
     ExcAhead ah;
-    ah.load(st.x, st.cs, off, ent, 0, base);
+    ah.load(st.x, st.cs, off, ent, 0);
     for (int e = 0; e < ps.count; ++e) {
-      const ExcAhead cur = ah;
-      if (e + 1 < ps.count) ah.load(st.x, st.cs, off, ent, e + 1, base);
+      const ExcNow cur(ah, base);
+      if (e + 1 < ps.count) ah.load(st.x, st.cs, off, ent, e + 1);
       const double c = cur.c, sn = cur.sn;
       const double sgn0 = cur.sgn;
       const int i0 = cur.i0, i1 = cur.i1;
+      const int ia = i0 + (int)threadIdx.x;
+      const bool has = ia < i1;
+      uint32_t ru = 0u, rw = 0u;
+      double sg = 0.0;
+      double2 pu = make_double2(0.0, 0.0), pw = pu, lu = pu, lw = pu;
+      if (has) {
+        ru = cur.e0 & 0x7fffu;
+        rw = cur.e0 >> 16;
+        sg = (cur.e0 & 0x8000u) ? -sgn0 : sgn0;
+        pu = cp[ru];
+        pw = cp[rw];
+        lu = cl[ru];
+        lw = cl[rw];
+      }
+      if (e > 0) {
+        double gs = 0.0;
+        if (had_prev) gs = wave_sum(gprev);
+        if (lane == 0) red[e - 1][wv] = gs;
+      }
       double g = 0.0;
-      if (i0 + wv * 64 < i1) {  // this wave has pairs of this excitation
-        for (int i = i0 + threadIdx.x; i < i1; i += T) {
-          const uint32_t en = i == i0 + (int)threadIdx.x ? cur.e0 : ent[i];
-          const uint32_t ru = en & 0x7fffu, rw = en >> 16;
-          const double sg = (en & 0x8000u) ? -sgn0 : sgn0;
-          const double2 pu = cp[ru], pw = cp[rw], lu = cl[ru], lw = cl[rw];
-          g += sg * ((lw.x * pu.x + lw.y * pu.y) - (lu.x * pw.x + lu.y * pw.y));
-          const double s = sg * sn;
-          cp[ru] = make_double2(c * pu.x + s * pw.x, c * pu.y + s * pw.y);
-          cp[rw] = make_double2(c * pw.x - s * pu.x, c * pw.y - s * pu.y);
-          cl[ru] = make_double2(c * lu.x + s * lw.x, c * lu.y + s * lw.y);
-          cl[rw] = make_double2(c * lw.x - s * lu.x, c * lw.y - s * lu.y);
-        }
-        g = wave_sum(g);
+      if (has) {
+        g += sg * ((lw.x * pu.x + lw.y * pu.y) - (lu.x * pw.x + lu.y * pw.y));
+        const double s = sg * sn;
+        cp[ru] = make_double2(c * pu.x + s * pw.x, c * pu.y + s * pw.y);
+        cp[rw] = make_double2(c * pw.x - s * pu.x, c * pw.y - s * pu.y);
+        cl[ru] = make_double2(c * lu.x + s * lw.x, c * lu.y + s * lw.y);
+        cl[rw] = make_double2(c * lw.x - s * lu.x, c * lw.y - s * lu.y);
       }
-      if (lane == 0) red[e & 1][wv] = g;
-      // the last wave (pairs rarely reach it) folds the previous excitation's wave sums
-      if (threadIdx.x == T - 64 && prev_e >= 0) {
-        double sum = 0.0;
-        for (int i = 0; i < NW; ++i) sum += red[prev_e & 1][i];
-        gsum[prev_e] = sum;
+      for (int i = ia + T; i < i1; i += T) {
+        const uint32_t en = ent[i];
+        const uint32_t qu = en & 0x7fffu, qw = en >> 16;
+        const double sq = (en & 0x8000u) ? -sgn0 : sgn0;
+        const double2 au = cp[qu], aw = cp[qw], bu = cl[qu], bw = cl[qw];
+        g += sq * ((bw.x * au.x + bw.y * au.y) - (bu.x * aw.x + bu.y * aw.y));
+        const double s = sq * sn;
+        cp[qu] = make_double2(c * au.x + s * aw.x, c * au.y + s * aw.y);
+        cp[qw] = make_double2(c * aw.x - s * au.x, c * aw.y - s * au.y);
+        cl[qu] = make_double2(c * bu.x + s * bw.x, c * bu.y + s * bw.y);
+        cl[qw] = make_double2(c * bw.x - s * bu.x, c * bw.y - s * bu.y);
       }
-      prev_e = e;
+      gprev = g;
+      had_prev = i0 + wv * 64 < i1;
       __syncthreads();
     }
-    if (threadIdx.x == T - 64 && prev_e >= 0) {
-      double sum = 0.0;
-      for (int i = 0; i < NW; ++i) sum += red[prev_e & 1][i];
-      gsum[prev_e] = sum;
+    {
+      double gs = 0.0;
+      if (had_prev) gs = wave_sum(gprev);
+      if (lane == 0) red[ps.count - 1][wv] = gs;
     }
-    __syncthreads();  // gsum complete
-    if (cst) gpart[((size_t)b * K + st.x[threadIdx.x].k) * ntiles + t] = gsum[threadIdx.x];
+    __syncthreads();  // red complete
+    if (cst) {
+      double sum = 0.0;
+      for (int w = 0; w < NW; ++w) sum += red[threadIdx.x][w];
+      gpart[((size_t)b * K + st.x[threadIdx.x].k) * ntiles + t] = sum;
+    }
     if constexpr (RP) {
       tm.refresh();
-      SC::gather_store(tm, cp, rtab, vp, base);
-      SC::gather_store(tm, cl, rtab, vl, base);
+      SC::put_zeros(tm, vp, base, insec, zero);
+      SC::put_zeros(tm, vl, base, insec, zero);
     } else {
-      gather_loop<T>(ps.lmask, tileN, cp, rtab, vp, base);
-      gather_loop<T>(ps.lmask, tileN, cl, rtab, vl, base);
+      zeros_loop<T>(ps.lmask, tileN, rtab, vp, base);
+      zeros_loop<T>(ps.lmask, tileN, rtab, vl, base);
     }
+    put_list<T>(cp, sphys, ns, vp, base);
+    put_list<T>(cl, sphys, ns, vl, base);
     if (next >= total) break;
-    __syncthreads();  // cp, cl, the table, gsum and the (cos, sin) stage are no longer read
+    __syncthreads();  // cp, cl, the table, red and the (cos, sin) stage are no longer read
     stage_class(base_of(next));
     if (cst) st.cs[threadIdx.x] = csv;
     item = next;

@@ -479,7 +479,7 @@ std::string build_plan(Plan& p, int n, int ne, const double* h1, const double* h
   }
   // forward/reverse windows whose largest class block would not fit next to the rank table
   // and the compact in-sector vector(s) are halved (same local set, order kept)
-  auto fit_blocks = [&](std::vector<Plan::Pass>& ws, int vectors) -> bool {
+  auto fit_blocks = [&](std::vector<Plan::Pass>& ws, int vectors, int static_bytes) -> bool {
     std::vector<Plan::Pass> out;
     std::vector<Plan::Pass> todo(ws.rbegin(), ws.rend());
     while (!todo.empty()) {
@@ -488,7 +488,7 @@ std::string build_plan(Plan& p, int n, int ne, const double* h1, const double* h
       const int ns = max_class_size(p, w.lmask);
       if (ns >= 32768) return false;
       const int budget_words =
-          (kLdsBytes - (2 << pc32(w.lmask)) - 16 * vectors * ns - kStageBytes - 4096) / 4;
+          (kLdsBytes - (2 << pc32(w.lmask)) - 16 * vectors * ns - static_bytes - 1024) / 4;
       if (max_pair_block_words(p, w.lmask, w.items) <= budget_words) {
         out.push_back(w);
         continue;
@@ -504,7 +504,8 @@ std::string build_plan(Plan& p, int n, int ne, const double* h1, const double* h
     ws.swap(out);
     return true;
   };
-  if (!fit_blocks(fw, 1) || !fit_blocks(rv, 2))
+  // static LDS: the pass stage, plus per-wave gradient partials of up to 16 waves (reverse)
+  if (!fit_blocks(fw, 1, kStageBytes) || !fit_blocks(rv, 2, kStageBytes + 16 * 8 * kMaxPassExc))
     return "tile too large for the pair lists of one excitation";
   p.nfwd = (int)fw.size();
   p.nexp = (int)ex.size();
@@ -582,6 +583,7 @@ std::vector<uint32_t> pair_block(const Plan& p, uint32_t lmask, const std::vecto
   w[1] = (uint32_t)m;
   for (size_t i = 0; i < ns; i += 2)
     w.push_back(cs[i] | (i + 1 < ns ? cs[i + 1] << 16 : 0u));
+  for (size_t i = 0; i < ns; ++i) w.push_back(bucket[i].second);  // local physical offsets
   const size_t ent0 = w.size();
   for (size_t j = 0; j < m; ++j) {
     const auto& e = p.ex[items[j]];

@@ -46,6 +46,7 @@ constexpr int kMaxPassExc = 256;  // excitations per forward/reverse pass (stage
 //               off[j] .. off[j+1]-1
 //   then ceil(ns / 2) words: the in-sector compact indices in ascending order, two uint16 per
 //   word (the position of a state in this list is its rank)
+//   then ns words: the local physical offset (deposit of the compact index) of each rank
 //   then one word per pair of each excitation: rank of u (u & supp == from) in bits 0-14,
 //   the parity of u over the tile-local part of the JW mask in bit 15, rank of u ^ supp in
 //   bits 16-31.
