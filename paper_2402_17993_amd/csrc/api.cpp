@@ -131,7 +131,6 @@ LaunchArgs make_args(const ucc_ctx* c, const Buffers& b, int B, hipStream_t st) 
   a.pairs = c->d_pairs;
   a.blobs = reinterpret_cast<const uint4*>(c->d_blob);
   a.cls = reinterpret_cast<const int2*>(c->d_cls);
-  a.list = reinterpret_cast<const uint2*>(c->d_list);
   a.psi = b.psi;
   a.lam = b.lam;
   a.cs = b.cs;
@@ -222,13 +221,11 @@ void free_tables(ucc_ctx* c) {
   free_ptr(c->d_pairs);
   free_ptr(c->d_blob);
   free_ptr(c->d_cls);
-  free_ptr(c->d_list);
   c->d_passes = nullptr;
   c->d_exc = nullptr;
   c->d_pairs = nullptr;
   c->d_blob = nullptr;
   c->d_cls = nullptr;
-  c->d_list = nullptr;
 }
 
 ucc_status upload_tables(ucc_ctx* c) {
@@ -238,8 +235,7 @@ ucc_status upload_tables(ucc_ctx* c) {
       (e = upload(&c->d_exc, t.exc)) != hipSuccess ||
       (e = upload(&c->d_pairs, t.pairs)) != hipSuccess ||
       (e = upload(&c->d_blob, t.blob)) != hipSuccess ||
-      (e = upload(&c->d_cls, t.cls)) != hipSuccess ||
-      (e = upload(&c->d_list, t.list)) != hipSuccess)
+      (e = upload(&c->d_cls, t.cls)) != hipSuccess)
     return hip_fail(e, "device table upload");
   return UCC_OK;
 }

@@ -59,7 +59,6 @@ struct ucc_ctx {
   uint32_t* d_pairs = nullptr;
   uint32_t* d_blob = nullptr;
   int32_t* d_cls = nullptr;
-  uint32_t* d_list = nullptr;
   ucc::Buffers buf;
   int last_B = 0;
   std::atomic<int> busy{0};  // held by a server job

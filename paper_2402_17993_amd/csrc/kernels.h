@@ -20,7 +20,6 @@ struct LaunchArgs {
   int blob_stride = 0;  // uint4 per batch entry when entries have their own Hamiltonian
   int cu_share = 0;     // compute units the persistent pass kernels may fill (0 = all)
   const int2* cls = nullptr;
-  const uint2* list = nullptr;
   double2* psi = nullptr;
   double2* lam = nullptr;
   double2* cs = nullptr;

@@ -263,7 +263,9 @@ constexpr uint32_t kNoRank = 0xffffu;
 
 // Stage the class block of a forward/reverse pass (layout: ucc_internal.h) and build the rank
 // table rtab[c] = rank of in-sector compact index c, kNoRank elsewhere.
-template <int T>
+// (The in-sector index list sits at word 3 + m of a forward/reverse block and at word
+// 3 + 2 ns of an expectation block.)
+template <int T, bool EXP = false>
 __device__ __forceinline__ void stage_sc_class(uint32_t* blk, uint16_t* rtab,
                                                const uint32_t* __restrict__ src, int words,
                                                uint32_t tileN) {
@@ -272,8 +274,8 @@ __device__ __forceinline__ void stage_sc_class(uint32_t* blk, uint16_t* rtab,
   uint32_t* rt2 = reinterpret_cast<uint32_t*>(rtab);
   for (uint32_t c = threadIdx.x; c < tileN / 2; c += T) rt2[c] = 0xffffffffu;
   __syncthreads();
-  const int ns = (int)blk[0], m = (int)blk[1];
-  const uint16_t* sl = reinterpret_cast<const uint16_t*>(blk + 3 + m);
+  const int ns = (int)blk[0];
+  const uint16_t* sl = reinterpret_cast<const uint16_t*>(blk + (EXP ? 3 + 2 * ns : 3 + (int)blk[1]));
   for (int i = threadIdx.x; i < ns; i += T) rtab[sl[i]] = (uint16_t)i;
   __syncthreads();
 }
@@ -676,63 +678,47 @@ __global__ __launch_bounds__(T) LDS_BOUND_OCCUPANCY void k_rev(
   }
 }
 
-// lambda values of the first J entries (per quad lane 0) of an apply-H item, loaded before
-// the next tile's prefetch is issued; later entries (beyond J * T/4) load on use.
-template <int T>
-struct OldBuf {
-  static constexpr int J = 4096 / T;
-  RegBuf<J> r;
-  template <int I = 0>
-  __device__ __forceinline__ void load(const uint2* lst, const double2* __restrict__ vl, uint32_t base,
-                                       int nlist, bool rmw) {
-    const int it = (threadIdx.x >> 2) + I * (T / 4);
-    rget<I, J>(r) = (rmw && it < nlist) ? ld16(vl + (base | lst[it].y)) : dvec2{0.0, 0.0};
-    if constexpr (I + 1 < J) load<I + 1>(lst, vl, base, nlist, rmw);
-  }
-  template <int I = 0>
-  __device__ __forceinline__ dvec2 pick(int j, dvec2 v) const {
-    v = j == I ? rget<I, J>(r) : v;
-    if constexpr (I + 1 < J)
-      return pick<I + 1>(j, v);
-    else
-      return v;
-  }
-  __device__ __forceinline__ dvec2 get(int j, const double2* __restrict__ vl, uint32_t u,
-                                       bool rmw) const {
-    if (j < J) return pick(j, dvec2{0.0, 0.0});
-    return rmw ? ld16(vl + u) : dvec2{0.0, 0.0};
-  }
-};
-
-// Expectation / apply-H pass.  Only in-sector basis states u of a tile can be non-zero (the
-// HF state has N = n_elec, S_z = 0 and every factor and every Hamiltonian term conserves
-// both).  Each in-sector u is handled by a quad of lanes; lane s of the quad gathers
-//     (H psi)[u] += <u|H_g|u ^ x_g> psi[u ^ x_g]
-// over every fourth group of the pass (matrix element evaluated at the source state
-// v = u ^ x_g from the compiled group table), and the quad adds its four partial sums in a
-// fixed order.  The energy partial is sum_u Re(conj(psi[u]) (H psi)[u]).  With APPLY the
-// gathered values are added into lambda (first pass: written).
-//
-// The pass's group tables arrive as one blob (layout: ExpBlob in ucc_internal.h) that each
-// workgroup copies into LDS behind the tile once.
+// Expectation / apply-H pass.  Only in-sector basis states can be non-zero.  For every
+// in-sector target u of the tile, a quad of lanes walks u's row of the class block: each
+// entry is one group g of the pass whose source v = u ^ x_g has a valid pattern, and adds
+//     <u|H_g|v> psi[v] = (-1)^popcount(v & m_g) (A_g[P] + sum_r B_g[P][r] n_r(v)) psi[v]
+// (the tile-global parts of the sign and of the occupation sum are folded into per-slot
+// values once per tile; the local sign bit and the source rank come with the entry).  The
+// quad adds its four partial sums in a fixed order; the pass holding the diagonal group
+// adds <u|H_0|u> psi[u].  The energy partial is sum_u Re(conj(psi[u]) (H psi)[u]); with
+// APPLY the row sums are added into lambda (first pass: written).
 template <int T, int KT, bool APPLY>
-__global__ __launch_bounds__(T) LDS_BOUND_OCCUPANCY void k_exp(const DevPass* __restrict__ passes, int pidx,
-                                           const uint4* __restrict__ blobs,
-                                           const int2* __restrict__ cls,
-                                           const uint2* __restrict__ list,
-                                           const double2* __restrict__ psi,
-                                           double2* __restrict__ lam, int n, uint32_t amask,
-                                           uint32_t bmask, double* __restrict__ epart,
-                                           int estride, int first, int total, int bstride) {
+__global__ __launch_bounds__(T) LDS_BOUND_OCCUPANCY void k_exp(
+    const DevPass* __restrict__ passes, int pidx, const uint4* __restrict__ blobs,
+    const int2* __restrict__ pcls, const uint32_t* __restrict__ blocks,
+    const double2* __restrict__ psi, double2* __restrict__ lam, int n, uint32_t amask,
+    uint32_t bmask, double* __restrict__ epart, int estride, int first, int total, int bstride) {
   extern __shared__ double2 lds[];
   using TL = Tile<T, KT>;
+  using SC = Sector<T, KT>;
+  constexpr bool RP = KT != 0;
   const DevPass ps = passes[pidx];
   const uint32_t tileN = 1u << ps.k;
+  const int k = ps.k;
   const int tb = n - ps.k;
   const uint32_t tmask = (1u << tb) - 1u;
-  uint4* lb = reinterpret_cast<uint4*>(lds + tileN);
-  // The blob of batch entry b sits at blobs + b * bstride (bstride 0: one Hamiltonian for
-  // the whole batch, copied once; otherwise re-staged whenever the entry changes).
+  // LDS: in-sector psi | value table | per-tile slot values t1, t2 | diagonal prep |
+  //      wave sums | class block | rank table
+  double2* cp = lds;
+  uint4* lb = reinterpret_cast<uint4*>(lds + ps.ns_max);
+  double* t1 = reinterpret_cast<double*>(lb + ps.blob_len);
+  double* t2 = t1 + ((ps.n_slots + 1) & ~1);
+  double* dpre = t2 + ((ps.n_occ + 1) & ~1);  // [0] global part of the diagonal, [1 + j] local bit j
+  double* red = dpre + ((k + 2) & ~1);
+  uint32_t* blk = reinterpret_cast<uint32_t*>(red + 16);
+  uint16_t* rtab = reinterpret_cast<uint16_t*>(blk + ps.stage_len);
+  const uint32_t* bw = reinterpret_cast<const uint32_t*>(lb);
+  const double* dw = reinterpret_cast<const double*>(lb);
+  const TL tm(ps.lmask);
+  int item = blockIdx.x;
+  if (item >= total) return;
+  // The value table of batch entry b sits at blobs + b * bstride (bstride 0: one Hamiltonian
+  // for the whole batch, copied once; otherwise re-staged whenever the entry changes).
   int blob_b = -1;
   auto stage_blob = [&](int b) {
     const int key = bstride ? b : 0;
@@ -741,148 +727,146 @@ __global__ __launch_bounds__(T) LDS_BOUND_OCCUPANCY void k_exp(const DevPass* __
     for (int i = threadIdx.x; i < ps.blob_len; i += T) lb[i] = gb[i];
     blob_b = key;
   };
-  uint2* lst = reinterpret_cast<uint2*>(lb + ps.blob_len);  // the class's in-sector list
-  double* red = reinterpret_cast<double*>(lst + ps.stage_len);
-  int staged = -1, nlist = 0;
-  const uint32_t* bw = reinterpret_cast<const uint32_t*>(lb);
-  const TL tm(ps.lmask);
-  const int sub = threadIdx.x & 3;
-  const bool rmw = APPLY && !first && sub == 0;
-  typename TL::Buf r;
-  OldBuf<T> olds;
-  int item = blockIdx.x;
-  if (item >= total) return;
+  int staged = -1;
   auto base_of = [&](int it) { return dep(it & tmask, ps.gmask); };
+  auto vec_of = [&](int it) { return psi + ((size_t)(it >> tb) << n); };
   auto stage_class = [&](uint32_t base) {
-    const int cli = tile_class(base, amask, bmask, ps.nbeta_g);
-    if (cli != staged) {
-      __syncthreads();  // the previous list is no longer read
-      const int2 cl = cls[ps.cls_base + cli];
-      for (int i = threadIdx.x; i < cl.y; i += T) lst[i] = list[cl.x + i];
-      nlist = cl.y;
-      staged = cli;
-      __syncthreads();
+    const int cl = tile_class(base, amask, bmask, ps.nbeta_g);
+    if (cl != staged) {
+      const int2 bl = pcls[ps.cls_base + cl];
+      stage_sc_class<T, true>(blk, rtab, blocks + bl.x, bl.y, tileN);
+      staged = cl;
     }
   };
-  // prologue: first tile, its class list and lambda values; the next tile in flight.
-  // Loads are issued in the order they are consumed (vector-memory counters retire in
-  // issue order): lambda values of an item before the prefetch of the item after it.
-  {
-    const uint32_t base = base_of(item);
-    stage_blob(item >> tb);
-    stage_class(base);
-    olds.load(lst, APPLY ? lam + ((size_t)(item >> tb) << n) : nullptr, base, nlist, rmw);
-    tm.load(lds, psi + ((size_t)(item >> tb) << n), base, tileN);
-    const int next = item + gridDim.x;
-    if (KT && next < total) tm.fetch(r, psi + ((size_t)(next >> tb) << n), base_of(next));
-  }
-  __syncthreads();
+  typename TL::Buf r;
+  stage_blob(item >> tb);
+  stage_class(base_of(item));  // its barriers also publish the value table
+  if (RP) tm.fetch(r, vec_of(item), base_of(item));
+  const int sub = threadIdx.x & 3;
   for (;;) {
     const int b = item >> tb;
     const uint32_t t = item & tmask;
     const uint32_t base = base_of(item);
     double2* __restrict__ vl = APPLY ? lam + ((size_t)b << n) : nullptr;
-    const int nd = (int)bw[0], no = (int)bw[1], npl = (int)bw[2];
-    const uint4* occr = reinterpret_cast<const uint4*>(bw + bw[3]);
-    const uint4* plr = reinterpret_cast<const uint4*>(bw + bw[4]);
-    const double* dg = reinterpret_cast<const double*>(bw + bw[5]);
-    const double* dw = reinterpret_cast<const double*>(bw);  // double view of the blob
+    uint32_t insec = 0u;
+    if constexpr (RP)
+      SC::take(r, cp, rtab, insec);
+    else
+      take_loop<T, false>(ps.lmask, tileN, cp, rtab, vec_of(item), base, 0u);
+    (void)insec;
+    // per-tile slot values
+    const int n_slots = (int)bw[0], n_occ = (int)bw[1], has_diag = (int)bw[2];
+    const uint32_t* mglob = bw + bw[4];
+    const uint32_t* xloc = bw + bw[5];
+    const double* A = dw + (bw[6] >> 1);
+    const double* Bloc = dw + (bw[7] >> 1);
+    const double* Bglob = dw + (bw[8] >> 1);
+    const double* dg = dw + (bw[9] >> 1);
+    const double* bl = dg + 1 + n + n * n;
+    for (int s = threadIdx.x; s < n_slots; s += T) {
+      double val = A[s];
+      if (s < n_occ)
+        for (uint32_t gbits = base; gbits; gbits &= gbits - 1) val += Bglob[(size_t)s * n + (__ffs(gbits) - 1)];
+      const bool neg = parity(base & mglob[s]);
+      t1[s] = neg ? -val : val;
+      if (s < n_occ) t2[s] = neg ? -1.0 : 1.0;
+    }
+    if (has_diag) {
+      const int j = (int)threadIdx.x - 64;  // a wave other than the slot loop's first
+      if (threadIdx.x == 0) {
+        double d = dg[0];
+        for (uint32_t gbits = base; gbits; gbits &= gbits - 1) {
+          const int rr = __ffs(gbits) - 1;
+          d += dg[1 + rr];
+          for (uint32_t g2 = gbits & (gbits - 1); g2; g2 &= g2 - 1) d += dg[1 + n + rr * n + (__ffs(g2) - 1)];
+        }
+        dpre[0] = d;
+      } else if (j >= 0 && j < k) {
+        uint32_t lm = ps.lmask;
+        for (int q = 0; q < j; ++q) lm &= lm - 1;
+        const int pj = __ffs(lm) - 1;  // physical bit of local bit j
+        double d = dg[1 + pj];
+        for (uint32_t gbits = base; gbits; gbits &= gbits - 1) {
+          const int rr = __ffs(gbits) - 1;
+          d += rr < pj ? dg[1 + n + rr * n + pj] : dg[1 + n + pj * n + rr];
+        }
+        dpre[1 + j] = d;
+      }
+    }
+    __syncthreads();  // cp and the per-tile values complete
+    const int next = item + gridDim.x;
+    if (RP && next < total) {
+      tm.refresh();
+      tm.fetch(r, vec_of(next), base_of(next));
+    }
+    const int ns = (int)blk[0];
+    const uint32_t* off = blk + 2;
+    const uint32_t* mid = off + ns + 1;
+    const uint16_t* sl = reinterpret_cast<const uint16_t*>(mid + ns);
+    const uint32_t* sphys = mid + ns + ((ns + 1) >> 1);
+    const uint32_t* ent = sphys + ns;
     double eacc = 0.0;
-    for (int j = 0;; ++j) {
-      const int it = (threadIdx.x >> 2) + j * (T / 4);
-      if (it >= nlist) break;
-      const uint2 ent = lst[it];
-      const uint32_t c = ent.x;
-      const uint32_t u = base | ent.y;
-      const double2 pu = lds[c];
-      const dvec2 old = olds.get(j, vl, u, rmw);
+    for (int i0 = 0; i0 < ns; i0 += T / 4) {
+      const int i = i0 + ((int)threadIdx.x >> 2);
+      const bool row = i < ns;  // the same for the four lanes of a quad
       double ax = 0.0, ay = 0.0;
-      if (nd) {  // diagonal c0 + sum_r a_r n_r + sum_{r<s} b_rs n_r n_s; set bits split by rank
-        double f = sub == 0 ? dg[0] : 0.0;
-        uint32_t rem = u;
-        int rank = 0;
-        while (rem) {
-          const int q = __ffs(rem) - 1;
-          rem &= rem - 1;
-          if ((rank++ & 3) == sub) {
-            f += dg[1 + q];
-            const double* brow = dg + 1 + n + q * n;
-            for (uint32_t r2 = rem; r2; r2 &= r2 - 1) f += brow[__ffs(r2) - 1];
-          }
+      dvec2 old = {0.0, 0.0};
+      uint32_t phys = 0u;
+      if (row) {
+        phys = base | sphys[i];
+        if (APPLY && !first && sub == 0) old = ld16(vl + phys);
+        const int e0 = (int)off[i], e1 = (int)mid[i], e2 = (int)off[i + 1];
+        for (int e = e0 + sub; e < e1; e += 4) {  // groups with occupation rows
+          const uint32_t en = ent[e];
+          const uint32_t rv = en & 0x7fffu, slot = en >> 16;
+          const double* br = Bloc + (size_t)slot * k;
+          double occ = 0.0;
+          for (uint32_t bits = (uint32_t)sl[rv] & ~xloc[slot]; bits; bits &= bits - 1) occ += br[__ffs(bits) - 1];
+          double val = t1[slot] + t2[slot] * occ;
+          if (en & 0x8000u) val = -val;
+          const double2 pv = cp[rv];
+          ax += val * pv.x;
+          ay += val * pv.y;
         }
-        ax += f * pu.x;
-        ay += f * pu.y;
-      }
-      // groups with occupation-number terms: lane `sub` of the quad takes every fourth one
-      for (int gb = 0; gb < no; gb += 4) {
-        const int g = gb + sub;
-        if (g < no) {
-          const uint4 ha = occr[2 * g], hb = occr[2 * g + 1];  // {xc, xphys, m, valid}, {spos, nsup, occ, a}
-          const uint32_t spos = hb.x, nsup = hb.y;
-          uint32_t P = ((u >> (spos & 31u)) & 1u) | (((u >> ((spos >> 5) & 31u)) & 1u) << 1);
-          if (nsup == 4)
-            P |= (((u >> ((spos >> 10) & 31u)) & 1u) << 2) | (((u >> ((spos >> 15) & 31u)) & 1u) << 3);
-          if ((ha.w >> P) & 1u) {
-            const uint32_t Pv = P ^ ((1u << nsup) - 1u);
-            const uint32_t slot = __popc(ha.w & ((1u << Pv) - 1u));
-            double val = dw[(hb.w >> 1) + slot];
-            const double* Bt = dw + (hb.z >> 1) + slot * n;
-            for (uint32_t rr = u & ~ha.y; rr; rr &= rr - 1) val += Bt[__ffs(rr) - 1];
-            if (parity(u & ha.z)) val = -val;
-            const double2 pw = lds[c ^ ha.x];
-            ax += val * pw.x;
-            ay += val * pw.y;
-          }
+        for (int e = e1 + sub; e < e2; e += 4) {
+          const uint32_t en = ent[e];
+          const uint32_t rv = en & 0x7fffu;
+          const double val = (en & 0x8000u) ? -t1[en >> 16] : t1[en >> 16];
+          const double2 pv = cp[rv];
+          ax += val * pv.x;
+          ay += val * pv.y;
         }
-      }
-      // plain groups (+-A[pattern]); the next record is fetched while this one is used
-      uint4 hn = sub < npl ? plr[sub] : make_uint4(0u, 0u, 0u, 0u);
-      for (int gb = 0; gb < npl; gb += 4) {
-        const int g = gb + sub;
-        const uint4 h = hn;  // {xc | size4 << 31, spos, m, valid | a << 16}
-        if (g + 4 < npl) hn = plr[g + 4];
-        if (g < npl) {
-          const uint32_t spos = h.y;
-          uint32_t P = ((u >> (spos & 31u)) & 1u) | (((u >> ((spos >> 5) & 31u)) & 1u) << 1);
-          uint32_t full = 3u;
-          if (h.x >> 31) {
-            P |= (((u >> ((spos >> 10) & 31u)) & 1u) << 2) | (((u >> ((spos >> 15) & 31u)) & 1u) << 3);
-            full = 15u;
+        if (has_diag) {  // c0 + sum_r a_r n_r + sum_{r<s} b_rs n_r n_s; set bits split by rank
+          double f = sub == 0 ? dpre[0] : 0.0;
+          int rank = 0;
+          for (uint32_t rem = (uint32_t)sl[i]; rem;) {
+            const int q = __ffs(rem) - 1;
+            rem &= rem - 1;
+            if ((rank++ & 3) == sub) {
+              f += dpre[1 + q];
+              for (uint32_t r2 = rem; r2; r2 &= r2 - 1) f += bl[q * k + (__ffs(r2) - 1)];
+            }
           }
-          const uint32_t valid = h.w & 0xffffu;
-          if ((valid >> P) & 1u) {
-            const uint32_t Pv = P ^ full;
-            double val = dw[(h.w >> 17) + __popc(valid & ((1u << Pv) - 1u))];
-            if (parity(u & h.z)) val = -val;
-            const double2 pw = lds[c ^ (h.x & 0x7fffffffu)];
-            ax += val * pw.x;
-            ay += val * pw.y;
-          }
+          const double2 pu = cp[i];
+          ax += f * pu.x;
+          ay += f * pu.y;
         }
       }
       ax = quad_sum(ax);
       ay = quad_sum(ay);
-      if (sub == 0) {
+      if (row && sub == 0) {
+        const double2 pu = cp[i];
         eacc += pu.x * ax + pu.y * ay;
-        if (APPLY) vl[u] = make_double2(old.x + ax, old.y + ay);
+        if (APPLY) st16(vl + phys, dvec2{old.x + ax, old.y + ay});
       }
     }
-    const double s = block_sum<T>(eacc, red);
-    if (threadIdx.x == 0) epart[(size_t)b * estride + t] = s;
-    const int next = item + gridDim.x;
+    const double es = block_sum<T>(eacc, red);
+    if (threadIdx.x == 0) epart[(size_t)b * estride + t] = es;
     if (next >= total) break;
-    const uint32_t nbase = base_of(next);
-    __syncthreads();  // the tile and the list are no longer read
-    if (KT)
-      tm.put(r, lds);
-    else
-      tm.load(lds, psi + ((size_t)(next >> tb) << n), nbase, tileN);
-    stage_blob(next >> tb);  // visible to the next item after the barrier below
-    stage_class(nbase);
-    olds.load(lst, APPLY ? lam + ((size_t)(next >> tb) << n) : nullptr, nbase, nlist, rmw);
-    const int next2 = next + gridDim.x;
-    if (KT && next2 < total) tm.fetch(r, psi + ((size_t)(next2 >> tb) << n), base_of(next2));
-    __syncthreads();
+    __syncthreads();  // cp, the per-tile values and the class block are no longer read
+    stage_blob(next >> tb);
+    stage_class(base_of(next));
+    if (bstride) __syncthreads();  // a re-staged value table is read by the next tile's prep
     item = next;
   }
 }
@@ -1009,15 +993,16 @@ template <int T, int KT, bool APPLY>
 hipError_t exp_t(const LaunchArgs& a, int pidx, int eslot, int first) {
   const DevPass& hp = a.hpasses[pidx];
   const int k = hp.k;
-  const size_t lds = (sizeof(double2) << k) + 16 * size_t(hp.blob_len) + 8 * size_t(hp.stage_len) +
-                     (T / 64) * sizeof(double);
+  const size_t lds = 16 * size_t(hp.ns_max) + 16 * size_t(hp.blob_len) +
+                     8 * (size_t((hp.n_slots + 1) & ~1) + size_t((hp.n_occ + 1) & ~1) + size_t((k + 2) & ~1) + 16) +
+                     4 * size_t(hp.stage_len) + (size_t(2) << k);
   hipError_t e = set_lds(k_exp<T, KT, APPLY>, lds);
   if (e != hipSuccess) return e;
   const int total = a.B << (a.n - k);
   const int grid =
-      KT ? pass_grid(total, resident_grid(k_exp<T, KT, APPLY>, T, lds, a.cu_share), 1 << (a.n - k)) : total;
+      pass_grid(total, resident_grid(k_exp<T, KT, APPLY>, T, lds, a.cu_share), 1 << (a.n - k));
   hipLaunchKernelGGL((k_exp<T, KT, APPLY>), dim3(grid), dim3(T), lds, a.stream, a.passes, pidx,
-                     a.blobs, a.cls, a.list, a.psi, a.lam, a.n, a.amask, a.bmask,
+                     a.blobs, a.cls, a.pairs, a.psi, a.lam, a.n, a.amask, a.bmask,
                      a.epart + (size_t)eslot, a.estride, first, total, a.blob_stride);
   return hipGetLastError();
 }

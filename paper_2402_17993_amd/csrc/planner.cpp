@@ -456,26 +456,8 @@ std::string build_plan(Plan& p, int n, int ne, const double* h1, const double* h
     }
   }
   {
-    // keep tile + blob + staged class list + reduction slots inside one workgroup's LDS:
-    // split passes whose group tables would not fit (same local set, groups in order)
-    std::vector<Plan::Pass> split;
-    for (auto& ps : ex) {
-      const int budget = kLdsBytes - (16 << p.ke) - 8 * max_class_size(p, ps.lmask) - 256;
-      Plan::Pass cur;
-      cur.kind = kExp;
-      cur.lmask = ps.lmask;
-      for (int g : ps.items) {
-        cur.items.push_back(g);
-        if (cur.items.size() > 1 && exp_blob_bytes(p, cur.items) > budget) {
-          cur.items.pop_back();
-          split.push_back(cur);
-          cur.items.assign(1, g);
-        }
-      }
-      if (exp_blob_bytes(p, cur.items) > budget) return "tile too large for the expectation tables";
-      split.push_back(cur);
-    }
-    ex.swap(split);
+    std::string err = split_exp_passes(p, ex);
+    if (!err.empty()) return err;
   }
   // forward/reverse windows whose largest class block would not fit next to the rank table
   // and the compact in-sector vector(s) are halved (same local set, order kept)
@@ -518,37 +500,6 @@ std::string build_plan(Plan& p, int n, int ne, const double* h1, const double* h
 }
 
 namespace {
-
-// Order of groups inside an expectation blob: diagonal, occupation-term groups, plain.
-std::vector<int> blob_order(const Plan& p, const std::vector<int>& items) {
-  std::vector<int> out;
-  for (int g : items)
-    if (g == 0) out.push_back(g);
-  for (int g : items)
-    if (g != 0 && p.groups[g].has_occ) out.push_back(g);
-  for (int g : items)
-    if (g != 0 && !p.groups[g].has_occ) out.push_back(g);
-  return out;
-}
-
-// Words of a blob: header, group headers, one double per valid pattern (plus n per valid
-// pattern for occupation rows), the diagonal table.
-size_t blob_words(const Plan& p, const std::vector<int>& items) {
-  size_t w = ExpBlob::kHeaderWords;
-  for (int g : items) {
-    if (g == 0) {
-      w += 2 * (1 + p.n + p.n * p.n);
-    } else {
-      const size_t nv = __builtin_popcount(p.groups[g].valid);
-      w += 2 * nv;
-      if (p.groups[g].has_occ)
-        w += ExpBlob::kOccWords + 2 * nv * p.n;
-      else
-        w += ExpBlob::kPlainWords;
-    }
-  }
-  return ((w + 3) & ~size_t(3)) + 4;  // slack for the 16-byte alignment of the plain records
-}
 
 // In-sector local compact indices of a tile with local bits lmask, bucketed by the class
 // (alpha, beta electron counts of the global bits): bucket ag * (nbg + 1) + bg.
@@ -600,10 +551,142 @@ std::vector<uint32_t> pair_block(const Plan& p, uint32_t lmask, const std::vecto
   return w;
 }
 
+
+// ---- expectation passes: slots, value tables, class row lists (layouts in ucc_internal.h)
+
+// Pattern of the bits of v at the positions of mask (lowest position -> bit 0).
+uint32_t extract_bits(uint32_t v, uint32_t mask) {
+  uint32_t r = 0;
+  int j = 0;
+  for (uint32_t m = mask; m; m &= m - 1, ++j)
+    if (v & m & (~m + 1u)) r |= 1u << j;
+  return r;
+}
+
+// Slot layout of one expectation pass: the non-diagonal groups with occupation rows first,
+// then the others, each contributing one slot per valid source pattern (ascending pattern).
+struct ExpSlots {
+  bool has_diag = false;
+  std::vector<int> groups;      // slot order
+  std::vector<int> slot_base;   // first slot of each group in `groups`
+  int n_slots = 0, n_occ = 0, n_occ_groups = 0;
+};
+
+ExpSlots exp_slots(const Plan& p, const std::vector<int>& items) {
+  ExpSlots e;
+  for (int g : items)
+    if (g == 0) e.has_diag = true;
+  for (int pass = 0; pass < 2; ++pass)
+    for (int g : items) {
+      if (g == 0 || p.groups[g].has_occ != (pass == 0)) continue;
+      e.groups.push_back(g);
+      e.slot_base.push_back(e.n_slots);
+      e.n_slots += pc32(p.groups[g].valid);
+      if (pass == 0) {
+        e.n_occ = e.n_slots;
+        e.n_occ_groups = (int)e.groups.size();
+      }
+    }
+  return e;
+}
+
+// Words of the value table of a pass with this slot layout and k local bits.
+size_t exp_table_words(const Plan& p, const ExpSlots& e, int k) {
+  size_t w = 16 + e.n_slots + e.n_occ;
+  w = (w + 1) & ~size_t(1);
+  w += 2 * (size_t(e.n_slots) + size_t(e.n_occ) * k + size_t(e.n_occ) * p.n);
+  if (e.has_diag) w += 2 * (1 + size_t(p.n) + size_t(p.n) * p.n + size_t(k) * k);
+  return (w + 3) & ~size_t(3);
+}
+
+// Row lists of one class bucket: for each in-sector target u (by rank), the entries of the
+// groups with occupation rows, then the others (off[i] .. mid[i] .. off[i+1]); an entry names
+// the source rank, the local JW sign and the slot of (group, source pattern).  With count
+// set, only the entries per group are counted.
+void exp_class_rows(const Plan& p, uint32_t L, const ExpSlots& e,
+                    const std::vector<std::pair<uint32_t, uint32_t>>& bucket, std::vector<uint32_t>* off,
+                    std::vector<uint32_t>* mid, std::vector<uint32_t>* ent, std::vector<size_t>* count) {
+  const size_t ns = bucket.size();
+  std::vector<uint32_t> cs(ns);
+  for (size_t i = 0; i < ns; ++i) cs[i] = bucket[i].first;
+  if (count) count->assign(e.groups.size(), 0);
+  auto visit = [&](size_t i, size_t j) {
+    const auto& g = p.groups[e.groups[j]];
+    const uint32_t pv = bucket[i].second ^ g.x;  // local physical offset of the source
+    const uint32_t P = extract_bits(pv, g.x);
+    if (!((g.valid >> P) & 1u)) return;
+    if (count) {
+      (*count)[j] += 1;
+      return;
+    }
+    const uint32_t cv = cs[i] ^ compact_bits(g.x, L);
+    const uint32_t rv = (uint32_t)(std::lower_bound(cs.begin(), cs.end(), cv) - cs.begin());
+    const uint32_t slot = (uint32_t)e.slot_base[j] + (uint32_t)pc32(g.valid & ((1u << P) - 1u));
+    const uint32_t sg = pc32(pv & g.m & L) & 1;
+    ent->push_back(rv | (sg << 15) | (slot << 16));
+  };
+  for (size_t i = 0; i < ns; ++i) {
+    if (off) off->push_back((uint32_t)ent->size());
+    for (size_t j = 0; j < (size_t)e.n_occ_groups; ++j) visit(i, j);
+    if (mid) mid->push_back((uint32_t)ent->size());
+    for (size_t j = e.n_occ_groups; j < e.groups.size(); ++j) visit(i, j);
+  }
+  if (off) off->push_back((uint32_t)ent->size());
+}
+
+// Words of a class block with ns rows and nent entries.
+size_t exp_block_words(size_t ns, size_t nent) { return 2 + (ns + 1) + ns + (ns + 1) / 2 + ns + nent; }
+
+// LDS bytes of an expectation pass (k local bits, largest class ns_max, largest block
+// words, value-table words) beside the per-item tables and 16 waves' reduction slots.
+size_t exp_pass_lds(int k, size_t ns_max, size_t blk_words, size_t table_words, const ExpSlots& e) {
+  return 16 * ns_max + 4 * table_words + 8 * (size_t(e.n_slots) + e.n_occ + k + 2) + 16 * 8 +
+         4 * blk_words + (size_t(2) << k) + 1024;
+}
+
 }  // namespace
 
-int exp_blob_bytes(const Plan& p, const std::vector<int>& groups) {
-  return (int)(4 * blob_words(p, groups));
+std::string split_exp_passes(Plan& p, std::vector<Plan::Pass>& ex) {
+  std::vector<Plan::Pass> out;
+  for (auto& ps : ex) {
+    const int k = pc32(ps.lmask);
+    auto buckets = class_buckets(p, ps.lmask);
+    size_t ns_max = 0;
+    for (auto& b : buckets) ns_max = std::max(ns_max, b.size());
+    // entries each group adds to each class
+    const ExpSlots all = exp_slots(p, ps.items);
+    std::vector<std::vector<size_t>> cnt(buckets.size());
+    for (size_t c = 0; c < buckets.size(); ++c)
+      exp_class_rows(p, ps.lmask, all, buckets[c], nullptr, nullptr, nullptr, &cnt[c]);
+    std::map<int, size_t> pos;
+    for (size_t j = 0; j < all.groups.size(); ++j) pos[all.groups[j]] = j;
+    auto fits = [&](const std::vector<int>& items) {
+      const ExpSlots e = exp_slots(p, items);
+      size_t blk = 0;
+      for (size_t c = 0; c < buckets.size(); ++c) {
+        size_t nent = 0;
+        for (int g : items)
+          if (g != 0) nent += cnt[c][pos[g]];
+        blk = std::max(blk, exp_block_words(buckets[c].size(), nent));
+      }
+      return exp_pass_lds(k, ns_max, blk, exp_table_words(p, e, k), e) <= (size_t)kLdsBytes;
+    };
+    Plan::Pass cur;
+    cur.kind = kExp;
+    cur.lmask = ps.lmask;
+    for (int g : ps.items) {
+      cur.items.push_back(g);
+      if (cur.items.size() > 1 && !fits(cur.items)) {
+        cur.items.pop_back();
+        out.push_back(cur);
+        cur.items.assign(1, g);
+      }
+    }
+    if (!fits(cur.items)) return "tile too large for the expectation tables";
+    out.push_back(cur);
+  }
+  ex.swap(out);
+  return "";
 }
 
 int max_class_size(const Plan& p, uint32_t lmask) {
@@ -629,86 +712,99 @@ void build_tables(const Plan& p, Tables& t) {
     dp.k = pc32(ps.lmask);
     dp.kind = ps.kind;
     if (ps.kind == kExp) {
-      const std::vector<int> order = blob_order(p, ps.items);
-      const size_t words = blob_words(p, order);
+      const int k = dp.k;
+      const ExpSlots e = exp_slots(p, ps.items);
+      const size_t words = exp_table_words(p, e, k);
       std::vector<uint32_t> b(words, 0u);
       auto put_double = [&](size_t w, double v) { std::memcpy(&b[w], &v, sizeof(double)); };
-      int nd = 0, no = 0, npl = 0;
-      for (int g : order) (g == 0 ? nd : p.groups[g].has_occ ? no : npl)++;
-      size_t w = ExpBlob::kHeaderWords;
-      const size_t occ_rec = w;
-      w += ExpBlob::kOccWords * no;
-      w = (w + 3) & ~size_t(3);
-      const size_t plain_rec = w;
-      w += ExpBlob::kPlainWords * npl;
-      b[0] = nd;
-      b[1] = no;
-      b[2] = npl;
-      b[3] = (uint32_t)occ_rec;
-      b[4] = (uint32_t)plain_rec;
-      b[6] = n;
-      int io = 0, ip = 0;
-      for (size_t i = 0; i < order.size(); ++i) {
-        const int gi = order[i];
-        if (gi == 0) continue;
-        const auto& g = p.groups[gi];
-        const size_t a_off = w;
-        int slot = 0;
-        for (int P = 0; P < 16; ++P)
-          if ((g.valid >> P) & 1u) put_double(w + 2 * slot++, g.A[P]);
-        w += 2 * slot;
-        const uint32_t xc = compact_bits(g.x, ps.lmask);
-        if (g.has_occ) {
-          uint32_t* h = &b[occ_rec + ExpBlob::kOccWords * io++];
-          h[0] = xc;
-          h[1] = g.x;
-          h[2] = g.m;
-          h[3] = g.valid;
-          h[4] = pack_positions(g.x);
-          h[5] = pc32(g.x);
-          h[6] = (uint32_t)w;
-          h[7] = (uint32_t)a_off;
-          slot = 0;
-          for (int P = 0; P < 16; ++P)
-            if ((g.valid >> P) & 1u) {
-              for (int r = 0; r < n; ++r) put_double(w + 2 * (slot * n + r), g.B[P * n + r]);
-              ++slot;
-            }
-          w += 2 * slot * n;
-        } else {
-          uint32_t* h = &b[plain_rec + ExpBlob::kPlainWords * ip++];
-          h[0] = xc | (pc32(g.x) == 4 ? 0x80000000u : 0u);
-          h[1] = pack_positions(g.x);
-          h[2] = g.m;
-          h[3] = g.valid | ((uint32_t)a_off << 16);
+      std::vector<int> lbit;  // physical bit of each local compact bit
+      for (uint32_t m = ps.lmask; m; m &= m - 1) lbit.push_back(__builtin_ctz(m));
+      size_t w = 16;
+      const size_t o_mglob = w;
+      w += e.n_slots;
+      const size_t o_xloc = w;
+      w += e.n_occ;
+      w = (w + 1) & ~size_t(1);
+      const size_t o_A = w;
+      w += 2 * size_t(e.n_slots);
+      const size_t o_Bloc = w;
+      w += 2 * size_t(e.n_occ) * k;
+      const size_t o_Bglob = w;
+      w += 2 * size_t(e.n_occ) * n;
+      const size_t o_diag = w;
+      b[0] = e.n_slots;
+      b[1] = e.n_occ;
+      b[2] = e.has_diag ? 1u : 0u;
+      b[3] = k;
+      b[4] = (uint32_t)o_mglob;
+      b[5] = (uint32_t)o_xloc;
+      b[6] = (uint32_t)o_A;
+      b[7] = (uint32_t)o_Bloc;
+      b[8] = (uint32_t)o_Bglob;
+      b[9] = (uint32_t)o_diag;
+      b[10] = n;
+      for (size_t j = 0; j < e.groups.size(); ++j) {
+        const auto& g = p.groups[e.groups[j]];
+        int slot = e.slot_base[j];
+        for (int P = 0; P < 16; ++P) {
+          if (!((g.valid >> P) & 1u)) continue;
+          b[o_mglob + slot] = g.m & ~ps.lmask;
+          put_double(o_A + 2 * size_t(slot), g.A[P]);
+          if (slot < e.n_occ) {
+            b[o_xloc + slot] = compact_bits(g.x, ps.lmask);
+            for (int q = 0; q < k; ++q)
+              put_double(o_Bloc + 2 * (size_t(slot) * k + q), g.B[P * n + lbit[q]]);
+            for (int r = 0; r < n; ++r)
+              if (!((ps.lmask >> r) & 1u)) put_double(o_Bglob + 2 * (size_t(slot) * n + r), g.B[P * n + r]);
+          }
+          ++slot;
         }
       }
-      b[5] = (uint32_t)w;
-      if (nd) {
-        put_double(w, p.diag_c0);
-        for (int r = 0; r < n; ++r) put_double(w + 2 * (1 + r), p.diag_a[r]);
-        for (int i = 0; i < n * n; ++i) put_double(w + 2 * (1 + n + i), p.diag_b[i]);
+      if (e.has_diag) {
+        put_double(o_diag, p.diag_c0);
+        for (int r = 0; r < n; ++r) put_double(o_diag + 2 * (1 + r), p.diag_a[r]);
+        for (int i = 0; i < n * n; ++i) put_double(o_diag + 2 * (1 + n + i), p.diag_b[i]);
+        const size_t o_bl = o_diag + 2 * (1 + n + size_t(n) * n);
+        for (int q = 0; q < k; ++q)
+          for (int q2 = q + 1; q2 < k; ++q2)
+            put_double(o_bl + 2 * (size_t(q) * k + q2), p.diag_b[lbit[q] * n + lbit[q2]]);
       }
       dp.first = 0;
-      dp.count = (int)order.size();
+      dp.count = (int)ps.items.size();
+      dp.n_slots = e.n_slots;
+      dp.n_occ = e.n_occ;
+      dp.has_diag = e.has_diag ? 1 : 0;
       dp.blob_off = (int)(t.blob.size() / 4);
       dp.blob_len = (int)(words / 4);
       t.blob.insert(t.blob.end(), b.begin(), b.end());
-      // in-sector tile lists, bucketed by the (alpha, beta) electron count of the global bits
+      // class blocks: rows of in-sector targets with their (source, sign, slot) entries
       int nbg = 0;
       auto buckets = class_buckets(p, ps.lmask, &nbg);
       dp.cls_base = (int)t.cls.size() / 2;
       dp.nbeta_g = nbg;
       dp.stage_len = 0;
+      dp.ns_max = 0;
       for (auto& bk : buckets) {
-        dp.stage_len = std::max(dp.stage_len, (int)bk.size());
-        t.cls.push_back((int32_t)(t.list.size() / 2));
-        t.cls.push_back((int32_t)bk.size());
-        for (auto& e : bk) {
-          t.list.push_back(e.first);
-          t.list.push_back(e.second);
-        }
+        const size_t ns = bk.size();
+        std::vector<uint32_t> off, mid, ent;
+        exp_class_rows(p, ps.lmask, e, bk, &off, &mid, &ent, nullptr);
+        std::vector<uint32_t> blk;
+        blk.push_back((uint32_t)ns);
+        blk.push_back((uint32_t)ent.size());
+        blk.insert(blk.end(), off.begin(), off.end());
+        blk.insert(blk.end(), mid.begin(), mid.end());
+        for (size_t i = 0; i < ns; i += 2)
+          blk.push_back(bk[i].first | (i + 1 < ns ? bk[i + 1].first << 16 : 0u));
+        for (size_t i = 0; i < ns; ++i) blk.push_back(bk[i].second);
+        blk.insert(blk.end(), ent.begin(), ent.end());
+        while (t.pairs.size() % 4) t.pairs.push_back(0u);  // 16-byte aligned blocks
+        t.cls.push_back((int32_t)t.pairs.size());
+        t.cls.push_back((int32_t)blk.size());
+        dp.stage_len = std::max(dp.stage_len, (int)blk.size());
+        dp.ns_max = std::max(dp.ns_max, (int)ns);
+        t.pairs.insert(t.pairs.end(), blk.begin(), blk.end());
       }
+      dp.stage_len = (dp.stage_len + 3) & ~3;
     } else {
       dp.first = (int)t.exc.size();
       dp.count = (int)ps.items.size();

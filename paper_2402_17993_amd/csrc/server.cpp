@@ -63,7 +63,7 @@ bool batch_compatible(const ucc_ctx* a, const ucc_ctx* b) {
   const Tables& s = a->tab;
   const Tables& t = b->tab;
   return same_bytes(s.passes, t.passes) && same_bytes(s.exc, t.exc) && same_bytes(s.pairs, t.pairs) &&
-         same_bytes(s.cls, t.cls) && same_bytes(s.list, t.list) && s.blob.size() == t.blob.size();
+         same_bytes(s.cls, t.cls) && s.blob.size() == t.blob.size();
 }
 
 size_t entry_footprint(const ucc_ctx* c) {

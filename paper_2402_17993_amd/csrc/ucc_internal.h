@@ -53,26 +53,28 @@ constexpr int kMaxPassExc = 256;  // excitations per forward/reverse pass (stage
 // Only in-sector amplitudes can be non-zero, so only these pairs change anything; a
 // workgroup holds the in-sector amplitudes of its tile in LDS by rank.
 
-// Blob of one expectation pass: uint32 words, copied into LDS behind the tile; every
-// double sits at an even word offset and every record at a 16-byte boundary.
-//   [0] n_diag (0 or 1)  [1] n_occ  [2] n_plain  [3] word offset of the occ records
-//   [4] word offset of the plain records  [5] word offset of the diagonal table
-//   [6] n_qubits  [7] 0
-//   occ records (groups with occupation-number terms), 8 words each:
-//     {compact x, physical x, physical parity mask m, valid-pattern mask,
-//      ascending physical support positions (5 bits each), support size,
-//      word offset of the occupation rows, word offset of the A values}
-//   plain records (groups without them), 4 words each:
-//     {compact x | (support size == 4) << 31, support positions, parity mask m,
-//      valid-pattern mask | word offset of the A values << 16}
-//   A values: one double per valid support pattern, in pattern order, so the value of a
-//     valid source pattern P sits at slot popcount(valid & ((1 << P) - 1))
-//   occupation rows: n doubles per valid pattern of an occ group (same slots)
-//   diagonal: c0, a[n], b[n*n] (if n_diag)
-struct ExpBlob {
-  static constexpr int kHeaderWords = 8;
-  static constexpr int kOccWords = 8;
-  static constexpr int kPlainWords = 4;
+// Value table ("blob") of one expectation pass: uint32 words, doubles at even offsets.
+// Slots: one per (non-diagonal group, valid source pattern P), groups with occupation rows
+// first (slots [0, n_occ)), in ascending pattern order within a group.
+//   [0] n_slots [1] n_occ [2] has_diag [3] k [4] off mglob [5] off xloc [6] off A
+//   [7] off Bloc [8] off Bglob [9] off diag [10] n_qubits [11..15] 0
+//   mglob[n_slots]: physical global part of the group's parity mask m
+//   xloc[n_occ]:    compact local x mask of the slot's group
+//   A[n_slots]:     A_g[P]
+//   Bloc[n_occ][k]: B_g[P][r] for the local bits r in compact order (0 on x)
+//   Bglob[n_occ][n]: B_g[P][r] for the global bits r (physical order; 0 on local bits)
+//   diag (has_diag): c0, a[n], b[n*n] (physical, b[r*n+s] for r < s), bl[k*k] (the local
+//     couplings b in compact order, [j*k+j'] for j < j')
+// so that for a source v = u ^ x_g with pattern P
+//   <u|H_g|v> = (-1)^popcount(v & m_g) (A_g[P] + sum_{r not in x_g} B_g[P][r] n_r(v)).
+// Class block of one expectation pass for one tile class: uint32 words
+//   [0] ns  [1] nent  [2 .. 2+ns] off (ns+1)  then mid (ns)  then the in-sector compact
+//   indices (ceil(ns/2) words, two uint16 each, by rank)  then their local physical offsets
+//   (ns)  then nent entries.  Row i (the target of rank i) owns entries off[i] .. off[i+1]-1;
+//   those before mid[i] use slots with occupation rows.  Entry: source rank (bits 0-14),
+//   parity of the source's local bits over m_g (bit 15), slot (bits 16-31).
+struct ExpTables {
+  static constexpr int kHeaderWords = 16;
 };
 
 struct DevPass {
@@ -82,13 +84,16 @@ struct DevPass {
   int32_t kind;     // PassKind
   int32_t first;    // first record in DevExc[] (fwd/rev) or DevGroup[] (exp)
   int32_t count;    // records in this pass
-  int32_t cls_base; // first class entry of this pass (int2): exp -> (list offset, count),
-                    // fwd/rev -> (pair-block word offset, word count)
+  int32_t cls_base; // first class entry of this pass (int2): (class-block word offset, words)
   int32_t nbeta_g;  // number of beta bits among the global bits (class index stride - 1)
   int32_t blob_off; // exp: first uint4 of the pass's blob
   int32_t blob_len; // exp: blob length in uint4
-  int32_t stage_len; // exp: largest class list (entries); fwd/rev: largest block (words)
-  int32_t ns_max;    // fwd/rev: largest in-sector count of a tile class
+  int32_t stage_len; // largest class block of the pass (words)
+  int32_t ns_max;    // largest in-sector count of a tile class
+  int32_t n_slots;   // exp: slots of the value table
+  int32_t n_occ;     // exp: slots with occupation rows
+  int32_t has_diag;  // exp: the diagonal group is in this pass
+  int32_t pad;
 };
 
 // Host-side plan: everything ucc_build derives from the inputs.
@@ -143,17 +148,17 @@ struct Plan {
 struct Tables {
   std::vector<DevPass> passes;
   std::vector<DevExc> exc;
-  std::vector<uint32_t> pairs;  // forward/reverse pair-list blocks
-  std::vector<uint32_t> blob;   // expectation-pass blobs (multiple of 4 words each)
-  std::vector<int32_t> cls;     // pairs (offset, count)
-  std::vector<uint32_t> list;   // pairs (compact c, physical local offset)
+  std::vector<uint32_t> pairs;  // class blocks of every pass
+  std::vector<uint32_t> blob;   // expectation-pass value tables (multiple of 4 words each)
+  std::vector<int32_t> cls;     // pairs (class-block word offset, word count)
 };
 
 // LDS limit of one workgroup on gfx950 and what an expectation pass may spend on its blob.
 constexpr int kLdsBytes = 163840;
 constexpr int kStageBytes = 12288;  // static LDS of a forward/reverse pass (records, cos/sin)
-int exp_blob_bytes(const Plan& p, const std::vector<int>& groups);
 int max_class_size(const Plan& p, uint32_t lmask);
+// Split expectation cover passes so that each pass's tables fit one workgroup's LDS.
+std::string split_exp_passes(Plan& p, std::vector<Plan::Pass>& ex);
 int max_pair_block_words(const Plan& p, uint32_t lmask, const std::vector<int>& items);
 
 // planner.cpp
