@@ -64,7 +64,7 @@ typedef struct {
   int32_t block_threads_fwd; /* per-kind workgroup size (forward, expectation/apply-H, */
   int32_t block_threads_exp; /* reverse); overrides block_threads for that kind */
   int32_t block_threads_rev;
-  int32_t tile_qubits_exp;   /* k of expectation / apply-H passes (4..13) */
+  int32_t tile_qubits_exp;   /* k of expectation / apply-H passes (4..14) */
   int32_t autotune;          /* 1: time the candidate tile sizes and workgroup sizes of the
                                 kinds left automatic on this device at batch max(1, max_batch)
                                 during ucc_build and keep the fastest (results are cached per

@@ -322,8 +322,8 @@ ucc_status ucc_build(int32_t n_qubits, int32_t n_elec, const double* h1, const d
   // one complex128 tile of 2^k amplitudes (two for the reverse sweep) must fit in 160 KB of LDS
   if (o.tile_qubits && (o.tile_qubits < 4 || o.tile_qubits > 14))
     return fail(UCC_EINVAL, "tile_qubits must be 0 or in [4, 14]");
-  if (o.tile_qubits_exp && (o.tile_qubits_exp < 4 || o.tile_qubits_exp > 13))
-    return fail(UCC_EINVAL, "tile_qubits_exp must be 0 or in [4, 13]");
+  if (o.tile_qubits_exp && (o.tile_qubits_exp < 4 || o.tile_qubits_exp > 14))
+    return fail(UCC_EINVAL, "tile_qubits_exp must be 0 or in [4, 14]");
   if (o.tile_qubits_rev && (o.tile_qubits_rev < 4 || o.tile_qubits_rev > 13))
     return fail(UCC_EINVAL, "tile_qubits_rev must be 0 or in [4, 13]");
   for (int t : {o.block_threads, o.block_threads_fwd, o.block_threads_exp, o.block_threads_rev})

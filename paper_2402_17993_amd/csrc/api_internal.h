@@ -43,7 +43,7 @@ struct Profiler {
 };
 
 struct Tuning {
-  int kf = 14, ke = 13, kr = 13, tf = 1024, te = 1024, tr = 512, launch_mode = 1;
+  int kf = 14, ke = 14, kr = 13, tf = 1024, te = 1024, tr = 512, launch_mode = 1;
 };
 
 }  // namespace ucc

@@ -728,13 +728,18 @@ __global__ __launch_bounds__(T) LDS_BOUND_OCCUPANCY void k_exp(
     blob_b = key;
   };
   int staged = -1;
+  const uint32_t* __restrict__ gent = nullptr;  // the staged class's entries (in memory)
   auto base_of = [&](int it) { return dep(it & tmask, ps.gmask); };
   auto vec_of = [&](int it) { return psi + ((size_t)(it >> tb) << n); };
   auto stage_class = [&](uint32_t base) {
     const int cl = tile_class(base, amask, bmask, ps.nbeta_g);
     if (cl != staged) {
       const int2 bl = pcls[ps.cls_base + cl];
-      stage_sc_class<T, true>(blk, rtab, blocks + bl.x, bl.y, tileN);
+      const uint32_t* src = blocks + bl.x;
+      const int ns = (int)src[0];
+      const int words = (3 + 3 * ns + ((ns + 1) >> 1) + 3) & ~3;
+      stage_sc_class<T, true>(blk, rtab, src, words, tileN);
+      gent = src + words;
       staged = cl;
     }
   };
@@ -804,7 +809,7 @@ __global__ __launch_bounds__(T) LDS_BOUND_OCCUPANCY void k_exp(
     const uint32_t* mid = off + ns + 1;
     const uint16_t* sl = reinterpret_cast<const uint16_t*>(mid + ns);
     const uint32_t* sphys = mid + ns + ((ns + 1) >> 1);
-    const uint32_t* ent = sphys + ns;
+    const uint32_t* __restrict__ ent = gent;
     double eacc = 0.0;
     for (int i0 = 0; i0 < ns; i0 += T / 4) {
       const int i = i0 + ((int)threadIdx.x >> 2);
@@ -815,9 +820,10 @@ __global__ __launch_bounds__(T) LDS_BOUND_OCCUPANCY void k_exp(
       if (row) {
         phys = base | sphys[i];
         if (APPLY && !first && sub == 0) old = ld16(vl + phys);
-        const int e0 = (int)off[i], e1 = (int)mid[i], e2 = (int)off[i + 1];
-        for (int e = e0 + sub; e < e1; e += 4) {  // groups with occupation rows
-          const uint32_t en = ent[e];
+        // lane `sub` takes every fourth 16-byte chunk of four entries of the row
+        const uint4* __restrict__ e4 = reinterpret_cast<const uint4*>(ent);
+        const int q0 = (int)off[i] >> 2, q1 = (int)mid[i] >> 2, q2 = (int)off[i + 1] >> 2;
+        auto occ_entry = [&](uint32_t en) {  // groups with occupation rows
           const uint32_t rv = en & 0x7fffu, slot = en >> 16;
           const double* br = Bloc + (size_t)slot * k;
           double occ = 0.0;
@@ -827,14 +833,26 @@ __global__ __launch_bounds__(T) LDS_BOUND_OCCUPANCY void k_exp(
           const double2 pv = cp[rv];
           ax += val * pv.x;
           ay += val * pv.y;
-        }
-        for (int e = e1 + sub; e < e2; e += 4) {
-          const uint32_t en = ent[e];
-          const uint32_t rv = en & 0x7fffu;
+        };
+        auto plain_entry = [&](uint32_t en) {
           const double val = (en & 0x8000u) ? -t1[en >> 16] : t1[en >> 16];
-          const double2 pv = cp[rv];
+          const double2 pv = cp[en & 0x7fffu];
           ax += val * pv.x;
           ay += val * pv.y;
+        };
+        for (int q = q0 + sub; q < q1; q += 4) {
+          const uint4 E = e4[q];
+          occ_entry(E.x);
+          occ_entry(E.y);
+          occ_entry(E.z);
+          occ_entry(E.w);
+        }
+        for (int q = q1 + sub; q < q2; q += 4) {
+          const uint4 E = e4[q];
+          plain_entry(E.x);
+          plain_entry(E.y);
+          plain_entry(E.z);
+          plain_entry(E.w);
         }
         if (has_diag) {  // c0 + sum_r a_r n_r + sum_{r<s} b_rs n_r n_s; set bits split by rank
           double f = sub == 0 ? dpre[0] : 0.0;
@@ -1031,6 +1049,8 @@ hipError_t rev_k(const LaunchArgs& a, int pidx) {
 template <int T, bool APPLY>
 hipError_t exp_k(const LaunchArgs& a, int pidx, int eslot, int first) {
   const int k = a.hpasses[pidx].k;
+  if constexpr (T >= 512)
+    if (k == 14) return exp_t<T, 14, APPLY>(a, pidx, eslot, first);
   if (k == 13) return exp_t<T, 13, APPLY>(a, pidx, eslot, first);
   if (k == 12) return exp_t<T, 12, APPLY>(a, pidx, eslot, first);
   return exp_t<T, 0, APPLY>(a, pidx, eslot, first);

@@ -570,23 +570,26 @@ struct ExpSlots {
   std::vector<int> groups;      // slot order
   std::vector<int> slot_base;   // first slot of each group in `groups`
   int n_slots = 0, n_occ = 0, n_occ_groups = 0;
+  int pad_slot = 0;  // value 0, no occupation terms: fills rows to whole 16-byte chunks
 };
 
 ExpSlots exp_slots(const Plan& p, const std::vector<int>& items) {
   ExpSlots e;
   for (int g : items)
     if (g == 0) e.has_diag = true;
-  for (int pass = 0; pass < 2; ++pass)
+  for (int pass = 0; pass < 2; ++pass) {
     for (int g : items) {
       if (g == 0 || p.groups[g].has_occ != (pass == 0)) continue;
       e.groups.push_back(g);
       e.slot_base.push_back(e.n_slots);
       e.n_slots += pc32(p.groups[g].valid);
-      if (pass == 0) {
-        e.n_occ = e.n_slots;
-        e.n_occ_groups = (int)e.groups.size();
-      }
     }
+    if (pass == 0) {  // the zero slot that pads rows closes the occupation slots
+      e.pad_slot = e.n_slots++;
+      e.n_occ = e.n_slots;
+      e.n_occ_groups = (int)e.groups.size();
+    }
+  }
   return e;
 }
 
@@ -625,17 +628,24 @@ void exp_class_rows(const Plan& p, uint32_t L, const ExpSlots& e,
     const uint32_t sg = pc32(pv & g.m & L) & 1;
     ent->push_back(rv | (sg << 15) | (slot << 16));
   };
+  auto pad = [&]() {  // both parts of a row start on a 16-byte boundary
+    if (ent)
+      while (ent->size() % 4) ent->push_back((uint32_t)e.pad_slot << 16);
+  };
   for (size_t i = 0; i < ns; ++i) {
     if (off) off->push_back((uint32_t)ent->size());
     for (size_t j = 0; j < (size_t)e.n_occ_groups; ++j) visit(i, j);
+    pad();
     if (mid) mid->push_back((uint32_t)ent->size());
     for (size_t j = e.n_occ_groups; j < e.groups.size(); ++j) visit(i, j);
+    pad();
   }
   if (off) off->push_back((uint32_t)ent->size());
 }
 
-// Words of a class block with ns rows and nent entries.
-size_t exp_block_words(size_t ns, size_t nent) { return 2 + (ns + 1) + ns + (ns + 1) / 2 + ns + nent; }
+// Words of the part of a class block with ns rows that a workgroup stages in LDS (header,
+// row offsets, in-sector indices and offsets); the entries behind it are read from memory.
+size_t exp_block_words(size_t ns) { return (2 + (ns + 1) + ns + (ns + 1) / 2 + ns + 3) & ~size_t(3); }
 
 // LDS bytes of an expectation pass (k local bits, largest class ns_max, largest block
 // words, value-table words) beside the per-item tables and 16 waves' reduction slots.
@@ -653,22 +663,9 @@ std::string split_exp_passes(Plan& p, std::vector<Plan::Pass>& ex) {
     auto buckets = class_buckets(p, ps.lmask);
     size_t ns_max = 0;
     for (auto& b : buckets) ns_max = std::max(ns_max, b.size());
-    // entries each group adds to each class
-    const ExpSlots all = exp_slots(p, ps.items);
-    std::vector<std::vector<size_t>> cnt(buckets.size());
-    for (size_t c = 0; c < buckets.size(); ++c)
-      exp_class_rows(p, ps.lmask, all, buckets[c], nullptr, nullptr, nullptr, &cnt[c]);
-    std::map<int, size_t> pos;
-    for (size_t j = 0; j < all.groups.size(); ++j) pos[all.groups[j]] = j;
+    const size_t blk = exp_block_words(ns_max);
     auto fits = [&](const std::vector<int>& items) {
       const ExpSlots e = exp_slots(p, items);
-      size_t blk = 0;
-      for (size_t c = 0; c < buckets.size(); ++c) {
-        size_t nent = 0;
-        for (int g : items)
-          if (g != 0) nent += cnt[c][pos[g]];
-        blk = std::max(blk, exp_block_words(buckets[c].size(), nent));
-      }
       return exp_pass_lds(k, ns_max, blk, exp_table_words(p, e, k), e) <= (size_t)kLdsBytes;
     };
     Plan::Pass cur;
@@ -760,6 +757,7 @@ void build_tables(const Plan& p, Tables& t) {
           ++slot;
         }
       }
+      b[o_xloc + e.pad_slot] = 0xffffffffu;
       if (e.has_diag) {
         put_double(o_diag, p.diag_c0);
         for (int r = 0; r < n; ++r) put_double(o_diag + 2 * (1 + r), p.diag_a[r]);
@@ -796,11 +794,12 @@ void build_tables(const Plan& p, Tables& t) {
         for (size_t i = 0; i < ns; i += 2)
           blk.push_back(bk[i].first | (i + 1 < ns ? bk[i + 1].first << 16 : 0u));
         for (size_t i = 0; i < ns; ++i) blk.push_back(bk[i].second);
+        while (blk.size() % 4) blk.push_back(0u);  // entries on a 16-byte boundary
         blk.insert(blk.end(), ent.begin(), ent.end());
         while (t.pairs.size() % 4) t.pairs.push_back(0u);  // 16-byte aligned blocks
         t.cls.push_back((int32_t)t.pairs.size());
         t.cls.push_back((int32_t)blk.size());
-        dp.stage_len = std::max(dp.stage_len, (int)blk.size());
+        dp.stage_len = std::max(dp.stage_len, (int)exp_block_words(ns));
         dp.ns_max = std::max(dp.ns_max, (int)ns);
         t.pairs.insert(t.pairs.end(), blk.begin(), blk.end());
       }

@@ -38,11 +38,11 @@ Tuning choose_tuning(int n, int K, int batch, const ucc_options& o) {
   (void)batch;
   Tuning t;
   t.kf = o.tile_qubits ? o.tile_qubits : std::min(n, 14);
-  t.ke = o.tile_qubits_exp ? o.tile_qubits_exp : std::min(n, 13);
+  t.ke = o.tile_qubits_exp ? o.tile_qubits_exp : std::min(n, 14);
   t.kr = o.tile_qubits_rev ? o.tile_qubits_rev : std::min(n, 13);
   // One-tile states are latency-bound: small workgroups.  Multi-tile states: large
-  // workgroups keep a 2^14 forward tile in 16 registers per thread and give the apply-H
-  // gather its lanes; the two-vector reverse tile takes 512.
+  // workgroups keep a 2^14 tile in 16 registers per thread and give the apply-H rows their
+  // lanes; the two-vector reverse tile takes 512.
   const bool small = n <= 12;
   t.tf = pick(o.block_threads_fwd, o.block_threads, small ? 256 : 1024);
   t.te = pick(o.block_threads_exp, o.block_threads, small ? 256 : 1024);
@@ -84,7 +84,7 @@ ucc_status autotune(ucc_ctx* c, int B) {
     }
   }
   const std::vector<int> kfs = tile_candidates(o.tile_qubits, p.n, {14, 13});
-  const std::vector<int> kes = tile_candidates(o.tile_qubits_exp, p.n, {13, 12});
+  const std::vector<int> kes = tile_candidates(o.tile_qubits_exp, p.n, {14, 13});
   const std::vector<int> krs = tile_candidates(o.tile_qubits_rev, p.n, {13, 12});
   std::vector<int> ts;
   for (int t : {256, 512, 1024})

@@ -70,9 +70,12 @@ constexpr int kMaxPassExc = 256;  // excitations per forward/reverse pass (stage
 // Class block of one expectation pass for one tile class: uint32 words
 //   [0] ns  [1] nent  [2 .. 2+ns] off (ns+1)  then mid (ns)  then the in-sector compact
 //   indices (ceil(ns/2) words, two uint16 each, by rank)  then their local physical offsets
-//   (ns)  then nent entries.  Row i (the target of rank i) owns entries off[i] .. off[i+1]-1;
-//   those before mid[i] use slots with occupation rows.  Entry: source rank (bits 0-14),
-//   parity of the source's local bits over m_g (bit 15), slot (bits 16-31).
+//   (ns)  then zero words up to a 16-byte boundary  then nent entries (everything before the
+//   entries is staged in LDS; the entries are read from memory).  Row i (the target of rank
+//   i) owns entries off[i] .. off[i+1]-1; those before mid[i] use slots with occupation rows;
+//   both parts start on 16-byte boundaries, filled up with entries of the zero slot (the last
+//   occupation slot, value 0, x mask all ones).  Entry: source rank (bits 0-14), parity of
+//   the source's local bits over m_g (bit 15), slot (bits 16-31).
 struct ExpTables {
   static constexpr int kHeaderWords = 16;
 };
@@ -88,7 +91,7 @@ struct DevPass {
   int32_t nbeta_g;  // number of beta bits among the global bits (class index stride - 1)
   int32_t blob_off; // exp: first uint4 of the pass's blob
   int32_t blob_len; // exp: blob length in uint4
-  int32_t stage_len; // largest class block of the pass (words)
+  int32_t stage_len; // largest class block of the pass (words; exp: its staged part)
   int32_t ns_max;    // largest in-sector count of a tile class
   int32_t n_slots;   // exp: slots of the value table
   int32_t n_occ;     // exp: slots with occupation rows

@@ -171,7 +171,7 @@ def test_16q_autotuned_context(ucc):
     ctx = ucc.Context(n, ne, h1, h2, exc, max_batch=4, autotune=True)
     info = ctx.plan_info()
     assert info["autotuned"] == 1
-    assert info["tile_qubits"] in (13, 14) and info["tile_qubits_exp"] in (12, 13)
+    assert info["tile_qubits"] in (13, 14) and info["tile_qubits_exp"] in (13, 14)
     assert info["tile_qubits_rev"] in (12, 13)
     e, gr = ctx.energy_grad(th)
     e_ref, g_ref = oracle_eg(n, ne, h, g, exc, th[3])
