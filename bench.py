@@ -89,6 +89,86 @@ def served_same_workload(ucc, h1, h2, exc, thetas, iters=4):
     return BATCH * (iters + 1) / wall
 
 
+def single_latency(ucc, torch, n, ne, reps=30):
+    """Median latency of one E + grad evaluation (B = 1, theta on the device) at n qubits,
+    integrals from seed 0, theta ~ U(-0.05, 0.05) from seed 1."""
+    from paper_2402_17993_amd.inputs import make_integrals, make_thetas, uccsd_excitations
+
+    h1, h2 = make_integrals(n // 2, 0)
+    exc = uccsd_excitations(n, ne)
+    ctx = ucc.Context(n, ne, h1, h2, exc, device=0)
+    th = torch.tensor(make_thetas(len(exc), 1, 0.05), device="cuda:0", dtype=torch.float64)
+    for _ in range(3):
+        ctx.energy_grad(th)
+    torch.cuda.synchronize()
+    ts = []
+    for _ in range(reps):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        ctx.energy_grad(th)
+        b.record()
+        b.synchronize()
+        ts.append(a.elapsed_time(b))
+    info = ctx.plan_info()
+    ctx.close()
+    return {"us_p50": 1e3 * float(np.percentile(ts, 50)), "us_p99": 1e3 * float(np.percentile(ts, 99)),
+            "passes_fwd_exp_rev": [info["n_fwd_passes"], info["n_exp_passes"], info["n_rev_passes"]]}
+
+
+def large_state(ucc, torch, n=26, ne=14):
+    """One E + grad evaluation of a 1 GiB state (26 qubits, 14 electrons, K = 2478), integrals
+    from seed 0, theta ~ U(-0.05, 0.05) from seed 1; per-kind HIP-event times and the
+    algorithmic HBM rate of the whole evaluation."""
+    from paper_2402_17993_amd.inputs import make_integrals, make_thetas, uccsd_excitations
+
+    h1, h2 = make_integrals(n // 2, 0)
+    exc = uccsd_excitations(n, ne)
+    t0 = time.perf_counter()
+    ctx = ucc.Context(n, ne, h1, h2, exc, device=0)
+    build_s = time.perf_counter() - t0
+    th = torch.tensor(make_thetas(len(exc), 1, 0.05), device="cuda:0", dtype=torch.float64)
+    ctx.energy_grad(th)
+    torch.cuda.synchronize()
+    ctx.profile(True)
+    ctx.profile_read(reset=True)
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    ctx.energy_grad(th)
+    b.record()
+    b.synchronize()
+    st = ctx.profile_read(reset=True)
+    ctx.profile(False)
+    info = ctx.plan_info()
+    ctx.close()
+    ms = a.elapsed_time(b)
+    byt = sum(v["bytes"] for v in st.values())
+    return {"n_qubits": n, "n_elec": ne, "n_exc": len(exc), "n_pauli": info["n_pauli"],
+            "ms": ms, "GBps": byt / (ms * 1e-3) / 1e9, "frac": byt / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+            "passes_fwd_exp_rev": [info["n_fwd_passes"], info["n_exp_passes"], info["n_rev_passes"]],
+            "kernels_ms": {k: v["ms"] for k, v in st.items() if v["launches"]},
+            "plan_build_s": build_s}
+
+
+def cpu_small():
+    """The oracle per E + grad evaluation at 8 and 16 qubits (one thread)."""
+    from threadpoolctl import threadpool_limits
+
+    from oracle import ansatz, hamiltonian
+    from paper_2402_17993_amd.inputs import make_integrals, make_thetas, uccsd_excitations
+
+    out = {}
+    with threadpool_limits(limits=1):
+        for n, ne, scale in ((8, 4, 0.1), (16, 8, 0.05)):
+            h1, h2 = make_integrals(n // 2, 0)
+            exc = uccsd_excitations(n, ne)
+            th = make_thetas(len(exc), 1, scale)
+            t0 = time.perf_counter()
+            h, g = hamiltonian.spin_orbital_integrals(h1, h2)
+            ansatz.energy_and_gradient(h, g, n, (1 << ne) - 1, exc, th)
+            out[f"{n}q_s_per_eval"] = time.perf_counter() - t0
+    return out
+
+
 MIX = {"monomer": (12, 8), "dimer": (18, 10), "trimer": (24, 14)}
 
 
@@ -162,6 +242,8 @@ def main():
     ap.add_argument("--launch-mode", type=int, default=0)
     ap.add_argument("--no-autotune", action="store_true",
                     help="use the fixed tuning table instead of timing the candidates")
+    ap.add_argument("--no-extra", action="store_true",
+                    help="skip the one-at-a-time rate, the B = 1 latencies and the 26-qubit evaluation")
     ap.add_argument("--serve-arrivals", type=int, default=70,
                     help="arrivals of the serving trace (0 = skip the serving legs)")
     ap.add_argument("--copy-calibration", type=float, default=0.0, metavar="GIB",
@@ -234,7 +316,6 @@ def main():
 
     ms_per_step = 1e3 * wall_plain / args.steps
     value = BATCH * args.steps / wall_plain
-    plain = one_at_a_time(ctx, td)
 
     dom = max((k for k in stats if stats[k]["launches"]), key=lambda k: stats[k]["ms"])
     d = stats[dom]
@@ -267,7 +348,8 @@ def main():
                    "n_exc": K, "n_pauli": info["n_pauli"], "n_groups": info["n_groups"],
                    "passes_fwd_exp_rev": [info["n_fwd_passes"], info["n_exp_passes"],
                                           info["n_rev_passes"]],
-                   "tile_qubits": [info["tile_qubits"], info["tile_qubits_rev"]],
+                   "tile_qubits_fwd_exp_rev": [info["tile_qubits"], info["tile_qubits_exp"],
+                                               info["tile_qubits_rev"]],
                    "block_threads_fwd_exp_rev": [info["block_threads_fwd"],
                                                  info["block_threads_exp"],
                                                  info["block_threads_rev"]],
@@ -284,12 +366,18 @@ def main():
                     for k, v in stats.items() if v["launches"]},
         "parity": {"max_abs_dE": de, "max_abs_dgrad": dg, "entries": sorted(gold["entries"])},
     }
-    out["one_at_a_time_evals_per_s"] = plain
+    if not args.no_extra:
+        out["one_at_a_time_evals_per_s"] = one_at_a_time(ctx, td)
+        out["latency_B1"] = {f"{n}q": single_latency(ucc, torch, n, ne)
+                             for n, ne in ((8, 4), (12, 8), (16, 8))}
+        out["large_26q"] = large_state(ucc, torch)
     if args.serve_arrivals > 0:
         out["served_evals_per_s"] = served_same_workload(ucc, h1, h2, exc, thetas)
         out["serving_mix"] = serving_mix(ucc, args.serve_arrivals)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline()
+        if not args.no_extra:
+            out["cpu_baseline_small"] = cpu_small()
     print(json.dumps(out))
 
 
