@@ -800,10 +800,6 @@ __global__ __launch_bounds__(T) LDS_BOUND_OCCUPANCY void k_exp(
     }
     __syncthreads();  // cp and the per-tile values complete
     const int next = item + gridDim.x;
-    if (RP && next < total) {
-      tm.refresh();
-      tm.fetch(r, vec_of(next), base_of(next));
-    }
     const int ns = (int)blk[0];
     const uint32_t* off = blk + 2;
     const uint32_t* mid = off + ns + 1;
@@ -877,6 +873,12 @@ __global__ __launch_bounds__(T) LDS_BOUND_OCCUPANCY void k_exp(
         eacc += pu.x * ax + pu.y * ay;
         if (APPLY) st16(vl + phys, dvec2{old.x + ax, old.y + ay});
       }
+    }
+    // The next tile is requested after the row walk: its entry and lambda loads then never
+    // wait behind the tile's loads (vector-memory counters retire in issue order).
+    if (RP && next < total) {
+      tm.refresh();
+      tm.fetch(r, vec_of(next), base_of(next));
     }
     const double es = block_sum<T>(eacc, red);
     if (threadIdx.x == 0) epart[(size_t)b * estride + t] = es;
