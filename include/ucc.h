@@ -57,7 +57,11 @@ typedef struct {
   int32_t max_batch;         /* theta vectors allocated up front (grows on demand); 0 =
                                 none until the first evaluation (contexts that are only
                                 evaluated through a server) */
-  int32_t launch_mode;       /* 0 auto, 1 one kernel launch per pass, 2 persistent work queue */
+  int32_t launch_mode;       /* 0 auto; 1 one launch per pass (persistent workgroups over the
+                                batch's tiles); 2 the whole evaluation in one launch, one
+                                workgroup per theta vector holding the state's N/S_z sector in
+                                LDS -- only for states that are a single tile (n_qubits <= 12);
+                                auto picks 2 where it applies */
   int32_t host_only;         /* 1: plan on the host only (no device memory, no evaluation);
                                 for introspection and tests on machines without a GPU */
   int32_t device;            /* HIP device ordinal; -1 = current device */
@@ -213,6 +217,7 @@ enum {
   UCC_KERNEL_APPLYH = 3, /* apply-H pass (lambda = H psi, energy as a by-product) */
   UCC_KERNEL_REV = 4,    /* reverse-sweep pass (two vectors, gradient partials) */
   UCC_KERNEL_REDUCE = 5, /* fixed-order reduction of partials */
+  UCC_KERNEL_WHOLE = 6,  /* whole evaluation of a one-tile state in one launch (launch_mode 2) */
   UCC_KERNEL_KINDS = 8
 };
 

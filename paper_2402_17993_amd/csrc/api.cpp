@@ -190,6 +190,13 @@ ucc_status enqueue_eval(const ucc_ctx* c, Buffers& b, const double* d_theta, int
     prof->recs.push_back(r);
     return e;
   };
+  if (p.launch_mode == 2) {  // the whole evaluation in one launch: theta in, state, E and G out
+    const double bytes = 8.0 * B * p.K + S + 8.0 * B * (1 + (grad ? p.K : 0));
+    hipError_t e = timed(UCC_KERNEL_WHOLE, bytes,
+                         [&] { return launch_whole(a, d_theta, grad, p.nfwd, p.nexp, p.nrev); });
+    if (e != hipSuccess) return hip_fail(e, "launch k_whole");
+    return UCC_OK;
+  }
   hipError_t e = timed(UCC_KERNEL_TRIG, 24.0 * B * p.K, [&] { return launch_trig(a, d_theta); });
   if (e != hipSuccess) return hip_fail(e, "launch k_trig");
   for (int i = 0; i < p.nfwd; ++i) {
@@ -240,11 +247,40 @@ ucc_status upload_tables(ucc_ctx* c) {
   return UCC_OK;
 }
 
+// The whole-evaluation launch applies when every pass is a single tile and its LDS fits.
+bool whole_launch_fits(const Plan& p, const Tables& t) {
+  int ns = 0, max_blk = 0, max_blob = 0, max_slots = 0, max_occ = 0;
+  for (const DevPass& d : t.passes) {
+    if (d.k != p.n) return false;
+    ns = std::max(ns, d.ns_max);
+    max_blk = std::max(max_blk, d.stage_len);
+    if (d.kind == kExp) {
+      max_blob = std::max(max_blob, d.blob_len);
+      max_slots = std::max(max_slots, d.n_slots);
+      max_occ = std::max(max_occ, d.n_occ);
+    }
+  }
+  const size_t static_bytes = kStageBytes + 8 * kMaxPassExc * 4 + 64;  // stage, 4 waves' partials
+  return whole_lds(p.K, ns, max_blk, max_blob, max_slots, max_occ, p.n) + static_bytes <=
+         (size_t)kLdsBytes;
+}
+
 void apply_tuning(Plan& p, const Tuning& tu) {
   p.tf = tu.tf;
   p.te = tu.te;
   p.tr = tu.tr;
   p.launch_mode = tu.launch_mode;
+}
+
+// Launch mode 0 (auto) resolves to 2 where the whole-evaluation launch applies, else 1.
+ucc_status resolve_launch_mode(ucc_ctx* c) {
+  Plan& p = c->plan;
+  const bool fits = whole_launch_fits(p, c->tab);
+  if (c->opt.launch_mode == 2 && !fits)
+    return fail(UCC_EINVAL, "launch_mode 2 needs a state that is one tile whose tables fit in LDS "
+                            "(n_qubits <= 12)");
+  if (c->opt.launch_mode == 0) p.launch_mode = fits ? 2 : 1;
+  return UCC_OK;
 }
 
 ucc_status replan(ucc_ctx* c, int kf, int ke, int kr) {
@@ -268,7 +304,8 @@ ucc_status replan(ucc_ctx* c, int kf, int ke, int kr) {
   p = std::move(np);
   c->tab = Tables();
   build_tables(p, c->tab);
-  ucc_status s = upload_tables(c);
+  ucc_status s = resolve_launch_mode(c);
+  if (s == UCC_OK) s = upload_tables(c);
   if (s == UCC_OK && cap) s = ensure_buffers(c, c->buf, cap, lam);
   return s;
 }
@@ -346,6 +383,13 @@ ucc_status ucc_build(int32_t n_qubits, int32_t n_elec, const double* h1, const d
   }
   apply_tuning(c->plan, tu);
   build_tables(c->plan, c->tab);
+  {
+    const ucc_status rs = resolve_launch_mode(c);
+    if (rs != UCC_OK) {
+      delete c;
+      return rs;
+    }
+  }
   if (c->host_only) {
     *out = c;
     return UCC_OK;

@@ -88,6 +88,8 @@ bool batch_compatible(const ucc_ctx* a, const ucc_ctx* b);
 size_t entry_footprint(const ucc_ctx* c);
 Tuning choose_tuning(int n, int K, int batch, const ucc_options& o);
 void apply_tuning(Plan& p, const Tuning& tu);
+bool whole_launch_fits(const Plan& p, const Tables& t);
+ucc_status resolve_launch_mode(ucc_ctx* c);
 void free_tables(ucc_ctx* c);
 ucc_status upload_tables(ucc_ctx* c);
 // Re-plan for tile sizes (kf, ke, kr): new host and device tables, buffers re-allocated.

@@ -38,5 +38,14 @@ hipError_t launch_fwd(const LaunchArgs& a, int pidx, int init);
 hipError_t launch_exp(const LaunchArgs& a, int pidx, int eslot, int first, bool apply);
 hipError_t launch_rev(const LaunchArgs& a, int pidx);
 hipError_t launch_reduce(const LaunchArgs& a, int ne, bool grad, int nt);
+// Whole evaluation of a one-tile plan in one launch (one 256-thread workgroup per entry).
+hipError_t launch_whole(const LaunchArgs& a, const double* theta, bool grad, int nfwd, int nexp,
+                        int nrev);
+// Dynamic LDS bytes of that launch (host and planner use the same formula).
+inline size_t whole_lds(int K, int ns, int max_blk, int max_blob, int max_slots, int max_occ, int n) {
+  return 16 * size_t(K) + 32 * size_t(ns) + 16 * size_t(max_blob) +
+         8 * (size_t((max_slots + 1) & ~1) + size_t((max_occ + 1) & ~1) + size_t((n + 2) & ~1) + 16) +
+         4 * size_t(max_blk);
+}
 
 }  // namespace ucc

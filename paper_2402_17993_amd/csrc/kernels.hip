@@ -396,6 +396,249 @@ __device__ __forceinline__ void zeros_loop(uint32_t lmask, uint32_t tileN, const
     if (rtab[c] == kNoRank) v[base | dep(c, lmask)] = make_double2(0.0, 0.0);
 }
 
+// ---- pass bodies shared by the per-pass kernels and the whole-evaluation kernel
+
+// Forward excitations of a pass on the in-sector amplitudes cp of a tile (class block blk,
+// records and (cos, sin) in st): U_k = exp(theta_k G_k) in Trotter order, one barrier each.
+template <int T>
+__device__ __forceinline__ void fwd_excitations(double2* cp, const uint32_t* blk, const PassStage& st,
+                                                int count, uint32_t base) {
+  const uint32_t* off = blk + 2;
+  const int m = (int)blk[1], ns = (int)blk[0];
+  const uint32_t* ent = blk + 3 + m + ((ns + 1) >> 1) + ns;
+  ExcAhead ah;
+  ah.load(st.x, st.cs, off, ent, 0);
+  for (int e = 0; e < count; ++e) {
+    const ExcNow cur(ah, base);
+    if (e + 1 < count) ah.load(st.x, st.cs, off, ent, e + 1);
+    const double c = cur.c;
+    const double s = cur.sgn * cur.sn;
+    for (int i = cur.i0 + threadIdx.x; i < cur.i1; i += T) {
+      const uint32_t en = i == cur.i0 + (int)threadIdx.x ? cur.e0 : ent[i];
+      const uint32_t ru = en & 0x7fffu, rw = en >> 16;
+      const double sg = (en & 0x8000u) ? -s : s;
+      const double2 a = cp[ru], bb = cp[rw];
+      cp[ru] = make_double2(c * a.x - sg * bb.x, c * a.y - sg * bb.y);
+      cp[rw] = make_double2(c * bb.x + sg * a.x, c * bb.y + sg * a.y);
+    }
+    __syncthreads();
+  }
+}
+
+// Reverse excitations of a pass (descending k) on in-sector psi (cp) and lambda (cl): the
+// partial of <lambda|G_k|psi> over the tile's pairs, then exp(-theta_k G_k) on both.  On
+// return red[e][w] holds wave w's partial of excitation e (complete after the final barrier).
+// The wave sum of excitation e's partial runs while excitation e+1's first amplitudes load
+// (off the barrier-to-barrier chain); the sums run in uniform control flow (whole wave),
+// skipped by waves that had no pair.
+template <int T>
+__device__ __forceinline__ void rev_excitations(double2* cp, double2* cl, const uint32_t* blk,
+                                                const PassStage& st, int count, uint32_t base,
+                                                double (*red)[T / 64]) {
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const uint32_t* off = blk + 2;
+  const int m = (int)blk[1], ns = (int)blk[0];
+  const uint32_t* ent = blk + 3 + m + ((ns + 1) >> 1) + ns;
+  double gprev = 0.0;
+  bool had_prev = false;
+  ExcAhead ah;
+  ah.load(st.x, st.cs, off, ent, 0);
+  for (int e = 0; e < count; ++e) {
+    const ExcNow cur(ah, base);
+    if (e + 1 < count) ah.load(st.x, st.cs, off, ent, e + 1);
+    const double c = cur.c, sn = cur.sn;
+    const double sgn0 = cur.sgn;
+    const int i0 = cur.i0, i1 = cur.i1;
+    const int ia = i0 + (int)threadIdx.x;
+    const bool has = ia < i1;
+    uint32_t ru = 0u, rw = 0u;
+    double sg = 0.0;
+    double2 pu = make_double2(0.0, 0.0), pw = pu, lu = pu, lw = pu;
+    if (has) {
+      ru = cur.e0 & 0x7fffu;
+      rw = cur.e0 >> 16;
+      sg = (cur.e0 & 0x8000u) ? -sgn0 : sgn0;
+      pu = cp[ru];
+      pw = cp[rw];
+      lu = cl[ru];
+      lw = cl[rw];
+    }
+    if (e > 0) {
+      double gs = 0.0;
+      if (had_prev) gs = wave_sum(gprev);
+      if (lane == 0) red[e - 1][wv] = gs;
+    }
+    double g = 0.0;
+    if (has) {
+      g += sg * ((lw.x * pu.x + lw.y * pu.y) - (lu.x * pw.x + lu.y * pw.y));
+      const double s = sg * sn;
+      cp[ru] = make_double2(c * pu.x + s * pw.x, c * pu.y + s * pw.y);
+      cp[rw] = make_double2(c * pw.x - s * pu.x, c * pw.y - s * pu.y);
+      cl[ru] = make_double2(c * lu.x + s * lw.x, c * lu.y + s * lw.y);
+      cl[rw] = make_double2(c * lw.x - s * lu.x, c * lw.y - s * lu.y);
+    }
+    for (int i = ia + T; i < i1; i += T) {
+      const uint32_t en = ent[i];
+      const uint32_t qu = en & 0x7fffu, qw = en >> 16;
+      const double sq = (en & 0x8000u) ? -sgn0 : sgn0;
+      const double2 au = cp[qu], aw = cp[qw], bu = cl[qu], bw = cl[qw];
+      g += sq * ((bw.x * au.x + bw.y * au.y) - (bu.x * aw.x + bu.y * aw.y));
+      const double s = sq * sn;
+      cp[qu] = make_double2(c * au.x + s * aw.x, c * au.y + s * aw.y);
+      cp[qw] = make_double2(c * aw.x - s * au.x, c * aw.y - s * au.y);
+      cl[qu] = make_double2(c * bu.x + s * bw.x, c * bu.y + s * bw.y);
+      cl[qw] = make_double2(c * bw.x - s * bu.x, c * bw.y - s * bu.y);
+    }
+    gprev = g;
+    had_prev = i0 + wv * 64 < i1;
+    __syncthreads();
+  }
+  {
+    double gs = 0.0;
+    if (had_prev) gs = wave_sum(gprev);
+    if (lane == 0) red[count - 1][wv] = gs;
+  }
+  __syncthreads();  // red complete
+}
+
+// Per-tile values of an expectation pass (value table bw, layout in ucc_internal.h) for a
+// tile with global bits base: t1[slot] = sign_g * (A + global part of the occupation sum),
+// t2[slot] = sign_g for slots with occupation rows; with the diagonal group, dpre[0] = its
+// global part and dpre[1 + j] = a_r + global couplings of local bit j.  (Needs T >= 64 + k.)
+template <int T>
+__device__ __forceinline__ void exp_prep(const uint32_t* bw, double* t1, double* t2, double* dpre,
+                                         uint32_t lmask, int k, int n, uint32_t base) {
+  const double* dw = reinterpret_cast<const double*>(bw);
+  const int n_slots = (int)bw[0], n_occ = (int)bw[1], has_diag = (int)bw[2];
+  const uint32_t* mglob = bw + bw[4];
+  const double* A = dw + (bw[6] >> 1);
+  const double* Bglob = dw + (bw[8] >> 1);
+  const double* dg = dw + (bw[9] >> 1);
+  for (int s = threadIdx.x; s < n_slots; s += T) {
+    double val = A[s];
+    if (s < n_occ)
+      for (uint32_t gbits = base; gbits; gbits &= gbits - 1) val += Bglob[(size_t)s * n + (__ffs(gbits) - 1)];
+    const bool neg = parity(base & mglob[s]);
+    t1[s] = neg ? -val : val;
+    if (s < n_occ) t2[s] = neg ? -1.0 : 1.0;
+  }
+  if (has_diag) {
+    const int j = (int)threadIdx.x - 64;  // a wave other than the slot loop's first
+    if (threadIdx.x == 0) {
+      double d = dg[0];
+      for (uint32_t gbits = base; gbits; gbits &= gbits - 1) {
+        const int rr = __ffs(gbits) - 1;
+        d += dg[1 + rr];
+        for (uint32_t g2 = gbits & (gbits - 1); g2; g2 &= g2 - 1) d += dg[1 + n + rr * n + (__ffs(g2) - 1)];
+      }
+      dpre[0] = d;
+    } else if (j >= 0 && j < k) {
+      uint32_t lm = lmask;
+      for (int q = 0; q < j; ++q) lm &= lm - 1;
+      const int pj = __ffs(lm) - 1;  // physical bit of local bit j
+      double d = dg[1 + pj];
+      for (uint32_t gbits = base; gbits; gbits &= gbits - 1) {
+        const int rr = __ffs(gbits) - 1;
+        d += rr < pj ? dg[1 + n + rr * n + pj] : dg[1 + n + pj * n + rr];
+      }
+      dpre[1 + j] = d;
+    }
+  }
+}
+
+// Row walk of an expectation pass: for every in-sector target u of the tile (rank i), a quad
+// of lanes sums its row's entries (groups with occupation rows, then the others, then the
+// diagonal) in a fixed order.  Returns the thread's share of sum_u Re(conj(psi[u]) (H psi)[u]).
+// With APPLY the row sums are added into lambda (first pass: written): in HBM at base | the
+// state's local offset (LDSLAM false), or in LDS by rank (LDSLAM true).
+template <int T, bool APPLY, bool LDSLAM>
+__device__ __forceinline__ double exp_rows(const double2* cp, const uint32_t* blk,
+                                           const uint32_t* __restrict__ ent, const uint32_t* bw,
+                                           const double* t1, const double* t2, const double* dpre,
+                                           int k, int n, uint32_t base, double2* __restrict__ vl,
+                                           int first) {
+  const double* dw = reinterpret_cast<const double*>(bw);
+  const int has_diag = (int)bw[2];
+  const uint32_t* xloc = bw + bw[5];
+  const double* Bloc = dw + (bw[7] >> 1);
+  const double* bl = dw + (bw[9] >> 1) + 1 + n + n * n;
+  const int sub = threadIdx.x & 3;
+  const int ns = (int)blk[0];
+  const uint32_t* off = blk + 2;
+  const uint32_t* mid = off + ns + 1;
+  const uint16_t* sl = reinterpret_cast<const uint16_t*>(mid + ns);
+  const uint32_t* sphys = mid + ns + ((ns + 1) >> 1);
+  double eacc = 0.0;
+  for (int i0 = 0; i0 < ns; i0 += T / 4) {
+    const int i = i0 + ((int)threadIdx.x >> 2);
+    const bool row = i < ns;  // the same for the four lanes of a quad
+    double ax = 0.0, ay = 0.0;
+    dvec2 old = {0.0, 0.0};
+    uint32_t phys = 0u;
+    if (row) {
+      phys = LDSLAM ? (uint32_t)i : (base | sphys[i]);
+      if (APPLY && !first && sub == 0) old = ld16(vl + phys);
+      // lane `sub` takes every fourth 16-byte chunk of four entries of the row
+      const uint4* __restrict__ e4 = reinterpret_cast<const uint4*>(ent);
+      const int q0 = (int)off[i] >> 2, q1 = (int)mid[i] >> 2, q2 = (int)off[i + 1] >> 2;
+      auto occ_entry = [&](uint32_t en) {  // groups with occupation rows
+        const uint32_t rv = en & 0x7fffu, slot = en >> 16;
+        const double* br = Bloc + (size_t)slot * k;
+        double occ = 0.0;
+        for (uint32_t bits = (uint32_t)sl[rv] & ~xloc[slot]; bits; bits &= bits - 1) occ += br[__ffs(bits) - 1];
+        double val = t1[slot] + t2[slot] * occ;
+        if (en & 0x8000u) val = -val;
+        const double2 pv = cp[rv];
+        ax += val * pv.x;
+        ay += val * pv.y;
+      };
+      auto plain_entry = [&](uint32_t en) {
+        const double val = (en & 0x8000u) ? -t1[en >> 16] : t1[en >> 16];
+        const double2 pv = cp[en & 0x7fffu];
+        ax += val * pv.x;
+        ay += val * pv.y;
+      };
+      for (int q = q0 + sub; q < q1; q += 4) {
+        const uint4 E = e4[q];
+        occ_entry(E.x);
+        occ_entry(E.y);
+        occ_entry(E.z);
+        occ_entry(E.w);
+      }
+      for (int q = q1 + sub; q < q2; q += 4) {
+        const uint4 E = e4[q];
+        plain_entry(E.x);
+        plain_entry(E.y);
+        plain_entry(E.z);
+        plain_entry(E.w);
+      }
+      if (has_diag) {  // c0 + sum_r a_r n_r + sum_{r<s} b_rs n_r n_s; set bits split by rank
+        double f = sub == 0 ? dpre[0] : 0.0;
+        int rank = 0;
+        for (uint32_t rem = (uint32_t)sl[i]; rem;) {
+          const int q = __ffs(rem) - 1;
+          rem &= rem - 1;
+          if ((rank++ & 3) == sub) {
+            f += dpre[1 + q];
+            for (uint32_t r2 = rem; r2; r2 &= r2 - 1) f += bl[q * k + (__ffs(r2) - 1)];
+          }
+        }
+        const double2 pu = cp[i];
+        ax += f * pu.x;
+        ay += f * pu.y;
+      }
+    }
+    ax = quad_sum(ax);
+    ay = quad_sum(ay);
+    if (row && sub == 0) {
+      const double2 pu = cp[i];
+      eacc += pu.x * ax + pu.y * ay;
+      if (APPLY) st16(vl + phys, dvec2{old.x + ax, old.y + ay});
+    }
+  }
+  return eacc;
+}
+
 // The pass kernels hold one or two workgroups per CU, i.e. T/256 waves per SIMD each: let
 // the register allocator use the VGPRs that occupancy leaves.
 #define LDS_BOUND_OCCUPANCY __attribute__((amdgpu_waves_per_eu(T / 256, 2 * T / 256)))
@@ -479,24 +722,7 @@ __global__ __launch_bounds__(T) LDS_BOUND_OCCUPANCY void k_fwd(
     }
     const int m = (int)blk[1], ns = (int)blk[0];
     const uint32_t* sphys = blk + 3 + m + ((ns + 1) >> 1);
-    const uint32_t* ent = sphys + ns;
-    ExcAhead ah;
-    ah.load(st.x, st.cs, off, ent, 0);
-    for (int e = 0; e < ps.count; ++e) {
-      const ExcNow cur(ah, base);
-      if (e + 1 < ps.count) ah.load(st.x, st.cs, off, ent, e + 1);
-      const double c = cur.c;
-      const double s = cur.sgn * cur.sn;
-      for (int i = cur.i0 + threadIdx.x; i < cur.i1; i += T) {
-        const uint32_t en = i == cur.i0 + (int)threadIdx.x ? cur.e0 : ent[i];
-        const uint32_t ru = en & 0x7fffu, rw = en >> 16;
-        const double sg = (en & 0x8000u) ? -s : s;
-        const double2 a = cp[ru], bb = cp[rw];
-        cp[ru] = make_double2(c * a.x - sg * bb.x, c * a.y - sg * bb.y);
-        cp[rw] = make_double2(c * bb.x + sg * a.x, c * bb.y + sg * a.y);
-      }
-      __syncthreads();
-    }
+    fwd_excitations<T>(cp, blk, st, ps.count, base);
     if constexpr (RP) {
       tm.refresh();
       SC::put_zeros(tm, v, base, insec, zero);
@@ -591,70 +817,7 @@ __global__ __launch_bounds__(T) LDS_BOUND_OCCUPANCY void k_rev(
     }
     const int m = (int)blk[1], ns = (int)blk[0];
     const uint32_t* sphys = blk + 3 + m + ((ns + 1) >> 1);
-    const uint32_t* ent = sphys + ns;
-    // The wave sum of excitation e's partial runs while excitation e+1's first amplitudes
-    // load (off the barrier-to-barrier chain); lane 0 of each wave keeps it in red[e].  The
-    // sums run in uniform control flow (whole wave), skipped by waves that had no pair.
-    double gprev = 0.0;
-    bool had_prev = false;
-    ExcAhead ah;
-    ah.load(st.x, st.cs, off, ent, 0);
-    for (int e = 0; e < ps.count; ++e) {
-      const ExcNow cur(ah, base);
-      if (e + 1 < ps.count) ah.load(st.x, st.cs, off, ent, e + 1);
-      const double c = cur.c, sn = cur.sn;
-      const double sgn0 = cur.sgn;
-      const int i0 = cur.i0, i1 = cur.i1;
-      const int ia = i0 + (int)threadIdx.x;
-      const bool has = ia < i1;
-      uint32_t ru = 0u, rw = 0u;
-      double sg = 0.0;
-      double2 pu = make_double2(0.0, 0.0), pw = pu, lu = pu, lw = pu;
-      if (has) {
-        ru = cur.e0 & 0x7fffu;
-        rw = cur.e0 >> 16;
-        sg = (cur.e0 & 0x8000u) ? -sgn0 : sgn0;
-        pu = cp[ru];
-        pw = cp[rw];
-        lu = cl[ru];
-        lw = cl[rw];
-      }
-      if (e > 0) {
-        double gs = 0.0;
-        if (had_prev) gs = wave_sum(gprev);
-        if (lane == 0) red[e - 1][wv] = gs;
-      }
-      double g = 0.0;
-      if (has) {
-        g += sg * ((lw.x * pu.x + lw.y * pu.y) - (lu.x * pw.x + lu.y * pw.y));
-        const double s = sg * sn;
-        cp[ru] = make_double2(c * pu.x + s * pw.x, c * pu.y + s * pw.y);
-        cp[rw] = make_double2(c * pw.x - s * pu.x, c * pw.y - s * pu.y);
-        cl[ru] = make_double2(c * lu.x + s * lw.x, c * lu.y + s * lw.y);
-        cl[rw] = make_double2(c * lw.x - s * lu.x, c * lw.y - s * lu.y);
-      }
-      for (int i = ia + T; i < i1; i += T) {
-        const uint32_t en = ent[i];
-        const uint32_t qu = en & 0x7fffu, qw = en >> 16;
-        const double sq = (en & 0x8000u) ? -sgn0 : sgn0;
-        const double2 au = cp[qu], aw = cp[qw], bu = cl[qu], bw = cl[qw];
-        g += sq * ((bw.x * au.x + bw.y * au.y) - (bu.x * aw.x + bu.y * aw.y));
-        const double s = sq * sn;
-        cp[qu] = make_double2(c * au.x + s * aw.x, c * au.y + s * aw.y);
-        cp[qw] = make_double2(c * aw.x - s * au.x, c * aw.y - s * au.y);
-        cl[qu] = make_double2(c * bu.x + s * bw.x, c * bu.y + s * bw.y);
-        cl[qw] = make_double2(c * bw.x - s * bu.x, c * bw.y - s * bu.y);
-      }
-      gprev = g;
-      had_prev = i0 + wv * 64 < i1;
-      __syncthreads();
-    }
-    {
-      double gs = 0.0;
-      if (had_prev) gs = wave_sum(gprev);
-      if (lane == 0) red[ps.count - 1][wv] = gs;
-    }
-    __syncthreads();  // red complete
+    rev_excitations<T>(cp, cl, blk, st, ps.count, base, red);
     if (cst) {
       double sum = 0.0;
       for (int w = 0; w < NW; ++w) sum += red[threadIdx.x][w];
@@ -759,121 +922,10 @@ __global__ __launch_bounds__(T) LDS_BOUND_OCCUPANCY void k_exp(
     else
       take_loop<T, false>(ps.lmask, tileN, cp, rtab, vec_of(item), base, 0u);
     (void)insec;
-    // per-tile slot values
-    const int n_slots = (int)bw[0], n_occ = (int)bw[1], has_diag = (int)bw[2];
-    const uint32_t* mglob = bw + bw[4];
-    const uint32_t* xloc = bw + bw[5];
-    const double* A = dw + (bw[6] >> 1);
-    const double* Bloc = dw + (bw[7] >> 1);
-    const double* Bglob = dw + (bw[8] >> 1);
-    const double* dg = dw + (bw[9] >> 1);
-    const double* bl = dg + 1 + n + n * n;
-    for (int s = threadIdx.x; s < n_slots; s += T) {
-      double val = A[s];
-      if (s < n_occ)
-        for (uint32_t gbits = base; gbits; gbits &= gbits - 1) val += Bglob[(size_t)s * n + (__ffs(gbits) - 1)];
-      const bool neg = parity(base & mglob[s]);
-      t1[s] = neg ? -val : val;
-      if (s < n_occ) t2[s] = neg ? -1.0 : 1.0;
-    }
-    if (has_diag) {
-      const int j = (int)threadIdx.x - 64;  // a wave other than the slot loop's first
-      if (threadIdx.x == 0) {
-        double d = dg[0];
-        for (uint32_t gbits = base; gbits; gbits &= gbits - 1) {
-          const int rr = __ffs(gbits) - 1;
-          d += dg[1 + rr];
-          for (uint32_t g2 = gbits & (gbits - 1); g2; g2 &= g2 - 1) d += dg[1 + n + rr * n + (__ffs(g2) - 1)];
-        }
-        dpre[0] = d;
-      } else if (j >= 0 && j < k) {
-        uint32_t lm = ps.lmask;
-        for (int q = 0; q < j; ++q) lm &= lm - 1;
-        const int pj = __ffs(lm) - 1;  // physical bit of local bit j
-        double d = dg[1 + pj];
-        for (uint32_t gbits = base; gbits; gbits &= gbits - 1) {
-          const int rr = __ffs(gbits) - 1;
-          d += rr < pj ? dg[1 + n + rr * n + pj] : dg[1 + n + pj * n + rr];
-        }
-        dpre[1 + j] = d;
-      }
-    }
+    exp_prep<T>(bw, t1, t2, dpre, ps.lmask, k, n, base);
     __syncthreads();  // cp and the per-tile values complete
     const int next = item + gridDim.x;
-    const int ns = (int)blk[0];
-    const uint32_t* off = blk + 2;
-    const uint32_t* mid = off + ns + 1;
-    const uint16_t* sl = reinterpret_cast<const uint16_t*>(mid + ns);
-    const uint32_t* sphys = mid + ns + ((ns + 1) >> 1);
-    const uint32_t* __restrict__ ent = gent;
-    double eacc = 0.0;
-    for (int i0 = 0; i0 < ns; i0 += T / 4) {
-      const int i = i0 + ((int)threadIdx.x >> 2);
-      const bool row = i < ns;  // the same for the four lanes of a quad
-      double ax = 0.0, ay = 0.0;
-      dvec2 old = {0.0, 0.0};
-      uint32_t phys = 0u;
-      if (row) {
-        phys = base | sphys[i];
-        if (APPLY && !first && sub == 0) old = ld16(vl + phys);
-        // lane `sub` takes every fourth 16-byte chunk of four entries of the row
-        const uint4* __restrict__ e4 = reinterpret_cast<const uint4*>(ent);
-        const int q0 = (int)off[i] >> 2, q1 = (int)mid[i] >> 2, q2 = (int)off[i + 1] >> 2;
-        auto occ_entry = [&](uint32_t en) {  // groups with occupation rows
-          const uint32_t rv = en & 0x7fffu, slot = en >> 16;
-          const double* br = Bloc + (size_t)slot * k;
-          double occ = 0.0;
-          for (uint32_t bits = (uint32_t)sl[rv] & ~xloc[slot]; bits; bits &= bits - 1) occ += br[__ffs(bits) - 1];
-          double val = t1[slot] + t2[slot] * occ;
-          if (en & 0x8000u) val = -val;
-          const double2 pv = cp[rv];
-          ax += val * pv.x;
-          ay += val * pv.y;
-        };
-        auto plain_entry = [&](uint32_t en) {
-          const double val = (en & 0x8000u) ? -t1[en >> 16] : t1[en >> 16];
-          const double2 pv = cp[en & 0x7fffu];
-          ax += val * pv.x;
-          ay += val * pv.y;
-        };
-        for (int q = q0 + sub; q < q1; q += 4) {
-          const uint4 E = e4[q];
-          occ_entry(E.x);
-          occ_entry(E.y);
-          occ_entry(E.z);
-          occ_entry(E.w);
-        }
-        for (int q = q1 + sub; q < q2; q += 4) {
-          const uint4 E = e4[q];
-          plain_entry(E.x);
-          plain_entry(E.y);
-          plain_entry(E.z);
-          plain_entry(E.w);
-        }
-        if (has_diag) {  // c0 + sum_r a_r n_r + sum_{r<s} b_rs n_r n_s; set bits split by rank
-          double f = sub == 0 ? dpre[0] : 0.0;
-          int rank = 0;
-          for (uint32_t rem = (uint32_t)sl[i]; rem;) {
-            const int q = __ffs(rem) - 1;
-            rem &= rem - 1;
-            if ((rank++ & 3) == sub) {
-              f += dpre[1 + q];
-              for (uint32_t r2 = rem; r2; r2 &= r2 - 1) f += bl[q * k + (__ffs(r2) - 1)];
-            }
-          }
-          const double2 pu = cp[i];
-          ax += f * pu.x;
-          ay += f * pu.y;
-        }
-      }
-      ax = quad_sum(ax);
-      ay = quad_sum(ay);
-      if (row && sub == 0) {
-        const double2 pu = cp[i];
-        eacc += pu.x * ax + pu.y * ay;
-        if (APPLY) st16(vl + phys, dvec2{old.x + ax, old.y + ay});
-      }
-    }
+    const double eacc = exp_rows<T, APPLY, false>(cp, blk, gent, bw, t1, t2, dpre, k, n, base, vl, first);
     // The next tile is requested after the row walk: its entry and lambda loads then never
     // wait behind the tile's loads (vector-memory counters retire in issue order).
     if (RP && next < total) {
@@ -889,6 +941,109 @@ __global__ __launch_bounds__(T) LDS_BOUND_OCCUPANCY void k_exp(
     if (bstride) __syncthreads();  // a re-staged value table is read by the next tile's prep
     item = next;
   }
+}
+
+// Whole evaluation in one launch, for states that are a single tile (every pass has k = n):
+// one workgroup per batch entry keeps the in-sector amplitudes of psi and lambda in LDS
+// through all passes.  It forms cos/sin, synthesizes |HF>, runs the forward passes, the
+// expectation / apply-H passes (energy summed in pass order) and, with GRAD, the reverse
+// passes (dE/dtheta_k = 2 sum of the per-wave partials), then writes the final state as a whole
+// vector (zeros outside the sector).  The pass bodies are those of the per-pass kernels.
+template <int T, bool GRAD>
+__global__ __launch_bounds__(T) void k_whole(
+    const DevPass* __restrict__ passes, int nfwd, int nexp, int nrev,
+    const DevExc* __restrict__ exc, const int2* __restrict__ pcls,
+    const uint32_t* __restrict__ blocks, const uint4* __restrict__ blobs, int bstride,
+    const double* __restrict__ theta, int K, double2* __restrict__ psi, int n, uint32_t hf,
+    double* __restrict__ E, double* __restrict__ G, int ns, int max_blk, int max_blob,
+    int max_slots, int max_occ) {
+  extern __shared__ double2 lds[];
+  constexpr int NW = T / 64;
+  __shared__ PassStage st;
+  __shared__ double red[kMaxPassExc][NW];
+  __shared__ int hf_rank;
+  const int b = blockIdx.x;
+  // LDS: (cos, sin) of every excitation | psi and lambda by rank | value table | per-tile
+  //      slot values t1, t2 | diagonal prep | wave sums | class block
+  double2* csa = lds;
+  double2* cp = csa + K;
+  double2* cl = cp + ns;
+  uint4* lb = reinterpret_cast<uint4*>(cl + ns);
+  double* t1 = reinterpret_cast<double*>(lb + max_blob);
+  double* t2 = t1 + ((max_slots + 1) & ~1);
+  double* dpre = t2 + ((max_occ + 1) & ~1);
+  double* red2 = dpre + ((n + 2) & ~1);
+  uint32_t* blk = reinterpret_cast<uint32_t*>(red2 + 16);
+  const uint32_t* bw = reinterpret_cast<const uint32_t*>(lb);
+  for (int k = threadIdx.x; k < K; k += T) {
+    double sv, cv;
+    sincos(theta[(size_t)b * K + k], &sv, &cv);
+    csa[k] = make_double2(cv, sv);
+  }
+  for (int i = threadIdx.x; i < ns; i += T) cp[i] = make_double2(0.0, 0.0);
+  // the in-sector list is the same for every pass of a one-tile plan (ascending index)
+  const DevPass p0 = passes[0];
+  stage_words<T>(blk, blocks + pcls[p0.cls_base].x, pcls[p0.cls_base].y);
+  __syncthreads();
+  {
+    const uint16_t* sl = reinterpret_cast<const uint16_t*>(blk + 3 + (int)blk[1]);
+    for (int i = threadIdx.x; i < ns; i += T)
+      if ((uint32_t)sl[i] == hf) hf_rank = i;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) cp[hf_rank] = make_double2(1.0, 0.0);
+  auto stage_pass = [&](const DevPass& ps) {
+    __syncthreads();  // the previous pass no longer reads the stage or the block
+    for (int i = threadIdx.x; i < ps.count; i += T) {
+      const DevExc x = exc[ps.first + i];
+      st.x[i] = x;
+      st.cs[i] = csa[x.k];
+    }
+    const int2 bl = pcls[ps.cls_base];
+    stage_words<T>(blk, blocks + bl.x, bl.y);
+    __syncthreads();
+  };
+  for (int q = 0; q < nfwd; ++q) {
+    const DevPass ps = passes[q];
+    stage_pass(ps);
+    fwd_excitations<T>(cp, blk, st, ps.count, 0u);
+  }
+  double etot = 0.0;
+  for (int j = 0; j < nexp; ++j) {
+    const DevPass ps = passes[nfwd + j];
+    __syncthreads();
+    const uint4* __restrict__ gb = blobs + (size_t)b * bstride + ps.blob_off;
+    for (int i = threadIdx.x; i < ps.blob_len; i += T) lb[i] = gb[i];
+    const uint32_t* src = blocks + pcls[ps.cls_base].x;
+    const int words = (3 + 3 * ns + ((ns + 1) >> 1) + 3) & ~3;
+    stage_words<T>(blk, src, words);
+    __syncthreads();
+    exp_prep<T>(bw, t1, t2, dpre, ps.lmask, ps.k, n, 0u);
+    __syncthreads();
+    double e = exp_rows<T, GRAD, true>(cp, blk, src + words, bw, t1, t2, dpre, ps.k, n, 0u, cl, j == 0);
+    e = block_sum<T>(e, red2);
+    if (threadIdx.x == 0) etot += e;
+  }
+  if (GRAD) {
+    for (int j = 0; j < nrev; ++j) {
+      const DevPass ps = passes[nfwd + nexp + j];
+      stage_pass(ps);
+      rev_excitations<T>(cp, cl, blk, st, ps.count, 0u, red);
+      if ((int)threadIdx.x < ps.count) {
+        double sum = 0.0;
+        for (int w = 0; w < NW; ++w) sum += red[threadIdx.x][w];
+        G[(size_t)b * K + st.x[threadIdx.x].k] = 2.0 * sum;
+      }
+    }
+  }
+  if (threadIdx.x == 0) E[b] = etot;
+  // the final state: zeros everywhere, then (after the workgroup barrier orders them) the
+  // in-sector values at their indices (the list of the staged forward block, restaged)
+  double2* __restrict__ v = psi + ((size_t)b << n);
+  for (uint32_t c = threadIdx.x; c < (1u << n); c += T) st16(v + c, dvec2{0.0, 0.0});
+  stage_pass(p0);
+  const uint16_t* sl = reinterpret_cast<const uint16_t*>(blk + 3 + (int)blk[1]);
+  for (int i = threadIdx.x; i < ns; i += T) st16(v + sl[i], ld16(cp + i));
 }
 
 // Fixed-order reductions.  epart: [B][ne] energy partials; gpart: [B][K][nt] gradient partials.
@@ -1095,6 +1250,31 @@ hipError_t launch_exp(const LaunchArgs& a, int pidx, int eslot, int first, bool 
     case 1024: return exp_k<1024, false>(a, pidx, eslot, first);
     default: return exp_k<512, false>(a, pidx, eslot, first);
   }
+}
+
+hipError_t launch_whole(const LaunchArgs& a, const double* theta, bool grad, int nfwd, int nexp,
+                        int nrev) {
+  int ns = 0, max_blk = 0, max_blob = 0, max_slots = 0, max_occ = 0;
+  for (int i = 0; i < nfwd + nexp + nrev; ++i) {
+    const DevPass& hp = a.hpasses[i];
+    ns = std::max(ns, hp.ns_max);
+    max_blk = std::max(max_blk, hp.stage_len);
+    if (hp.kind == kExp) {
+      max_blob = std::max(max_blob, hp.blob_len);
+      max_slots = std::max(max_slots, hp.n_slots);
+      max_occ = std::max(max_occ, hp.n_occ);
+    }
+  }
+  const size_t lds = whole_lds(a.K, ns, max_blk, max_blob, max_slots, max_occ, a.n);
+  auto go = [&](auto kern) -> hipError_t {
+    hipError_t e = set_lds(kern, lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(kern, dim3(a.B), dim3(256), lds, a.stream, a.passes, nfwd, nexp, nrev,
+                       a.exc, a.cls, a.pairs, a.blobs, a.blob_stride, theta, a.K, a.psi, a.n,
+                       a.hf, a.E, a.G, ns, max_blk, max_blob, max_slots, max_occ);
+    return hipGetLastError();
+  };
+  return grad ? go(k_whole<256, true>) : go(k_whole<256, false>);
 }
 
 hipError_t launch_reduce(const LaunchArgs& a, int ne, bool grad, int nt) {

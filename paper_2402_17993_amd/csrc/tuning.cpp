@@ -47,7 +47,7 @@ Tuning choose_tuning(int n, int K, int batch, const ucc_options& o) {
   t.tf = pick(o.block_threads_fwd, o.block_threads, small ? 256 : 1024);
   t.te = pick(o.block_threads_exp, o.block_threads, small ? 256 : 1024);
   t.tr = pick(o.block_threads_rev, o.block_threads, small ? 256 : 512);
-  t.launch_mode = o.launch_mode ? o.launch_mode : 1;
+  t.launch_mode = o.launch_mode ? o.launch_mode : 1;  // 0 is resolved once the tables exist
   return t;
 }
 
@@ -80,7 +80,7 @@ ucc_status autotune(ucc_ctx* c, int B) {
       if (s != UCC_OK) return s;
       apply_tuning(p, tu);
       p.autotuned = true;
-      return UCC_OK;
+      return resolve_launch_mode(c);
     }
   }
   const std::vector<int> kfs = tile_candidates(o.tile_qubits, p.n, {14, 13});
@@ -109,6 +109,7 @@ ucc_status autotune(ucc_ctx* c, int B) {
     hipError_t e = hipMemcpy(c->buf.theta, th.data(), th.size() * sizeof(double), hipMemcpyHostToDevice);
     if (e != hipSuccess) return hip_fail(e, "autotune theta upload");
     for (int T : ts) {
+      p.launch_mode = 1;  // per-kind timings
       p.tf = o.block_threads_fwd ? o.block_threads_fwd : T;
       p.te = o.block_threads_exp ? o.block_threads_exp : T;
       p.tr = o.block_threads_rev ? o.block_threads_rev : T;
@@ -136,9 +137,11 @@ ucc_status autotune(ucc_ctx* c, int B) {
   if (s != UCC_OK) return s;
   apply_tuning(p, tu);
   p.autotuned = true;
-  std::lock_guard<std::mutex> lock(g_cache_mu);
-  g_cache[key] = tu;
-  return UCC_OK;
+  {
+    std::lock_guard<std::mutex> lock(g_cache_mu);
+    g_cache[key] = tu;
+  }
+  return resolve_launch_mode(c);
 }
 
 }  // namespace ucc

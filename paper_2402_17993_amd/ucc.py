@@ -30,7 +30,7 @@ EXPORTED = [
     "ucc_server_create", "ucc_submit", "ucc_poll", "ucc_wait", "ucc_cancel", "ucc_server_destroy",
 ]
 
-KERNEL_KINDS = ["trig", "fwd", "exp", "applyh", "rev", "reduce"]
+KERNEL_KINDS = ["trig", "fwd", "exp", "applyh", "rev", "reduce", "whole"]
 
 
 class Options(ctypes.Structure):

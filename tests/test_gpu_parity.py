@@ -98,6 +98,35 @@ def test_12q_tilings(ucc, kf, kr, c0, threads):
     assert abs(ctx.energy(th)[0] - e_ref) <= E_TOL
 
 
+@pytest.mark.parametrize("n,ne,seed", [(8, 4, 21), (12, 8, 22), (12, 4, 23)])
+def test_whole_evaluation_launch(ucc, n, ne, seed):
+    say(f"case: {n}q/{ne}e whole-evaluation launch vs per-pass launches, batch 3")
+    h1, h2, h, g, exc = system(n, ne, seed=seed)
+    th = make_thetas(len(exc), seed, 0.2, batch=3)
+    one = ucc.Context(n, ne, h1, h2, exc, max_batch=3)  # auto: one launch
+    per = ucc.Context(n, ne, h1, h2, exc, max_batch=3, launch_mode=1)
+    assert one.plan_info()["launch_mode"] == 2 and per.plan_info()["launch_mode"] == 1
+    e1, g1 = one.energy_grad(th)
+    e2, g2 = per.energy_grad(th)
+    assert np.max(np.abs(e1 - e2)) <= 1e-12 and np.max(np.abs(g1 - g2)) <= 1e-12
+    for b in range(3):
+        e_ref, g_ref = oracle_eg(n, ne, h, g, exc, th[b])
+        assert abs(e1[b] - e_ref) <= E_TOL and np.max(np.abs(g1[b] - g_ref)) <= G_TOL
+    # the reverse sweep returns the state to |HF>
+    hf = np.zeros(1 << n, complex)
+    hf[(1 << ne) - 1] = 1.0
+    assert np.max(np.abs(one.state(2) - hf)) <= 1e-12
+    # energy only: same energies, and the state is the Trotter state
+    e3 = one.energy(th)
+    assert np.max(np.abs(e3 - e1)) <= 1e-12
+    ref = ansatz.trotter_state(n, (1 << ne) - 1, exc, th[1])
+    assert np.max(np.abs(one.state(1) - ref)) <= 1e-12
+    # batch entry == solo run, bitwise
+    solo = ucc.Context(n, ne, h1, h2, exc)
+    es, gs = solo.energy_grad(th[2])
+    assert es[0] == e1[2] and np.array_equal(gs[0], g1[2])
+
+
 def test_minimal_system_and_single_excitation(ucc):
     say("case: 4q/2e full list, and a one-excitation list")
     n, ne = 4, 2

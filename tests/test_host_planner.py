@@ -224,3 +224,17 @@ def test_server_argument_errors():
     assert L.ucc_poll(None, 1, ucc.ctypes.byref(done), None, None, None) == -1
     assert L.ucc_cancel(None, 1) == -1
     L.ucc_server_destroy(None)  # accepted
+
+
+def test_launch_mode_resolution():
+    # one-tile states take the whole-evaluation launch by default; larger ones cannot
+    for n, ne, want in ((4, 2, 2), (8, 4, 2), (12, 8, 2), (16, 8, 1)):
+        ctx, *_ = host_ctx(n, ne)
+        assert ctx.plan_info()["launch_mode"] == want, (n, want)
+    ctx, *_ = host_ctx(12, 8, launch_mode=1)
+    assert ctx.plan_info()["launch_mode"] == 1
+    with pytest.raises(ucc.UCCError) as ei:
+        host_ctx(16, 8, launch_mode=2)
+    assert ei.value.status == -1
+    with pytest.raises(ucc.UCCError):  # a 12-qubit state split into tiles is not one tile
+        host_ctx(12, 8, launch_mode=2, tile_qubits=8)
