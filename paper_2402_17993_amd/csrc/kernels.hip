@@ -1,11 +1,12 @@
 // CDNA4 (gfx950) kernels of the UCCSD state-vector path.  All arithmetic is FP64.
 //
-// Every kernel works on one tile of one state vector per workgroup: the 2^k amplitudes
-// whose global bits equal the tile index.  blockIdx.x = tile, blockIdx.y = batch entry.
-// The tile is staged in LDS with coalesced 16-byte loads (the lowest physical bits are
-// always local, so consecutive lanes read consecutive addresses; every load of a thread is
-// issued before the first one is waited on), all of the pass's work is applied in LDS, and
-// the tile is written back.
+// The pass kernels are persistent: each workgroup walks (batch entry, tile) items, a tile
+// being the 2^k amplitudes whose global bits equal the tile index.  A tile is streamed
+// through registers with coalesced 16-byte loads (the lowest physical bits are always local,
+// so consecutive lanes read consecutive addresses; the next tile's loads are in flight while
+// the current one is worked on); only its amplitudes inside the particle-number / S_z sector
+// go to LDS, by rank, all of the pass's work is applied there, and the tile is written back
+// (exact zeros outside the sector, the LDS values at their physical offsets inside).
 //
 //   k_trig      cos/sin of every amplitude of every batch entry
 //   k_fwd       forward excitation pass: U_k = exp(theta_k G_k) for the pass's excitations
@@ -13,6 +14,8 @@
 //   k_exp       expectation / apply-H pass over the pass's x-groups (Eq. 2 as a Pauli sum)
 //   k_rev       reverse pass over (psi, lambda): gradient partials, then U_k^dag on both
 //   k_reduce    fixed-order sums of the per-tile partials
+//   k_whole     a whole evaluation (all of the above) in one launch, one workgroup per batch
+//               entry, for states that are a single tile
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -120,8 +123,8 @@ __device__ __forceinline__ const dvec2& rget(const RegBuf<N>& r) {
 
 // Element c = threadIdx.x + j*T of a tile sits at base | dt | dj: dt deposits the thread's
 // low compact bits into the local mask, dj the bits of j into the next local bits (uniform).
-// KT = log2 of the tile size for the unrolled register-staged path (12 or 13); KT = 0 is a
-// plain loop for small tiles.
+// KT = log2 of the tile size for the unrolled register-staged path (12, 13 or 14); KT = 0 is
+// a plain loop for other tiles.
 template <int T, int KT>
 struct Tile {
   static constexpr int L2T = log2i<T>();
@@ -156,71 +159,11 @@ struct Tile {
     return dt | ((J & 1) ? h0 : 0u) | ((J & 2) ? h1 : 0u) | ((J & 4) ? h2 : 0u) |
            ((J & 8) ? h3 : 0u) | ((J & 16) ? h4 : 0u);
   }
-  // fetch issues every load of the thread into registers; put waits and writes into LDS
+  // fetch issues every load of the thread into registers (waited on where they are used)
   template <int J = 0>
   __device__ __forceinline__ void fetch(Buf& r, const double2* __restrict__ v, uint32_t base) const {
     rget<J, EPT>(r) = ld16(v + (base | off<J>()));
     if constexpr (J + 1 < EPT) fetch<J + 1>(r, v, base);
-  }
-  template <int J = 0>
-  __device__ __forceinline__ void put(const Buf& r, double2* lds) const {
-    st16(lds + threadIdx.x + J * T, rget<J, EPT>(r));
-    if constexpr (J + 1 < EPT) put<J + 1>(r, lds);
-  }
-  // rs <- the thread's own tile elements in LDS, then those elements <- r (the next tile)
-  template <int J = 0>
-  __device__ __forceinline__ void swap(Buf& rs, const Buf& r, double2* lds) const {
-    rget<J, EPT>(rs) = ld16(lds + threadIdx.x + J * T);
-    st16(lds + threadIdx.x + J * T, rget<J, EPT>(r));
-    if constexpr (J + 1 < EPT) swap<J + 1>(rs, r, lds);
-  }
-  template <int J = 0>
-  __device__ __forceinline__ void save(Buf& rs, const double2* lds) const {
-    rget<J, EPT>(rs) = ld16(lds + threadIdx.x + J * T);
-    if constexpr (J + 1 < EPT) save<J + 1>(rs, lds);
-  }
-  template <int J = 0>
-  __device__ __forceinline__ void store_regs(const Buf& rs, double2* __restrict__ v, uint32_t base) const {
-    st16(v + (base | off<J>()), rget<J, EPT>(rs));
-    if constexpr (J + 1 < EPT) store_regs<J + 1>(rs, v, base);
-  }
-  template <int J = 0>
-  __device__ __forceinline__ void store_j(const double2* lds, double2* __restrict__ v,
-                                          uint32_t base) const {
-    st16(v + (base | off<J>()), ld16(lds + threadIdx.x + J * T));
-    if constexpr (J + 1 < EPT) store_j<J + 1>(lds, v, base);
-  }
-  template <int J = 0>
-  __device__ __forceinline__ void init_j(double2* lds, uint32_t base, uint32_t hf) const {
-    lds[threadIdx.x + J * T] = make_double2((base | off<J>()) == hf ? 1.0 : 0.0, 0.0);
-    if constexpr (J + 1 < EPT) init_j<J + 1>(lds, base, hf);
-  }
-  __device__ __forceinline__ void load(double2* lds, const double2* __restrict__ v, uint32_t base,
-                                       uint32_t tileN) const {
-    if constexpr (KT == 0) {
-      for (uint32_t c = threadIdx.x; c < tileN; c += T) lds[c] = v[base | dep(c, lmask)];
-    } else {
-      Buf r;
-      fetch(r, v, base);
-      put(r, lds);
-    }
-  }
-  __device__ __forceinline__ void init_hf(double2* lds, uint32_t base, uint32_t tileN,
-                                          uint32_t hf) const {
-    if constexpr (KT == 0) {
-      for (uint32_t c = threadIdx.x; c < tileN; c += T)
-        lds[c] = make_double2((base | dep(c, lmask)) == hf ? 1.0 : 0.0, 0.0);
-    } else {
-      init_j(lds, base, hf);
-    }
-  }
-  __device__ __forceinline__ void store(const double2* lds, double2* __restrict__ v, uint32_t base,
-                                        uint32_t tileN) const {
-    if constexpr (KT == 0) {
-      for (uint32_t c = threadIdx.x; c < tileN; c += T) v[base | dep(c, lmask)] = lds[c];
-    } else {
-      store_j(lds, v, base);
-    }
   }
 };
 

@@ -229,6 +229,16 @@ def test_18q_batch64_against_stored_oracle_values(ucc):
         b = int(b)
         assert abs(e[b] - ent["energy"]) <= E_TOL, b
         assert np.max(np.abs(gr[b] - np.array(ent["grad"]))) <= G_TOL, b
+    # the launch configuration the benchmark times: tiles and workgroup sizes autotuned at
+    # batch 64 on this device
+    tuned = ucc.Context(n, ne, h1, h2, exc, max_batch=64, autotune=True)
+    say(f"autotuned: {tuned.plan_info()}")
+    et, gt = tuned.energy_grad(th)
+    for b, ent in gold["entries"].items():
+        b = int(b)
+        assert abs(et[b] - ent["energy"]) <= E_TOL, b
+        assert np.max(np.abs(gt[b] - np.array(ent["grad"]))) <= G_TOL, b
+    assert np.max(np.abs(et - e)) <= E_TOL and np.max(np.abs(gt - gr)) <= G_TOL
     # every entry returned the state to |HF> (the reverse sweep undoes the forward one)
     hf = (1 << ne) - 1
     for b in (0, 31, 63):
@@ -240,6 +250,46 @@ def test_18q_batch64_against_stored_oracle_values(ucc):
     assert e1[0] == e[1] and np.array_equal(g1[0], gr[1])
     e_only = ctx.energy(th)
     assert np.max(np.abs(e_only - e)) <= 1e-12
+
+
+def shift_rule_check(ucc, ctx, th, ks, batch):
+    """g_k against the exact four-point shift rule on the GPU's own energies (E is a trig
+    polynomial of degree 2 in each theta_k, since G_k^3 = -G_k), for the components ks."""
+    c = (np.sqrt(2.0) - 1.0) / 2.0
+    shifts = (np.pi / 4, -np.pi / 4, np.pi / 2, -np.pi / 2)
+    _, g = ctx.energy_grad(th)
+    rows = []
+    for k in ks:
+        for d in shifts:
+            t = th.copy()
+            t[k] += d
+            rows.append(t)
+    rows = np.array(rows)
+    es = np.concatenate([ctx.energy(rows[i:i + batch]) for i in range(0, len(rows), batch)])
+    for j, k in enumerate(ks):
+        ep, em, ep2, em2 = es[4 * j:4 * j + 4]
+        assert abs(((ep - em) - c * (ep2 - em2)) - g[0][k]) <= G_TOL, k
+
+
+def test_18q_gradient_shift_rule(ucc):
+    say("case: 18q/10e gradient vs four-point shift rule, 16 components, autotuned batch 64")
+    n, ne = 18, 10
+    h1, h2 = make_integrals(n // 2, 7)
+    exc = uccsd_excitations(n, ne)
+    th = make_thetas(len(exc), 8, 0.1)
+    ctx = ucc.Context(n, ne, h1, h2, exc, max_batch=64, autotune=True)
+    ks = list(np.linspace(0, len(exc) - 1, 16).astype(int))
+    shift_rule_check(ucc, ctx, th, ks, 64)
+
+
+def test_26q_gradient_shift_rule(ucc):
+    say("case: 26q/14e gradient vs four-point shift rule, 2 components")
+    n, ne = 26, 14
+    h1, h2 = make_integrals(n // 2, 9)
+    exc = uccsd_excitations(n, ne)
+    th = make_thetas(len(exc), 10, 0.05)
+    ctx = ucc.Context(n, ne, h1, h2, exc)
+    shift_rule_check(ucc, ctx, th, [0, len(exc) - 1], 8)
 
 
 def test_26q_theta_zero_closed_forms(ucc):
