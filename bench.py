@@ -240,6 +240,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--launch-mode", type=int, default=0)
+    ap.add_argument("--store-states", type=int, default=0,
+                    help="0 auto, 1 keep forward states for the reverse sweep, 2 recompute")
     ap.add_argument("--no-autotune", action="store_true",
                     help="use the fixed tuning table instead of timing the candidates")
     ap.add_argument("--no-extra", action="store_true",
@@ -270,7 +272,7 @@ def main():
     K = len(exc)
     thetas = make_thetas(K, TSEED, SCALE, batch=BATCH)
     ctx = ucc.Context(N, NE, h1, h2, exc, max_batch=BATCH, device=0, launch_mode=args.launch_mode,
-                      autotune=not args.no_autotune)
+                      autotune=not args.no_autotune, store_states=args.store_states)
     info = ctx.plan_info()
     td = torch.tensor(thetas, device=dev, dtype=torch.float64)
 
@@ -354,6 +356,7 @@ def main():
                                                  info["block_threads_exp"],
                                                  info["block_threads_rev"]],
                    "autotuned": bool(info["autotuned"]), "launch_mode": info["launch_mode"],
+                   "store_states": info["store_states"],
                    "integral_seed": ISEED, "theta_seeds": "1..64", "theta_scale": SCALE},
         "p50_ms": float(np.percentile(step_ms, 50)),
         "p99_ms": float(np.percentile(step_ms, 99)),

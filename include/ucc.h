@@ -73,7 +73,16 @@ typedef struct {
                                 kinds left automatic on this device at batch max(1, max_batch)
                                 during ucc_build and keep the fastest (results are cached per
                                 process by (n_qubits, n_elec, n_exc, batch)); 0: fixed table */
-  int32_t reserved[2];
+  int32_t store_states;      /* 0 auto (1 when n_qubits <= 20 and the tile options allow it);
+                                1 gradient calls keep the state each forward pass leaves (the
+                                last one is the state buffer itself), and the reverse sweep
+                                reads them instead of recomputing the state: a reverse pass
+                                then streams psi in and lambda in and out (3 state streams
+                                instead of 4), its passes are the forward passes in mirror
+                                order, so tile_qubits = tile_qubits_rev <= 13; costs
+                                (n_fwd_passes - 1) extra state vectors per theta vector;
+                                2 recompute (the reverse sweep runs psi back to |HF>) */
+  int32_t reserved[1];
 } ucc_options;
 
 /* Fill *opt with defaults (all automatic, launch_mode 0, max_batch 1). */
@@ -117,8 +126,9 @@ ucc_status ucc_energy(ucc_ctx* ctx, const double* theta, int32_t B, double* ener
  * ucc_energy_grad -- energies and gradients dE_b/dtheta_{b,k} by the adjoint method.
  *
  *   grad    [B * n_exc] float64, host or device pointer
- * Other arguments as ucc_energy.  The reverse sweep returns the state buffer to |HF>, so
- * after this call ucc_get_state reports |HF> (to rounding).
+ * Other arguments as ucc_energy.  After the call the context holds Psi(theta_b) if the plan
+ * stores forward states (ucc_plan_info.store_states = 1); otherwise the reverse sweep has run
+ * the state buffer back to |HF> and ucc_get_state reports |HF> (to rounding).
  */
 ucc_status ucc_energy_grad(ucc_ctx* ctx, const double* theta, int32_t B, double* energy,
                            double* grad, void* stream);
@@ -150,6 +160,7 @@ typedef struct {
   int32_t contiguous_fwd, contiguous_exp, contiguous_rev;
   int32_t block_threads_fwd, block_threads_exp, block_threads_rev, launch_mode;
   int32_t autotuned;         /* 1 if the choices above come from measurement */
+  int32_t store_states;      /* 1 if gradient calls keep the forward states (ucc_options) */
   int32_t perm[32];          /* physical bit of logical qubit q (q < n_qubits) */
   int64_t job_footprint;     /* device bytes one server job on this context holds */
 } ucc_plan_info;

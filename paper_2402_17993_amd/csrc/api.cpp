@@ -59,6 +59,7 @@ void free_ptr(void* p) {
 void free_buffers(Buffers& b) {
   free_ptr(b.psi);
   free_ptr(b.lam);
+  free_ptr(b.ck);
   free_ptr(b.theta);
   free_ptr(b.cs);
   free_ptr(b.epart);
@@ -92,6 +93,7 @@ ucc_status ensure_buffers(const ucc_ctx* c, Buffers& b, int B, bool need_lam) {
       {reinterpret_cast<void**>(&b.G), cap * size_t(p.K) * 8},
       {reinterpret_cast<void**>(&b.lam), lam ? cap * S * 16 : 0},
       {reinterpret_cast<void**>(&b.gpart), lam ? cap * size_t(p.K) * ntr * 8 : 0},
+      {reinterpret_cast<void**>(&b.ck), lam && p.ckpt ? size_t(p.nfwd - 1) * cap * S * 16 : 0},
   };
   for (auto& r : reqs) {
     if (r.bytes == 0) continue;
@@ -193,14 +195,22 @@ ucc_status enqueue_eval(const ucc_ctx* c, Buffers& b, const double* d_theta, int
   if (p.launch_mode == 2) {  // the whole evaluation in one launch: theta in, state, E and G out
     const double bytes = 8.0 * B * p.K + S + 8.0 * B * (1 + (grad ? p.K : 0));
     hipError_t e = timed(UCC_KERNEL_WHOLE, bytes,
-                         [&] { return launch_whole(a, d_theta, grad, p.nfwd, p.nexp, p.nrev); });
+                         [&] { return launch_whole(a, d_theta, grad, p.nfwd, p.nexp, p.nrev, p.ckpt); });
     if (e != hipSuccess) return hip_fail(e, "launch k_whole");
     return UCC_OK;
   }
+  // Stored states (gradient calls of such plans): forward pass i writes state i (the last
+  // one into psi) from state i - 1, and the reverse pass of forward window w reads state w.
+  // Otherwise every pass works on psi in place.
+  const bool ck = grad && p.ckpt;
+  const size_t cstride = size_t(b.cap) << p.n;
+  auto state = [&](int w) { return w == p.nfwd - 1 ? b.psi : b.ck + w * cstride; };
   hipError_t e = timed(UCC_KERNEL_TRIG, 24.0 * B * p.K, [&] { return launch_trig(a, d_theta); });
   if (e != hipSuccess) return hip_fail(e, "launch k_trig");
   for (int i = 0; i < p.nfwd; ++i) {
-    e = timed(UCC_KERNEL_FWD, i == 0 ? S : 2 * S, [&] { return launch_fwd(a, i, i == 0); });
+    double2* dst = ck ? state(i) : b.psi;
+    const double2* src = ck && i > 0 ? state(i - 1) : dst;
+    e = timed(UCC_KERNEL_FWD, i == 0 ? S : 2 * S, [&] { return launch_fwd(a, i, i == 0, src, dst); });
     if (e != hipSuccess) return hip_fail(e, "launch k_fwd");
   }
   const int nte = 1 << (p.n - p.ke);
@@ -212,7 +222,9 @@ ucc_status enqueue_eval(const ucc_ctx* c, Buffers& b, const double* d_theta, int
   }
   if (grad)
     for (int j = 0; j < p.nrev; ++j) {
-      e = timed(UCC_KERNEL_REV, 4 * S, [&] { return launch_rev(a, p.nfwd + p.nexp + j); });
+      e = timed(UCC_KERNEL_REV, ck ? 3 * S : 4 * S, [&] {
+        return launch_rev(a, p.nfwd + p.nexp + j, ck ? state(p.nfwd - 1 - j) : b.psi, !ck);
+      });
       if (e != hipSuccess) return hip_fail(e, "launch k_rev");
     }
   const double rb = 8.0 * B * (double(p.nexp) * nte + (grad ? double(p.K) * (1 << (p.n - p.kr)) : 0.0));
@@ -285,10 +297,11 @@ ucc_status resolve_launch_mode(ucc_ctx* c) {
 
 ucc_status replan(ucc_ctx* c, int kf, int ke, int kr) {
   Plan& p = c->plan;
+  if (p.ckpt) kr = kf;
   if (p.kf == kf && p.ke == ke && p.kr == kr) return UCC_OK;
   Plan np;
   const std::string msg = build_plan(np, p.n, p.ne, p.h1.data(), p.h2.data(), p.exc.data(), p.K,
-                                     kf, ke, kr, c->opt.contiguous_qubits);
+                                     kf, ke, kr, c->opt.contiguous_qubits, p.ckpt);
   if (!msg.empty()) return fail(UCC_EINVAL, msg);
   np.tf = p.tf;
   np.te = p.te;
@@ -369,6 +382,10 @@ ucc_status ucc_build(int32_t n_qubits, int32_t n_elec, const double* h1, const d
   if (o.launch_mode < 0 || o.launch_mode > 2) return fail(UCC_EINVAL, "launch_mode must be 0..2");
   if (o.max_batch < 0) return fail(UCC_EINVAL, "max_batch must be >= 0");
   if (o.autotune && o.host_only) return fail(UCC_EINVAL, "autotune needs a device context");
+  if (o.store_states < 0 || o.store_states > 2) return fail(UCC_EINVAL, "store_states must be 0..2");
+  if (o.store_states == 1 &&
+      (o.tile_qubits > 13 || (o.tile_qubits && o.tile_qubits_rev && o.tile_qubits != o.tile_qubits_rev)))
+    return fail(UCC_EINVAL, "store_states 1 needs one tile size of at most 13 for both sweeps");
 
   ucc_ctx* c = new (std::nothrow) ucc_ctx();
   if (!c) return fail(UCC_ENOMEM, "host allocation failed");
@@ -376,7 +393,7 @@ ucc_status ucc_build(int32_t n_qubits, int32_t n_elec, const double* h1, const d
   c->host_only = o.host_only != 0;
   const Tuning tu = choose_tuning(n_qubits, n_exc, std::max(1, o.max_batch), o);
   msg = build_plan(c->plan, n_qubits, n_elec, h1, h2, exc, n_exc, tu.kf, tu.ke, tu.kr,
-                   o.contiguous_qubits);
+                   o.contiguous_qubits, tu.ckpt);
   if (!msg.empty()) {
     delete c;
     return fail(UCC_EINVAL, msg);
@@ -525,6 +542,7 @@ ucc_status ucc_get_plan_info(const ucc_ctx* c, ucc_plan_info* info) {
   info->block_threads_rev = p.tr;
   info->autotuned = p.autotuned ? 1 : 0;
   info->launch_mode = p.launch_mode;
+  info->store_states = p.ckpt ? 1 : 0;
   for (int q = 0; q < p.n; ++q) info->perm[q] = p.perm[q];
   info->job_footprint = (int64_t)entry_footprint(c);
   return UCC_OK;

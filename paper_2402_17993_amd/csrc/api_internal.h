@@ -20,6 +20,8 @@ struct Buffers {
   int cap = 0;
   double2* psi = nullptr;  // [cap][2^n]
   double2* lam = nullptr;  // [cap][2^n] (gradient calls only)
+  double2* ck = nullptr;   // [n_fwd - 1][cap][2^n]: the states forward passes 0 .. n_fwd - 2
+                           // leave (gradient calls of stored-state plans; the last is psi)
   double* theta = nullptr; // [cap][K]
   double2* cs = nullptr;   // [cap][K] (cos, sin)
   double* epart = nullptr; // [cap][n_exp_passes * tiles]
@@ -44,6 +46,7 @@ struct Profiler {
 
 struct Tuning {
   int kf = 14, ke = 14, kr = 13, tf = 1024, te = 1024, tr = 512, launch_mode = 1;
+  bool ckpt = false;  // stored forward states (then kr == kf)
 };
 
 }  // namespace ucc
@@ -86,6 +89,8 @@ ucc_status enqueue_eval(const ucc_ctx* c, Buffers& b, const double* d_theta, int
 bool batch_compatible(const ucc_ctx* a, const ucc_ctx* b);
 // Device bytes one batch entry of this context occupies in a server group.
 size_t entry_footprint(const ucc_ctx* c);
+// Whether a plan for n qubits under options o stores forward states (store_states 0 = auto).
+bool stores_states(int n, const ucc_options& o);
 Tuning choose_tuning(int n, int K, int batch, const ucc_options& o);
 void apply_tuning(Plan& p, const Tuning& tu);
 bool whole_launch_fits(const Plan& p, const Tables& t);

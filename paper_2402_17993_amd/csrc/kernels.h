@@ -34,13 +34,17 @@ struct LaunchArgs {
 int device_cus();
 
 hipError_t launch_trig(const LaunchArgs& a, const double* theta);
-hipError_t launch_fwd(const LaunchArgs& a, int pidx, int init);
+// Forward pass pidx from state src into state dst (src == dst: in place; init: src unused).
+hipError_t launch_fwd(const LaunchArgs& a, int pidx, int init, const double2* src, double2* dst);
 hipError_t launch_exp(const LaunchArgs& a, int pidx, int eslot, int first, bool apply);
-hipError_t launch_rev(const LaunchArgs& a, int pidx);
+// Reverse pass pidx on (psi, a.lam); write_psi = 0: psi is a stored state, read only.
+hipError_t launch_rev(const LaunchArgs& a, int pidx, double2* psi, bool write_psi);
 hipError_t launch_reduce(const LaunchArgs& a, int ne, bool grad, int nt);
 // Whole evaluation of a one-tile plan in one launch (one 256-thread workgroup per entry).
+// fwd_state: the state written to psi is Psi(theta) also for gradient calls (else the state
+// the reverse sweep ends on).
 hipError_t launch_whole(const LaunchArgs& a, const double* theta, bool grad, int nfwd, int nexp,
-                        int nrev);
+                        int nrev, bool fwd_state);
 // Dynamic LDS bytes of that launch (host and planner use the same formula).
 inline size_t whole_lds(int K, int ns, int max_blk, int max_blob, int max_slots, int max_occ, int n) {
   return 16 * size_t(K) + 32 * size_t(ns) + 16 * size_t(max_blob) +

@@ -600,13 +600,14 @@ __device__ __forceinline__ double exp_rows(const double2* cp, const uint32_t* bl
 // stores of step 4 and step 1 of the next item waits for nothing issued after them.
 //
 // Forward pass: U_k = exp(theta_k G_k) in Trotter order, each a Givens rotation on the
-// tile's in-sector pairs (u, u ^ supp) listed in the class block.
+// tile's in-sector pairs (u, u ^ supp) listed in the class block.  Tiles are read from src
+// and written to psi (the same vectors for an in-place pass; INIT reads nothing).
 template <int T, int KT, bool INIT>
 __global__ __launch_bounds__(T) LDS_BOUND_OCCUPANCY void k_fwd(
     const DevPass* __restrict__ passes, int pidx, const DevExc* __restrict__ exc,
     const int2* __restrict__ pcls, const uint32_t* __restrict__ pairs,
-    const double2* __restrict__ cs, int K, double2* __restrict__ psi, int n, uint32_t hf,
-    uint32_t amask, uint32_t bmask, int total) {
+    const double2* __restrict__ cs, int K, const double2* src, double2* __restrict__ psi, int n,
+    uint32_t hf, uint32_t amask, uint32_t bmask, int total) {
   extern __shared__ double2 lds[];
   __shared__ PassStage st;
   using TL = Tile<T, KT>;
@@ -629,6 +630,7 @@ __global__ __launch_bounds__(T) LDS_BOUND_OCCUPANCY void k_fwd(
   auto cs_of = [&](int it) { return cs[(size_t)(it >> tb) * K + st.x[threadIdx.x].k]; };
   auto base_of = [&](int it) { return dep(it & tmask, ps.gmask); };
   auto vec_of = [&](int it) { return psi + ((size_t)(it >> tb) << n); };
+  auto src_of = [&](int it) { return src + ((size_t)(it >> tb) << n); };
   auto stage_class = [&](uint32_t base) {
     const int cl = tile_class(base, amask, bmask, ps.nbeta_g);
     if (cl != staged) {
@@ -638,7 +640,7 @@ __global__ __launch_bounds__(T) LDS_BOUND_OCCUPANCY void k_fwd(
     }
   };
   stage_class(base_of(item));
-  if (RP && !INIT) tm.fetch(r, vec_of(item), base_of(item));
+  if (RP && !INIT) tm.fetch(r, src_of(item), base_of(item));
   if (cst) st.cs[threadIdx.x] = cs_of(item);
   const uint32_t* off = blk + 2;
   const dvec2 zero = {0.0, 0.0};
@@ -653,14 +655,14 @@ __global__ __launch_bounds__(T) LDS_BOUND_OCCUPANCY void k_fwd(
       else
         SC::take(r, cp, rtab, insec);
     } else {
-      take_loop<T, INIT>(ps.lmask, tileN, cp, rtab, v, base, hf);
+      take_loop<T, INIT>(ps.lmask, tileN, cp, rtab, src_of(item), base, hf);
     }
     __syncthreads();
     const int next = item + gridDim.x;
     double2 csv = make_double2(1.0, 0.0);
     if (next < total) {
       tm.refresh();
-      if (RP && !INIT) tm.fetch(r, vec_of(next), base_of(next));
+      if (RP && !INIT) tm.fetch(r, src_of(next), base_of(next));
       if (cst) csv = cs_of(next);
     }
     const int m = (int)blk[1], ns = (int)blk[0];
@@ -683,8 +685,10 @@ __global__ __launch_bounds__(T) LDS_BOUND_OCCUPANCY void k_fwd(
 
 // Reverse pass: for each excitation (descending k) the partial of <lambda|G_k|psi> over the
 // tile's in-sector pairs, then psi, lambda <- exp(-theta_k G_k) (psi, lambda).  Per-item
-// gradient partials collect in LDS and are stored with the tiles.
-template <int T, int KT>
+// gradient partials collect in LDS and are stored with the tiles.  WP = false: psi is the
+// stored state the matching forward window left; it is read and never written (the state
+// this pass ends on is the previous stored state).
+template <int T, int KT, bool WP>
 __global__ __launch_bounds__(T) LDS_BOUND_OCCUPANCY void k_rev(
     const DevPass* __restrict__ passes, int pidx, const DevExc* __restrict__ exc,
     const int2* __restrict__ pcls, const uint32_t* __restrict__ pairs,
@@ -768,13 +772,13 @@ __global__ __launch_bounds__(T) LDS_BOUND_OCCUPANCY void k_rev(
     }
     if constexpr (RP) {
       tm.refresh();
-      SC::put_zeros(tm, vp, base, insec, zero);
+      if (WP) SC::put_zeros(tm, vp, base, insec, zero);
       SC::put_zeros(tm, vl, base, insec, zero);
     } else {
-      zeros_loop<T>(ps.lmask, tileN, rtab, vp, base);
+      if (WP) zeros_loop<T>(ps.lmask, tileN, rtab, vp, base);
       zeros_loop<T>(ps.lmask, tileN, rtab, vl, base);
     }
-    put_list<T>(cp, sphys, ns, vp, base);
+    if (WP) put_list<T>(cp, sphys, ns, vp, base);
     put_list<T>(cl, sphys, ns, vl, base);
     if (next >= total) break;
     __syncthreads();  // cp, cl, the table, red and the (cos, sin) stage are no longer read
@@ -890,8 +894,9 @@ __global__ __launch_bounds__(T) LDS_BOUND_OCCUPANCY void k_exp(
 // one workgroup per batch entry keeps the in-sector amplitudes of psi and lambda in LDS
 // through all passes.  It forms cos/sin, synthesizes |HF>, runs the forward passes, the
 // expectation / apply-H passes (energy summed in pass order) and, with GRAD, the reverse
-// passes (dE/dtheta_k = 2 sum of the per-wave partials), then writes the final state as a whole
-// vector (zeros outside the sector).  The pass bodies are those of the per-pass kernels.
+// passes (dE/dtheta_k = 2 sum of the per-wave partials).  The state is written as a whole
+// vector (zeros outside the sector): Psi(theta) after the forward passes with fwd_state, else
+// the state the launch ends on.  The pass bodies are those of the per-pass kernels.
 template <int T, bool GRAD>
 __global__ __launch_bounds__(T) void k_whole(
     const DevPass* __restrict__ passes, int nfwd, int nexp, int nrev,
@@ -899,7 +904,7 @@ __global__ __launch_bounds__(T) void k_whole(
     const uint32_t* __restrict__ blocks, const uint4* __restrict__ blobs, int bstride,
     const double* __restrict__ theta, int K, double2* __restrict__ psi, int n, uint32_t hf,
     double* __restrict__ E, double* __restrict__ G, int ns, int max_blk, int max_blob,
-    int max_slots, int max_occ) {
+    int max_slots, int max_occ, int fwd_state) {
   extern __shared__ double2 lds[];
   constexpr int NW = T / 64;
   __shared__ PassStage st;
@@ -946,11 +951,21 @@ __global__ __launch_bounds__(T) void k_whole(
     stage_words<T>(blk, blocks + bl.x, bl.y);
     __syncthreads();
   };
+  // the state as a whole vector: zeros, then (after the workgroup barrier orders them) the
+  // in-sector values at their indices (the list of the staged forward/reverse block)
+  double2* __restrict__ v = psi + ((size_t)b << n);
+  auto write_state = [&]() {
+    for (uint32_t c = threadIdx.x; c < (1u << n); c += T) st16(v + c, dvec2{0.0, 0.0});
+    __syncthreads();
+    const uint16_t* sl = reinterpret_cast<const uint16_t*>(blk + 3 + (int)blk[1]);
+    for (int i = threadIdx.x; i < ns; i += T) st16(v + sl[i], ld16(cp + i));
+  };
   for (int q = 0; q < nfwd; ++q) {
     const DevPass ps = passes[q];
     stage_pass(ps);
     fwd_excitations<T>(cp, blk, st, ps.count, 0u);
   }
+  if (fwd_state) write_state();
   double etot = 0.0;
   for (int j = 0; j < nexp; ++j) {
     const DevPass ps = passes[nfwd + j];
@@ -980,13 +995,10 @@ __global__ __launch_bounds__(T) void k_whole(
     }
   }
   if (threadIdx.x == 0) E[b] = etot;
-  // the final state: zeros everywhere, then (after the workgroup barrier orders them) the
-  // in-sector values at their indices (the list of the staged forward block, restaged)
-  double2* __restrict__ v = psi + ((size_t)b << n);
-  for (uint32_t c = threadIdx.x; c < (1u << n); c += T) st16(v + c, dvec2{0.0, 0.0});
-  stage_pass(p0);
-  const uint16_t* sl = reinterpret_cast<const uint16_t*>(blk + 3 + (int)blk[1]);
-  for (int i = threadIdx.x; i < ns; i += T) st16(v + sl[i], ld16(cp + i));
+  if (!fwd_state) {
+    stage_pass(p0);  // a forward block (the expectation block has another layout)
+    write_state();
+  }
 }
 
 // Fixed-order reductions.  epart: [B][ne] energy partials; gpart: [B][K][nt] gradient partials.
@@ -1074,7 +1086,7 @@ inline size_t sc_lds(const DevPass& hp, int vectors) {
 }
 
 template <int T, int KT, bool INIT>
-hipError_t fwd_ti(const LaunchArgs& a, int pidx) {
+hipError_t fwd_ti(const LaunchArgs& a, int pidx, const double2* src, double2* dst) {
   const DevPass& hp = a.hpasses[pidx];
   const int k = hp.k;
   const size_t lds = sc_lds(hp, 1);
@@ -1083,28 +1095,35 @@ hipError_t fwd_ti(const LaunchArgs& a, int pidx) {
   const int total = a.B << (a.n - k);
   const int grid = pass_grid(total, resident_grid(k_fwd<T, KT, INIT>, T, lds, a.cu_share), 1 << (a.n - k));
   hipLaunchKernelGGL((k_fwd<T, KT, INIT>), dim3(grid), dim3(T), lds, a.stream, a.passes, pidx,
-                     a.exc, a.cls, a.pairs, a.cs, a.K, a.psi, a.n, a.hf, a.amask, a.bmask, total);
+                     a.exc, a.cls, a.pairs, a.cs, a.K, src, dst, a.n, a.hf, a.amask, a.bmask,
+                     total);
   return hipGetLastError();
 }
 
 template <int T, int KT>
-hipError_t fwd_t(const LaunchArgs& a, int pidx, int init) {
-  return init ? fwd_ti<T, KT, true>(a, pidx) : fwd_ti<T, KT, false>(a, pidx);
+hipError_t fwd_t(const LaunchArgs& a, int pidx, int init, const double2* src, double2* dst) {
+  return init ? fwd_ti<T, KT, true>(a, pidx, src, dst) : fwd_ti<T, KT, false>(a, pidx, src, dst);
 }
 
-template <int T, int KT>
-hipError_t rev_t(const LaunchArgs& a, int pidx) {
+template <int T, int KT, bool WP>
+hipError_t rev_tw(const LaunchArgs& a, int pidx, double2* psi) {
   const DevPass& hp = a.hpasses[pidx];
   const int k = hp.k;
   const size_t lds = sc_lds(hp, 2);
-  hipError_t e = set_lds(k_rev<T, KT>, lds);
+  hipError_t e = set_lds(k_rev<T, KT, WP>, lds);
   if (e != hipSuccess) return e;
   const int total = a.B << (a.n - k);
-  const int grid = pass_grid(total, resident_grid(k_rev<T, KT>, T, lds, a.cu_share), 1 << (a.n - k));
-  hipLaunchKernelGGL((k_rev<T, KT>), dim3(grid), dim3(T), lds, a.stream, a.passes, pidx, a.exc,
-                     a.cls, a.pairs, a.cs, a.K, a.psi, a.lam, a.n, a.amask, a.bmask, a.gpart,
+  const int grid =
+      pass_grid(total, resident_grid(k_rev<T, KT, WP>, T, lds, a.cu_share), 1 << (a.n - k));
+  hipLaunchKernelGGL((k_rev<T, KT, WP>), dim3(grid), dim3(T), lds, a.stream, a.passes, pidx,
+                     a.exc, a.cls, a.pairs, a.cs, a.K, psi, a.lam, a.n, a.amask, a.bmask, a.gpart,
                      total);
   return hipGetLastError();
+}
+
+template <int T, int KT>
+hipError_t rev_t(const LaunchArgs& a, int pidx, double2* psi, bool wp) {
+  return wp ? rev_tw<T, KT, true>(a, pidx, psi) : rev_tw<T, KT, false>(a, pidx, psi);
 }
 
 template <int T, int KT, bool APPLY>
@@ -1128,22 +1147,22 @@ hipError_t exp_t(const LaunchArgs& a, int pidx, int eslot, int first) {
 // Tile-size dispatch: unrolled register staging where the tile fits in at most 32 elements
 // per thread (16 for the two-vector reverse pass), a loop otherwise.
 template <int T>
-hipError_t fwd_k(const LaunchArgs& a, int pidx, int init) {
+hipError_t fwd_k(const LaunchArgs& a, int pidx, int init, const double2* src, double2* dst) {
   const int k = a.hpasses[pidx].k;
   if constexpr (T >= 512)
-    if (k == 14) return fwd_t<T, 14>(a, pidx, init);
-  if (k == 13) return fwd_t<T, 13>(a, pidx, init);
-  if (k == 12) return fwd_t<T, 12>(a, pidx, init);
-  return fwd_t<T, 0>(a, pidx, init);
+    if (k == 14) return fwd_t<T, 14>(a, pidx, init, src, dst);
+  if (k == 13) return fwd_t<T, 13>(a, pidx, init, src, dst);
+  if (k == 12) return fwd_t<T, 12>(a, pidx, init, src, dst);
+  return fwd_t<T, 0>(a, pidx, init, src, dst);
 }
 
 template <int T>
-hipError_t rev_k(const LaunchArgs& a, int pidx) {
+hipError_t rev_k(const LaunchArgs& a, int pidx, double2* psi, bool wp) {
   const int k = a.hpasses[pidx].k;
   if constexpr (T >= 512)
-    if (k == 13) return rev_t<T, 13>(a, pidx);
-  if (k == 12) return rev_t<T, 12>(a, pidx);
-  return rev_t<T, 0>(a, pidx);
+    if (k == 13) return rev_t<T, 13>(a, pidx, psi, wp);
+  if (k == 12) return rev_t<T, 12>(a, pidx, psi, wp);
+  return rev_t<T, 0>(a, pidx, psi, wp);
 }
 
 template <int T, bool APPLY>
@@ -1164,19 +1183,19 @@ hipError_t launch_trig(const LaunchArgs& a, const double* theta) {
   return hipGetLastError();
 }
 
-hipError_t launch_fwd(const LaunchArgs& a, int pidx, int init) {
+hipError_t launch_fwd(const LaunchArgs& a, int pidx, int init, const double2* src, double2* dst) {
   switch (a.tf) {
-    case 256: return fwd_k<256>(a, pidx, init);
-    case 1024: return fwd_k<1024>(a, pidx, init);
-    default: return fwd_k<512>(a, pidx, init);
+    case 256: return fwd_k<256>(a, pidx, init, src, dst);
+    case 1024: return fwd_k<1024>(a, pidx, init, src, dst);
+    default: return fwd_k<512>(a, pidx, init, src, dst);
   }
 }
 
-hipError_t launch_rev(const LaunchArgs& a, int pidx) {
+hipError_t launch_rev(const LaunchArgs& a, int pidx, double2* psi, bool write_psi) {
   switch (a.tr) {
-    case 256: return rev_k<256>(a, pidx);
-    case 1024: return rev_k<1024>(a, pidx);
-    default: return rev_k<512>(a, pidx);
+    case 256: return rev_k<256>(a, pidx, psi, write_psi);
+    case 1024: return rev_k<1024>(a, pidx, psi, write_psi);
+    default: return rev_k<512>(a, pidx, psi, write_psi);
   }
 }
 
@@ -1196,7 +1215,7 @@ hipError_t launch_exp(const LaunchArgs& a, int pidx, int eslot, int first, bool 
 }
 
 hipError_t launch_whole(const LaunchArgs& a, const double* theta, bool grad, int nfwd, int nexp,
-                        int nrev) {
+                        int nrev, bool fwd_state) {
   int ns = 0, max_blk = 0, max_blob = 0, max_slots = 0, max_occ = 0;
   for (int i = 0; i < nfwd + nexp + nrev; ++i) {
     const DevPass& hp = a.hpasses[i];
@@ -1214,7 +1233,8 @@ hipError_t launch_whole(const LaunchArgs& a, const double* theta, bool grad, int
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(kern, dim3(a.B), dim3(256), lds, a.stream, a.passes, nfwd, nexp, nrev,
                        a.exc, a.cls, a.pairs, a.blobs, a.blob_stride, theta, a.K, a.psi, a.n,
-                       a.hf, a.E, a.G, ns, max_blk, max_blob, max_slots, max_occ);
+                       a.hf, a.E, a.G, ns, max_blk, max_blob, max_slots, max_occ,
+                       fwd_state ? 1 : 0);
     return hipGetLastError();
   };
   return grad ? go(k_whole<256, true>) : go(k_whole<256, false>);

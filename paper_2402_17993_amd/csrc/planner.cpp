@@ -232,7 +232,7 @@ std::string validate_inputs(int n, int ne, const double* h1, const double* h2, c
 }
 
 std::string build_plan(Plan& p, int n, int ne, const double* h1, const double* h2,
-                       const int32_t* exc, int K, int kf, int ke, int kr, int c0) {
+                       const int32_t* exc, int K, int kf, int ke, int kr, int c0, bool ckpt) {
   p = Plan();
   p.n = n;
   p.ne = ne;
@@ -423,9 +423,10 @@ std::string build_plan(Plan& p, int n, int ne, const double* h1, const double* h
   }
 
   // ---- pass plan.
+  p.ckpt = ckpt;
   p.kf = std::min(kf, n);
   p.ke = std::min(ke, n);
-  p.kr = std::min(kr, n);
+  p.kr = ckpt ? p.kf : std::min(kr, n);
   auto best_windows = [&](int kind, int k, int& c0_out) {
     std::vector<Plan::Pass> best;
     const int req = pick_c0(k, c0);
@@ -441,7 +442,8 @@ std::string build_plan(Plan& p, int n, int ne, const double* h1, const double* h
     return best;
   };
   auto fw = best_windows(kFwd, p.kf, p.c0f);
-  auto rv = best_windows(kRev, p.kr, p.c0r);
+  std::vector<Plan::Pass> rv;
+  if (!ckpt) rv = best_windows(kRev, p.kr, p.c0r);
   std::vector<Plan::Pass> ex;
   {
     const int req = pick_c0(p.ke, c0);
@@ -487,8 +489,21 @@ std::string build_plan(Plan& p, int n, int ne, const double* h1, const double* h
     return true;
   };
   // static LDS: the pass stage, plus per-wave gradient partials of up to 16 waves (reverse)
-  if (!fit_blocks(fw, 1, kStageBytes) || !fit_blocks(rv, 2, kStageBytes + 16 * 8 * kMaxPassExc))
+  const int rev_static = kStageBytes + 16 * 8 * kMaxPassExc;
+  if (ckpt) {
+    // one window list for both sweeps: it must fit the two-vector reverse pass; the reverse
+    // pass of window w starts from the state forward window w left (stored)
+    if (!fit_blocks(fw, 2, rev_static)) return "tile too large for the pair lists of one excitation";
+    p.c0r = p.c0f;
+    for (auto it = fw.rbegin(); it != fw.rend(); ++it) {
+      Plan::Pass r = *it;
+      r.kind = kRev;
+      std::reverse(r.items.begin(), r.items.end());
+      rv.push_back(r);
+    }
+  } else if (!fit_blocks(fw, 1, kStageBytes) || !fit_blocks(rv, 2, rev_static)) {
     return "tile too large for the pair lists of one excitation";
+  }
   p.nfwd = (int)fw.size();
   p.nexp = (int)ex.size();
   p.nrev = (int)rv.size();

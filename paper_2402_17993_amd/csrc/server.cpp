@@ -47,7 +47,8 @@ bool batch_compatible(const ucc_ctx* a, const ucc_ctx* b) {
       p.c0f != q.c0f ||
       p.c0e != q.c0e || p.c0r != q.c0r || p.tf != q.tf || p.te != q.te || p.tr != q.tr ||
       p.launch_mode != q.launch_mode || p.nfwd != q.nfwd || p.nexp != q.nexp || p.nrev != q.nrev ||
-      p.hf != q.hf || p.amask != q.amask || p.bmask != q.bmask || a->device != b->device)
+      p.hf != q.hf || p.amask != q.amask || p.bmask != q.bmask || p.ckpt != q.ckpt ||
+      a->device != b->device)
     return false;
   if (!same_bytes(p.exc, q.exc) || p.groups.size() != q.groups.size() || p.passes.size() != q.passes.size())
     return false;
@@ -70,8 +71,9 @@ size_t entry_footprint(const ucc_ctx* c) {
   const Plan& p = c->plan;
   const size_t S = size_t(16) << p.n;
   const size_t nte = size_t(1) << (p.n - p.ke), ntr = size_t(1) << (p.n - p.kr);
-  return 2 * S + size_t(p.K) * (8 + 16 + 8) + 8 + 8 * size_t(p.nexp) * nte + 8 * size_t(p.K) * ntr +
-         4 * c->tab.blob.size();
+  const size_t stored = p.ckpt ? size_t(p.nfwd - 1) * S : 0;
+  return 2 * S + stored + size_t(p.K) * (8 + 16 + 8) + 8 + 8 * size_t(p.nexp) * nte +
+         8 * size_t(p.K) * ntr + 4 * c->tab.blob.size();
 }
 
 namespace {

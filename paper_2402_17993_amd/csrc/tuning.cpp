@@ -22,9 +22,9 @@ int pick(int fixed_kind, int fixed_all, int table) {
 }
 
 struct Key {
-  int n, ne, K, B;
+  int n, ne, K, B, ck;
   bool operator<(const Key& o) const {
-    return std::tie(n, ne, K, B) < std::tie(o.n, o.ne, o.K, o.B);
+    return std::tie(n, ne, K, B, ck) < std::tie(o.n, o.ne, o.K, o.B, o.ck);
   }
 };
 
@@ -33,18 +33,32 @@ std::map<Key, Tuning> g_cache;
 
 }  // namespace
 
+// Auto: stored states up to 20 qubits (at most a few hundred MiB per theta vector), where the
+// tile options leave one tile size for both sweeps.
+bool stores_states(int n, const ucc_options& o) {
+  if (o.store_states == 1) return true;
+  if (o.store_states == 2) return false;
+  if (n > 20 || o.tile_qubits > 13) return false;
+  return !(o.tile_qubits && o.tile_qubits_rev && o.tile_qubits != o.tile_qubits_rev);
+}
+
 Tuning choose_tuning(int n, int K, int batch, const ucc_options& o) {
   (void)K;
   (void)batch;
   Tuning t;
+  t.ckpt = stores_states(n, o);
   t.kf = o.tile_qubits ? o.tile_qubits : std::min(n, 14);
   t.ke = o.tile_qubits_exp ? o.tile_qubits_exp : std::min(n, 14);
   t.kr = o.tile_qubits_rev ? o.tile_qubits_rev : std::min(n, 13);
+  if (t.ckpt) {  // one tile size for both sweeps, at most the reverse pass's 13
+    const int k = o.tile_qubits ? o.tile_qubits : o.tile_qubits_rev ? o.tile_qubits_rev : 13;
+    t.kf = t.kr = std::min(n, k);
+  }
   // One-tile states are latency-bound: small workgroups.  Multi-tile states: large
   // workgroups keep a 2^14 tile in 16 registers per thread and give the apply-H rows their
-  // lanes; the two-vector reverse tile takes 512.
+  // lanes; the two-vector reverse tile (and a 2^13 forward tile) takes 512.
   const bool small = n <= 12;
-  t.tf = pick(o.block_threads_fwd, o.block_threads, small ? 256 : 1024);
+  t.tf = pick(o.block_threads_fwd, o.block_threads, small ? 256 : t.kf <= 13 ? 512 : 1024);
   t.te = pick(o.block_threads_exp, o.block_threads, small ? 256 : 1024);
   t.tr = pick(o.block_threads_rev, o.block_threads, small ? 256 : 512);
   t.launch_mode = o.launch_mode ? o.launch_mode : 1;  // 0 is resolved once the tables exist
@@ -66,11 +80,12 @@ std::vector<int> tile_candidates(int fixed, int n, std::initializer_list<int> ks
 // Candidates: the tile sizes and workgroup sizes the options leave automatic.  Plans for a
 // few tile triples (kf, ke, kr) are built and every workgroup size is timed on each (all
 // kinds at once, the per-kind HIP-event sums kept apart); each kind then takes its fastest
-// (tile, workgroup) pair.
+// (tile, workgroup) pair, except that with stored states the forward and reverse kinds take
+// the tile size whose two best times add up to the least.
 ucc_status autotune(ucc_ctx* c, int B) {
   const ucc_options& o = c->opt;
   Plan& p = c->plan;
-  const Key key{p.n, p.ne, p.K, B};
+  const Key key{p.n, p.ne, p.K, B, p.ckpt ? 1 : 0};
   {
     std::lock_guard<std::mutex> lock(g_cache_mu);
     auto it = g_cache.find(key);
@@ -83,9 +98,13 @@ ucc_status autotune(ucc_ctx* c, int B) {
       return resolve_launch_mode(c);
     }
   }
-  const std::vector<int> kfs = tile_candidates(o.tile_qubits, p.n, {14, 13});
+  // with stored states the forward and reverse passes share one tile size
+  const bool ck = p.ckpt;
+  const std::vector<int> kfs =
+      ck ? tile_candidates(o.tile_qubits ? o.tile_qubits : o.tile_qubits_rev, p.n, {13, 12})
+         : tile_candidates(o.tile_qubits, p.n, {14, 13});
   const std::vector<int> kes = tile_candidates(o.tile_qubits_exp, p.n, {14, 13});
-  const std::vector<int> krs = tile_candidates(o.tile_qubits_rev, p.n, {13, 12});
+  const std::vector<int> krs = ck ? kfs : tile_candidates(o.tile_qubits_rev, p.n, {13, 12});
   std::vector<int> ts;
   for (int t : {256, 512, 1024})
     if (!o.block_threads || t == o.block_threads) ts.push_back(t);
@@ -97,10 +116,15 @@ ucc_status autotune(ucc_ctx* c, int B) {
     double ms = 1e300;
     int k = 0, t = 0;
   };
-  Best bf, be, br;
+  std::map<int, Best> bf, br;  // per tile size
+  Best be;
+  auto keep = [](Best& b, double ms, int k, int t) {
+    if (ms < b.ms) b = Best{ms, k, t};
+  };
   const size_t triples = std::max(kfs.size(), std::max(kes.size(), krs.size()));
   for (size_t i = 0; i < triples; ++i) {
-    const int kf = kfs[i % kfs.size()], ke = kes[i % kes.size()], kr = krs[i % krs.size()];
+    const int kf = kfs[i % kfs.size()], ke = kes[i % kes.size()];
+    const int kr = ck ? kf : krs[i % krs.size()];
     s = replan(c, kf, ke, kr);
     if (s != UCC_OK) return s;
     s = ensure_buffers(c, c->buf, B, true);
@@ -121,18 +145,29 @@ ucc_status autotune(ucc_ctx* c, int B) {
       ucc_kernel_stat st[UCC_KERNEL_KINDS];
       profile_sum(pr, st, &e);
       if (e != hipSuccess) return hip_fail(e, "autotune events");
-      if (st[UCC_KERNEL_FWD].ms < bf.ms) bf = Best{st[UCC_KERNEL_FWD].ms, kf, p.tf};
-      if (st[UCC_KERNEL_APPLYH].ms < be.ms) be = Best{st[UCC_KERNEL_APPLYH].ms, ke, p.te};
-      if (st[UCC_KERNEL_REV].ms < br.ms) br = Best{st[UCC_KERNEL_REV].ms, kr, p.tr};
+      keep(bf[kf], st[UCC_KERNEL_FWD].ms, kf, p.tf);
+      keep(be, st[UCC_KERNEL_APPLYH].ms, ke, p.te);
+      keep(br[kr], st[UCC_KERNEL_REV].ms, kr, p.tr);
     }
   }
+  Best f, r;
+  if (ck) {  // the tile size with the fastest forward + reverse sweep
+    for (auto& kv : bf)
+      if (kv.second.ms + br[kv.first].ms < f.ms + r.ms) {
+        f = kv.second;
+        r = br[kv.first];
+      }
+  } else {
+    for (auto& kv : bf) keep(f, kv.second.ms, kv.second.k, kv.second.t);
+    for (auto& kv : br) keep(r, kv.second.ms, kv.second.k, kv.second.t);
+  }
   Tuning tu = base;
-  tu.kf = bf.k;
-  tu.tf = bf.t;
+  tu.kf = f.k;
+  tu.tf = f.t;
   tu.ke = be.k;
   tu.te = be.t;
-  tu.kr = br.k;
-  tu.tr = br.t;
+  tu.kr = r.k;
+  tu.tr = r.t;
   s = replan(c, tu.kf, tu.ke, tu.kr);
   if (s != UCC_OK) return s;
   apply_tuning(p, tu);

@@ -145,6 +145,9 @@ struct Plan {
   int tf = 512, te = 1024, tr = 256;  // workgroup sizes per pass kind
   bool autotuned = false;
   int launch_mode = 1;
+  // Stored forward states: gradient calls keep the state after every forward pass and the
+  // reverse passes (the forward passes in mirror order, kr == kf) read them.
+  bool ckpt = false;
 };
 
 // Device-ready flattened tables built from a Plan.
@@ -168,8 +171,9 @@ int max_pair_block_words(const Plan& p, uint32_t lmask, const std::vector<int>& 
 // Returns "" on success, otherwise an error message (inputs invalid).
 std::string validate_inputs(int n, int ne, const double* h1, const double* h2, const int32_t* exc,
                             int K);
+// ckpt: reverse passes mirror the forward passes (kr is then ignored; see Plan::ckpt).
 std::string build_plan(Plan& p, int n, int ne, const double* h1, const double* h2,
-                       const int32_t* exc, int K, int kf, int ke, int kr, int c0);
+                       const int32_t* exc, int K, int kf, int ke, int kr, int c0, bool ckpt);
 void build_tables(const Plan& p, Tables& t);
 uint32_t deposit_bits(uint32_t v, uint32_t mask);
 int count_plan_passes(const Plan& p, int kind);

@@ -112,10 +112,18 @@ def test_whole_evaluation_launch(ucc, n, ne, seed):
     for b in range(3):
         e_ref, g_ref = oracle_eg(n, ne, h, g, exc, th[b])
         assert abs(e1[b] - e_ref) <= E_TOL and np.max(np.abs(g1[b] - g_ref)) <= G_TOL
-    # the reverse sweep returns the state to |HF>
+    # the plan stores forward states, so the context holds Psi(theta) after a gradient call
+    assert one.plan_info()["store_states"] == 1
+    ref2 = ansatz.trotter_state(n, (1 << ne) - 1, exc, th[2])
+    assert np.max(np.abs(one.state(2) - ref2)) <= 1e-12
+    # without stored states the one launch ends on the state the reverse sweep returns: |HF>
+    rec = ucc.Context(n, ne, h1, h2, exc, max_batch=3, store_states=2)
+    assert rec.plan_info()["launch_mode"] == 2 and rec.plan_info()["store_states"] == 0
+    e4, g4 = rec.energy_grad(th)
+    assert np.max(np.abs(e4 - e1)) <= 1e-12 and np.max(np.abs(g4 - g1)) <= 1e-12
     hf = np.zeros(1 << n, complex)
     hf[(1 << ne) - 1] = 1.0
-    assert np.max(np.abs(one.state(2) - hf)) <= 1e-12
+    assert np.max(np.abs(rec.state(2) - hf)) <= 1e-12
     # energy only: same energies, and the state is the Trotter state
     e3 = one.energy(th)
     assert np.max(np.abs(e3 - e1)) <= 1e-12
@@ -156,11 +164,19 @@ def test_state_invariants_and_reverse_sweep(ucc):
     assert abs(np.linalg.norm(psi) - 1.0) <= 1e-13
     assert np.all(psi.imag == 0.0)
     assert np.all(psi[~sector_mask(n, ne)] == 0.0)
+    assert ctx.plan_info()["store_states"] == 0  # two tile sizes: the state is recomputed
     ctx.energy_grad(th)
     back = ctx.state(0)
     hf = np.zeros(1 << n, complex)
     hf[(1 << ne) - 1] = 1.0
     assert np.max(np.abs(back - hf)) <= 1e-13
+    # stored forward states (one tile size for both sweeps): the gradient call leaves Psi(theta)
+    st = ucc.Context(n, ne, h1, h2, exc, tile_qubits=8)
+    assert st.plan_info()["store_states"] == 1 and st.plan_info()["n_fwd_passes"] > 1
+    e_st, g_st = st.energy_grad(th)
+    e_ref, g_ref = oracle_eg(n, ne, h, g, exc, th)
+    assert abs(e_st[0] - e_ref) <= E_TOL and np.max(np.abs(g_st[0] - g_ref)) <= G_TOL
+    assert np.max(np.abs(st.state(0) - ref)) <= 1e-12
 
 
 def test_16q_energy_gradient(ucc):
@@ -174,6 +190,12 @@ def test_16q_energy_gradient(ucc):
     assert abs(e[0] - e_ref) <= E_TOL
     assert np.max(np.abs(gr[0] - g_ref)) <= G_TOL
     assert abs(ctx.energy(th)[0] - e_ref) <= E_TOL
+    # stored forward states at 2^12 tiles, and the recomputing reverse sweep
+    for kw in (dict(store_states=1, tile_qubits=12), dict(store_states=2)):
+        c2 = ucc.Context(n, ne, h1, h2, exc, **kw)
+        assert c2.plan_info()["store_states"] == (kw["store_states"] == 1)
+        e2, g2 = c2.energy_grad(th)
+        assert abs(e2[0] - e_ref) <= E_TOL and np.max(np.abs(g2[0] - g_ref)) <= G_TOL, kw
 
 
 @pytest.mark.parametrize("tf,te,tr", [(256, 1024, 512), (1024, 256, 1024), (512, 512, 256)])
@@ -239,10 +261,22 @@ def test_18q_batch64_against_stored_oracle_values(ucc):
         assert abs(et[b] - ent["energy"]) <= E_TOL, b
         assert np.max(np.abs(gt[b] - np.array(ent["grad"]))) <= G_TOL, b
     assert np.max(np.abs(et - e)) <= E_TOL and np.max(np.abs(gt - gr)) <= G_TOL
-    # every entry returned the state to |HF> (the reverse sweep undoes the forward one)
+    # forward states are stored: the context holds Psi(theta_b), the same state (bitwise) an
+    # energy-only call leaves, and entry 0 is the oracle's Trotter state
+    assert ctx.plan_info()["store_states"] == 1
+    after_grad = {b: ctx.state(b) for b in (0, 31, 63)}
+    ctx.energy(th)
+    for b in (0, 31, 63):
+        assert np.array_equal(ctx.state(b), after_grad[b]), b
+    ref0 = ansatz.trotter_state(n, (1 << ne) - 1, exc, th[0])
+    assert np.max(np.abs(after_grad[0] - ref0)) <= 1e-12
+    # without stored states the reverse sweep runs each entry back to |HF>
+    rec = ucc.Context(n, ne, h1, h2, exc, max_batch=64, store_states=2)
+    er, gr2 = rec.energy_grad(th)
+    assert np.max(np.abs(er - e)) <= E_TOL and np.max(np.abs(gr2 - gr)) <= G_TOL
     hf = (1 << ne) - 1
     for b in (0, 31, 63):
-        s = ctx.state(b)
+        s = rec.state(b)
         assert abs(s[hf] - 1.0) <= 1e-12 and np.max(np.abs(np.delete(s, hf))) <= 1e-12
     # batch entry == solo run, bitwise
     solo = ucc.Context(n, ne, h1, h2, exc)

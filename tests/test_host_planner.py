@@ -49,6 +49,8 @@ def test_library_exports_every_declared_symbol():
     dict(exc=[[0, 1, 4, 5], [0, 1, 4, 5]]),  # duplicate
     dict(h1_asym=True), dict(h2_asym=True), dict(tile_qubits=20), dict(block_threads=300),
     dict(block_threads_rev=128), dict(block_threads_exp=768), dict(autotune=True),
+    dict(store_states=3), dict(store_states=1, tile_qubits=14),
+    dict(store_states=1, tile_qubits=7, tile_qubits_rev=6),
 ])
 def test_invalid_inputs_are_rejected(bad):
     n, ne = bad.get("n", 8), bad.get("ne", 4)
@@ -60,8 +62,9 @@ def test_invalid_inputs_are_rejected(bad):
         h2 = h2.copy()
         h2[0, 1, 2, 3] += 1e-6
     exc = np.array(bad.get("exc", uccsd_excitations(8, 4)), dtype=np.int32)
-    kw = {k: bad[k] for k in ("tile_qubits", "block_threads", "block_threads_rev",
-                              "block_threads_exp", "autotune") if k in bad}
+    kw = {k: bad[k] for k in ("tile_qubits", "tile_qubits_rev", "block_threads",
+                              "block_threads_rev", "block_threads_exp", "autotune",
+                              "store_states") if k in bad}
     with pytest.raises(ucc.UCCError) as ei:
         ucc.Context(n, ne, h1[: n // 2, : n // 2] if n <= 8 else np.zeros((n // 2,) * 2),
                     h2 if n == 8 else np.zeros((n // 2,) * 4), exc, host_only=True, **kw)
@@ -161,12 +164,15 @@ def test_excitation_signs_match_ladder_operators(n, ne):
 
 # ---------------------------------------------------------------- pass plan
 
-@pytest.mark.parametrize("n,ne,kf,ke,kr", [(8, 4, 0, 0, 0), (12, 8, 8, 9, 7), (16, 8, 0, 0, 0),
-                                           (18, 10, 0, 0, 0), (18, 10, 10, 11, 9),
-                                           (18, 10, 14, 12, 13)])
-def test_pass_plan_covers_everything_in_order(n, ne, kf, ke, kr):
-    ctx, _, _, exc = host_ctx(n, ne, tile_qubits=kf, tile_qubits_exp=ke, tile_qubits_rev=kr)
+@pytest.mark.parametrize("n,ne,kf,ke,kr,ss,stored", [
+    (8, 4, 0, 0, 0, 0, 1), (12, 8, 8, 9, 7, 0, 0), (16, 8, 0, 0, 0, 0, 1), (16, 8, 0, 0, 0, 2, 0),
+    (18, 10, 0, 0, 0, 0, 1), (18, 10, 10, 11, 9, 0, 0), (18, 10, 14, 12, 13, 0, 0),
+    (18, 10, 0, 12, 11, 1, 1), (18, 10, 0, 0, 0, 2, 0)])
+def test_pass_plan_covers_everything_in_order(n, ne, kf, ke, kr, ss, stored):
+    ctx, _, _, exc = host_ctx(n, ne, tile_qubits=kf, tile_qubits_exp=ke, tile_qubits_rev=kr,
+                              store_states=ss)
     info = ctx.plan_info()
+    assert info["store_states"] == stored
     passes = ctx.pass_table()
     et = ctx.excitation_table()
     gt = ctx.group_table()
@@ -184,6 +190,11 @@ def test_pass_plan_covers_everything_in_order(n, ne, kf, ke, kr):
             assert p["local"] & ((1 << c0) - 1) == (1 << c0) - 1
             for e in p["items"]:
                 assert int(et["supp"][e]) & ~p["local"] == 0
+    if stored:  # the reverse passes are the forward windows in mirror order
+        assert info["tile_qubits"] == info["tile_qubits_rev"] and len(rev) == len(fwd)
+        for r, f in zip(rev, fwd[::-1]):
+            assert r["local"] == f["local"]
+            assert np.array_equal(r["items"], np.asarray(f["items"])[::-1])
     seen = np.concatenate([p["items"] for p in exp_])
     assert np.array_equal(np.sort(seen), np.arange(info["n_groups"]))
     for p in exp_:
@@ -203,11 +214,19 @@ def test_batch_compatibility_and_job_footprint():
     c = ucc.Context(16, 8, *make_integrals(8, 1), uccsd_excitations(16, 8), host_only=True)
     d = ucc.Context(12, 8, *make_integrals(6, 2), exc[:-1], host_only=True)
     e = ucc.Context(12, 8, *make_integrals(6, 2), exc, host_only=True, tile_qubits=10)
+    f = ucc.Context(12, 8, *make_integrals(6, 2), exc, host_only=True, store_states=2)
     assert not a.batch_compatible(c) and not a.batch_compatible(d) and not a.batch_compatible(e)
+    assert not a.batch_compatible(f)
     # footprint: two complex128 vectors plus partial sums, rows and one table row
     info = a.plan_info()
     S = 16 << 12
     assert 2 * S < info["job_footprint"] < 2 * S + (1 << 20)
+    # stored states: one more vector per forward pass but the last
+    info = c.plan_info()
+    S = 16 << 16
+    assert info["store_states"] == 1
+    extra = (info["n_fwd_passes"] - 1) * S
+    assert 2 * S + extra < info["job_footprint"] < 2 * S + extra + (4 << 20)
 
 
 def test_server_argument_errors():
