@@ -207,21 +207,27 @@ ucc_status enqueue_eval(const ucc_ctx* c, Buffers& b, const double* d_theta, int
   auto state = [&](int w) { return w == p.nfwd - 1 ? b.psi : b.ck + w * cstride; };
   hipError_t e = timed(UCC_KERNEL_TRIG, 24.0 * B * p.K, [&] { return launch_trig(a, d_theta); });
   if (e != hipSuccess) return hip_fail(e, "launch k_trig");
-  for (int i = 0; i < p.nfwd; ++i) {
+  // Consecutive passes visit the batch entries in opposite orders, so a pass starts on the
+  // vectors the previous one wrote last (still in the last-level caches).
+  int seq = 0;
+  for (int i = 0; i < p.nfwd; ++i, ++seq) {
+    a.flip = seq & 1;
     double2* dst = ck ? state(i) : b.psi;
     const double2* src = ck && i > 0 ? state(i - 1) : dst;
     e = timed(UCC_KERNEL_FWD, i == 0 ? S : 2 * S, [&] { return launch_fwd(a, i, i == 0, src, dst); });
     if (e != hipSuccess) return hip_fail(e, "launch k_fwd");
   }
   const int nte = 1 << (p.n - p.ke);
-  for (int j = 0; j < p.nexp; ++j) {
+  for (int j = 0; j < p.nexp; ++j, ++seq) {
+    a.flip = seq & 1;
     const double bytes = grad ? S + (j == 0 ? sec : 2 * sec) : S;
     e = timed(grad ? UCC_KERNEL_APPLYH : UCC_KERNEL_EXP, bytes,
               [&] { return launch_exp(a, p.nfwd + j, j * nte, j == 0, grad); });
     if (e != hipSuccess) return hip_fail(e, "launch k_exp");
   }
   if (grad)
-    for (int j = 0; j < p.nrev; ++j) {
+    for (int j = 0; j < p.nrev; ++j, ++seq) {
+      a.flip = seq & 1;
       e = timed(UCC_KERNEL_REV, ck ? 3 * S : 4 * S, [&] {
         return launch_rev(a, p.nfwd + p.nexp + j, ck ? state(p.nfwd - 1 - j) : b.psi, !ck);
       });

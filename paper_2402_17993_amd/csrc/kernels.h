@@ -19,6 +19,7 @@ struct LaunchArgs {
   const uint4* blobs = nullptr;
   int blob_stride = 0;  // uint4 per batch entry when entries have their own Hamiltonian
   int cu_share = 0;     // compute units the persistent pass kernels may fill (0 = all)
+  int flip = 0;         // 1: pass kernels visit the batch entries in descending order
   const int2* cls = nullptr;
   double2* psi = nullptr;
   double2* lam = nullptr;

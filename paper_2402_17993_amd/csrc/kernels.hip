@@ -272,50 +272,51 @@ struct ExcNow {
 // Tile elements of the thread (registers) and the tile's in-sector amplitudes (LDS, by rank).
 // Amplitudes outside the N / S_z sector are exactly zero and stay zero (the reference state is
 // in the sector and every factor conserves N and S_z).  A pass reads the whole tile and writes
-// the whole tile: in-sector values by rank list, the others as the constant zero they are,
-// from a register that is never overwritten, so no store ever holds up the next tile's loads
-// (a load into a register that a pending store still reads would wait for that store).
-//   take:      in-sector values -> cv[rank]; bit J of *insec marks in-sector elements
-//   put_zeros: zero stores for the elements outside the sector
-//   put_list:  in-sector values from cv to HBM through the class's physical offsets
+// the whole tile.
+//   take:     in-sector values -> cv[rank]
+//   put_tile: every element of the thread, in tile order: cv[rank] inside the sector, zero
+//             outside.  One unconditional 16-byte store per element, so the number of stores
+//             a thread has in flight is known when the code is compiled and the next tile's
+//             take waits for that tile's loads only (vector-memory counters retire in issue
+//             order; a data-dependent store count would make it wait for every store).  The
+//             store data comes from LDS into fresh registers, never from the prefetch
+//             registers, so the next tile's loads do not wait for these stores either.
 template <int T, int KT>
 struct Sector {
   using TL = Tile<T, KT>;
   static constexpr int EPT = TL::EPT;
   template <int J = 0>
   static __device__ __forceinline__ void take(const typename TL::Buf& r, double2* cv,
-                                              const uint16_t* rtab, uint32_t& insec) {
+                                              const uint16_t* rtab) {
     const uint32_t rk = rtab[threadIdx.x + J * T];
-    if (rk != kNoRank) {
-      st16(cv + rk, rget<J, EPT>(r));
-      insec |= 1u << J;
-    }
-    if constexpr (J + 1 < EPT) take<J + 1>(r, cv, rtab, insec);
+    // the element's load is waited for on every path (also where no lane is in the sector),
+    // so no load stays pending into registers the next prefetch overwrites
+    const dvec2& x = rget<J, EPT>(r);
+    asm volatile("" : : "v"(x.x), "v"(x.y));
+    if (rk != kNoRank) st16(cv + rk, x);
+    if constexpr (J + 1 < EPT) take<J + 1>(r, cv, rtab);
   }
   template <int J = 0>
   static __device__ __forceinline__ void take_hf(const TL& tm, double2* cv, const uint16_t* rtab,
-                                                 uint32_t base, uint32_t hf, uint32_t& insec) {
+                                                 uint32_t base, uint32_t hf) {
     const uint32_t rk = rtab[threadIdx.x + J * T];
     if (rk != kNoRank) {
       const uint32_t ph = base | tm.template off<J>();
       st16(cv + rk, dvec2{ph == hf ? 1.0 : 0.0, 0.0});
-      insec |= 1u << J;
     }
-    if constexpr (J + 1 < EPT) take_hf<J + 1>(tm, cv, rtab, base, hf, insec);
+    if constexpr (J + 1 < EPT) take_hf<J + 1>(tm, cv, rtab, base, hf);
   }
   template <int J = 0>
-  static __device__ __forceinline__ void put_zeros(const TL& tm, double2* __restrict__ v,
-                                                   uint32_t base, uint32_t insec, dvec2 zero) {
-    if (!((insec >> J) & 1u)) st16(v + (base | tm.template off<J>()), zero);
-    if constexpr (J + 1 < EPT) put_zeros<J + 1>(tm, v, base, insec, zero);
+  static __device__ __forceinline__ void put_tile(const TL& tm, const double2* cv,
+                                                  const uint16_t* rtab, double2* __restrict__ v,
+                                                  uint32_t base) {
+    const uint32_t rk = rtab[threadIdx.x + J * T];
+    const bool in = rk != kNoRank;
+    const dvec2 d = ld16(cv + (in ? rk : 0u));
+    st16(v + (base | tm.template off<J>()), in ? d : dvec2{0.0, 0.0});
+    if constexpr (J + 1 < EPT) put_tile<J + 1>(tm, cv, rtab, v, base);
   }
 };
-
-template <int T>
-__device__ __forceinline__ void put_list(const double2* cv, const uint32_t* sphys, int ns,
-                                         double2* __restrict__ v, uint32_t base) {
-  for (int i = threadIdx.x; i < ns; i += T) st16(v + (base | sphys[i]), ld16(cv + i));
-}
 
 // Loop forms for tiles without a register-staged variant (KT = 0).
 template <int T, bool INIT>
@@ -333,10 +334,13 @@ __device__ __forceinline__ void take_loop(uint32_t lmask, uint32_t tileN, double
 }
 
 template <int T>
-__device__ __forceinline__ void zeros_loop(uint32_t lmask, uint32_t tileN, const uint16_t* rtab,
-                                           double2* __restrict__ v, uint32_t base) {
-  for (uint32_t c = threadIdx.x; c < tileN; c += T)
-    if (rtab[c] == kNoRank) v[base | dep(c, lmask)] = make_double2(0.0, 0.0);
+__device__ __forceinline__ void put_tile_loop(uint32_t lmask, uint32_t tileN, const double2* cv,
+                                              const uint16_t* rtab, double2* __restrict__ v,
+                                              uint32_t base) {
+  for (uint32_t c = threadIdx.x; c < tileN; c += T) {
+    const uint32_t rk = rtab[c];
+    v[base | dep(c, lmask)] = rk != kNoRank ? cv[rk] : make_double2(0.0, 0.0);
+  }
 }
 
 // ---- pass bodies shared by the per-pass kernels and the whole-evaluation kernel
@@ -589,15 +593,15 @@ __device__ __forceinline__ double exp_rows(const double2* cp, const uint32_t* bl
 // Forward and reverse passes are persistent over (batch entry, tile) items with stride
 // gridDim.x (a multiple of the tile count where possible, so a workgroup keeps one tile
 // index and one class).  Per item:
-//   1. the tile (prefetched into registers: one 16-byte load per element, consecutive lanes
-//      on consecutive addresses) gives its in-sector amplitudes to LDS, by rank;
-//   2. the next item's tile is requested into the same registers (their only readers were
-//      LDS writes), so its loads are in flight during step 3;
-//   3. the pass's excitations run in order on the in-sector amplitudes in LDS, one barrier
+//   1. the next item's (cos, sin) and tile are requested into registers (one 16-byte load
+//      per element, consecutive lanes on consecutive addresses), so the loads are in flight
+//      during step 2;
+//   2. the pass's excitations run in order on the in-sector amplitudes in LDS, one barrier
 //      per excitation;
-//   4. the whole tile is written: zeros outside the sector, in-sector values from LDS.
-// Vector-memory counters retire in issue order, so the loads of step 2 come before the
-// stores of step 4 and step 1 of the next item waits for nothing issued after them.
+//   3. the whole tile is written (put_tile);
+//   4. the next tile gives its in-sector amplitudes to LDS, by rank (take).
+// The take of step 4 sits at the end of the loop body, so the compiler sees the loads of
+// step 1 followed by exactly the stores of step 3 and waits for the loads alone.
 //
 // Forward pass: U_k = exp(theta_k G_k) in Trotter order, each a Givens rotation on the
 // tile's in-sector pairs (u, u ^ supp) listed in the class block.  Tiles are read from src
@@ -607,7 +611,7 @@ __global__ __launch_bounds__(T) LDS_BOUND_OCCUPANCY void k_fwd(
     const DevPass* __restrict__ passes, int pidx, const DevExc* __restrict__ exc,
     const int2* __restrict__ pcls, const uint32_t* __restrict__ pairs,
     const double2* __restrict__ cs, int K, const double2* src, double2* __restrict__ psi, int n,
-    uint32_t hf, uint32_t amask, uint32_t bmask, int total) {
+    uint32_t hf, uint32_t amask, uint32_t bmask, int total, int flip) {
   extern __shared__ double2 lds[];
   __shared__ PassStage st;
   using TL = Tile<T, KT>;
@@ -624,13 +628,15 @@ __global__ __launch_bounds__(T) LDS_BOUND_OCCUPANCY void k_fwd(
   const bool cst = (int)threadIdx.x < ps.count;
   int item = blockIdx.x;
   if (item >= total) return;
+  const int nb = total >> tb;
+  auto ent = [&](int it) { return flip ? nb - 1 - (it >> tb) : it >> tb; };  // batch entry
   stage_records<T>(st, ps, exc);
   typename TL::Buf r;
   int staged = -1;
-  auto cs_of = [&](int it) { return cs[(size_t)(it >> tb) * K + st.x[threadIdx.x].k]; };
+  auto cs_of = [&](int it) { return cs[(size_t)ent(it) * K + st.x[threadIdx.x].k]; };
   auto base_of = [&](int it) { return dep(it & tmask, ps.gmask); };
-  auto vec_of = [&](int it) { return psi + ((size_t)(it >> tb) << n); };
-  auto src_of = [&](int it) { return src + ((size_t)(it >> tb) << n); };
+  auto vec_of = [&](int it) { return psi + ((size_t)ent(it) << n); };
+  auto src_of = [&](int it) { return src + ((size_t)ent(it) << n); };
   auto stage_class = [&](uint32_t base) {
     const int cl = tile_class(base, amask, bmask, ps.nbeta_g);
     if (cl != staged) {
@@ -639,45 +645,49 @@ __global__ __launch_bounds__(T) LDS_BOUND_OCCUPANCY void k_fwd(
       staged = cl;
     }
   };
-  stage_class(base_of(item));
-  if (RP && !INIT) tm.fetch(r, src_of(item), base_of(item));
-  if (cst) st.cs[threadIdx.x] = cs_of(item);
-  const uint32_t* off = blk + 2;
-  const dvec2 zero = {0.0, 0.0};
-  for (;;) {
-    const uint32_t base = base_of(item);
-    double2* __restrict__ v = vec_of(item);
-    uint32_t insec = 0u;
+  // in-sector amplitudes of the tile of item `it` into cp (from the prefetch registers)
+  auto take = [&](int it) {
     if constexpr (RP) {
       tm.refresh();
       if (INIT)
-        SC::take_hf(tm, cp, rtab, base, hf, insec);
+        SC::take_hf(tm, cp, rtab, base_of(it), hf);
       else
-        SC::take(r, cp, rtab, insec);
+        SC::take(r, cp, rtab);
     } else {
-      take_loop<T, INIT>(ps.lmask, tileN, cp, rtab, src_of(item), base, hf);
+      take_loop<T, INIT>(ps.lmask, tileN, cp, rtab, src_of(it), base_of(it), hf);
     }
-    __syncthreads();
+  };
+  stage_class(base_of(item));
+  double2 csv = make_double2(1.0, 0.0);
+  if (cst) csv = cs_of(item);
+  if (RP && !INIT) tm.fetch(r, src_of(item), base_of(item));
+  take(item);
+  if (cst) st.cs[threadIdx.x] = csv;
+  for (;;) {
+    const uint32_t base = base_of(item);
+    double2* __restrict__ v = vec_of(item);
+    __syncthreads();  // the tile's amplitudes and (cos, sin) are in LDS
+    // the next item's (cos, sin) and tile are requested now (in that order: the tile's
+    // loads are then the youngest before this item's stores) and land during the excitations
     const int next = item + gridDim.x;
-    double2 csv = make_double2(1.0, 0.0);
     if (next < total) {
+      if (cst) csv = cs_of(next);
       tm.refresh();
       if (RP && !INIT) tm.fetch(r, src_of(next), base_of(next));
-      if (cst) csv = cs_of(next);
     }
-    const int m = (int)blk[1], ns = (int)blk[0];
-    const uint32_t* sphys = blk + 3 + m + ((ns + 1) >> 1);
     fwd_excitations<T>(cp, blk, st, ps.count, base);
+    // the whole tile: a fixed number of stores per thread, so the next take waits for its
+    // own loads only
     if constexpr (RP) {
       tm.refresh();
-      SC::put_zeros(tm, v, base, insec, zero);
+      SC::put_tile(tm, cp, rtab, v, base);
     } else {
-      zeros_loop<T>(ps.lmask, tileN, rtab, v, base);
+      put_tile_loop<T>(ps.lmask, tileN, cp, rtab, v, base);
     }
-    put_list<T>(cp, sphys, ns, v, base);
     if (next >= total) break;
     __syncthreads();  // cp, the table and the (cos, sin) stage are no longer read
     stage_class(base_of(next));
+    take(next);
     if (cst) st.cs[threadIdx.x] = csv;
     item = next;
   }
@@ -693,7 +703,7 @@ __global__ __launch_bounds__(T) LDS_BOUND_OCCUPANCY void k_rev(
     const DevPass* __restrict__ passes, int pidx, const DevExc* __restrict__ exc,
     const int2* __restrict__ pcls, const uint32_t* __restrict__ pairs,
     const double2* __restrict__ cs, int K, double2* __restrict__ psi, double2* __restrict__ lam,
-    int n, uint32_t amask, uint32_t bmask, double* __restrict__ gpart, int total) {
+    int n, uint32_t amask, uint32_t bmask, double* __restrict__ gpart, int total, int flip) {
   extern __shared__ double2 lds[];
   constexpr int NW = T / 64;
   __shared__ PassStage st;
@@ -711,16 +721,17 @@ __global__ __launch_bounds__(T) LDS_BOUND_OCCUPANCY void k_rev(
   uint32_t* blk = reinterpret_cast<uint32_t*>(lds + 2 * ps.ns_max);
   uint16_t* rtab = reinterpret_cast<uint16_t*>(blk + ps.stage_len);
   const TL tm(ps.lmask);
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const bool cst = (int)threadIdx.x < ps.count;
   int item = blockIdx.x;
   if (item >= total) return;
+  const int nb = total >> tb;
+  auto ent = [&](int it) { return flip ? nb - 1 - (it >> tb) : it >> tb; };  // batch entry
   stage_records<T>(st, ps, exc);
   typename TL::Buf rp, rl;
   int staged = -1;
-  auto cs_of = [&](int it) { return cs[(size_t)(it >> tb) * K + st.x[threadIdx.x].k]; };
+  auto cs_of = [&](int it) { return cs[(size_t)ent(it) * K + st.x[threadIdx.x].k]; };
   auto base_of = [&](int it) { return dep(it & tmask, ps.gmask); };
-  auto off_of = [&](int it) { return (size_t)(it >> tb) << n; };
+  auto off_of = [&](int it) { return (size_t)ent(it) << n; };
   auto stage_class = [&](uint32_t base) {
     const int c = tile_class(base, amask, bmask, ps.nbeta_g);
     if (c != staged) {
@@ -729,41 +740,40 @@ __global__ __launch_bounds__(T) LDS_BOUND_OCCUPANCY void k_rev(
       staged = c;
     }
   };
+  auto take = [&](int it) {
+    if constexpr (RP) {
+      SC::take(rp, cp, rtab);
+      SC::take(rl, cl, rtab);
+    } else {
+      take_loop<T, false>(ps.lmask, tileN, cp, rtab, psi + off_of(it), base_of(it), 0u);
+      take_loop<T, false>(ps.lmask, tileN, cl, rtab, lam + off_of(it), base_of(it), 0u);
+    }
+  };
   stage_class(base_of(item));
+  double2 csv = make_double2(1.0, 0.0);
+  if (cst) csv = cs_of(item);
   if (RP) {
     tm.fetch(rp, psi + off_of(item), base_of(item));
     tm.fetch(rl, lam + off_of(item), base_of(item));
   }
-  if (cst) st.cs[threadIdx.x] = cs_of(item);
-  const uint32_t* off = blk + 2;
-  const dvec2 zero = {0.0, 0.0};
+  take(item);
+  if (cst) st.cs[threadIdx.x] = csv;
   for (;;) {
-    const int b = item >> tb;
+    const int b = ent(item);
     const uint32_t t = item & tmask;
     const uint32_t base = base_of(item);
     double2* __restrict__ vp = psi + off_of(item);
     double2* __restrict__ vl = lam + off_of(item);
-    uint32_t insec = 0u;
-    if constexpr (RP) {
-      SC::take(rp, cp, rtab, insec);
-      SC::take(rl, cl, rtab, insec);
-    } else {
-      take_loop<T, false>(ps.lmask, tileN, cp, rtab, vp, base, 0u);
-      take_loop<T, false>(ps.lmask, tileN, cl, rtab, vl, base, 0u);
-    }
-    __syncthreads();
+    __syncthreads();  // the tile's amplitudes and (cos, sin) are in LDS
     const int next = item + gridDim.x;
-    double2 csv = make_double2(1.0, 0.0);
     if (next < total) {
+      if (cst) csv = cs_of(next);
       if (RP) {
         tm.refresh();
         tm.fetch(rp, psi + off_of(next), base_of(next));
         tm.fetch(rl, lam + off_of(next), base_of(next));
       }
-      if (cst) csv = cs_of(next);
     }
-    const int m = (int)blk[1], ns = (int)blk[0];
-    const uint32_t* sphys = blk + 3 + m + ((ns + 1) >> 1);
     rev_excitations<T>(cp, cl, blk, st, ps.count, base, red);
     if (cst) {
       double sum = 0.0;
@@ -772,17 +782,16 @@ __global__ __launch_bounds__(T) LDS_BOUND_OCCUPANCY void k_rev(
     }
     if constexpr (RP) {
       tm.refresh();
-      if (WP) SC::put_zeros(tm, vp, base, insec, zero);
-      SC::put_zeros(tm, vl, base, insec, zero);
+      if (WP) SC::put_tile(tm, cp, rtab, vp, base);
+      SC::put_tile(tm, cl, rtab, vl, base);
     } else {
-      if (WP) zeros_loop<T>(ps.lmask, tileN, rtab, vp, base);
-      zeros_loop<T>(ps.lmask, tileN, rtab, vl, base);
+      if (WP) put_tile_loop<T>(ps.lmask, tileN, cp, rtab, vp, base);
+      put_tile_loop<T>(ps.lmask, tileN, cl, rtab, vl, base);
     }
-    if (WP) put_list<T>(cp, sphys, ns, vp, base);
-    put_list<T>(cl, sphys, ns, vl, base);
     if (next >= total) break;
     __syncthreads();  // cp, cl, the table, red and the (cos, sin) stage are no longer read
     stage_class(base_of(next));
+    take(next);
     if (cst) st.cs[threadIdx.x] = csv;
     item = next;
   }
@@ -802,7 +811,8 @@ __global__ __launch_bounds__(T) LDS_BOUND_OCCUPANCY void k_exp(
     const DevPass* __restrict__ passes, int pidx, const uint4* __restrict__ blobs,
     const int2* __restrict__ pcls, const uint32_t* __restrict__ blocks,
     const double2* __restrict__ psi, double2* __restrict__ lam, int n, uint32_t amask,
-    uint32_t bmask, double* __restrict__ epart, int estride, int first, int total, int bstride) {
+    uint32_t bmask, double* __restrict__ epart, int estride, int first, int total, int bstride,
+    int flip) {
   extern __shared__ double2 lds[];
   using TL = Tile<T, KT>;
   using SC = Sector<T, KT>;
@@ -827,6 +837,8 @@ __global__ __launch_bounds__(T) LDS_BOUND_OCCUPANCY void k_exp(
   const TL tm(ps.lmask);
   int item = blockIdx.x;
   if (item >= total) return;
+  const int nb = total >> tb;
+  auto ent = [&](int it) { return flip ? nb - 1 - (it >> tb) : it >> tb; };  // batch entry
   // The value table of batch entry b sits at blobs + b * bstride (bstride 0: one Hamiltonian
   // for the whole batch, copied once; otherwise re-staged whenever the entry changes).
   int blob_b = -1;
@@ -840,7 +852,7 @@ __global__ __launch_bounds__(T) LDS_BOUND_OCCUPANCY void k_exp(
   int staged = -1;
   const uint32_t* __restrict__ gent = nullptr;  // the staged class's entries (in memory)
   auto base_of = [&](int it) { return dep(it & tmask, ps.gmask); };
-  auto vec_of = [&](int it) { return psi + ((size_t)(it >> tb) << n); };
+  auto vec_of = [&](int it) { return psi + ((size_t)ent(it) << n); };
   auto stage_class = [&](uint32_t base) {
     const int cl = tile_class(base, amask, bmask, ps.nbeta_g);
     if (cl != staged) {
@@ -854,21 +866,19 @@ __global__ __launch_bounds__(T) LDS_BOUND_OCCUPANCY void k_exp(
     }
   };
   typename TL::Buf r;
-  stage_blob(item >> tb);
+  stage_blob(ent(item));
   stage_class(base_of(item));  // its barriers also publish the value table
   if (RP) tm.fetch(r, vec_of(item), base_of(item));
   const int sub = threadIdx.x & 3;
   for (;;) {
-    const int b = item >> tb;
+    const int b = ent(item);
     const uint32_t t = item & tmask;
     const uint32_t base = base_of(item);
     double2* __restrict__ vl = APPLY ? lam + ((size_t)b << n) : nullptr;
-    uint32_t insec = 0u;
     if constexpr (RP)
-      SC::take(r, cp, rtab, insec);
+      SC::take(r, cp, rtab);
     else
       take_loop<T, false>(ps.lmask, tileN, cp, rtab, vec_of(item), base, 0u);
-    (void)insec;
     exp_prep<T>(bw, t1, t2, dpre, ps.lmask, k, n, base);
     __syncthreads();  // cp and the per-tile values complete
     const int next = item + gridDim.x;
@@ -883,7 +893,7 @@ __global__ __launch_bounds__(T) LDS_BOUND_OCCUPANCY void k_exp(
     if (threadIdx.x == 0) epart[(size_t)b * estride + t] = es;
     if (next >= total) break;
     __syncthreads();  // cp, the per-tile values and the class block are no longer read
-    stage_blob(next >> tb);
+    stage_blob(ent(next));
     stage_class(base_of(next));
     if (bstride) __syncthreads();  // a re-staged value table is read by the next tile's prep
     item = next;
@@ -1096,7 +1106,7 @@ hipError_t fwd_ti(const LaunchArgs& a, int pidx, const double2* src, double2* ds
   const int grid = pass_grid(total, resident_grid(k_fwd<T, KT, INIT>, T, lds, a.cu_share), 1 << (a.n - k));
   hipLaunchKernelGGL((k_fwd<T, KT, INIT>), dim3(grid), dim3(T), lds, a.stream, a.passes, pidx,
                      a.exc, a.cls, a.pairs, a.cs, a.K, src, dst, a.n, a.hf, a.amask, a.bmask,
-                     total);
+                     total, a.flip);
   return hipGetLastError();
 }
 
@@ -1117,7 +1127,7 @@ hipError_t rev_tw(const LaunchArgs& a, int pidx, double2* psi) {
       pass_grid(total, resident_grid(k_rev<T, KT, WP>, T, lds, a.cu_share), 1 << (a.n - k));
   hipLaunchKernelGGL((k_rev<T, KT, WP>), dim3(grid), dim3(T), lds, a.stream, a.passes, pidx,
                      a.exc, a.cls, a.pairs, a.cs, a.K, psi, a.lam, a.n, a.amask, a.bmask, a.gpart,
-                     total);
+                     total, a.flip);
   return hipGetLastError();
 }
 
@@ -1140,7 +1150,7 @@ hipError_t exp_t(const LaunchArgs& a, int pidx, int eslot, int first) {
       pass_grid(total, resident_grid(k_exp<T, KT, APPLY>, T, lds, a.cu_share), 1 << (a.n - k));
   hipLaunchKernelGGL((k_exp<T, KT, APPLY>), dim3(grid), dim3(T), lds, a.stream, a.passes, pidx,
                      a.blobs, a.cls, a.pairs, a.psi, a.lam, a.n, a.amask, a.bmask,
-                     a.epart + (size_t)eslot, a.estride, first, total, a.blob_stride);
+                     a.epart + (size_t)eslot, a.estride, first, total, a.blob_stride, a.flip);
   return hipGetLastError();
 }
 
