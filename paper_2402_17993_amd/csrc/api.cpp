@@ -278,7 +278,7 @@ bool whole_launch_fits(const Plan& p, const Tables& t) {
       max_occ = std::max(max_occ, d.n_occ);
     }
   }
-  const size_t static_bytes = kStageBytes + 8 * kMaxPassExc * 4 + 64;  // stage, 4 waves' partials
+  const size_t static_bytes = kStageBytes + 8 * kGqWords + 64;  // stage, gradient partials
   return whole_lds(p.K, ns, max_blk, max_blob, max_slots, max_occ, p.n) + static_bytes <=
          (size_t)kLdsBytes;
 }

@@ -223,49 +223,30 @@ __device__ __forceinline__ void stage_sc_class(uint32_t* blk, uint16_t* rtab,
   __syncthreads();
 }
 
-// Wave-uniform values in scalar registers.
-__device__ __forceinline__ int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
-__device__ __forceinline__ double uniform(double v) {
-  const int lo = __builtin_amdgcn_readfirstlane(__double2loint(v));
-  const int hi = __builtin_amdgcn_readfirstlane(__double2hiint(v));
-  return __hiloint2double(hi, lo);
+// Sign sigma_k (-1)^popcount(base & m_global) that excitation x carries on every pair of the
+// tile with global-bit offset base.
+__device__ __forceinline__ double exc_sign(const DevExc& x, uint32_t base) {
+  return parity(base & x.mglob) ? -(double)x.sigma : (double)x.sigma;
 }
 
-// Everything excitation e needs before its amplitudes: (cos, sin), its record's sign data,
-// the range of its pairs in the class block and the thread's first pair entry.  Loaded one
-// excitation ahead and kept raw (converting to scalar registers at load time would wait for
-// the loads there); cur() turns them into wave-uniform values where they are used.
-struct ExcAhead {
-  double2 t;
-  uint32_t mglob;
-  int sigma, i0, i1;
-  uint32_t e0;
-  __device__ __forceinline__ void load(const DevExc* sx, const double2* scs, const uint32_t* off,
-                                       const uint32_t* ent, int e) {
-    t = scs[e];
-    mglob = sx[e].mglob;
-    sigma = sx[e].sigma;
-    i0 = (int)off[e];
-    i1 = (int)off[e + 1];
-    const int i = i0 + (int)threadIdx.x;
-    e0 = i < i1 ? ent[i] : 0u;
-  }
-};
+// (cos theta_k, sin theta_k) of a staged record, with the tile's sign folded into the sine.
+__device__ __forceinline__ double2 signed_cs(double2 cs, const DevExc& x, uint32_t base) {
+  return make_double2(cs.x, exc_sign(x, base) * cs.y);
+}
 
-// Wave-uniform view of an ExcAhead for a tile with global-bit offset base: cos, sin and the
-// sign sigma_k (-1)^popcount(base & m_global) common to the whole tile.
-struct ExcNow {
-  double c, sn, sgn;
+// What excitation e needs before its amplitudes, loaded one excitation ahead by the lane:
+// (cos, signed sin), the range of its pairs in the class block and the lane's first entry.
+struct ExcNext {
+  double2 t;
   int i0, i1;
   uint32_t e0;
-  __device__ __forceinline__ explicit ExcNow(const ExcAhead& a, uint32_t base) {
-    c = uniform(a.t.x);
-    sn = uniform(a.t.y);
-    const int sig = parity(base & (uint32_t)uniform((int)a.mglob)) ? -a.sigma : a.sigma;
-    sgn = (double)uniform(sig);
-    i0 = uniform(a.i0);
-    i1 = uniform(a.i1);
-    e0 = a.e0;
+  __device__ __forceinline__ void load(const double2* scs, const uint32_t* off, const uint32_t* ent,
+                                       int e, int lane) {
+    t = scs[e];
+    i0 = (int)off[e];
+    i1 = (int)off[e + 1];
+    const int i = i0 + lane;
+    e0 = i < i1 ? ent[i] : 0u;
   }
 };
 
@@ -346,106 +327,82 @@ __device__ __forceinline__ void put_tile_loop(uint32_t lmask, uint32_t tileN, co
 // ---- pass bodies shared by the per-pass kernels and the whole-evaluation kernel
 
 // Forward excitations of a pass on the in-sector amplitudes cp of a tile (class block blk,
-// records and (cos, sin) in st): U_k = exp(theta_k G_k) in Trotter order, one barrier each.
+// (cos, signed sin) of each excitation in scs): U_k = exp(theta_k G_k) in Trotter order, each
+// a Givens rotation on the excitation's pairs.  One wave (wave 0) applies them all: the LDS
+// operations of a wave take effect in issue order, so excitation e+1 reads what excitation e
+// wrote without a workgroup barrier, and the pairs of one excitation are disjoint, so no two
+// lanes touch the same amplitude within one excitation.  The other waves return at once; the
+// caller synchronizes the workgroup before cp is read again.
 template <int T>
-__device__ __forceinline__ void fwd_excitations(double2* cp, const uint32_t* blk, const PassStage& st,
-                                                int count, uint32_t base) {
+__device__ __forceinline__ void fwd_excitations(double2* cp, const uint32_t* blk, const double2* scs,
+                                                int count) {
+  if (threadIdx.x >= 64) return;
+  const int lane = threadIdx.x;
   const uint32_t* off = blk + 2;
   const int m = (int)blk[1], ns = (int)blk[0];
   const uint32_t* ent = blk + 3 + m + ((ns + 1) >> 1) + ns;
-  ExcAhead ah;
-  ah.load(st.x, st.cs, off, ent, 0);
+  ExcNext nx;
+  nx.load(scs, off, ent, 0, lane);
   for (int e = 0; e < count; ++e) {
-    const ExcNow cur(ah, base);
-    if (e + 1 < count) ah.load(st.x, st.cs, off, ent, e + 1);
-    const double c = cur.c;
-    const double s = cur.sgn * cur.sn;
-    for (int i = cur.i0 + threadIdx.x; i < cur.i1; i += T) {
-      const uint32_t en = i == cur.i0 + (int)threadIdx.x ? cur.e0 : ent[i];
+    const ExcNext cur = nx;
+    if (e + 1 < count) nx.load(scs, off, ent, e + 1, lane);
+    const double c = cur.t.x, s = cur.t.y;
+    for (int i = cur.i0 + lane; i < cur.i1; i += 64) {
+      const uint32_t en = i == cur.i0 + lane ? cur.e0 : ent[i];
       const uint32_t ru = en & 0x7fffu, rw = en >> 16;
       const double sg = (en & 0x8000u) ? -s : s;
       const double2 a = cp[ru], bb = cp[rw];
       cp[ru] = make_double2(c * a.x - sg * bb.x, c * a.y - sg * bb.y);
       cp[rw] = make_double2(c * bb.x + sg * a.x, c * bb.y + sg * a.y);
     }
-    __syncthreads();
   }
 }
 
 // Reverse excitations of a pass (descending k) on in-sector psi (cp) and lambda (cl): the
-// partial of <lambda|G_k|psi> over the tile's pairs, then exp(-theta_k G_k) on both.  On
-// return red[e][w] holds wave w's partial of excitation e (complete after the final barrier).
-// The wave sum of excitation e's partial runs while excitation e+1's first amplitudes load
-// (off the barrier-to-barrier chain); the sums run in uniform control flow (whole wave),
-// skipped by waves that had no pair.
+// partial of <lambda|G_k|psi> over the tile's pairs (without the tile's sign, which
+// multiplies the sum exactly), then exp(-theta_k G_k) on both, applied by wave 0 alone as in
+// fwd_excitations.  Each quad's partial goes to gq (layout at kGqStride); rev_partial sums
+// them after the caller's workgroup barrier.
 template <int T>
 __device__ __forceinline__ void rev_excitations(double2* cp, double2* cl, const uint32_t* blk,
-                                                const PassStage& st, int count, uint32_t base,
-                                                double (*red)[T / 64]) {
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+                                                const double2* scs, int count, double* gq) {
+  if (threadIdx.x >= 64) return;
+  const int lane = threadIdx.x;
   const uint32_t* off = blk + 2;
   const int m = (int)blk[1], ns = (int)blk[0];
   const uint32_t* ent = blk + 3 + m + ((ns + 1) >> 1) + ns;
-  double gprev = 0.0;
-  bool had_prev = false;
-  ExcAhead ah;
-  ah.load(st.x, st.cs, off, ent, 0);
+  ExcNext nx;
+  nx.load(scs, off, ent, 0, lane);
   for (int e = 0; e < count; ++e) {
-    const ExcNow cur(ah, base);
-    if (e + 1 < count) ah.load(st.x, st.cs, off, ent, e + 1);
-    const double c = cur.c, sn = cur.sn;
-    const double sgn0 = cur.sgn;
-    const int i0 = cur.i0, i1 = cur.i1;
-    const int ia = i0 + (int)threadIdx.x;
-    const bool has = ia < i1;
-    uint32_t ru = 0u, rw = 0u;
-    double sg = 0.0;
-    double2 pu = make_double2(0.0, 0.0), pw = pu, lu = pu, lw = pu;
-    if (has) {
-      ru = cur.e0 & 0x7fffu;
-      rw = cur.e0 >> 16;
-      sg = (cur.e0 & 0x8000u) ? -sgn0 : sgn0;
-      pu = cp[ru];
-      pw = cp[rw];
-      lu = cl[ru];
-      lw = cl[rw];
-    }
-    if (e > 0) {
-      double gs = 0.0;
-      if (had_prev) gs = wave_sum(gprev);
-      if (lane == 0) red[e - 1][wv] = gs;
-    }
+    const ExcNext cur = nx;
+    if (e + 1 < count) nx.load(scs, off, ent, e + 1, lane);
+    const double c = cur.t.x, s = cur.t.y;
     double g = 0.0;
-    if (has) {
-      g += sg * ((lw.x * pu.x + lw.y * pu.y) - (lu.x * pw.x + lu.y * pw.y));
-      const double s = sg * sn;
-      cp[ru] = make_double2(c * pu.x + s * pw.x, c * pu.y + s * pw.y);
-      cp[rw] = make_double2(c * pw.x - s * pu.x, c * pw.y - s * pu.y);
-      cl[ru] = make_double2(c * lu.x + s * lw.x, c * lu.y + s * lw.y);
-      cl[rw] = make_double2(c * lw.x - s * lu.x, c * lw.y - s * lu.y);
-    }
-    for (int i = ia + T; i < i1; i += T) {
-      const uint32_t en = ent[i];
+    for (int i = cur.i0 + lane; i < cur.i1; i += 64) {
+      const uint32_t en = i == cur.i0 + lane ? cur.e0 : ent[i];
       const uint32_t qu = en & 0x7fffu, qw = en >> 16;
-      const double sq = (en & 0x8000u) ? -sgn0 : sgn0;
+      const bool neg = (en & 0x8000u) != 0u;
       const double2 au = cp[qu], aw = cp[qw], bu = cl[qu], bw = cl[qw];
-      g += sq * ((bw.x * au.x + bw.y * au.y) - (bu.x * aw.x + bu.y * aw.y));
-      const double s = sq * sn;
-      cp[qu] = make_double2(c * au.x + s * aw.x, c * au.y + s * aw.y);
-      cp[qw] = make_double2(c * aw.x - s * au.x, c * aw.y - s * au.y);
-      cl[qu] = make_double2(c * bu.x + s * bw.x, c * bu.y + s * bw.y);
-      cl[qw] = make_double2(c * bw.x - s * bu.x, c * bw.y - s * bu.y);
+      const double t = (bw.x * au.x + bw.y * au.y) - (bu.x * aw.x + bu.y * aw.y);
+      g += neg ? -t : t;
+      const double sq = neg ? -s : s;
+      cp[qu] = make_double2(c * au.x + sq * aw.x, c * au.y + sq * aw.y);
+      cp[qw] = make_double2(c * aw.x - sq * au.x, c * aw.y - sq * au.y);
+      cl[qu] = make_double2(c * bu.x + sq * bw.x, c * bu.y + sq * bw.y);
+      cl[qw] = make_double2(c * bw.x - sq * bu.x, c * bw.y - sq * bu.y);
     }
-    gprev = g;
-    had_prev = i0 + wv * 64 < i1;
-    __syncthreads();
+    g = quad_sum(g);
+    if ((lane & 3) == 0) gq[(lane >> 2) * kGqStride + e] = g;
   }
-  {
-    double gs = 0.0;
-    if (had_prev) gs = wave_sum(gprev);
-    if (lane == 0) red[count - 1][wv] = gs;
-  }
-  __syncthreads();  // red complete
+}
+
+// Tile partial of <lambda|G_k|psi> for the pass's excitation e: the 16 quad partials in a
+// fixed order, times the tile's sign of the excitation.
+__device__ __forceinline__ double rev_partial(const double* gq, int e, const DevExc& x, uint32_t base) {
+  double s = 0.0;
+#pragma unroll
+  for (int q = 0; q < 16; ++q) s += gq[q * kGqStride + e];
+  return exc_sign(x, base) * s;
 }
 
 // Per-tile values of an expectation pass (value table bw, layout in ucc_internal.h) for a
@@ -596,8 +553,8 @@ __device__ __forceinline__ double exp_rows(const double2* cp, const uint32_t* bl
 //   1. the next item's (cos, sin) and tile are requested into registers (one 16-byte load
 //      per element, consecutive lanes on consecutive addresses), so the loads are in flight
 //      during step 2;
-//   2. the pass's excitations run in order on the in-sector amplitudes in LDS, one barrier
-//      per excitation;
+//   2. the pass's excitations run in order on the in-sector amplitudes in LDS (one wave,
+//      no barrier between excitations; the workgroup synchronizes once at the end);
 //   3. the whole tile is written (put_tile);
 //   4. the next tile gives its in-sector amplitudes to LDS, by rank (take).
 // The take of step 4 sits at the end of the loop body, so the compiler sees the loads of
@@ -662,7 +619,7 @@ __global__ __launch_bounds__(T) LDS_BOUND_OCCUPANCY void k_fwd(
   if (cst) csv = cs_of(item);
   if (RP && !INIT) tm.fetch(r, src_of(item), base_of(item));
   take(item);
-  if (cst) st.cs[threadIdx.x] = csv;
+  if (cst) st.cs[threadIdx.x] = signed_cs(csv, st.x[threadIdx.x], base_of(item));
   for (;;) {
     const uint32_t base = base_of(item);
     double2* __restrict__ v = vec_of(item);
@@ -675,7 +632,8 @@ __global__ __launch_bounds__(T) LDS_BOUND_OCCUPANCY void k_fwd(
       tm.refresh();
       if (RP && !INIT) tm.fetch(r, src_of(next), base_of(next));
     }
-    fwd_excitations<T>(cp, blk, st, ps.count, base);
+    fwd_excitations<T>(cp, blk, st.cs, ps.count);
+    __syncthreads();  // the excitations are applied
     // the whole tile: a fixed number of stores per thread, so the next take waits for its
     // own loads only
     if constexpr (RP) {
@@ -688,7 +646,7 @@ __global__ __launch_bounds__(T) LDS_BOUND_OCCUPANCY void k_fwd(
     __syncthreads();  // cp, the table and the (cos, sin) stage are no longer read
     stage_class(base_of(next));
     take(next);
-    if (cst) st.cs[threadIdx.x] = csv;
+    if (cst) st.cs[threadIdx.x] = signed_cs(csv, st.x[threadIdx.x], base_of(next));
     item = next;
   }
 }
@@ -705,9 +663,8 @@ __global__ __launch_bounds__(T) LDS_BOUND_OCCUPANCY void k_rev(
     const double2* __restrict__ cs, int K, double2* __restrict__ psi, double2* __restrict__ lam,
     int n, uint32_t amask, uint32_t bmask, double* __restrict__ gpart, int total, int flip) {
   extern __shared__ double2 lds[];
-  constexpr int NW = T / 64;
   __shared__ PassStage st;
-  __shared__ double red[kMaxPassExc][NW];  // per-wave partials of <lambda|G_k|psi>
+  __shared__ double gq[kGqWords];  // quad partials of <lambda|G_k|psi>
   using TL = Tile<T, KT>;
   using SC = Sector<T, KT>;
   constexpr bool RP = KT != 0;
@@ -757,7 +714,7 @@ __global__ __launch_bounds__(T) LDS_BOUND_OCCUPANCY void k_rev(
     tm.fetch(rl, lam + off_of(item), base_of(item));
   }
   take(item);
-  if (cst) st.cs[threadIdx.x] = csv;
+  if (cst) st.cs[threadIdx.x] = signed_cs(csv, st.x[threadIdx.x], base_of(item));
   for (;;) {
     const int b = ent(item);
     const uint32_t t = item & tmask;
@@ -774,12 +731,11 @@ __global__ __launch_bounds__(T) LDS_BOUND_OCCUPANCY void k_rev(
         tm.fetch(rl, lam + off_of(next), base_of(next));
       }
     }
-    rev_excitations<T>(cp, cl, blk, st, ps.count, base, red);
-    if (cst) {
-      double sum = 0.0;
-      for (int w = 0; w < NW; ++w) sum += red[threadIdx.x][w];
-      gpart[((size_t)b * K + st.x[threadIdx.x].k) * ntiles + t] = sum;
-    }
+    rev_excitations<T>(cp, cl, blk, st.cs, ps.count, gq);
+    __syncthreads();  // the excitations are applied and gq is complete
+    if (cst)
+      gpart[((size_t)b * K + st.x[threadIdx.x].k) * ntiles + t] =
+          rev_partial(gq, threadIdx.x, st.x[threadIdx.x], base);
     if constexpr (RP) {
       tm.refresh();
       if (WP) SC::put_tile(tm, cp, rtab, vp, base);
@@ -789,10 +745,10 @@ __global__ __launch_bounds__(T) LDS_BOUND_OCCUPANCY void k_rev(
       put_tile_loop<T>(ps.lmask, tileN, cl, rtab, vl, base);
     }
     if (next >= total) break;
-    __syncthreads();  // cp, cl, the table, red and the (cos, sin) stage are no longer read
+    __syncthreads();  // cp, cl, the table, gq and the (cos, sin) stage are no longer read
     stage_class(base_of(next));
     take(next);
-    if (cst) st.cs[threadIdx.x] = csv;
+    if (cst) st.cs[threadIdx.x] = signed_cs(csv, st.x[threadIdx.x], base_of(next));
     item = next;
   }
 }
@@ -916,9 +872,8 @@ __global__ __launch_bounds__(T) void k_whole(
     double* __restrict__ E, double* __restrict__ G, int ns, int max_blk, int max_blob,
     int max_slots, int max_occ, int fwd_state) {
   extern __shared__ double2 lds[];
-  constexpr int NW = T / 64;
   __shared__ PassStage st;
-  __shared__ double red[kMaxPassExc][NW];
+  __shared__ double gq[kGqWords];
   __shared__ int hf_rank;
   const int b = blockIdx.x;
   // LDS: (cos, sin) of every excitation | psi and lambda by rank | value table | per-tile
@@ -955,7 +910,7 @@ __global__ __launch_bounds__(T) void k_whole(
     for (int i = threadIdx.x; i < ps.count; i += T) {
       const DevExc x = exc[ps.first + i];
       st.x[i] = x;
-      st.cs[i] = csa[x.k];
+      st.cs[i] = signed_cs(csa[x.k], x, 0u);
     }
     const int2 bl = pcls[ps.cls_base];
     stage_words<T>(blk, blocks + bl.x, bl.y);
@@ -973,8 +928,9 @@ __global__ __launch_bounds__(T) void k_whole(
   for (int q = 0; q < nfwd; ++q) {
     const DevPass ps = passes[q];
     stage_pass(ps);
-    fwd_excitations<T>(cp, blk, st, ps.count, 0u);
+    fwd_excitations<T>(cp, blk, st.cs, ps.count);
   }
+  __syncthreads();  // the forward excitations are applied
   if (fwd_state) write_state();
   double etot = 0.0;
   for (int j = 0; j < nexp; ++j) {
@@ -996,12 +952,10 @@ __global__ __launch_bounds__(T) void k_whole(
     for (int j = 0; j < nrev; ++j) {
       const DevPass ps = passes[nfwd + nexp + j];
       stage_pass(ps);
-      rev_excitations<T>(cp, cl, blk, st, ps.count, 0u, red);
-      if ((int)threadIdx.x < ps.count) {
-        double sum = 0.0;
-        for (int w = 0; w < NW; ++w) sum += red[threadIdx.x][w];
-        G[(size_t)b * K + st.x[threadIdx.x].k] = 2.0 * sum;
-      }
+      rev_excitations<T>(cp, cl, blk, st.cs, ps.count, gq);
+      __syncthreads();  // the excitations are applied and gq is complete
+      if ((int)threadIdx.x < ps.count)
+        G[(size_t)b * K + st.x[threadIdx.x].k] = 2.0 * rev_partial(gq, threadIdx.x, st.x[threadIdx.x], 0u);
     }
   }
   if (threadIdx.x == 0) E[b] = etot;

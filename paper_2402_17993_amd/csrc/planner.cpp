@@ -488,8 +488,8 @@ std::string build_plan(Plan& p, int n, int ne, const double* h1, const double* h
     ws.swap(out);
     return true;
   };
-  // static LDS: the pass stage, plus per-wave gradient partials of up to 16 waves (reverse)
-  const int rev_static = kStageBytes + 16 * 8 * kMaxPassExc;
+  // static LDS: the pass stage, plus the gradient partials (reverse)
+  const int rev_static = kStageBytes + 8 * kGqWords;
   if (ckpt) {
     // one window list for both sweeps: it must fit the two-vector reverse pass; the reverse
     // pass of window w starts from the state forward window w left (stored)

@@ -38,6 +38,10 @@ struct DevExc {
 };
 
 constexpr int kMaxPassExc = 256;  // excitations per forward/reverse pass (staged in LDS)
+// Gradient partials of a reverse pass in LDS: quad q's partial of excitation e at
+// q * kGqStride + e (the stride spreads the 16 quads of one write over distinct banks).
+constexpr int kGqStride = kMaxPassExc + 1;
+constexpr int kGqWords = 16 * kGqStride;  // doubles
 
 // Class block of one forward/reverse pass for one tile class (the alpha and beta electron
 // counts of the tile's global bits): uint32 words
