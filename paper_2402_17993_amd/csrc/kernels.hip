@@ -94,6 +94,14 @@ typedef double dvec2 __attribute__((ext_vector_type(2)));
 
 __device__ __forceinline__ dvec2 ld16(const double2* p) { return *reinterpret_cast<const dvec2*>(p); }
 __device__ __forceinline__ void st16(double2* p, dvec2 v) { *reinterpret_cast<dvec2*>(p) = v; }
+// Streaming (non-temporal) forms for the state tiles, which are read and written once per
+// pass: they then do not push the tables that every tile reads out of the L2 cache.
+__device__ __forceinline__ dvec2 ld16_stream(const double2* p) {
+  return __builtin_nontemporal_load(reinterpret_cast<const dvec2*>(p));
+}
+__device__ __forceinline__ void st16_stream(double2* p, dvec2 v) {
+  __builtin_nontemporal_store(v, reinterpret_cast<dvec2*>(p));
+}
 
 // Fixed-size register buffer of N complex values addressed by compile-time index (a nest
 // of structs rather than an array, so it always lives in VGPRs).
@@ -162,7 +170,7 @@ struct Tile {
   // fetch issues every load of the thread into registers (waited on where they are used)
   template <int J = 0>
   __device__ __forceinline__ void fetch(Buf& r, const double2* __restrict__ v, uint32_t base) const {
-    rget<J, EPT>(r) = ld16(v + (base | off<J>()));
+    rget<J, EPT>(r) = ld16_stream(v + (base | off<J>()));
     if constexpr (J + 1 < EPT) fetch<J + 1>(r, v, base);
   }
 };
@@ -234,21 +242,30 @@ __device__ __forceinline__ double2 signed_cs(double2 cs, const DevExc& x, uint32
   return make_double2(cs.x, exc_sign(x, base) * cs.y);
 }
 
-// What excitation e needs before its amplitudes, loaded one excitation ahead by the lane:
-// (cos, signed sin), the range of its pairs in the class block and the lane's first entry.
-struct ExcNext {
+// The chain's per-excitation values, kept ahead of use by the lane: (cos, signed sin) and the
+// range of the excitation's pairs in the class block are loaded two excitations ahead, the
+// lane's first pair entry (which needs the range) one excitation ahead, so the entry a lane
+// needs is in its registers when the excitation starts and the amplitude reads are the only
+// LDS round trip on the chain.
+struct ExcRange {
   double2 t;
   int i0, i1;
-  uint32_t e0;
-  __device__ __forceinline__ void load(const double2* scs, const uint32_t* off, const uint32_t* ent,
-                                       int e, int lane) {
+  __device__ __forceinline__ void load(const double2* scs, const uint32_t* off, int e) {
     t = scs[e];
     i0 = (int)off[e];
     i1 = (int)off[e + 1];
-    const int i = i0 + lane;
-    e0 = i < i1 ? ent[i] : 0u;
   }
 };
+
+// The lane's first pair entry (0 without one).  The read itself is unconditional (of entry 0
+// where the lane has no pair), so the chain's LDS reads are a fixed sequence and the compiler
+// can wait for each of them by count.
+__device__ __forceinline__ uint32_t first_entry(const ExcRange& r, const uint32_t* ent, int lane) {
+  const int i = r.i0 + lane;
+  const bool in = i < r.i1;
+  const uint32_t v = ent[in ? i : 0];
+  return in ? v : 0u;
+}
 
 // Tile elements of the thread (registers) and the tile's in-sector amplitudes (LDS, by rank).
 // Amplitudes outside the N / S_z sector are exactly zero and stay zero (the reference state is
@@ -294,7 +311,7 @@ struct Sector {
     const uint32_t rk = rtab[threadIdx.x + J * T];
     const bool in = rk != kNoRank;
     const dvec2 d = ld16(cv + (in ? rk : 0u));
-    st16(v + (base | tm.template off<J>()), in ? d : dvec2{0.0, 0.0});
+    st16_stream(v + (base | tm.template off<J>()), in ? d : dvec2{0.0, 0.0});
     if constexpr (J + 1 < EPT) put_tile<J + 1>(tm, cv, rtab, v, base);
   }
 };
@@ -341,20 +358,39 @@ __device__ __forceinline__ void fwd_excitations(double2* cp, const uint32_t* blk
   const uint32_t* off = blk + 2;
   const int m = (int)blk[1], ns = (int)blk[0];
   const uint32_t* ent = blk + 3 + m + ((ns + 1) >> 1) + ns;
-  ExcNext nx;
-  nx.load(scs, off, ent, 0, lane);
+  ExcRange cur, nxt;
+  cur.load(scs, off, 0);
+  uint32_t e0 = first_entry(cur, ent, lane);
+  nxt = cur;
+  if (count > 1) nxt.load(scs, off, 1);
   for (int e = 0; e < count; ++e) {
-    const ExcNext cur = nx;
-    if (e + 1 < count) nx.load(scs, off, ent, e + 1, lane);
     const double c = cur.t.x, s = cur.t.y;
-    for (int i = cur.i0 + lane; i < cur.i1; i += 64) {
-      const uint32_t en = i == cur.i0 + lane ? cur.e0 : ent[i];
-      const uint32_t ru = en & 0x7fffu, rw = en >> 16;
-      const double sg = (en & 0x8000u) ? -s : s;
-      const double2 a = cp[ru], bb = cp[rw];
-      cp[ru] = make_double2(c * a.x - sg * bb.x, c * a.y - sg * bb.y);
-      cp[rw] = make_double2(c * bb.x + sg * a.x, c * bb.y + sg * a.y);
+    const int ia = cur.i0 + lane;
+    const bool has = ia < cur.i1;
+    const uint32_t ru = e0 & 0x7fffu, rw = e0 >> 16;
+    const double sg0 = (e0 & 0x8000u) ? -s : s;
+    // reads without branches (rank 0 where the lane has no pair; results unused there)
+    const double2 a = cp[has ? ru : 0u], bb = cp[has ? rw : 0u];
+    // ahead: the next excitation's first entry, the one after's range (clamped to the last
+    // excitation, whose values are then loaded again and not used)
+    const uint32_t e0n = first_entry(nxt, ent, lane);
+    ExcRange nn;
+    nn.load(scs, off, min(e + 2, count - 1));
+    if (has) {
+      cp[ru] = make_double2(c * a.x - sg0 * bb.x, c * a.y - sg0 * bb.y);
+      cp[rw] = make_double2(c * bb.x + sg0 * a.x, c * bb.y + sg0 * a.y);
     }
+    for (int i = ia + 64; i < cur.i1; i += 64) {
+      const uint32_t en = ent[i];
+      const uint32_t qu = en & 0x7fffu, qw = en >> 16;
+      const double sg = (en & 0x8000u) ? -s : s;
+      const double2 x = cp[qu], y = cp[qw];
+      cp[qu] = make_double2(c * x.x - sg * y.x, c * x.y - sg * y.y);
+      cp[qw] = make_double2(c * y.x + sg * x.x, c * y.y + sg * x.y);
+    }
+    cur = nxt;
+    nxt = nn;
+    e0 = e0n;
   }
 }
 
@@ -371,15 +407,34 @@ __device__ __forceinline__ void rev_excitations(double2* cp, double2* cl, const 
   const uint32_t* off = blk + 2;
   const int m = (int)blk[1], ns = (int)blk[0];
   const uint32_t* ent = blk + 3 + m + ((ns + 1) >> 1) + ns;
-  ExcNext nx;
-  nx.load(scs, off, ent, 0, lane);
+  ExcRange cur, nxt;
+  cur.load(scs, off, 0);
+  uint32_t e0 = first_entry(cur, ent, lane);
+  nxt = cur;
+  if (count > 1) nxt.load(scs, off, 1);
   for (int e = 0; e < count; ++e) {
-    const ExcNext cur = nx;
-    if (e + 1 < count) nx.load(scs, off, ent, e + 1, lane);
     const double c = cur.t.x, s = cur.t.y;
+    const int ia = cur.i0 + lane;
+    const bool has = ia < cur.i1;
+    const uint32_t ru = e0 & 0x7fffu, rw = e0 >> 16;
+    const bool neg0 = (e0 & 0x8000u) != 0u;
+    const uint32_t su = has ? ru : 0u, sw = has ? rw : 0u;
+    const double2 pu = cp[su], pw = cp[sw], lu = cl[su], lw = cl[sw];
+    const uint32_t e0n = first_entry(nxt, ent, lane);
+    ExcRange nn;
+    nn.load(scs, off, min(e + 2, count - 1));
     double g = 0.0;
-    for (int i = cur.i0 + lane; i < cur.i1; i += 64) {
-      const uint32_t en = i == cur.i0 + lane ? cur.e0 : ent[i];
+    if (has) {
+      const double t = (lw.x * pu.x + lw.y * pu.y) - (lu.x * pw.x + lu.y * pw.y);
+      g = neg0 ? -t : t;
+      const double sq = neg0 ? -s : s;
+      cp[ru] = make_double2(c * pu.x + sq * pw.x, c * pu.y + sq * pw.y);
+      cp[rw] = make_double2(c * pw.x - sq * pu.x, c * pw.y - sq * pu.y);
+      cl[ru] = make_double2(c * lu.x + sq * lw.x, c * lu.y + sq * lw.y);
+      cl[rw] = make_double2(c * lw.x - sq * lu.x, c * lw.y - sq * lu.y);
+    }
+    for (int i = ia + 64; i < cur.i1; i += 64) {
+      const uint32_t en = ent[i];
       const uint32_t qu = en & 0x7fffu, qw = en >> 16;
       const bool neg = (en & 0x8000u) != 0u;
       const double2 au = cp[qu], aw = cp[qw], bu = cl[qu], bw = cl[qw];
@@ -393,6 +448,9 @@ __device__ __forceinline__ void rev_excitations(double2* cp, double2* cl, const 
     }
     g = quad_sum(g);
     if ((lane & 3) == 0) gq[(lane >> 2) * kGqStride + e] = g;
+    cur = nxt;
+    nxt = nn;
+    e0 = e0n;
   }
 }
 
@@ -473,15 +531,25 @@ __device__ __forceinline__ double exp_rows(const double2* cp, const uint32_t* bl
   const uint16_t* sl = reinterpret_cast<const uint16_t*>(mid + ns);
   const uint32_t* sphys = mid + ns + ((ns + 1) >> 1);
   double eacc = 0.0;
-  for (int i0 = 0; i0 < ns; i0 += T / 4) {
+  // lambda in HBM: lane `sub` of every quad loads the old value of the quad's row in
+  // iteration `sub` up front (one memory latency per tile instead of one per row) and is the
+  // lane that adds that row's sum and stores it; later iterations load in the loop
+  dvec2 old_pre = {0.0, 0.0};
+  if (APPLY && !LDSLAM && !first) {
+    const int ir = sub * (T / 4) + ((int)threadIdx.x >> 2);
+    if (ir < ns) old_pre = ld16(vl + (base | sphys[ir]));
+  }
+  int it = 0;
+  for (int i0 = 0; i0 < ns; i0 += T / 4, ++it) {
     const int i = i0 + ((int)threadIdx.x >> 2);
     const bool row = i < ns;  // the same for the four lanes of a quad
+    const int owner = LDSLAM ? 0 : (it & 3);  // the lane that finishes row i
     double ax = 0.0, ay = 0.0;
     dvec2 old = {0.0, 0.0};
     uint32_t phys = 0u;
     if (row) {
       phys = LDSLAM ? (uint32_t)i : (base | sphys[i]);
-      if (APPLY && !first && sub == 0) old = ld16(vl + phys);
+      if (APPLY && !first && sub == owner) old = (!LDSLAM && it < 4) ? old_pre : ld16(vl + phys);
       // lane `sub` takes every fourth 16-byte chunk of four entries of the row
       const uint4* __restrict__ e4 = reinterpret_cast<const uint4*>(ent);
       const int q0 = (int)off[i] >> 2, q1 = (int)mid[i] >> 2, q2 = (int)off[i + 1] >> 2;
@@ -509,12 +577,20 @@ __device__ __forceinline__ double exp_rows(const double2* cp, const uint32_t* bl
         occ_entry(E.z);
         occ_entry(E.w);
       }
-      for (int q = q1 + sub; q < q2; q += 4) {
-        const uint4 E = e4[q];
+      // the lane's next chunk is requested before the current one is used
+      int q = q1 + sub;
+      uint4 E = make_uint4(0u, 0u, 0u, 0u);
+      if (q < q2) E = e4[q];
+      while (q < q2) {
+        const int qn = q + 4;
+        uint4 En = make_uint4(0u, 0u, 0u, 0u);
+        if (qn < q2) En = e4[qn];
         plain_entry(E.x);
         plain_entry(E.y);
         plain_entry(E.z);
         plain_entry(E.w);
+        E = En;
+        q = qn;
       }
       if (has_diag) {  // c0 + sum_r a_r n_r + sum_{r<s} b_rs n_r n_s; set bits split by rank
         double f = sub == 0 ? dpre[0] : 0.0;
@@ -534,7 +610,7 @@ __device__ __forceinline__ double exp_rows(const double2* cp, const uint32_t* bl
     }
     ax = quad_sum(ax);
     ay = quad_sum(ay);
-    if (row && sub == 0) {
+    if (row && sub == owner) {
       const double2 pu = cp[i];
       eacc += pu.x * ax + pu.y * ay;
       if (APPLY) st16(vl + phys, dvec2{old.x + ax, old.y + ay});
