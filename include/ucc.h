@@ -270,8 +270,9 @@ ucc_status ucc_profile_read(ucc_ctx* ctx, ucc_kernel_stat* stats, int32_t reset)
  * runs join at its next round.  Groups' kernels overlap on the device.  A job's result does
  * not depend on what else runs (bitwise).
  *
- * Footprint of one job: two complex128 state vectors of 2^n amplitudes (psi, lambda), its
- * per-tile partial sums, theta/cos-sin/gradient rows and one row of expectation tables.
+ * Footprint of one job: two complex128 state vectors of 2^n amplitudes (psi, lambda), plus
+ * n_fwd_passes - 1 more when the plan stores forward states, its per-tile partial sums,
+ * theta/cos-sin/gradient rows and one row of expectation tables.
  *
  *   hbm_budget_bytes  device memory the server may hold for job state (0 = 64 GiB)
  *   slots             maximum concurrently active jobs (1..4096)

@@ -288,7 +288,8 @@ int ucc_server::cu_share_for(const Group& g) const {
   auto members = [](const Group& h) { return h.jobs.size() + h.joining.size(); };
   auto work = [&](const Group& h) {
     const Plan& p = h.proto->plan;
-    return double(members(h)) * double(2 * p.nfwd + p.nexp + 4 * p.nrev) * double(size_t(1) << p.n);
+    return double(members(h)) * double(2 * p.nfwd + p.nexp + (p.ckpt ? 3 : 4) * p.nrev) *
+           double(size_t(1) << p.n);
   };
   auto demand = [&](const Group& h) {
     const Plan& p = h.proto->plan;
