@@ -141,10 +141,11 @@ struct Tile {
   static_assert(JB <= 5, "tile too large for the workgroup");
   using Buf = RegBuf<EPT>;
   uint32_t lmask;
+  uint32_t tid;  // the thread's index among the T threads that share the tile
   mutable uint32_t dt;
   uint32_t h0 = 0, h1 = 0, h2 = 0, h3 = 0, h4 = 0;  // physical bits of j's bits 0..4
-  __device__ __forceinline__ explicit Tile(uint32_t lm) : lmask(lm) {
-    dt = dep(threadIdx.x, lm);
+  __device__ __forceinline__ explicit Tile(uint32_t lm, uint32_t t = threadIdx.x) : lmask(lm), tid(t) {
+    dt = dep(t, lm);
     uint32_t mm = lm;
 #pragma unroll
     for (int i = 0; i < L2T; ++i) mm &= mm - 1;
@@ -284,20 +285,20 @@ struct Sector {
   using TL = Tile<T, KT>;
   static constexpr int EPT = TL::EPT;
   template <int J = 0>
-  static __device__ __forceinline__ void take(const typename TL::Buf& r, double2* cv,
+  static __device__ __forceinline__ void take(const TL& tm, const typename TL::Buf& r, double2* cv,
                                               const uint16_t* rtab) {
-    const uint32_t rk = rtab[threadIdx.x + J * T];
+    const uint32_t rk = rtab[tm.tid + J * T];
     // the element's load is waited for on every path (also where no lane is in the sector),
     // so no load stays pending into registers the next prefetch overwrites
     const dvec2& x = rget<J, EPT>(r);
     asm volatile("" : : "v"(x.x), "v"(x.y));
     if (rk != kNoRank) st16(cv + rk, x);
-    if constexpr (J + 1 < EPT) take<J + 1>(r, cv, rtab);
+    if constexpr (J + 1 < EPT) take<J + 1>(tm, r, cv, rtab);
   }
   template <int J = 0>
   static __device__ __forceinline__ void take_hf(const TL& tm, double2* cv, const uint16_t* rtab,
                                                  uint32_t base, uint32_t hf) {
-    const uint32_t rk = rtab[threadIdx.x + J * T];
+    const uint32_t rk = rtab[tm.tid + J * T];
     if (rk != kNoRank) {
       const uint32_t ph = base | tm.template off<J>();
       st16(cv + rk, dvec2{ph == hf ? 1.0 : 0.0, 0.0});
@@ -308,7 +309,7 @@ struct Sector {
   static __device__ __forceinline__ void put_tile(const TL& tm, const double2* cv,
                                                   const uint16_t* rtab, double2* __restrict__ v,
                                                   uint32_t base) {
-    const uint32_t rk = rtab[threadIdx.x + J * T];
+    const uint32_t rk = rtab[tm.tid + J * T];
     const bool in = rk != kNoRank;
     const dvec2 d = ld16(cv + (in ? rk : 0u));
     st16_stream(v + (base | tm.template off<J>()), in ? d : dvec2{0.0, 0.0});
@@ -685,7 +686,7 @@ __global__ __launch_bounds__(T) LDS_BOUND_OCCUPANCY void k_fwd(
       if (INIT)
         SC::take_hf(tm, cp, rtab, base_of(it), hf);
       else
-        SC::take(r, cp, rtab);
+        SC::take(tm, r, cp, rtab);
     } else {
       take_loop<T, INIT>(ps.lmask, tileN, cp, rtab, src_of(it), base_of(it), hf);
     }
@@ -775,8 +776,8 @@ __global__ __launch_bounds__(T) LDS_BOUND_OCCUPANCY void k_rev(
   };
   auto take = [&](int it) {
     if constexpr (RP) {
-      SC::take(rp, cp, rtab);
-      SC::take(rl, cl, rtab);
+      SC::take(tm, rp, cp, rtab);
+      SC::take(tm, rl, cl, rtab);
     } else {
       take_loop<T, false>(ps.lmask, tileN, cp, rtab, psi + off_of(it), base_of(it), 0u);
       take_loop<T, false>(ps.lmask, tileN, cl, rtab, lam + off_of(it), base_of(it), 0u);
@@ -827,6 +828,95 @@ __global__ __launch_bounds__(T) LDS_BOUND_OCCUPANCY void k_rev(
     if (cst) st.cs[threadIdx.x] = signed_cs(csv, st.x[threadIdx.x], base_of(next));
     item = next;
   }
+}
+
+// Reverse pass, overlapped form, for workgroups whose items all have the same tile (the grid
+// is a multiple of the tile count): the in-sector amplitudes of two items live in two LDS
+// slots.  While wave 0 applies the excitations of item j (slot j & 1) and stores its gradient
+// partials, the upper half of the workgroup writes item j - 1 out of the other slot and reads
+// item j + 1 into it (its (cos, signed sin) included), so the tile traffic runs beside the
+// excitation chain instead of around it.  The same class block and rank table serve both
+// slots.  A producer thread writes and then reads the same tile elements, hence the same LDS
+// ranks, so the two steps need no synchronization between threads.
+template <int T, int KT, bool WP>
+__global__ __launch_bounds__(T) LDS_BOUND_OCCUPANCY void k_rev2(
+    const DevPass* __restrict__ passes, int pidx, const DevExc* __restrict__ exc,
+    const int2* __restrict__ pcls, const uint32_t* __restrict__ pairs,
+    const double2* __restrict__ cs, int K, double2* __restrict__ psi, double2* __restrict__ lam,
+    int n, uint32_t amask, uint32_t bmask, double* __restrict__ gpart, int total, int flip) {
+  extern __shared__ double2 lds[];
+  constexpr int P = T / 2;  // producer threads: the upper half of the workgroup
+  __shared__ DevExc sx[kMaxPassExc];
+  __shared__ double2 scs[2][kMaxPassExc];
+  __shared__ double gq[kGqWords];
+  using TL = Tile<P, KT>;
+  using SC = Sector<P, KT>;
+  const DevPass ps = passes[pidx];
+  const uint32_t tileN = 1u << ps.k;
+  const int tb = n - ps.k;
+  const uint32_t tmask = (1u << tb) - 1u;
+  const int ntiles = 1 << tb;
+  const int ns_max = ps.ns_max;
+  double2* cpb = lds;                // [2][ns_max] psi by rank
+  double2* clb = lds + 2 * ns_max;   // [2][ns_max] lambda by rank
+  uint32_t* blk = reinterpret_cast<uint32_t*>(lds + 4 * ns_max);
+  uint16_t* rtab = reinterpret_cast<uint16_t*>(blk + ps.stage_len);
+  const int item0 = blockIdx.x;
+  if (item0 >= total) return;
+  const int nb = total >> tb;
+  auto ent = [&](int it) { return flip ? nb - 1 - (it >> tb) : it >> tb; };  // batch entry
+  auto base_of = [&](int it) { return dep(it & tmask, ps.gmask); };
+  auto off_of = [&](int it) { return (size_t)ent(it) << n; };
+  for (int i = threadIdx.x; i < ps.count; i += T) sx[i] = exc[ps.first + i];
+  {
+    const int2 bl = pcls[ps.cls_base + tile_class(base_of(item0), amask, bmask, ps.nbeta_g)];
+    stage_sc_class<T>(blk, rtab, pairs + bl.x, bl.y, tileN);  // its barriers publish sx too
+  }
+  const bool prod = (int)threadIdx.x >= P;
+  const TL tm(ps.lmask, prod ? threadIdx.x - P : 0u);
+  // producers: item `it` into slot s (its (cos, signed sin), then psi, then lambda)
+  auto read_item = [&](int it, int s) {
+    const uint32_t base = base_of(it);
+    for (int e = (int)tm.tid; e < ps.count; e += P)
+      scs[s][e] = signed_cs(cs[(size_t)ent(it) * K + sx[e].k], sx[e], base);
+    typename TL::Buf r;
+    tm.refresh();
+    tm.fetch(r, psi + off_of(it), base);
+    SC::take(tm, r, cpb + s * ns_max, rtab);
+    tm.refresh();
+    tm.fetch(r, lam + off_of(it), base);
+    SC::take(tm, r, clb + s * ns_max, rtab);
+  };
+  auto write_item = [&](int it, int s) {
+    const uint32_t base = base_of(it);
+    tm.refresh();
+    if (WP) SC::put_tile(tm, cpb + s * ns_max, rtab, psi + off_of(it), base);
+    SC::put_tile(tm, clb + s * ns_max, rtab, lam + off_of(it), base);
+  };
+  if (prod) read_item(item0, 0);
+  __syncthreads();
+  int item = item0, j = 0;
+  for (;;) {
+    const int slot = j & 1;
+    const int next = item + gridDim.x;
+    if (threadIdx.x < 64) {
+      rev_excitations<T>(cpb + slot * ns_max, clb + slot * ns_max, blk, scs[slot], ps.count, gq);
+      // the chain's partials are this wave's own LDS writes: read back in issue order
+      const uint32_t base = base_of(item);
+      const int b = ent(item);
+      const uint32_t t = item & tmask;
+      for (int e = threadIdx.x; e < ps.count; e += 64)
+        gpart[((size_t)b * K + sx[e].k) * ntiles + t] = rev_partial(gq, e, sx[e], base);
+    } else if (prod) {
+      if (j > 0) write_item(item - (int)gridDim.x, slot ^ 1);
+      if (next < total) read_item(next, slot ^ 1);
+    }
+    __syncthreads();  // item j applied; item j + 1 read; item j - 1 written
+    if (next >= total) break;
+    item = next;
+    ++j;
+  }
+  if (prod) write_item(item, j & 1);
 }
 
 // Expectation / apply-H pass.  Only in-sector basis states can be non-zero.  For every
@@ -908,7 +998,7 @@ __global__ __launch_bounds__(T) LDS_BOUND_OCCUPANCY void k_exp(
     const uint32_t base = base_of(item);
     double2* __restrict__ vl = APPLY ? lam + ((size_t)b << n) : nullptr;
     if constexpr (RP)
-      SC::take(r, cp, rtab);
+      SC::take(tm, r, cp, rtab);
     else
       take_loop<T, false>(ps.lmask, tileN, cp, rtab, vec_of(item), base, 0u);
     exp_prep<T>(bw, t1, t2, dpre, ps.lmask, k, n, base);
@@ -1145,8 +1235,38 @@ hipError_t fwd_t(const LaunchArgs& a, int pidx, int init, const double2* src, do
   return init ? fwd_ti<T, KT, true>(a, pidx, src, dst) : fwd_ti<T, KT, false>(a, pidx, src, dst);
 }
 
+// The overlapped reverse pass needs every workgroup to keep one tile (a grid that is a
+// multiple of the tile count), register staging and room for two LDS slots.
+template <int T, int KT, bool WP>
+hipError_t rev_overlapped(const LaunchArgs& a, int pidx, double2* psi, bool* used) {
+  *used = false;
+  if constexpr (T < 512 || KT == 0) {
+    return hipSuccess;
+  } else {
+    const DevPass& hp = a.hpasses[pidx];
+    const int k = hp.k;
+    const int ntiles = 1 << (a.n - k);
+    const size_t lds = sc_lds(hp, 4);
+    const size_t stat = sizeof(DevExc) * kMaxPassExc + 2 * 16 * kMaxPassExc + 8 * kGqWords;
+    if (lds + stat > (size_t)kLdsBytes) return hipSuccess;
+    hipError_t e = set_lds(k_rev2<T, KT, WP>, lds);
+    if (e != hipSuccess) return e;
+    const int total = a.B << (a.n - k);
+    const int grid = pass_grid(total, resident_grid(k_rev2<T, KT, WP>, T, lds, a.cu_share), ntiles);
+    if (grid < ntiles || grid % ntiles != 0) return hipSuccess;
+    hipLaunchKernelGGL((k_rev2<T, KT, WP>), dim3(grid), dim3(T), lds, a.stream, a.passes, pidx,
+                       a.exc, a.cls, a.pairs, a.cs, a.K, psi, a.lam, a.n, a.amask, a.bmask,
+                       a.gpart, total, a.flip);
+    *used = true;
+    return hipGetLastError();
+  }
+}
+
 template <int T, int KT, bool WP>
 hipError_t rev_tw(const LaunchArgs& a, int pidx, double2* psi) {
+  bool used = false;
+  hipError_t e0 = rev_overlapped<T, KT, WP>(a, pidx, psi, &used);
+  if (e0 != hipSuccess || used) return e0;
   const DevPass& hp = a.hpasses[pidx];
   const int k = hp.k;
   const size_t lds = sc_lds(hp, 2);
