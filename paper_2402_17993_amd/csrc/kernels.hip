@@ -168,11 +168,12 @@ struct Tile {
     return dt | ((J & 1) ? h0 : 0u) | ((J & 2) ? h1 : 0u) | ((J & 4) ? h2 : 0u) |
            ((J & 8) ? h3 : 0u) | ((J & 16) ? h4 : 0u);
   }
-  // fetch issues every load of the thread into registers (waited on where they are used)
-  template <int J = 0>
+  // fetch issues the loads of elements J .. JE - 1 of the thread into registers (waited on
+  // where they are used)
+  template <int J = 0, int JE = EPT>
   __device__ __forceinline__ void fetch(Buf& r, const double2* __restrict__ v, uint32_t base) const {
     rget<J, EPT>(r) = ld16_stream(v + (base | off<J>()));
-    if constexpr (J + 1 < EPT) fetch<J + 1>(r, v, base);
+    if constexpr (J + 1 < JE) fetch<J + 1, JE>(r, v, base);
   }
 };
 
@@ -284,7 +285,7 @@ template <int T, int KT>
 struct Sector {
   using TL = Tile<T, KT>;
   static constexpr int EPT = TL::EPT;
-  template <int J = 0>
+  template <int J = 0, int JE = EPT>
   static __device__ __forceinline__ void take(const TL& tm, const typename TL::Buf& r, double2* cv,
                                               const uint16_t* rtab) {
     const uint32_t rk = rtab[tm.tid + J * T];
@@ -293,7 +294,7 @@ struct Sector {
     const dvec2& x = rget<J, EPT>(r);
     asm volatile("" : : "v"(x.x), "v"(x.y));
     if (rk != kNoRank) st16(cv + rk, x);
-    if constexpr (J + 1 < EPT) take<J + 1>(tm, r, cv, rtab);
+    if constexpr (J + 1 < JE) take<J + 1, JE>(tm, r, cv, rtab);
   }
   template <int J = 0>
   static __device__ __forceinline__ void take_hf(const TL& tm, double2* cv, const uint16_t* rtab,
@@ -514,12 +515,14 @@ __device__ __forceinline__ void exp_prep(const uint32_t* bw, double* t1, double*
 // diagonal) in a fixed order.  Returns the thread's share of sum_u Re(conj(psi[u]) (H psi)[u]).
 // With APPLY the row sums are added into lambda (first pass: written): in HBM at base | the
 // state's local offset (LDSLAM false), or in LDS by rank (LDSLAM true).
-template <int T, bool APPLY, bool LDSLAM>
+// OLDL: the old lambda values of the rows are in LDS (oldl, by rank), read there instead of
+// from HBM.
+template <int T, bool APPLY, bool LDSLAM, bool OLDL = false>
 __device__ __forceinline__ double exp_rows(const double2* cp, const uint32_t* blk,
                                            const uint32_t* __restrict__ ent, const uint32_t* bw,
                                            const double* t1, const double* t2, const double* dpre,
                                            int k, int n, uint32_t base, double2* __restrict__ vl,
-                                           int first) {
+                                           int first, const double2* oldl = nullptr) {
   const double* dw = reinterpret_cast<const double*>(bw);
   const int has_diag = (int)bw[2];
   const uint32_t* xloc = bw + bw[5];
@@ -536,7 +539,7 @@ __device__ __forceinline__ double exp_rows(const double2* cp, const uint32_t* bl
   // iteration `sub` up front (one memory latency per tile instead of one per row) and is the
   // lane that adds that row's sum and stores it; later iterations load in the loop
   dvec2 old_pre = {0.0, 0.0};
-  if (APPLY && !LDSLAM && !first) {
+  if (APPLY && !LDSLAM && !OLDL && !first) {
     const int ir = sub * (T / 4) + ((int)threadIdx.x >> 2);
     if (ir < ns) old_pre = ld16(vl + (base | sphys[ir]));
   }
@@ -550,7 +553,8 @@ __device__ __forceinline__ double exp_rows(const double2* cp, const uint32_t* bl
     uint32_t phys = 0u;
     if (row) {
       phys = LDSLAM ? (uint32_t)i : (base | sphys[i]);
-      if (APPLY && !first && sub == owner) old = (!LDSLAM && it < 4) ? old_pre : ld16(vl + phys);
+      if (APPLY && !first && sub == owner)
+        old = OLDL ? ld16(oldl + i) : (!LDSLAM && it < 4) ? old_pre : ld16(vl + phys);
       // lane `sub` takes every fourth 16-byte chunk of four entries of the row
       const uint4* __restrict__ e4 = reinterpret_cast<const uint4*>(ent);
       const int q0 = (int)off[i] >> 2, q1 = (int)mid[i] >> 2, q2 = (int)off[i + 1] >> 2;
@@ -1022,6 +1026,109 @@ __global__ __launch_bounds__(T) LDS_BOUND_OCCUPANCY void k_exp(
   }
 }
 
+// Expectation / apply-H pass, overlapped form for light passes (few entries per row) whose
+// workgroups keep one tile and one value table: the lower half of the workgroup walks the
+// rows of item j (LDS slot j & 1) while the upper half reads the tile of item j + 1 into the
+// other slot, in two halves of registers.  The walk's own memory reads (entries, old lambda)
+// then never queue behind the tile's loads (vector-memory counters are per wave).  The
+// per-tile slot values depend only on the tile, so they are computed once.
+template <int T, int KT, bool APPLY>
+__global__ __launch_bounds__(T) LDS_BOUND_OCCUPANCY void k_exp2(
+    const DevPass* __restrict__ passes, int pidx, const uint4* __restrict__ blobs,
+    const int2* __restrict__ pcls, const uint32_t* __restrict__ blocks,
+    const double2* __restrict__ psi, double2* __restrict__ lam, int n, uint32_t amask,
+    uint32_t bmask, double* __restrict__ epart, int estride, int first, int total, int flip) {
+  extern __shared__ double2 lds[];
+  constexpr int P = T / 2;    // producers: the upper half
+  constexpr int NWW = P / 64;  // walker waves
+  using TL = Tile<P, KT>;
+  using SC = Sector<P, KT>;
+  constexpr int H = TL::EPT / 2;  // elements per register half
+  __shared__ double red[2][16];
+  const DevPass ps = passes[pidx];
+  const uint32_t tileN = 1u << ps.k;
+  const int k = ps.k;
+  const int tb = n - ps.k;
+  const uint32_t tmask = (1u << tb) - 1u;
+  const int ns_max = ps.ns_max;
+  // LDS: psi of two items by rank | (APPLY) old lambda of two items by rank | value table |
+  //      slot values t1, t2 | diagonal prep | class block | rank table
+  double2* cpb = lds;
+  double2* clb = lds + 2 * ns_max;
+  uint4* lb = reinterpret_cast<uint4*>(lds + (APPLY ? 4 : 2) * ns_max);
+  double* t1 = reinterpret_cast<double*>(lb + ps.blob_len);
+  double* t2 = t1 + ((ps.n_slots + 1) & ~1);
+  double* dpre = t2 + ((ps.n_occ + 1) & ~1);
+  uint32_t* blk = reinterpret_cast<uint32_t*>(dpre + ((k + 2) & ~1));
+  uint16_t* rtab = reinterpret_cast<uint16_t*>(blk + ps.stage_len);
+  const uint32_t* bw = reinterpret_cast<const uint32_t*>(lb);
+  const int item0 = blockIdx.x;
+  if (item0 >= total) return;
+  const int nb = total >> tb;
+  auto ent = [&](int it) { return flip ? nb - 1 - (it >> tb) : it >> tb; };  // batch entry
+  auto base_of = [&](int it) { return dep(it & tmask, ps.gmask); };
+  const uint32_t base = base_of(item0);  // the same for every item of the workgroup
+  const uint32_t t = item0 & tmask;
+  {
+    const uint4* __restrict__ gb = blobs + ps.blob_off;
+    for (int i = threadIdx.x; i < ps.blob_len; i += T) lb[i] = gb[i];
+  }
+  const uint32_t* gent;
+  {
+    const int2 bl = pcls[ps.cls_base + tile_class(base, amask, bmask, ps.nbeta_g)];
+    const uint32_t* src = blocks + bl.x;
+    const int ns = (int)src[0];
+    const int words = (3 + 3 * ns + ((ns + 1) >> 1) + 3) & ~3;
+    stage_sc_class<T, true>(blk, rtab, src, words, tileN);  // its barriers publish the table
+    gent = src + words;
+  }
+  exp_prep<T>(bw, t1, t2, dpre, ps.lmask, k, n, base);
+  const bool prod = (int)threadIdx.x >= P;
+  const TL tm(ps.lmask, prod ? threadIdx.x - P : 0u);
+  const int nsc = (int)blk[0];
+  const uint32_t* sphys = blk + 2 + 2 * nsc + 1 + ((nsc + 1) >> 1);  // rows' local offsets
+  auto read_item = [&](int it, int s) {
+    const double2* v = psi + ((size_t)ent(it) << n);
+    typename TL::Buf r;
+    tm.refresh();
+    tm.template fetch<0, H>(r, v, base);
+    SC::template take<0, H>(tm, r, cpb + s * ns_max, rtab);
+    tm.refresh();
+    tm.template fetch<H, 2 * H>(r, v, base);
+    SC::template take<H, 2 * H>(tm, r, cpb + s * ns_max, rtab);
+    if (APPLY && !first) {  // the rows' old lambda values, for the walk to read from LDS
+      const double2* vl = lam + ((size_t)ent(it) << n);
+      for (int i = (int)tm.tid; i < nsc; i += P) st16(clb + s * ns_max + i, ld16(vl + (base | sphys[i])));
+    }
+  };
+  if (prod) read_item(item0, 0);
+  __syncthreads();  // slot 0, t1, t2, dpre
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  int item = item0, j = 0;
+  for (;;) {
+    const int slot = j & 1;
+    const int next = item + gridDim.x;
+    if (!prod) {
+      double2* __restrict__ vl = APPLY ? lam + ((size_t)ent(item) << n) : nullptr;
+      double e = exp_rows<P, APPLY, false, APPLY>(cpb + slot * ns_max, blk, gent, bw, t1, t2, dpre,
+                                                  k, n, base, vl, first, clb + slot * ns_max);
+      e = wave_sum(e);
+      if (lane == 0) red[slot][w] = e;
+    } else if (next < total) {
+      read_item(next, slot ^ 1);
+    }
+    __syncthreads();  // item j walked, its wave sums written; item j + 1 read
+    if (threadIdx.x == 0) {
+      double sum = 0.0;
+      for (int i = 0; i < NWW; ++i) sum += red[slot][i];
+      epart[(size_t)ent(item) * estride + t] = sum;
+    }
+    if (next >= total) break;
+    item = next;
+    ++j;
+  }
+}
+
 // Whole evaluation in one launch, for states that are a single tile (every pass has k = n):
 // one workgroup per batch entry keeps the in-sector amplitudes of psi and lambda in LDS
 // through all passes.  It forms cos/sin, synthesizes |HF>, runs the forward passes, the
@@ -1286,8 +1393,41 @@ hipError_t rev_t(const LaunchArgs& a, int pidx, double2* psi, bool wp) {
   return wp ? rev_tw<T, KT, true>(a, pidx, psi) : rev_tw<T, KT, false>(a, pidx, psi);
 }
 
+// Passes with at most this many entries per row take the overlapped form where it applies.
+constexpr int kLightRow = 64;
+
+template <int T, int KT, bool APPLY>
+hipError_t exp_overlapped(const LaunchArgs& a, int pidx, int eslot, int first, bool* used) {
+  *used = false;
+  if constexpr (T < 512 || KT == 0 || (T == 512 && KT > 13)) {
+    return hipSuccess;
+  } else {
+    const DevPass& hp = a.hpasses[pidx];
+    const int k = hp.k;
+    const int ntiles = 1 << (a.n - k);
+    if (hp.row_avg > kLightRow || a.blob_stride != 0) return hipSuccess;
+    const size_t lds = (APPLY ? 64 : 32) * size_t(hp.ns_max) + 16 * size_t(hp.blob_len) +
+                       8 * (size_t((hp.n_slots + 1) & ~1) + size_t((hp.n_occ + 1) & ~1) + size_t((k + 2) & ~1)) +
+                       4 * size_t(hp.stage_len) + (size_t(2) << k);
+    if (lds + 256 > (size_t)kLdsBytes) return hipSuccess;
+    hipError_t e = set_lds(k_exp2<T, KT, APPLY>, lds);
+    if (e != hipSuccess) return e;
+    const int total = a.B << (a.n - k);
+    const int grid = pass_grid(total, resident_grid(k_exp2<T, KT, APPLY>, T, lds, a.cu_share), ntiles);
+    if (grid < ntiles || grid % ntiles != 0) return hipSuccess;
+    hipLaunchKernelGGL((k_exp2<T, KT, APPLY>), dim3(grid), dim3(T), lds, a.stream, a.passes, pidx,
+                       a.blobs, a.cls, a.pairs, a.psi, a.lam, a.n, a.amask, a.bmask,
+                       a.epart + (size_t)eslot, a.estride, first, total, a.flip);
+    *used = true;
+    return hipGetLastError();
+  }
+}
+
 template <int T, int KT, bool APPLY>
 hipError_t exp_t(const LaunchArgs& a, int pidx, int eslot, int first) {
+  bool used = false;
+  hipError_t e0 = exp_overlapped<T, KT, APPLY>(a, pidx, eslot, first, &used);
+  if (e0 != hipSuccess || used) return e0;
   const DevPass& hp = a.hpasses[pidx];
   const int k = hp.k;
   const size_t lds = 16 * size_t(hp.ns_max) + 16 * size_t(hp.blob_len) +

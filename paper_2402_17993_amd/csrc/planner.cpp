@@ -797,10 +797,13 @@ void build_tables(const Plan& p, Tables& t) {
       dp.nbeta_g = nbg;
       dp.stage_len = 0;
       dp.ns_max = 0;
+      size_t rows = 0, entries = 0;
       for (auto& bk : buckets) {
         const size_t ns = bk.size();
         std::vector<uint32_t> off, mid, ent;
         exp_class_rows(p, ps.lmask, e, bk, &off, &mid, &ent, nullptr);
+        rows += ns;
+        entries += ent.size();
         std::vector<uint32_t> blk;
         blk.push_back((uint32_t)ns);
         blk.push_back((uint32_t)ent.size());
@@ -819,6 +822,7 @@ void build_tables(const Plan& p, Tables& t) {
         t.pairs.insert(t.pairs.end(), blk.begin(), blk.end());
       }
       dp.stage_len = (dp.stage_len + 3) & ~3;
+      dp.row_avg = rows ? (int)((entries + rows - 1) / rows) : 0;
     } else {
       dp.first = (int)t.exc.size();
       dp.count = (int)ps.items.size();

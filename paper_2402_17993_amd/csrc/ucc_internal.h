@@ -100,7 +100,7 @@ struct DevPass {
   int32_t n_slots;   // exp: slots of the value table
   int32_t n_occ;     // exp: slots with occupation rows
   int32_t has_diag;  // exp: the diagonal group is in this pass
-  int32_t pad;
+  int32_t row_avg;   // exp: entries per target row, averaged over the pass's classes (rounded up)
 };
 
 // Host-side plan: everything ucc_build derives from the inputs.
