@@ -25,6 +25,13 @@ Gradient: dE/dtheta_k = 2 Re <lambda_k| G_k |psi_k>, with psi_k the state
 after factor k and lambda_k = U_{k+1}^dag ... U_K^dag H psi_K, swept from
 k = K down to 1 (the adjoint method).
 
+Trotter variants (Eqs. 5 and 6): M slices of the first-order product apply
+the list M times with angles theta/M; the second-order (symmetric) product
+applies, per slice, the list in order and then in reverse order, with
+angles theta/(2M).  Reading: factors act in the order they are listed (the
+first row first), as for M = 1.  A parameter that occurs several times gets
+the sum of its occurrences' adjoint terms, each times the angle scale.
+
 Pinned by: dense expm of G_k, the four-term parameter-shift rule and
 central finite differences, the Slater-Condon gradient at theta = 0.
 """
@@ -79,36 +86,53 @@ def all_pairs(n, exc):
     return [excitation_pairs(n, row) for row in np.asarray(exc).reshape(-1, 4)]
 
 
-def trotter_state(n, hf_occ, exc, theta, pairs=None):
-    """U_K ... U_1 |HF> (Eq. 5 with M = 1)."""
-    if pairs is None:
-        pairs = all_pairs(n, exc)
-    psi = hf_state(n, hf_occ)
-    for pk, t in zip(pairs, np.asarray(theta, dtype=np.float64)):
-        psi = apply_factor(psi, pk, t)
+def trotter_sequence(n_exc, slices=1, order=1):
+    """Factors of Eq. 5 (order 1) or Eq. 6 (order 2) in the order they act: the parameter
+    index of each factor, and the scale of its angle (1/M, or 1/(2M))."""
+    if slices < 1 or order not in (1, 2):
+        raise ValueError("slices >= 1 and order 1 or 2")
+    one = list(range(n_exc)) if order == 1 else list(range(n_exc)) + list(range(n_exc - 1, -1, -1))
+    return one * slices, 1.0 / (slices * order)
+
+
+def apply_sequence(psi, pairs, theta, slices=1, order=1):
+    """The Trotter product for amplitudes theta applied to psi."""
+    seq, scale = trotter_sequence(len(pairs), slices, order)
+    theta = np.asarray(theta, dtype=np.float64)
+    for k in seq:
+        psi = apply_factor(psi, pairs[k], scale * theta[k])
     return psi
 
 
-def energy(h, g, n, hf_occ, exc, theta, pairs=None):
+def trotter_state(n, hf_occ, exc, theta, pairs=None, slices=1, order=1):
+    """The Trotter product applied to |HF> (U_K ... U_1 |HF> for Eq. 5 with M = 1)."""
+    if pairs is None:
+        pairs = all_pairs(n, exc)
+    return apply_sequence(hf_state(n, hf_occ), pairs, theta, slices, order)
+
+
+def energy(h, g, n, hf_occ, exc, theta, pairs=None, slices=1, order=1):
     """Trotterized UCCSD energy <Psi|H|Psi> (the VQE cost)."""
-    psi = trotter_state(n, hf_occ, exc, theta, pairs)
+    psi = trotter_state(n, hf_occ, exc, theta, pairs, slices, order)
     return _energy(h, g, psi)[0]
 
 
-def energy_and_gradient(h, g, n, hf_occ, exc, theta, pairs=None, return_states=False):
-    """(E, dE/dtheta) by a forward pass and an adjoint reverse sweep."""
+def energy_and_gradient(h, g, n, hf_occ, exc, theta, pairs=None, return_states=False,
+                        slices=1, order=1):
+    """(E, dE/dtheta) by a forward pass and an adjoint reverse sweep over the factors."""
     if pairs is None:
         pairs = all_pairs(n, exc)
     theta = np.asarray(theta, dtype=np.float64)
-    psi = trotter_state(n, hf_occ, exc, theta, pairs)
+    seq, scale = trotter_sequence(theta.size, slices, order)
+    psi = trotter_state(n, hf_occ, exc, theta, pairs, slices, order)
     lam = apply_h(h, g, psi)
     e = np.vdot(psi, lam)
     psi_final = psi.copy()
     grad = np.zeros(theta.size)
-    for k in range(theta.size - 1, -1, -1):
-        grad[k] = 2.0 * np.vdot(lam, apply_generator(psi, pairs[k])).real
-        psi = apply_factor(psi, pairs[k], -theta[k])
-        lam = apply_factor(lam, pairs[k], -theta[k])
+    for k in reversed(seq):
+        grad[k] += scale * 2.0 * np.vdot(lam, apply_generator(psi, pairs[k])).real
+        psi = apply_factor(psi, pairs[k], -scale * theta[k])
+        lam = apply_factor(lam, pairs[k], -scale * theta[k])
     if return_states:
         return float(e.real), grad, dict(psi=psi_final, psi_back=psi, im_e=float(e.imag))
     return float(e.real), grad

@@ -23,7 +23,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 
 def case_dimer_18q():
     """18 qubits, 10 electrons, integrals seed 0, batch of 64 thetas U(-0.05, 0.05) from seeds
-    1..64: oracle energy and gradient of batch entries 0, 1 and 63."""
+    1..64: oracle energy of every batch entry, and energy and gradient of entries 0, 1, 9, 18,
+    27, 36, 45, 54 and 63."""
     n, ne = 18, 10
     h1, h2 = make_integrals(n // 2, 0)
     h, g = hamiltonian.spin_orbital_integrals(h1, h2)
@@ -32,9 +33,10 @@ def case_dimer_18q():
     pairs = ansatz.all_pairs(n, exc)
     out = {"n": n, "ne": ne, "integral_seed": 0, "theta_seed": 1, "theta_scale": 0.05,
            "batch": 64, "entries": {}}
-    for b in (0, 1, 63):
+    for b in (0, 1, 9, 18, 27, 36, 45, 54, 63):
         e, gr = ansatz.energy_and_gradient(h, g, n, (1 << ne) - 1, exc, thetas[b], pairs)
         out["entries"][str(b)] = {"energy": e, "grad": gr.tolist()}
+    out["energies"] = [ansatz.energy(h, g, n, (1 << ne) - 1, exc, thetas[b], pairs) for b in range(64)]
     return out
 
 

@@ -239,7 +239,7 @@ def test_16q_autotuned_context(ucc):
 
 
 def test_18q_batch64_against_stored_oracle_values(ucc):
-    say("case: 18q/10e batch 64 energy+grad (stored oracle values for entries 0, 1, 63)")
+    say("case: 18q/10e batch 64 energy+grad (stored oracle energies of all 64 entries, gradients of 9)")
     gold = json.load(open(os.path.join(HERE, "golden", "dimer_18q.json")))
     n, ne = gold["n"], gold["ne"]
     h1, h2 = make_integrals(n // 2, gold["integral_seed"])
@@ -247,6 +247,7 @@ def test_18q_batch64_against_stored_oracle_values(ucc):
     th = make_thetas(len(exc), gold["theta_seed"], gold["theta_scale"], batch=gold["batch"])
     ctx = ucc.Context(n, ne, h1, h2, exc, max_batch=64)
     e, gr = ctx.energy_grad(th)
+    assert np.max(np.abs(e - np.array(gold["energies"]))) <= E_TOL
     for b, ent in gold["entries"].items():
         b = int(b)
         assert abs(e[b] - ent["energy"]) <= E_TOL, b
@@ -256,6 +257,7 @@ def test_18q_batch64_against_stored_oracle_values(ucc):
     tuned = ucc.Context(n, ne, h1, h2, exc, max_batch=64, autotune=True)
     say(f"autotuned: {tuned.plan_info()}")
     et, gt = tuned.energy_grad(th)
+    assert np.max(np.abs(et - np.array(gold["energies"]))) <= E_TOL
     for b, ent in gold["entries"].items():
         b = int(b)
         assert abs(et[b] - ent["energy"]) <= E_TOL, b

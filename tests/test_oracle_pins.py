@@ -372,3 +372,69 @@ def test_steepest_descent_lowers_energy():
     es, _ = ansatz.steepest_descent(h, g, n, hf_mask(ne), exc, th0, 20, 0.1)
     assert es.shape == (21,)
     assert np.all(np.diff(es) < 1e-12)
+
+
+# ---------------------------------------------------------------- P12-P15: Trotter variants (Eqs. 5, 6)
+
+def test_p12_variants_reduce_to_the_single_slice_product():
+    n, ne = 8, 4
+    _, _, h, g = system(4, ne, seed=2)
+    exc = uccsd_excitations(n, ne)
+    th = make_thetas(len(exc), 3, 0.3)
+    e1, g1 = ansatz.energy_and_gradient(h, g, n, hf_mask(ne), exc, th)
+    e2, g2 = ansatz.energy_and_gradient(h, g, n, hf_mask(ne), exc, th, slices=1, order=1)
+    assert e1 == e2 and np.array_equal(g1, g2)
+    # the second-order product with M slices is the first-order product of the list followed by
+    # its reverse, M times, at angles theta / (2M): built here from dense matrices
+    M = 2
+    psi = ansatz.hf_state(n, hf_mask(ne))
+    seq = (list(range(len(exc))) + list(range(len(exc) - 1, -1, -1))) * M
+    for k in seq:
+        psi = scipy.linalg.expm(th[k] / (2 * M) * dense.generator_dense(n, exc[k])) @ psi
+    np.testing.assert_allclose(ansatz.trotter_state(n, hf_mask(ne), exc, th, slices=M, order=2), psi,
+                               atol=1e-13)
+
+
+@pytest.mark.parametrize("order,expected", [(1, 0.5), (2, 0.25)])
+def test_p13_trotter_error_shrinks_as_1_over_m_to_the_order(order, expected):
+    # against the Trotter-free state exp(sum_k theta_k G_k)|HF>: the error of the first-order
+    # product falls as 1/M, the symmetric one as 1/M^2
+    n, ne = 8, 4
+    exc = uccsd_excitations(n, ne)
+    th = make_thetas(len(exc), 5, 0.3)
+    A = sum(t * dense.generator_dense(n, row) for t, row in zip(th, exc))
+    exact = scipy.linalg.expm(A) @ ansatz.hf_state(n, hf_mask(ne))
+    err = {M: np.linalg.norm(ansatz.trotter_state(n, hf_mask(ne), exc, th, slices=M, order=order) - exact)
+           for M in (8, 16)}
+    ratio = err[16] / err[8]
+    assert abs(ratio - expected) < 0.1 * expected, (order, err)
+
+
+def test_p14_symmetric_product_is_time_reversible():
+    # S(-theta) S(theta) = 1 for the second-order product; not for the first-order one
+    n, ne = 8, 4
+    exc = uccsd_excitations(n, ne)
+    pairs = ansatz.all_pairs(n, exc)
+    th = make_thetas(len(exc), 7, 0.4)
+    hf = ansatz.hf_state(n, hf_mask(ne))
+    for M in (1, 2):
+        back = ansatz.apply_sequence(ansatz.apply_sequence(hf, pairs, th, M, 2), pairs, -th, M, 2)
+        assert np.max(np.abs(back - hf)) < 1e-13
+    back = ansatz.apply_sequence(ansatz.apply_sequence(hf, pairs, th, 1, 1), pairs, -th, 1, 1)
+    assert np.max(np.abs(back - hf)) > 1e-4
+
+
+@pytest.mark.parametrize("slices,order", [(3, 1), (2, 2)])
+def test_p15_variant_gradient_central_differences(slices, order):
+    n, ne = 8, 4
+    _, _, h, g = system(4, ne, seed=4)
+    exc = uccsd_excitations(n, ne)
+    th = make_thetas(len(exc), 11, 0.3)
+    _, grad = ansatz.energy_and_gradient(h, g, n, hf_mask(ne), exc, th, slices=slices, order=order)
+    for k in range(len(exc)):
+        def E(d):
+            t = th.copy()
+            t[k] += d
+            return ansatz.energy(h, g, n, hf_mask(ne), exc, t, slices=slices, order=order)
+        fd = (E(1e-4) - E(-1e-4)) / 2e-4
+        assert abs(fd - grad[k]) < 1e-7, k
