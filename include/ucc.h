@@ -49,7 +49,8 @@ typedef struct ucc_server ucc_server; /* opaque: continuous-batching VQE server 
 
 /* Build options.  Zero means "choose automatically" unless stated otherwise. */
 typedef struct {
-  int32_t trotter_steps;     /* M of Eq. 5; only 1 is supported (0 is read as 1) */
+  int32_t trotter_steps;     /* M of Eqs. 5 and 6: slices of the Trotter product, 1..64 (0 is
+                                read as 1); every factor's angle is theta_k / (M * order) */
   int32_t tile_qubits;       /* k: local qubits per tile of forward passes (4..14) */
   int32_t tile_qubits_rev;   /* k of reverse-sweep passes (4..13) */
   int32_t contiguous_qubits; /* lowest physical bits kept inside every tile (2..k-4) */
@@ -82,7 +83,10 @@ typedef struct {
                                 order, so tile_qubits = tile_qubits_rev <= 13; costs
                                 (n_fwd_passes - 1) extra state vectors per theta vector;
                                 2 recompute (the reverse sweep runs psi back to |HF>) */
-  int32_t reserved[1];
+  int32_t trotter_order;     /* 1 (or 0): first-order product, Eq. 5 -- each slice applies the
+                                excitation list in order; 2: symmetric second-order product,
+                                Eq. 6 -- each slice applies the list in order, then in reverse
+                                order.  Gradients sum over all factors of an amplitude. */
 } ucc_options;
 
 /* Fill *opt with defaults (all automatic, launch_mode 0, max_batch 1). */
@@ -161,6 +165,7 @@ typedef struct {
   int32_t block_threads_fwd, block_threads_exp, block_threads_rev, launch_mode;
   int32_t autotuned;         /* 1 if the choices above come from measurement */
   int32_t store_states;      /* 1 if gradient calls keep the forward states (ucc_options) */
+  int32_t trotter_steps, trotter_order;  /* M and the order of the Trotter product */
   int32_t perm[32];          /* physical bit of logical qubit q (q < n_qubits) */
   int64_t job_footprint;     /* device bytes one server job on this context holds */
 } ucc_plan_info;
@@ -211,9 +216,11 @@ ucc_status ucc_get_excitation_table(const ucc_ctx* ctx, uint32_t* supp, uint32_t
 /*
  * ucc_get_pass_table -- the pass plan.  kind[p] 0 = forward, 1 = expectation/apply-H,
  * 2 = reverse; local[p] = physical mask of the tile's local qubits; first/count index the
- * excitation order (kinds 0 and 2, count items in application order) or the group list
- * (kind 1) through items[].  Arrays sized n_fwd + n_exp + n_rev passes; items sized
- * 2 * n_exc + n_groups.  Any pointer may be NULL.
+ * factors of the Trotter product (kinds 0 and 2, count items in application order; factor o
+ * is amplitude o mod n_exc for order 1, and follows the list then its reverse per slice for
+ * order 2) or the group list (kind 1) through items[].  Arrays sized n_fwd + n_exp + n_rev
+ * passes; items sized 2 * L + n_groups, L = n_exc * trotter_steps * trotter_order factors.
+ * Any pointer may be NULL.
  */
 ucc_status ucc_get_pass_table(const ucc_ctx* ctx, int32_t* kind, uint32_t* local, int32_t* first,
                               int32_t* count, int32_t* items);

@@ -92,7 +92,7 @@ ucc_status ensure_buffers(const ucc_ctx* c, Buffers& b, int B, bool need_lam) {
       {reinterpret_cast<void**>(&b.E), cap * size_t(8)},
       {reinterpret_cast<void**>(&b.G), cap * size_t(p.K) * 8},
       {reinterpret_cast<void**>(&b.lam), lam ? cap * S * 16 : 0},
-      {reinterpret_cast<void**>(&b.gpart), lam ? cap * size_t(p.K) * ntr * 8 : 0},
+      {reinterpret_cast<void**>(&b.gpart), lam ? cap * p.seq.size() * ntr * 8 : 0},
       {reinterpret_cast<void**>(&b.ck), lam && p.ckpt ? size_t(p.nfwd - 1) * cap * S * 16 : 0},
   };
   for (auto& r : reqs) {
@@ -133,6 +133,9 @@ LaunchArgs make_args(const ucc_ctx* c, const Buffers& b, int B, hipStream_t st) 
   a.pairs = c->d_pairs;
   a.blobs = reinterpret_cast<const uint4*>(c->d_blob);
   a.cls = reinterpret_cast<const int2*>(c->d_cls);
+  a.L = (int)p.seq.size();
+  a.scale = p.scale;
+  a.occ = c->d_occ;
   a.psi = b.psi;
   a.lam = b.lam;
   a.cs = b.cs;
@@ -233,7 +236,8 @@ ucc_status enqueue_eval(const ucc_ctx* c, Buffers& b, const double* d_theta, int
       });
       if (e != hipSuccess) return hip_fail(e, "launch k_rev");
     }
-  const double rb = 8.0 * B * (double(p.nexp) * nte + (grad ? double(p.K) * (1 << (p.n - p.kr)) : 0.0));
+  const double rb =
+      8.0 * B * (double(p.nexp) * nte + (grad ? double(p.seq.size()) * (1 << (p.n - p.kr)) : 0.0));
   e = timed(UCC_KERNEL_REDUCE, rb,
             [&] { return launch_reduce(a, p.nexp * nte, grad, 1 << (p.n - p.kr)); });
   if (e != hipSuccess) return hip_fail(e, "launch k_reduce");
@@ -246,11 +250,13 @@ void free_tables(ucc_ctx* c) {
   free_ptr(c->d_pairs);
   free_ptr(c->d_blob);
   free_ptr(c->d_cls);
+  free_ptr(c->d_occ);
   c->d_passes = nullptr;
   c->d_exc = nullptr;
   c->d_pairs = nullptr;
   c->d_blob = nullptr;
   c->d_cls = nullptr;
+  c->d_occ = nullptr;
 }
 
 ucc_status upload_tables(ucc_ctx* c) {
@@ -260,7 +266,8 @@ ucc_status upload_tables(ucc_ctx* c) {
       (e = upload(&c->d_exc, t.exc)) != hipSuccess ||
       (e = upload(&c->d_pairs, t.pairs)) != hipSuccess ||
       (e = upload(&c->d_blob, t.blob)) != hipSuccess ||
-      (e = upload(&c->d_cls, t.cls)) != hipSuccess)
+      (e = upload(&c->d_cls, t.cls)) != hipSuccess ||
+      (e = upload(&c->d_occ, t.occ)) != hipSuccess)
     return hip_fail(e, "device table upload");
   return UCC_OK;
 }
@@ -279,7 +286,7 @@ bool whole_launch_fits(const Plan& p, const Tables& t) {
     }
   }
   const size_t static_bytes = kStageBytes + 8 * kGqWords + 64;  // stage, gradient partials
-  return whole_lds(p.K, ns, max_blk, max_blob, max_slots, max_occ, p.n) + static_bytes <=
+  return whole_lds(p.K, (int)p.seq.size(), ns, max_blk, max_blob, max_slots, max_occ, p.n) + static_bytes <=
          (size_t)kLdsBytes;
 }
 
@@ -307,7 +314,7 @@ ucc_status replan(ucc_ctx* c, int kf, int ke, int kr) {
   if (p.kf == kf && p.ke == ke && p.kr == kr) return UCC_OK;
   Plan np;
   const std::string msg = build_plan(np, p.n, p.ne, p.h1.data(), p.h2.data(), p.exc.data(), p.K,
-                                     kf, ke, kr, c->opt.contiguous_qubits, p.ckpt);
+                                     kf, ke, kr, c->opt.contiguous_qubits, p.ckpt, p.M, p.order);
   if (!msg.empty()) return fail(UCC_EINVAL, msg);
   np.tf = p.tf;
   np.te = p.te;
@@ -371,8 +378,10 @@ ucc_status ucc_build(int32_t n_qubits, int32_t n_elec, const double* h1, const d
   ucc_options o;
   ucc_default_options(&o);
   if (opt) o = *opt;
-  if (o.trotter_steps > 1 || o.trotter_steps < 0)
-    return fail(UCC_EINVAL, "only one Trotter slice (M = 1) is supported");
+  if (o.trotter_steps > 64 || o.trotter_steps < 0)
+    return fail(UCC_EINVAL, "trotter_steps (M) must be 0..64 (0 is read as 1)");
+  if (o.trotter_order < 0 || o.trotter_order > 2)
+    return fail(UCC_EINVAL, "trotter_order must be 0, 1 or 2");
   std::string msg = validate_inputs(n_qubits, n_elec, h1, h2, exc, n_exc);
   if (!msg.empty()) return fail(UCC_EINVAL, msg);
   // one complex128 tile of 2^k amplitudes (two for the reverse sweep) must fit in 160 KB of LDS
@@ -399,7 +408,8 @@ ucc_status ucc_build(int32_t n_qubits, int32_t n_elec, const double* h1, const d
   c->host_only = o.host_only != 0;
   const Tuning tu = choose_tuning(n_qubits, n_exc, std::max(1, o.max_batch), o);
   msg = build_plan(c->plan, n_qubits, n_elec, h1, h2, exc, n_exc, tu.kf, tu.ke, tu.kr,
-                   o.contiguous_qubits, tu.ckpt);
+                   o.contiguous_qubits, tu.ckpt, std::max(1, o.trotter_steps),
+                   std::max(1, o.trotter_order));
   if (!msg.empty()) {
     delete c;
     return fail(UCC_EINVAL, msg);
@@ -549,6 +559,8 @@ ucc_status ucc_get_plan_info(const ucc_ctx* c, ucc_plan_info* info) {
   info->autotuned = p.autotuned ? 1 : 0;
   info->launch_mode = p.launch_mode;
   info->store_states = p.ckpt ? 1 : 0;
+  info->trotter_steps = p.M;
+  info->trotter_order = p.order;
   for (int q = 0; q < p.n; ++q) info->perm[q] = p.perm[q];
   info->job_footprint = (int64_t)entry_footprint(c);
   return UCC_OK;

@@ -25,7 +25,7 @@ struct Buffers {
   double* theta = nullptr; // [cap][K]
   double2* cs = nullptr;   // [cap][K] (cos, sin)
   double* epart = nullptr; // [cap][n_exp_passes * tiles]
-  double* gpart = nullptr; // [cap][K][reverse tiles]
+  double* gpart = nullptr; // [cap][L][reverse tiles] (L factors of the Trotter product)
   double* E = nullptr;     // [cap]
   double* G = nullptr;     // [cap][K]
 };
@@ -62,6 +62,7 @@ struct ucc_ctx {
   uint32_t* d_pairs = nullptr;
   uint32_t* d_blob = nullptr;
   int32_t* d_cls = nullptr;
+  int32_t* d_occ = nullptr;  // factors of each amplitude (Tables::occ)
   ucc::Buffers buf;
   int last_B = 0;
   std::atomic<int> busy{0};  // held by a server job

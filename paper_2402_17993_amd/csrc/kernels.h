@@ -10,6 +10,9 @@ namespace ucc {
 struct LaunchArgs {
   hipStream_t stream = nullptr;
   int n = 0, K = 0, B = 0;
+  int L = 0;                  // factors of the Trotter product
+  double scale = 1.0;         // angle scale of every factor: 1 / (M * order)
+  const int32_t* occ = nullptr;  // [K + 1] offsets, then the factors of each amplitude
   int tf = 512, te = 1024, tr = 256;  // workgroup size of forward, expectation, reverse passes
   uint32_t hf = 0, amask = 0, bmask = 0;
   const DevPass* passes = nullptr;
@@ -26,7 +29,7 @@ struct LaunchArgs {
   double2* cs = nullptr;
   double* epart = nullptr;  // [B][estride]
   int estride = 0;
-  double* gpart = nullptr;  // [B][K][tiles of a reverse pass]
+  double* gpart = nullptr;  // [B][L][tiles of a reverse pass]
   double* E = nullptr;
   double* G = nullptr;
 };
@@ -47,8 +50,9 @@ hipError_t launch_reduce(const LaunchArgs& a, int ne, bool grad, int nt);
 hipError_t launch_whole(const LaunchArgs& a, const double* theta, bool grad, int nfwd, int nexp,
                         int nrev, bool fwd_state);
 // Dynamic LDS bytes of that launch (host and planner use the same formula).
-inline size_t whole_lds(int K, int ns, int max_blk, int max_blob, int max_slots, int max_occ, int n) {
-  return 16 * size_t(K) + 32 * size_t(ns) + 16 * size_t(max_blob) +
+inline size_t whole_lds(int K, int L, int ns, int max_blk, int max_blob, int max_slots, int max_occ,
+                        int n) {
+  return 16 * size_t(K) + 8 * size_t((L + 1) & ~1) + 32 * size_t(ns) + 16 * size_t(max_blob) +
          8 * (size_t((max_slots + 1) & ~1) + size_t((max_occ + 1) & ~1) + size_t((n + 2) & ~1) + 16) +
          4 * size_t(max_blk);
 }

@@ -179,11 +179,12 @@ struct Tile {
 
 }  // namespace
 
-__global__ void k_trig(const double* __restrict__ theta, double2* __restrict__ cs, int n) {
+__global__ void k_trig(const double* __restrict__ theta, double2* __restrict__ cs, int n,
+                       double scale) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) {
     double s, c;
-    sincos(theta[i], &s, &c);
+    sincos(scale * theta[i], &s, &c);
     cs[i] = make_double2(c, s);
   }
 }
@@ -742,7 +743,7 @@ __global__ __launch_bounds__(T) LDS_BOUND_OCCUPANCY void k_rev(
     const DevPass* __restrict__ passes, int pidx, const DevExc* __restrict__ exc,
     const int2* __restrict__ pcls, const uint32_t* __restrict__ pairs,
     const double2* __restrict__ cs, int K, double2* __restrict__ psi, double2* __restrict__ lam,
-    int n, uint32_t amask, uint32_t bmask, double* __restrict__ gpart, int total, int flip) {
+    int n, uint32_t amask, uint32_t bmask, double* __restrict__ gpart, int L, int total, int flip) {
   extern __shared__ double2 lds[];
   __shared__ PassStage st;
   __shared__ double gq[kGqWords];  // quad partials of <lambda|G_k|psi>
@@ -815,7 +816,7 @@ __global__ __launch_bounds__(T) LDS_BOUND_OCCUPANCY void k_rev(
     rev_excitations<T>(cp, cl, blk, st.cs, ps.count, gq);
     __syncthreads();  // the excitations are applied and gq is complete
     if (cst)
-      gpart[((size_t)b * K + st.x[threadIdx.x].k) * ntiles + t] =
+      gpart[((size_t)b * L + st.x[threadIdx.x].occ) * ntiles + t] =
           rev_partial(gq, threadIdx.x, st.x[threadIdx.x], base);
     if constexpr (RP) {
       tm.refresh();
@@ -847,7 +848,7 @@ __global__ __launch_bounds__(T) LDS_BOUND_OCCUPANCY void k_rev2(
     const DevPass* __restrict__ passes, int pidx, const DevExc* __restrict__ exc,
     const int2* __restrict__ pcls, const uint32_t* __restrict__ pairs,
     const double2* __restrict__ cs, int K, double2* __restrict__ psi, double2* __restrict__ lam,
-    int n, uint32_t amask, uint32_t bmask, double* __restrict__ gpart, int total, int flip) {
+    int n, uint32_t amask, uint32_t bmask, double* __restrict__ gpart, int L, int total, int flip) {
   extern __shared__ double2 lds[];
   constexpr int P = T / 2;  // producer threads: the upper half of the workgroup
   __shared__ DevExc sx[kMaxPassExc];
@@ -910,7 +911,7 @@ __global__ __launch_bounds__(T) LDS_BOUND_OCCUPANCY void k_rev2(
       const int b = ent(item);
       const uint32_t t = item & tmask;
       for (int e = threadIdx.x; e < ps.count; e += 64)
-        gpart[((size_t)b * K + sx[e].k) * ntiles + t] = rev_partial(gq, e, sx[e], base);
+        gpart[((size_t)b * L + sx[e].occ) * ntiles + t] = rev_partial(gq, e, sx[e], base);
     } else if (prod) {
       if (j > 0) write_item(item - (int)gridDim.x, slot ^ 1);
       if (next < total) read_item(next, slot ^ 1);
@@ -1143,16 +1144,19 @@ __global__ __launch_bounds__(T) void k_whole(
     const uint32_t* __restrict__ blocks, const uint4* __restrict__ blobs, int bstride,
     const double* __restrict__ theta, int K, double2* __restrict__ psi, int n, uint32_t hf,
     double* __restrict__ E, double* __restrict__ G, int ns, int max_blk, int max_blob,
-    int max_slots, int max_occ, int fwd_state) {
+    int max_slots, int max_occ, int fwd_state, int L, double scale,
+    const int32_t* __restrict__ occ) {
   extern __shared__ double2 lds[];
   __shared__ PassStage st;
   __shared__ double gq[kGqWords];
   __shared__ int hf_rank;
   const int b = blockIdx.x;
-  // LDS: (cos, sin) of every excitation | psi and lambda by rank | value table | per-tile
-  //      slot values t1, t2 | diagonal prep | wave sums | class block
+  // LDS: (cos, sin) of every amplitude | gradient partial of every factor | psi and lambda by
+  //      rank | value table | per-tile slot values t1, t2 | diagonal prep | wave sums |
+  //      class block
   double2* csa = lds;
-  double2* cp = csa + K;
+  double* gocc = reinterpret_cast<double*>(csa + K);
+  double2* cp = reinterpret_cast<double2*>(gocc + ((L + 1) & ~1));
   double2* cl = cp + ns;
   uint4* lb = reinterpret_cast<uint4*>(cl + ns);
   double* t1 = reinterpret_cast<double*>(lb + max_blob);
@@ -1163,7 +1167,7 @@ __global__ __launch_bounds__(T) void k_whole(
   const uint32_t* bw = reinterpret_cast<const uint32_t*>(lb);
   for (int k = threadIdx.x; k < K; k += T) {
     double sv, cv;
-    sincos(theta[(size_t)b * K + k], &sv, &cv);
+    sincos(scale * theta[(size_t)b * K + k], &sv, &cv);
     csa[k] = make_double2(cv, sv);
   }
   for (int i = threadIdx.x; i < ns; i += T) cp[i] = make_double2(0.0, 0.0);
@@ -1228,7 +1232,13 @@ __global__ __launch_bounds__(T) void k_whole(
       rev_excitations<T>(cp, cl, blk, st.cs, ps.count, gq);
       __syncthreads();  // the excitations are applied and gq is complete
       if ((int)threadIdx.x < ps.count)
-        G[(size_t)b * K + st.x[threadIdx.x].k] = 2.0 * rev_partial(gq, threadIdx.x, st.x[threadIdx.x], 0u);
+        gocc[st.x[threadIdx.x].occ] = rev_partial(gq, threadIdx.x, st.x[threadIdx.x], 0u);
+    }
+    __syncthreads();  // every factor's partial
+    for (int k = threadIdx.x; k < K; k += T) {
+      double g = 0.0;
+      for (int q = occ[k]; q < occ[k + 1]; ++q) g += gocc[occ[K + 1 + q]];
+      G[(size_t)b * K + k] = 2.0 * scale * g;
     }
   }
   if (threadIdx.x == 0) E[b] = etot;
@@ -1238,11 +1248,16 @@ __global__ __launch_bounds__(T) void k_whole(
   }
 }
 
-// Fixed-order reductions.  epart: [B][ne] energy partials; gpart: [B][K][nt] gradient partials.
+// Fixed-order reductions.  epart: [B][ne] energy partials; gpart: [B][L][nt] gradient partials
+// of the factors.
+// G[b][k] = 2 scale sum over the factors o of amplitude k (ascending) of the tile partials of
+// factor o (ascending tiles).
 template <int T>
 __global__ __launch_bounds__(T) void k_reduce(const double* __restrict__ epart, int ne,
-                                              const double* __restrict__ gpart, int K, int nt,
-                                              double* __restrict__ E, double* __restrict__ G) {
+                                              const double* __restrict__ gpart, int K, int L,
+                                              const int32_t* __restrict__ occ, double scale,
+                                              int nt, double* __restrict__ E,
+                                              double* __restrict__ G) {
   __shared__ double red[T / 64];
   const int b = blockIdx.x;
   double s = 0.0;
@@ -1251,10 +1266,14 @@ __global__ __launch_bounds__(T) void k_reduce(const double* __restrict__ epart, 
   if (threadIdx.x == 0) E[b] = s;
   if (gpart) {
     for (int k = threadIdx.x; k < K; k += T) {
-      const double* p = gpart + ((size_t)b * K + k) * nt;
       double g = 0.0;
-      for (int t = 0; t < nt; ++t) g += p[t];
-      G[(size_t)b * K + k] = 2.0 * g;
+      for (int q = occ[k]; q < occ[k + 1]; ++q) {
+        const double* p = gpart + ((size_t)b * L + occ[K + 1 + q]) * nt;
+        double go = 0.0;
+        for (int t = 0; t < nt; ++t) go += p[t];
+        g += go;
+      }
+      G[(size_t)b * K + k] = 2.0 * scale * g;
     }
   }
 }
@@ -1363,7 +1382,7 @@ hipError_t rev_overlapped(const LaunchArgs& a, int pidx, double2* psi, bool* use
     if (grid < ntiles || grid % ntiles != 0) return hipSuccess;
     hipLaunchKernelGGL((k_rev2<T, KT, WP>), dim3(grid), dim3(T), lds, a.stream, a.passes, pidx,
                        a.exc, a.cls, a.pairs, a.cs, a.K, psi, a.lam, a.n, a.amask, a.bmask,
-                       a.gpart, total, a.flip);
+                       a.gpart, a.L, total, a.flip);
     *used = true;
     return hipGetLastError();
   }
@@ -1384,7 +1403,7 @@ hipError_t rev_tw(const LaunchArgs& a, int pidx, double2* psi) {
       pass_grid(total, resident_grid(k_rev<T, KT, WP>, T, lds, a.cu_share), 1 << (a.n - k));
   hipLaunchKernelGGL((k_rev<T, KT, WP>), dim3(grid), dim3(T), lds, a.stream, a.passes, pidx,
                      a.exc, a.cls, a.pairs, a.cs, a.K, psi, a.lam, a.n, a.amask, a.bmask, a.gpart,
-                     total, a.flip);
+                     a.L, total, a.flip);
   return hipGetLastError();
 }
 
@@ -1479,7 +1498,8 @@ hipError_t exp_k(const LaunchArgs& a, int pidx, int eslot, int first) {
 
 hipError_t launch_trig(const LaunchArgs& a, const double* theta) {
   const int total = a.B * a.K;
-  hipLaunchKernelGGL(k_trig, dim3((total + 255) / 256), dim3(256), 0, a.stream, theta, a.cs, total);
+  hipLaunchKernelGGL(k_trig, dim3((total + 255) / 256), dim3(256), 0, a.stream, theta, a.cs, total,
+                     a.scale);
   return hipGetLastError();
 }
 
@@ -1527,14 +1547,14 @@ hipError_t launch_whole(const LaunchArgs& a, const double* theta, bool grad, int
       max_occ = std::max(max_occ, hp.n_occ);
     }
   }
-  const size_t lds = whole_lds(a.K, ns, max_blk, max_blob, max_slots, max_occ, a.n);
+  const size_t lds = whole_lds(a.K, a.L, ns, max_blk, max_blob, max_slots, max_occ, a.n);
   auto go = [&](auto kern) -> hipError_t {
     hipError_t e = set_lds(kern, lds);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(kern, dim3(a.B), dim3(256), lds, a.stream, a.passes, nfwd, nexp, nrev,
                        a.exc, a.cls, a.pairs, a.blobs, a.blob_stride, theta, a.K, a.psi, a.n,
                        a.hf, a.E, a.G, ns, max_blk, max_blob, max_slots, max_occ,
-                       fwd_state ? 1 : 0);
+                       fwd_state ? 1 : 0, a.L, a.scale, a.occ);
     return hipGetLastError();
   };
   return grad ? go(k_whole<256, true>) : go(k_whole<256, false>);
@@ -1542,7 +1562,7 @@ hipError_t launch_whole(const LaunchArgs& a, const double* theta, bool grad, int
 
 hipError_t launch_reduce(const LaunchArgs& a, int ne, bool grad, int nt) {
   hipLaunchKernelGGL(k_reduce<256>, dim3(a.B), dim3(256), 0, a.stream, a.epart, ne,
-                     grad ? a.gpart : nullptr, a.K, nt, a.E, a.G);
+                     grad ? a.gpart : nullptr, a.K, a.L, a.occ, a.scale, nt, a.E, a.G);
   return hipGetLastError();
 }
 

@@ -94,9 +94,10 @@ std::vector<Plan::Pass> plan_windows(const Plan& p, int kind, int k, int c0) {
     cur.lmask = pad_mask(cur.lmask, k, p.n);
     out.push_back(cur);
   };
-  for (int t = 0; t < p.K; ++t) {
-    const int e = (kind == kRev) ? p.K - 1 - t : t;
-    const uint32_t s = p.ex[e].supp;
+  const int L = (int)p.seq.size();
+  for (int t = 0; t < L; ++t) {
+    const int e = (kind == kRev) ? L - 1 - t : t;  // factor index
+    const uint32_t s = p.ex[p.seq[e]].supp;
     if (!cur.items.empty() && (pc32(cur.lmask | s) > k || (int)cur.items.size() >= kMaxPassExc)) {
       close();
       cur.items.clear();
@@ -232,7 +233,8 @@ std::string validate_inputs(int n, int ne, const double* h1, const double* h2, c
 }
 
 std::string build_plan(Plan& p, int n, int ne, const double* h1, const double* h2,
-                       const int32_t* exc, int K, int kf, int ke, int kr, int c0, bool ckpt) {
+                       const int32_t* exc, int K, int kf, int ke, int kr, int c0, bool ckpt,
+                       int M, int order) {
   p = Plan();
   p.n = n;
   p.ne = ne;
@@ -422,6 +424,18 @@ std::string build_plan(Plan& p, int n, int ne, const double* h1, const double* h
     p.ex.push_back(e);
   }
 
+  // ---- Trotter product: factors in the order they act (Eq. 5: the list, M times; Eq. 6: the
+  // list and then its reverse, M times), angles scaled by 1 / (M * order).
+  p.M = M;
+  p.order = order;
+  p.scale = 1.0 / (double(M) * order);
+  p.seq.clear();
+  for (int m = 0; m < M; ++m) {
+    for (int k = 0; k < K; ++k) p.seq.push_back(k);
+    if (order == 2)
+      for (int k = K - 1; k >= 0; --k) p.seq.push_back(k);
+  }
+
   // ---- pass plan.
   p.ckpt = ckpt;
   p.kf = std::min(kf, n);
@@ -552,7 +566,7 @@ std::vector<uint32_t> pair_block(const Plan& p, uint32_t lmask, const std::vecto
   for (size_t i = 0; i < ns; ++i) w.push_back(bucket[i].second);  // local physical offsets
   const size_t ent0 = w.size();
   for (size_t j = 0; j < m; ++j) {
-    const auto& e = p.ex[items[j]];
+    const auto& e = p.ex[p.seq[items[j]]];
     const uint32_t sc = compact_bits(e.supp, lmask), fc = compact_bits(e.from, lmask);
     const uint32_t mc = compact_bits(e.m & lmask, lmask);
     for (size_t i = 0; i < ns; ++i) {
@@ -715,6 +729,15 @@ int max_pair_block_words(const Plan& p, uint32_t lmask, const std::vector<int>& 
 
 void build_tables(const Plan& p, Tables& t) {
   t = Tables();
+  // factors of each amplitude, ascending (the gradient sums them in this order)
+  t.occ.assign(size_t(p.K) + 1, 0);
+  for (int k : p.seq) ++t.occ[size_t(k) + 1];
+  for (int k = 0; k < p.K; ++k) t.occ[size_t(k) + 1] += t.occ[k];
+  {
+    std::vector<int32_t> fill(t.occ.begin(), t.occ.end() - 1), idx(p.seq.size());
+    for (size_t o = 0; o < p.seq.size(); ++o) idx[fill[p.seq[o]]++] = (int32_t)o;
+    t.occ.insert(t.occ.end(), idx.begin(), idx.end());
+  }
   const int n = p.n;
   const uint32_t full = (n >= 32) ? 0xffffffffu : ((1u << n) - 1u);
   for (const auto& ps : p.passes) {
@@ -826,7 +849,8 @@ void build_tables(const Plan& p, Tables& t) {
     } else {
       dp.first = (int)t.exc.size();
       dp.count = (int)ps.items.size();
-      for (int k : ps.items) {
+      for (int o : ps.items) {
+        const int k = p.seq[o];
         const auto& e = p.ex[k];
         DevExc d{};
         d.supp_c = compact_bits(e.supp, ps.lmask);
@@ -836,6 +860,7 @@ void build_tables(const Plan& p, Tables& t) {
         d.nsup = e.nsup;
         d.k = k;
         d.sigma = e.sigma;
+        d.occ = o;
         t.exc.push_back(d);
       }
       int nbg = 0;

@@ -48,6 +48,7 @@ bool batch_compatible(const ucc_ctx* a, const ucc_ctx* b) {
       p.c0e != q.c0e || p.c0r != q.c0r || p.tf != q.tf || p.te != q.te || p.tr != q.tr ||
       p.launch_mode != q.launch_mode || p.nfwd != q.nfwd || p.nexp != q.nexp || p.nrev != q.nrev ||
       p.hf != q.hf || p.amask != q.amask || p.bmask != q.bmask || p.ckpt != q.ckpt ||
+      p.M != q.M || p.order != q.order ||
       a->device != b->device)
     return false;
   if (!same_bytes(p.exc, q.exc) || p.groups.size() != q.groups.size() || p.passes.size() != q.passes.size())
@@ -73,7 +74,7 @@ size_t entry_footprint(const ucc_ctx* c) {
   const size_t nte = size_t(1) << (p.n - p.ke), ntr = size_t(1) << (p.n - p.kr);
   const size_t stored = p.ckpt ? size_t(p.nfwd - 1) * S : 0;
   return 2 * S + stored + size_t(p.K) * (8 + 16 + 8) + 8 + 8 * size_t(p.nexp) * nte +
-         8 * size_t(p.K) * ntr + 4 * c->tab.blob.size();
+         8 * p.seq.size() * ntr + 4 * c->tab.blob.size();
 }
 
 namespace {

@@ -22,9 +22,9 @@ int pick(int fixed_kind, int fixed_all, int table) {
 }
 
 struct Key {
-  int n, ne, K, B, ck;
+  int n, ne, L, B, ck;  // L: factors of the Trotter product
   bool operator<(const Key& o) const {
-    return std::tie(n, ne, K, B, ck) < std::tie(o.n, o.ne, o.K, o.B, o.ck);
+    return std::tie(n, ne, L, B, ck) < std::tie(o.n, o.ne, o.L, o.B, o.ck);
   }
 };
 
@@ -85,7 +85,7 @@ std::vector<int> tile_candidates(int fixed, int n, std::initializer_list<int> ks
 ucc_status autotune(ucc_ctx* c, int B) {
   const ucc_options& o = c->opt;
   Plan& p = c->plan;
-  const Key key{p.n, p.ne, p.K, B, p.ckpt ? 1 : 0};
+  const Key key{p.n, p.ne, (int)p.seq.size(), B, p.ckpt ? 1 : 0};
   {
     std::lock_guard<std::mutex> lock(g_cache_mu);
     auto it = g_cache.find(key);

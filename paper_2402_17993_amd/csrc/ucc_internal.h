@@ -25,7 +25,8 @@ constexpr int kMaxQubits = 30;
 
 enum PassKind : int32_t { kFwd = 0, kExp = 1, kRev = 2 };
 
-// One excitation inside one forward or reverse pass, in compact tile coordinates.
+// One factor of the Trotter product inside one forward or reverse pass, in compact tile
+// coordinates.
 struct DevExc {
   uint32_t supp_c;  // compact support (2 or 4 bits)
   uint32_t from_c;  // compact pattern u & supp on which T_k acts (its occupied orbitals)
@@ -34,7 +35,7 @@ struct DevExc {
   int32_t nsup;     // 2 (single) or 4 (double)
   int32_t k;        // amplitude index
   int32_t sigma;    // constant sign of T_k on its from-pattern (+1 or -1)
-  int32_t pad;
+  int32_t occ;      // factor index in the Trotter product (gradient partial slot)
 };
 
 constexpr int kMaxPassExc = 256;  // excitations per forward/reverse pass (staged in LDS)
@@ -136,6 +137,11 @@ struct Plan {
     int sigma = 1, nsup = 0;
   };
   std::vector<Exc> ex;
+  // Trotter product (Eqs. 5, 6): the amplitude index of each factor in the order they act,
+  // and the angle scale 1 / (M * order).  Pass items index this sequence.
+  int M = 1, order = 1;
+  double scale = 1.0;
+  std::vector<int32_t> seq;
 
   struct Pass {
     int kind = 0;
@@ -161,6 +167,7 @@ struct Tables {
   std::vector<uint32_t> pairs;  // class blocks of every pass
   std::vector<uint32_t> blob;   // expectation-pass value tables (multiple of 4 words each)
   std::vector<int32_t> cls;     // pairs (class-block word offset, word count)
+  std::vector<int32_t> occ;     // [K + 1] offsets, then the factors of each amplitude ascending
 };
 
 // LDS limit of one workgroup on gfx950 and what an expectation pass may spend on its blob.
@@ -176,8 +183,10 @@ int max_pair_block_words(const Plan& p, uint32_t lmask, const std::vector<int>& 
 std::string validate_inputs(int n, int ne, const double* h1, const double* h2, const int32_t* exc,
                             int K);
 // ckpt: reverse passes mirror the forward passes (kr is then ignored; see Plan::ckpt).
+// M, order: the Trotter product (Eq. 5 with M slices, or Eq. 6 with order 2).
 std::string build_plan(Plan& p, int n, int ne, const double* h1, const double* h2,
-                       const int32_t* exc, int K, int kf, int ke, int kr, int c0, bool ckpt);
+                       const int32_t* exc, int K, int kf, int ke, int kr, int c0, bool ckpt,
+                       int M = 1, int order = 1);
 void build_tables(const Plan& p, Tables& t);
 uint32_t deposit_bits(uint32_t v, uint32_t mask);
 int count_plan_passes(const Plan& p, int kind);

@@ -39,7 +39,7 @@ class Options(ctypes.Structure):
                 ("launch_mode", _i32), ("host_only", _i32), ("device", _i32),
                 ("block_threads_fwd", _i32), ("block_threads_exp", _i32),
                 ("block_threads_rev", _i32), ("tile_qubits_exp", _i32), ("autotune", _i32),
-                ("store_states", _i32), ("reserved", _i32 * 1)]
+                ("store_states", _i32), ("trotter_order", _i32)]
 
 
 class PlanInfo(ctypes.Structure):
@@ -50,7 +50,8 @@ class PlanInfo(ctypes.Structure):
                 ("contiguous_fwd", _i32), ("contiguous_exp", _i32), ("contiguous_rev", _i32),
                 ("block_threads_fwd", _i32), ("block_threads_exp", _i32),
                 ("block_threads_rev", _i32), ("launch_mode", _i32), ("autotuned", _i32),
-                ("store_states", _i32), ("perm", _i32 * 32), ("job_footprint", ctypes.c_int64)]
+                ("store_states", _i32), ("trotter_steps", _i32), ("trotter_order", _i32),
+                ("perm", _i32 * 32), ("job_footprint", ctypes.c_int64)]
 
 
 class KernelStat(ctypes.Structure):
@@ -131,7 +132,8 @@ class Context:
                  tile_qubits_rev=0,
                  contiguous_qubits=0, block_threads=0, block_threads_fwd=0,
                  block_threads_exp=0, block_threads_rev=0, max_batch=1, launch_mode=0,
-                 autotune=False, store_states=0, host_only=False, device=-1):
+                 autotune=False, store_states=0, trotter_steps=1, trotter_order=1,
+                 host_only=False, device=-1):
         L = lib()
         self._h = None
         self.n_qubits, self.n_elec = int(n_qubits), int(n_elec)
@@ -148,6 +150,7 @@ class Context:
         o.block_threads_rev, o.autotune = block_threads_rev, int(bool(autotune))
         o.max_batch, o.launch_mode = max_batch, launch_mode
         o.store_states = store_states
+        o.trotter_steps, o.trotter_order = trotter_steps, trotter_order
         o.host_only, o.device = int(bool(host_only)), device
         h = _vp()
         check(L.ucc_build(self.n_qubits, self.n_elec, _ptr(h1), _ptr(h2), _ptr(exc),
@@ -256,7 +259,8 @@ class Context:
         P = info["n_fwd_passes"] + info["n_exp_passes"] + info["n_rev_passes"]
         kind, first, count = (np.empty(P, np.int32) for _ in range(3))
         local = np.empty(P, np.uint32)
-        items = np.empty(2 * self.n_exc + info["n_groups"], np.int32)
+        L = self.n_exc * info["trotter_steps"] * info["trotter_order"]
+        items = np.empty(2 * L + info["n_groups"], np.int32)
         check(lib().ucc_get_pass_table(self._h, _ptr(kind), _ptr(local), _ptr(first), _ptr(count),
                                        _ptr(items)))
         return [dict(kind=int(kind[i]), local=int(local[i]),

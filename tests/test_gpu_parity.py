@@ -360,3 +360,27 @@ def test_determinism_and_device_pointers(ucc):
     assert np.array_equal(tr.grad.cpu().numpy(), g_a)
     e_ref, g_ref = oracle_eg(n, ne, h, g, exc, th[2])
     assert abs(e_a[2] - e_ref) <= E_TOL and np.max(np.abs(g_a[2] - g_ref)) <= G_TOL
+
+
+@pytest.mark.parametrize("n,ne,M,order,kw", [
+    (8, 4, 3, 1, {}),                        # one launch (launch_mode 2)
+    (8, 4, 2, 2, dict(launch_mode=1)),       # per-pass launches, one tile
+    (12, 8, 2, 2, {}),                       # one tile, one launch
+    (12, 4, 2, 1, dict(tile_qubits=8)),      # several tiles, stored states
+    (16, 8, 2, 2, {}),                       # stored states, overlapped reverse passes
+    (16, 8, 3, 1, dict(store_states=2)),     # recomputing reverse sweep
+])
+def test_trotter_variants(ucc, n, ne, M, order, kw):
+    say(f"case: {n}q/{ne}e Trotter product M={M} order={order} {kw}, batch 2")
+    h1, h2, h, g, exc = system(n, ne, seed=31 + M + order)
+    th = make_thetas(len(exc), 41 + n, 0.2, batch=2)
+    ctx = ucc.Context(n, ne, h1, h2, exc, max_batch=2, trotter_steps=M, trotter_order=order, **kw)
+    info = ctx.plan_info()
+    assert (info["trotter_steps"], info["trotter_order"]) == (M, order)
+    e, gr = ctx.energy_grad(th)
+    for b in range(2):
+        e_ref, g_ref = ansatz.energy_and_gradient(h, g, n, (1 << ne) - 1, exc, th[b], slices=M,
+                                                  order=order)
+        assert abs(e[b] - e_ref) <= E_TOL, b
+        assert np.max(np.abs(gr[b] - g_ref)) <= G_TOL, b
+    assert np.max(np.abs(ctx.energy(th) - e)) <= 1e-12

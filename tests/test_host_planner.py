@@ -49,7 +49,8 @@ def test_library_exports_every_declared_symbol():
     dict(exc=[[0, 1, 4, 5], [0, 1, 4, 5]]),  # duplicate
     dict(h1_asym=True), dict(h2_asym=True), dict(tile_qubits=20), dict(block_threads=300),
     dict(block_threads_rev=128), dict(block_threads_exp=768), dict(autotune=True),
-    dict(store_states=3), dict(store_states=1, tile_qubits=14),
+    dict(store_states=3), dict(store_states=1, tile_qubits=14), dict(trotter_steps=65),
+    dict(trotter_steps=-1), dict(trotter_order=3),
     dict(store_states=1, tile_qubits=7, tile_qubits_rev=6),
 ])
 def test_invalid_inputs_are_rejected(bad):
@@ -64,7 +65,7 @@ def test_invalid_inputs_are_rejected(bad):
     exc = np.array(bad.get("exc", uccsd_excitations(8, 4)), dtype=np.int32)
     kw = {k: bad[k] for k in ("tile_qubits", "tile_qubits_rev", "block_threads",
                               "block_threads_rev", "block_threads_exp", "autotune",
-                              "store_states") if k in bad}
+                              "store_states", "trotter_steps", "trotter_order") if k in bad}
     with pytest.raises(ucc.UCCError) as ei:
         ucc.Context(n, ne, h1[: n // 2, : n // 2] if n <= 8 else np.zeros((n // 2,) * 2),
                     h2 if n == 8 else np.zeros((n // 2,) * 4), exc, host_only=True, **kw)
@@ -257,3 +258,26 @@ def test_launch_mode_resolution():
     assert ei.value.status == -1
     with pytest.raises(ucc.UCCError):  # a 12-qubit state split into tiles is not one tile
         host_ctx(12, 8, launch_mode=2, tile_qubits=8)
+
+
+@pytest.mark.parametrize("n,ne,M,order,kw", [(8, 4, 3, 1, {}), (12, 8, 2, 2, {}),
+                                             (16, 8, 2, 2, {}), (16, 8, 3, 1, dict(store_states=2))])
+def test_trotter_product_plan(n, ne, M, order, kw):
+    # the factors of Eq. 5 (M slices) or Eq. 6 (list, then reversed list, per slice) in order,
+    # every forward pass a window of consecutive factors, the reverse passes in the opposite order
+    ctx, _, _, exc = host_ctx(n, ne, trotter_steps=M, trotter_order=order, **kw)
+    info = ctx.plan_info()
+    assert (info["trotter_steps"], info["trotter_order"]) == (M, order)
+    K = len(exc)
+    L = K * M * order
+    passes = ctx.pass_table()
+    fwd = np.concatenate([p["items"] for p in passes if p["kind"] == 0])
+    rev = np.concatenate([p["items"] for p in passes if p["kind"] == 2])
+    assert np.array_equal(fwd, np.arange(L)) and np.array_equal(rev, np.arange(L)[::-1])
+    et = ctx.excitation_table()
+    one = list(range(K)) + (list(range(K - 1, -1, -1)) if order == 2 else [])
+    seq = np.array(one * M)
+    for p in passes:
+        if p["kind"] != 1:
+            for o in p["items"]:
+                assert int(et["supp"][seq[o]]) & ~p["local"] == 0
