@@ -157,6 +157,38 @@ def large_state(ucc, torch, n=26, ne=14):
             "plan_build_s": build_s}
 
 
+def trotter_variants(ucc, torch, h1, h2, exc, thetas, steps=5):
+    """The benchmark workload (18 qubits, batch 64) under the other Trotter products of the
+    paper: M slices of the first-order product (Eq. 5) and the symmetric second-order product
+    (Eq. 6).  Evals/s over `steps` timed evaluations, HIP-event kernel times and the algorithmic
+    HBM rate."""
+    td = torch.tensor(thetas, device="cuda:0", dtype=torch.float64)
+    out = {}
+    for M, order in ((2, 1), (1, 2), (3, 1)):
+        ctx = ucc.Context(N, NE, h1, h2, exc, max_batch=BATCH, device=0, trotter_steps=M,
+                          trotter_order=order)
+        ctx.energy_grad(td)
+        torch.cuda.synchronize()
+        ctx.profile(True)
+        ctx.profile_read(reset=True)
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        for _ in range(steps):
+            ctx.energy_grad(td)
+        b.record()
+        b.synchronize()
+        st = ctx.profile_read(reset=True)
+        info = ctx.plan_info()
+        ctx.close()
+        ms = a.elapsed_time(b) / steps
+        byt = sum(v["bytes"] for v in st.values()) / steps
+        out[f"M{M}_order{order}"] = {
+            "evals_per_s": BATCH / (ms * 1e-3), "ms_per_step": ms,
+            "GBps": byt / (ms * 1e-3) / 1e9, "frac": byt / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+            "passes_fwd_exp_rev": [info["n_fwd_passes"], info["n_exp_passes"], info["n_rev_passes"]]}
+    return out
+
+
 def cpu_small():
     """The oracle per E + grad evaluation at 8 and 16 qubits (one thread)."""
     from threadpoolctl import threadpool_limits
@@ -389,6 +421,7 @@ def main():
         out["latency_B1"] = {f"{n}q": single_latency(ucc, torch, n, ne)
                              for n, ne in ((8, 4), (12, 8), (16, 8))}
         out["large_26q"] = large_state(ucc, torch)
+        out["trotter_variants_18q_b64"] = trotter_variants(ucc, torch, h1, h2, exc, thetas)
     if args.serve_arrivals > 0:
         out["served_evals_per_s"] = served_same_workload(ucc, h1, h2, exc, thetas)
         out["serving_mix"] = serving_mix(ucc, args.serve_arrivals)
