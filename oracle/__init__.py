@@ -16,6 +16,8 @@ Modules
                the adjoint gradient, the steepest-descent VQE loop
   dense        small-n dense matrices: H, G_k, expm, FCI, Pauli decomposition
   closed_forms Hartree-Fock energy and the theta = 0 gradient (Slater-Condon)
+  trotter_free exp(sum_k theta_k G_k)|HF> without a product formula (Sec. 3.2),
+               by expm_multiply on the sparse generator, and its energy
 
 Parity status per function is stated in each module header.
 """

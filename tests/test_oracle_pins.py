@@ -12,7 +12,7 @@ import numpy as np
 import pytest
 import scipy.linalg
 
-from oracle import ansatz, closed_forms, dense, fermion, hamiltonian
+from oracle import ansatz, closed_forms, dense, fermion, hamiltonian, trotter_free
 from paper_2402_17993_amd.inputs import make_integrals, make_thetas, uccsd_excitations
 
 
@@ -438,3 +438,99 @@ def test_p15_variant_gradient_central_differences(slices, order):
             return ansatz.energy(h, g, n, hf_mask(ne), exc, t, slices=slices, order=order)
         fd = (E(1e-4) - E(-1e-4)) / 2e-4
         assert abs(fd - grad[k]) < 1e-7, k
+
+
+# ---------------------------------------------------------------- P16-P20: Trotter-free UCCSD (Sec. 3.2)
+
+def test_p16_trotter_free_equals_dense_expm():
+    # expm_multiply on the sparse ladder-operator generator against scipy.linalg.expm (a
+    # different algorithm) of the generator built from dense Kronecker ladder matrices
+    n, ne = 8, 4
+    exc = uccsd_excitations(n, ne)
+    for seed, scale in ((5, 0.3), (6, 1.0)):
+        th = make_thetas(len(exc), seed, scale)
+        A = sum(t * dense.generator_dense(n, row) for t, row in zip(th, exc))
+        ref = scipy.linalg.expm(A) @ ansatz.hf_state(n, hf_mask(ne))
+        np.testing.assert_allclose(trotter_free.trotter_free_state(n, hf_mask(ne), exc, th), ref,
+                                   atol=1e-12)
+
+
+def test_p17_single_excitation_is_a_plane_rotation():
+    # one excitation: exp(theta G)|HF> = cos(theta)|HF> + s sin(theta)|D> with T|HF> = s|D>
+    n, ne = 8, 4
+    hf = hf_mask(ne)
+    for row in ([1, -1, 5, -1], [0, 3, 4, 7], [2, 3, 4, 5]):
+        u, v, s = ansatz.excitation_pairs(n, row)
+        i = int(np.flatnonzero(u == hf)[0])
+        for th in (0.37, -1.2, 2.9):
+            ref = np.zeros(1 << n, dtype=np.complex128)
+            ref[hf] = np.cos(th)
+            ref[v[i]] = s[i] * np.sin(th)
+            got = trotter_free.trotter_free_state(n, hf, np.array([row]), [th])
+            np.testing.assert_allclose(got, ref, atol=1e-13)
+
+
+def test_p18_commuting_excitations_factorize():
+    # excitations on pairwise disjoint orbitals commute, so the exponential of their sum is
+    # the product of their factors in any order (the Trotter product is then exact)
+    n, ne = 8, 4
+    exc = np.array([(0, -1, 4, -1), (1, -1, 5, -1), (2, 3, 6, 7)], dtype=np.int32)
+    th = np.array([0.7, -0.4, 1.1])
+    free = trotter_free.trotter_free_state(n, hf_mask(ne), exc, th)
+    for perm in ([0, 1, 2], [2, 0, 1]):
+        prod = ansatz.trotter_state(n, hf_mask(ne), exc[perm], th[perm])
+        np.testing.assert_allclose(free, prod, atol=1e-13)
+    # a non-commuting pair does not factorize
+    exc2 = np.array([(0, -1, 4, -1), (0, 2, 4, 6)], dtype=np.int32)
+    th2 = np.array([0.7, 0.9])
+    assert np.max(np.abs(trotter_free.trotter_free_state(n, hf_mask(ne), exc2, th2)
+                         - ansatz.trotter_state(n, hf_mask(ne), exc2, th2))) > 1e-3
+
+
+def test_p19_trotter_products_converge_to_it():
+    # first-order products with M slices approach the Trotter-free state with error ~ 1/M
+    n, ne = 10, 4
+    exc = uccsd_excitations(n, ne)
+    pairs = ansatz.all_pairs(n, exc)
+    th = make_thetas(len(exc), 12, 0.3)
+    free = trotter_free.trotter_free_state(n, hf_mask(ne), exc, th, pairs)
+    err = {M: np.linalg.norm(ansatz.trotter_state(n, hf_mask(ne), exc, th, pairs, slices=M) - free)
+           for M in (8, 16, 32)}
+    assert abs(err[16] / err[8] - 0.5) < 0.05 and abs(err[32] / err[16] - 0.5) < 0.05, err
+    # the symmetric second-order products as 1/M^2
+    err2 = {M: np.linalg.norm(ansatz.trotter_state(n, hf_mask(ne), exc, th, pairs, slices=M, order=2)
+                              - free) for M in (8, 16)}
+    assert abs(err2[16] / err2[8] - 0.25) < 0.025, err2
+
+
+def test_p20_unitary_time_reversible_and_additive():
+    n, ne = 10, 6
+    exc = uccsd_excitations(n, ne)
+    pairs = ansatz.all_pairs(n, exc)
+    th = make_thetas(len(exc), 13, 0.5)
+    psi = trotter_free.trotter_free_state(n, hf_mask(ne), exc, th, pairs)
+    assert abs(np.linalg.norm(psi) - 1.0) < 1e-13
+    back = trotter_free.trotter_free_state(n, hf_mask(ne), exc, -th, pairs, psi0=psi)
+    np.testing.assert_allclose(back, ansatz.hf_state(n, hf_mask(ne)), atol=1e-13)
+    # non-interacting fragments (the layout of P8): energies add
+    r = np.random.default_rng(8)
+    ns = 4
+    h1 = np.zeros((ns, ns))
+    h2 = np.zeros((ns,) * 4)
+    sub = []
+    for blk in [(0, 1), (2, 3)]:
+        a1, a2 = make_integrals(2, int(r.integers(1000)))
+        ix = np.array(blk)
+        h1[np.ix_(ix, ix)] = a1
+        h2[np.ix_(ix, ix, ix, ix)] = a2
+        sub.append((a1, a2))
+    h, g = hamiltonian.spin_orbital_integrals(h1, h2)
+    exc_a = np.array([(0, -1, 2, -1), (1, -1, 3, -1), (0, 1, 2, 3)], dtype=np.int32)
+    exc_b = exc_a + 4 * (exc_a >= 0)
+    t = make_thetas(6, 9, 0.8)
+    e_ab = trotter_free.trotter_free_energy(h, g, 8, 0b00110011, np.concatenate([exc_a, exc_b]), t)
+    parts = 0.0
+    for (a1, a2), tt in zip(sub, (t[:3], t[3:])):
+        hs, gs = hamiltonian.spin_orbital_integrals(a1, a2)
+        parts += trotter_free.trotter_free_energy(hs, gs, 4, 0b0011, exc_a, tt)
+    assert abs(e_ab - parts) < 1e-12
