@@ -138,6 +138,25 @@ ucc_status ucc_energy_grad(ucc_ctx* ctx, const double* theta, int32_t B, double*
                            double* grad, void* stream);
 
 /*
+ * ucc_energy_trotter_free -- E_b = <Psi_b|H|Psi_b> for the Trotter-free ansatz
+ * |Psi_b> = exp(sum_k theta_{b,k} (T_k - T_k^dag)) |HF>: the exponential of the whole cluster
+ * generator (Eqs. 3-4) with no product formula, the reference of Sec. 3.2 (Table 6, Table S3).
+ * The trotter_steps / trotter_order options do not apply.
+ *
+ * exp(A)|HF> is summed as a Chebyshev series in A / rho, rho = max(sum_k |theta_{b,k}|, 2^-10)
+ * (a bound on the spectral radius of A), cut where the remainder bound falls below 1e-16;
+ * every term is one product with A on the device (42 terms at rho = 14, 114 at rho = 62).
+ *
+ *   theta, B, energy, stream  as ucc_energy
+ *   terms   nullable host [B] int32: the number of series terms used for each entry
+ * The call reads the series degrees back (one stream synchronization) before it launches the
+ * products.  After the call the context holds |Psi_b> (ucc_get_state).
+ * Errors: as ucc_energy; UCC_EINVAL if sum_k |theta_{b,k}| of some entry exceeds about 1400.
+ */
+ucc_status ucc_energy_trotter_free(ucc_ctx* ctx, const double* theta, int32_t B, double* energy,
+                                   int32_t* terms, void* stream);
+
+/*
  * ucc_get_state -- copy state vector b held by the context to the host, in the logical
  * qubit order of this header (qubit q = bit q), as interleaved (re, im) pairs.
  *   re_im  host, [2 * 2^n_qubits] float64
@@ -225,6 +244,19 @@ ucc_status ucc_get_excitation_table(const ucc_ctx* ctx, uint32_t* supp, uint32_t
 ucc_status ucc_get_pass_table(const ucc_ctx* ctx, int32_t* kind, uint32_t* local, int32_t* first,
                               int32_t* count, int32_t* items);
 
+/*
+ * ucc_get_generator_passes -- the pass plan of the Trotter-free evaluation (built on first
+ * use; also on host_only contexts): the generator sum_k theta_k G_k is compiled as one x-group
+ * per excitation (x = its support) and covered by expectation-style passes.
+ *   cap       capacity of local[]
+ *   local     nullable [cap]: physical local-qubit mask of each pass
+ *   exc_pass  nullable [n_exc]: the pass that holds excitation k
+ *   n_passes  receives the pass count
+ * Errors: UCC_EINVAL (NULL ctx or n_passes, cap too small for local).
+ */
+ucc_status ucc_get_generator_passes(ucc_ctx* ctx, int32_t cap, uint32_t* local, int32_t* exc_pass,
+                                    int32_t* n_passes);
+
 /* ---------------------------------------------------------------- profiling */
 
 /* Kernel kinds reported by ucc_profile_read. */
@@ -236,7 +268,9 @@ enum {
   UCC_KERNEL_REV = 4,    /* reverse-sweep pass (two vectors, gradient partials) */
   UCC_KERNEL_REDUCE = 5, /* fixed-order reduction of partials */
   UCC_KERNEL_WHOLE = 6,  /* whole evaluation of a one-tile state in one launch (launch_mode 2) */
-  UCC_KERNEL_KINDS = 8
+  UCC_KERNEL_GEN = 7,    /* Trotter-free: generator product pass (y += (2/rho) A x) */
+  UCC_KERNEL_CHEB = 8,   /* Trotter-free: series coefficients, value tables, start, sum update */
+  UCC_KERNEL_KINDS = 10
 };
 
 typedef struct {
@@ -246,12 +280,14 @@ typedef struct {
   double bytes;     /* algorithmic HBM bytes of those launches: every amplitude a pass must
                        read or write, 16 B each (per-kind model: fwd 2S per vector (S = 16 * 2^n;
                        the first pass writes only, S), exp S, apply-H S + 32 B per N/S_z-sector
-                       amplitude (16 B on the first pass), rev 4S, trig 24 B per amplitude) */
+                       amplitude (16 B on the first pass), rev 4S, trig 24 B per amplitude,
+                       gen as apply-H, series sum update 3S) */
 } ucc_kernel_stat;
 
 /*
  * ucc_profile -- enable (1) or disable (0) per-launch timing: every kernel launch of later
- * ucc_energy / ucc_energy_grad calls on this context is bracketed by HIP events recorded on
+ * ucc_energy / ucc_energy_grad / ucc_energy_trotter_free calls on this context is bracketed
+ * by HIP events recorded on
  * the call's stream.  Adds two event records per launch; off by default.
  */
 ucc_status ucc_profile(ucc_ctx* ctx, int32_t enable);

@@ -531,6 +531,7 @@ void ucc_destroy(ucc_ctx* c) {
     (void)hipDeviceSynchronize();
     free_buffers(c->buf);
     free_tables(c);
+    free_gen(c->gen);
   }
   delete c;
 }

@@ -49,6 +49,27 @@ struct Tuning {
   bool ckpt = false;  // stored forward states (then kr == kf)
 };
 
+// Trotter-free evaluation (trotter_free.cpp): the generator's plan and tables, built on first
+// use for the expectation tile size ke of the context's plan, and their buffers.
+struct GenSet {
+  int ke = -1;  // tile size the tables were planned with (-1: not built)
+  Plan plan;
+  Tables tab;
+  std::vector<int32_t> map;  // generator_value_map of tab
+  DevPass* d_passes = nullptr;
+  uint32_t* d_pairs = nullptr;
+  uint32_t* d_blob = nullptr;  // value-table template (unit values)
+  int32_t* d_cls = nullptr;
+  int32_t* d_map = nullptr;
+  int cap = 0;
+  double2* y = nullptr;     // [cap][2^n]: the third Chebyshev vector (psi and lam hold the others)
+  uint32_t* bank = nullptr; // [cap][tab.blob.size()]: value tables of each entry
+  double* coef = nullptr;   // [cap][kChebMaxTerms + 1]
+  double* cfac = nullptr;   // [cap]: 2 / rho
+  int32_t* deg = nullptr;   // [cap]: series degree
+};
+void free_gen(GenSet& g);
+
 }  // namespace ucc
 
 struct ucc_ctx {
@@ -64,6 +85,7 @@ struct ucc_ctx {
   int32_t* d_cls = nullptr;
   int32_t* d_occ = nullptr;  // factors of each amplitude (Tables::occ)
   ucc::Buffers buf;
+  ucc::GenSet gen;
   int last_B = 0;
   std::atomic<int> busy{0};  // held by a server job
   std::unique_ptr<ucc::Profiler> prof;

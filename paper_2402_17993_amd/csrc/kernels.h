@@ -44,6 +44,23 @@ hipError_t launch_exp(const LaunchArgs& a, int pidx, int eslot, int first, bool 
 // Reverse pass pidx on (psi, a.lam); write_psi = 0: psi is a stored state, read only.
 hipError_t launch_rev(const LaunchArgs& a, int pidx, double2* psi, bool write_psi);
 hipError_t launch_reduce(const LaunchArgs& a, int ne, bool grad, int nt);
+
+// Trotter-free evaluation (chebyshev.hip).  Chebyshev series of exp(A) with rho = max(sum_k
+// |theta_k|, kChebRhoMin) per entry, cut where the tail bound falls below kChebTol, at most
+// kChebMaxTerms terms; coef is [B][kChebMaxTerms + 1].
+constexpr double kChebRhoMin = 1.0 / 1024;
+constexpr double kChebTol = 1e-16;
+constexpr int kChebMaxTerms = 2048;
+hipError_t launch_cheb_coef(const double* theta, int K, int B, double tol, int max_terms, double* coef,
+                            double* cfac, int* deg, hipStream_t st);
+// bank [B][nd doubles]: the generator value tables of each entry (template words, unit values
+// scaled by theta_k * cfac[b]).
+hipError_t launch_gen_values(const uint32_t* tmpl, const int32_t* map, int nd, const double* theta,
+                             int K, const double* cfac, uint32_t* bank, int B, hipStream_t st);
+hipError_t launch_cheb_init(double2* y0, double2* y1, double2* F, const double* coef, int cstride,
+                            int n, uint32_t hf, int B, hipStream_t st);
+hipError_t launch_cheb_acc(double2* y, double2* F, const double* coef, int cstride, const int* deg,
+                           int j, double yscale, int n, int B, hipStream_t st);
 // Whole evaluation of a one-tile plan in one launch (one 256-thread workgroup per entry).
 // fwd_state: the state written to psi is Psi(theta) also for gradient calls (else the state
 // the reverse sweep ends on).

@@ -111,7 +111,8 @@ std::vector<Plan::Pass> plan_windows(const Plan& p, int kind, int k, int c0) {
 }
 
 // Greedy set cover of the x-group supports by k-bit local sets containing the low c0 bits.
-std::vector<Plan::Pass> plan_cover(const Plan& p, int k, int c0) {
+// diag: the first pass also takes the diagonal group (group 0).
+std::vector<Plan::Pass> plan_cover(const Plan& p, int k, int c0, bool diag = true) {
   const int n = p.n;
   const uint32_t F = (1u << c0) - 1u;
   std::vector<int> unc;
@@ -158,7 +159,7 @@ std::vector<Plan::Pass> plan_cover(const Plan& p, int k, int c0) {
     ps.lmask = pad_mask(F, k, n);
     out.push_back(ps);
   }
-  out[0].items.insert(out[0].items.begin(), 0);  // diagonal group
+  if (diag) out[0].items.insert(out[0].items.begin(), 0);  // diagonal group
   return out;
 }
 
@@ -713,6 +714,67 @@ std::string split_exp_passes(Plan& p, std::vector<Plan::Pass>& ex) {
   }
   ex.swap(out);
   return "";
+}
+
+std::string build_generator_plan(const Plan& p, Plan& g, int k, int c0) {
+  g = Plan();
+  g.n = p.n;
+  g.ne = p.ne;
+  g.ns = p.ns;
+  g.K = p.K;
+  g.nalpha = p.nalpha;
+  g.nbeta = p.nbeta;
+  g.nsec = p.nsec;
+  std::copy(p.perm, p.perm + 32, g.perm);
+  std::copy(p.iperm, p.iperm + 32, g.iperm);
+  g.amask = p.amask;
+  g.bmask = p.bmask;
+  g.hf = p.hf;
+  g.ex = p.ex;
+  g.groups.resize(1);  // group 0 (the diagonal) stays empty: G_k has no diagonal part
+  for (const auto& e : p.ex) {
+    // source v on T_k's from-pattern: <v ^ supp|G_k|v> = sigma (-1)^popcount(v & m); on the
+    // complementary pattern (T_k^dag acts): -sigma (-1)^popcount(v & m), m excluding supp
+    Plan::Group gr;
+    gr.x = e.supp;
+    gr.m = e.m;
+    const uint32_t pf = extract_bits(e.from, e.supp), pt = extract_bits(e.from ^ e.supp, e.supp);
+    gr.valid = (1u << pf) | (1u << pt);
+    gr.A[pf] = e.sigma;
+    gr.A[pt] = -e.sigma;
+    g.groups.push_back(gr);
+  }
+  g.ke = std::min(k, p.n);
+  std::vector<Plan::Pass> ex;
+  const int req = pick_c0(g.ke, c0);
+  const int lo = req >= 0 ? req : std::min(4, std::max(0, g.ke - 4));
+  const int hi = req >= 0 ? req : std::max(lo, std::min(8, g.ke - 4));
+  for (int c = lo; c <= hi; ++c) {
+    auto w = plan_cover(g, g.ke, c, false);
+    if (ex.empty() || w.size() <= ex.size()) {
+      ex = w;
+      g.c0e = c;
+    }
+  }
+  std::string err = split_exp_passes(g, ex);
+  if (!err.empty()) return err;
+  g.nexp = (int)ex.size();
+  g.passes = ex;
+  return "";
+}
+
+std::vector<int32_t> generator_value_map(const Plan& g, const Tables& t) {
+  std::vector<int32_t> map(t.blob.size() / 2, -1);
+  for (size_t i = 0; i < g.passes.size(); ++i) {
+    const ExpSlots e = exp_slots(g, g.passes[i].items);
+    const size_t base = size_t(t.passes[i].blob_off) * 4;
+    const size_t a0 = (base + t.blob[base + 6]) / 2;  // first A value (doubles)
+    for (size_t j = 0; j < e.groups.size(); ++j) {
+      const int nv = pc32(g.groups[e.groups[j]].valid);
+      for (int v = 0; v < nv; ++v) map[a0 + e.slot_base[j] + v] = e.groups[j] - 1;
+    }
+  }
+  return map;
 }
 
 int max_class_size(const Plan& p, uint32_t lmask) {

@@ -1,0 +1,285 @@
+// Trotter-free evaluation (Sec. 3.2, the reference the paper computes with a sparse
+// matrix-exponential action): E = <Psi|H|Psi> with |Psi> = exp(sum_k theta_k G_k)|HF>, no
+// product formula.
+//
+// exp(A)|HF> is summed as a Chebyshev series (chebyshev.hip).  Every term needs one product
+// A y, which runs on the expectation-pass kernels with the generator compiled as x-groups
+// (one per excitation, build_generator_plan) and per-entry value tables holding
+// theta_k * 2 / rho; the three-term recurrence adds the previous vector through the apply
+// kernel's accumulate mode (lambda += A psi), so a term costs the generator passes plus one
+// sweep that adds the term into the sum.  The energy then comes from the context's own
+// expectation passes on the sum.
+#include <hip/hip_runtime_api.h>
+
+#include <algorithm>
+#include <cstring>
+#include <vector>
+
+#include "api_internal.h"
+#include "kernels.h"
+#include "ucc.h"
+
+namespace ucc {
+
+namespace {
+
+template <typename T>
+hipError_t upload_vec(T** dst, const std::vector<T>& src) {
+  *dst = nullptr;
+  const size_t bytes = std::max<size_t>(src.size(), 1) * sizeof(T);
+  hipError_t e = hipMalloc(reinterpret_cast<void**>(dst), bytes);
+  if (e != hipSuccess) return e;
+  if (!src.empty()) e = hipMemcpy(*dst, src.data(), src.size() * sizeof(T), hipMemcpyHostToDevice);
+  return e;
+}
+
+template <typename T>
+void release(T*& p) {
+  if (p) (void)hipFree(p);
+  p = nullptr;
+}
+
+void free_gen_buffers(GenSet& g) {
+  release(g.y);
+  release(g.bank);
+  release(g.coef);
+  release(g.cfac);
+  release(g.deg);
+  g.cap = 0;
+}
+
+void free_gen_tables(GenSet& g) {
+  release(g.d_passes);
+  release(g.d_pairs);
+  release(g.d_blob);
+  release(g.d_cls);
+  release(g.d_map);
+}
+
+// Host plan and tables of the generator for the context's expectation tile size (and, with
+// upload, their device copies).  Rebuilt when the context was re-planned.
+ucc_status ensure_gen_plan(ucc_ctx* c, bool upload) {
+  GenSet& g = c->gen;
+  const Plan& p = c->plan;
+  if (g.ke != p.ke) {
+    if (!c->host_only) {
+      hipError_t e = hipDeviceSynchronize();
+      if (e != hipSuccess) return hip_fail(e, "hipDeviceSynchronize");
+    }
+    free_gen_buffers(g);
+    free_gen_tables(g);
+    const std::string msg = build_generator_plan(p, g.plan, p.ke, c->opt.contiguous_qubits);
+    if (!msg.empty()) return fail(UCC_EINVAL, msg);
+    g.tab = Tables();
+    build_tables(g.plan, g.tab);
+    g.map = generator_value_map(g.plan, g.tab);
+    g.ke = p.ke;
+  }
+  if (upload && !g.d_passes) {
+    hipError_t e;
+    if ((e = upload_vec(&g.d_passes, g.tab.passes)) != hipSuccess ||
+        (e = upload_vec(&g.d_pairs, g.tab.pairs)) != hipSuccess ||
+        (e = upload_vec(&g.d_blob, g.tab.blob)) != hipSuccess ||
+        (e = upload_vec(&g.d_cls, g.tab.cls)) != hipSuccess ||
+        (e = upload_vec(&g.d_map, g.map)) != hipSuccess) {
+      free_gen_tables(g);
+      return hip_fail(e, "generator table upload");
+    }
+  }
+  return UCC_OK;
+}
+
+ucc_status ensure_gen_buffers(ucc_ctx* c, int B) {
+  GenSet& g = c->gen;
+  if (B <= g.cap) return UCC_OK;
+  hipError_t e = hipDeviceSynchronize();
+  if (e != hipSuccess) return hip_fail(e, "hipDeviceSynchronize");
+  free_gen_buffers(g);
+  const size_t S = size_t(1) << c->plan.n;
+  struct Req {
+    void** ptr;
+    size_t bytes;
+  } reqs[] = {
+      {reinterpret_cast<void**>(&g.y), size_t(B) * S * 16},
+      {reinterpret_cast<void**>(&g.bank), size_t(B) * g.tab.blob.size() * 4},
+      {reinterpret_cast<void**>(&g.coef), size_t(B) * (kChebMaxTerms + 1) * 8},
+      {reinterpret_cast<void**>(&g.cfac), size_t(B) * 8},
+      {reinterpret_cast<void**>(&g.deg), size_t(B) * 4},
+  };
+  for (auto& r : reqs) {
+    e = hipMalloc(r.ptr, std::max<size_t>(r.bytes, 16));
+    if (e != hipSuccess) {
+      free_gen_buffers(g);
+      return hip_fail(e, "hipMalloc(Trotter-free buffers)");
+    }
+  }
+  g.cap = B;
+  return UCC_OK;
+}
+
+// The launch sequence of one Trotter-free call on stream st.  The series degree of each entry
+// is read back once (the number of generator products to launch); terms (host, nullable)
+// receives it.
+ucc_status enqueue_trotter_free(ucc_ctx* c, const double* d_theta, int B, hipStream_t st,
+                                int32_t* terms) {
+  const Plan& p = c->plan;
+  GenSet& g = c->gen;
+  Buffers& b = c->buf;
+  Profiler* prof = c->prof.get();
+  auto timed = [&](int kind, double bytes, auto&& fn) -> hipError_t {
+    if (!prof) return fn();
+    Profiler::Rec r{kind, prof->get(), prof->get(), bytes};
+    if (!r.a || !r.b) return hipErrorOutOfMemory;
+    hipError_t e = hipEventRecord(r.a, st);
+    if (e == hipSuccess) e = fn();
+    if (e == hipSuccess) e = hipEventRecord(r.b, st);
+    prof->recs.push_back(r);
+    return e;
+  };
+  const int cstride = kChebMaxTerms + 1;
+  const double S = 16.0 * double(size_t(1) << p.n) * B;
+  const double sec = 16.0 * double(p.nsec) * B;
+  hipError_t e = timed(UCC_KERNEL_CHEB, 8.0 * B * p.K, [&] {
+    return launch_cheb_coef(d_theta, p.K, B, kChebTol, kChebMaxTerms, g.coef, g.cfac, g.deg, st);
+  });
+  if (e != hipSuccess) return hip_fail(e, "launch k_cheb_coef");
+  std::vector<int32_t> deg(B);
+  e = hipMemcpyAsync(deg.data(), g.deg, sizeof(int32_t) * B, hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  if (e != hipSuccess) return hip_fail(e, "read series degrees");
+  int m = 0;
+  for (int i = 0; i < B; ++i) {
+    if (deg[i] < 0)
+      return fail(UCC_EINVAL, "sum of |theta| of entry " + std::to_string(i) +
+                                  " is too large for the Chebyshev series (limit about 1400)");
+    m = std::max(m, deg[i]);
+  }
+  if (terms) std::copy(deg.begin(), deg.end(), terms);
+  const int nd = (int)(g.tab.blob.size() / 2);
+  e = timed(UCC_KERNEL_CHEB, 16.0 * B * nd, [&] {
+    return launch_gen_values(g.d_blob, g.d_map, nd, d_theta, p.K, g.cfac, g.bank, B, st);
+  });
+  if (e != hipSuccess) return hip_fail(e, "launch k_gen_values");
+  double2* y0 = b.lam;
+  double2* y1 = g.y;
+  double2* F = b.psi;
+  e = timed(UCC_KERNEL_CHEB, 3 * S,
+            [&] { return launch_cheb_init(y0, y1, F, g.coef, cstride, p.n, p.hf, B, st); });
+  if (e != hipSuccess) return hip_fail(e, "launch k_cheb_init");
+
+  LaunchArgs a = make_args(c, b, B, st);
+  a.passes = g.d_passes;
+  a.hpasses = g.tab.passes.data();
+  a.pairs = g.d_pairs;
+  a.cls = reinterpret_cast<const int2*>(g.d_cls);
+  a.blobs = reinterpret_cast<const uint4*>(g.bank);
+  a.blob_stride = (int)(g.tab.blob.size() / 4);
+  int seq = 0;
+  // dst (+)= (2 / rho) A src over the generator's passes (first: the first pass writes dst)
+  auto apply = [&](double2* src, double2* dst, bool first) -> hipError_t {
+    a.psi = src;
+    a.lam = dst;
+    for (int i = 0; i < g.plan.nexp; ++i, ++seq) {
+      a.flip = seq & 1;
+      const bool fw = first && i == 0;
+      hipError_t r = timed(UCC_KERNEL_GEN, S + (fw ? sec : 2 * sec),
+                           [&] { return launch_exp(a, i, 0, fw ? 1 : 0, true); });
+      if (r != hipSuccess) return r;
+    }
+    return hipSuccess;
+  };
+  auto acc = [&](double2* y, int j, double yscale) {
+    return timed(UCC_KERNEL_CHEB, yscale != 1.0 ? 4 * S : 3 * S, [&] {
+      return launch_cheb_acc(y, F, g.coef, cstride, g.deg, j, yscale, p.n, B, st);
+    });
+  };
+  if (m >= 1) {
+    e = apply(y0, y1, true);  // y1 = (2 / rho) A y0 = 2 y_1
+    if (e == hipSuccess) e = acc(y1, 1, 0.5);
+    for (int j = 2; j <= m && e == hipSuccess; ++j) {
+      e = apply(y1, y0, false);  // y0 = y_{j-2} + (2 / rho) A y_{j-1} = y_j
+      if (e == hipSuccess) e = acc(y0, j, 1.0);
+      std::swap(y0, y1);
+    }
+    if (e != hipSuccess) return hip_fail(e, "launch Chebyshev term");
+  }
+
+  // E = <F|H|F> on the context's own expectation passes
+  LaunchArgs h = make_args(c, b, B, st);
+  const int nte = 1 << (p.n - p.ke);
+  for (int j = 0; j < p.nexp; ++j, ++seq) {
+    h.flip = seq & 1;
+    e = timed(UCC_KERNEL_EXP, S, [&] { return launch_exp(h, p.nfwd + j, j * nte, j == 0, false); });
+    if (e != hipSuccess) return hip_fail(e, "launch k_exp");
+  }
+  e = timed(UCC_KERNEL_REDUCE, 8.0 * B * p.nexp * nte,
+            [&] { return launch_reduce(h, p.nexp * nte, false, 1 << (p.n - p.kr)); });
+  if (e != hipSuccess) return hip_fail(e, "launch k_reduce");
+  return UCC_OK;
+}
+
+}  // namespace
+
+void free_gen(GenSet& g) {
+  free_gen_buffers(g);
+  free_gen_tables(g);
+  g.ke = -1;
+}
+
+}  // namespace ucc
+
+using namespace ucc;
+
+extern "C" {
+
+ucc_status ucc_energy_trotter_free(ucc_ctx* c, const double* theta, int32_t B, double* energy,
+                                   int32_t* terms, void* stream) {
+  g_last_error.clear();
+  if (!c) return fail(UCC_EINVAL, "ctx is NULL");
+  if (c->host_only) return fail(UCC_EINVAL, "context was built host_only");
+  if (B < 1 || B > 65535) return fail(UCC_EINVAL, "B must be in [1, 65535]");
+  if (!theta || !energy) return fail(UCC_EINVAL, "NULL output or input");
+  if (c->busy) return fail(UCC_EBUSY, "context is in use by a server job");
+  hipError_t e = hipSetDevice(c->device);
+  if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
+  ucc_status s = ensure_buffers(c, c->buf, B, true);
+  if (s == UCC_OK) s = ensure_gen_plan(c, true);
+  if (s == UCC_OK) s = ensure_gen_buffers(c, B);
+  if (s != UCC_OK) return s;
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  const double* d_theta = theta;
+  if (!is_device_ptr(theta)) {
+    e = hipMemcpyAsync(c->buf.theta, theta, size_t(B) * c->plan.K * sizeof(double),
+                       hipMemcpyHostToDevice, st);
+    if (e != hipSuccess) return hip_fail(e, "copy theta");
+    d_theta = c->buf.theta;
+  }
+  s = enqueue_trotter_free(c, d_theta, B, st, terms);
+  if (s != UCC_OK) return s;
+  const bool host_e = !is_device_ptr(energy);
+  e = hipMemcpyAsync(energy, c->buf.E, B * sizeof(double),
+                     host_e ? hipMemcpyDeviceToHost : hipMemcpyDeviceToDevice, st);
+  if (e == hipSuccess && host_e) e = hipStreamSynchronize(st);
+  if (e != hipSuccess) return hip_fail(e, "copy energy");
+  c->last_B = B;
+  return UCC_OK;
+}
+
+ucc_status ucc_get_generator_passes(ucc_ctx* c, int32_t cap, uint32_t* local, int32_t* exc_pass,
+                                    int32_t* n_passes) {
+  g_last_error.clear();
+  if (!c || !n_passes) return fail(UCC_EINVAL, "NULL argument");
+  ucc_status s = ensure_gen_plan(c, false);
+  if (s != UCC_OK) return s;
+  const Plan& g = c->gen.plan;
+  *n_passes = g.nexp;
+  if (local && cap < g.nexp) return fail(UCC_EINVAL, "cap is smaller than the pass count");
+  for (int i = 0; i < g.nexp; ++i) {
+    if (local) local[i] = g.passes[i].lmask;
+    if (exc_pass)
+      for (int it : g.passes[i].items) exc_pass[it - 1] = i;
+  }
+  return UCC_OK;
+}
+
+}  // extern "C"

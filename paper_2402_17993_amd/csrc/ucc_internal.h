@@ -188,6 +188,14 @@ std::string build_plan(Plan& p, int n, int ne, const double* h1, const double* h
                        const int32_t* exc, int K, int kf, int ke, int kr, int c0, bool ckpt,
                        int M = 1, int order = 1);
 void build_tables(const Plan& p, Tables& t);
+// Trotter-free evaluation (Sec. 3.2): the generator A = sum_k theta_k G_k written as x-groups,
+// one per excitation (x = its support, values +-sigma_k on the two patterns G_k connects, no
+// occupation rows, no diagonal group), covered by expectation passes of k local bits.  g gets
+// the groups and passes of p's excitations; build_tables(g, ...) compiles it.
+std::string build_generator_plan(const Plan& p, Plan& g, int k, int c0);
+// Per double of the compiled generator's value tables: the excitation whose unit value
+// (+-sigma_k) the double holds, or -1 for words that do not depend on theta.
+std::vector<int32_t> generator_value_map(const Plan& g, const Tables& t);
 uint32_t deposit_bits(uint32_t v, uint32_t mask);
 int count_plan_passes(const Plan& p, int kind);
 

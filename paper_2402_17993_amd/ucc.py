@@ -22,7 +22,8 @@ STATUS = {0: "UCC_OK", -1: "UCC_EINVAL", -2: "UCC_ENOMEM", -3: "UCC_EDEVICE", -4
 STATUS_CODES = {v: k for k, v in STATUS.items()}
 
 EXPORTED = [
-    "ucc_default_options", "ucc_build", "ucc_energy", "ucc_energy_grad", "ucc_get_state",
+    "ucc_default_options", "ucc_build", "ucc_energy", "ucc_energy_grad",
+    "ucc_energy_trotter_free", "ucc_get_generator_passes", "ucc_get_state",
     "ucc_destroy", "ucc_last_error", "ucc_get_plan_info", "ucc_batch_compatible",
     "ucc_get_pauli_terms",
     "ucc_get_group_table", "ucc_get_excitation_table", "ucc_get_pass_table",
@@ -30,7 +31,8 @@ EXPORTED = [
     "ucc_server_create", "ucc_submit", "ucc_poll", "ucc_wait", "ucc_cancel", "ucc_server_destroy",
 ]
 
-KERNEL_KINDS = ["trig", "fwd", "exp", "applyh", "rev", "reduce", "whole"]
+KERNEL_KINDS = ["trig", "fwd", "exp", "applyh", "rev", "reduce", "whole", "gen", "cheb"]
+N_KERNEL_KINDS = 10
 
 
 class Options(ctypes.Structure):
@@ -81,6 +83,8 @@ def lib():
         "ucc_build": (_i32, [_i32, _i32, _vp, _vp, _vp, _i32, _P(Options), _P(_vp)]),
         "ucc_energy": (_i32, [_vp, _vp, _i32, _vp, _vp]),
         "ucc_energy_grad": (_i32, [_vp, _vp, _i32, _vp, _vp, _vp]),
+        "ucc_energy_trotter_free": (_i32, [_vp, _vp, _i32, _vp, _vp, _vp]),
+        "ucc_get_generator_passes": (_i32, [_vp, _i32, _vp, _vp, _P(_i32)]),
         "ucc_get_state": (_i32, [_vp, _i32, _vp]),
         "ucc_destroy": (None, [_vp]),
         "ucc_last_error": (ctypes.c_char_p, []),
@@ -197,6 +201,46 @@ class Context:
         """(E [B], dE/dtheta [B, K])."""
         return self._run(theta, True, stream)
 
+    def energy_trotter_free(self, theta, stream=None, return_terms=False):
+        """E [B] of the Trotter-free ansatz exp(sum_k theta_k G_k)|HF> (no product formula);
+        with return_terms also the series terms used per entry (int32 [B])."""
+        L = lib()
+        if _is_torch_cuda(theta):
+            import torch
+            th = theta.detach().to(torch.float64).contiguous()
+            B = th.numel() // self.n_exc
+            if th.numel() != B * self.n_exc or B < 1:
+                raise ValueError("theta must hold B * n_exc amplitudes")
+            E = torch.empty(B, dtype=torch.float64, device=th.device)
+            terms = np.zeros(B, dtype=np.int32)
+            st = stream if stream is not None else torch.cuda.current_stream(th.device).cuda_stream
+            check(L.ucc_energy_trotter_free(self._h, _vp(th.data_ptr()), B, _vp(E.data_ptr()),
+                                            _ptr(terms), _vp(st)), "ucc_energy_trotter_free")
+        else:
+            th = np.ascontiguousarray(theta, dtype=np.float64)
+            B = th.size // self.n_exc
+            if th.size != B * self.n_exc or B < 1:
+                raise ValueError("theta must hold B * n_exc amplitudes")
+            E = np.empty(B)
+            terms = np.zeros(B, dtype=np.int32)
+            st = _vp(stream) if stream is not None else None
+            check(L.ucc_energy_trotter_free(self._h, _ptr(th), B, _ptr(E), _ptr(terms), st),
+                  "ucc_energy_trotter_free")
+        return (E, terms) if return_terms else E
+
+    def generator_passes(self):
+        """(local masks [n_passes] uint32, pass of each excitation [n_exc] int32) of the
+        Trotter-free evaluation's generator plan."""
+        L = lib()
+        n = ctypes.c_int32()
+        check(L.ucc_get_generator_passes(self._h, 0, None, None, ctypes.byref(n)),
+              "ucc_get_generator_passes")
+        local = np.zeros(max(n.value, 1), dtype=np.uint32)
+        where = np.full(self.n_exc, -1, dtype=np.int32)
+        check(L.ucc_get_generator_passes(self._h, n.value, _ptr(local), _ptr(where), ctypes.byref(n)),
+              "ucc_get_generator_passes")
+        return local[: n.value], where
+
     def state(self, b=0):
         out = np.empty(2 << self.n_qubits)
         check(lib().ucc_get_state(self._h, int(b), _ptr(out)), "ucc_get_state")
@@ -209,7 +253,7 @@ class Context:
 
     def profile_read(self, reset=True):
         """{kind: dict(launches, ms, bytes)} accumulated since the last reset."""
-        st = (KernelStat * 8)()
+        st = (KernelStat * N_KERNEL_KINDS)()
         check(lib().ucc_profile_read(self._h, st, int(bool(reset))), "ucc_profile_read")
         return {name: dict(launches=st[i].launches, ms=st[i].ms, bytes=st[i].bytes)
                 for i, name in enumerate(KERNEL_KINDS)}

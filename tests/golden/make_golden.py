@@ -15,7 +15,7 @@ import numpy as np
 ROOT = os.path.dirname(os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
 sys.path.insert(0, ROOT)
 
-from oracle import ansatz, closed_forms, hamiltonian  # noqa: E402
+from oracle import ansatz, closed_forms, hamiltonian, trotter_free  # noqa: E402
 from paper_2402_17993_amd.inputs import make_integrals, make_thetas, uccsd_excitations  # noqa: E402
 
 HERE = os.path.dirname(os.path.abspath(__file__))
@@ -40,6 +40,23 @@ def case_dimer_18q():
     return out
 
 
+def case_dimer_18q_trotter_free():
+    """The batch of case dimer_18q under the Trotter-free ansatz (Sec. 3.2): oracle energy of
+    entries 0, 1, 9, 18, 27, 36, 45, 54 and 63."""
+    n, ne = 18, 10
+    h1, h2 = make_integrals(n // 2, 0)
+    h, g = hamiltonian.spin_orbital_integrals(h1, h2)
+    exc = uccsd_excitations(n, ne)
+    thetas = make_thetas(len(exc), 1, 0.05, batch=64)
+    pairs = ansatz.all_pairs(n, exc)
+    out = {"n": n, "ne": ne, "integral_seed": 0, "theta_seed": 1, "theta_scale": 0.05,
+           "batch": 64, "energies": {}}
+    for b in (0, 1, 9, 18, 27, 36, 45, 54, 63):
+        out["energies"][str(b)] = trotter_free.trotter_free_energy(h, g, n, (1 << ne) - 1, exc,
+                                                                   thetas[b], pairs)
+    return out
+
+
 def case_large_26q_theta0():
     """26 qubits, 14 electrons, integrals seed 0, theta = 0: closed-form Hartree-Fock energy
     and Slater-Condon gradient (the oracle's closed forms; no state vector needed)."""
@@ -52,7 +69,8 @@ def case_large_26q_theta0():
             "grad": closed_forms.gradient_at_zero(h, g, range(ne), exc).tolist()}
 
 
-CASES = {"dimer_18q": case_dimer_18q, "large_26q_theta0": case_large_26q_theta0}
+CASES = {"dimer_18q": case_dimer_18q, "dimer_18q_trotter_free": case_dimer_18q_trotter_free,
+         "large_26q_theta0": case_large_26q_theta0}
 
 if __name__ == "__main__":
     names = sys.argv[1:] or list(CASES)

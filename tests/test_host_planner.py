@@ -281,3 +281,25 @@ def test_trotter_product_plan(n, ne, M, order, kw):
         if p["kind"] != 1:
             for o in p["items"]:
                 assert int(et["supp"][seq[o]]) & ~p["local"] == 0
+
+
+# ---------------------------------------------------------------- Trotter-free generator plan
+
+@pytest.mark.parametrize("n,ne,kw", [(8, 4, {}), (12, 8, dict(tile_qubits_exp=8)),
+                                     (16, 8, {}), (18, 10, dict(tile_qubits_exp=12))])
+def test_generator_plan_covers_every_excitation_once(n, ne, kw):
+    ctx, _, _, exc = host_ctx(n, ne, **kw)
+    local, where = ctx.generator_passes()
+    info = ctx.plan_info()
+    t = ctx.excitation_table()
+    k = min(n, kw.get("tile_qubits_exp", 14))
+    assert len(local) >= 1 and np.all(where >= 0) and np.all(where < len(local))
+    for m in local:
+        assert bin(int(m)).count("1") == k
+    # each excitation's support lies inside its pass's local qubits
+    for e, p in enumerate(where):
+        assert int(t["supp"][e]) & ~int(local[p]) == 0
+    # the generator needs no more passes than the Hamiltonian's expectation sweep (its
+    # supports are x-masks of H's groups) plus the LDS splits
+    assert len(local) <= info["n_exp_passes"] + 2
+    ctx.close()
