@@ -189,6 +189,41 @@ def trotter_variants(ucc, torch, h1, h2, exc, thetas, steps=5):
     return out
 
 
+def trotter_free(ucc, torch, h1, h2, exc, thetas, steps=5):
+    """The benchmark batch (18 qubits, 64 amplitude vectors) under the Trotter-free ansatz of
+    Sec. 3.2: energies per second, series terms per entry, HIP-event kernel times and the
+    algorithmic HBM rate of the generator passes; energies of 9 entries against the stored
+    oracle values."""
+    td = torch.tensor(thetas, device="cuda:0", dtype=torch.float64)
+    ctx = ucc.Context(N, NE, h1, h2, exc, max_batch=BATCH, device=0)
+    E, terms = ctx.energy_trotter_free(td, return_terms=True)
+    torch.cuda.synchronize()
+    gold = json.load(open(os.path.join(ROOT, "tests", "golden", "dimer_18q_trotter_free.json")))
+    E = E.cpu().numpy()
+    de = max(abs(E[int(b)] - v) for b, v in gold["energies"].items())
+    ctx.profile(True)
+    ctx.profile_read(reset=True)
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    for _ in range(steps):
+        ctx.energy_trotter_free(td)
+    b.record()
+    b.synchronize()
+    st = ctx.profile_read(reset=True)
+    local, _ = ctx.generator_passes()
+    ctx.close()
+    ms = a.elapsed_time(b) / steps
+    byt = sum(v["bytes"] for v in st.values()) / steps
+    return {"energies_per_s": BATCH / (ms * 1e-3), "ms_per_batch": ms,
+            "terms_min_mean_max": [int(terms.min()), float(terms.mean()), int(terms.max())],
+            "generator_passes": int(len(local)),
+            "GBps": byt / (ms * 1e-3) / 1e9, "frac": byt / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+            "kernels": {k: {"launches": v["launches"] // steps, "ms": v["ms"] / steps,
+                            "GBps": v["bytes"] / (v["ms"] * 1e-3) / 1e9}
+                        for k, v in st.items() if v["launches"]},
+            "max_abs_dE_vs_oracle": float(de), "energies_checked": len(gold["energies"])}
+
+
 def cpu_small():
     """The oracle per E + grad evaluation at 8 and 16 qubits (one thread)."""
     from threadpoolctl import threadpool_limits
@@ -422,6 +457,7 @@ def main():
                              for n, ne in ((8, 4), (12, 8), (16, 8))}
         out["large_26q"] = large_state(ucc, torch)
         out["trotter_variants_18q_b64"] = trotter_variants(ucc, torch, h1, h2, exc, thetas)
+        out["trotter_free_18q_b64"] = trotter_free(ucc, torch, h1, h2, exc, thetas)
     if args.serve_arrivals > 0:
         out["served_evals_per_s"] = served_same_workload(ucc, h1, h2, exc, thetas)
         out["serving_mix"] = serving_mix(ucc, args.serve_arrivals)

@@ -13,6 +13,7 @@
 // tables, the start vectors and the running sum.
 //
 //   k_cheb_coef   rho, degree m and J_0 .. J_m (Miller's backward recurrence) per batch entry
+//                 (rho >= kChebRhoMin keeps 2 / rho finite when every theta is 0)
 //   k_gen_values  the generator's value tables of each entry: unit values times theta_k 2/rho
 //   k_cheb_init   y_0 = |HF>, y_1 = 0, F = J_0 |HF>
 //   k_cheb_acc    F += 2 J_j y_j (entries whose degree is reached are left alone)
@@ -32,16 +33,19 @@ typedef double dvec2 __attribute__((ext_vector_type(2)));
 __device__ __forceinline__ dvec2 ld16(const double2* p) { return *reinterpret_cast<const dvec2*>(p); }
 __device__ __forceinline__ void st16(double2* p, dvec2 v) { *reinterpret_cast<dvec2*>(p) = v; }
 
-// One thread per batch entry.  coef[b][0] = J_0(rho), coef[b][j] = 2 J_j(rho) for 1 <= j <= m;
-// deg[b] = m, or -1 when no m <= max_terms meets the tolerance (rho too large).
-__global__ void k_cheb_coef(const double* __restrict__ theta, int K, int B, double tol,
-                            int max_terms, double* __restrict__ coef, double* __restrict__ cfac,
-                            int* __restrict__ deg) {
-  const int b = blockIdx.x * blockDim.x + threadIdx.x;
-  if (b >= B) return;
-  double rho = 0.0;
-  for (int k = 0; k < K; ++k) rho += fabs(theta[(size_t)b * K + k]);
-  rho = fmax(rho, kChebRhoMin);
+// One wave per batch entry: the lanes sum |theta| (lane l takes k = l, l + 64, ..., then a
+// fixed butterfly), lane 0 does the rest.  coef[b][0] = J_0(rho), coef[b][j] = 2 J_j(rho) for
+// 1 <= j <= m; deg[b] = m, or -1 when no m <= max_terms meets the tolerance (rho too large).
+__global__ __launch_bounds__(64) void k_cheb_coef(const double* __restrict__ theta, int K, int B,
+                                                  double tol, int max_terms,
+                                                  double* __restrict__ coef,
+                                                  double* __restrict__ cfac, int* __restrict__ deg) {
+  const int b = blockIdx.x;
+  double part = 0.0;
+  for (int k = threadIdx.x; k < K; k += 64) part += fabs(theta[(size_t)b * K + k]);
+  for (int o = 32; o >= 1; o >>= 1) part += __shfl_xor(part, o);
+  if (threadIdx.x != 0) return;
+  const double rho = fmax(part, kChebRhoMin);
   cfac[b] = 2.0 / rho;
   // degree: term_j = (rho/2)^j / j! bounds |J_j|; the tail after m = j - 1 is at most
   // 2 term_j / (1 - (rho/2) / (j + 1)) once (rho/2) / (j + 1) < 1/2
@@ -143,8 +147,8 @@ inline int stream_grid(size_t total) {
 
 hipError_t launch_cheb_coef(const double* theta, int K, int B, double tol, int max_terms, double* coef,
                             double* cfac, int* deg, hipStream_t st) {
-  hipLaunchKernelGGL(k_cheb_coef, dim3((B + 63) / 64), dim3(64), 0, st, theta, K, B, tol, max_terms,
-                     coef, cfac, deg);
+  hipLaunchKernelGGL(k_cheb_coef, dim3(B), dim3(64), 0, st, theta, K, B, tol, max_terms, coef, cfac,
+                     deg);
   return hipGetLastError();
 }
 

@@ -7,6 +7,20 @@
 
 namespace ucc {
 
+// Generator product pass of the Trotter-free evaluation, per-entry values and series update.
+struct GenPassArgs {
+  const uint4* tmpl = nullptr;    // value tables with unit values (the overlapped kernel's)
+  const int32_t* vmap = nullptr;  // per double of the value tables: excitation of a unit value, or -1
+  const double* theta = nullptr;  // [B][K]
+  int K = 0;
+  const double* cfac = nullptr;   // [B]: 2 / rho
+  double2* facc = nullptr;        // series sum (nullable: no update)
+  const double* coef = nullptr;   // [B][cstride]: series coefficients
+  int cstride = 0;
+  const int* deg = nullptr;       // [B]: series degree (entries beyond it are not updated)
+  int j = 0;                      // term index
+};
+
 struct LaunchArgs {
   hipStream_t stream = nullptr;
   int n = 0, K = 0, B = 0;
@@ -41,6 +55,12 @@ hipError_t launch_trig(const LaunchArgs& a, const double* theta);
 // Forward pass pidx from state src into state dst (src == dst: in place; init: src unused).
 hipError_t launch_fwd(const LaunchArgs& a, int pidx, int init, const double2* src, double2* dst);
 hipError_t launch_exp(const LaunchArgs& a, int pidx, int eslot, int first, bool apply);
+// lambda (+)= (generator values) psi over generator pass pidx (first: the pass writes lambda).
+// Where the overlapped kernel applies, it takes the values from g (theta, cfac) and, with
+// g.facc, adds coef_j times the new lambda into the series sum; *fused reports that it ran.
+// Otherwise the per-entry value tables a.blobs (a.blob_stride) are used and no sum update
+// happens.
+hipError_t launch_gen(const LaunchArgs& a, int pidx, int first, const GenPassArgs& g, bool* fused);
 // Reverse pass pidx on (psi, a.lam); write_psi = 0: psi is a stored state, read only.
 hipError_t launch_rev(const LaunchArgs& a, int pidx, double2* psi, bool write_psi);
 hipError_t launch_reduce(const LaunchArgs& a, int ne, bool grad, int nt);

@@ -517,13 +517,15 @@ __device__ __forceinline__ void exp_prep(const uint32_t* bw, double* t1, double*
 // With APPLY the row sums are added into lambda (first pass: written): in HBM at base | the
 // state's local offset (LDSLAM false), or in LDS by rank (LDSLAM true).
 // OLDL: the old lambda values of the rows are in LDS (oldl, by rank), read there instead of
-// from HBM.
-template <int T, bool APPLY, bool LDSLAM, bool OLDL = false>
+// from HBM.  ACC (with facc non-null): every row's new value v is also added, times fc, into
+// facc at the same place (the running sum of a series whose terms this pass completes).
+template <int T, bool APPLY, bool LDSLAM, bool OLDL = false, bool ACC = false>
 __device__ __forceinline__ double exp_rows(const double2* cp, const uint32_t* blk,
                                            const uint32_t* __restrict__ ent, const uint32_t* bw,
                                            const double* t1, const double* t2, const double* dpre,
                                            int k, int n, uint32_t base, double2* __restrict__ vl,
-                                           int first, const double2* oldl = nullptr) {
+                                           int first, const double2* oldl = nullptr,
+                                           double2* __restrict__ facc = nullptr, double fc = 0.0) {
   const double* dw = reinterpret_cast<const double*>(bw);
   const int has_diag = (int)bw[2];
   const uint32_t* xloc = bw + bw[5];
@@ -619,7 +621,14 @@ __device__ __forceinline__ double exp_rows(const double2* cp, const uint32_t* bl
     if (row && sub == owner) {
       const double2 pu = cp[i];
       eacc += pu.x * ax + pu.y * ay;
-      if (APPLY) st16(vl + phys, dvec2{old.x + ax, old.y + ay});
+      if (APPLY) {
+        const dvec2 nv = {old.x + ax, old.y + ay};
+        st16(vl + phys, nv);
+        if (ACC && facc) {
+          const dvec2 f = ld16(facc + phys);
+          st16(facc + phys, dvec2{f.x + fc * nv.x, f.y + fc * nv.y});
+        }
+      }
     }
   }
   return eacc;
@@ -1033,12 +1042,17 @@ __global__ __launch_bounds__(T) LDS_BOUND_OCCUPANCY void k_exp(
 // other slot, in two halves of registers.  The walk's own memory reads (entries, old lambda)
 // then never queue behind the tile's loads (vector-memory counters are per wave).  The
 // per-tile slot values depend only on the tile, so they are computed once.
-template <int T, int KT, bool APPLY>
+// GEN (the generator products of the Trotter-free evaluation): the value table holds unit
+// values; the producers also scale the next item's slot values by theta_k * cfac of its batch
+// entry (the slot's excitation k from the value map) into the other of two value slots, and
+// with ga.facc the walkers add coef_j times each new row value into the series sum.
+template <int T, int KT, bool APPLY, bool GEN = false>
 __global__ __launch_bounds__(T) LDS_BOUND_OCCUPANCY void k_exp2(
     const DevPass* __restrict__ passes, int pidx, const uint4* __restrict__ blobs,
     const int2* __restrict__ pcls, const uint32_t* __restrict__ blocks,
     const double2* __restrict__ psi, double2* __restrict__ lam, int n, uint32_t amask,
-    uint32_t bmask, double* __restrict__ epart, int estride, int first, int total, int flip) {
+    uint32_t bmask, double* __restrict__ epart, int estride, int first, int total, int flip,
+    GenPassArgs ga) {
   extern __shared__ double2 lds[];
   constexpr int P = T / 2;    // producers: the upper half
   constexpr int NWW = P / 64;  // walker waves
@@ -1088,7 +1102,25 @@ __global__ __launch_bounds__(T) LDS_BOUND_OCCUPANCY void k_exp2(
   const TL tm(ps.lmask, prod ? threadIdx.x - P : 0u);
   const int nsc = (int)blk[0];
   const uint32_t* sphys = blk + 2 + 2 * nsc + 1 + ((nsc + 1) >> 1);  // rows' local offsets
+  // GEN: per-item slot values (two slots) and the slot -> excitation map, behind the rank table
+  double* t1x = reinterpret_cast<double*>(rtab + tileN);
+  int* kmap = reinterpret_cast<int*>(t1x + 2 * ps.n_slots);
+  if (GEN) {
+    const int32_t* vm = ga.vmap + ((size_t)ps.blob_off * 4 + bw[6]) / 2;
+    for (int q = threadIdx.x; q < ps.n_slots; q += T) kmap[q] = vm[q];
+    __syncthreads();  // t1 (exp_prep) and kmap complete
+  }
+  auto scale_values = [&](int it, int s) {
+    const int b = ent(it);
+    const double c = ga.cfac[b];
+    const double* th = ga.theta + (size_t)b * ga.K;
+    for (int q = (int)tm.tid; q < ps.n_slots; q += P) {
+      const int km = kmap[q];
+      t1x[s * ps.n_slots + q] = km >= 0 ? t1[q] * th[km] * c : t1[q];
+    }
+  };
   auto read_item = [&](int it, int s) {
+    if (GEN) scale_values(it, s);
     const double2* v = psi + ((size_t)ent(it) << n);
     typename TL::Buf r;
     tm.refresh();
@@ -1110,9 +1142,18 @@ __global__ __launch_bounds__(T) LDS_BOUND_OCCUPANCY void k_exp2(
     const int slot = j & 1;
     const int next = item + gridDim.x;
     if (!prod) {
-      double2* __restrict__ vl = APPLY ? lam + ((size_t)ent(item) << n) : nullptr;
-      double e = exp_rows<P, APPLY, false, APPLY>(cpb + slot * ns_max, blk, gent, bw, t1, t2, dpre,
-                                                  k, n, base, vl, first, clb + slot * ns_max);
+      const int b = ent(item);
+      double2* __restrict__ vl = APPLY ? lam + ((size_t)b << n) : nullptr;
+      double2* facc = nullptr;
+      double fc = 0.0;
+      if (GEN && ga.facc && ga.j <= ga.deg[b]) {
+        facc = ga.facc + ((size_t)b << n);
+        fc = ga.coef[(size_t)b * ga.cstride + ga.j];
+      }
+      double e = exp_rows<P, APPLY, false, APPLY, GEN>(cpb + slot * ns_max, blk, gent, bw,
+                                                       GEN ? t1x + slot * ps.n_slots : t1, t2, dpre,
+                                                       k, n, base, vl, first, clb + slot * ns_max,
+                                                       facc, fc);
       e = wave_sum(e);
       if (lane == 0) red[slot][w] = e;
     } else if (next < total) {
@@ -1436,7 +1477,7 @@ hipError_t exp_overlapped(const LaunchArgs& a, int pidx, int eslot, int first, b
     if (grid < ntiles || grid % ntiles != 0) return hipSuccess;
     hipLaunchKernelGGL((k_exp2<T, KT, APPLY>), dim3(grid), dim3(T), lds, a.stream, a.passes, pidx,
                        a.blobs, a.cls, a.pairs, a.psi, a.lam, a.n, a.amask, a.bmask,
-                       a.epart + (size_t)eslot, a.estride, first, total, a.flip);
+                       a.epart + (size_t)eslot, a.estride, first, total, a.flip, GenPassArgs());
     *used = true;
     return hipGetLastError();
   }
@@ -1461,6 +1502,45 @@ hipError_t exp_t(const LaunchArgs& a, int pidx, int eslot, int first) {
                      a.blobs, a.cls, a.pairs, a.psi, a.lam, a.n, a.amask, a.bmask,
                      a.epart + (size_t)eslot, a.estride, first, total, a.blob_stride, a.flip);
   return hipGetLastError();
+}
+
+// Generator pass of the Trotter-free evaluation: the overlapped kernel with per-entry values
+// (and the fused series update) where it applies, else k_exp on the per-entry value tables.
+template <int T, int KT>
+hipError_t gen_t(const LaunchArgs& a, int pidx, int first, const GenPassArgs& g, bool* fused) {
+  *fused = false;
+  if constexpr (!(T < 512 || KT == 0 || (T == 512 && KT > 13))) {
+    const DevPass& hp = a.hpasses[pidx];
+    const int k = hp.k;
+    const int ntiles = 1 << (a.n - k);
+    const size_t lds = 64 * size_t(hp.ns_max) + 16 * size_t(hp.blob_len) +
+                       8 * (size_t((hp.n_slots + 1) & ~1) + size_t((hp.n_occ + 1) & ~1) + size_t((k + 2) & ~1)) +
+                       4 * size_t(hp.stage_len) + (size_t(2) << k) + 20 * size_t(hp.n_slots) + 16;
+    if (hp.row_avg <= kLightRow && lds + 256 <= (size_t)kLdsBytes) {
+      hipError_t e = set_lds(k_exp2<T, KT, true, true>, lds);
+      if (e != hipSuccess) return e;
+      const int total = a.B << (a.n - k);
+      const int grid = pass_grid(total, resident_grid(k_exp2<T, KT, true, true>, T, lds, a.cu_share), ntiles);
+      if (grid >= ntiles && grid % ntiles == 0) {
+        hipLaunchKernelGGL((k_exp2<T, KT, true, true>), dim3(grid), dim3(T), lds, a.stream, a.passes,
+                           pidx, g.tmpl, a.cls, a.pairs, a.psi, a.lam, a.n, a.amask, a.bmask, a.epart,
+                           a.estride, first, total, a.flip, g);
+        *fused = true;
+        return hipGetLastError();
+      }
+    }
+  }
+  return exp_t<T, KT, true>(a, pidx, 0, first);
+}
+
+template <int T>
+hipError_t gen_k(const LaunchArgs& a, int pidx, int first, const GenPassArgs& g, bool* fused) {
+  const int k = a.hpasses[pidx].k;
+  if constexpr (T >= 512)
+    if (k == 14) return gen_t<T, 14>(a, pidx, first, g, fused);
+  if (k == 13) return gen_t<T, 13>(a, pidx, first, g, fused);
+  if (k == 12) return gen_t<T, 12>(a, pidx, first, g, fused);
+  return gen_t<T, 0>(a, pidx, first, g, fused);
 }
 
 // Tile-size dispatch: unrolled register staging where the tile fits in at most 32 elements
@@ -1531,6 +1611,14 @@ hipError_t launch_exp(const LaunchArgs& a, int pidx, int eslot, int first, bool 
     case 256: return exp_k<256, false>(a, pidx, eslot, first);
     case 1024: return exp_k<1024, false>(a, pidx, eslot, first);
     default: return exp_k<512, false>(a, pidx, eslot, first);
+  }
+}
+
+hipError_t launch_gen(const LaunchArgs& a, int pidx, int first, const GenPassArgs& g, bool* fused) {
+  switch (a.te) {
+    case 256: return gen_k<256>(a, pidx, first, g, fused);
+    case 1024: return gen_k<1024>(a, pidx, first, g, fused);
+    default: return gen_k<512>(a, pidx, first, g, fused);
   }
 }
 

@@ -4,10 +4,10 @@
 //
 // exp(A)|HF> is summed as a Chebyshev series (chebyshev.hip).  Every term needs one product
 // A y, which runs on the expectation-pass kernels with the generator compiled as x-groups
-// (one per excitation, build_generator_plan) and per-entry value tables holding
-// theta_k * 2 / rho; the three-term recurrence adds the previous vector through the apply
-// kernel's accumulate mode (lambda += A psi), so a term costs the generator passes plus one
-// sweep that adds the term into the sum.  The energy then comes from the context's own
+// (one per excitation, build_generator_plan) and per-entry values theta_k * 2 / rho; the
+// three-term recurrence adds the previous vector through the apply kernel's accumulate mode
+// (lambda += A psi), and the last pass of a term also adds the finished term into the sum, so
+// a term costs the generator passes alone.  The energy then comes from the context's own
 // expectation passes on the sum.
 #include <hip/hip_runtime_api.h>
 
@@ -174,31 +174,46 @@ ucc_status enqueue_trotter_free(ucc_ctx* c, const double* d_theta, int B, hipStr
   a.cls = reinterpret_cast<const int2*>(g.d_cls);
   a.blobs = reinterpret_cast<const uint4*>(g.bank);
   a.blob_stride = (int)(g.tab.blob.size() / 4);
-  int seq = 0;
-  // dst (+)= (2 / rho) A src over the generator's passes (first: the first pass writes dst)
-  auto apply = [&](double2* src, double2* dst, bool first) -> hipError_t {
-    a.psi = src;
-    a.lam = dst;
-    for (int i = 0; i < g.plan.nexp; ++i, ++seq) {
-      a.flip = seq & 1;
-      const bool fw = first && i == 0;
-      hipError_t r = timed(UCC_KERNEL_GEN, S + (fw ? sec : 2 * sec),
-                           [&] { return launch_exp(a, i, 0, fw ? 1 : 0, true); });
-      if (r != hipSuccess) return r;
-    }
-    return hipSuccess;
-  };
+  GenPassArgs ga;
+  ga.tmpl = reinterpret_cast<const uint4*>(g.d_blob);
+  ga.vmap = g.d_map;
+  ga.theta = d_theta;
+  ga.K = p.K;
+  ga.cfac = g.cfac;
+  ga.coef = g.coef;
+  ga.cstride = cstride;
+  ga.deg = g.deg;
   auto acc = [&](double2* y, int j, double yscale) {
     return timed(UCC_KERNEL_CHEB, yscale != 1.0 ? 4 * S : 3 * S, [&] {
       return launch_cheb_acc(y, F, g.coef, cstride, g.deg, j, yscale, p.n, B, st);
     });
   };
+  int seq = 0;
+  // dst (+)= (2 / rho) A src over the generator's passes (first: the first pass writes dst);
+  // term > 0: dst is series term `term`, added into F by the last pass (or a sweep after it)
+  auto apply = [&](double2* src, double2* dst, bool first, int term) -> hipError_t {
+    a.psi = src;
+    a.lam = dst;
+    const int last = g.plan.nexp - 1;
+    for (int i = 0; i <= last; ++i, ++seq) {
+      a.flip = seq & 1;
+      const bool fw = first && i == 0;
+      ga.facc = term > 0 && i == last ? F : nullptr;
+      ga.j = term;
+      bool fused = false;
+      hipError_t r = timed(UCC_KERNEL_GEN, S + (fw ? sec : 2 * sec) + (ga.facc ? 2 * sec : 0.0),
+                           [&] { return launch_gen(a, i, fw ? 1 : 0, ga, &fused); });
+      if (r != hipSuccess) return r;
+      if (ga.facc && !fused) r = acc(dst, term, 1.0);
+      if (r != hipSuccess) return r;
+    }
+    return hipSuccess;
+  };
   if (m >= 1) {
-    e = apply(y0, y1, true);  // y1 = (2 / rho) A y0 = 2 y_1
+    e = apply(y0, y1, true, 0);  // y1 = (2 / rho) A y0 = 2 y_1
     if (e == hipSuccess) e = acc(y1, 1, 0.5);
     for (int j = 2; j <= m && e == hipSuccess; ++j) {
-      e = apply(y1, y0, false);  // y0 = y_{j-2} + (2 / rho) A y_{j-1} = y_j
-      if (e == hipSuccess) e = acc(y0, j, 1.0);
+      e = apply(y1, y0, false, j);  // y0 = y_{j-2} + (2 / rho) A y_{j-1} = y_j, F += c_j y_j
       std::swap(y0, y1);
     }
     if (e != hipSuccess) return hip_fail(e, "launch Chebyshev term");
