@@ -138,12 +138,12 @@ struct Tile {
   static constexpr int L2T = log2i<T>();
   static constexpr int EPT = KT ? (1 << KT) / T : 1;
   static constexpr int JB = KT ? KT - L2T : 0;
-  static_assert(JB <= 5, "tile too large for the workgroup");
+  static_assert(JB <= 6, "tile too large for the workgroup");
   using Buf = RegBuf<EPT>;
   uint32_t lmask;
   uint32_t tid;  // the thread's index among the T threads that share the tile
   mutable uint32_t dt;
-  uint32_t h0 = 0, h1 = 0, h2 = 0, h3 = 0, h4 = 0;  // physical bits of j's bits 0..4
+  uint32_t h0 = 0, h1 = 0, h2 = 0, h3 = 0, h4 = 0, h5 = 0;  // physical bits of j's bits 0..5
   __device__ __forceinline__ explicit Tile(uint32_t lm, uint32_t t = threadIdx.x) : lmask(lm), tid(t) {
     dt = dep(t, lm);
     uint32_t mm = lm;
@@ -159,6 +159,7 @@ struct Tile {
     if (JB > 2) h2 = low();
     if (JB > 3) h3 = low();
     if (JB > 4) h4 = low();
+    if (JB > 5) h5 = low();
   }
   // Make the per-element offsets look fresh to the compiler, so they are recomputed (one OR
   // each) where used instead of being hoisted and held in registers across a whole pass.
@@ -166,7 +167,7 @@ struct Tile {
   template <int J>
   __device__ __forceinline__ uint32_t off() const {
     return dt | ((J & 1) ? h0 : 0u) | ((J & 2) ? h1 : 0u) | ((J & 4) ? h2 : 0u) |
-           ((J & 8) ? h3 : 0u) | ((J & 16) ? h4 : 0u);
+           ((J & 8) ? h3 : 0u) | ((J & 16) ? h4 : 0u) | ((J & 32) ? h5 : 0u);
   }
   // fetch issues the loads of elements J .. JE - 1 of the thread into registers (waited on
   // where they are used)
@@ -1036,17 +1037,30 @@ __global__ __launch_bounds__(T) LDS_BOUND_OCCUPANCY void k_exp(
   }
 }
 
+// Producer side of the overlapped expectation pass: the thread's tile elements in PD chunks of
+// H, each loaded into registers and then given to LDS by rank.
+template <int C, int PD, int H, class TL, class SC>
+__device__ __forceinline__ void read_chunks(const TL& tm, typename TL::Buf& r, const double2* v,
+                                            uint32_t base, double2* cv, const uint16_t* rtab) {
+  if constexpr (C < PD) {
+    tm.refresh();
+    tm.template fetch<C * H, (C + 1) * H>(r, v, base);
+    SC::template take<C * H, (C + 1) * H>(tm, r, cv, rtab);
+    read_chunks<C + 1, PD, H, TL, SC>(tm, r, v, base, cv, rtab);
+  }
+}
+
 // Expectation / apply-H pass, overlapped form for light passes (few entries per row) whose
-// workgroups keep one tile and one value table: the lower half of the workgroup walks the
-// rows of item j (LDS slot j & 1) while the upper half reads the tile of item j + 1 into the
-// other slot, in two halves of registers.  The walk's own memory reads (entries, old lambda)
+// workgroups keep one tile and one value table: the lower (PD - 1) / PD of the workgroup walks
+// the rows of item j (LDS slot j & 1) while the top 1 / PD reads the tile of item j + 1 into
+// the other slot, in PD register chunks.  The walk's own memory reads (entries, old lambda)
 // then never queue behind the tile's loads (vector-memory counters are per wave).  The
 // per-tile slot values depend only on the tile, so they are computed once.
 // GEN (the generator products of the Trotter-free evaluation): the value table holds unit
 // values; the producers also scale the next item's slot values by theta_k * cfac of its batch
 // entry (the slot's excitation k from the value map) into the other of two value slots, and
 // with ga.facc the walkers add coef_j times each new row value into the series sum.
-template <int T, int KT, bool APPLY, bool GEN = false>
+template <int T, int KT, bool APPLY, bool GEN = false, int PD = 2>
 __global__ __launch_bounds__(T) LDS_BOUND_OCCUPANCY void k_exp2(
     const DevPass* __restrict__ passes, int pidx, const uint4* __restrict__ blobs,
     const int2* __restrict__ pcls, const uint32_t* __restrict__ blocks,
@@ -1054,11 +1068,13 @@ __global__ __launch_bounds__(T) LDS_BOUND_OCCUPANCY void k_exp2(
     uint32_t bmask, double* __restrict__ epart, int estride, int first, int total, int flip,
     GenPassArgs ga) {
   extern __shared__ double2 lds[];
-  constexpr int P = T / 2;    // producers: the upper half
-  constexpr int NWW = P / 64;  // walker waves
+  constexpr int P = T / PD;     // producers: the top 1/PD of the workgroup
+  constexpr int W = T - P;      // walkers
+  constexpr int NWW = W / 64;   // walker waves
+  static_assert(NWW <= 16, "walker waves");
   using TL = Tile<P, KT>;
   using SC = Sector<P, KT>;
-  constexpr int H = TL::EPT / 2;  // elements per register half
+  constexpr int H = TL::EPT / PD;  // elements per register chunk
   __shared__ double red[2][16];
   const DevPass ps = passes[pidx];
   const uint32_t tileN = 1u << ps.k;
@@ -1098,8 +1114,8 @@ __global__ __launch_bounds__(T) LDS_BOUND_OCCUPANCY void k_exp2(
     gent = src + words;
   }
   exp_prep<T>(bw, t1, t2, dpre, ps.lmask, k, n, base);
-  const bool prod = (int)threadIdx.x >= P;
-  const TL tm(ps.lmask, prod ? threadIdx.x - P : 0u);
+  const bool prod = (int)threadIdx.x >= W;
+  const TL tm(ps.lmask, prod ? threadIdx.x - W : 0u);
   const int nsc = (int)blk[0];
   const uint32_t* sphys = blk + 2 + 2 * nsc + 1 + ((nsc + 1) >> 1);  // rows' local offsets
   // GEN: per-item slot values (two slots) and the slot -> excitation map, behind the rank table
@@ -1123,12 +1139,7 @@ __global__ __launch_bounds__(T) LDS_BOUND_OCCUPANCY void k_exp2(
     if (GEN) scale_values(it, s);
     const double2* v = psi + ((size_t)ent(it) << n);
     typename TL::Buf r;
-    tm.refresh();
-    tm.template fetch<0, H>(r, v, base);
-    SC::template take<0, H>(tm, r, cpb + s * ns_max, rtab);
-    tm.refresh();
-    tm.template fetch<H, 2 * H>(r, v, base);
-    SC::template take<H, 2 * H>(tm, r, cpb + s * ns_max, rtab);
+    read_chunks<0, PD, H, TL, SC>(tm, r, v, base, cpb + s * ns_max, rtab);
     if (APPLY && !first) {  // the rows' old lambda values, for the walk to read from LDS
       const double2* vl = lam + ((size_t)ent(it) << n);
       for (int i = (int)tm.tid; i < nsc; i += P) st16(clb + s * ns_max + i, ld16(vl + (base | sphys[i])));
@@ -1150,7 +1161,7 @@ __global__ __launch_bounds__(T) LDS_BOUND_OCCUPANCY void k_exp2(
         facc = ga.facc + ((size_t)b << n);
         fc = ga.coef[(size_t)b * ga.cstride + ga.j];
       }
-      double e = exp_rows<P, APPLY, false, APPLY, GEN>(cpb + slot * ns_max, blk, gent, bw,
+      double e = exp_rows<W, APPLY, false, APPLY, GEN>(cpb + slot * ns_max, blk, gent, bw,
                                                        GEN ? t1x + slot * ps.n_slots : t1, t2, dpre,
                                                        k, n, base, vl, first, clb + slot * ns_max,
                                                        facc, fc);
@@ -1455,6 +1466,10 @@ hipError_t rev_t(const LaunchArgs& a, int pidx, double2* psi, bool wp) {
 
 // Passes with at most this many entries per row take the overlapped form where it applies.
 constexpr int kLightRow = 64;
+// Producer share of the overlapped expectation pass: a quarter of a 1024-thread workgroup
+// (12 walker waves; the row walk bounds these passes), half of a smaller one.
+template <int T>
+constexpr int exp2_pd() { return T == 1024 ? 4 : 2; }
 
 template <int T, int KT, bool APPLY>
 hipError_t exp_overlapped(const LaunchArgs& a, int pidx, int eslot, int first, bool* used) {
@@ -1470,12 +1485,14 @@ hipError_t exp_overlapped(const LaunchArgs& a, int pidx, int eslot, int first, b
                        8 * (size_t((hp.n_slots + 1) & ~1) + size_t((hp.n_occ + 1) & ~1) + size_t((k + 2) & ~1)) +
                        4 * size_t(hp.stage_len) + (size_t(2) << k);
     if (lds + 256 > (size_t)kLdsBytes) return hipSuccess;
-    hipError_t e = set_lds(k_exp2<T, KT, APPLY>, lds);
+    constexpr int PD = exp2_pd<T>();
+    hipError_t e = set_lds(k_exp2<T, KT, APPLY, false, PD>, lds);
     if (e != hipSuccess) return e;
     const int total = a.B << (a.n - k);
-    const int grid = pass_grid(total, resident_grid(k_exp2<T, KT, APPLY>, T, lds, a.cu_share), ntiles);
+    const int grid =
+        pass_grid(total, resident_grid(k_exp2<T, KT, APPLY, false, PD>, T, lds, a.cu_share), ntiles);
     if (grid < ntiles || grid % ntiles != 0) return hipSuccess;
-    hipLaunchKernelGGL((k_exp2<T, KT, APPLY>), dim3(grid), dim3(T), lds, a.stream, a.passes, pidx,
+    hipLaunchKernelGGL((k_exp2<T, KT, APPLY, false, PD>), dim3(grid), dim3(T), lds, a.stream, a.passes, pidx,
                        a.blobs, a.cls, a.pairs, a.psi, a.lam, a.n, a.amask, a.bmask,
                        a.epart + (size_t)eslot, a.estride, first, total, a.flip, GenPassArgs());
     *used = true;
@@ -1516,13 +1533,15 @@ hipError_t gen_t(const LaunchArgs& a, int pidx, int first, const GenPassArgs& g,
     const size_t lds = 64 * size_t(hp.ns_max) + 16 * size_t(hp.blob_len) +
                        8 * (size_t((hp.n_slots + 1) & ~1) + size_t((hp.n_occ + 1) & ~1) + size_t((k + 2) & ~1)) +
                        4 * size_t(hp.stage_len) + (size_t(2) << k) + 20 * size_t(hp.n_slots) + 16;
+    constexpr int PD = exp2_pd<T>();
     if (hp.row_avg <= kLightRow && lds + 256 <= (size_t)kLdsBytes) {
-      hipError_t e = set_lds(k_exp2<T, KT, true, true>, lds);
+      hipError_t e = set_lds(k_exp2<T, KT, true, true, PD>, lds);
       if (e != hipSuccess) return e;
       const int total = a.B << (a.n - k);
-      const int grid = pass_grid(total, resident_grid(k_exp2<T, KT, true, true>, T, lds, a.cu_share), ntiles);
+      const int grid =
+          pass_grid(total, resident_grid(k_exp2<T, KT, true, true, PD>, T, lds, a.cu_share), ntiles);
       if (grid >= ntiles && grid % ntiles == 0) {
-        hipLaunchKernelGGL((k_exp2<T, KT, true, true>), dim3(grid), dim3(T), lds, a.stream, a.passes,
+        hipLaunchKernelGGL((k_exp2<T, KT, true, true, PD>), dim3(grid), dim3(T), lds, a.stream, a.passes,
                            pidx, g.tmpl, a.cls, a.pairs, a.psi, a.lam, a.n, a.amask, a.bmask, a.epart,
                            a.estride, first, total, a.flip, g);
         *fused = true;
