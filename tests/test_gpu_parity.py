@@ -340,6 +340,21 @@ def test_26q_theta_zero_closed_forms(ucc):
     assert np.max(np.abs(gr[0] - np.array(gold["grad"]))) <= G_TOL
 
 
+def test_30q_largest_state_theta_zero_closed_forms(ucc):
+    # the largest state the library accepts (n_qubits = 30: 16 GiB per vector), 4,424
+    # excitations: energy and gradient at theta = 0 against the closed forms
+    say("case: 30q/16e theta = 0 energy+grad vs closed forms (largest state)")
+    n, ne = 30, 16
+    h1, h2 = make_integrals(n // 2, 0)
+    h, g = hamiltonian.spin_orbital_integrals(h1, h2)
+    exc = uccsd_excitations(n, ne)
+    ctx = ucc.Context(n, ne, h1, h2, exc)
+    e, gr = ctx.energy_grad(np.zeros(len(exc)))
+    assert abs(e[0] - closed_forms.hf_energy_spatial(h1, h2, ne)) <= E_TOL
+    assert np.max(np.abs(gr[0] - closed_forms.gradient_at_zero(h, g, range(ne), exc))) <= G_TOL
+    ctx.close()
+
+
 def test_determinism_and_device_pointers(ucc):
     import torch
     say("case: 12q/8e determinism, torch device pointers, autograd")
