@@ -257,6 +257,24 @@ ucc_status ucc_get_pass_table(const ucc_ctx* ctx, int32_t* kind, uint32_t* local
 ucc_status ucc_get_generator_passes(ucc_ctx* ctx, int32_t cap, uint32_t* local, int32_t* exc_pass,
                                     int32_t* n_passes);
 
+/* ---------------------------------------------------------------- fragments */
+
+/*
+ * ucc_fmo2_energy -- the two-body FMO energy of Eq. 1 (Sec. 2.1),
+ *   E = sum_{I > J} E_IJ - (N_f - 2) sum_I E_I,
+ * from the energies of every fragment (monomer) and every fragment pair (dimer), as computed
+ * by ucc_energy / ucc_energy_grad / served VQE jobs on each fragment's own context.  Used as
+ * in the paper for the correlation energies as well (the formula is additive).
+ *   n_frag   N_f, 2 <= n_frag <= 65535
+ *   e_mono   host [n_frag]: E_I
+ *   e_dimer  host [n_frag (n_frag - 1) / 2]: E_IJ for the pairs (I, J), I > J, in the order
+ *            (1,0), (2,0), (2,1), (3,0), (3,1), (3,2), ...
+ *   e_total  host, receives E
+ * Errors: UCC_EINVAL (NULL pointer, n_frag out of range, a non-finite energy).
+ */
+ucc_status ucc_fmo2_energy(int32_t n_frag, const double* e_mono, const double* e_dimer,
+                           double* e_total);
+
 /* ---------------------------------------------------------------- profiling */
 
 /* Kernel kinds reported by ucc_profile_read. */

@@ -22,6 +22,12 @@ __all__ = [
     "make_integrals",
     "uccsd_excitations",
     "make_thetas",
+    "fragment_orbitals",
+    "fragment_integrals",
+    "delocalizing_rotation",
+    "rotate_integrals",
+    "embed_amplitudes",
+    "rotate_amplitudes",
     "WORKLOADS",
 ]
 
@@ -97,6 +103,114 @@ def make_thetas(n_exc: int, seed: int, scale: float, batch: int | None = None):
     out = np.empty((batch, n_exc))
     for b in range(batch):
         out[b] = np.random.default_rng(seed + b).uniform(-scale, scale, size=n_exc)
+    return out
+
+
+# ---------------------------------------------------------------- fragment systems
+# Inputs of the size-consistency experiment of Sec. 3.2 (Table 6): identical fragments far
+# apart (no integral couples two of them), described either by orbitals localized on the
+# fragments (LMO) or by orbitals delocalized over a pair (CMO).  These functions only lay out
+# and rotate the inputs (integrals and the amplitudes of one cluster operator written in
+# another orbital basis); the energies come from the oracle or the GPU path.
+
+
+def fragment_orbitals(n_frag: int, ns_frag: int, nocc_frag: int) -> np.ndarray:
+    """Spatial index, in the combined system, of orbital p of fragment f ([n_frag, ns_frag]):
+    all fragments' occupied orbitals first (fragment by fragment), then all virtual ones, so
+    the combined Hartree-Fock reference is the lowest orbitals."""
+    out = np.empty((n_frag, ns_frag), dtype=np.int64)
+    nv = ns_frag - nocc_frag
+    for f in range(n_frag):
+        for p in range(ns_frag):
+            out[f, p] = f * nocc_frag + p if p < nocc_frag else n_frag * nocc_frag + f * nv + (p - nocc_frag)
+    return out
+
+
+def fragment_integrals(frags, nocc_frag: int):
+    """Block-diagonal (h1, h2) of non-interacting fragments [(h1_f, h2_f), ...] of equal size,
+    in the orbital layout of fragment_orbitals."""
+    nf, ns = len(frags), frags[0][0].shape[0]
+    m = fragment_orbitals(nf, ns, nocc_frag)
+    N = nf * ns
+    h1 = np.zeros((N, N))
+    h2 = np.zeros((N, N, N, N))
+    for f, (a1, a2) in enumerate(frags):
+        ix = m[f]
+        h1[np.ix_(ix, ix)] = a1
+        h2[np.ix_(ix, ix, ix, ix)] = a2
+    return h1, h2
+
+
+def delocalizing_rotation(ns_frag: int, nocc_frag: int) -> np.ndarray:
+    """Orthogonal U of two fragments (spatial, old orbital x new orbital): orbital p of A and
+    of B become (A_p + B_p) / sqrt(2) and (A_p - B_p) / sqrt(2).  Occupied orbitals mix only
+    with occupied ones and virtual with virtual, so the Hartree-Fock determinant is unchanged
+    (up to sign); the new order is occupied pairs, then virtual pairs."""
+    m = fragment_orbitals(2, ns_frag, nocc_frag)
+    U = np.zeros((2 * ns_frag, 2 * ns_frag))
+    r = 1.0 / np.sqrt(2.0)
+    for p in range(ns_frag):
+        base = 2 * p if p < nocc_frag else 2 * nocc_frag + 2 * (p - nocc_frag)
+        a, b = m[0, p], m[1, p]
+        U[a, base], U[b, base] = r, r
+        U[a, base + 1], U[b, base + 1] = r, -r
+    return U
+
+
+def rotate_integrals(h1, h2, U):
+    """Integrals over the orbitals phi'_q = sum_p U[p, q] phi_p (real, chemist order)."""
+    h1r = U.T @ h1 @ U
+    h2r = np.einsum("pqrs,pa,qb,rc,sd->abcd", h2, U, U, U, U, optimize=True)
+    return np.ascontiguousarray(h1r), np.ascontiguousarray(h2r)
+
+
+def embed_amplitudes(exc_frag, thetas_frag, n_frag: int, ns_frag: int, nocc_frag: int, exc_all):
+    """Amplitudes over the combined excitation list exc_all: each fragment's excitation
+    (rows of exc_frag, fragment spin-orbital indices) carries that fragment's amplitude, every
+    other excitation (those across fragments) 0."""
+    m = fragment_orbitals(n_frag, ns_frag, nocc_frag)
+    index = {tuple(int(x) for x in r): k for k, r in enumerate(np.asarray(exc_all))}
+    out = np.zeros(len(exc_all))
+    for f in range(n_frag):
+        so = lambda q: -1 if q < 0 else 2 * int(m[f, q // 2]) + (q & 1)  # noqa: E731
+        for r, t in zip(np.asarray(exc_frag), thetas_frag[f]):
+            out[index[tuple(so(int(q)) for q in r)]] = t
+    return out
+
+
+def rotate_amplitudes(exc, theta, U):
+    """The same cluster operator written in the rotated orbitals (U as in rotate_integrals,
+    spin-free, occupied and virtual spaces each mapped to themselves).  T1 = sum t_ai a_a^+ a_i
+    and T2 = (1/4) sum tau_abij a_a^+ a_b^+ a_j a_i (tau antisymmetric, tau_abij = theta of
+    row (i, j, a, b) for i < j, a < b) transform as tensors; the result is read back on the
+    same list of excitations, which holds every non-zero element."""
+    exc = np.asarray(exc)
+    n = 2 * U.shape[0]
+    Us = np.zeros((n, n))
+    Us[0::2, 0::2] = U
+    Us[1::2, 1::2] = U
+    t1 = np.zeros((n, n))
+    tau = np.zeros((n, n, n, n))
+    for (i, j, a, b), t in zip(exc, theta):
+        if j < 0:
+            t1[a, i] = t
+        else:
+            tau[a, b, i, j], tau[b, a, i, j], tau[a, b, j, i], tau[b, a, j, i] = t, -t, -t, t
+    t1r = Us.T @ t1 @ Us
+    taur = np.einsum("abij,aA,bB,iI,jJ->ABIJ", tau, Us, Us, Us, Us, optimize=True)
+    out = np.empty(len(exc))
+    for k, (i, j, a, b) in enumerate(exc):
+        out[k] = t1r[a, i] if j < 0 else taur[a, b, i, j]
+    # nothing outside the list
+    rest1 = t1r.copy()
+    rest2 = taur.copy()
+    for i, j, a, b in exc:
+        if j < 0:
+            rest1[a, i] = 0.0
+        else:
+            rest2[a, b, i, j] = rest2[b, a, i, j] = rest2[a, b, j, i] = rest2[b, a, j, i] = 0.0
+    if max(np.max(np.abs(rest1)), np.max(np.abs(rest2))) > 1e-12:
+        raise ValueError("rotated cluster operator has terms outside the excitation list")
     return out
 
 

@@ -23,7 +23,7 @@ STATUS_CODES = {v: k for k, v in STATUS.items()}
 
 EXPORTED = [
     "ucc_default_options", "ucc_build", "ucc_energy", "ucc_energy_grad",
-    "ucc_energy_trotter_free", "ucc_get_generator_passes", "ucc_get_state",
+    "ucc_energy_trotter_free", "ucc_get_generator_passes", "ucc_fmo2_energy", "ucc_get_state",
     "ucc_destroy", "ucc_last_error", "ucc_get_plan_info", "ucc_batch_compatible",
     "ucc_get_pauli_terms",
     "ucc_get_group_table", "ucc_get_excitation_table", "ucc_get_pass_table",
@@ -85,6 +85,7 @@ def lib():
         "ucc_energy_grad": (_i32, [_vp, _vp, _i32, _vp, _vp, _vp]),
         "ucc_energy_trotter_free": (_i32, [_vp, _vp, _i32, _vp, _vp, _vp]),
         "ucc_get_generator_passes": (_i32, [_vp, _i32, _vp, _vp, _P(_i32)]),
+        "ucc_fmo2_energy": (_i32, [_i32, _vp, _vp, _P(_dbl)]),
         "ucc_get_state": (_i32, [_vp, _i32, _vp]),
         "ucc_destroy": (None, [_vp]),
         "ucc_last_error": (ctypes.c_char_p, []),
@@ -433,6 +434,18 @@ def _autograd():
 
 
 _UCCEnergy = None
+
+
+def fmo2_energy(e_mono, e_dimer):
+    """Eq. 1: sum over pairs I > J of E_IJ minus (N_f - 2) times the sum of the E_I.  e_dimer
+    lists the pairs (1,0), (2,0), (2,1), (3,0), ..."""
+    em = np.ascontiguousarray(e_mono, dtype=np.float64)
+    ed = np.ascontiguousarray(e_dimer, dtype=np.float64)
+    if ed.size != em.size * (em.size - 1) // 2:
+        raise ValueError("e_dimer must hold one energy per fragment pair")
+    out = ctypes.c_double()
+    check(lib().ucc_fmo2_energy(em.size, _ptr(em), _ptr(ed), ctypes.byref(out)), "ucc_fmo2_energy")
+    return out.value
 
 
 def ucc_energy_fn(theta, ctx):

@@ -33,7 +33,7 @@ def logical_to_phys(n, ne):
 
 def test_library_exports_every_declared_symbol():
     header = open(os.path.join(ROOT, "include", "ucc.h")).read()
-    declared = set(re.findall(r"\b(ucc_[a-z_]+)\s*\(", header))
+    declared = set(re.findall(r"\b(ucc_[a-z0-9_]+)\s*\(", header))
     declared -= {"ucc_status"}
     L = ctypes.CDLL(ucc.LIB_PATH)
     for name in sorted(declared):
@@ -303,3 +303,25 @@ def test_generator_plan_covers_every_excitation_once(n, ne, kw):
     # supports are x-masks of H's groups) plus the LDS splits
     assert len(local) <= info["n_exp_passes"] + 2
     ctx.close()
+
+
+# ---------------------------------------------------------------- FMO two-body energy (Eq. 1)
+
+def test_fmo2_energy_assembly():
+    r = np.random.default_rng(3)
+    for nf in (2, 3, 5):
+        em = r.normal(size=nf)
+        pairs = [(i, j) for i in range(nf) for j in range(i)]
+        ed = r.normal(size=len(pairs))
+        # Eq. 1 as printed, and its equivalent monomer-plus-pair-correction form
+        ref = ed.sum() - (nf - 2) * em.sum()
+        alt = em.sum() + sum(ed[k] - em[i] - em[j] for k, (i, j) in enumerate(pairs))
+        assert abs(ucc.fmo2_energy(em, ed) - ref) < 1e-12 and abs(ref - alt) < 1e-12
+    # non-interacting fragments whose pair energies are exactly additive give the monomer sum
+    em = np.array([-1.25, -2.5, -0.75])
+    ed = np.array([em[1] + em[0], em[2] + em[0], em[2] + em[1]])
+    assert ucc.fmo2_energy(em, ed) == em.sum()
+    with pytest.raises(ValueError):
+        ucc.fmo2_energy(em, ed[:2])
+    with pytest.raises(ucc.UCCError):
+        ucc.fmo2_energy(em, np.array([0.0, np.nan, 0.0]))

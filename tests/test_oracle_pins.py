@@ -13,6 +13,7 @@ import pytest
 import scipy.linalg
 
 from oracle import ansatz, closed_forms, dense, fermion, hamiltonian, trotter_free
+from paper_2402_17993_amd import inputs
 from paper_2402_17993_amd.inputs import make_integrals, make_thetas, uccsd_excitations
 
 
@@ -534,3 +535,49 @@ def test_p20_unitary_time_reversible_and_additive():
         hs, gs = hamiltonian.spin_orbital_integrals(a1, a2)
         parts += trotter_free.trotter_free_energy(hs, gs, 4, 0b0011, exc_a, tt)
     assert abs(e_ab - parts) < 1e-12
+
+
+# ---------------------------------------------------------------- P21: size consistency and orbital invariance (Sec. 3.2, Table 6)
+
+def dimer_system(seed=7, scale=0.3):
+    """Two identical non-interacting 8-qubit fragments (4 orbitals, 4 electrons each): the
+    monomer, the dimer in fragment-localized orbitals (LMO) and in orbitals delocalized over
+    the pair (CMO), with the monomer's amplitudes on both fragments."""
+    a1, a2 = make_integrals(4, seed)
+    exc_m = uccsd_excitations(8, 4)
+    th_m = make_thetas(len(exc_m), 3, scale)
+    h1, h2 = inputs.fragment_integrals([(a1, a2), (a1, a2)], 2)
+    exc_d = uccsd_excitations(16, 8)
+    th_l = inputs.embed_amplitudes(exc_m, [th_m, th_m], 2, 4, 2, exc_d)
+    U = inputs.delocalizing_rotation(4, 2)
+    h1c, h2c = inputs.rotate_integrals(h1, h2, U)
+    th_c = inputs.rotate_amplitudes(exc_d, th_l, U)
+    return (a1, a2, exc_m, th_m), (h1, h2, th_l), (h1c, h2c, th_c), exc_d, U
+
+
+def test_p21_fragment_inputs_round_trip_and_hf_invariance():
+    _, (h1, h2, th_l), (h1c, h2c, th_c), exc_d, U = dimer_system()
+    assert np.allclose(U.T @ U, np.eye(8), atol=1e-15)
+    b1, b2 = inputs.rotate_integrals(h1c, h2c, U.T)
+    assert np.max(np.abs(b1 - h1)) < 1e-13 and np.max(np.abs(b2 - h2)) < 1e-13
+    assert np.max(np.abs(inputs.rotate_amplitudes(exc_d, th_c, U.T) - th_l)) < 1e-13
+    # the rotation keeps the occupied space, so the HF energy (closed form) is unchanged
+    assert abs(closed_forms.hf_energy_spatial(h1c, h2c, 8) - closed_forms.hf_energy_spatial(h1, h2, 8)) < 1e-12
+
+
+def test_p21_trotter_free_is_size_consistent_and_orbital_invariant():
+    (a1, a2, exc_m, th_m), lmo, cmo, exc_d, _ = dimer_system()
+    hm, gm = hamiltonian.spin_orbital_integrals(a1, a2)
+    em_t = ansatz.energy(hm, gm, 8, 0b1111, exc_m, th_m)
+    em_f = trotter_free.trotter_free_energy(hm, gm, 8, 0b1111, exc_m, th_m)
+    e = {}
+    for name, (x1, x2, th) in (("LMO", lmo), ("CMO", cmo)):
+        H, G = hamiltonian.spin_orbital_integrals(x1, x2)
+        e[name] = (ansatz.energy(H, G, 16, 0xFF, exc_d, th),
+                   trotter_free.trotter_free_energy(H, G, 16, 0xFF, exc_d, th))
+    # exp(T - T^dag) is the same operator in any orbital basis that keeps the occupied space:
+    # the Trotter-free dimer is twice the monomer in both bases
+    assert abs(e["LMO"][1] - 2 * em_f) < 1e-12 and abs(e["CMO"][1] - 2 * em_f) < 1e-12
+    # the Trotterized product is additive with localized orbitals only
+    assert abs(e["LMO"][0] - 2 * em_t) < 1e-12
+    assert abs(e["CMO"][0] - 2 * em_t) > 1e-4
