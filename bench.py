@@ -224,6 +224,62 @@ def trotter_free(ucc, torch, h1, h2, exc, thetas, steps=5):
             "max_abs_dE_vs_oracle": float(de), "energies_checked": len(gold["energies"])}
 
 
+def size_consistency(ucc, iters=400, lr=0.1):
+    """Table 6 of Sec. 3.2 on synthetic fragments: an 8-qubit monomer (4 orbitals, 4 electrons,
+    integrals seed 11 with the two-electron part scaled by 6 so that the optimal amplitudes are
+    large, as for the paper's square 4H) optimized by steepest-descent VQE on the server, then
+    the 16-qubit dimer of two far-apart copies in fragment-localized (LMO) and pair-delocalized
+    (CMO) orbitals with the monomer's amplitudes carried over (the CMO ones rotated with the
+    orbitals): Trotterized and Trotter-free energies minus twice the monomer's (the
+    size-consistency error) and minus the exact (FCI) energy, the Trotterized dimers
+    re-optimized by VQE from there, and Eq. 1 over three such fragments."""
+    from paper_2402_17993_amd import inputs
+    from paper_2402_17993_amd.inputs import make_integrals, make_thetas, uccsd_excitations
+    gold = json.load(open(os.path.join(ROOT, "tests", "golden", "fragment_h4.json")))
+    kcal = 627.5094740631
+    a1, a2 = make_integrals(4, gold["integral_seed"])
+    a2 = gold["h2_scale"] * a2
+    exc_m = uccsd_excitations(8, 4)
+    mono = ucc.Context(8, 4, a1, a2, exc_m)
+    exc_d = uccsd_excitations(16, 8)
+    h1, h2 = inputs.fragment_integrals([(a1, a2), (a1, a2)], 2)
+    U = inputs.delocalizing_rotation(4, 2)
+    h1c, h2c = inputs.rotate_integrals(h1, h2, U)
+    ctx = {"LMO": ucc.Context(16, 8, h1, h2, exc_d), "CMO": ucc.Context(16, 8, h1c, h2c, exc_d)}
+    t0 = time.perf_counter()
+    with ucc.Server(slots=4) as srv:
+        rm = srv.wait(srv.submit(mono, make_thetas(len(exc_m), 3, 0.01), iters, lr))
+        th_m = rm["theta"]
+        em_t = float(rm["energies"][-1])
+        em_f = float(mono.energy_trotter_free(th_m)[0])
+        th0 = {"LMO": inputs.embed_amplitudes(exc_m, [th_m, th_m], 2, 4, 2, exc_d)}
+        th0["CMO"] = inputs.rotate_amplitudes(exc_d, th0["LMO"], U)
+        efci = gold["fci_energy"]
+        out = {"monomer": {"trotterized_vqe": em_t, "trotter_free_at_same_theta": em_f,
+                           "dE_fci_kcal_trotterized": (em_t - efci) * kcal,
+                           "dE_fci_kcal_trotter_free": (em_f - efci) * kcal,
+                           "vqe_steps": iters, "lr": lr}}
+        tickets = {k: srv.submit(ctx[k], th0[k], iters, lr) for k in ctx}
+        for k in ctx:
+            r = srv.wait(tickets[k])
+            e0 = float(r["energies"][0])
+            ef = float(ctx[k].energy_trotter_free(th0[k])[0])
+            out[f"dimer_{k}"] = {
+                "trotterized_minus_2x_monomer": e0 - 2 * em_t,
+                "trotter_free_minus_2x_monomer": ef - 2 * em_f,
+                "trotterized_reoptimized_minus_2x_monomer": float(r["energies"][-1]) - 2 * em_t,
+                "dE_fci_kcal_trotterized": (e0 - 2 * efci) * kcal,
+                "dE_fci_kcal_trotter_free": (ef - 2 * efci) * kcal,
+                "dE_fci_kcal_trotterized_reoptimized": (float(r["energies"][-1]) - 2 * efci) * kcal}
+    e_pair = {k: 2 * em_t + out[f"dimer_{k}"]["trotterized_minus_2x_monomer"] for k in ctx}
+    out["fmo2_three_fragments_minus_3x_monomer"] = {
+        k: ucc.fmo2_energy(np.full(3, em_t), np.full(3, e_pair[k])) - 3 * em_t for k in ctx}
+    out["wall_s"] = time.perf_counter() - t0
+    for c in (mono, *ctx.values()):
+        c.close()
+    return out
+
+
 def cpu_small():
     """The oracle per E + grad evaluation at 8 and 16 qubits (one thread)."""
     from threadpoolctl import threadpool_limits
@@ -458,6 +514,7 @@ def main():
         out["large_26q"] = large_state(ucc, torch)
         out["trotter_variants_18q_b64"] = trotter_variants(ucc, torch, h1, h2, exc, thetas)
         out["trotter_free_18q_b64"] = trotter_free(ucc, torch, h1, h2, exc, thetas)
+        out["size_consistency_h8"] = size_consistency(ucc)
     if args.serve_arrivals > 0:
         out["served_evals_per_s"] = served_same_workload(ucc, h1, h2, exc, thetas)
         out["serving_mix"] = serving_mix(ucc, args.serve_arrivals)

@@ -15,7 +15,7 @@ import numpy as np
 ROOT = os.path.dirname(os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
 sys.path.insert(0, ROOT)
 
-from oracle import ansatz, closed_forms, hamiltonian, trotter_free  # noqa: E402
+from oracle import ansatz, closed_forms, dense, hamiltonian, trotter_free  # noqa: E402
 from paper_2402_17993_amd.inputs import make_integrals, make_thetas, uccsd_excitations  # noqa: E402
 
 HERE = os.path.dirname(os.path.abspath(__file__))
@@ -57,6 +57,17 @@ def case_dimer_18q_trotter_free():
     return out
 
 
+def case_fragment_h4():
+    """The fragment of the size-consistency workload (4 orbitals, 4 electrons; integrals seed
+    11 with the two-electron integrals scaled by 6 for strong correlation): FCI energy of the
+    N = 4, S_z = 0 sector (dense eigh).  Two non-interacting copies have twice this energy."""
+    a1, a2 = make_integrals(4, 11)
+    a2 = 6.0 * a2
+    h, g = hamiltonian.spin_orbital_integrals(a1, a2)
+    return {"n_spatial": 4, "n_elec": 4, "integral_seed": 11, "h2_scale": 6.0,
+            "fci_energy": dense.fci_energy(dense.hamiltonian_dense(h, g), 8, 4)}
+
+
 def case_large_26q_theta0():
     """26 qubits, 14 electrons, integrals seed 0, theta = 0: closed-form Hartree-Fock energy
     and Slater-Condon gradient (the oracle's closed forms; no state vector needed)."""
@@ -70,7 +81,7 @@ def case_large_26q_theta0():
 
 
 CASES = {"dimer_18q": case_dimer_18q, "dimer_18q_trotter_free": case_dimer_18q_trotter_free,
-         "large_26q_theta0": case_large_26q_theta0}
+         "fragment_h4": case_fragment_h4, "large_26q_theta0": case_large_26q_theta0}
 
 if __name__ == "__main__":
     names = sys.argv[1:] or list(CASES)
