@@ -159,14 +159,18 @@ def large_state(ucc, torch, n=26, ne=14):
 
 def trotter_variants(ucc, torch, h1, h2, exc, thetas, steps=5):
     """The benchmark workload (18 qubits, batch 64) under the other Trotter products of the
-    paper: M slices of the first-order product (Eq. 5) and the symmetric second-order product
-    (Eq. 6).  Evals/s over `steps` timed evaluations, HIP-event kernel times and the algorithmic
-    HBM rate."""
-    td = torch.tensor(thetas, device="cuda:0", dtype=torch.float64)
+    paper: M slices of the first-order product (Eq. 5), the symmetric second-order product
+    (Eq. 6), and the single product with the excitations in magnitude order (Sec. 2.3).
+    Evals/s over `steps` timed evaluations, HIP-event kernel times and the algorithmic HBM
+    rate."""
+    from paper_2402_17993_amd.inputs import magnitude_order
+    perm = magnitude_order(h1, h2, NE, exc)
+    tdm = torch.tensor(thetas[:, perm], device="cuda:0", dtype=torch.float64)
     out = {}
-    for M, order in ((2, 1), (1, 2), (3, 1)):
-        ctx = ucc.Context(N, NE, h1, h2, exc, max_batch=BATCH, device=0, trotter_steps=M,
-                          trotter_order=order)
+    for M, order, mag in ((2, 1, False), (1, 2, False), (3, 1, False), (1, 1, True)):
+        ctx = ucc.Context(N, NE, h1, h2, exc[perm] if mag else exc, max_batch=BATCH, device=0,
+                          trotter_steps=M, trotter_order=order)
+        td = tdm if mag else torch.tensor(thetas, device="cuda:0", dtype=torch.float64)
         ctx.energy_grad(td)
         torch.cuda.synchronize()
         ctx.profile(True)
@@ -182,7 +186,7 @@ def trotter_variants(ucc, torch, h1, h2, exc, thetas, steps=5):
         ctx.close()
         ms = a.elapsed_time(b) / steps
         byt = sum(v["bytes"] for v in st.values()) / steps
-        out[f"M{M}_order{order}"] = {
+        out[f"M{M}_order{order}" + ("_magnitude_ordered" if mag else "")] = {
             "evals_per_s": BATCH / (ms * 1e-3), "ms_per_step": ms,
             "GBps": byt / (ms * 1e-3) / 1e9, "frac": byt / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
             "passes_fwd_exp_rev": [info["n_fwd_passes"], info["n_exp_passes"], info["n_rev_passes"]]}

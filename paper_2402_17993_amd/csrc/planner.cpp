@@ -82,31 +82,39 @@ uint32_t pad_mask(uint32_t mask, int k, int n) {
   return mask;
 }
 
-// Ordered windows: consecutive excitations (in application order) whose support union,
-// together with the contiguous low bits, fits in k local bits.
+// Windows of factors that fit k local bits (with the contiguous low bits), in application
+// order.  A window takes, scanning the factors not yet placed, every factor that fits and
+// commutes with all factors it would move ahead of: two excitations on disjoint spin orbitals
+// are even fermion operators on disjoint modes, so they commute and exchanging them leaves the
+// product (and every adjoint gradient term) unchanged.  Factors that do not fit, or overlap a
+// factor left behind, stay for later windows in their order.
 std::vector<Plan::Pass> plan_windows(const Plan& p, int kind, int k, int c0) {
   const uint32_t F = (1u << c0) - 1u;
+  const int L = (int)p.seq.size();
+  std::vector<int> rest(L);
+  for (int t = 0; t < L; ++t) rest[t] = (kind == kRev) ? L - 1 - t : t;  // factor indices
   std::vector<Plan::Pass> out;
-  Plan::Pass cur;
-  cur.kind = kind;
-  cur.lmask = F;
-  auto close = [&]() {
+  while (!rest.empty()) {
+    Plan::Pass cur;
+    cur.kind = kind;
+    cur.lmask = F;
+    uint32_t skipped = 0;  // supports of the factors left behind in this scan
+    std::vector<int> keep;
+    keep.reserve(rest.size());
+    for (int e : rest) {
+      const uint32_t s = p.ex[p.seq[e]].supp;
+      if ((s & skipped) == 0 && pc32(cur.lmask | s) <= k && (int)cur.items.size() < kMaxPassExc) {
+        cur.items.push_back(e);
+        cur.lmask |= s;
+      } else {
+        skipped |= s;
+        keep.push_back(e);
+      }
+    }
     cur.lmask = pad_mask(cur.lmask, k, p.n);
     out.push_back(cur);
-  };
-  const int L = (int)p.seq.size();
-  for (int t = 0; t < L; ++t) {
-    const int e = (kind == kRev) ? L - 1 - t : t;  // factor index
-    const uint32_t s = p.ex[p.seq[e]].supp;
-    if (!cur.items.empty() && (pc32(cur.lmask | s) > k || (int)cur.items.size() >= kMaxPassExc)) {
-      close();
-      cur.items.clear();
-      cur.lmask = F;
-    }
-    cur.lmask |= s;
-    cur.items.push_back(e);
+    rest.swap(keep);
   }
-  close();
   return out;
 }
 

@@ -22,6 +22,7 @@ __all__ = [
     "make_integrals",
     "uccsd_excitations",
     "make_thetas",
+    "magnitude_order",
     "fragment_orbitals",
     "fragment_integrals",
     "delocalizing_rotation",
@@ -104,6 +105,42 @@ def make_thetas(n_exc: int, seed: int, scale: float, batch: int | None = None):
     for b in range(batch):
         out[b] = np.random.default_rng(seed + b).uniform(-scale, scale, size=n_exc)
     return out
+
+
+def magnitude_order(h1, h2, n_elec: int, exc) -> np.ndarray:
+    """Permutation of the excitation list into decreasing magnitude of a first-order estimate
+    of each amplitude (the magnitude ordering the paper's circuits use, Sec. 2.3): singles
+    f_ai / (f_ii - f_aa), doubles <ij||ab> / (f_ii + f_jj - f_aa - f_bb), with the Fock
+    matrix of the reference f_pq = h_pq + sum_{k occupied} (<pk|qk> - <pk|kq>) in spin
+    orbitals (<pq|rs> = (pr|qs) for matching spins).  Equal magnitudes keep the list order.
+    Apply as exc[perm] (and theta[perm])."""
+    exc = np.asarray(exc)
+    ns = h1.shape[0]
+    n = 2 * ns
+    sp = np.arange(n) // 2
+    sg = np.arange(n) % 2
+
+    def g(p, q, r, s_):  # <pq|rs> in spin orbitals
+        if sg[p] != sg[r] or sg[q] != sg[s_]:
+            return 0.0
+        return h2[sp[p], sp[r], sp[q], sp[s_]]
+
+    f = np.zeros((n, n))
+    for p in range(n):
+        for q in range(n):
+            v = h1[sp[p], sp[q]] if sg[p] == sg[q] else 0.0
+            for k in range(n_elec):
+                v += g(p, k, q, k) - g(p, k, k, q)
+            f[p, q] = v
+    est = np.empty(len(exc))
+    for m, (i, j, a, b) in enumerate(exc):
+        if j < 0:
+            num, den = f[a, i], f[i, i] - f[a, a]
+        else:
+            num = g(i, j, a, b) - g(i, j, b, a)
+            den = f[i, i] + f[j, j] - f[a, a] - f[b, b]
+        est[m] = abs(num) / max(abs(den), 1e-8)
+    return np.argsort(-est, kind="stable")
 
 
 # ---------------------------------------------------------------- fragment systems

@@ -9,7 +9,7 @@ import numpy as np
 import pytest
 
 from oracle import dense, hamiltonian, fermion, ansatz
-from paper_2402_17993_amd import ucc
+from paper_2402_17993_amd import inputs, ucc
 from paper_2402_17993_amd.inputs import make_integrals, uccsd_excitations
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
@@ -184,6 +184,7 @@ def test_pass_plan_covers_everything_in_order(n, ne, kf, ke, kr, ss, stored):
     K = len(exc)
     assert np.array_equal(np.concatenate([p["items"] for p in fwd]), np.arange(K))
     assert np.array_equal(np.concatenate([p["items"] for p in rev]), np.arange(K)[::-1])
+    check_commuting_reorder(np.concatenate([p["items"] for p in fwd]), np.arange(K), et["supp"])
     for group, k, c0 in ((fwd, info["tile_qubits"], info["contiguous_fwd"]),
                          (rev, info["tile_qubits_rev"], info["contiguous_rev"])):
         for p in group:
@@ -202,6 +203,40 @@ def test_pass_plan_covers_everything_in_order(n, ne, kf, ke, kr, ss, stored):
         assert bin(p["local"]).count("1") == info["tile_qubits_exp"]
         for gi in p["items"]:
             assert int(gt["x"][gi]) & ~p["local"] == 0
+
+
+def check_commuting_reorder(applied, listed, supp):
+    """applied is a permutation of listed in which every pair of factors whose order changed
+    acts on disjoint spin orbitals (so the product is unchanged)."""
+    applied, listed = np.asarray(applied), np.asarray(listed)
+    assert np.array_equal(np.sort(applied), np.sort(listed))
+    pos = {int(e): i for i, e in enumerate(applied)}
+    for x in range(len(listed)):
+        for y in range(x + 1, len(listed)):
+            a, b = int(listed[x]), int(listed[y])
+            if pos[a] > pos[b]:
+                assert int(supp[a]) & int(supp[b]) == 0, (a, b)
+
+
+@pytest.mark.parametrize("n,ne,kw", [(12, 8, dict(tile_qubits=8, tile_qubits_rev=8)),
+                                     (16, 8, dict(store_states=2)), (16, 8, dict(store_states=1))])
+def test_windows_of_a_magnitude_ordered_list(n, ne, kw):
+    # a scattered Trotter order: windows may take later factors ahead of earlier ones they
+    # commute with; the applied sequence is then a commuting rearrangement of the list
+    h1, h2 = make_integrals(n // 2, 0)
+    exc = uccsd_excitations(n, ne)
+    exc = exc[inputs.magnitude_order(h1, h2, ne, exc)]
+    ctx = ucc.Context(n, ne, h1, h2, exc, host_only=True, **kw)
+    passes = ctx.pass_table()
+    et = ctx.excitation_table()
+    fwd = np.concatenate([p["items"] for p in passes if p["kind"] == 0])
+    rev = np.concatenate([p["items"] for p in passes if p["kind"] == 2])
+    K = len(exc)
+    assert not np.array_equal(fwd, np.arange(K))  # something was moved
+    check_commuting_reorder(fwd, np.arange(K), et["supp"])
+    check_commuting_reorder(rev, np.arange(K)[::-1], et["supp"])
+    if ctx.plan_info()["store_states"]:
+        assert np.array_equal(rev, fwd[::-1])
 
 
 # ---------------------------------------------------------------- serving (host side)
