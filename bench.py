@@ -123,6 +123,57 @@ def single_latency(ucc, torch, n, ne, reps=30):
             "passes_fwd_exp_rev": [info["n_fwd_passes"], info["n_exp_passes"], info["n_rev_passes"]]}
 
 
+def paper_shaped(ucc, torch, reps=20):
+    """Systems of the paper's dimer sizes under Jordan-Wigner (its SCBKT counts plus the two
+    tapered qubits): 10 spatial orbitals / 16 electrons (the 18-qubit (FH)3 dimers of Table 4,
+    20 qubits here) and 11 / 16 (the 20-qubit (FH)2-H2O dimer timed on a DGX H100, 22 qubits
+    here).  Synthetic integrals (seed 0) and amplitudes U(-0.05, 0.05) (seed 1); per size the
+    median time of one energy (the paper's function evaluation) and of one energy + gradient,
+    B = 1, and E + grad evals/s at batch 16.  The paper's per-evaluation times (6.5-6.6 s and
+    12.1 s, whole job or VQE part) are context only: other hardware, other integrals."""
+    from paper_2402_17993_amd.inputs import make_integrals, make_thetas, uccsd_excitations
+
+    out = {}
+    for ns, ne in ((10, 16), (11, 16)):
+        n = 2 * ns
+        h1, h2 = make_integrals(ns, 0)
+        exc = uccsd_excitations(n, ne)
+        t0 = time.perf_counter()
+        ctx = ucc.Context(n, ne, h1, h2, exc, device=0, max_batch=16)
+        build_s = time.perf_counter() - t0
+        th = torch.tensor(make_thetas(len(exc), 1, 0.05), device="cuda:0", dtype=torch.float64)
+        thb = torch.tensor(make_thetas(len(exc), 1, 0.05, batch=16), device="cuda:0",
+                           dtype=torch.float64)
+        res = {"n_qubits": n, "n_elec": ne, "n_exc": len(exc), "plan_build_s": build_s}
+        for name, fn in (("energy", lambda: ctx.energy(th)), ("energy_grad", lambda: ctx.energy_grad(th))):
+            for _ in range(2):
+                fn()
+            torch.cuda.synchronize()
+            ts = []
+            for _ in range(reps):
+                a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                a.record()
+                fn()
+                b.record()
+                b.synchronize()
+                ts.append(a.elapsed_time(b))
+            res[f"{name}_ms_p50"] = float(np.percentile(ts, 50))
+        ctx.energy_grad(thb)
+        torch.cuda.synchronize()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        for _ in range(3):
+            ctx.energy_grad(thb)
+        b.record()
+        b.synchronize()
+        res["batch16_evals_per_s"] = 16 * 3 / (a.elapsed_time(b) * 1e-3)
+        info = ctx.plan_info()
+        res["passes_fwd_exp_rev"] = [info["n_fwd_passes"], info["n_exp_passes"], info["n_rev_passes"]]
+        ctx.close()
+        out[f"{n}q_{ne}e"] = res
+    return out
+
+
 def large_state(ucc, torch, n=26, ne=14):
     """One E + grad evaluation of a 1 GiB state (26 qubits, 14 electrons, K = 2478), integrals
     from seed 0, theta ~ U(-0.05, 0.05) from seed 1; per-kind HIP-event times and the
@@ -544,6 +595,7 @@ def main():
         out["latency_B1"] = {f"{n}q": single_latency(ucc, torch, n, ne)
                              for n, ne in ((8, 4), (12, 8), (16, 8))}
         out["large_26q"] = large_state(ucc, torch)
+        out["paper_shaped_dimers"] = paper_shaped(ucc, torch)
         out["trotter_variants_18q_b64"] = trotter_variants(ucc, torch, h1, h2, exc, thetas)
         out["trotter_free_18q_b64"] = trotter_free(ucc, torch, h1, h2, exc, thetas)
         out["size_consistency_h8"] = size_consistency(ucc)
