@@ -73,6 +73,25 @@ def copy_calibration(gib):
     print(json.dumps({"copy_bytes_read": n * 8, "copy_bytes_written": n * 8, "launches": 3}))
 
 
+def copy_rate(torch, gib=1.0, reps=5):
+    """GB/s of a plain device-to-device copy (bytes read + written over the event time): what
+    the memory system sustains for pure streaming on this device, beside the 8 TB/s peak."""
+    n = int(gib * 2 ** 30) // 8
+    a = torch.ones(n, dtype=torch.float64, device="cuda:0")
+    b = torch.empty_like(a)
+    b.copy_(a)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        b.copy_(a)
+    e1.record()
+    e1.synchronize()
+    rate = 2 * n * 8 * reps / (e0.elapsed_time(e1) * 1e-3) / 1e9
+    del a, b
+    return rate
+
+
 def one_at_a_time(ctx, td):
     """The plain path: one ucc_energy_grad call per theta vector (B = 1), device-resident."""
     import torch
@@ -582,7 +601,8 @@ def main():
         "ms_per_step_with_event_probes": 1e3 * wall / args.steps,
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                     "avg_launch_ms": avg_ms, "algorithmic_bytes_per_launch": bytes_per_launch},
+                     "avg_launch_ms": avg_ms, "algorithmic_bytes_per_launch": bytes_per_launch,
+                     "device_copy_GBps": copy_rate(torch)},
         "kernels": {k: {"launches": v["launches"], "ms": v["ms"],
                         "GBps": (v["bytes"] / (v["ms"] * 1e-3) / 1e9) if v["ms"] else None}
                     for k, v in stats.items() if v["launches"]},
