@@ -345,6 +345,27 @@ def size_consistency(ucc, iters=400, lr=0.1):
                 "dE_fci_kcal_trotterized": (e0 - 2 * efci) * kcal,
                 "dE_fci_kcal_trotter_free": (ef - 2 * efci) * kcal,
                 "dE_fci_kcal_trotterized_reoptimized": (float(r["energies"][-1]) - 2 * efci) * kcal}
+    # the Trotter-free rows of Table 6: the monomer optimized by steepest descent on central
+    # differences (h = 1e-5) of Trotter-free energies, all 2K + 1 of a step in one batched
+    # call; the dimers at that optimum carried over (LMO) and rotated (CMO)
+    K = len(exc_m)
+    thf = np.array(th_m)
+    hstep = 1e-5
+    X = np.empty((2 * K + 1, K))
+    for _ in range(iters):
+        X[:] = thf
+        X[1:K + 1] += hstep * np.eye(K)
+        X[K + 1:] -= hstep * np.eye(K)
+        Ef = mono.energy_trotter_free(X)
+        thf = thf - lr * (Ef[1:K + 1] - Ef[K + 1:]) / (2 * hstep)
+    emf_opt = float(mono.energy_trotter_free(thf)[0])
+    thf_d = {"LMO": inputs.embed_amplitudes(exc_m, [thf, thf], 2, 4, 2, exc_d)}
+    thf_d["CMO"] = inputs.rotate_amplitudes(exc_d, thf_d["LMO"], U)
+    out["trotter_free_vqe"] = {
+        "monomer_dE_fci_kcal": (emf_opt - efci) * kcal,
+        **{f"dimer_{k}_dE_fci_kcal": (float(ctx[k].energy_trotter_free(thf_d[k])[0]) - 2 * efci) * kcal
+           for k in ctx},
+        "steps": iters, "fd_step": hstep}
     # Sec. 3.2 (Table S3, Fig. 3): the delocalized dimer re-optimized by VQE with M = 1..5
     # slices of Eq. 5 and with Eq. 6 (all jobs at once on the server), their energies against
     # FCI, the fit E = alpha (1/M)^beta + gamma over M, and the Trotter-free energy at the
