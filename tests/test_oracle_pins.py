@@ -581,3 +581,29 @@ def test_p21_trotter_free_is_size_consistent_and_orbital_invariant():
     # the Trotterized product is additive with localized orbitals only
     assert abs(e["LMO"][0] - 2 * em_t) < 1e-12
     assert abs(e["CMO"][0] - 2 * em_t) > 1e-4
+
+
+def test_p22_trotter_free_gradient():
+    # central differences of expm_multiply energies; at theta = 0 the Slater-Condon gradient
+    # (both ansaetze start as |HF> + sum_k theta_k G_k|HF>); for pairwise commuting
+    # excitations the Trotterized gradient
+    n, ne = 8, 4
+    _, _, h, g = system(4, ne, seed=6)
+    exc = uccsd_excitations(n, ne)
+    th = make_thetas(len(exc), 21, 0.3)
+    e, gr = trotter_free.trotter_free_energy_and_gradient(h, g, n, hf_mask(ne), exc, th)
+    assert abs(e - trotter_free.trotter_free_energy(h, g, n, hf_mask(ne), exc, th)) < 1e-12
+    for k in range(len(exc)):
+        tp, tm = th.copy(), th.copy()
+        tp[k] += 1e-4
+        tm[k] -= 1e-4
+        fd = (trotter_free.trotter_free_energy(h, g, n, hf_mask(ne), exc, tp)
+              - trotter_free.trotter_free_energy(h, g, n, hf_mask(ne), exc, tm)) / 2e-4
+        assert abs(fd - gr[k]) < 1e-7, k
+    _, g0 = trotter_free.trotter_free_energy_and_gradient(h, g, n, hf_mask(ne), exc, np.zeros(len(exc)))
+    np.testing.assert_allclose(g0, closed_forms.gradient_at_zero(h, g, range(ne), exc), atol=1e-12)
+    exc_c = np.array([(0, -1, 4, -1), (1, -1, 5, -1), (2, 3, 6, 7)], dtype=np.int32)
+    th_c = np.array([0.7, -0.4, 1.1])
+    _, gf = trotter_free.trotter_free_energy_and_gradient(h, g, n, hf_mask(ne), exc_c, th_c)
+    _, gt = ansatz.energy_and_gradient(h, g, n, hf_mask(ne), exc_c, th_c)
+    np.testing.assert_allclose(gf, gt, atol=1e-12)
