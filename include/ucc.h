@@ -157,6 +157,20 @@ ucc_status ucc_energy_trotter_free(ucc_ctx* ctx, const double* theta, int32_t B,
                                    int32_t* terms, void* stream);
 
 /*
+ * ucc_energy_grad_trotter_free -- the Trotter-free energies and their gradients
+ * dE_b/dtheta_{b,k} (not in the paper, which optimizes this ansatz without gradients): the
+ * adjoint of the Chebyshev recurrence, reusing the forward series vectors.
+ *   grad   [B * n_exc] float64, host or device pointer
+ * Other arguments and errors as ucc_energy_trotter_free; the context additionally keeps the
+ * m + 1 series vectors of every entry (m the largest series degree of the call, about
+ * 1.4 sum_k |theta_k| + 30; 16 * 2^n bytes each per entry): UCC_ENOMEM if they do not fit.
+ * After the call the context holds |Psi_b> (ucc_get_state).
+ */
+ucc_status ucc_energy_grad_trotter_free(ucc_ctx* ctx, const double* theta, int32_t B,
+                                        double* energy, double* grad, int32_t* terms,
+                                        void* stream);
+
+/*
  * ucc_get_state -- copy state vector b held by the context to the host, in the logical
  * qubit order of this header (qubit q = bit q), as interleaved (re, im) pairs.
  *   re_im  host, [2 * 2^n_qubits] float64

@@ -65,8 +65,15 @@ struct GenSet {
   double2* y = nullptr;     // [cap][2^n]: the third Chebyshev vector (psi and lam hold the others)
   uint32_t* bank = nullptr; // [cap][tab.blob.size()]: value tables of each entry
   double* coef = nullptr;   // [cap][kChebMaxTerms + 1]
-  double* cfac = nullptr;   // [cap]: 2 / rho
+  double* cfac = nullptr;   // [2][cap]: 2 / rho, then -2 / rho
   int32_t* deg = nullptr;   // [cap]: series degree
+  // gradient calls: H Psi, identity (cos, sin), gradient sum, energies, the series vectors
+  double2* lam2 = nullptr;  // [cap][2^n]
+  double2* ics = nullptr;   // [cap][K]
+  double* gacc = nullptr;   // [cap][K]
+  double* esave = nullptr;  // [cap]
+  double2* ystore = nullptr;
+  size_t ystore_bytes = 0;
 };
 void free_gen(GenSet& g);
 

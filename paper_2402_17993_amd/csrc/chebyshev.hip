@@ -47,6 +47,7 @@ __global__ __launch_bounds__(64) void k_cheb_coef(const double* __restrict__ the
   if (threadIdx.x != 0) return;
   const double rho = fmax(part, kChebRhoMin);
   cfac[b] = 2.0 / rho;
+  cfac[B + b] = -2.0 / rho;  // the transposed generator -A of the adjoint sweep
   // degree: term_j = (rho/2)^j / j! bounds |J_j|; the tail after m = j - 1 is at most
   // 2 term_j / (1 - (rho/2) / (j + 1)) once (rho/2) / (j + 1) < 1/2
   const double h = 0.5 * rho;
@@ -137,6 +138,27 @@ __global__ void k_cheb_acc(double2* __restrict__ y, double2* __restrict__ F,
   }
 }
 
+__global__ void k_fill_zero(double2* __restrict__ v, size_t total) {
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < total;
+       i += (size_t)gridDim.x * blockDim.x)
+    st16(v + i, dvec2{0.0, 0.0});
+}
+
+__global__ void k_fill_identity_cs(double2* __restrict__ cs, size_t total) {
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < total;
+       i += (size_t)gridDim.x * blockDim.x)
+    cs[i] = make_double2(1.0, 0.0);
+}
+
+// gacc[b][k] += a_b * g[b][k], a_b = cfac[b] (or half of it: the first series term)
+__global__ void k_grad_acc(double* __restrict__ gacc, const double* __restrict__ g,
+                           const double* __restrict__ cfac, int half, int B, int K) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= B * K) return;
+  const double a = half ? 0.5 * cfac[i / K] : cfac[i / K];
+  gacc[i] += a * g[i];
+}
+
 inline int stream_grid(size_t total) {
   const size_t per = 256;
   const size_t want = (total + per - 1) / per;
@@ -173,6 +195,26 @@ hipError_t launch_cheb_acc(double2* y, double2* F, const double* coef, int cstri
   const int grid = stream_grid(size_t(B) << n);
   hipLaunchKernelGGL(k_cheb_acc, dim3(grid), dim3(256), 0, st, y, F, coef, cstride, deg, j, yscale, n,
                      B);
+  return hipGetLastError();
+}
+
+}  // namespace ucc
+
+namespace ucc {
+
+hipError_t launch_fill_zero(double2* v, size_t n, hipStream_t st) {
+  hipLaunchKernelGGL(k_fill_zero, dim3(stream_grid(n)), dim3(256), 0, st, v, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill_identity_cs(double2* cs, size_t n, hipStream_t st) {
+  hipLaunchKernelGGL(k_fill_identity_cs, dim3(stream_grid(n)), dim3(256), 0, st, cs, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_grad_acc(double* gacc, const double* g, const double* cfac, int half, int B, int K,
+                           hipStream_t st) {
+  hipLaunchKernelGGL(k_grad_acc, dim3((B * K + 255) / 256), dim3(256), 0, st, gacc, g, cfac, half, B, K);
   return hipGetLastError();
 }
 

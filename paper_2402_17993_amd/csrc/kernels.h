@@ -67,7 +67,7 @@ hipError_t launch_reduce(const LaunchArgs& a, int ne, bool grad, int nt);
 
 // Trotter-free evaluation (chebyshev.hip).  Chebyshev series of exp(A) with rho = max(sum_k
 // |theta_k|, kChebRhoMin) per entry, cut where the tail bound falls below kChebTol, at most
-// kChebMaxTerms terms; coef is [B][kChebMaxTerms + 1].
+// kChebMaxTerms terms; coef is [B][kChebMaxTerms + 1]; cfac is [2][B]: 2 / rho, then -2 / rho.
 constexpr double kChebRhoMin = 1.0 / 1024;
 constexpr double kChebTol = 1e-16;
 constexpr int kChebMaxTerms = 2048;
@@ -81,6 +81,12 @@ hipError_t launch_cheb_init(double2* y0, double2* y1, double2* F, const double* 
                             int n, uint32_t hf, int B, hipStream_t st);
 hipError_t launch_cheb_acc(double2* y, double2* F, const double* coef, int cstride, const int* deg,
                            int j, double yscale, int n, int B, hipStream_t st);
+// Adjoint sweep of the Trotter-free gradient: zero fill, identity (cos, sin) = (1, 0) for the
+// reverse passes used as pure partial-sum passes, and gacc += cfac[b] (x 1/2) * g.
+hipError_t launch_fill_zero(double2* v, size_t n, hipStream_t st);
+hipError_t launch_fill_identity_cs(double2* cs, size_t n, hipStream_t st);
+hipError_t launch_grad_acc(double* gacc, const double* g, const double* cfac, int half, int B, int K,
+                           hipStream_t st);
 // Whole evaluation of a one-tile plan in one launch (one 256-thread workgroup per entry).
 // fwd_state: the state written to psi is Psi(theta) also for gradient calls (else the state
 // the reverse sweep ends on).

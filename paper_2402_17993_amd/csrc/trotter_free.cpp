@@ -45,6 +45,12 @@ void free_gen_buffers(GenSet& g) {
   release(g.coef);
   release(g.cfac);
   release(g.deg);
+  release(g.lam2);
+  release(g.ics);
+  release(g.gacc);
+  release(g.esave);
+  release(g.ystore);
+  g.ystore_bytes = 0;
   g.cap = 0;
 }
 
@@ -103,8 +109,12 @@ ucc_status ensure_gen_buffers(ucc_ctx* c, int B) {
       {reinterpret_cast<void**>(&g.y), size_t(B) * S * 16},
       {reinterpret_cast<void**>(&g.bank), size_t(B) * g.tab.blob.size() * 4},
       {reinterpret_cast<void**>(&g.coef), size_t(B) * (kChebMaxTerms + 1) * 8},
-      {reinterpret_cast<void**>(&g.cfac), size_t(B) * 8},
+      {reinterpret_cast<void**>(&g.cfac), size_t(B) * 16},
       {reinterpret_cast<void**>(&g.deg), size_t(B) * 4},
+      {reinterpret_cast<void**>(&g.lam2), size_t(B) * S * 16},
+      {reinterpret_cast<void**>(&g.ics), size_t(B) * c->plan.K * 16},
+      {reinterpret_cast<void**>(&g.gacc), size_t(B) * c->plan.K * 8 + 16},
+      {reinterpret_cast<void**>(&g.esave), size_t(B) * 8},
   };
   for (auto& r : reqs) {
     e = hipMalloc(r.ptr, std::max<size_t>(r.bytes, 16));
@@ -117,11 +127,35 @@ ucc_status ensure_gen_buffers(ucc_ctx* c, int B) {
   return UCC_OK;
 }
 
+// Series vectors y_0 .. y_m of every entry, kept for the adjoint sweep of gradient calls.
+ucc_status ensure_ystore(ucc_ctx* c, int B, int m) {
+  GenSet& g = c->gen;
+  const size_t bytes = size_t(m + 1) * (size_t(B) << c->plan.n) * 16;
+  if (bytes <= g.ystore_bytes) return UCC_OK;
+  hipError_t e = hipDeviceSynchronize();
+  if (e != hipSuccess) return hip_fail(e, "hipDeviceSynchronize");
+  release(g.ystore);
+  g.ystore_bytes = 0;
+  e = hipMalloc(reinterpret_cast<void**>(&g.ystore), bytes);
+  if (e != hipSuccess) return hip_fail(e, "hipMalloc(series vectors)");
+  g.ystore_bytes = bytes;
+  return UCC_OK;
+}
+
 // The launch sequence of one Trotter-free call on stream st.  The series degree of each entry
 // is read back once (the number of generator products to launch); terms (host, nullable)
-// receives it.
+// receives it.  With grad, the energies end in gen.esave and dE/dtheta in gen.gacc (else the
+// energies in buf.E).
+//
+// Gradient (adjoint of the recurrence; the coefficients and rho are held fixed: the series
+// sums exp(A) whatever rho is, so its rho dependence is below the truncation tolerance):
+// with lambda = H F and mu_j = dE/dy_j / 2,
+//   mu_j = c_j lambda + (2/rho) A^T mu_{j+1} + mu_{j+2},  A^T = -A,
+//   dE/dtheta_k = sum_{j=0}^{m-1} a_j 2 <mu_{j+1}| G_k |y_j>,  a_j = 2/rho (1/rho for j = 0),
+// the inner products from the reverse passes run with cos = 1, sin = 0 (they leave both vectors
+// unchanged and produce exactly these partials), summed per term by k_reduce.
 ucc_status enqueue_trotter_free(ucc_ctx* c, const double* d_theta, int B, hipStream_t st,
-                                int32_t* terms) {
+                                int32_t* terms, bool grad) {
   const Plan& p = c->plan;
   GenSet& g = c->gen;
   Buffers& b = c->buf;
@@ -155,6 +189,15 @@ ucc_status enqueue_trotter_free(ucc_ctx* c, const double* d_theta, int B, hipStr
     m = std::max(m, deg[i]);
   }
   if (terms) std::copy(deg.begin(), deg.end(), terms);
+  if (grad) {
+    ucc_status s = ensure_ystore(c, B, m);
+    if (s != UCC_OK) return s;
+  }
+  const size_t BS = size_t(B) << p.n;
+  auto keep = [&](int j, const double2* y) -> hipError_t {  // y_j into the store
+    if (!grad) return hipSuccess;
+    return hipMemcpyAsync(g.ystore + size_t(j) * BS, y, BS * 16, hipMemcpyDeviceToDevice, st);
+  };
   const int nd = (int)(g.tab.blob.size() / 2);
   e = timed(UCC_KERNEL_CHEB, 16.0 * B * nd, [&] {
     return launch_gen_values(g.d_blob, g.d_map, nd, d_theta, p.K, g.cfac, g.bank, B, st);
@@ -188,6 +231,12 @@ ucc_status enqueue_trotter_free(ucc_ctx* c, const double* d_theta, int B, hipStr
       return launch_cheb_acc(y, F, g.coef, cstride, g.deg, j, yscale, p.n, B, st);
     });
   };
+  // dst += c_j y for entries with j <= their degree
+  auto acc2 = [&](const double2* y, double2* dst, int j) {
+    return timed(UCC_KERNEL_CHEB, 3 * S, [&] {
+      return launch_cheb_acc(const_cast<double2*>(y), dst, g.coef, cstride, g.deg, j, 1.0, p.n, B, st);
+    });
+  };
   int seq = 0;
   // dst (+)= (2 / rho) A src over the generator's passes (first: the first pass writes dst);
   // term > 0: dst is series term `term`, added into F by the last pass (or a sweep after it)
@@ -209,27 +258,74 @@ ucc_status enqueue_trotter_free(ucc_ctx* c, const double* d_theta, int B, hipStr
     }
     return hipSuccess;
   };
-  if (m >= 1) {
+  e = keep(0, y0);
+  if (e == hipSuccess && m >= 1) {
     e = apply(y0, y1, true, 0);  // y1 = (2 / rho) A y0 = 2 y_1
     if (e == hipSuccess) e = acc(y1, 1, 0.5);
+    if (e == hipSuccess) e = keep(1, y1);
     for (int j = 2; j <= m && e == hipSuccess; ++j) {
       e = apply(y1, y0, false, j);  // y0 = y_{j-2} + (2 / rho) A y_{j-1} = y_j, F += c_j y_j
+      if (e == hipSuccess) e = keep(j, y0);
       std::swap(y0, y1);
     }
-    if (e != hipSuccess) return hip_fail(e, "launch Chebyshev term");
   }
+  if (e != hipSuccess) return hip_fail(e, "launch Chebyshev term");
 
-  // E = <F|H|F> on the context's own expectation passes
+  // E = <F|H|F> on the context's own expectation passes (gradient calls: apply-H passes, which
+  // also leave lambda = H F)
   LaunchArgs h = make_args(c, b, B, st);
   const int nte = 1 << (p.n - p.ke);
+  if (grad) {
+    h.lam = g.lam2;
+    e = launch_fill_zero(g.lam2, BS, st);  // lambda is written on the N / S_z sector only
+    if (e != hipSuccess) return hip_fail(e, "launch k_fill_zero");
+  }
   for (int j = 0; j < p.nexp; ++j, ++seq) {
     h.flip = seq & 1;
-    e = timed(UCC_KERNEL_EXP, S, [&] { return launch_exp(h, p.nfwd + j, j * nte, j == 0, false); });
+    e = timed(grad ? UCC_KERNEL_APPLYH : UCC_KERNEL_EXP, grad ? S + (j == 0 ? sec : 2 * sec) : S,
+              [&] { return launch_exp(h, p.nfwd + j, j * nte, j == 0, grad); });
     if (e != hipSuccess) return hip_fail(e, "launch k_exp");
   }
   e = timed(UCC_KERNEL_REDUCE, 8.0 * B * p.nexp * nte,
             [&] { return launch_reduce(h, p.nexp * nte, false, 1 << (p.n - p.kr)); });
   if (e != hipSuccess) return hip_fail(e, "launch k_reduce");
+  if (!grad) return UCC_OK;
+
+  // ---- adjoint sweep
+  e = hipMemcpyAsync(g.esave, b.E, size_t(B) * 8, hipMemcpyDeviceToDevice, st);
+  double2* p1 = b.lam;  // mu_{j+1}
+  double2* p2 = g.y;    // mu_{j+2}
+  if (e == hipSuccess) e = launch_fill_zero(p1, BS, st);
+  if (e == hipSuccess) e = launch_fill_zero(p2, BS, st);
+  if (e == hipSuccess) e = launch_fill_zero(reinterpret_cast<double2*>(g.gacc), (size_t(B) * p.K + 1) / 2, st);
+  if (e == hipSuccess) e = launch_fill_identity_cs(g.ics, size_t(B) * p.K, st);
+  // the generator's values with -2 / rho: A^T
+  if (e == hipSuccess)
+    e = launch_gen_values(g.d_blob, g.d_map, nd, d_theta, p.K, g.cfac + B, g.bank, B, st);
+  if (e != hipSuccess) return hip_fail(e, "launch adjoint set-up");
+  ga.cfac = g.cfac + B;
+  LaunchArgs r = make_args(c, b, B, st);
+  r.cs = g.ics;
+  const int ntr = 1 << (p.n - p.kr);
+  for (int j = m; j >= 1; --j) {
+    if (j < m) e = apply(p1, p2, false, 0);  // mu_{j+2} - (2 / rho) A mu_{j+1}
+    if (e == hipSuccess) e = acc2(g.lam2, p2, j);  // + c_j lambda = mu_j
+    if (e != hipSuccess) return hip_fail(e, "launch adjoint term");
+    // 2 <mu_j| G_k |y_{j-1}> for every k, then times a_{j-1}
+    r.lam = p2;
+    double2* yj = g.ystore + size_t(j - 1) * BS;
+    for (int i = 0; i < p.nrev; ++i, ++seq) {
+      r.flip = seq & 1;
+      e = timed(UCC_KERNEL_REV, p.ckpt ? 3 * S : 4 * S,
+                [&] { return launch_rev(r, p.nfwd + p.nexp + i, yj, !p.ckpt); });
+      if (e != hipSuccess) return hip_fail(e, "launch k_rev");
+    }
+    e = timed(UCC_KERNEL_REDUCE, 8.0 * B * double(p.seq.size()) * ntr,
+              [&] { return launch_reduce(r, p.nexp * nte, true, ntr); });
+    if (e == hipSuccess) e = launch_grad_acc(g.gacc, b.G, g.cfac, j == 1, B, p.K, st);
+    if (e != hipSuccess) return hip_fail(e, "launch gradient sum");
+    std::swap(p1, p2);
+  }
   return UCC_OK;
 }
 
@@ -269,13 +365,49 @@ ucc_status ucc_energy_trotter_free(ucc_ctx* c, const double* theta, int32_t B, d
     if (e != hipSuccess) return hip_fail(e, "copy theta");
     d_theta = c->buf.theta;
   }
-  s = enqueue_trotter_free(c, d_theta, B, st, terms);
+  s = enqueue_trotter_free(c, d_theta, B, st, terms, false);
   if (s != UCC_OK) return s;
   const bool host_e = !is_device_ptr(energy);
   e = hipMemcpyAsync(energy, c->buf.E, B * sizeof(double),
                      host_e ? hipMemcpyDeviceToHost : hipMemcpyDeviceToDevice, st);
   if (e == hipSuccess && host_e) e = hipStreamSynchronize(st);
   if (e != hipSuccess) return hip_fail(e, "copy energy");
+  c->last_B = B;
+  return UCC_OK;
+}
+
+ucc_status ucc_energy_grad_trotter_free(ucc_ctx* c, const double* theta, int32_t B,
+                                        double* energy, double* grad, int32_t* terms,
+                                        void* stream) {
+  g_last_error.clear();
+  if (!c) return fail(UCC_EINVAL, "ctx is NULL");
+  if (c->host_only) return fail(UCC_EINVAL, "context was built host_only");
+  if (B < 1 || B > 65535) return fail(UCC_EINVAL, "B must be in [1, 65535]");
+  if (!theta || !energy || !grad) return fail(UCC_EINVAL, "NULL output or input");
+  if (c->busy) return fail(UCC_EBUSY, "context is in use by a server job");
+  hipError_t e = hipSetDevice(c->device);
+  if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
+  ucc_status s = ensure_buffers(c, c->buf, B, true);
+  if (s == UCC_OK) s = ensure_gen_plan(c, true);
+  if (s == UCC_OK) s = ensure_gen_buffers(c, B);
+  if (s != UCC_OK) return s;
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  const size_t tb = size_t(B) * c->plan.K * sizeof(double);
+  const double* d_theta = theta;
+  if (!is_device_ptr(theta)) {
+    e = hipMemcpyAsync(c->buf.theta, theta, tb, hipMemcpyHostToDevice, st);
+    if (e != hipSuccess) return hip_fail(e, "copy theta");
+    d_theta = c->buf.theta;
+  }
+  s = enqueue_trotter_free(c, d_theta, B, st, terms, true);
+  if (s != UCC_OK) return s;
+  const bool host_e = !is_device_ptr(energy), host_g = !is_device_ptr(grad);
+  e = hipMemcpyAsync(energy, c->gen.esave, B * sizeof(double),
+                     host_e ? hipMemcpyDeviceToHost : hipMemcpyDeviceToDevice, st);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(grad, c->gen.gacc, tb, host_g ? hipMemcpyDeviceToHost : hipMemcpyDeviceToDevice, st);
+  if (e == hipSuccess && (host_e || host_g)) e = hipStreamSynchronize(st);
+  if (e != hipSuccess) return hip_fail(e, "copy energy and gradient");
   c->last_B = B;
   return UCC_OK;
 }

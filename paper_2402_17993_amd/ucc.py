@@ -23,7 +23,8 @@ STATUS_CODES = {v: k for k, v in STATUS.items()}
 
 EXPORTED = [
     "ucc_default_options", "ucc_build", "ucc_energy", "ucc_energy_grad",
-    "ucc_energy_trotter_free", "ucc_get_generator_passes", "ucc_fmo2_energy", "ucc_get_state",
+    "ucc_energy_trotter_free", "ucc_energy_grad_trotter_free", "ucc_get_generator_passes",
+    "ucc_fmo2_energy", "ucc_get_state",
     "ucc_destroy", "ucc_last_error", "ucc_get_plan_info", "ucc_batch_compatible",
     "ucc_get_pauli_terms",
     "ucc_get_group_table", "ucc_get_excitation_table", "ucc_get_pass_table",
@@ -84,6 +85,7 @@ def lib():
         "ucc_energy": (_i32, [_vp, _vp, _i32, _vp, _vp]),
         "ucc_energy_grad": (_i32, [_vp, _vp, _i32, _vp, _vp, _vp]),
         "ucc_energy_trotter_free": (_i32, [_vp, _vp, _i32, _vp, _vp, _vp]),
+        "ucc_energy_grad_trotter_free": (_i32, [_vp, _vp, _i32, _vp, _vp, _vp, _vp]),
         "ucc_get_generator_passes": (_i32, [_vp, _i32, _vp, _vp, _P(_i32)]),
         "ucc_fmo2_energy": (_i32, [_i32, _vp, _vp, _P(_dbl)]),
         "ucc_get_state": (_i32, [_vp, _i32, _vp]),
@@ -228,6 +230,36 @@ class Context:
             check(L.ucc_energy_trotter_free(self._h, _ptr(th), B, _ptr(E), _ptr(terms), st),
                   "ucc_energy_trotter_free")
         return (E, terms) if return_terms else E
+
+    def energy_grad_trotter_free(self, theta, stream=None, return_terms=False):
+        """(E [B], dE/dtheta [B, K]) of the Trotter-free ansatz by the adjoint of the series;
+        with return_terms also the series terms used per entry."""
+        L = lib()
+        if _is_torch_cuda(theta):
+            import torch
+            th = theta.detach().to(torch.float64).contiguous()
+            B = th.numel() // self.n_exc
+            if th.numel() != B * self.n_exc or B < 1:
+                raise ValueError("theta must hold B * n_exc amplitudes")
+            E = torch.empty(B, dtype=torch.float64, device=th.device)
+            G = torch.empty(B, self.n_exc, dtype=torch.float64, device=th.device)
+            terms = np.zeros(B, dtype=np.int32)
+            st = stream if stream is not None else torch.cuda.current_stream(th.device).cuda_stream
+            check(L.ucc_energy_grad_trotter_free(self._h, _vp(th.data_ptr()), B, _vp(E.data_ptr()),
+                                                 _vp(G.data_ptr()), _ptr(terms), _vp(st)),
+                  "ucc_energy_grad_trotter_free")
+        else:
+            th = np.ascontiguousarray(theta, dtype=np.float64)
+            B = th.size // self.n_exc
+            if th.size != B * self.n_exc or B < 1:
+                raise ValueError("theta must hold B * n_exc amplitudes")
+            E = np.empty(B)
+            G = np.empty((B, self.n_exc))
+            terms = np.zeros(B, dtype=np.int32)
+            st = _vp(stream) if stream is not None else None
+            check(L.ucc_energy_grad_trotter_free(self._h, _ptr(th), B, _ptr(E), _ptr(G), _ptr(terms), st),
+                  "ucc_energy_grad_trotter_free")
+        return (E, G, terms) if return_terms else (E, G)
 
     def generator_passes(self):
         """(local masks [n_passes] uint32, pass of each excitation [n_exc] int32) of the

@@ -127,3 +127,48 @@ def test_torch_pointers_and_errors(ucc):
     # the context still works afterwards
     assert np.array_equal(ctx.energy_trotter_free(th), e_np)
     ctx.close()
+
+
+@pytest.mark.parametrize("n,ne,kw,scale,ks", [
+    (8, 4, {}, 0.5, None),
+    (12, 8, dict(tile_qubits_exp=8, tile_qubits=8, tile_qubits_rev=8), 0.2, None),
+    (12, 4, dict(store_states=2, block_threads=512), 0.3, None),
+    (16, 8, {}, 0.05, [0, 7, 41, 200, 359]),
+])
+def test_gradient_against_oracle(ucc, n, ne, kw, scale, ks):
+    say(f"case: Trotter-free gradient {n}q/{ne}e {kw} scale {scale}")
+    h1, h2, h, g, exc = system(n, ne, seed=n + 1)
+    ctx = ucc.Context(n, ne, h1, h2, exc, **kw)
+    ths = np.stack([make_thetas(len(exc), 50 + i, scale) for i in range(2)])
+    E, G = ctx.energy_grad_trotter_free(ths)
+    e_only = ctx.energy_trotter_free(ths)
+    for b, th in enumerate(ths):
+        e_ref, g_ref = trotter_free.trotter_free_energy_and_gradient(h, g, n, (1 << ne) - 1, exc, th,
+                                                                    ks=ks)
+        assert abs(E[b] - e_ref) <= E_TOL and abs(E[b] - e_only[b]) <= 1e-12
+        sel = np.arange(len(exc)) if ks is None else np.array(ks)
+        assert np.max(np.abs(G[b][sel] - g_ref[sel])) <= 1e-9, (b, np.max(np.abs(G[b][sel] - g_ref[sel])))
+    # entry 1 alone gives the same gradient bitwise
+    E1, G1 = ctx.energy_grad_trotter_free(ths[1])
+    assert E1[0] == E[1] and np.array_equal(G1[0], G[1])
+    ctx.close()
+
+
+def test_18q_gradient_central_differences(ucc):
+    # full size: components against central differences of the device's own energies
+    say("case: Trotter-free gradient 18q/10e against central differences of GPU energies")
+    n, ne = 18, 10
+    h1, h2, h, g, exc = system(n, ne, seed=0)
+    th = make_thetas(len(exc), 1, 0.05)
+    ctx = ucc.Context(n, ne, h1, h2, exc)
+    _, G = ctx.energy_grad_trotter_free(th)
+    ks = [0, 13, 77, 300, 559]
+    hstep = 1e-4
+    X = np.tile(th, (2 * len(ks), 1))
+    for i, k in enumerate(ks):
+        X[2 * i, k] += hstep
+        X[2 * i + 1, k] -= hstep
+    Ef = ctx.energy_trotter_free(X)
+    fd = (Ef[0::2] - Ef[1::2]) / (2 * hstep)
+    assert np.max(np.abs(fd - G[0][ks])) <= 1e-7, (fd, G[0][ks])
+    ctx.close()
