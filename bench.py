@@ -285,10 +285,22 @@ def trotter_free(ucc, torch, h1, h2, exc, thetas, steps=5):
     b.synchronize()
     st = ctx.profile_read(reset=True)
     local, _ = ctx.generator_passes()
+    # energies and gradients (adjoint of the series)
+    ctx.energy_grad_trotter_free(td)
+    torch.cuda.synchronize()
+    ctx.profile(False)
+    a2, b2 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a2.record()
+    for _ in range(steps):
+        ctx.energy_grad_trotter_free(td)
+    b2.record()
+    b2.synchronize()
+    eg_ms = a2.elapsed_time(b2) / steps
     ctx.close()
     ms = a.elapsed_time(b) / steps
     byt = sum(v["bytes"] for v in st.values()) / steps
     return {"energies_per_s": BATCH / (ms * 1e-3), "ms_per_batch": ms,
+            "energy_grad_per_s": BATCH / (eg_ms * 1e-3), "energy_grad_ms_per_batch": eg_ms,
             "terms_min_mean_max": [int(terms.min()), float(terms.mean()), int(terms.max())],
             "generator_passes": int(len(local)),
             "GBps": byt / (ms * 1e-3) / 1e9, "frac": byt / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
@@ -345,19 +357,13 @@ def size_consistency(ucc, iters=400, lr=0.1):
                 "dE_fci_kcal_trotterized": (e0 - 2 * efci) * kcal,
                 "dE_fci_kcal_trotter_free": (ef - 2 * efci) * kcal,
                 "dE_fci_kcal_trotterized_reoptimized": (float(r["energies"][-1]) - 2 * efci) * kcal}
-    # the Trotter-free rows of Table 6: the monomer optimized by steepest descent on central
-    # differences (h = 1e-5) of Trotter-free energies, all 2K + 1 of a step in one batched
-    # call; the dimers at that optimum carried over (LMO) and rotated (CMO)
-    K = len(exc_m)
+    # the Trotter-free rows of Table 6: the monomer optimized by steepest descent with the
+    # adjoint Trotter-free gradient; the dimers at that optimum carried over (LMO) and rotated
+    # (CMO)
     thf = np.array(th_m)
-    hstep = 1e-5
-    X = np.empty((2 * K + 1, K))
     for _ in range(iters):
-        X[:] = thf
-        X[1:K + 1] += hstep * np.eye(K)
-        X[K + 1:] -= hstep * np.eye(K)
-        Ef = mono.energy_trotter_free(X)
-        thf = thf - lr * (Ef[1:K + 1] - Ef[K + 1:]) / (2 * hstep)
+        _, gf = mono.energy_grad_trotter_free(thf)
+        thf = thf - lr * gf[0]
     emf_opt = float(mono.energy_trotter_free(thf)[0])
     thf_d = {"LMO": inputs.embed_amplitudes(exc_m, [thf, thf], 2, 4, 2, exc_d)}
     thf_d["CMO"] = inputs.rotate_amplitudes(exc_d, thf_d["LMO"], U)
@@ -365,7 +371,7 @@ def size_consistency(ucc, iters=400, lr=0.1):
         "monomer_dE_fci_kcal": (emf_opt - efci) * kcal,
         **{f"dimer_{k}_dE_fci_kcal": (float(ctx[k].energy_trotter_free(thf_d[k])[0]) - 2 * efci) * kcal
            for k in ctx},
-        "steps": iters, "fd_step": hstep}
+        "steps": iters}
     # Sec. 3.2 (Table S3, Fig. 3): the delocalized dimer re-optimized by VQE with M = 1..5
     # slices of Eq. 5 and with Eq. 6 (all jobs at once on the server), their energies against
     # FCI, the fit E = alpha (1/M)^beta + gamma over M, and the Trotter-free energy at the
