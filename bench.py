@@ -410,7 +410,8 @@ def size_consistency(ucc, iters=400, lr=0.1):
 
 
 def cpu_small():
-    """The oracle per E + grad evaluation at 8 and 16 qubits (one thread)."""
+    """The oracle per E + grad evaluation at 8 and 16 qubits, and per Trotter-free energy at 16
+    qubits (one thread)."""
     from threadpoolctl import threadpool_limits
 
     from oracle import ansatz, hamiltonian
@@ -426,6 +427,15 @@ def cpu_small():
             h, g = hamiltonian.spin_orbital_integrals(h1, h2)
             ansatz.energy_and_gradient(h, g, n, (1 << ne) - 1, exc, th)
             out[f"{n}q_s_per_eval"] = time.perf_counter() - t0
+        # the Trotter-free energy as the paper computes it (expm_multiply), 16 qubits
+        from oracle import trotter_free
+        h1, h2 = make_integrals(8, 0)
+        exc = uccsd_excitations(16, 8)
+        th = make_thetas(len(exc), 1, 0.05)
+        h, g = hamiltonian.spin_orbital_integrals(h1, h2)
+        t0 = time.perf_counter()
+        trotter_free.trotter_free_energy(h, g, 16, 0xFF, exc, th)
+        out["16q_trotter_free_s_per_energy"] = time.perf_counter() - t0
     return out
 
 
