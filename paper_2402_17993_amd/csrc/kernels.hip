@@ -352,11 +352,15 @@ __device__ __forceinline__ void put_tile_loop(uint32_t lmask, uint32_t tileN, co
 // a Givens rotation on the excitation's pairs.  One wave (wave 0) applies them all: the LDS
 // operations of a wave take effect in issue order, so excitation e+1 reads what excitation e
 // wrote without a workgroup barrier, and the pairs of one excitation are disjoint, so no two
-// lanes touch the same amplitude within one excitation.  The other waves return at once; the
-// caller synchronizes the workgroup before cp is read again.
+// lanes touch the same amplitude within one excitation.  Every LDS operation of an excitation
+// is issued by all 64 lanes (lanes without a pair use a sink), so the number of operations
+// in flight is known when the code is compiled and the chain waits for its reads by count,
+// never for the previous excitation's writes.  The other waves return at once; the caller
+// synchronizes the workgroup before cp is read again.
 template <int T>
 __device__ __forceinline__ void fwd_excitations(double2* cp, const uint32_t* blk, const double2* scs,
                                                 int count) {
+  __shared__ double2 sink[1];  // written and read by lanes without a pair; never used
   if (threadIdx.x >= 64) return;
   const int lane = threadIdx.x;
   const uint32_t* off = blk + 2;
@@ -373,17 +377,17 @@ __device__ __forceinline__ void fwd_excitations(double2* cp, const uint32_t* blk
     const bool has = ia < cur.i1;
     const uint32_t ru = e0 & 0x7fffu, rw = e0 >> 16;
     const double sg0 = (e0 & 0x8000u) ? -s : s;
-    // reads without branches (rank 0 where the lane has no pair; results unused there)
-    const double2 a = cp[has ? ru : 0u], bb = cp[has ? rw : 0u];
+    // reads and writes without branches: a lane without a pair reads and writes the sink
+    double2* pa = has ? cp + ru : sink;
+    double2* pb = has ? cp + rw : sink;
+    const double2 a = *pa, bb = *pb;
     // ahead: the next excitation's first entry, the one after's range (clamped to the last
     // excitation, whose values are then loaded again and not used)
     const uint32_t e0n = first_entry(nxt, ent, lane);
     ExcRange nn;
     nn.load(scs, off, min(e + 2, count - 1));
-    if (has) {
-      cp[ru] = make_double2(c * a.x - sg0 * bb.x, c * a.y - sg0 * bb.y);
-      cp[rw] = make_double2(c * bb.x + sg0 * a.x, c * bb.y + sg0 * a.y);
-    }
+    *pa = make_double2(c * a.x - sg0 * bb.x, c * a.y - sg0 * bb.y);
+    *pb = make_double2(c * bb.x + sg0 * a.x, c * bb.y + sg0 * a.y);
     for (int i = ia + 64; i < cur.i1; i += 64) {
       const uint32_t en = ent[i];
       const uint32_t qu = en & 0x7fffu, qw = en >> 16;
@@ -406,6 +410,7 @@ __device__ __forceinline__ void fwd_excitations(double2* cp, const uint32_t* blk
 template <int T>
 __device__ __forceinline__ void rev_excitations(double2* cp, double2* cl, const uint32_t* blk,
                                                 const double2* scs, int count, double* gq) {
+  __shared__ double2 sink[1];  // written and read by lanes without a pair; never used
   if (threadIdx.x >= 64) return;
   const int lane = threadIdx.x;
   const uint32_t* off = blk + 2;
@@ -422,21 +427,22 @@ __device__ __forceinline__ void rev_excitations(double2* cp, double2* cl, const 
     const bool has = ia < cur.i1;
     const uint32_t ru = e0 & 0x7fffu, rw = e0 >> 16;
     const bool neg0 = (e0 & 0x8000u) != 0u;
-    const uint32_t su = has ? ru : 0u, sw = has ? rw : 0u;
-    const double2 pu = cp[su], pw = cp[sw], lu = cl[su], lw = cl[sw];
+    // reads and writes without branches: a lane without a pair reads and writes the sink
+    double2* qpu = has ? cp + ru : sink;
+    double2* qpw = has ? cp + rw : sink;
+    double2* qlu = has ? cl + ru : sink;
+    double2* qlw = has ? cl + rw : sink;
+    const double2 pu = *qpu, pw = *qpw, lu = *qlu, lw = *qlw;
     const uint32_t e0n = first_entry(nxt, ent, lane);
     ExcRange nn;
     nn.load(scs, off, min(e + 2, count - 1));
-    double g = 0.0;
-    if (has) {
-      const double t = (lw.x * pu.x + lw.y * pu.y) - (lu.x * pw.x + lu.y * pw.y);
-      g = neg0 ? -t : t;
-      const double sq = neg0 ? -s : s;
-      cp[ru] = make_double2(c * pu.x + sq * pw.x, c * pu.y + sq * pw.y);
-      cp[rw] = make_double2(c * pw.x - sq * pu.x, c * pw.y - sq * pu.y);
-      cl[ru] = make_double2(c * lu.x + sq * lw.x, c * lu.y + sq * lw.y);
-      cl[rw] = make_double2(c * lw.x - sq * lu.x, c * lw.y - sq * lu.y);
-    }
+    const double t = (lw.x * pu.x + lw.y * pu.y) - (lu.x * pw.x + lu.y * pw.y);
+    double g = has ? (neg0 ? -t : t) : 0.0;
+    const double sq = neg0 ? -s : s;
+    *qpu = make_double2(c * pu.x + sq * pw.x, c * pu.y + sq * pw.y);
+    *qpw = make_double2(c * pw.x - sq * pu.x, c * pw.y - sq * pu.y);
+    *qlu = make_double2(c * lu.x + sq * lw.x, c * lu.y + sq * lw.y);
+    *qlw = make_double2(c * lw.x - sq * lu.x, c * lw.y - sq * lu.y);
     for (int i = ia + 64; i < cur.i1; i += 64) {
       const uint32_t en = ent[i];
       const uint32_t qu = en & 0x7fffu, qw = en >> 16;
@@ -450,8 +456,9 @@ __device__ __forceinline__ void rev_excitations(double2* cp, double2* cl, const 
       cl[qu] = make_double2(c * bu.x + sq * bw.x, c * bu.y + sq * bw.y);
       cl[qw] = make_double2(c * bw.x - sq * bu.x, c * bw.y - sq * bu.y);
     }
+    // the four lanes of a quad hold the same sum (the adds commute exactly) and all write it
     g = quad_sum(g);
-    if ((lane & 3) == 0) gq[(lane >> 2) * kGqStride + e] = g;
+    gq[(lane >> 2) * kGqStride + e] = g;
     cur = nxt;
     nxt = nn;
     e0 = e0n;
