@@ -977,7 +977,6 @@ __global__ __launch_bounds__(T) LDS_BOUND_OCCUPANCY void k_exp(
   uint32_t* blk = reinterpret_cast<uint32_t*>(red + 16);
   uint16_t* rtab = reinterpret_cast<uint16_t*>(blk + ps.stage_len);
   const uint32_t* bw = reinterpret_cast<const uint32_t*>(lb);
-  const double* dw = reinterpret_cast<const double*>(lb);
   const TL tm(ps.lmask);
   int item = blockIdx.x;
   if (item >= total) return;
@@ -1013,7 +1012,6 @@ __global__ __launch_bounds__(T) LDS_BOUND_OCCUPANCY void k_exp(
   stage_blob(ent(item));
   stage_class(base_of(item));  // its barriers also publish the value table
   if (RP) tm.fetch(r, vec_of(item), base_of(item));
-  const int sub = threadIdx.x & 3;
   for (;;) {
     const int b = ent(item);
     const uint32_t t = item & tmask;
@@ -1432,7 +1430,8 @@ hipError_t rev_overlapped(const LaunchArgs& a, int pidx, double2* psi, bool* use
     const int k = hp.k;
     const int ntiles = 1 << (a.n - k);
     const size_t lds = sc_lds(hp, 4);
-    const size_t stat = sizeof(DevExc) * kMaxPassExc + 2 * 16 * kMaxPassExc + 8 * kGqWords;
+    // static LDS: excitation records, two (cos, sin) stages, quad partials, the chain's sink
+    const size_t stat = sizeof(DevExc) * kMaxPassExc + 2 * 16 * kMaxPassExc + 8 * kGqWords + 16;
     if (lds + stat > (size_t)kLdsBytes) return hipSuccess;
     hipError_t e = set_lds(k_rev2<T, KT, WP>, lds);
     if (e != hipSuccess) return e;
