@@ -529,7 +529,7 @@ def main():
         return
     if args.gpus != 1:
         print("bench.py measures one GPU: the workload shards by independent theta vectors and "
-              "fragment jobs, and this build runs on a single MI355X; use --gpus 1.",
+              "fragment jobs (one process per GPU); this benchmark drives a single MI355X; use --gpus 1.",
               file=sys.stderr)
         sys.exit(2)
 
