@@ -465,6 +465,32 @@ __device__ __forceinline__ void rev_excitations(double2* cp, double2* cl, const 
   }
 }
 
+// The per-quad partials of rev_excitations for a pass whose rotations are the identity, with
+// the excitations shared among NW waves (wave w: e = w, w + NW, ...) and cp, cl only read.
+// Lane l of a wave sums the pairs i0 + l, i0 + l + 64, ... of an excitation in the order the
+// chain does, so each quad's partial is the chain's.
+template <int NW>
+__device__ __forceinline__ void rev_partials_only(const double2* cp, const double2* cl,
+                                                  const uint32_t* blk, int count, double* gq, int w,
+                                                  int lane) {
+  const uint32_t* off = blk + 2;
+  const int m = (int)blk[1], ns = (int)blk[0];
+  const uint32_t* ent = blk + 3 + m + ((ns + 1) >> 1) + ns;
+  for (int e = w; e < count; e += NW) {  // the same for every lane of the wave
+    const int i1 = (int)off[e + 1];
+    double g = 0.0;
+    for (int i = (int)off[e] + lane; i < i1; i += 64) {
+      const uint32_t en = ent[i];
+      const uint32_t qu = en & 0x7fffu, qw = en >> 16;
+      const double2 au = cp[qu], aw = cp[qw], bu = cl[qu], bw = cl[qw];
+      const double t = (bw.x * au.x + bw.y * au.y) - (bu.x * aw.x + bu.y * aw.y);
+      g += (en & 0x8000u) ? -t : t;
+    }
+    g = quad_sum(g);
+    gq[(lane >> 2) * kGqStride + e] = g;
+  }
+}
+
 // Tile partial of <lambda|G_k|psi> for the pass's excitation e: the 16 quad partials in a
 // fixed order, times the tile's sign of the excitation.
 __device__ __forceinline__ double rev_partial(const double* gq, int e, const DevExc& x, uint32_t base) {
@@ -860,7 +886,13 @@ __global__ __launch_bounds__(T) LDS_BOUND_OCCUPANCY void k_rev(
 // excitation chain instead of around it.  The same class block and rank table serve both
 // slots.  A producer thread writes and then reads the same tile elements, hence the same LDS
 // ranks, so the two steps need no synchronization between threads.
-template <int T, int KT, bool WP>
+// GONLY (a sweep whose rotations are all the identity, as in the adjoint of the Trotter-free
+// series): only the gradient partials are computed.  Every wave of the lower half takes
+// excitations w, w + P/64, ... of the pass, its lanes take the pairs as the chain does and each
+// quad's partial goes to gq, so the partials are those of the chain with (cos, sin) = (1, 0);
+// a wave writes gpart for its own excitations only (its own LDS writes, read back in issue
+// order).  Nothing is written back to HBM.
+template <int T, int KT, bool WP, bool GONLY = false>
 __global__ __launch_bounds__(T) LDS_BOUND_OCCUPANCY void k_rev2(
     const DevPass* __restrict__ passes, int pidx, const DevExc* __restrict__ exc,
     const int2* __restrict__ pcls, const uint32_t* __restrict__ pairs,
@@ -899,8 +931,9 @@ __global__ __launch_bounds__(T) LDS_BOUND_OCCUPANCY void k_rev2(
   // producers: item `it` into slot s (its (cos, signed sin), then psi, then lambda)
   auto read_item = [&](int it, int s) {
     const uint32_t base = base_of(it);
-    for (int e = (int)tm.tid; e < ps.count; e += P)
-      scs[s][e] = signed_cs(cs[(size_t)ent(it) * K + sx[e].k], sx[e], base);
+    if (!GONLY)
+      for (int e = (int)tm.tid; e < ps.count; e += P)
+        scs[s][e] = signed_cs(cs[(size_t)ent(it) * K + sx[e].k], sx[e], base);
     typename TL::Buf r;
     tm.refresh();
     tm.fetch(r, psi + off_of(it), base);
@@ -921,7 +954,16 @@ __global__ __launch_bounds__(T) LDS_BOUND_OCCUPANCY void k_rev2(
   for (;;) {
     const int slot = j & 1;
     const int next = item + gridDim.x;
-    if (threadIdx.x < 64) {
+    if (GONLY && !prod) {
+      constexpr int NW = P / 64;
+      const int lane = (int)threadIdx.x & 63, w = (int)threadIdx.x >> 6;
+      rev_partials_only<NW>(cpb + slot * ns_max, clb + slot * ns_max, blk, ps.count, gq, w, lane);
+      const uint32_t base = base_of(item);
+      const int b = ent(item);
+      const uint32_t t = item & tmask;
+      for (int e = w + NW * lane; e < ps.count; e += NW * 64)
+        gpart[((size_t)b * L + sx[e].occ) * ntiles + t] = rev_partial(gq, e, sx[e], base);
+    } else if (!GONLY && threadIdx.x < 64) {
       rev_excitations<T>(cpb + slot * ns_max, clb + slot * ns_max, blk, scs[slot], ps.count, gq);
       // the chain's partials are this wave's own LDS writes: read back in issue order
       const uint32_t base = base_of(item);
@@ -930,7 +972,7 @@ __global__ __launch_bounds__(T) LDS_BOUND_OCCUPANCY void k_rev2(
       for (int e = threadIdx.x; e < ps.count; e += 64)
         gpart[((size_t)b * L + sx[e].occ) * ntiles + t] = rev_partial(gq, e, sx[e], base);
     } else if (prod) {
-      if (j > 0) write_item(item - (int)gridDim.x, slot ^ 1);
+      if (!GONLY && j > 0) write_item(item - (int)gridDim.x, slot ^ 1);
       if (next < total) read_item(next, slot ^ 1);
     }
     __syncthreads();  // item j applied; item j + 1 read; item j - 1 written
@@ -938,7 +980,7 @@ __global__ __launch_bounds__(T) LDS_BOUND_OCCUPANCY void k_rev2(
     item = next;
     ++j;
   }
-  if (prod) write_item(item, j & 1);
+  if (!GONLY && prod) write_item(item, j & 1);
 }
 
 // Expectation / apply-H pass.  Only in-sector basis states can be non-zero.  For every
@@ -1420,7 +1462,7 @@ hipError_t fwd_t(const LaunchArgs& a, int pidx, int init, const double2* src, do
 
 // The overlapped reverse pass needs every workgroup to keep one tile (a grid that is a
 // multiple of the tile count), register staging and room for two LDS slots.
-template <int T, int KT, bool WP>
+template <int T, int KT, bool WP, bool GONLY = false>
 hipError_t rev_overlapped(const LaunchArgs& a, int pidx, double2* psi, bool* used) {
   *used = false;
   if constexpr (T < 512 || KT == 0) {
@@ -1433,12 +1475,13 @@ hipError_t rev_overlapped(const LaunchArgs& a, int pidx, double2* psi, bool* use
     // static LDS: excitation records, two (cos, sin) stages, quad partials, the chain's sink
     const size_t stat = sizeof(DevExc) * kMaxPassExc + 2 * 16 * kMaxPassExc + 8 * kGqWords + 16;
     if (lds + stat > (size_t)kLdsBytes) return hipSuccess;
-    hipError_t e = set_lds(k_rev2<T, KT, WP>, lds);
+    hipError_t e = set_lds(k_rev2<T, KT, WP, GONLY>, lds);
     if (e != hipSuccess) return e;
     const int total = a.B << (a.n - k);
-    const int grid = pass_grid(total, resident_grid(k_rev2<T, KT, WP>, T, lds, a.cu_share), ntiles);
+    const int grid =
+        pass_grid(total, resident_grid(k_rev2<T, KT, WP, GONLY>, T, lds, a.cu_share), ntiles);
     if (grid < ntiles || grid % ntiles != 0) return hipSuccess;
-    hipLaunchKernelGGL((k_rev2<T, KT, WP>), dim3(grid), dim3(T), lds, a.stream, a.passes, pidx,
+    hipLaunchKernelGGL((k_rev2<T, KT, WP, GONLY>), dim3(grid), dim3(T), lds, a.stream, a.passes, pidx,
                        a.exc, a.cls, a.pairs, a.cs, a.K, psi, a.lam, a.n, a.amask, a.bmask,
                        a.gpart, a.L, total, a.flip);
     *used = true;
@@ -1449,7 +1492,9 @@ hipError_t rev_overlapped(const LaunchArgs& a, int pidx, double2* psi, bool* use
 template <int T, int KT, bool WP>
 hipError_t rev_tw(const LaunchArgs& a, int pidx, double2* psi) {
   bool used = false;
-  hipError_t e0 = rev_overlapped<T, KT, WP>(a, pidx, psi, &used);
+  // partials only: psi and lambda are left as they are (the identity rotations change nothing)
+  hipError_t e0 = a.gonly ? rev_overlapped<T, KT, false, true>(a, pidx, psi, &used)
+                          : rev_overlapped<T, KT, WP>(a, pidx, psi, &used);
   if (e0 != hipSuccess || used) return e0;
   const DevPass& hp = a.hpasses[pidx];
   const int k = hp.k;

@@ -152,8 +152,9 @@ ucc_status ensure_ystore(ucc_ctx* c, int B, int m) {
 // with lambda = H F and mu_j = dE/dy_j / 2,
 //   mu_j = c_j lambda + (2/rho) A^T mu_{j+1} + mu_{j+2},  A^T = -A,
 //   dE/dtheta_k = sum_{j=0}^{m-1} a_j 2 <mu_{j+1}| G_k |y_j>,  a_j = 2/rho (1/rho for j = 0),
-// the inner products from the reverse passes run with cos = 1, sin = 0 (they leave both vectors
-// unchanged and produce exactly these partials), summed per term by k_reduce.
+// the inner products from the reverse windows run with cos = 1, sin = 0 (they leave both vectors
+// unchanged and produce exactly these partials) in their partials-only form (no rotations, no
+// write-back; the plain form runs where it does not apply), summed per term by k_reduce.
 ucc_status enqueue_trotter_free(ucc_ctx* c, const double* d_theta, int B, hipStream_t st,
                                 int32_t* terms, bool grad) {
   const Plan& p = c->plan;
@@ -306,6 +307,7 @@ ucc_status enqueue_trotter_free(ucc_ctx* c, const double* d_theta, int B, hipStr
   ga.cfac = g.cfac + B;
   LaunchArgs r = make_args(c, b, B, st);
   r.cs = g.ics;
+  r.gonly = true;
   const int ntr = 1 << (p.n - p.kr);
   for (int j = m; j >= 1; --j) {
     if (j < m) e = apply(p1, p2, false, 0);  // mu_{j+2} - (2 / rho) A mu_{j+1}
@@ -316,8 +318,8 @@ ucc_status enqueue_trotter_free(ucc_ctx* c, const double* d_theta, int B, hipStr
     double2* yj = g.ystore + size_t(j - 1) * BS;
     for (int i = 0; i < p.nrev; ++i, ++seq) {
       r.flip = seq & 1;
-      e = timed(UCC_KERNEL_REV, p.ckpt ? 3 * S : 4 * S,
-                [&] { return launch_rev(r, p.nfwd + p.nexp + i, yj, !p.ckpt); });
+      // bytes of the partials-only form: y_{j-1} and mu_j read, nothing written
+      e = timed(UCC_KERNEL_REV, 2 * S, [&] { return launch_rev(r, p.nfwd + p.nexp + i, yj, !p.ckpt); });
       if (e != hipSuccess) return hip_fail(e, "launch k_rev");
     }
     e = timed(UCC_KERNEL_REDUCE, 8.0 * B * double(p.seq.size()) * ntr,
