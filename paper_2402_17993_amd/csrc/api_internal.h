@@ -61,6 +61,14 @@ struct GenSet {
   uint32_t* d_blob = nullptr;  // value-table template (unit values)
   int32_t* d_cls = nullptr;
   int32_t* d_map = nullptr;
+  // partials-only reverse windows of the adjoint (build_partials_plan) and their device tables
+  int kp = -1;  // reverse tile size they were planned with (-1: not built)
+  Plan pplan;
+  Tables ptab;
+  DevPass* d_ppasses = nullptr;
+  DevExc* d_pexc = nullptr;
+  uint32_t* d_ppairs = nullptr;
+  int32_t* d_pcls = nullptr;
   int cap = 0;
   double2* y = nullptr;     // [cap][2^n]: the third Chebyshev vector (psi and lam hold the others)
   uint32_t* bank = nullptr; // [cap][tab.blob.size()]: value tables of each entry

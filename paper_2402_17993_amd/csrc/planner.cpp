@@ -771,6 +771,68 @@ std::string build_generator_plan(const Plan& p, Plan& g, int k, int c0) {
   return "";
 }
 
+// Windows of the partials-only reverse passes (the adjoint of the Trotter-free series, whose
+// reverse windows run with identity rotations): the factors then do not act on each other, so
+// their order is free.  Scanning the factors in list order, every window takes each
+// remaining factor whose support still fits k local bits (the low c0 bits of the reverse plan
+// included); a window whose largest class block would not fit the overlapped pass's LDS next
+// to its two slots of (psi, lambda), the rank table and the kernel's static arrays is halved.
+std::string build_partials_plan(const Plan& p, Plan& q) {
+  q = p;
+  const int k = p.kr;
+  const uint32_t F = (1u << p.c0r) - 1u;
+  const int L = (int)p.seq.size();
+  std::vector<int> rest(L);
+  for (int t = 0; t < L; ++t) rest[t] = t;
+  std::vector<Plan::Pass> ws;
+  while (!rest.empty()) {
+    Plan::Pass cur;
+    cur.kind = kRev;
+    cur.lmask = F;
+    std::vector<int> keep;
+    keep.reserve(rest.size());
+    for (int e : rest) {
+      const uint32_t s = p.ex[p.seq[e]].supp;
+      if (pc32(cur.lmask | s) <= k && (int)cur.items.size() < kMaxPassExc) {
+        cur.items.push_back(e);
+        cur.lmask |= s;
+      } else {
+        keep.push_back(e);
+      }
+    }
+    if (cur.items.empty()) return "tile too small for the support of one excitation";
+    cur.lmask = pad_mask(cur.lmask, k, p.n);
+    ws.push_back(cur);
+    rest.swap(keep);
+  }
+  const long stat = long(sizeof(DevExc)) * kMaxPassExc + 32L * kMaxPassExc + 8L * kGqWords + 16;
+  std::vector<Plan::Pass> out;
+  std::vector<Plan::Pass> todo(ws.rbegin(), ws.rend());
+  while (!todo.empty()) {
+    Plan::Pass w = todo.back();
+    todo.pop_back();
+    const int ns = max_class_size(p, w.lmask);
+    if (ns >= 32768) return "tile too large for the pair lists of one excitation";
+    const long budget_words = (long(kLdsBytes) - (2L << pc32(w.lmask)) - 64L * ns - stat) / 4 - 4;
+    if (max_pair_block_words(p, w.lmask, w.items) <= budget_words) {
+      out.push_back(w);
+      continue;
+    }
+    if (w.items.size() < 2) return "tile too large for the pair lists of one excitation";
+    Plan::Pass a = w, b = w;
+    const size_t h = w.items.size() / 2;
+    a.items.assign(w.items.begin(), w.items.begin() + h);
+    b.items.assign(w.items.begin() + h, w.items.end());
+    todo.push_back(b);
+    todo.push_back(a);
+  }
+  q.passes = out;
+  q.nfwd = 0;
+  q.nexp = 0;
+  q.nrev = (int)out.size();
+  return "";
+}
+
 std::vector<int32_t> generator_value_map(const Plan& g, const Tables& t) {
   std::vector<int32_t> map(t.blob.size() / 2, -1);
   for (size_t i = 0; i < g.passes.size(); ++i) {

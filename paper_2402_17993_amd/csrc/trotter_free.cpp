@@ -60,6 +60,10 @@ void free_gen_tables(GenSet& g) {
   release(g.d_blob);
   release(g.d_cls);
   release(g.d_map);
+  release(g.d_ppasses);
+  release(g.d_pexc);
+  release(g.d_ppairs);
+  release(g.d_pcls);
 }
 
 // Host plan and tables of the generator for the context's expectation tile size (and, with
@@ -80,6 +84,22 @@ ucc_status ensure_gen_plan(ucc_ctx* c, bool upload) {
     build_tables(g.plan, g.tab);
     g.map = generator_value_map(g.plan, g.tab);
     g.ke = p.ke;
+    g.kp = -1;
+  }
+  if (g.kp != p.kr) {  // the reverse tile changes without the expectation tile in a re-plan
+    if (!c->host_only && g.d_ppasses) {
+      hipError_t e = hipDeviceSynchronize();
+      if (e != hipSuccess) return hip_fail(e, "hipDeviceSynchronize");
+    }
+    release(g.d_ppasses);
+    release(g.d_pexc);
+    release(g.d_ppairs);
+    release(g.d_pcls);
+    const std::string msg = build_partials_plan(p, g.pplan);
+    if (!msg.empty()) return fail(UCC_EINVAL, msg);
+    g.ptab = Tables();
+    build_tables(g.pplan, g.ptab);
+    g.kp = p.kr;
   }
   if (upload && !g.d_passes) {
     hipError_t e;
@@ -90,6 +110,16 @@ ucc_status ensure_gen_plan(ucc_ctx* c, bool upload) {
         (e = upload_vec(&g.d_map, g.map)) != hipSuccess) {
       free_gen_tables(g);
       return hip_fail(e, "generator table upload");
+    }
+  }
+  if (upload && !g.d_ppasses) {
+    hipError_t e;
+    if ((e = upload_vec(&g.d_ppasses, g.ptab.passes)) != hipSuccess ||
+        (e = upload_vec(&g.d_pexc, g.ptab.exc)) != hipSuccess ||
+        (e = upload_vec(&g.d_ppairs, g.ptab.pairs)) != hipSuccess ||
+        (e = upload_vec(&g.d_pcls, g.ptab.cls)) != hipSuccess) {
+      free_gen_tables(g);
+      return hip_fail(e, "partials table upload");
     }
   }
   return UCC_OK;
@@ -305,9 +335,16 @@ ucc_status enqueue_trotter_free(ucc_ctx* c, const double* d_theta, int B, hipStr
     e = launch_gen_values(g.d_blob, g.d_map, nd, d_theta, p.K, g.cfac + B, g.bank, B, st);
   if (e != hipSuccess) return hip_fail(e, "launch adjoint set-up");
   ga.cfac = g.cfac + B;
+  // the partials-only passes run over the order-free windows of g.pplan (same tile, same
+  // factors, fewer windows than the Trotter order allows)
   LaunchArgs r = make_args(c, b, B, st);
   r.cs = g.ics;
   r.gonly = true;
+  r.passes = g.d_ppasses;
+  r.hpasses = g.ptab.passes.data();
+  r.exc = g.d_pexc;
+  r.pairs = g.d_ppairs;
+  r.cls = reinterpret_cast<const int2*>(g.d_pcls);
   const int ntr = 1 << (p.n - p.kr);
   for (int j = m; j >= 1; --j) {
     if (j < m) e = apply(p1, p2, false, 0);  // mu_{j+2} - (2 / rho) A mu_{j+1}
@@ -316,10 +353,10 @@ ucc_status enqueue_trotter_free(ucc_ctx* c, const double* d_theta, int B, hipStr
     // 2 <mu_j| G_k |y_{j-1}> for every k, then times a_{j-1}
     r.lam = p2;
     double2* yj = g.ystore + size_t(j - 1) * BS;
-    for (int i = 0; i < p.nrev; ++i, ++seq) {
+    for (int i = 0; i < g.pplan.nrev; ++i, ++seq) {
       r.flip = seq & 1;
       // bytes of the partials-only form: y_{j-1} and mu_j read, nothing written
-      e = timed(UCC_KERNEL_REV, 2 * S, [&] { return launch_rev(r, p.nfwd + p.nexp + i, yj, !p.ckpt); });
+      e = timed(UCC_KERNEL_REV, 2 * S, [&] { return launch_rev(r, i, yj, !p.ckpt); });
       if (e != hipSuccess) return hip_fail(e, "launch k_rev");
     }
     e = timed(UCC_KERNEL_REDUCE, 8.0 * B * double(p.seq.size()) * ntr,
@@ -337,6 +374,7 @@ void free_gen(GenSet& g) {
   free_gen_buffers(g);
   free_gen_tables(g);
   g.ke = -1;
+  g.kp = -1;
 }
 
 }  // namespace ucc

@@ -193,6 +193,9 @@ void build_tables(const Plan& p, Tables& t);
 // occupation rows, no diagonal group), covered by expectation passes of k local bits.  g gets
 // the groups and passes of p's excitations; build_tables(g, ...) compiles it.
 std::string build_generator_plan(const Plan& p, Plan& g, int k, int c0);
+// Order-free windows (tile p.kr) for reverse passes whose rotations are the identity; every
+// factor of p.seq in exactly one window.  q: a copy of p with only these reverse passes.
+std::string build_partials_plan(const Plan& p, Plan& q);
 // Per double of the compiled generator's value tables: the excitation whose unit value
 // (+-sigma_k) the double holds, or -1 for words that do not depend on theta.
 std::vector<int32_t> generator_value_map(const Plan& g, const Tables& t);
