@@ -271,6 +271,20 @@ ucc_status ucc_get_pass_table(const ucc_ctx* ctx, int32_t* kind, uint32_t* local
 ucc_status ucc_get_generator_passes(ucc_ctx* ctx, int32_t cap, uint32_t* local, int32_t* exc_pass,
                                     int32_t* n_passes);
 
+/*
+ * ucc_get_partials_passes -- the windows of the partials-only reverse passes that the
+ * Trotter-free gradient runs after every series term (built on first use; also on host_only
+ * contexts).  Their rotations are the identity, so the factors' order is free: every factor
+ * of the Trotter product sits in exactly one window of tile_qubits_rev local qubits.
+ *   cap          capacity of local[]
+ *   local        nullable [cap]: physical local-qubit mask of each window
+ *   factor_pass  nullable [L]: the window that holds factor o (L as in ucc_get_pass_table)
+ *   n_passes     receives the window count
+ * Errors: UCC_EINVAL (NULL ctx or n_passes, cap too small for local).
+ */
+ucc_status ucc_get_partials_passes(ucc_ctx* ctx, int32_t cap, uint32_t* local, int32_t* factor_pass,
+                                   int32_t* n_passes);
+
 /* ---------------------------------------------------------------- fragments */
 
 /*

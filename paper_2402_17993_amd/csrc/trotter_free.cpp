@@ -469,4 +469,21 @@ ucc_status ucc_get_generator_passes(ucc_ctx* c, int32_t cap, uint32_t* local, in
   return UCC_OK;
 }
 
+ucc_status ucc_get_partials_passes(ucc_ctx* c, int32_t cap, uint32_t* local, int32_t* factor_pass,
+                                   int32_t* n_passes) {
+  g_last_error.clear();
+  if (!c || !n_passes) return fail(UCC_EINVAL, "NULL argument");
+  ucc_status s = ensure_gen_plan(c, false);
+  if (s != UCC_OK) return s;
+  const Plan& q = c->gen.pplan;
+  *n_passes = q.nrev;
+  if (local && cap < q.nrev) return fail(UCC_EINVAL, "cap is smaller than the pass count");
+  for (int i = 0; i < q.nrev; ++i) {
+    if (local) local[i] = q.passes[i].lmask;
+    if (factor_pass)
+      for (int o : q.passes[i].items) factor_pass[o] = i;
+  }
+  return UCC_OK;
+}
+
 }  // extern "C"

@@ -24,6 +24,7 @@ STATUS_CODES = {v: k for k, v in STATUS.items()}
 EXPORTED = [
     "ucc_default_options", "ucc_build", "ucc_energy", "ucc_energy_grad",
     "ucc_energy_trotter_free", "ucc_energy_grad_trotter_free", "ucc_get_generator_passes",
+    "ucc_get_partials_passes",
     "ucc_fmo2_energy", "ucc_get_state",
     "ucc_destroy", "ucc_last_error", "ucc_get_plan_info", "ucc_batch_compatible",
     "ucc_get_pauli_terms",
@@ -87,6 +88,7 @@ def lib():
         "ucc_energy_trotter_free": (_i32, [_vp, _vp, _i32, _vp, _vp, _vp]),
         "ucc_energy_grad_trotter_free": (_i32, [_vp, _vp, _i32, _vp, _vp, _vp, _vp]),
         "ucc_get_generator_passes": (_i32, [_vp, _i32, _vp, _vp, _P(_i32)]),
+        "ucc_get_partials_passes": (_i32, [_vp, _i32, _vp, _vp, _P(_i32)]),
         "ucc_fmo2_energy": (_i32, [_i32, _vp, _vp, _P(_dbl)]),
         "ucc_get_state": (_i32, [_vp, _i32, _vp]),
         "ucc_destroy": (None, [_vp]),
@@ -272,6 +274,21 @@ class Context:
         where = np.full(self.n_exc, -1, dtype=np.int32)
         check(L.ucc_get_generator_passes(self._h, n.value, _ptr(local), _ptr(where), ctypes.byref(n)),
               "ucc_get_generator_passes")
+        return local[: n.value], where
+
+    def partials_passes(self):
+        """(local masks [n_windows] uint32, window of each factor [L] int32) of the order-free
+        windows of the Trotter-free gradient's partials-only reverse passes."""
+        L = lib()
+        n = ctypes.c_int32()
+        check(L.ucc_get_partials_passes(self._h, 0, None, None, ctypes.byref(n)),
+              "ucc_get_partials_passes")
+        info = self.plan_info()
+        nf = self.n_exc * info["trotter_steps"] * info["trotter_order"]
+        local = np.zeros(max(n.value, 1), dtype=np.uint32)
+        where = np.full(nf, -1, dtype=np.int32)
+        check(L.ucc_get_partials_passes(self._h, n.value, _ptr(local), _ptr(where), ctypes.byref(n)),
+              "ucc_get_partials_passes")
         return local[: n.value], where
 
     def state(self, b=0):

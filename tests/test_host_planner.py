@@ -340,6 +340,29 @@ def test_generator_plan_covers_every_excitation_once(n, ne, kw):
     ctx.close()
 
 
+@pytest.mark.parametrize("n,ne,kw", [(8, 4, {}), (12, 8, dict(tile_qubits=8, tile_qubits_rev=8)),
+                                     (12, 4, dict(store_states=2, tile_qubits_rev=9)),
+                                     (16, 8, dict(trotter_steps=2)), (18, 10, {})])
+def test_partials_windows_hold_every_factor_once(n, ne, kw):
+    # the Trotter-free gradient's partials-only reverse passes: order-free windows of the
+    # reverse tile, every factor of the product in exactly one, inside its local qubits
+    ctx, _, _, exc = host_ctx(n, ne, **kw)
+    local, where = ctx.partials_passes()
+    info = ctx.plan_info()
+    t = ctx.excitation_table()
+    L = len(exc) * info["trotter_steps"] * info["trotter_order"]
+    assert len(where) == L and np.all(where >= 0) and np.all(where < len(local))
+    for m in local:
+        assert bin(int(m)).count("1") == info["tile_qubits_rev"]
+    for o, w in enumerate(where):
+        assert int(t["supp"][o % len(exc)]) & ~int(local[w]) == 0
+    # never more windows than the Trotter-ordered reverse sweep
+    assert 1 <= len(local) <= info["n_rev_passes"]
+    if (n, ne) == (18, 10):
+        assert len(local) < info["n_rev_passes"]
+    ctx.close()
+
+
 # ---------------------------------------------------------------- FMO two-body energy (Eq. 1)
 
 def test_fmo2_energy_assembly():
