@@ -133,6 +133,8 @@ def test_torch_pointers_and_errors(ucc):
     (8, 4, {}, 0.5, None),
     (12, 8, dict(tile_qubits_exp=8, tile_qubits=8, tile_qubits_rev=8), 0.2, None),
     (12, 4, dict(store_states=2, block_threads=512), 0.3, None),
+    # 256-thread reverse workgroups: the partials passes take the plain (chain) form
+    (12, 8, dict(block_threads_rev=256), 0.2, None),
     (16, 8, {}, 0.05, [0, 7, 41, 200, 359]),
 ])
 def test_gradient_against_oracle(ucc, n, ne, kw, scale, ks):
