@@ -69,6 +69,8 @@ struct GenSet {
   DevExc* d_pexc = nullptr;
   uint32_t* d_ppairs = nullptr;
   int32_t* d_pcls = nullptr;
+  uint32_t* d_sec = nullptr;  // [nsec]: physical indices of the N / S_z sector's basis states
+  int nsec = 0;
   int cap = 0;
   double2* y = nullptr;     // [cap][2^n]: the third Chebyshev vector (psi and lam hold the others)
   uint32_t* bank = nullptr; // [cap][tab.blob.size()]: value tables of each entry
@@ -80,8 +82,9 @@ struct GenSet {
   double2* ics = nullptr;   // [cap][K]
   double* gacc = nullptr;   // [cap][K]
   double* esave = nullptr;  // [cap]
-  double2* ystore = nullptr;
+  double2* ystore = nullptr;  // in-sector amplitudes only are written; the rest is zero
   size_t ystore_bytes = 0;
+  int ystore_B = -1;  // batch size of the slot layout the store was zeroed for
 };
 void free_gen(GenSet& g);
 

@@ -159,6 +159,31 @@ __global__ void k_grad_acc(double* __restrict__ gacc, const double* __restrict__
   gacc[i] += a * g[i];
 }
 
+// Sector-only forms (one grid row per batch entry; sec holds the sector's physical indices).
+__global__ void k_sector_copy(const double2* __restrict__ src, double2* __restrict__ dst,
+                              const uint32_t* __restrict__ sec, int nsec, int n) {
+  const size_t off = (size_t)blockIdx.y << n;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < nsec; i += gridDim.x * blockDim.x) {
+    const size_t at = off | sec[i];
+    st16(dst + at, ld16(src + at));
+  }
+}
+
+__global__ void k_sector_acc(const double2* __restrict__ src, double2* __restrict__ dst,
+                             const uint32_t* __restrict__ sec, int nsec, const double* __restrict__ coef,
+                             int cstride, const int* __restrict__ deg, int j, int n) {
+  const int b = blockIdx.y;
+  if (j > deg[b]) return;
+  const double c = coef[(size_t)b * cstride + j];
+  const size_t off = (size_t)b << n;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < nsec; i += gridDim.x * blockDim.x) {
+    const size_t at = off | sec[i];
+    const dvec2 v = ld16(src + at);
+    const dvec2 f = ld16(dst + at);
+    st16(dst + at, dvec2{f.x + c * v.x, f.y + c * v.y});
+  }
+}
+
 inline int stream_grid(size_t total) {
   const size_t per = 256;
   const size_t want = (total + per - 1) / per;
@@ -209,6 +234,27 @@ hipError_t launch_fill_zero(double2* v, size_t n, hipStream_t st) {
 
 hipError_t launch_fill_identity_cs(double2* cs, size_t n, hipStream_t st) {
   hipLaunchKernelGGL(k_fill_identity_cs, dim3(stream_grid(n)), dim3(256), 0, st, cs, n);
+  return hipGetLastError();
+}
+
+inline dim3 sector_grid(int nsec, int B) {
+  const int per_entry = std::max(1, std::min((nsec + 255) / 256, std::max(1, device_cus() * 16 / std::max(B, 1))));
+  return dim3(per_entry, B);
+}
+
+hipError_t launch_sector_copy(const double2* src, double2* dst, const uint32_t* sec, int nsec, int n,
+                              int B, hipStream_t st) {
+  if (nsec <= 0 || B <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_sector_copy, sector_grid(nsec, B), dim3(256), 0, st, src, dst, sec, nsec, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_sector_acc(const double2* src, double2* dst, const uint32_t* sec, int nsec,
+                             const double* coef, int cstride, const int* deg, int j, int n, int B,
+                             hipStream_t st) {
+  if (nsec <= 0 || B <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_sector_acc, sector_grid(nsec, B), dim3(256), 0, st, src, dst, sec, nsec, coef,
+                     cstride, deg, j, n);
   return hipGetLastError();
 }
 

@@ -90,6 +90,14 @@ hipError_t launch_fill_zero(double2* v, size_t n, hipStream_t st);
 hipError_t launch_fill_identity_cs(double2* cs, size_t n, hipStream_t st);
 hipError_t launch_grad_acc(double* gacc, const double* g, const double* cfac, int half, int B, int K,
                            hipStream_t st);
+// The same on the N / S_z sector only (sec: its nsec physical basis indices), for vectors whose
+// other amplitudes are zero or never read: dst = src (copy), dst += coef[b][j] src for entries
+// with j <= deg[b] (acc; the arithmetic of launch_cheb_acc with yscale 1).
+hipError_t launch_sector_copy(const double2* src, double2* dst, const uint32_t* sec, int nsec, int n,
+                              int B, hipStream_t st);
+hipError_t launch_sector_acc(const double2* src, double2* dst, const uint32_t* sec, int nsec,
+                             const double* coef, int cstride, const int* deg, int j, int n, int B,
+                             hipStream_t st);
 // Whole evaluation of a one-tile plan in one launch (one 256-thread workgroup per entry).
 // fwd_state: the state written to psi is Psi(theta) also for gradient calls (else the state
 // the reverse sweep ends on).

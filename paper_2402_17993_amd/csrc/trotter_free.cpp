@@ -51,6 +51,7 @@ void free_gen_buffers(GenSet& g) {
   release(g.esave);
   release(g.ystore);
   g.ystore_bytes = 0;
+  g.ystore_B = -1;
   g.cap = 0;
 }
 
@@ -64,6 +65,32 @@ void free_gen_tables(GenSet& g) {
   release(g.d_pexc);
   release(g.d_ppairs);
   release(g.d_pcls);
+  release(g.d_sec);
+  g.nsec = 0;
+}
+
+// Physical indices of the basis states with nalpha alpha and nbeta beta electrons (every
+// combination of each spin's occupied bits, deposited into its qubit mask).
+std::vector<uint32_t> sector_indices(const Plan& p) {
+  auto combos = [](int nbits, int k) {
+    std::vector<uint32_t> v;
+    if (k < 0 || k > nbits) return v;
+    if (k == 0) return std::vector<uint32_t>{0u};
+    const uint64_t end = uint64_t(1) << nbits;
+    for (uint64_t x = (uint64_t(1) << k) - 1; x < end;) {  // next subset of the same size
+      v.push_back((uint32_t)x);
+      const uint64_t c = x & (~x + 1), r = x + c;
+      x = (((r ^ x) >> 2) / c) | r;
+    }
+    return v;
+  };
+  const auto av = combos(__builtin_popcount(p.amask), p.nalpha);
+  const auto bv = combos(__builtin_popcount(p.bmask), p.nbeta);
+  std::vector<uint32_t> out;
+  out.reserve(av.size() * bv.size());
+  for (uint32_t a : av)
+    for (uint32_t b : bv) out.push_back(deposit_bits(a, p.amask) | deposit_bits(b, p.bmask));
+  return out;
 }
 
 // Host plan and tables of the generator for the context's expectation tile size (and, with
@@ -112,6 +139,16 @@ ucc_status ensure_gen_plan(ucc_ctx* c, bool upload) {
       return hip_fail(e, "generator table upload");
     }
   }
+  if (upload && !g.d_sec) {
+    const std::vector<uint32_t> sec = sector_indices(p);
+    if (sec.size() != p.nsec) return fail(UCC_EINVAL, "sector enumeration disagrees with the plan");
+    hipError_t e = upload_vec(&g.d_sec, sec);
+    if (e != hipSuccess) {
+      free_gen_tables(g);
+      return hip_fail(e, "sector index upload");
+    }
+    g.nsec = (int)sec.size();
+  }
   if (upload && !g.d_ppasses) {
     hipError_t e;
     if ((e = upload_vec(&g.d_ppasses, g.ptab.passes)) != hipSuccess ||
@@ -158,17 +195,27 @@ ucc_status ensure_gen_buffers(ucc_ctx* c, int B) {
 }
 
 // Series vectors y_0 .. y_m of every entry, kept for the adjoint sweep of gradient calls.
-ucc_status ensure_ystore(ucc_ctx* c, int B, int m) {
+// Only in-sector amplitudes are copied into the store, so it is zeroed when allocated and
+// whenever the slot layout (the batch size) changes.
+ucc_status ensure_ystore(ucc_ctx* c, int B, int m, hipStream_t st) {
   GenSet& g = c->gen;
   const size_t bytes = size_t(m + 1) * (size_t(B) << c->plan.n) * 16;
-  if (bytes <= g.ystore_bytes) return UCC_OK;
-  hipError_t e = hipDeviceSynchronize();
-  if (e != hipSuccess) return hip_fail(e, "hipDeviceSynchronize");
-  release(g.ystore);
-  g.ystore_bytes = 0;
-  e = hipMalloc(reinterpret_cast<void**>(&g.ystore), bytes);
-  if (e != hipSuccess) return hip_fail(e, "hipMalloc(series vectors)");
-  g.ystore_bytes = bytes;
+  hipError_t e;
+  if (bytes > g.ystore_bytes) {
+    e = hipDeviceSynchronize();
+    if (e != hipSuccess) return hip_fail(e, "hipDeviceSynchronize");
+    release(g.ystore);
+    g.ystore_bytes = 0;
+    g.ystore_B = -1;
+    e = hipMalloc(reinterpret_cast<void**>(&g.ystore), bytes);
+    if (e != hipSuccess) return hip_fail(e, "hipMalloc(series vectors)");
+    g.ystore_bytes = bytes;
+  }
+  if (g.ystore_B != B) {
+    e = launch_fill_zero(g.ystore, g.ystore_bytes / 16, st);
+    if (e != hipSuccess) return hip_fail(e, "launch k_fill_zero");
+    g.ystore_B = B;
+  }
   return UCC_OK;
 }
 
@@ -221,13 +268,16 @@ ucc_status enqueue_trotter_free(ucc_ctx* c, const double* d_theta, int B, hipStr
   }
   if (terms) std::copy(deg.begin(), deg.end(), terms);
   if (grad) {
-    ucc_status s = ensure_ystore(c, B, m);
+    ucc_status s = ensure_ystore(c, B, m, st);
     if (s != UCC_OK) return s;
   }
   const size_t BS = size_t(B) << p.n;
-  auto keep = [&](int j, const double2* y) -> hipError_t {  // y_j into the store
+  const double secb = 16.0 * double(g.nsec) * B;
+  auto keep = [&](int j, const double2* y) -> hipError_t {  // y_j into the store (its sector)
     if (!grad) return hipSuccess;
-    return hipMemcpyAsync(g.ystore + size_t(j) * BS, y, BS * 16, hipMemcpyDeviceToDevice, st);
+    return timed(UCC_KERNEL_CHEB, 2 * secb, [&] {
+      return launch_sector_copy(y, g.ystore + size_t(j) * BS, g.d_sec, g.nsec, p.n, B, st);
+    });
   };
   const int nd = (int)(g.tab.blob.size() / 2);
   e = timed(UCC_KERNEL_CHEB, 16.0 * B * nd, [&] {
@@ -262,10 +312,11 @@ ucc_status enqueue_trotter_free(ucc_ctx* c, const double* d_theta, int B, hipStr
       return launch_cheb_acc(y, F, g.coef, cstride, g.deg, j, yscale, p.n, B, st);
     });
   };
-  // dst += c_j y for entries with j <= their degree
+  // dst += c_j y for entries with j <= their degree, on the sector (y and dst are zero
+  // outside it)
   auto acc2 = [&](const double2* y, double2* dst, int j) {
-    return timed(UCC_KERNEL_CHEB, 3 * S, [&] {
-      return launch_cheb_acc(const_cast<double2*>(y), dst, g.coef, cstride, g.deg, j, 1.0, p.n, B, st);
+    return timed(UCC_KERNEL_CHEB, 3 * secb, [&] {
+      return launch_sector_acc(y, dst, g.d_sec, g.nsec, g.coef, cstride, g.deg, j, p.n, B, st);
     });
   };
   int seq = 0;
