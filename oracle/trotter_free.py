@@ -39,10 +39,12 @@ from .ansatz import all_pairs, hf_state
 from .hamiltonian import apply_h, energy as _energy
 
 
-def generator_matrix(n, exc, theta, pairs=None):
-    """Sparse A = sum_k theta_k (T_k - T_k^dag) over the 2^n basis states (CSR, float64)."""
+def generator_matrix(n, exc, theta, pairs=None, dim=None):
+    """Sparse A = sum_k theta_k (T_k - T_k^dag) over the 2^n basis states (CSR, float64).
+    With dim, pairs index a basis of dim states (a sector) instead of all 2^n."""
     if pairs is None:
         pairs = all_pairs(n, exc)
+    N = (1 << n) if dim is None else int(dim)
     theta = np.asarray(theta, dtype=np.float64)
     rows, cols, vals = [], [], []
     for (u, v, s), t in zip(pairs, theta):
@@ -51,9 +53,9 @@ def generator_matrix(n, exc, theta, pairs=None):
         cols += [u, v]
         vals += [t * s, -t * s]
     if not rows:
-        return scipy.sparse.csr_matrix((1 << n, 1 << n))
+        return scipy.sparse.csr_matrix((N, N))
     A = scipy.sparse.coo_matrix((np.concatenate(vals), (np.concatenate(rows), np.concatenate(cols))),
-                                shape=(1 << n, 1 << n))
+                                shape=(N, N))
     return A.tocsr()
 
 

@@ -15,7 +15,7 @@ import numpy as np
 ROOT = os.path.dirname(os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
 sys.path.insert(0, ROOT)
 
-from oracle import ansatz, closed_forms, dense, hamiltonian, trotter_free  # noqa: E402
+from oracle import ansatz, closed_forms, dense, hamiltonian, sector, trotter_free  # noqa: E402
 from paper_2402_17993_amd.inputs import make_integrals, make_thetas, uccsd_excitations  # noqa: E402
 
 HERE = os.path.dirname(os.path.abspath(__file__))
@@ -23,26 +23,77 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 
 def case_dimer_18q():
     """18 qubits, 10 electrons, integrals seed 0, batch of 64 thetas U(-0.05, 0.05) from seeds
-    1..64: oracle energy of every batch entry, and energy and gradient of entries 0, 1, 9, 18,
-    27, 36, 45, 54 and 63."""
+    1..64: oracle energy and gradient of every batch entry (computed on the N / S_z sector)."""
     n, ne = 18, 10
     h1, h2 = make_integrals(n // 2, 0)
     h, g = hamiltonian.spin_orbital_integrals(h1, h2)
     exc = uccsd_excitations(n, ne)
     thetas = make_thetas(len(exc), 1, 0.05, batch=64)
-    pairs = ansatz.all_pairs(n, exc)
+    basis = sector.hf_sector(n, (1 << ne) - 1)[0]
+    pairs = sector.all_pairs(n, basis, exc)
     out = {"n": n, "ne": ne, "integral_seed": 0, "theta_seed": 1, "theta_scale": 0.05,
            "batch": 64, "entries": {}}
-    for b in (0, 1, 9, 18, 27, 36, 45, 54, 63):
-        e, gr = ansatz.energy_and_gradient(h, g, n, (1 << ne) - 1, exc, thetas[b], pairs)
+    for b in range(64):
+        e, gr = sector.energy_and_gradient(h, g, n, (1 << ne) - 1, exc, thetas[b], basis, pairs)
         out["entries"][str(b)] = {"energy": e, "grad": gr.tolist()}
-    out["energies"] = [ansatz.energy(h, g, n, (1 << ne) - 1, exc, thetas[b], pairs) for b in range(64)]
+    out["energies"] = [out["entries"][str(b)]["energy"] for b in range(64)]
+    return out
+
+
+def _large(n, ne, ks=None):
+    """Energy and adjoint gradient at integrals seed 0, theta U(-0.05, 0.05) from seed 1, on the
+    N / S_z sector (the full 2^n vectors do not fit a host at these sizes)."""
+    h1, h2 = make_integrals(n // 2, 0)
+    h, g = hamiltonian.spin_orbital_integrals(h1, h2)
+    exc = uccsd_excitations(n, ne)
+    th = make_thetas(len(exc), 1, 0.05)
+    e, gr = sector.energy_and_gradient(h, g, n, (1 << ne) - 1, exc, th)
+    return {"n": n, "ne": ne, "integral_seed": 0, "theta_seed": 1, "theta_scale": 0.05,
+            "n_exc": len(exc), "energy": e, "grad": gr.tolist()}
+
+
+def case_large_24q():
+    """24 qubits, 14 electrons (the serving mix's trimer size): E and the full gradient."""
+    return _large(24, 14)
+
+
+def case_large_26q():
+    """26 qubits, 14 electrons (the single large instance): E and the full gradient."""
+    return _large(26, 14)
+
+
+SERVING_JOBS = ((12, 8, 1201), (18, 10, 1202), (24, 14, 1203))
+
+
+def case_serving_jobs():
+    """Steepest-descent VQE jobs of the serving mix's three sizes (monomer 12q/8e, dimer
+    18q/10e, trimer 24q/14e; integrals seed s, theta0 U(-0.05, 0.05) from seed s + 1), two
+    steps of theta <- theta - 0.1 grad: energies before each step and after the last, and
+    the final amplitudes."""
+    out = {"lr": 0.1, "iters": 2, "theta_scale": 0.05, "jobs": []}
+    for n, ne, seed in SERVING_JOBS:
+        h1, h2 = make_integrals(n // 2, seed)
+        h, g = hamiltonian.spin_orbital_integrals(h1, h2)
+        exc = uccsd_excitations(n, ne)
+        th = make_thetas(len(exc), seed + 1, 0.05)
+        basis = sector.hf_sector(n, (1 << ne) - 1)[0]
+        es = []
+        for step in range(out["iters"] + 1):
+            if step < out["iters"]:
+                e, gr = sector.energy_and_gradient(h, g, n, (1 << ne) - 1, exc, th, basis)
+                es.append(e)
+                th = th - out["lr"] * gr
+            else:
+                es.append(sector.energy(h, g, n, (1 << ne) - 1, exc, th, basis))
+        out["jobs"].append({"n": n, "ne": ne, "integral_seed": seed, "theta_seed": seed + 1,
+                            "energies": es, "theta": th.tolist()})
     return out
 
 
 def case_dimer_18q_trotter_free():
     """The batch of case dimer_18q under the Trotter-free ansatz (Sec. 3.2): oracle energy of
-    entries 0, 1, 9, 18, 27, 36, 45, 54 and 63."""
+    entries 0, 1, 9, 18, 27, 36, 45, 54 and 63 (expm_multiply over all 2^18 states), and the
+    energy and full gradient of entries 0 and 63."""
     n, ne = 18, 10
     h1, h2 = make_integrals(n // 2, 0)
     h, g = hamiltonian.spin_orbital_integrals(h1, h2)
@@ -54,6 +105,14 @@ def case_dimer_18q_trotter_free():
     for b in (0, 1, 9, 18, 27, 36, 45, 54, 63):
         out["energies"][str(b)] = trotter_free.trotter_free_energy(h, g, n, (1 << ne) - 1, exc,
                                                                    thetas[b], pairs)
+    # full gradients of entries 0 and 63 (Frechet derivative, on the N / S_z sector)
+    basis = sector.hf_sector(n, (1 << ne) - 1)[0]
+    spairs = sector.all_pairs(n, basis, exc)
+    out["gradients"] = {}
+    for b in (0, 63):
+        e, gr = sector.trotter_free_energy_and_gradient(h, g, n, (1 << ne) - 1, exc, thetas[b],
+                                                        ks=range(len(exc)), basis=basis, pairs=spairs)
+        out["gradients"][str(b)] = {"energy": e, "grad": gr.tolist()}
     return out
 
 
@@ -81,7 +140,11 @@ def case_large_26q_theta0():
 
 
 CASES = {"dimer_18q": case_dimer_18q, "dimer_18q_trotter_free": case_dimer_18q_trotter_free,
-         "fragment_h4": case_fragment_h4, "large_26q_theta0": case_large_26q_theta0}
+         "fragment_h4": case_fragment_h4, "large_26q_theta0": case_large_26q_theta0,
+         "large_24q": case_large_24q, "large_26q": case_large_26q,
+         "serving_jobs": case_serving_jobs}
+
+COMPACT = ("dimer_18q", "dimer_18q_trotter_free", "large_24q", "large_26q", "serving_jobs")
 
 if __name__ == "__main__":
     names = sys.argv[1:] or list(CASES)
@@ -90,5 +153,6 @@ if __name__ == "__main__":
         data = CASES[name]()
         data["generator"] = "tests/golden/make_golden.py (oracle/)"
         with open(os.path.join(HERE, f"{name}.json"), "w") as f:
-            json.dump(data, f, indent=1)
+            # large cases on one line per file, the small ones readable
+            json.dump(data, f, indent=None if name in COMPACT else 1)
         print(f"{name}: {time.time() - t:.1f}s")
