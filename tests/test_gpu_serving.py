@@ -5,6 +5,8 @@ by the same kernels in the same order whatever else runs, and the host update is
 arithmetic); one job's trajectory is checked against the CPU oracle's steepest descent
 (|dE| <= 1e-10 Ha per step, theta within 1e-9).
 """
+import json
+import os
 import time
 
 import numpy as np
@@ -71,6 +73,33 @@ def test_results_identical_alone_and_in_the_mix(ucc):
     es_ref, th_ref = ansatz.steepest_descent(h, g, 8, 15, uccsd_excitations(8, 4), th0[5], iters, LR)
     assert np.max(np.abs(res[5]["energies"] - es_ref)) <= 1e-10
     assert np.max(np.abs(res[5]["theta"] - th_ref)) <= 1e-9
+
+
+def test_jobs_of_the_mix_sizes_against_oracle_and_alone(ucc):
+    """Monomer 12q/8e, dimer 18q/10e and trimer 24q/14e jobs (the serving mix's sizes) served
+    together: each trajectory equals its solo run bitwise and the oracle's steepest descent
+    (tests/golden/serving_jobs.json) to 1e-10 Ha per step, amplitudes to 1e-9."""
+    gold = json.load(open(os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden",
+                                       "serving_jobs.json")))
+    iters, lr = gold["iters"], gold["lr"]
+    jobs = []
+    for jb in gold["jobs"]:
+        say(f"case: served {jb['n']}q/{jb['ne']}e job, integrals seed {jb['integral_seed']}")
+        ctx = make_ctx(ucc, jb["n"], jb["ne"], jb["integral_seed"])
+        jobs.append((ctx, make_thetas(ctx.n_exc, jb["theta_seed"], gold["theta_scale"]), jb))
+    alone = [solo_sd(ctx, th, iters, lr) for ctx, th, _ in jobs]
+    with ucc.Server(slots=8) as srv:
+        tickets = [srv.submit(ctx, th, iters, lr) for ctx, th, _ in jobs]
+        res = [srv.wait(t) for t in tickets]
+    for r, a, (_, _, jb) in zip(res, alone, jobs):
+        assert r["status"] == 0 and r["rounds"] == iters + 1
+        assert np.array_equal(r["energies"], a[0]) and np.array_equal(r["theta"], a[1]), jb["n"]
+        de = float(np.max(np.abs(r["energies"] - np.array(jb["energies"]))))
+        dt = float(np.max(np.abs(r["theta"] - np.array(jb["theta"]))))
+        say(f"{jb['n']}q: max |dE| {de:.2e}, max |dtheta| {dt:.2e}")
+        assert de <= 1e-10 and dt <= 1e-9, jb["n"]
+    for ctx, _, _ in jobs:
+        ctx.close()
 
 
 def test_jobs_join_while_others_run(ucc):

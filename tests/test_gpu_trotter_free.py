@@ -16,6 +16,7 @@ from paper_2402_17993_amd.inputs import make_integrals, make_thetas, uccsd_excit
 pytestmark = pytest.mark.gpu
 
 E_TOL = 1e-10
+G_TOL = 1e-9
 HERE = os.path.dirname(os.path.abspath(__file__))
 
 
@@ -97,6 +98,13 @@ def test_18q_batch_against_stored_oracle_values(ucc):
     # amplitudes with sum |theta| about 14)
     et = ctx.energy(thetas[:4])
     assert np.all(np.abs(et - E[:4]) > 1e-6) and np.all(np.abs(et - E[:4]) < 0.1)
+    # energies and full gradients of entries 0 and 63 against the oracle's Frechet-derivative
+    # gradient, from one batched gradient call (the sector-only series store and update)
+    EG, GG = ctx.energy_grad_trotter_free(thetas)
+    for b, ent in ref["gradients"].items():
+        b = int(b)
+        assert abs(EG[b] - ent["energy"]) <= E_TOL, b
+        assert np.max(np.abs(GG[b] - np.array(ent["grad"]))) <= G_TOL, b
     ctx.close()
 
 
