@@ -137,6 +137,35 @@ ucc_status ucc_energy(ucc_ctx* ctx, const double* theta, int32_t B, double* ener
 ucc_status ucc_energy_grad(ucc_ctx* ctx, const double* theta, int32_t B, double* energy,
                            double* grad, void* stream);
 
+/* Device scratch held by the allocation-free entry point, per GPU, until the process ends. */
+#define UCC_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+
+/*
+ * ucc_energy_grad_noalloc -- ucc_energy_grad for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid hipMalloc).  Same
+ * kernels and the same results (bitwise) as ucc_energy_grad on the same context; every
+ * per-call buffer (psi, lambda, stored forward states, cos/sin, per-tile partials) lives in one
+ * static device array of UCC_NOALLOC_SCRATCH_BYTES per GPU instead of the context's buffers.
+ * No hipMalloc, hipFree, memset node or other allocating call is made.
+ *
+ *   theta   device pointer, [B * n_exc] float64
+ *   B       1 <= B <= 65535, and the call's buffers must fit the scratch: 2 B 16 2^n bytes
+ *           (psi, lambda) + (stored-state plans) (n_fwd_passes - 1) B 16 2^n + small
+ *           partials; e.g. 18 qubits with stored states (13 forward passes) need 56 MiB at B = 1
+ *   energy  device pointer, [B] float64 (written in stream order)
+ *   grad    device pointer, [B * n_exc] float64
+ *   stream  hipStream_t; NULL = the default stream
+ * The scratch array is shared by every call on a GPU and keeps the last call's contents (what
+ * must start at zero is cleared by a kernel on the stream): calls that overlap on one GPU
+ * (different streams or threads, any contexts) race and must be serialized by the caller.
+ * The context's own buffers are not touched, so ucc_get_state does not see this call's state.
+ * Errors: UCC_EINVAL (NULL or host pointers, B out of range, host_only context),
+ *         UCC_ENOMEM (the call needs more than UCC_NOALLOC_SCRATCH_BYTES), UCC_EBUSY (a server
+ *         job holds the context), UCC_EDEVICE (HIP errors, symbol lookup).
+ */
+ucc_status ucc_energy_grad_noalloc(ucc_ctx* ctx, const double* theta, int32_t B, double* energy,
+                                   double* grad, void* stream);
+
 /*
  * ucc_energy_trotter_free -- E_b = <Psi_b|H|Psi_b> for the Trotter-free ansatz
  * |Psi_b> = exp(sum_k theta_{b,k} (T_k - T_k^dag)) |HF>: the exponential of the whole cluster

@@ -22,7 +22,7 @@ STATUS = {0: "UCC_OK", -1: "UCC_EINVAL", -2: "UCC_ENOMEM", -3: "UCC_EDEVICE", -4
 STATUS_CODES = {v: k for k, v in STATUS.items()}
 
 EXPORTED = [
-    "ucc_default_options", "ucc_build", "ucc_energy", "ucc_energy_grad",
+    "ucc_default_options", "ucc_build", "ucc_energy", "ucc_energy_grad", "ucc_energy_grad_noalloc",
     "ucc_energy_trotter_free", "ucc_energy_grad_trotter_free", "ucc_get_generator_passes",
     "ucc_get_partials_passes",
     "ucc_fmo2_energy", "ucc_get_state",
@@ -85,6 +85,7 @@ def lib():
         "ucc_build": (_i32, [_i32, _i32, _vp, _vp, _vp, _i32, _P(Options), _P(_vp)]),
         "ucc_energy": (_i32, [_vp, _vp, _i32, _vp, _vp]),
         "ucc_energy_grad": (_i32, [_vp, _vp, _i32, _vp, _vp, _vp]),
+        "ucc_energy_grad_noalloc": (_i32, [_vp, _vp, _i32, _vp, _vp, _vp]),
         "ucc_energy_trotter_free": (_i32, [_vp, _vp, _i32, _vp, _vp, _vp]),
         "ucc_energy_grad_trotter_free": (_i32, [_vp, _vp, _i32, _vp, _vp, _vp, _vp]),
         "ucc_get_generator_passes": (_i32, [_vp, _i32, _vp, _vp, _P(_i32)]),
@@ -205,6 +206,20 @@ class Context:
     def energy_grad(self, theta, stream=None):
         """(E [B], dE/dtheta [B, K])."""
         return self._run(theta, True, stream)
+
+    def energy_grad_noalloc(self, theta, energy, grad, stream=None):
+        """ucc_energy_grad_noalloc: theta [B, K] in, energy [B] and grad [B, K] out, all
+        contiguous float64 torch CUDA tensors the caller owns; the call allocates nothing."""
+        import torch
+        for name, t in (("theta", theta), ("energy", energy), ("grad", grad)):
+            if not (_is_torch_cuda(t) and t.dtype == torch.float64 and t.is_contiguous()):
+                raise ValueError(f"{name} must be a contiguous float64 CUDA tensor")
+        B = theta.numel() // self.n_exc
+        if theta.numel() != B * self.n_exc or energy.numel() != B or grad.numel() != B * self.n_exc:
+            raise ValueError("theta [B, K], energy [B] and grad [B, K] do not match")
+        st = stream if stream is not None else torch.cuda.current_stream(theta.device).cuda_stream
+        check(lib().ucc_energy_grad_noalloc(self._h, _vp(theta.data_ptr()), B, _vp(energy.data_ptr()),
+                                            _vp(grad.data_ptr()), _vp(st)), "ucc_energy_grad_noalloc")
 
     def energy_trotter_free(self, theta, stream=None, return_terms=False):
         """E [B] of the Trotter-free ansatz exp(sum_k theta_k G_k)|HF> (no product formula);
