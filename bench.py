@@ -60,17 +60,21 @@ def cpu_baseline():
 
 def copy_calibration(gib):
     """A plain device copy of known size, for scaling HBM byte counters (FETCH_SIZE,
-    WRITE_SIZE) read under rocprofv3 --pmc: the copy kernel moves exactly `gib` GiB each way."""
+    WRITE_SIZE) read under rocprofv3 --pmc: the library's streaming copy kernel
+    (ucc_stream_probe, mode 0) moves exactly `gib` GiB each way per launch."""
     import torch
 
-    n = int(gib * 2 ** 30) // 8
-    a = torch.ones(n, dtype=torch.float64, device="cuda:0")
+    from paper_2402_17993_amd import ucc
+
+    n = int(gib * 2 ** 30)
+    a = torch.ones(n // 8, dtype=torch.float64, device="cuda:0")
     b = torch.empty_like(a)
     torch.cuda.synchronize()
     for _ in range(3):
-        b.copy_(a)
+        ucc.stream_probe(a, b, n, 0)
     torch.cuda.synchronize()
-    print(json.dumps({"copy_bytes_read": n * 8, "copy_bytes_written": n * 8, "launches": 3}))
+    print(json.dumps({"copy_bytes_read": n, "copy_bytes_written": n, "launches": 3,
+                      "kernel": "ucc::k_stream<true>"}))
 
 
 def copy_rate(torch, gib=1.0, reps=5):
@@ -90,6 +94,33 @@ def copy_rate(torch, gib=1.0, reps=5):
     rate = 2 * n * 8 * reps / (e0.elapsed_time(e1) * 1e-3) / 1e9
     del a, b
     return rate
+
+
+def stream_rates(ucc, torch, gib=1.0, reps=5):
+    """GB/s of the library's plain streaming kernels (ucc_stream_probe: 16-byte non-temporal
+    loads and stores, the pass kernels' access pattern) over `gib` GiB: a copy (bytes read +
+    written) and a read-only sweep; the ceiling the pass kernels are read against."""
+    n = int(gib * 2 ** 30)
+    a = torch.ones(n // 8, dtype=torch.float64, device="cuda:0")
+    b = torch.empty_like(a)
+    out = {}
+    for name, mode, moved in (("copy_GBps", 0, 2 * n), ("read_GBps", 1, n)):
+        dst = b if mode == 0 else torch.empty(1 << 13, dtype=torch.float64, device="cuda:0")
+        ucc.stream_probe(a, dst, n, mode)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            ucc.stream_probe(a, dst, n, mode)
+        e1.record()
+        e1.synchronize()
+        out[name] = moved * reps / (e0.elapsed_time(e1) * 1e-3) / 1e9
+    if not np.array_equal(b[:1024].cpu().numpy(), a[:1024].cpu().numpy()):
+        raise RuntimeError("stream probe copy is wrong")
+    del a, b
+    out["torch_copy_GBps"] = copy_rate(torch, gib, reps)
+    out["gib"] = gib
+    return out
 
 
 def one_at_a_time(ctx, td):
@@ -193,20 +224,26 @@ def paper_shaped(ucc, torch, reps=20):
     return out
 
 
-def large_state(ucc, torch, n=26, ne=14):
+def large_state(ucc, torch, n=26, ne=14, autotune=True):
     """One E + grad evaluation of a 1 GiB state (26 qubits, 14 electrons, K = 2478), integrals
-    from seed 0, theta ~ U(-0.05, 0.05) from seed 1; per-kind HIP-event times and the
-    algorithmic HBM rate of the whole evaluation."""
+    from seed 0, theta ~ U(-0.05, 0.05) from seed 1, tiles and workgroups autotuned at B = 1;
+    per-kind HIP-event times and the algorithmic HBM rate of the whole evaluation, after a
+    check of E and the full gradient against the stored oracle values."""
     from paper_2402_17993_amd.inputs import make_integrals, make_thetas, uccsd_excitations
 
     h1, h2 = make_integrals(n // 2, 0)
     exc = uccsd_excitations(n, ne)
     t0 = time.perf_counter()
-    ctx = ucc.Context(n, ne, h1, h2, exc, device=0)
+    ctx = ucc.Context(n, ne, h1, h2, exc, device=0, autotune=autotune)
     build_s = time.perf_counter() - t0
     th = torch.tensor(make_thetas(len(exc), 1, 0.05), device="cuda:0", dtype=torch.float64)
-    ctx.energy_grad(th)
+    e0, g0 = ctx.energy_grad(th)
     torch.cuda.synchronize()
+    gold = json.load(open(os.path.join(ROOT, "tests", "golden", f"large_{n}q.json")))
+    de = abs(float(e0[0]) - gold["energy"])
+    dg = float(np.max(np.abs(g0[0].cpu().numpy() - np.array(gold["grad"]))))
+    if de > 1e-10 or dg > 1e-9:
+        raise RuntimeError(f"{n}-qubit parity failed: |dE| {de:.2e}, |dg| {dg:.2e}")
     ctx.profile(True)
     ctx.profile_read(reset=True)
     a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -224,6 +261,9 @@ def large_state(ucc, torch, n=26, ne=14):
             "ms": ms, "GBps": byt / (ms * 1e-3) / 1e9, "frac": byt / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
             "passes_fwd_exp_rev": [info["n_fwd_passes"], info["n_exp_passes"], info["n_rev_passes"]],
             "kernels_ms": {k: v["ms"] for k, v in st.items() if v["launches"]},
+            "tile_qubits_fwd_exp_rev": [info["tile_qubits"], info["tile_qubits_exp"], info["tile_qubits_rev"]],
+            "autotuned": bool(info["autotuned"]),
+            "parity": {"max_abs_dE": de, "max_abs_dgrad": dg, "gradients_checked": len(gold["grad"])},
             "plan_build_s": build_s}
 
 
@@ -285,9 +325,15 @@ def trotter_free(ucc, torch, h1, h2, exc, thetas, steps=5):
     b.synchronize()
     st = ctx.profile_read(reset=True)
     local, _ = ctx.generator_passes()
-    # energies and gradients (adjoint of the series)
-    ctx.energy_grad_trotter_free(td)
+    # energies and gradients (adjoint of the series), checked against the oracle's
+    # Frechet-derivative gradients of two entries before the rate is reported
+    EG, GG = ctx.energy_grad_trotter_free(td)
     torch.cuda.synchronize()
+    EG, GG = EG.cpu().numpy(), GG.cpu().numpy()
+    de_g = max(abs(EG[int(b)] - v["energy"]) for b, v in gold["gradients"].items())
+    dg_g = max(float(np.max(np.abs(GG[int(b)] - np.array(v["grad"])))) for b, v in gold["gradients"].items())
+    if de_g > 1e-10 or dg_g > 1e-9:
+        raise RuntimeError(f"Trotter-free energy+gradient parity failed: |dE| {de_g:.2e}, |dg| {dg_g:.2e}")
     ctx.profile(False)
     a2, b2 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     a2.record()
@@ -307,7 +353,9 @@ def trotter_free(ucc, torch, h1, h2, exc, thetas, steps=5):
             "kernels": {k: {"launches": v["launches"] // steps, "ms": v["ms"] / steps,
                             "GBps": v["bytes"] / (v["ms"] * 1e-3) / 1e9}
                         for k, v in st.items() if v["launches"]},
-            "max_abs_dE_vs_oracle": float(de), "energies_checked": len(gold["energies"])}
+            "max_abs_dE_vs_oracle": float(de), "energies_checked": len(gold["energies"]),
+            "energy_grad_parity": {"max_abs_dE": float(de_g), "max_abs_dgrad": float(dg_g),
+                                   "entries_checked": sorted(gold["gradients"], key=int)}}
 
 
 def size_consistency(ucc, iters=400, lr=0.1):
@@ -492,9 +540,9 @@ def serving_mix(ucc, n_arrivals, rate=200.0, iters=30, lr=0.1, seed=0):
             out["by_kind"][k] = {"latency_p50_s": float(np.percentile(lat[sel], 50)),
                                  "latency_p99_s": float(np.percentile(lat[sel], 99)),
                                  "per_iteration_p50_ms": 1e3 * float(np.percentile(per_it[sel], 50))}
-    # alone vs in the mix: the first monomer and dimer jobs again, alone
+    # alone vs in the mix: the first job of each kind again, alone
     same = True
-    for k in ("monomer", "dimer"):
+    for k in ("monomer", "dimer", "trimer"):
         sel = [j for j, kind in enumerate(kinds) if kind == k]
         if sel:
             j = sel[0]
@@ -504,6 +552,37 @@ def serving_mix(ucc, n_arrivals, rate=200.0, iters=30, lr=0.1, seed=0):
                          np.array_equal(r["theta"], res[j]["theta"]))
     out["alone_equals_mix_bitwise"] = same
     return out
+
+
+def serving_trimers(ucc, jobs=4, iters=5, lr=0.1):
+    """Trimer-sized jobs alone on the server (24 qubits, 14 electrons, K = 1,715, 256 MiB per
+    state; integrals seed 1000 + i, theta0 U(-0.05, 0.05) from seed 2000 + i): they share one
+    batched launch sequence per round.  Evals/s and per-iteration time; the rocprofv3 summaries
+    of this leg give the trimers' kernel times and HBM traffic."""
+    from paper_2402_17993_amd.inputs import make_integrals, make_thetas, uccsd_excitations
+
+    n, ne = MIX["trimer"]
+    ctxs, ths = [], []
+    for i in range(jobs):
+        h1, h2 = make_integrals(n // 2, 1000 + i)
+        exc = uccsd_excitations(n, ne)
+        ctxs.append(ucc.Context(n, ne, h1, h2, exc, max_batch=0, device=0))
+        ths.append(make_thetas(len(exc), 2000 + i, 0.05))
+    with ucc.Server(slots=jobs) as srv:
+        t0 = time.perf_counter()
+        res = [srv.wait(t) for t in [srv.submit(c, th, iters, lr) for c, th in zip(ctxs, ths)]]
+        wall = time.perf_counter() - t0
+    assert all(r["status"] == 0 for r in res)
+    per_it = [(r["done_s"] - r["admit_s"]) / r["rounds"] for r in res]
+    for c in ctxs:
+        c.close()
+    return {"jobs": jobs, "iters": iters, "n_qubits": n, "n_elec": ne,
+            "evals_per_s": jobs * (iters + 1) / wall, "wall_s": wall,
+            "per_iteration_ms_p50": 1e3 * float(np.percentile(per_it, 50))}
+
+
+LEGS = ("all", "latency", "large_26q", "paper_shaped", "variants", "trotter_free",
+        "size_consistency", "serving", "serving_trimers", "stream")
 
 
 def main():
@@ -521,6 +600,8 @@ def main():
                     help="skip the one-at-a-time rate, the B = 1 latencies and the 26-qubit evaluation")
     ap.add_argument("--serve-arrivals", type=int, default=70,
                     help="arrivals of the serving trace (0 = skip the serving legs)")
+    ap.add_argument("--leg", default="all", choices=LEGS,
+                    help="run one leg alone and print {leg, result} (for profiling that leg)")
     ap.add_argument("--copy-calibration", type=float, default=0.0, metavar="GIB",
                     help="only run a plain device copy of GIB GiB (counter calibration) and exit")
     args = ap.parse_args()
@@ -544,6 +625,21 @@ def main():
     exc = uccsd_excitations(N, NE)
     K = len(exc)
     thetas = make_thetas(K, TSEED, SCALE, batch=BATCH)
+    if args.leg != "all":
+        legs = {
+            "latency": lambda: {f"{n}q": single_latency(ucc, torch, n, ne)
+                                for n, ne in ((8, 4), (12, 8), (16, 8))},
+            "large_26q": lambda: large_state(ucc, torch),
+            "paper_shaped": lambda: paper_shaped(ucc, torch),
+            "variants": lambda: trotter_variants(ucc, torch, h1, h2, exc, thetas),
+            "trotter_free": lambda: trotter_free(ucc, torch, h1, h2, exc, thetas),
+            "size_consistency": lambda: size_consistency(ucc),
+            "serving": lambda: serving_mix(ucc, args.serve_arrivals),
+            "serving_trimers": lambda: serving_trimers(ucc),
+            "stream": lambda: stream_rates(ucc, torch),
+        }
+        print(json.dumps({"leg": args.leg, "result": legs[args.leg]()}))
+        return
     ctx = ucc.Context(N, NE, h1, h2, exc, max_batch=BATCH, device=0, launch_mode=args.launch_mode,
                       autotune=not args.no_autotune, store_states=args.store_states)
     info = ctx.plan_info()
@@ -639,13 +735,13 @@ def main():
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "avg_launch_ms": avg_ms, "algorithmic_bytes_per_launch": bytes_per_launch,
-                     "device_copy_GBps": copy_rate(torch)},
+                     "stream_ceiling": stream_rates(ucc, torch)},
         "kernels": {k: {"launches": v["launches"], "ms": v["ms"],
                         "GBps": (v["bytes"] / (v["ms"] * 1e-3) / 1e9) if v["ms"] else None}
                     for k, v in stats.items() if v["launches"]},
         "parity": {"max_abs_dE": de, "max_abs_dgrad": dg,
                    "energies_checked": len(gold.get("energies", gold["entries"])),
-                   "gradients_checked": sorted(gold["entries"], key=int)},
+                   "gradients_checked": len(gold["entries"])},
     }
     if not args.no_extra:
         out["one_at_a_time_evals_per_s"] = one_at_a_time(ctx, td)

@@ -52,7 +52,8 @@ typedef struct {
   int32_t trotter_steps;     /* M of Eqs. 5 and 6: slices of the Trotter product, 1..64 (0 is
                                 read as 1); every factor's angle is theta_k / (M * order) */
   int32_t tile_qubits;       /* k: local qubits per tile of forward passes (4..14) */
-  int32_t tile_qubits_rev;   /* k of reverse-sweep passes (4..13) */
+  int32_t tile_qubits_rev;   /* k of reverse-sweep passes (4..14; 14 only with the
+                                recomputing sweep, store_states 2 or auto above 20 qubits) */
   int32_t contiguous_qubits; /* lowest physical bits kept inside every tile (2..k-4) */
   int32_t block_threads;     /* threads per workgroup of every pass kind: 256, 512 or 1024 */
   int32_t max_batch;         /* theta vectors allocated up front (grows on demand); 0 =
@@ -333,6 +334,21 @@ ucc_status ucc_fmo2_energy(int32_t n_frag, const double* e_mono, const double* e
                            double* e_total);
 
 /* ---------------------------------------------------------------- profiling */
+
+/*
+ * ucc_stream_probe -- a plain streaming kernel, for measuring what the device's memory system
+ * sustains with the access pattern of the pass kernels (consecutive lanes on consecutive
+ * 16-byte elements, non-temporal loads and stores, four loads in flight per thread): the
+ * ceiling beside which the pass kernels' bandwidth is read.  Not part of the method.
+ *   src     device pointer, `bytes` readable bytes
+ *   dst     device pointer: mode 0, `bytes` writable bytes (receives a copy of src);
+ *           mode 1, at least 64 KiB (one float64 sum per workgroup)
+ *   bytes   positive multiple of 16
+ *   mode    0 copy (moves 2 * bytes), 1 read only (moves bytes)
+ *   stream  hipStream_t; NULL = the default stream
+ * Errors: UCC_EINVAL (NULL or host pointers, bad size or mode), UCC_EDEVICE.
+ */
+ucc_status ucc_stream_probe(const void* src, void* dst, size_t bytes, int32_t mode, void* stream);
 
 /* Kernel kinds reported by ucc_profile_read. */
 enum {

@@ -389,8 +389,8 @@ ucc_status ucc_build(int32_t n_qubits, int32_t n_elec, const double* h1, const d
     return fail(UCC_EINVAL, "tile_qubits must be 0 or in [4, 14]");
   if (o.tile_qubits_exp && (o.tile_qubits_exp < 4 || o.tile_qubits_exp > 14))
     return fail(UCC_EINVAL, "tile_qubits_exp must be 0 or in [4, 14]");
-  if (o.tile_qubits_rev && (o.tile_qubits_rev < 4 || o.tile_qubits_rev > 13))
-    return fail(UCC_EINVAL, "tile_qubits_rev must be 0 or in [4, 13]");
+  if (o.tile_qubits_rev && (o.tile_qubits_rev < 4 || o.tile_qubits_rev > 14))
+    return fail(UCC_EINVAL, "tile_qubits_rev must be 0 or in [4, 14]");
   for (int t : {o.block_threads, o.block_threads_fwd, o.block_threads_exp, o.block_threads_rev})
     if (t && t != 256 && t != 512 && t != 1024)
       return fail(UCC_EINVAL, "block_threads (any kind) must be 0, 256, 512 or 1024");
@@ -399,7 +399,8 @@ ucc_status ucc_build(int32_t n_qubits, int32_t n_elec, const double* h1, const d
   if (o.autotune && o.host_only) return fail(UCC_EINVAL, "autotune needs a device context");
   if (o.store_states < 0 || o.store_states > 2) return fail(UCC_EINVAL, "store_states must be 0..2");
   if (o.store_states == 1 &&
-      (o.tile_qubits > 13 || (o.tile_qubits && o.tile_qubits_rev && o.tile_qubits != o.tile_qubits_rev)))
+      (o.tile_qubits > 13 || o.tile_qubits_rev > 13 ||
+       (o.tile_qubits && o.tile_qubits_rev && o.tile_qubits != o.tile_qubits_rev)))
     return fail(UCC_EINVAL, "store_states 1 needs one tile size of at most 13 for both sweeps");
 
   ucc_ctx* c = new (std::nothrow) ucc_ctx();

@@ -1351,6 +1351,11 @@ __global__ __launch_bounds__(T) void k_whole(
 // of the factors.
 // G[b][k] = 2 scale sum over the factors o of amplitude k (ascending) of the tile partials of
 // factor o (ascending tiles).
+// Final sums of one call.  Block (b, 0) sums entry b's per-tile energy partials; for the
+// gradient each wave takes amplitudes k = (blockIdx.y * waves + w), stepping by all the
+// grid's waves: lane l sums tiles l, l + 64, ... of each factor of k in order, the wave adds
+// its lanes in the fixed DPP order, and the factors are added in their order.  The order of
+// every sum depends only on the plan, never on the batch or the grid.
 template <int T>
 __global__ __launch_bounds__(T) void k_reduce(const double* __restrict__ epart, int ne,
                                               const double* __restrict__ gpart, int K, int L,
@@ -1359,21 +1364,24 @@ __global__ __launch_bounds__(T) void k_reduce(const double* __restrict__ epart, 
                                               double* __restrict__ G) {
   __shared__ double red[T / 64];
   const int b = blockIdx.x;
-  double s = 0.0;
-  for (int i = threadIdx.x; i < ne; i += T) s += epart[(size_t)b * ne + i];
-  s = block_sum<T>(s, red);
-  if (threadIdx.x == 0) E[b] = s;
-  if (gpart) {
-    for (int k = threadIdx.x; k < K; k += T) {
-      double g = 0.0;
-      for (int q = occ[k]; q < occ[k + 1]; ++q) {
-        const double* p = gpart + ((size_t)b * L + occ[K + 1 + q]) * nt;
-        double go = 0.0;
-        for (int t = 0; t < nt; ++t) go += p[t];
-        g += go;
-      }
-      G[(size_t)b * K + k] = 2.0 * scale * g;
+  if (blockIdx.y == 0) {
+    double s = 0.0;
+    for (int i = threadIdx.x; i < ne; i += T) s += epart[(size_t)b * ne + i];
+    s = block_sum<T>(s, red);
+    if (threadIdx.x == 0) E[b] = s;
+  }
+  if (!gpart) return;
+  constexpr int NW = T / 64;
+  const int lane = (int)threadIdx.x & 63, w = (int)threadIdx.x >> 6;
+  for (int k = (int)blockIdx.y * NW + w; k < K; k += (int)gridDim.y * NW) {
+    double g = 0.0;
+    for (int q = occ[k]; q < occ[k + 1]; ++q) {
+      const double* p = gpart + ((size_t)b * L + occ[K + 1 + q]) * nt;
+      double go = 0.0;
+      for (int t = lane; t < nt; t += 64) go += p[t];
+      g += wave_sum(go);
     }
+    if (lane == 0) G[(size_t)b * K + k] = 2.0 * scale * g;
   }
 }
 
@@ -1719,7 +1727,9 @@ hipError_t launch_whole(const LaunchArgs& a, const double* theta, bool grad, int
 }
 
 hipError_t launch_reduce(const LaunchArgs& a, int ne, bool grad, int nt) {
-  hipLaunchKernelGGL(k_reduce<256>, dim3(a.B), dim3(256), 0, a.stream, a.epart, ne,
+  // gradient: one wave per amplitude, up to 1024 blocks of 4 waves per batch entry
+  const int gy = grad ? std::min(1024, (a.K + 3) / 4) : 1;
+  hipLaunchKernelGGL(k_reduce<256>, dim3(a.B, gy), dim3(256), 0, a.stream, a.epart, ne,
                      grad ? a.gpart : nullptr, a.K, a.L, a.occ, a.scale, nt, a.E, a.G);
   return hipGetLastError();
 }

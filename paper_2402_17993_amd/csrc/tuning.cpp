@@ -38,7 +38,7 @@ std::map<Key, Tuning> g_cache;
 bool stores_states(int n, const ucc_options& o) {
   if (o.store_states == 1) return true;
   if (o.store_states == 2) return false;
-  if (n > 20 || o.tile_qubits > 13) return false;
+  if (n > 20 || o.tile_qubits > 13 || o.tile_qubits_rev > 13) return false;
   return !(o.tile_qubits && o.tile_qubits_rev && o.tile_qubits != o.tile_qubits_rev);
 }
 
@@ -104,7 +104,9 @@ ucc_status autotune(ucc_ctx* c, int B) {
       ck ? tile_candidates(o.tile_qubits ? o.tile_qubits : o.tile_qubits_rev, p.n, {13, 12})
          : tile_candidates(o.tile_qubits, p.n, {14, 13});
   const std::vector<int> kes = tile_candidates(o.tile_qubits_exp, p.n, {14, 13});
-  const std::vector<int> krs = ck ? kfs : tile_candidates(o.tile_qubits_rev, p.n, {13, 12});
+  // a recomputing sweep may take the forward sweep's 14 local qubits (its windows are then the
+  // forward windows in mirror order; two-vector tiles in the non-overlapped pass)
+  const std::vector<int> krs = ck ? kfs : tile_candidates(o.tile_qubits_rev, p.n, {14, 13});
   std::vector<int> ts;
   for (int t : {256, 512, 1024})
     if (!o.block_threads || t == o.block_threads) ts.push_back(t);

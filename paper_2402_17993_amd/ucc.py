@@ -23,6 +23,7 @@ STATUS_CODES = {v: k for k, v in STATUS.items()}
 
 EXPORTED = [
     "ucc_default_options", "ucc_build", "ucc_energy", "ucc_energy_grad", "ucc_energy_grad_noalloc",
+    "ucc_stream_probe",
     "ucc_energy_trotter_free", "ucc_energy_grad_trotter_free", "ucc_get_generator_passes",
     "ucc_get_partials_passes",
     "ucc_fmo2_energy", "ucc_get_state",
@@ -86,6 +87,7 @@ def lib():
         "ucc_energy": (_i32, [_vp, _vp, _i32, _vp, _vp]),
         "ucc_energy_grad": (_i32, [_vp, _vp, _i32, _vp, _vp, _vp]),
         "ucc_energy_grad_noalloc": (_i32, [_vp, _vp, _i32, _vp, _vp, _vp]),
+        "ucc_stream_probe": (_i32, [_vp, _vp, ctypes.c_size_t, _i32, _vp]),
         "ucc_energy_trotter_free": (_i32, [_vp, _vp, _i32, _vp, _vp, _vp]),
         "ucc_energy_grad_trotter_free": (_i32, [_vp, _vp, _i32, _vp, _vp, _vp, _vp]),
         "ucc_get_generator_passes": (_i32, [_vp, _i32, _vp, _vp, _P(_i32)]),
@@ -498,6 +500,15 @@ def _autograd():
 
 
 _UCCEnergy = None
+
+
+def stream_probe(src, dst, nbytes, mode, stream=None):
+    """ucc_stream_probe on torch CUDA tensors: mode 0 copies nbytes of src into dst, mode 1
+    reads nbytes of src (dst receives per-workgroup sums; at least 64 KiB)."""
+    import torch
+    st = stream if stream is not None else torch.cuda.current_stream(src.device).cuda_stream
+    check(lib().ucc_stream_probe(_vp(src.data_ptr()), _vp(dst.data_ptr()), int(nbytes), int(mode),
+                                 _vp(st)), "ucc_stream_probe")
 
 
 def fmo2_energy(e_mono, e_dimer):

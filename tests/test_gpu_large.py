@@ -56,8 +56,9 @@ def check(e, gr, gold):
     assert de <= E_TOL and dg <= G_TOL
 
 
-@pytest.mark.parametrize("kw", [dict(), dict(store_states=1), dict(autotune=True)],
-                         ids=["default", "stored-states", "autotuned"])
+@pytest.mark.parametrize("kw", [dict(), dict(store_states=1), dict(autotune=True),
+                                dict(tile_qubits=14, tile_qubits_rev=14)],
+                         ids=["default", "stored-states", "autotuned", "rev-tile-14"])
 def test_24q_energy_gradient_against_oracle(ucc, kw):
     gold = load("large_24q")
     n, ne, h1, h2, exc, th = inputs_of(gold)
@@ -85,11 +86,12 @@ def test_24q_batch_entries_equal_solo(ucc):
     solo.close()
 
 
-def test_26q_energy_gradient_against_oracle(ucc):
+@pytest.mark.parametrize("kw", [dict(), dict(tile_qubits_rev=14)], ids=["default", "rev-tile-14"])
+def test_26q_energy_gradient_against_oracle(ucc, kw):
     gold = load("large_26q")
     n, ne, h1, h2, exc, th = inputs_of(gold)
-    say("case: 26q/14e seed 0 energy+grad (all 2,478 components)")
-    ctx = ucc.Context(n, ne, h1, h2, exc)
+    say(f"case: 26q/14e seed 0 energy+grad (all 2,478 components), {kw}")
+    ctx = ucc.Context(n, ne, h1, h2, exc, **kw)
     e, gr = ctx.energy_grad(th)
     check(e[0], gr[0], gold)
     ctx.close()

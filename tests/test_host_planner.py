@@ -52,6 +52,7 @@ def test_library_exports_every_declared_symbol():
     dict(store_states=3), dict(store_states=1, tile_qubits=14), dict(trotter_steps=65),
     dict(trotter_steps=-1), dict(trotter_order=3),
     dict(store_states=1, tile_qubits=7, tile_qubits_rev=6),
+    dict(tile_qubits_rev=15), dict(store_states=1, tile_qubits_rev=14),
 ])
 def test_invalid_inputs_are_rejected(bad):
     n, ne = bad.get("n", 8), bad.get("ne", 4)
@@ -168,7 +169,7 @@ def test_excitation_signs_match_ladder_operators(n, ne):
 @pytest.mark.parametrize("n,ne,kf,ke,kr,ss,stored", [
     (8, 4, 0, 0, 0, 0, 1), (12, 8, 8, 9, 7, 0, 0), (16, 8, 0, 0, 0, 0, 1), (16, 8, 0, 0, 0, 2, 0),
     (18, 10, 0, 0, 0, 0, 1), (18, 10, 10, 11, 9, 0, 0), (18, 10, 14, 12, 13, 0, 0),
-    (18, 10, 0, 12, 11, 1, 1), (18, 10, 0, 0, 0, 2, 0)])
+    (18, 10, 0, 12, 11, 1, 1), (18, 10, 0, 0, 0, 2, 0), (18, 10, 14, 14, 14, 2, 0)])
 def test_pass_plan_covers_everything_in_order(n, ne, kf, ke, kr, ss, stored):
     ctx, _, _, exc = host_ctx(n, ne, tile_qubits=kf, tile_qubits_exp=ke, tile_qubits_rev=kr,
                               store_states=ss)
@@ -383,3 +384,13 @@ def test_fmo2_energy_assembly():
         ucc.fmo2_energy(em, ed[:2])
     with pytest.raises(ucc.UCCError):
         ucc.fmo2_energy(em, np.array([0.0, np.nan, 0.0]))
+
+
+def test_recomputing_sweep_at_the_forward_tile_size_takes_as_many_windows():
+    """26 qubits: with 14 local qubits for both sweeps, the recomputing reverse sweep needs no
+    more windows than the forward sweep (one per occupied pair); at 13 it needs 2.5x more."""
+    ctx14 = host_ctx(26, 14, tile_qubits=14, tile_qubits_rev=14)[0].plan_info()
+    ctx13 = host_ctx(26, 14, tile_qubits=14, tile_qubits_rev=13)[0].plan_info()
+    assert ctx14["store_states"] == 0 and ctx14["tile_qubits_rev"] == 14
+    assert ctx14["n_rev_passes"] <= ctx14["n_fwd_passes"] == 98
+    assert ctx13["n_rev_passes"] > 2 * ctx14["n_rev_passes"]
