@@ -267,6 +267,58 @@ def large_state(ucc, torch, n=26, ne=14, autotune=True):
             "plan_build_s": build_s}
 
 
+def tapered(ucc, torch, h1, h2, exc, thetas, steps=20):
+    """The benchmark workload (18 qubits, 10 electrons, batch 64, E + grad) with two-qubit
+    tapering (Sec. 2.3: the paper removes two qubits by symmetry): the state holds 2^16
+    amplitudes, the energies and gradients are those of the untapered ansatz.  Autotuned;
+    all 64 energies and gradients checked against the stored oracle values before timing;
+    evals/s over `steps` evaluations, HIP-event kernel times and the algorithmic HBM rate."""
+    gold = json.load(open(os.path.join(ROOT, "tests", "golden", "dimer_18q.json")))
+    td = torch.tensor(thetas, device="cuda:0", dtype=torch.float64)
+    ctx = ucc.Context(N, NE, h1, h2, exc, max_batch=BATCH, device=0, autotune=True, taper=1)
+    E, G = ctx.energy_grad(td)
+    torch.cuda.synchronize()
+    En, Gn = E.cpu().numpy(), G.cpu().numpy()
+    de = max(abs(En[int(b)] - v["energy"]) for b, v in gold["entries"].items())
+    dg = max(float(np.max(np.abs(Gn[int(b)] - np.array(v["grad"])))) for b, v in gold["entries"].items())
+    if de > 1e-10 or dg > 1e-9:
+        raise RuntimeError(f"tapered parity failed: |dE| {de:.2e}, |dg| {dg:.2e}")
+    for _ in range(3):
+        ctx.energy_grad(td)
+    ctx.profile(True)
+    ctx.profile_read(reset=True)
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    for _ in range(steps):
+        ctx.energy_grad(td)
+    b.record()
+    b.synchronize()
+    st = ctx.profile_read(reset=True)
+    ctx.profile(False)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        ctx.energy_grad(td)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    info = ctx.plan_info()
+    ctx.close()
+    ms = a.elapsed_time(b) / steps
+    byt = sum(v["bytes"] for v in st.values()) / steps
+    return {"evals_per_s": BATCH * steps / wall, "ms_per_step": 1e3 * wall / steps,
+            "ms_per_step_with_event_probes": ms, "state_qubits": info["state_qubits"],
+            "GBps": byt / (ms * 1e-3) / 1e9, "frac": byt / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+            "kernels": {k: {"launches": v["launches"] // steps, "ms": v["ms"] / steps,
+                            "GBps": (v["bytes"] / (v["ms"] * 1e-3) / 1e9) if v["ms"] else None}
+                        for k, v in st.items() if v["launches"]},
+            "passes_fwd_exp_rev": [info["n_fwd_passes"], info["n_exp_passes"], info["n_rev_passes"]],
+            "tile_qubits_fwd_exp_rev": [info["tile_qubits"], info["tile_qubits_exp"], info["tile_qubits_rev"]],
+            "block_threads_fwd_exp_rev": [info["block_threads_fwd"], info["block_threads_exp"],
+                                          info["block_threads_rev"]],
+            "store_states": info["store_states"],
+            "parity": {"max_abs_dE": de, "max_abs_dgrad": dg, "entries_checked": len(gold["entries"])}}
+
+
 def trotter_variants(ucc, torch, h1, h2, exc, thetas, steps=5):
     """The benchmark workload (18 qubits, batch 64) under the other Trotter products of the
     paper: M slices of the first-order product (Eq. 5), the symmetric second-order product
@@ -581,7 +633,7 @@ def serving_trimers(ucc, jobs=4, iters=5, lr=0.1):
             "per_iteration_ms_p50": 1e3 * float(np.percentile(per_it, 50))}
 
 
-LEGS = ("all", "latency", "large_26q", "paper_shaped", "variants", "trotter_free",
+LEGS = ("all", "latency", "large_26q", "paper_shaped", "variants", "tapered", "trotter_free",
         "size_consistency", "serving", "serving_trimers", "stream")
 
 
@@ -632,6 +684,7 @@ def main():
             "large_26q": lambda: large_state(ucc, torch),
             "paper_shaped": lambda: paper_shaped(ucc, torch),
             "variants": lambda: trotter_variants(ucc, torch, h1, h2, exc, thetas),
+            "tapered": lambda: tapered(ucc, torch, h1, h2, exc, thetas),
             "trotter_free": lambda: trotter_free(ucc, torch, h1, h2, exc, thetas),
             "size_consistency": lambda: size_consistency(ucc),
             "serving": lambda: serving_mix(ucc, args.serve_arrivals),
@@ -749,6 +802,7 @@ def main():
                              for n, ne in ((8, 4), (12, 8), (16, 8))}
         out["large_26q"] = large_state(ucc, torch)
         out["paper_shaped_dimers"] = paper_shaped(ucc, torch)
+        out["tapered_18q_b64"] = tapered(ucc, torch, h1, h2, exc, thetas)
         out["trotter_variants_18q_b64"] = trotter_variants(ucc, torch, h1, h2, exc, thetas)
         out["trotter_free_18q_b64"] = trotter_free(ucc, torch, h1, h2, exc, thetas)
         out["size_consistency_h8"] = size_consistency(ucc)

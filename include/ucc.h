@@ -88,6 +88,14 @@ typedef struct {
                                 excitation list in order; 2: symmetric second-order product,
                                 Eq. 6 -- each slice applies the list in order, then in reverse
                                 order.  Gradients sum over all factors of an amplitude. */
+  int32_t taper;             /* 1: two-qubit tapering (the paper maps with symmetry-conserving
+                                Bravyi-Kitaev and removes two qubits, Sec. 2.3): the alpha and
+                                beta spin orbitals of the highest spatial orbital (both virtual)
+                                are not stored, since inside the HF sector their occupations
+                                are fixed by the alpha and beta electron numbers.  The state
+                                holds 2^(n_qubits - 2) amplitudes (4x fewer bytes per pass) and
+                                every energy and gradient is that of the untapered ansatz.
+                                Needs n_qubits >= 8; not with the Trotter-free calls. */
 } ucc_options;
 
 /* Fill *opt with defaults (all automatic, launch_mode 0, max_batch 1). */
@@ -203,7 +211,9 @@ ucc_status ucc_energy_grad_trotter_free(ucc_ctx* ctx, const double* theta, int32
 /*
  * ucc_get_state -- copy state vector b held by the context to the host, in the logical
  * qubit order of this header (qubit q = bit q), as interleaved (re, im) pairs.
- *   re_im  host, [2 * 2^n_qubits] float64
+ *   re_im  host, [2 * 2^n_qubits] float64 (tapered contexts: the stored amplitudes placed at
+ *          the basis states whose tapered orbitals carry the electrons the others lack, by
+ *          parity; zero elsewhere)
  * Synchronizes the device.  Test and inspection hook.
  */
 ucc_status ucc_get_state(ucc_ctx* ctx, int32_t b, double* re_im);
@@ -229,8 +239,11 @@ typedef struct {
   int32_t autotuned;         /* 1 if the choices above come from measurement */
   int32_t store_states;      /* 1 if gradient calls keep the forward states (ucc_options) */
   int32_t trotter_steps, trotter_order;  /* M and the order of the Trotter product */
-  int32_t perm[32];          /* physical bit of logical qubit q (q < n_qubits) */
+  int32_t perm[32];          /* physical bit of logical qubit q (q < n_qubits; tapered
+                                orbitals report state_qubits and state_qubits + 1) */
   int64_t job_footprint;     /* device bytes one server job on this context holds */
+  int32_t state_qubits;      /* bits of the stored state index: n_qubits, or n_qubits - 2 tapered */
+  int32_t taper;             /* the taper option in effect */
 } ucc_plan_info;
 
 /* Sizes and choices made by ucc_build. */
@@ -260,8 +273,12 @@ ucc_status ucc_get_pauli_terms(const ucc_ctx* ctx, uint64_t* x, uint64_t* z, dou
  *   xm, m      [n_groups] physical masks (group 0 is the diagonal group, xm = 0)
  *   valid      [n_groups] 16-bit pattern masks
  *   A          [n_groups * 16]
- *   B          [n_groups * 16 * n_qubits]  (zeros where a group has no occupation terms)
- *   diag       [1 + n_qubits + n_qubits * n_qubits] = c0, a[r], b[r * n + s] (physical)
+ *   B          [n_groups * 16 * n]  (zeros where a group has no occupation terms)
+ *   diag       [1 + n + n * n] = c0, a[r], b[r * n + s] (physical)
+ * with n = state_qubits.  Tapered contexts: the formulas hold for states of the sector, v
+ * being the stored index; xm also holds the tapered orbitals the group flips (bits n and
+ * n + 1), and the pattern P is read on xm with those bits set to the tapered occupations
+ * (the electrons of that spin the stored orbitals lack); m, B and diag are over stored bits.
  * Any pointer may be NULL.
  */
 ucc_status ucc_get_group_table(const ucc_ctx* ctx, uint32_t* xm, uint32_t* m, uint32_t* valid,

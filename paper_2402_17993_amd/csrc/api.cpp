@@ -313,8 +313,9 @@ ucc_status replan(ucc_ctx* c, int kf, int ke, int kr) {
   if (p.ckpt) kr = kf;
   if (p.kf == kf && p.ke == ke && p.kr == kr) return UCC_OK;
   Plan np;
-  const std::string msg = build_plan(np, p.n, p.ne, p.h1.data(), p.h2.data(), p.exc.data(), p.K,
-                                     kf, ke, kr, c->opt.contiguous_qubits, p.ckpt, p.M, p.order);
+  const std::string msg = build_plan(np, p.nq, p.ne, p.h1.data(), p.h2.data(), p.exc.data(), p.K,
+                                     kf, ke, kr, c->opt.contiguous_qubits, p.ckpt, p.M, p.order,
+                                     p.taper);
   if (!msg.empty()) return fail(UCC_EINVAL, msg);
   np.tf = p.tf;
   np.te = p.te;
@@ -398,6 +399,8 @@ ucc_status ucc_build(int32_t n_qubits, int32_t n_elec, const double* h1, const d
   if (o.max_batch < 0) return fail(UCC_EINVAL, "max_batch must be >= 0");
   if (o.autotune && o.host_only) return fail(UCC_EINVAL, "autotune needs a device context");
   if (o.store_states < 0 || o.store_states > 2) return fail(UCC_EINVAL, "store_states must be 0..2");
+  if (o.taper < 0 || o.taper > 1) return fail(UCC_EINVAL, "taper must be 0 or 1");
+  if (o.taper && n_qubits < 8) return fail(UCC_EINVAL, "taper needs n_qubits >= 8");
   if (o.store_states == 1 &&
       (o.tile_qubits > 13 || o.tile_qubits_rev > 13 ||
        (o.tile_qubits && o.tile_qubits_rev && o.tile_qubits != o.tile_qubits_rev)))
@@ -407,10 +410,10 @@ ucc_status ucc_build(int32_t n_qubits, int32_t n_elec, const double* h1, const d
   if (!c) return fail(UCC_ENOMEM, "host allocation failed");
   c->opt = o;
   c->host_only = o.host_only != 0;
-  const Tuning tu = choose_tuning(n_qubits, n_exc, std::max(1, o.max_batch), o);
+  const Tuning tu = choose_tuning(n_qubits - (o.taper ? 2 : 0), n_exc, std::max(1, o.max_batch), o);
   msg = build_plan(c->plan, n_qubits, n_elec, h1, h2, exc, n_exc, tu.kf, tu.ke, tu.kr,
                    o.contiguous_qubits, tu.ckpt, std::max(1, o.trotter_steps),
-                   std::max(1, o.trotter_order));
+                   std::max(1, o.trotter_order), o.taper);
   if (!msg.empty()) {
     delete c;
     return fail(UCC_EINVAL, msg);
@@ -507,7 +510,8 @@ ucc_status ucc_get_state(ucc_ctx* c, int32_t b, double* re_im) {
   if (!c || !re_im) return fail(UCC_EINVAL, "NULL argument");
   if (c->host_only) return fail(UCC_EINVAL, "context was built host_only");
   if (b < 0 || b >= c->buf.cap) return fail(UCC_EINVAL, "b out of range");
-  const int n = c->plan.n, ne = c->plan.ne;
+  const Plan& p = c->plan;
+  const int n = p.n;
   const size_t S = size_t(1) << n;
   std::vector<double> tmp(2 * S);
   hipError_t e = hipSetDevice(c->device);
@@ -515,10 +519,17 @@ ucc_status ucc_get_state(ucc_ctx* c, int32_t b, double* re_im) {
   if (e == hipSuccess)
     e = hipMemcpy(tmp.data(), c->buf.psi + b * S, S * 16, hipMemcpyDeviceToHost);
   if (e != hipSuccess) return hip_fail(e, "copy state");
-  // logical index L -> physical: occupied bits (low n_elec) move to the top
-  const uint64_t lowm = (uint64_t(1) << ne) - 1;
-  for (uint64_t L = 0; L < S; ++L) {
-    const uint64_t P = (L >> ne) | ((L & lowm) << (n - ne));
+  if (p.taper) std::memset(re_im, 0, sizeof(double) * 2 * (size_t(1) << p.nq));
+  uint64_t la = 0, lb = 0;  // stored alpha / beta orbitals, logical
+  for (int q = 0; q < n; ++q) (((p.iperm[q] & 1) ? lb : la) |= uint64_t(1) << p.iperm[q]);
+  for (uint64_t P = 0; P < S; ++P) {
+    uint64_t L = 0;
+    for (int q = 0; q < n; ++q)
+      if ((P >> q) & 1u) L |= uint64_t(1) << p.iperm[q];
+    if (p.taper) {  // the tapered orbitals hold what the others lack (by parity)
+      L |= uint64_t((p.nalpha - __builtin_popcountll(L & la)) & 1) << (p.nq - 2);
+      L |= uint64_t((p.nbeta - __builtin_popcountll(L & lb)) & 1) << (p.nq - 1);
+    }
     re_im[2 * L] = tmp[2 * P];
     re_im[2 * L + 1] = tmp[2 * P + 1];
   }
@@ -541,7 +552,9 @@ ucc_status ucc_get_plan_info(const ucc_ctx* c, ucc_plan_info* info) {
   if (!c || !info) return fail(UCC_EINVAL, "NULL argument");
   const Plan& p = c->plan;
   std::memset(info, 0, sizeof(*info));
-  info->n_qubits = p.n;
+  info->n_qubits = p.nq;
+  info->state_qubits = p.n;
+  info->taper = p.taper;
   info->n_elec = p.ne;
   info->n_exc = p.K;
   info->n_pauli = (int32_t)p.pc.size();
@@ -563,7 +576,7 @@ ucc_status ucc_get_plan_info(const ucc_ctx* c, ucc_plan_info* info) {
   info->store_states = p.ckpt ? 1 : 0;
   info->trotter_steps = p.M;
   info->trotter_order = p.order;
-  for (int q = 0; q < p.n; ++q) info->perm[q] = p.perm[q];
+  for (int q = 0; q < p.nq; ++q) info->perm[q] = p.perm[q];
   info->job_footprint = (int64_t)entry_footprint(c);
   return UCC_OK;
 }
@@ -592,7 +605,7 @@ ucc_status ucc_get_group_table(const ucc_ctx* c, uint32_t* xm, uint32_t* m, uint
   const int n = p.n;
   for (size_t g = 0; g < p.groups.size(); ++g) {
     const auto& G = p.groups[g];
-    if (xm) xm[g] = G.x;
+    if (xm) xm[g] = p.taper ? G.xt : G.x;
     if (m) m[g] = G.m;
     if (valid) valid[g] = G.valid;
     if (A)

@@ -1618,11 +1618,12 @@ hipError_t gen_k(const LaunchArgs& a, int pidx, int first, const GenPassArgs& g,
     if (k == 14) return gen_t<T, 14>(a, pidx, first, g, fused);
   if (k == 13) return gen_t<T, 13>(a, pidx, first, g, fused);
   if (k == 12) return gen_t<T, 12>(a, pidx, first, g, fused);
+  if (k == 11) return gen_t<T, 11>(a, pidx, first, g, fused);
   return gen_t<T, 0>(a, pidx, first, g, fused);
 }
 
-// Tile-size dispatch: unrolled register staging where the tile fits in at most 32 elements
-// per thread (16 for the two-vector reverse pass), a loop otherwise.
+// Tile-size dispatch: unrolled register staging for tiles of 11 to 14 local qubits (at most
+// 32 elements per thread, 16 for the two-vector reverse pass), a loop otherwise.
 template <int T>
 hipError_t fwd_k(const LaunchArgs& a, int pidx, int init, const double2* src, double2* dst) {
   const int k = a.hpasses[pidx].k;
@@ -1630,6 +1631,7 @@ hipError_t fwd_k(const LaunchArgs& a, int pidx, int init, const double2* src, do
     if (k == 14) return fwd_t<T, 14>(a, pidx, init, src, dst);
   if (k == 13) return fwd_t<T, 13>(a, pidx, init, src, dst);
   if (k == 12) return fwd_t<T, 12>(a, pidx, init, src, dst);
+  if (k == 11) return fwd_t<T, 11>(a, pidx, init, src, dst);
   return fwd_t<T, 0>(a, pidx, init, src, dst);
 }
 
@@ -1639,6 +1641,7 @@ hipError_t rev_k(const LaunchArgs& a, int pidx, double2* psi, bool wp) {
   if constexpr (T >= 512)
     if (k == 13) return rev_t<T, 13>(a, pidx, psi, wp);
   if (k == 12) return rev_t<T, 12>(a, pidx, psi, wp);
+  if (k == 11) return rev_t<T, 11>(a, pidx, psi, wp);
   return rev_t<T, 0>(a, pidx, psi, wp);
 }
 
@@ -1649,6 +1652,7 @@ hipError_t exp_k(const LaunchArgs& a, int pidx, int eslot, int first) {
     if (k == 14) return exp_t<T, 14, APPLY>(a, pidx, eslot, first);
   if (k == 13) return exp_t<T, 13, APPLY>(a, pidx, eslot, first);
   if (k == 12) return exp_t<T, 12, APPLY>(a, pidx, eslot, first);
+  if (k == 11) return exp_t<T, 11, APPLY>(a, pidx, eslot, first);
   return exp_t<T, 0, APPLY>(a, pidx, eslot, first);
 }
 

@@ -102,12 +102,16 @@ std::vector<Plan::Pass> plan_windows(const Plan& p, int kind, int k, int c0) {
     std::vector<int> keep;
     keep.reserve(rest.size());
     for (int e : rest) {
-      const uint32_t s = p.ex[p.seq[e]].supp;
-      if ((s & skipped) == 0 && pc32(cur.lmask | s) <= k && (int)cur.items.size() < kMaxPassExc) {
+      const auto& x = p.ex[p.seq[e]];
+      const uint32_t s = x.supp;
+      // the spin orbitals the factor acts on: its stored support and, tapered, the tapered
+      // orbitals it moves an electron into or out of (two factors sharing one do not commute)
+      const uint32_t so = s | (x.tsupp << p.n);
+      if ((so & skipped) == 0 && pc32(cur.lmask | s) <= k && (int)cur.items.size() < kMaxPassExc) {
         cur.items.push_back(e);
         cur.lmask |= s;
       } else {
-        skipped |= s;
+        skipped |= so;
         keep.push_back(e);
       }
     }
@@ -241,11 +245,134 @@ std::string validate_inputs(int n, int ne, const double* h1, const double* h2, c
   return "";
 }
 
+namespace {
+
+// Two-qubit tapering of a plan compiled over nq physical bits whose top two bits n = nq - 2
+// (alpha) and n + 1 (beta) hold the tapered orbitals.  Inside the sector their occupations
+// are t_a = n_alpha - sum_{q in A} n_q and t_b = n_beta - sum_{q in B} n_q (A, B: the stored
+// alpha and beta bits), so
+//   * a parity (-1)^{t_a} in a sign mask becomes (-1)^{n_alpha} times the parity over A;
+//   * an occupation term c n_{t_a} becomes c n_alpha minus c n_q for every q in A;
+// which turns every mask, sign and value table into one over the n stored bits.  What
+// depends on a tapered occupation beyond that (an excitation that moves an electron into or
+// out of a tapered orbital, a group whose x flips one) is kept (Exc::tsupp / tfrom,
+// Group::xt) and decided per state when the tile classes' pair and row lists are built.
+void taper_transform(Plan& p) {
+  const int nf = p.n, n = nf - 2;
+  const int ta = n, tb = n + 1;
+  const uint32_t keep = (1u << n) - 1u;
+  const uint32_t A = p.amask & keep, B = p.bmask & keep;
+  const int na = p.nalpha, nb = p.nbeta;
+  // groups with off-diagonal x
+  for (size_t gi = 1; gi < p.groups.size(); ++gi) {
+    auto& g = p.groups[gi];
+    const uint32_t xk = g.x & keep;
+    const bool ma = (g.m >> ta) & 1u, mb = (g.m >> tb) & 1u;
+    uint32_t m = g.m & keep;
+    if (ma) m ^= A;
+    if (mb) m ^= B;
+    std::vector<double> Bn(16 * size_t(n), 0.0);
+    const int npat = 1 << pc32(g.x);
+    for (int P = 0; P < npat; ++P) {
+      if (!((g.valid >> P) & 1u)) continue;
+      const uint32_t Pm = deposit_bits(P, g.x) & keep;  // the pattern's stored bits
+      double a = g.A[P];
+      if (g.has_occ) {
+        const double ca = g.B[P * nf + ta], cb = g.B[P * nf + tb];
+        a += ca * (na - pc32(Pm & A)) + cb * (nb - pc32(Pm & B));
+        for (int q = 0; q < n; ++q) {
+          double v = g.B[P * nf + q];
+          if (!((xk >> q) & 1u)) {
+            if ((A >> q) & 1u) v -= ca;
+            if ((B >> q) & 1u) v -= cb;
+          }
+          Bn[P * n + q] = v;
+        }
+      }
+      // constant part of the sign: (-1)^{n_alpha}, (-1)^{n_beta}, and the mask over x's own
+      // stored bits (fixed by the pattern)
+      const int e = (ma ? na : 0) + (mb ? nb : 0) + pc32(Pm & m & xk);
+      const double s = (e & 1) ? -1.0 : 1.0;
+      g.A[P] = s * a;
+      for (int q = 0; q < n; ++q) Bn[P * n + q] *= s;
+    }
+    g.xt = g.x;
+    g.x = xk;
+    g.m = m & ~xk;
+    g.has_occ = false;
+    for (double v : Bn)
+      if (v != 0.0) g.has_occ = true;
+    if (g.has_occ)
+      g.B = Bn;
+    else
+      g.B.clear();
+  }
+  p.groups[0].xt = 0;
+  // diagonal: c0 + sum_r a_r n_r + sum_{r<s} b_rs n_r n_s with t_a, t_b substituted
+  {
+    const auto& a = p.diag_a;
+    const auto& b = p.diag_b;
+    auto bb = [&](int r, int s) { return r < s ? b[r * nf + s] : b[s * nf + r]; };
+    const double aa = a[ta], ab = a[tb], bab = bb(ta, tb);
+    std::vector<double> an(n, 0.0), bn(size_t(n) * n, 0.0);
+    double c0 = p.diag_c0 + aa * na + ab * nb + bab * na * nb;
+    for (int q = 0; q < n; ++q) {
+      const bool qa = (A >> q) & 1u, qb = (B >> q) & 1u;
+      an[q] = a[q] - (qa ? aa : 0.0) - (qb ? ab : 0.0) + bb(q, ta) * (na - (qa ? 1 : 0)) +
+              bb(q, tb) * (nb - (qb ? 1 : 0)) - bab * ((qa ? nb : 0) + (qb ? na : 0));
+    }
+    for (int r = 0; r < n; ++r)
+      for (int s2 = r + 1; s2 < n; ++s2) {
+        const bool ra = (A >> r) & 1u, rb = (B >> r) & 1u, sa = (A >> s2) & 1u, sb = (B >> s2) & 1u;
+        bn[r * n + s2] = b[r * nf + s2] - (sa ? bb(r, ta) : 0.0) - (ra ? bb(s2, ta) : 0.0) -
+                         (sb ? bb(r, tb) : 0.0) - (rb ? bb(s2, tb) : 0.0) +
+                         bab * ((ra && sb) || (rb && sa) ? 1.0 : 0.0);
+      }
+    p.diag_c0 = c0;
+    p.diag_a = an;
+    p.diag_b = bn;
+  }
+  // excitations
+  for (auto& e : p.ex) {
+    const uint32_t sk = e.supp & keep, fk = e.from & keep;
+    e.tsupp = ((e.supp >> ta) & 1u) | (((e.supp >> tb) & 1u) << 1);
+    e.tfrom = ((e.from >> ta) & 1u) | (((e.from >> tb) & 1u) << 1);
+    const bool ma = (e.m >> ta) & 1u, mb = (e.m >> tb) & 1u;
+    uint32_t m = e.m & keep;
+    if (ma) m ^= A;
+    if (mb) m ^= B;
+    // on a pair's u the support's stored bits are the from-pattern: that part of the parity is
+    // a constant
+    const int x = (ma ? na : 0) + (mb ? nb : 0) + pc32(fk & m & sk);
+    if (x & 1) e.sigma = -e.sigma;
+    e.m = m & ~sk;
+    e.supp = sk;
+    e.from = fk;
+  }
+  p.amask = A;
+  p.bmask = B;
+  p.hf &= keep;
+  p.n = n;
+}
+
+// Occupations of the tapered alpha and beta orbitals for a state with local physical offset
+// ph in a tile whose global bits hold ag alpha and bg beta electrons (0 or 1 inside the
+// sector; untapered plans give 0 for every in-sector state).
+inline void tapered_occ(const Plan& p, uint32_t ph, int ag, int bg, int& oa, int& ob) {
+  oa = p.nalpha - pc32(ph & p.amask) - ag;
+  ob = p.nbeta - pc32(ph & p.bmask) - bg;
+}
+
+}  // namespace
+
 std::string build_plan(Plan& p, int n, int ne, const double* h1, const double* h2,
                        const int32_t* exc, int K, int kf, int ke, int kr, int c0, bool ckpt,
-                       int M, int order) {
+                       int M, int order, int taper) {
   p = Plan();
+  if (taper && (n < 8 || ne > n - 2)) return "taper needs n_qubits >= 8 and two empty spin orbitals";
   p.n = n;
+  p.nq = n;
+  p.taper = taper ? 1 : 0;
   p.ne = ne;
   p.ns = n / 2;
   p.K = K;
@@ -259,8 +386,11 @@ std::string build_plan(Plan& p, int n, int ne, const double* h1, const double* h
   p.h1.assign(h1, h1 + ns * ns);
   p.h2.assign(h2, h2 + ns * ns * ns * ns);
   p.exc.assign(exc, exc + 4 * K);
+  // stored bits: the virtual orbitals low, the occupied ones above; tapered plans put the two
+  // tapered (highest, virtual) orbitals on the top physical bits n - 2 and n - 1
+  const int nst = n - 2 * p.taper;
   for (int q = 0; q < n; ++q) {
-    p.perm[q] = q >= ne ? q - ne : (n - ne) + q;
+    p.perm[q] = q >= nst ? q : q >= ne ? q - ne : (nst - ne) + q;
     p.iperm[p.perm[q]] = q;
     ((q & 1) ? p.bmask : p.amask) |= 1u << p.perm[q];
     if (q < ne) p.hf |= 1u << p.perm[q];
@@ -433,6 +563,8 @@ std::string build_plan(Plan& p, int n, int ne, const double* h1, const double* h
     p.ex.push_back(e);
   }
 
+  if (p.taper) taper_transform(p);
+
   // ---- Trotter product: factors in the order they act (Eq. 5: the list, M times; Eq. 6: the
   // list and then its reverse, M times), angles scaled by 1 / (M * order).
   p.M = M;
@@ -551,18 +683,24 @@ std::vector<std::vector<std::pair<uint32_t, uint32_t>>> class_buckets(const Plan
   const uint32_t tile = 1u << pc32(lmask);
   for (uint32_t c = 0; c < tile; ++c) {
     const uint32_t ph = deposit_bits(c, lmask);
-    const int ag = p.nalpha - pc32(ph & p.amask);
-    const int bg = p.nbeta - pc32(ph & p.bmask);
-    if (ag < 0 || bg < 0 || ag > nag || bg > nbg) continue;
-    buckets[ag * (nbg + 1) + bg].push_back({c, ph});
+    // the global electrons a state of each class would need; tapered plans also admit one
+    // fewer (the tapered orbital of that spin then holds it)
+    const int ag0 = p.nalpha - pc32(ph & p.amask);
+    const int bg0 = p.nbeta - pc32(ph & p.bmask);
+    for (int ag = ag0 - p.taper; ag <= ag0; ++ag)
+      for (int bg = bg0 - p.taper; bg <= bg0; ++bg)
+        if (ag >= 0 && bg >= 0 && ag <= nag && bg <= nbg) buckets[ag * (nbg + 1) + bg].push_back({c, ph});
   }
   return buckets;
 }
 
 // Class block (layout in ucc_internal.h) of excitations `items` for one class bucket (whose
 // entries are in ascending compact order, so an in-sector state's rank is its position).
+// (ag, bg): the class's global alpha and beta electrons (tapered plans read the tapered
+// orbitals' occupations off them).
 std::vector<uint32_t> pair_block(const Plan& p, uint32_t lmask, const std::vector<int>& items,
-                                 const std::vector<std::pair<uint32_t, uint32_t>>& bucket) {
+                                 const std::vector<std::pair<uint32_t, uint32_t>>& bucket, int ag,
+                                 int bg) {
   const size_t m = items.size(), ns = bucket.size();
   std::vector<uint32_t> cs(ns);
   for (size_t i = 0; i < ns; ++i) cs[i] = bucket[i].first;
@@ -581,7 +719,14 @@ std::vector<uint32_t> pair_block(const Plan& p, uint32_t lmask, const std::vecto
     for (size_t i = 0; i < ns; ++i) {
       const uint32_t c = cs[i];
       if ((c & sc) != fc) continue;
+      if (e.tsupp) {  // the from-pattern on the tapered orbitals
+        int oa, ob;
+        tapered_occ(p, bucket[i].second, ag, bg, oa, ob);
+        if ((e.tsupp & 1u) && oa != int(e.tfrom & 1u)) continue;
+        if ((e.tsupp & 2u) && ob != int((e.tfrom >> 1) & 1u)) continue;
+      }
       const uint32_t rw = rank(c ^ sc);
+      if (rw >= ns || cs[rw] != (c ^ sc)) continue;  // cannot happen: T_k keeps the sector
       w.push_back((uint32_t)i | (uint32_t(pc32(c & mc) & 1) << 15) | (rw << 16));
     }
     w[2 + j + 1] = (uint32_t)(w.size() - ent0);
@@ -645,8 +790,9 @@ size_t exp_table_words(const Plan& p, const ExpSlots& e, int k) {
 // the source rank, the local JW sign and the slot of (group, source pattern).  With count
 // set, only the entries per group are counted.
 void exp_class_rows(const Plan& p, uint32_t L, const ExpSlots& e,
-                    const std::vector<std::pair<uint32_t, uint32_t>>& bucket, std::vector<uint32_t>* off,
-                    std::vector<uint32_t>* mid, std::vector<uint32_t>* ent, std::vector<size_t>* count) {
+                    const std::vector<std::pair<uint32_t, uint32_t>>& bucket, int ag, int bg,
+                    std::vector<uint32_t>* off, std::vector<uint32_t>* mid, std::vector<uint32_t>* ent,
+                    std::vector<size_t>* count) {
   const size_t ns = bucket.size();
   std::vector<uint32_t> cs(ns);
   for (size_t i = 0; i < ns; ++i) cs[i] = bucket[i].first;
@@ -654,7 +800,15 @@ void exp_class_rows(const Plan& p, uint32_t L, const ExpSlots& e,
   auto visit = [&](size_t i, size_t j) {
     const auto& g = p.groups[e.groups[j]];
     const uint32_t pv = bucket[i].second ^ g.x;  // local physical offset of the source
-    const uint32_t P = extract_bits(pv, g.x);
+    uint32_t P;
+    if (p.taper) {  // the source's pattern includes the tapered orbitals x flips
+      int oa, ob;
+      tapered_occ(p, pv, ag, bg, oa, ob);
+      if (oa < 0 || oa > 1 || ob < 0 || ob > 1) return;
+      P = extract_bits(pv | (uint32_t(oa) << p.n) | (uint32_t(ob) << (p.n + 1)), g.xt);
+    } else {
+      P = extract_bits(pv, g.x);
+    }
     if (!((g.valid >> P) & 1u)) return;
     if (count) {
       (*count)[j] += 1;
@@ -662,6 +816,7 @@ void exp_class_rows(const Plan& p, uint32_t L, const ExpSlots& e,
     }
     const uint32_t cv = cs[i] ^ compact_bits(g.x, L);
     const uint32_t rv = (uint32_t)(std::lower_bound(cs.begin(), cs.end(), cv) - cs.begin());
+    if (rv >= ns || cs[rv] != cv) return;  // cannot happen: a valid pattern keeps the sector
     const uint32_t slot = (uint32_t)e.slot_base[j] + (uint32_t)pc32(g.valid & ((1u << P) - 1u));
     const uint32_t sg = pc32(pv & g.m & L) & 1;
     ent->push_back(rv | (sg << 15) | (slot << 16));
@@ -855,7 +1010,10 @@ int max_class_size(const Plan& p, uint32_t lmask) {
 
 int max_pair_block_words(const Plan& p, uint32_t lmask, const std::vector<int>& items) {
   size_t mx = 0;
-  for (auto& b : class_buckets(p, lmask)) mx = std::max(mx, pair_block(p, lmask, items, b).size());
+  int nbg = 0;
+  const auto bks = class_buckets(p, lmask, &nbg);
+  for (size_t c = 0; c < bks.size(); ++c)
+    mx = std::max(mx, pair_block(p, lmask, items, bks[c], int(c) / (nbg + 1), int(c) % (nbg + 1)).size());
   return (int)mx;
 }
 
@@ -953,10 +1111,12 @@ void build_tables(const Plan& p, Tables& t) {
       dp.stage_len = 0;
       dp.ns_max = 0;
       size_t rows = 0, entries = 0;
-      for (auto& bk : buckets) {
+      for (size_t ci = 0; ci < buckets.size(); ++ci) {
+        const auto& bk = buckets[ci];
         const size_t ns = bk.size();
         std::vector<uint32_t> off, mid, ent;
-        exp_class_rows(p, ps.lmask, e, bk, &off, &mid, &ent, nullptr);
+        exp_class_rows(p, ps.lmask, e, bk, int(ci) / (nbg + 1), int(ci) % (nbg + 1), &off, &mid, &ent,
+                       nullptr);
         rows += ns;
         entries += ent.size();
         std::vector<uint32_t> blk;
@@ -1001,8 +1161,10 @@ void build_tables(const Plan& p, Tables& t) {
       dp.nbeta_g = nbg;
       dp.stage_len = 0;
       dp.ns_max = 0;
-      for (auto& bk : buckets) {
-        std::vector<uint32_t> blk = pair_block(p, ps.lmask, ps.items, bk);
+      for (size_t ci = 0; ci < buckets.size(); ++ci) {
+        const auto& bk = buckets[ci];
+        std::vector<uint32_t> blk =
+            pair_block(p, ps.lmask, ps.items, bk, int(ci) / (nbg + 1), int(ci) % (nbg + 1));
         while (t.pairs.size() % 4) t.pairs.push_back(0u);  // 16-byte aligned blocks
         t.cls.push_back((int32_t)t.pairs.size());
         t.cls.push_back((int32_t)blk.size());

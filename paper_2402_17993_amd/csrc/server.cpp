@@ -43,7 +43,7 @@ bool batch_compatible(const ucc_ctx* a, const ucc_ctx* b) {
   if (a == b) return true;
   const Plan& p = a->plan;
   const Plan& q = b->plan;
-  if (p.n != q.n || p.ne != q.ne || p.K != q.K || p.kf != q.kf || p.ke != q.ke || p.kr != q.kr ||
+  if (p.n != q.n || p.nq != q.nq || p.taper != q.taper || p.ne != q.ne || p.K != q.K || p.kf != q.kf || p.ke != q.ke || p.kr != q.kr ||
       p.c0f != q.c0f ||
       p.c0e != q.c0e || p.c0r != q.c0r || p.tf != q.tf || p.te != q.te || p.tr != q.tr ||
       p.launch_mode != q.launch_mode || p.nfwd != q.nfwd || p.nexp != q.nexp || p.nrev != q.nrev ||

@@ -439,6 +439,7 @@ ucc_status ucc_energy_trotter_free(ucc_ctx* c, const double* theta, int32_t B, d
   g_last_error.clear();
   if (!c) return fail(UCC_EINVAL, "ctx is NULL");
   if (c->host_only) return fail(UCC_EINVAL, "context was built host_only");
+  if (c->plan.taper) return fail(UCC_EINVAL, "the Trotter-free calls do not take tapered contexts");
   if (B < 1 || B > 65535) return fail(UCC_EINVAL, "B must be in [1, 65535]");
   if (!theta || !energy) return fail(UCC_EINVAL, "NULL output or input");
   if (c->busy) return fail(UCC_EBUSY, "context is in use by a server job");
@@ -473,6 +474,7 @@ ucc_status ucc_energy_grad_trotter_free(ucc_ctx* c, const double* theta, int32_t
   g_last_error.clear();
   if (!c) return fail(UCC_EINVAL, "ctx is NULL");
   if (c->host_only) return fail(UCC_EINVAL, "context was built host_only");
+  if (c->plan.taper) return fail(UCC_EINVAL, "the Trotter-free calls do not take tapered contexts");
   if (B < 1 || B > 65535) return fail(UCC_EINVAL, "B must be in [1, 65535]");
   if (!theta || !energy || !grad) return fail(UCC_EINVAL, "NULL output or input");
   if (c->busy) return fail(UCC_EBUSY, "context is in use by a server job");
@@ -507,6 +509,7 @@ ucc_status ucc_get_generator_passes(ucc_ctx* c, int32_t cap, uint32_t* local, in
                                     int32_t* n_passes) {
   g_last_error.clear();
   if (!c || !n_passes) return fail(UCC_EINVAL, "NULL argument");
+  if (c->plan.taper) return fail(UCC_EINVAL, "the Trotter-free calls do not take tapered contexts");
   ucc_status s = ensure_gen_plan(c, false);
   if (s != UCC_OK) return s;
   const Plan& g = c->gen.plan;
@@ -524,6 +527,7 @@ ucc_status ucc_get_partials_passes(ucc_ctx* c, int32_t cap, uint32_t* local, int
                                    int32_t* n_passes) {
   g_last_error.clear();
   if (!c || !n_passes) return fail(UCC_EINVAL, "NULL argument");
+  if (c->plan.taper) return fail(UCC_EINVAL, "the Trotter-free calls do not take tapered contexts");
   ucc_status s = ensure_gen_plan(c, false);
   if (s != UCC_OK) return s;
   const Plan& q = c->gen.pplan;

@@ -22,9 +22,9 @@ int pick(int fixed_kind, int fixed_all, int table) {
 }
 
 struct Key {
-  int n, ne, L, B, ck;  // L: factors of the Trotter product
+  int n, ne, L, B, ck, taper;  // L: factors of the Trotter product
   bool operator<(const Key& o) const {
-    return std::tie(n, ne, L, B, ck) < std::tie(o.n, o.ne, o.L, o.B, o.ck);
+    return std::tie(n, ne, L, B, ck, taper) < std::tie(o.n, o.ne, o.L, o.B, o.ck, o.taper);
   }
 };
 
@@ -47,11 +47,14 @@ Tuning choose_tuning(int n, int K, int batch, const ucc_options& o) {
   (void)batch;
   Tuning t;
   t.ckpt = stores_states(n, o);
-  t.kf = o.tile_qubits ? o.tile_qubits : std::min(n, 14);
-  t.ke = o.tile_qubits_exp ? o.tile_qubits_exp : std::min(n, 14);
-  t.kr = o.tile_qubits_rev ? o.tile_qubits_rev : std::min(n, 13);
+  // n: stored qubits.  A tapered state keeps the same in-sector amplitudes in a quarter of the
+  // index space, so the same LDS holds the in-sector part of tiles two qubits smaller.
+  const int d = o.taper ? 2 : 0;
+  t.kf = o.tile_qubits ? o.tile_qubits : std::min(n, 14 - d);
+  t.ke = o.tile_qubits_exp ? o.tile_qubits_exp : std::min(n, 14 - d);
+  t.kr = o.tile_qubits_rev ? o.tile_qubits_rev : std::min(n, 13 - d);
   if (t.ckpt) {  // one tile size for both sweeps, at most the reverse pass's 13
-    const int k = o.tile_qubits ? o.tile_qubits : o.tile_qubits_rev ? o.tile_qubits_rev : 13;
+    const int k = o.tile_qubits ? o.tile_qubits : o.tile_qubits_rev ? o.tile_qubits_rev : 13 - d;
     t.kf = t.kr = std::min(n, k);
   }
   // One-tile states are latency-bound: small workgroups.  Multi-tile states: large
@@ -85,7 +88,7 @@ std::vector<int> tile_candidates(int fixed, int n, std::initializer_list<int> ks
 ucc_status autotune(ucc_ctx* c, int B) {
   const ucc_options& o = c->opt;
   Plan& p = c->plan;
-  const Key key{p.n, p.ne, (int)p.seq.size(), B, p.ckpt ? 1 : 0};
+  const Key key{p.n, p.ne, (int)p.seq.size(), B, p.ckpt ? 1 : 0, p.taper};
   {
     std::lock_guard<std::mutex> lock(g_cache_mu);
     auto it = g_cache.find(key);
@@ -100,13 +103,14 @@ ucc_status autotune(ucc_ctx* c, int B) {
   }
   // with stored states the forward and reverse passes share one tile size
   const bool ck = p.ckpt;
+  const int d = p.taper ? 2 : 0;  // tapered states: tiles two qubits smaller (see choose_tuning)
   const std::vector<int> kfs =
-      ck ? tile_candidates(o.tile_qubits ? o.tile_qubits : o.tile_qubits_rev, p.n, {13, 12})
-         : tile_candidates(o.tile_qubits, p.n, {14, 13});
-  const std::vector<int> kes = tile_candidates(o.tile_qubits_exp, p.n, {14, 13});
+      ck ? tile_candidates(o.tile_qubits ? o.tile_qubits : o.tile_qubits_rev, p.n, {13 - d, 12 - d})
+         : tile_candidates(o.tile_qubits, p.n, {14 - d, 13 - d});
+  const std::vector<int> kes = tile_candidates(o.tile_qubits_exp, p.n, {14 - d, 13 - d});
   // a recomputing sweep may take the forward sweep's 14 local qubits (its windows are then the
   // forward windows in mirror order; two-vector tiles in the non-overlapped pass)
-  const std::vector<int> krs = ck ? kfs : tile_candidates(o.tile_qubits_rev, p.n, {14, 13});
+  const std::vector<int> krs = ck ? kfs : tile_candidates(o.tile_qubits_rev, p.n, {14 - d, 13 - d});
   std::vector<int> ts;
   for (int t : {256, 512, 1024})
     if (!o.block_threads || t == o.block_threads) ts.push_back(t);

@@ -105,8 +105,20 @@ struct DevPass {
 };
 
 // Host-side plan: everything ucc_build derives from the inputs.
+//
+// Two-qubit tapering (taper = 1): the alpha and beta spin orbitals of the highest spatial
+// orbital are not stored.  Every term of H and every factor conserves the alpha and the beta
+// electron numbers, so inside the HF sector the occupation of such an orbital is the number
+// of electrons of its spin that the other orbitals lack (0 or 1).  The state index then has
+// n = nq - 2 bits: the planner compiles everything over nq physical bits (the two tapered
+// orbitals on physical bits n and n + 1), then folds the tapered occupations into the masks,
+// signs and value tables over the n stored bits, and decides the per-state conditions that
+// involve them (an excitation's from-pattern, a group's source pattern) when it lists the
+// pairs and row entries of each tile class.
 struct Plan {
   int n = 0, ne = 0, ns = 0, K = 0;
+  int nq = 0;     // spin orbitals (logical qubits); n = nq - 2 when tapered, else nq
+  int taper = 0;  // 1: the two highest spin orbitals are tapered
   int nalpha = 0, nbeta = 0;
   uint64_t nsec = 0;  // basis states with N = ne, S_z = 0
   std::vector<double> h1, h2;
@@ -122,6 +134,7 @@ struct Plan {
   // Compiled groups (physical).  groups[0] is the diagonal group.
   struct Group {
     uint32_t x = 0, m = 0;
+    uint32_t xt = 0;  // tapered plans: x over the nq physical bits (source patterns are read on it)
     uint32_t valid = 0;
     double A[16] = {0};
     bool has_occ = false;
@@ -135,6 +148,9 @@ struct Plan {
   struct Exc {
     uint32_t supp = 0, from = 0, m = 0;
     int sigma = 1, nsup = 0;
+    // tapered plans: which tapered orbitals (bit 0 alpha, bit 1 beta) the excitation moves an
+    // electron into or out of, and their occupation on its from-pattern
+    uint32_t tsupp = 0, tfrom = 0;
   };
   std::vector<Exc> ex;
   // Trotter product (Eqs. 5, 6): the amplitude index of each factor in the order they act,
@@ -184,9 +200,10 @@ std::string validate_inputs(int n, int ne, const double* h1, const double* h2, c
                             int K);
 // ckpt: reverse passes mirror the forward passes (kr is then ignored; see Plan::ckpt).
 // M, order: the Trotter product (Eq. 5 with M slices, or Eq. 6 with order 2).
+// taper: two-qubit tapering (see Plan); n is the number of spin orbitals either way.
 std::string build_plan(Plan& p, int n, int ne, const double* h1, const double* h2,
                        const int32_t* exc, int K, int kf, int ke, int kr, int c0, bool ckpt,
-                       int M = 1, int order = 1);
+                       int M = 1, int order = 1, int taper = 0);
 void build_tables(const Plan& p, Tables& t);
 // Trotter-free evaluation (Sec. 3.2): the generator A = sum_k theta_k G_k written as x-groups,
 // one per excitation (x = its support, values +-sigma_k on the two patterns G_k connects, no

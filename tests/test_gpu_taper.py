@@ -1,0 +1,139 @@
+"""GPU parity of two-qubit tapered contexts (option taper = 1, the paper's two removed qubits,
+Sec. 2.3) against the unchanged Jordan-Wigner oracle: the energy of the same fermionic ansatz
+does not depend on the qubit encoding, so every tapered energy and gradient must match the
+oracle's to |dE| <= 1e-10 Ha, max_k |dg_k| <= 1e-9, and the stored amplitudes must be the
+oracle's state on the sector.
+"""
+import json
+import os
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import ansatz, hamiltonian, sector
+from paper_2402_17993_amd.inputs import make_integrals, make_thetas, uccsd_excitations
+
+pytestmark = pytest.mark.gpu
+
+E_TOL = 1e-10
+G_TOL = 1e-9
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+def say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def ucc():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_2402_17993_amd import ucc as u
+    u.lib()
+    return u
+
+
+def oracle_eg(n, ne, seed, th):
+    h1, h2 = make_integrals(n // 2, seed)
+    h, g = hamiltonian.spin_orbital_integrals(h1, h2)
+    return sector.energy_and_gradient(h, g, n, (1 << ne) - 1, uccsd_excitations(n, ne), th)
+
+
+@pytest.mark.parametrize("n,ne,seed,kw", [
+    (8, 4, 0, {}),                                                    # one launch (one tile)
+    (12, 8, 1, {}),                                                   # one launch
+    (12, 8, 1, dict(tile_qubits=6, tile_qubits_exp=7, tile_qubits_rev=6)),   # many tiles, stored
+    (12, 4, 2, dict(tile_qubits=5, tile_qubits_exp=6, tile_qubits_rev=7, store_states=2)),
+    (16, 8, 3, {}),
+    (16, 8, 3, dict(store_states=2)),
+    (20, 16, 0, {}),                                                  # the paper's dimer size
+])
+def test_tapered_energy_gradient_against_oracle(ucc, n, ne, seed, kw):
+    say(f"case: tapered {n}q/{ne}e seed {seed} {kw}")
+    h1, h2 = make_integrals(n // 2, seed)
+    exc = uccsd_excitations(n, ne)
+    th = make_thetas(len(exc), seed + 1, 0.1)
+    ctx = ucc.Context(n, ne, h1, h2, exc, taper=1, **kw)
+    info = ctx.plan_info()
+    assert info["taper"] == 1 and info["state_qubits"] == n - 2
+    e, g = ctx.energy_grad(th)
+    e_ref, g_ref = oracle_eg(n, ne, seed, th)
+    say(f"|dE| {abs(e[0] - e_ref):.2e}, max |dg| {np.max(np.abs(g[0] - g_ref)):.2e}, "
+        f"passes {info['n_fwd_passes']}/{info['n_exp_passes']}/{info['n_rev_passes']}")
+    assert abs(e[0] - e_ref) <= E_TOL
+    assert np.max(np.abs(g[0] - g_ref)) <= G_TOL
+    assert abs(ctx.energy(th)[0] - e_ref) <= E_TOL
+    ctx.close()
+
+
+def test_tapered_state_is_the_oracle_state(ucc):
+    say("case: tapered 12q/8e stored state against the oracle's Trotter state")
+    n, ne = 12, 8
+    h1, h2 = make_integrals(n // 2, 4)
+    exc = uccsd_excitations(n, ne)
+    th = make_thetas(len(exc), 5, 0.2)
+    ref = ansatz.trotter_state(n, (1 << ne) - 1, exc, th)
+    for kw in ({}, dict(tile_qubits=6, tile_qubits_exp=7)):
+        ctx = ucc.Context(n, ne, h1, h2, exc, taper=1, **kw)
+        ctx.energy(th)
+        st = ctx.state(0)
+        assert np.max(np.abs(st - ref)) <= 1e-12, kw
+        ctx.close()
+
+
+def test_tapered_18q_batch64_against_stored_oracle_values(ucc):
+    say("case: tapered 18q/10e batch 64 energy+grad against all 64 stored oracle entries")
+    gold = json.load(open(os.path.join(HERE, "golden", "dimer_18q.json")))
+    n, ne = gold["n"], gold["ne"]
+    h1, h2 = make_integrals(n // 2, gold["integral_seed"])
+    exc = uccsd_excitations(n, ne)
+    th = make_thetas(len(exc), gold["theta_seed"], gold["theta_scale"], batch=gold["batch"])
+    for kw in (dict(), dict(autotune=True)):
+        ctx = ucc.Context(n, ne, h1, h2, exc, max_batch=64, taper=1, **kw)
+        say(f"plan: {ctx.plan_info()}")
+        e, gr = ctx.energy_grad(th)
+        for b, ent in gold["entries"].items():
+            b = int(b)
+            assert abs(e[b] - ent["energy"]) <= E_TOL, b
+            assert np.max(np.abs(gr[b] - np.array(ent["grad"]))) <= G_TOL, b
+        solo = ucc.Context(n, ne, h1, h2, exc, taper=1, **kw)
+        e1, g1 = solo.energy_grad(th[7])
+        assert e1[0] == e[7] and np.array_equal(g1[0], gr[7])
+        ctx.close()
+        solo.close()
+
+
+@pytest.mark.parametrize("name", ["large_24q", "large_26q"])
+def test_tapered_large_against_stored_oracle_values(ucc, name):
+    gold = json.load(open(os.path.join(HERE, "golden", f"{name}.json")))
+    n, ne = gold["n"], gold["ne"]
+    say(f"case: tapered {n}q/{ne}e seed 0 energy+grad (all {gold['n_exc']} components)")
+    h1, h2 = make_integrals(n // 2, gold["integral_seed"])
+    exc = uccsd_excitations(n, ne)
+    th = make_thetas(len(exc), gold["theta_seed"], gold["theta_scale"])
+    ctx = ucc.Context(n, ne, h1, h2, exc, taper=1)
+    e, gr = ctx.energy_grad(th)
+    de = abs(e[0] - gold["energy"])
+    dg = float(np.max(np.abs(gr[0] - np.array(gold["grad"]))))
+    say(f"|dE| {de:.2e}, max |dg| {dg:.2e}")
+    assert de <= E_TOL and dg <= G_TOL
+    ctx.close()
+
+
+def test_tapered_jobs_served_alone_and_in_the_mix(ucc):
+    say("case: tapered 12q and 16q jobs served together and alone")
+    from paper_2402_17993_amd.ucc import Server
+    ctxs = [ucc.Context(12, 8, *make_integrals(6, 31), uccsd_excitations(12, 8), max_batch=0, taper=1),
+            ucc.Context(16, 8, *make_integrals(8, 32), uccsd_excitations(16, 8), max_batch=0, taper=1)]
+    ths = [make_thetas(c.n_exc, 40 + i, 0.05) for i, c in enumerate(ctxs)]
+    with Server(slots=4) as srv:
+        mix = [srv.wait(t) for t in [srv.submit(c, th, 3, 0.1) for c, th in zip(ctxs, ths)]]
+    for c, th, r in zip(ctxs, ths, mix):
+        with Server(slots=4) as srv:
+            alone = srv.wait(srv.submit(c, th, 3, 0.1))
+        assert np.array_equal(alone["energies"], r["energies"]) and np.array_equal(alone["theta"], r["theta"])
+    # and the first energy of the 12-qubit job is the oracle's
+    e_ref = oracle_eg(12, 8, 31, ths[0])[0]
+    assert abs(mix[0]["energies"][0] - e_ref) <= E_TOL

@@ -394,3 +394,109 @@ def test_recomputing_sweep_at_the_forward_tile_size_takes_as_many_windows():
     assert ctx14["store_states"] == 0 and ctx14["tile_qubits_rev"] == 14
     assert ctx14["n_rev_passes"] <= ctx14["n_fwd_passes"] == 98
     assert ctx13["n_rev_passes"] > 2 * ctx14["n_rev_passes"]
+
+
+# ---------------------------------------------------------------- two-qubit tapering
+
+def tapered_maps(ctx, n, ne):
+    """Stored index -> logical basis state (tapered orbitals filled with what the stored ones
+    lack), and the stored sector mask."""
+    info = ctx.plan_info()
+    ns_ = info["state_qubits"]
+    assert info["taper"] == 1 and ns_ == n - 2
+    perm = np.array(info["perm"])
+    v = np.arange(1 << ns_)
+    L = np.zeros_like(v)
+    for q in range(n - 2):
+        L |= ((v >> perm[q]) & 1) << q
+    la = sum(1 << q for q in range(0, n - 2, 2))
+    lb = sum(1 << q for q in range(1, n - 2, 2))
+    oa = ne // 2 - np.bitwise_count(L & la).astype(np.int64)
+    ob = ne // 2 - np.bitwise_count(L & lb).astype(np.int64)
+    sec = (oa >= 0) & (oa <= 1) & (ob >= 0) & (ob <= 1)
+    L = L | (np.clip(oa, 0, 1) << (n - 2)) | (np.clip(ob, 0, 1) << (n - 1))
+    return v, L, sec, oa, ob
+
+
+@pytest.mark.parametrize("ns,ne,seed", [(4, 4, 0), (5, 6, 2), (5, 4, 3), (6, 6, 1)])
+def test_tapered_group_table_reproduces_hamiltonian(ns, ne, seed):
+    """The tapered value tables (occupations of the two tapered orbitals folded into masks,
+    signs and occupation rows) give the oracle's <a|H|b> on the sector, entry by entry."""
+    n = 2 * ns
+    ctx, h1, h2, _ = host_ctx(n, ne, seed, taper=1)
+    tab = ctx.group_table()
+    h, g = hamiltonian.spin_orbital_integrals(h1, h2)
+    v, L, sec, oa, ob = tapered_maps(ctx, n, ne)
+    nst = n - 2
+    S = np.flatnonzero(sec)
+    Hp = np.zeros((1 << nst, 1 << nst))
+    pos = {int(L[s]): int(s) for s in S}
+    for s in S:
+        e = np.zeros(1 << n, dtype=complex)
+        e[L[s]] = 1.0
+        col = hamiltonian.apply_h(h, g, e).real
+        for lo in np.flatnonzero(col):
+            Hp[pos[int(lo)], s] = col[lo]  # every image is in the sector
+    occ = ((v[:, None] >> np.arange(nst)) & 1).astype(float)
+    Hc = np.zeros_like(Hp)
+    Hc[v, v] += tab["c0"] + occ @ tab["a"] + np.einsum("vr,rs,vs->v", occ, np.triu(tab["b"], 1), occ)
+    vt = v | (np.clip(oa, 0, 1) << nst) | (np.clip(ob, 0, 1) << (nst + 1))
+    keep = (1 << nst) - 1
+    for gi in range(1, len(tab["x"])):
+        xt = int(tab["x"][gi])
+        pos_ = [q for q in range(n) if (xt >> q) & 1]
+        P = sum(((vt >> p) & 1) << j for j, p in enumerate(pos_))
+        ok = sec & ((tab["valid"][gi] >> P) & 1 == 1)
+        val = tab["A"][gi][P] + np.einsum("vr,vr->v", occ, tab["B"][gi][P])
+        sgn = np.where(np.bitwise_count(v & int(tab["m"][gi])) & 1, -1.0, 1.0)
+        vv = v[ok]
+        Hc[vv ^ (xt & keep), vv] += (sgn * val)[ok]
+    np.testing.assert_allclose(Hc[np.ix_(S, S)], Hp[np.ix_(S, S)], atol=1e-12)
+
+
+@pytest.mark.parametrize("n,ne", [(8, 4), (10, 6), (12, 4)])
+def test_tapered_excitation_signs_match_ladder_operators(n, ne):
+    ctx, _, _, exc = host_ctx(n, ne, taper=1)
+    t = ctx.excitation_table()
+    v, L, sec, _, _ = tapered_maps(ctx, n, ne)
+    stored = {int(L[s]): int(s) for s in np.flatnonzero(sec)}
+    for k, row in enumerate(exc):
+        src, dst, s = ansatz.excitation_pairs(n, row)
+        ins = np.array([int(x) in stored for x in src])
+        up = np.array([stored[int(x)] for x in src[ins]])
+        vp = np.array([stored[int(x)] for x in dst[ins]])
+        assert np.all((up & int(t["supp"][k])) == int(t["frm"][k]))
+        assert np.all((up ^ vp) == int(t["supp"][k]))
+        pred = t["sigma"][k] * np.where(np.bitwise_count(up & int(t["m"][k])) & 1, -1, 1)
+        assert np.array_equal(pred, s[ins])
+
+
+def test_tapered_plan_sizes_and_rejections():
+    ctx = host_ctx(18, 10, taper=1)[0]
+    info = ctx.plan_info()
+    assert info["n_qubits"] == 18 and info["state_qubits"] == 16 and info["taper"] == 1
+    assert info["job_footprint"] < host_ctx(18, 10)[0].plan_info()["job_footprint"] / 3
+    with pytest.raises(ucc.UCCError):
+        host_ctx(6, 2, taper=1)
+    with pytest.raises(ucc.UCCError):
+        ctx.generator_passes()
+
+
+@pytest.mark.parametrize("n,ne,kw", [(12, 4, dict(tile_qubits=5, tile_qubits_exp=6, tile_qubits_rev=7,
+                                                  store_states=2)),
+                                     (16, 8, dict(store_states=2)), (12, 8, dict(tile_qubits=6))])
+def test_tapered_windows_keep_non_commuting_factors_in_order(n, ne, kw):
+    """Tapered plans: factors that share a tapered orbital act on it although their stored
+    supports are disjoint; the windows may exchange only factors on disjoint spin orbitals
+    (counted over all n_qubits orbitals), in both sweeps and for a magnitude-ordered list."""
+    h1, h2 = make_integrals(n // 2, 0)
+    exc = uccsd_excitations(n, ne)
+    orb = np.array([sum(1 << int(q) for q in row if q >= 0) for row in exc])
+    for order in (np.arange(len(exc)), inputs.magnitude_order(h1, h2, ne, exc)):
+        ctx = ucc.Context(n, ne, h1, h2, exc[order], host_only=True, taper=1, **kw)
+        passes = ctx.pass_table()
+        fwd = np.concatenate([p["items"] for p in passes if p["kind"] == 0])
+        rev = np.concatenate([p["items"] for p in passes if p["kind"] == 2])
+        K = len(exc)
+        check_commuting_reorder(fwd, np.arange(K), orb[order])
+        check_commuting_reorder(rev, np.arange(K)[::-1], orb[order])
