@@ -542,27 +542,30 @@ def cpu_small():
 MIX = {"monomer": (12, 8), "dimer": (18, 10), "trimer": (24, 14)}
 
 
-def serving_mix(ucc, n_arrivals, rate=200.0, iters=30, lr=0.1, seed=0):
-    """FMO-like serving trace: Poisson arrivals at `rate`/s of monomer / dimer / trimer VQE
-    jobs in ratio 3:3:1, job i with integrals from seed 1000 + i and theta0 ~ U(-0.05, 0.05)
-    from seed 2000 + i, `iters` steepest-descent steps each.  Contexts are built before the
-    clock starts; latency runs from submission to the last energy."""
+def build_jobs(ucc, kinds, first_seed=0, workers=16):
+    """Contexts and starting amplitudes of serving jobs (job i: integrals seed 1000 + i,
+    theta0 U(-0.05, 0.05) from seed 2000 + i), built in parallel host threads (the planner is
+    host C++ and releases the interpreter lock)."""
+    import concurrent.futures
+
     from paper_2402_17993_amd.inputs import make_integrals, make_thetas, uccsd_excitations
 
-    rng = np.random.default_rng(seed)
-    arrive = np.cumsum(rng.exponential(1.0 / rate, n_arrivals))
-    kinds = [("monomer", "dimer", "trimer")[min(2, int(k) // 3)] for k in rng.integers(0, 7, n_arrivals)]
-    t0 = time.perf_counter()
-    jobs = []
-    for i, kind in enumerate(kinds):
-        n, ne = MIX[kind]
-        h1, h2 = make_integrals(n // 2, 1000 + i)
+    def one(i):
+        n, ne = MIX[kinds[i]]
+        h1, h2 = make_integrals(n // 2, 1000 + first_seed + i)
         exc = uccsd_excitations(n, ne)
         ctx = ucc.Context(n, ne, h1, h2, exc, max_batch=0, device=0)
-        jobs.append((kind, ctx, make_thetas(len(exc), 2000 + i, 0.05)))
-    build_s = time.perf_counter() - t0
+        return (kinds[i], ctx, make_thetas(len(exc), 2000 + first_seed + i, 0.05))
+
+    with concurrent.futures.ThreadPoolExecutor(max_workers=workers) as ex:
+        return list(ex.map(one, range(len(kinds))))
+
+
+def run_trace(ucc, jobs, arrive, iters, lr, slots=256):
+    """Submit job i at arrive[i] seconds after the start; wait for all.  Returns the results
+    and the makespan (start to the last completion)."""
     res = []
-    with ucc.Server(slots=256) as srv:
+    with ucc.Server(slots=slots) as srv:
         start = time.perf_counter()
         tickets = []
         for i, (kind, ctx, th) in enumerate(jobs):
@@ -574,24 +577,48 @@ def serving_mix(ucc, n_arrivals, rate=200.0, iters=30, lr=0.1, seed=0):
             res.append(srv.wait(t))
         makespan = time.perf_counter() - start
     assert all(r["status"] == 0 for r in res)
+    return res, makespan
+
+
+def mix_kinds(rng, n):
+    """Monomer : dimer : trimer = 3 : 3 : 1."""
+    return [("monomer", "dimer", "trimer")[min(2, int(k) // 3)] for k in rng.integers(0, 7, n)]
+
+
+def latency_stats(kinds, res):
     lat = np.array([r["done_s"] for r in res])
     per_it = np.array([(r["done_s"] - r["admit_s"]) / r["rounds"] for r in res])
-    out = {"arrivals": n_arrivals, "trace_s": float(arrive[-1]), "rate_per_s": rate,
-           "iters": iters, "jobs": {k: kinds.count(k) for k in MIX},
-           "makespan_s": makespan, "evals_per_s": len(res) * (iters + 1) / makespan,
-           # the trace overloads the server, so completions per second of makespan are the
-           # largest arrival rate of this mix it sustains
-           "sustained_jobs_per_s": len(res) / makespan,
-           "latency_p50_s": float(np.percentile(lat, 50)), "latency_p99_s": float(np.percentile(lat, 99)),
+    out = {"latency_p50_s": float(np.percentile(lat, 50)), "latency_p99_s": float(np.percentile(lat, 99)),
            "per_iteration_p50_ms": 1e3 * float(np.percentile(per_it, 50)),
-           "per_iteration_p99_ms": 1e3 * float(np.percentile(per_it, 99)),
-           "context_build_s": build_s, "by_kind": {}}
+           "per_iteration_p99_ms": 1e3 * float(np.percentile(per_it, 99)), "by_kind": {}}
     for k in MIX:
         sel = [j for j, kind in enumerate(kinds) if kind == k]
         if sel:
-            out["by_kind"][k] = {"latency_p50_s": float(np.percentile(lat[sel], 50)),
+            out["by_kind"][k] = {"jobs": len(sel), "latency_p50_s": float(np.percentile(lat[sel], 50)),
                                  "latency_p99_s": float(np.percentile(lat[sel], 99)),
-                                 "per_iteration_p50_ms": 1e3 * float(np.percentile(per_it[sel], 50))}
+                                 "per_iteration_p50_ms": 1e3 * float(np.percentile(per_it[sel], 50)),
+                                 "per_iteration_p99_ms": 1e3 * float(np.percentile(per_it[sel], 99))}
+    return out
+
+
+def serving_mix(ucc, n_arrivals, rate=200.0, iters=30, lr=0.1, seed=0):
+    """FMO-like serving trace: the first n_arrivals Poisson(rate) arrivals of monomer (12q/8e)
+    / dimer (18q/10e) / trimer (24q/14e) VQE jobs in ratio 3:3:1, `iters` steepest-descent
+    steps each.  Contexts are built before the clock starts; latency runs from submission to
+    the last energy.  The offered load exceeds what one device serves, so the queue grows over
+    the trace; completions over the makespan are the sustained rate under that overload."""
+    rng = np.random.default_rng(seed)
+    arrive = np.cumsum(rng.exponential(1.0 / rate, n_arrivals))
+    kinds = mix_kinds(rng, n_arrivals)
+    t0 = time.perf_counter()
+    jobs = build_jobs(ucc, kinds)
+    build_s = time.perf_counter() - t0
+    res, makespan = run_trace(ucc, jobs, arrive, iters, lr)
+    out = {"arrivals": n_arrivals, "trace_s": float(arrive[-1]), "rate_per_s": rate,
+           "iters": iters, "jobs": {k: kinds.count(k) for k in MIX},
+           "makespan_s": makespan, "evals_per_s": len(res) * (iters + 1) / makespan,
+           "completed_jobs_per_s": len(res) / makespan, "context_build_s": build_s}
+    out.update(latency_stats(kinds, res))
     # alone vs in the mix: the first job of each kind again, alone
     same = True
     for k in ("monomer", "dimer", "trimer"):
@@ -603,6 +630,44 @@ def serving_mix(ucc, n_arrivals, rate=200.0, iters=30, lr=0.1, seed=0):
             same &= bool(np.array_equal(r["energies"], res[j]["energies"]) and
                          np.array_equal(r["theta"], res[j]["theta"]))
     out["alone_equals_mix_bitwise"] = same
+    for _, ctx, _ in jobs:
+        ctx.close()
+    return out
+
+
+def serving_sweep(ucc, rates=(1.0, 2.0, 4.0, 5.0, 6.0, 7.0, 8.0), trace_s=6.0, iters=30, lr=0.1, seed=1):
+    """Largest sustainable arrival rate of the serving mix: Poisson arrivals at each rate for
+    `trace_s` seconds (same 3:3:1 mix and 30-step jobs as the trace); a rate is sustained when
+    the p99 job latency stays within twice the p99 at the lowest rate (the queue does not
+    grow over the trace).  One set of contexts serves every rate (job i of each trace reuses
+    context i)."""
+    rng = np.random.default_rng(seed)
+    nmax = int(max(rates) * trace_s * 1.5) + 8
+    kinds = mix_kinds(rng, nmax)
+    jobs = build_jobs(ucc, kinds, first_seed=5000)
+    out = {"trace_s": trace_s, "iters": iters, "points": []}
+    base_p99 = None
+    best = 0.0
+    for r in rates:
+        arr = np.cumsum(np.random.default_rng(seed + int(10 * r)).exponential(1.0 / r, nmax))
+        m = int(np.searchsorted(arr, trace_s))
+        res, makespan = run_trace(ucc, jobs[:m], arr[:m], iters, lr)
+        st = latency_stats(kinds[:m], res)
+        p99 = st["latency_p99_s"]
+        if base_p99 is None:
+            base_p99 = p99
+        ok = p99 <= 2.0 * base_p99
+        if ok:
+            best = r
+        out["points"].append({"rate_per_s": r, "jobs": m, "makespan_s": makespan,
+                              "evals_per_s": m * (iters + 1) / makespan,
+                              "latency_p50_s": st["latency_p50_s"], "latency_p99_s": p99,
+                              "by_kind_p99_s": {k: v["latency_p99_s"] for k, v in st["by_kind"].items()},
+                              "sustained": ok})
+    out["largest_sustained_rate_per_s"] = best
+    out["criterion"] = "p99 latency <= 2 x the p99 at the lowest rate"
+    for _, ctx, _ in jobs:
+        ctx.close()
     return out
 
 
@@ -634,7 +699,7 @@ def serving_trimers(ucc, jobs=4, iters=5, lr=0.1):
 
 
 LEGS = ("all", "latency", "large_26q", "paper_shaped", "variants", "tapered", "trotter_free",
-        "size_consistency", "serving", "serving_trimers", "stream")
+        "size_consistency", "serving", "serving_sweep", "serving_trimers", "stream")
 
 
 def main():
@@ -650,7 +715,7 @@ def main():
                     help="use the fixed tuning table instead of timing the candidates")
     ap.add_argument("--no-extra", action="store_true",
                     help="skip the one-at-a-time rate, the B = 1 latencies and the 26-qubit evaluation")
-    ap.add_argument("--serve-arrivals", type=int, default=70,
+    ap.add_argument("--serve-arrivals", type=int, default=700,
                     help="arrivals of the serving trace (0 = skip the serving legs)")
     ap.add_argument("--leg", default="all", choices=LEGS,
                     help="run one leg alone and print {leg, result} (for profiling that leg)")
@@ -689,6 +754,7 @@ def main():
             "size_consistency": lambda: size_consistency(ucc),
             "serving": lambda: serving_mix(ucc, args.serve_arrivals),
             "serving_trimers": lambda: serving_trimers(ucc),
+            "serving_sweep": lambda: serving_sweep(ucc),
             "stream": lambda: stream_rates(ucc, torch),
         }
         print(json.dumps({"leg": args.leg, "result": legs[args.leg]()}))
@@ -809,6 +875,7 @@ def main():
     if args.serve_arrivals > 0:
         out["served_evals_per_s"] = served_same_workload(ucc, h1, h2, exc, thetas)
         out["serving_mix"] = serving_mix(ucc, args.serve_arrivals)
+        out["serving_sweep"] = serving_sweep(ucc)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline()
         if not args.no_extra:
