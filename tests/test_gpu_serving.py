@@ -51,12 +51,15 @@ def solo_sd(ctx, th0, iters, lr=LR):
 
 
 def test_results_identical_alone_and_in_the_mix(ucc):
-    say("case: serving mix of 8q, 12q (three Hamiltonians), 16q (one Hamiltonian, two starts)")
+    say("case: serving mix of 8q, 12q (three Hamiltonians), 16q (two Hamiltonians, three starts)")
     ctxs = {"m1": make_ctx(ucc, 12, 8, 101), "m2": make_ctx(ucc, 12, 8, 102),
             "m3": make_ctx(ucc, 12, 8, 103), "d": make_ctx(ucc, 16, 8, 104),
-            "s": make_ctx(ucc, 8, 4, 105)}
+            "s": make_ctx(ucc, 8, 4, 105), "d2": make_ctx(ucc, 16, 8, 106)}
     assert ctxs["m1"].batch_compatible(ctxs["m2"]) and ctxs["m1"].batch_compatible(ctxs["m3"])
-    jobs = [("m1", 1), ("m2", 2), ("m3", 3), ("d", 4), ("d", 5), ("s", 6)]
+    # two 16-qubit Hamiltonians share a launch through per-entry value tables in the mix (the
+    # single-table pair walk runs them alone): the results must not differ by one bit
+    assert ctxs["d"].batch_compatible(ctxs["d2"])
+    jobs = [("m1", 1), ("m2", 2), ("m3", 3), ("d", 4), ("d", 5), ("s", 6), ("d2", 7)]
     iters = 5
     th0 = {j: make_thetas(ctxs[c].n_exc, seed, 0.05) for j, (c, seed) in enumerate(jobs)}
     alone = {j: solo_sd(ctxs[c], th0[j], iters) for j, (c, _) in enumerate(jobs)}
