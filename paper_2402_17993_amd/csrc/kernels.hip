@@ -600,17 +600,17 @@ __device__ __forceinline__ double exp_rows(const double2* cp, const uint32_t* bl
         const double* br = Bloc + (size_t)slot * k;
         double occ = 0.0;
         for (uint32_t bits = (uint32_t)sl[rv] & ~xloc[slot]; bits; bits &= bits - 1) occ += br[__ffs(bits) - 1];
-        double val = t1[slot] + t2[slot] * occ;
+        double val = __builtin_fma(t2[slot], occ, t1[slot]);
         if (en & 0x8000u) val = -val;
         const double2 pv = cp[rv];
-        ax += val * pv.x;
-        ay += val * pv.y;
+        ax = __builtin_fma(val, pv.x, ax);
+        ay = __builtin_fma(val, pv.y, ay);
       };
       auto plain_entry = [&](uint32_t en) {
         const double val = (en & 0x8000u) ? -t1[en >> 16] : t1[en >> 16];
         const double2 pv = cp[en & 0x7fffu];
-        ax += val * pv.x;
-        ay += val * pv.y;
+        ax = __builtin_fma(val, pv.x, ax);
+        ay = __builtin_fma(val, pv.y, ay);
       };
       for (int q = q0 + sub; q < q1; q += 4) {
         const uint4 E = e4[q];
@@ -646,15 +646,15 @@ __device__ __forceinline__ double exp_rows(const double2* cp, const uint32_t* bl
           }
         }
         const double2 pu = cp[i];
-        ax += f * pu.x;
-        ay += f * pu.y;
+        ax = __builtin_fma(f, pu.x, ax);
+        ay = __builtin_fma(f, pu.y, ay);
       }
     }
     ax = quad_sum(ax);
     ay = quad_sum(ay);
     if (row && sub == owner) {
       const double2 pu = cp[i];
-      eacc += pu.x * ax + pu.y * ay;
+      eacc += __builtin_fma(pu.x, ax, pu.y * ay);
       if (APPLY) {
         const dvec2 nv = {old.x + ax, old.y + ay};
         st16(vl + phys, nv);
@@ -1084,57 +1084,63 @@ __global__ __launch_bounds__(T) LDS_BOUND_OCCUPANCY void k_exp(
   }
 }
 
-// Row walk of an expectation pass for two vectors with the same tile (batch entries b0, b1):
-// each entry's matrix element (sign, slot value, occupation sum) is formed once and applied to
-// both vectors' sources, so the entry reads, the slot lookups and the occupation loops are
-// shared.  Same order of every sum as exp_rows (per vector).  xloc, Bloc, bl: the value
-// table's local parts (compact x masks of the occupation slots, their local occupation rows,
-// the diagonal's local couplings).  e0, e1: the thread's shares of the two energy partials.
-// With APPLY the row sums are added into (first pass: written to) lambda of b0 and, if vl1 is
-// non-null, of b1.
-template <int T, bool APPLY>
-__device__ __forceinline__ void exp_rows2(const double2* cp0, const double2* cp1, const uint32_t* blk,
+// Row walk of an expectation pass for V vectors with the same tile (V consecutive batch
+// entries, their in-sector tiles at cpb + v * ns_max): each entry's matrix element (sign, slot
+// value, occupation sum) is formed once and applied to every vector's source, so the entry
+// reads, the slot lookups and the occupation loops are shared.  Same order of every sum as
+// exp_rows (per vector).  xloc, Bloc, bl: the value table's local parts (compact x masks of the
+// occupation slots, their local occupation rows, the diagonal's local couplings).  e[v]: the
+// thread's share of vector v's energy partial.  With APPLY the row sums are added into (first
+// pass: written to) lambda of the vectors whose vl[v] is non-null.
+template <int T, bool APPLY, int V>
+__device__ __forceinline__ void exp_rowsv(const double2* cpb, int ns_max, const uint32_t* blk,
                                           const uint32_t* __restrict__ ent, const uint32_t* xloc,
                                           const double* Bloc, const double* bl, int has_diag,
                                           const double* t1, const double* t2, const double* dpre, int k,
-                                          uint32_t base, double2* __restrict__ vl0, double2* __restrict__ vl1,
-                                          int first, double& e0, double& e1) {
+                                          uint32_t base, double2* const* vl, int first, double* e) {
   const int sub = threadIdx.x & 3;
   const int ns = (int)blk[0];
   const uint32_t* off = blk + 2;
   const uint32_t* mid = off + ns + 1;
   const uint16_t* sl = reinterpret_cast<const uint16_t*>(mid + ns);
   const uint32_t* sphys = mid + ns + ((ns + 1) >> 1);
-  const bool two = vl1 != nullptr;
   int it = 0;
   for (int i0 = 0; i0 < ns; i0 += T / 4, ++it) {
     const int i = i0 + ((int)threadIdx.x >> 2);
     const bool row = i < ns;  // the same for the four lanes of a quad
     const int owner = it & 3;
-    double ax = 0.0, ay = 0.0, bx = 0.0, by = 0.0;
-    dvec2 old0 = {0.0, 0.0}, old1 = {0.0, 0.0};
+    double ax[V], ay[V];
+    dvec2 old[V];
+#pragma unroll
+    for (int v = 0; v < V; ++v) {
+      ax[v] = 0.0;
+      ay[v] = 0.0;
+      old[v] = dvec2{0.0, 0.0};
+    }
     uint32_t phys = 0u;
     if (row) {
       phys = base | sphys[i];
       if (APPLY && !first && sub == owner) {
-        old0 = ld16(vl0 + phys);
-        if (two) old1 = ld16(vl1 + phys);
+#pragma unroll
+        for (int v = 0; v < V; ++v)
+          if (vl[v]) old[v] = ld16(vl[v] + phys);
       }
       const uint4* __restrict__ e4 = reinterpret_cast<const uint4*>(ent);
       const int q0 = (int)off[i] >> 2, q1 = (int)mid[i] >> 2, q2 = (int)off[i + 1] >> 2;
       auto add = [&](double val, uint32_t rv) {
-        const double2 p0 = cp0[rv], p1 = cp1[rv];
-        ax += val * p0.x;
-        ay += val * p0.y;
-        bx += val * p1.x;
-        by += val * p1.y;
+#pragma unroll
+        for (int v = 0; v < V; ++v) {
+          const double2 pv = cpb[v * ns_max + rv];
+          ax[v] = __builtin_fma(val, pv.x, ax[v]);
+          ay[v] = __builtin_fma(val, pv.y, ay[v]);
+        }
       };
       auto occ_entry = [&](uint32_t en) {  // groups with occupation rows
         const uint32_t rv = en & 0x7fffu, slot = en >> 16;
         const double* br = Bloc + (size_t)slot * k;
         double occ = 0.0;
         for (uint32_t bits = (uint32_t)sl[rv] & ~xloc[slot]; bits; bits &= bits - 1) occ += br[__ffs(bits) - 1];
-        double val = t1[slot] + t2[slot] * occ;
+        double val = __builtin_fma(t2[slot], occ, t1[slot]);
         if (en & 0x8000u) val = -val;
         add(val, rv);
       };
@@ -1176,29 +1182,31 @@ __device__ __forceinline__ void exp_rows2(const double2* cp0, const double2* cp1
         add(f, (uint32_t)i);
       }
     }
-    ax = quad_sum(ax);
-    ay = quad_sum(ay);
-    bx = quad_sum(bx);
-    by = quad_sum(by);
+#pragma unroll
+    for (int v = 0; v < V; ++v) {
+      ax[v] = quad_sum(ax[v]);
+      ay[v] = quad_sum(ay[v]);
+    }
     if (row && sub == owner) {
-      const double2 pu0 = cp0[i], pu1 = cp1[i];
-      e0 += pu0.x * ax + pu0.y * ay;
-      e1 += pu1.x * bx + pu1.y * by;
-      if (APPLY) {
-        st16(vl0 + phys, dvec2{old0.x + ax, old0.y + ay});
-        if (two) st16(vl1 + phys, dvec2{old1.x + bx, old1.y + by});
+#pragma unroll
+      for (int v = 0; v < V; ++v) {
+        const double2 pu = cpb[v * ns_max + i];
+        e[v] += __builtin_fma(pu.x, ax[v], pu.y * ay[v]);
+        if (APPLY && vl[v]) st16(vl[v] + phys, dvec2{old[v].x + ax[v], old[v].y + ay[v]});
       }
     }
   }
 }
 
-// Expectation / apply-H pass over pairs of batch entries (b0 = 2 p, b1 = 2 p + 1) that share a
-// tile: both tiles' in-sector amplitudes in LDS, one row walk for both (exp_rows2).  For the
+// Expectation / apply-H pass over groups of V consecutive batch entries (b = V p .. V p + V - 1)
+// that share a tile: their in-sector tiles in LDS, one row walk for all (exp_rowsv).  For the
 // passes with long rows, whose walk bounds them.  The value table stays in memory except its
 // local parts; the per-tile slot values are formed from it once per item.  Needs one
-// Hamiltonian for the whole batch.  b0's next tile is requested into registers during the
-// walk; b1's tile is read after b0's is taken, beside the per-tile values.
-template <int T, int KT, bool APPLY>
+// Hamiltonian for the whole batch.  The first entry's next tile is requested into registers
+// during the walk; each further tile is read after the previous one is taken (the first
+// beside the per-tile values).  Entries past the batch reuse the last one's tile and write
+// nothing.
+template <int T, int KT, bool APPLY, int V>
 __global__ __launch_bounds__(T) LDS_BOUND_OCCUPANCY void k_expv(
     const DevPass* __restrict__ passes, int pidx, const uint4* __restrict__ blobs,
     const int2* __restrict__ pcls, const uint32_t* __restrict__ blocks,
@@ -1208,18 +1216,18 @@ __global__ __launch_bounds__(T) LDS_BOUND_OCCUPANCY void k_expv(
   using TL = Tile<T, KT>;
   using SC = Sector<T, KT>;
   constexpr bool RP = KT != 0;
-  __shared__ double red[2][T / 64];
+  __shared__ double red[V][T / 64];
   const DevPass ps = passes[pidx];
   const uint32_t tileN = 1u << ps.k;
   const int k = ps.k;
   const int tb = n - ps.k;
   const uint32_t tmask = (1u << tb) - 1u;
+  const int ns_max = ps.ns_max;
   const uint32_t* gb = reinterpret_cast<const uint32_t*>(blobs + ps.blob_off);  // value table (memory)
   const int n_slots = (int)gb[0], n_occ = (int)gb[1], has_diag = (int)gb[2];
-  // LDS: psi of b0 | psi of b1 | t1 | t2 | dpre | Bloc | bl | xloc | class block | rank table
-  double2* cp0 = lds;
-  double2* cp1 = lds + ps.ns_max;
-  double* t1 = reinterpret_cast<double*>(lds + 2 * ps.ns_max);
+  // LDS: psi of the V entries | t1 | t2 | dpre | Bloc | bl | xloc | class block | rank table
+  double2* cpb = lds;
+  double* t1 = reinterpret_cast<double*>(lds + V * ns_max);
   double* t2 = t1 + ((n_slots + 1) & ~1);
   double* dpre = t2 + ((n_occ + 1) & ~1);
   double* Bloc = dpre + ((k + 2) & ~1);
@@ -1240,8 +1248,8 @@ __global__ __launch_bounds__(T) LDS_BOUND_OCCUPANCY void k_expv(
   }
   int item = blockIdx.x;
   if (item >= total) return;
-  const int np = total >> tb;  // entry pairs
-  auto pair_of = [&](int it) { return flip ? np - 1 - (it >> tb) : it >> tb; };
+  const int ng = total >> tb;  // entry groups
+  auto group_of = [&](int it) { return flip ? ng - 1 - (it >> tb) : it >> tb; };
   int staged = -1;
   const uint32_t* __restrict__ gent = nullptr;
   auto base_of = [&](int it) { return dep(it & tmask, ps.gmask); };
@@ -1257,59 +1265,60 @@ __global__ __launch_bounds__(T) LDS_BOUND_OCCUPANCY void k_expv(
       staged = cl;
     }
   };
+  // batch entry of slot v of group g (past the batch: the last entry, nothing written)
+  auto entry = [&](int g, int v) { return min(V * g + v, B - 1); };
   typename TL::Buf r;
   stage_class(base_of(item));  // its barriers also publish the local tables
   const TL tm(ps.lmask);
-  if (RP) tm.fetch(r, psi + ((size_t)(2 * pair_of(item)) << n), base_of(item));
+  if (RP) tm.fetch(r, psi + ((size_t)entry(group_of(item), 0) << n), base_of(item));
   for (;;) {
-    const int p2 = pair_of(item);
-    const int b0 = 2 * p2, b1 = 2 * p2 + 1;
-    const bool two = b1 < B;
+    const int g = group_of(item);
     const uint32_t t = item & tmask;
     const uint32_t base = base_of(item);
-    const double2* v0 = psi + ((size_t)b0 << n);
-    const double2* v1 = psi + ((size_t)(two ? b1 : b0) << n);
     if constexpr (RP) {
-      SC::take(tm, r, cp0, rtab);
-      tm.refresh();
-      tm.fetch(r, v1, base);
+#pragma unroll
+      for (int v = 0; v < V; ++v) {
+        SC::take(tm, r, cpb + v * ns_max, rtab);
+        if (v + 1 < V) {
+          tm.refresh();
+          tm.fetch(r, psi + ((size_t)entry(g, v + 1) << n), base);
+        }
+        if (v == 0) exp_prep<T>(gb, t1, t2, dpre, ps.lmask, k, n, base);
+      }
     } else {
-      take_loop<T, false>(ps.lmask, tileN, cp0, rtab, v0, base, 0u);
+      for (int v = 0; v < V; ++v)
+        take_loop<T, false>(ps.lmask, tileN, cpb + v * ns_max, rtab, psi + ((size_t)entry(g, v) << n), base, 0u);
+      exp_prep<T>(gb, t1, t2, dpre, ps.lmask, k, n, base);
     }
-    exp_prep<T>(gb, t1, t2, dpre, ps.lmask, k, n, base);
-    if constexpr (RP)
-      SC::take(tm, r, cp1, rtab);
-    else
-      take_loop<T, false>(ps.lmask, tileN, cp1, rtab, v1, base, 0u);
-    __syncthreads();  // cp0, cp1 and the per-tile values complete
+    __syncthreads();  // the tiles and the per-tile values complete
     const int next = item + gridDim.x;
-    double e0 = 0.0, e1 = 0.0;
-    exp_rows2<T, APPLY>(cp0, cp1, blk, gent, xloc, Bloc, bl, has_diag, t1, t2, dpre, k, base,
-                        APPLY ? lam + ((size_t)b0 << n) : nullptr,
-                        APPLY && two ? lam + ((size_t)b1 << n) : nullptr, first, e0, e1);
+    double e[V];
+    double2* vl[V];
+#pragma unroll
+    for (int v = 0; v < V; ++v) {
+      e[v] = 0.0;
+      vl[v] = APPLY && V * g + v < B ? lam + ((size_t)(V * g + v) << n) : nullptr;
+    }
+    exp_rowsv<T, APPLY, V>(cpb, ns_max, blk, gent, xloc, Bloc, bl, has_diag, t1, t2, dpre, k, base, vl,
+                           first, e);
     if (RP && next < total) {
       tm.refresh();
-      tm.fetch(r, psi + ((size_t)(2 * pair_of(next)) << n), base_of(next));
+      tm.fetch(r, psi + ((size_t)entry(group_of(next), 0) << n), base_of(next));
     }
-    e0 = wave_sum(e0);
-    e1 = wave_sum(e1);
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    if (lane == 0) {
-      red[0][w] = e0;
-      red[1][w] = e1;
+#pragma unroll
+    for (int v = 0; v < V; ++v) {
+      const double ev = wave_sum(e[v]);
+      if (lane == 0) red[v][w] = ev;
     }
     __syncthreads();
-    if (threadIdx.x == 0) {
-      double s0 = 0.0, s1 = 0.0;
-      for (int i = 0; i < T / 64; ++i) {
-        s0 += red[0][i];
-        s1 += red[1][i];
-      }
-      epart[(size_t)b0 * estride + t] = s0;
-      if (two) epart[(size_t)b1 * estride + t] = s1;
+    if ((int)threadIdx.x < V && V * g + (int)threadIdx.x < B) {
+      double sum = 0.0;
+      for (int i = 0; i < T / 64; ++i) sum += red[threadIdx.x][i];
+      epart[(size_t)(V * g + threadIdx.x) * estride + t] = sum;
     }
     if (next >= total) break;
-    __syncthreads();  // cp0, cp1, the per-tile values, red and the class block are no longer read
+    __syncthreads();  // the tiles, the per-tile values, red and the class block are no longer read
     stage_class(base_of(next));
     item = next;
   }
@@ -1790,28 +1799,46 @@ hipError_t exp_overlapped(const LaunchArgs& a, int pidx, int eslot, int first, b
   }
 }
 
-// Passes with long rows over pairs of batch entries (k_expv), where one Hamiltonian serves the
-// batch and the two tiles fit beside the local value tables.
+// Passes with long rows over groups of batch entries (k_expv), where one Hamiltonian serves
+// the batch and the group's tiles fit beside the local value tables: four entries where they
+// fit, else two.
+inline size_t expv_lds(const DevPass& hp, int V) {
+  const int k = hp.k;
+  const size_t nd = size_t((hp.n_slots + 1) & ~1) + size_t((hp.n_occ + 1) & ~1) + size_t((k + 2) & ~1) +
+                    size_t(hp.n_occ) * k + (hp.has_diag ? size_t(k) * k : 0);
+  return 16 * size_t(V) * hp.ns_max + 8 * nd + 4 * size_t((hp.n_occ + 3) & ~3) + 4 * size_t(hp.stage_len) +
+         (size_t(2) << k);
+}
+
+template <int T, int KT, bool APPLY, int V>
+hipError_t launch_expv(const LaunchArgs& a, int pidx, int eslot, int first, size_t lds) {
+  hipError_t e = set_lds(k_expv<T, KT, APPLY, V>, lds);
+  if (e != hipSuccess) return e;
+  const int k = a.hpasses[pidx].k;
+  const int total = ((a.B + V - 1) / V) << (a.n - k);
+  const int grid =
+      pass_grid(total, resident_grid(k_expv<T, KT, APPLY, V>, T, lds, a.cu_share), 1 << (a.n - k));
+  hipLaunchKernelGGL((k_expv<T, KT, APPLY, V>), dim3(grid), dim3(T), lds, a.stream, a.passes, pidx,
+                     a.blobs, a.cls, a.pairs, a.psi, a.lam, a.n, a.amask, a.bmask,
+                     a.epart + (size_t)eslot, a.estride, first, a.B, total, a.flip);
+  return hipGetLastError();
+}
+
 template <int T, int KT, bool APPLY>
 hipError_t exp_pairs(const LaunchArgs& a, int pidx, int eslot, int first, bool* used) {
   *used = false;
   const DevPass& hp = a.hpasses[pidx];
-  const int k = hp.k;
-  if (a.blob_stride != 0 || T < 64 + k) return hipSuccess;
-  const size_t nd = size_t((hp.n_slots + 1) & ~1) + size_t((hp.n_occ + 1) & ~1) + size_t((k + 2) & ~1) +
-                    size_t(hp.n_occ) * k + (hp.has_diag ? size_t(k) * k : 0);
-  const size_t lds = 32 * size_t(hp.ns_max) + 8 * nd + 4 * size_t((hp.n_occ + 3) & ~3) +
-                     4 * size_t(hp.stage_len) + (size_t(2) << k);
-  if (lds + 2 * 8 * (T / 64) + 256 > (size_t)kLdsBytes) return hipSuccess;
-  hipError_t e = set_lds(k_expv<T, KT, APPLY>, lds);
-  if (e != hipSuccess) return e;
-  const int total = ((a.B + 1) / 2) << (a.n - k);
-  const int grid = pass_grid(total, resident_grid(k_expv<T, KT, APPLY>, T, lds, a.cu_share), 1 << (a.n - k));
-  hipLaunchKernelGGL((k_expv<T, KT, APPLY>), dim3(grid), dim3(T), lds, a.stream, a.passes, pidx, a.blobs,
-                     a.cls, a.pairs, a.psi, a.lam, a.n, a.amask, a.bmask, a.epart + (size_t)eslot,
-                     a.estride, first, a.B, total, a.flip);
-  *used = true;
-  return hipGetLastError();
+  if (a.blob_stride != 0 || T < 64 + hp.k) return hipSuccess;
+  const size_t stat = 4 * 8 * (T / 64) + 256;
+  if (expv_lds(hp, 4) + stat <= (size_t)kLdsBytes) {
+    *used = true;
+    return launch_expv<T, KT, APPLY, 4>(a, pidx, eslot, first, expv_lds(hp, 4));
+  }
+  if (expv_lds(hp, 2) + stat <= (size_t)kLdsBytes) {
+    *used = true;
+    return launch_expv<T, KT, APPLY, 2>(a, pidx, eslot, first, expv_lds(hp, 2));
+  }
+  return hipSuccess;
 }
 
 template <int T, int KT, bool APPLY>
