@@ -409,7 +409,8 @@ __device__ __forceinline__ void fwd_excitations(double2* cp, const uint32_t* blk
 // them after the caller's workgroup barrier.
 template <int T>
 __device__ __forceinline__ void rev_excitations(double2* cp, double2* cl, const uint32_t* blk,
-                                                const double2* scs, int count, double* gq) {
+                                                const double2* scs, int count, double* gq,
+                                                int gs = kGqStride) {
   __shared__ double2 sink[1];  // written and read by lanes without a pair; never used
   if (threadIdx.x >= 64) return;
   const int lane = threadIdx.x;
@@ -458,7 +459,7 @@ __device__ __forceinline__ void rev_excitations(double2* cp, double2* cl, const 
     }
     // the four lanes of a quad hold the same sum (the adds commute exactly) and all write it
     g = quad_sum(g);
-    gq[(lane >> 2) * kGqStride + e] = g;
+    gq[(lane >> 2) * gs + e] = g;
     cur = nxt;
     nxt = nn;
     e0 = e0n;
@@ -472,7 +473,7 @@ __device__ __forceinline__ void rev_excitations(double2* cp, double2* cl, const 
 template <int NW>
 __device__ __forceinline__ void rev_partials_only(const double2* cp, const double2* cl,
                                                   const uint32_t* blk, int count, double* gq, int w,
-                                                  int lane) {
+                                                  int lane, int gs = kGqStride) {
   const uint32_t* off = blk + 2;
   const int m = (int)blk[1], ns = (int)blk[0];
   const uint32_t* ent = blk + 3 + m + ((ns + 1) >> 1) + ns;
@@ -487,16 +488,17 @@ __device__ __forceinline__ void rev_partials_only(const double2* cp, const doubl
       g += (en & 0x8000u) ? -t : t;
     }
     g = quad_sum(g);
-    gq[(lane >> 2) * kGqStride + e] = g;
+    gq[(lane >> 2) * gs + e] = g;
   }
 }
 
 // Tile partial of <lambda|G_k|psi> for the pass's excitation e: the 16 quad partials in a
 // fixed order, times the tile's sign of the excitation.
-__device__ __forceinline__ double rev_partial(const double* gq, int e, const DevExc& x, uint32_t base) {
+__device__ __forceinline__ double rev_partial(const double* gq, int e, const DevExc& x, uint32_t base,
+                                              int gs = kGqStride) {
   double s = 0.0;
 #pragma unroll
-  for (int q = 0; q < 16; ++q) s += gq[q * kGqStride + e];
+  for (int q = 0; q < 16; ++q) s += gq[q * gs + e];
   return exc_sign(x, base) * s;
 }
 
@@ -900,9 +902,6 @@ __global__ __launch_bounds__(T) LDS_BOUND_OCCUPANCY void k_rev2(
     int n, uint32_t amask, uint32_t bmask, double* __restrict__ gpart, int L, int total, int flip) {
   extern __shared__ double2 lds[];
   constexpr int P = T / 2;  // producer threads: the upper half of the workgroup
-  __shared__ DevExc sx[kMaxPassExc];
-  __shared__ double2 scs[2][kMaxPassExc];
-  __shared__ double gq[kGqWords];
   using TL = Tile<P, KT>;
   using SC = Sector<P, KT>;
   const DevPass ps = passes[pidx];
@@ -911,10 +910,17 @@ __global__ __launch_bounds__(T) LDS_BOUND_OCCUPANCY void k_rev2(
   const uint32_t tmask = (1u << tb) - 1u;
   const int ntiles = 1 << tb;
   const int ns_max = ps.ns_max;
+  // LDS, all sized by the pass: psi and lambda of two slots by rank | class block | rank table |
+  // the excitation records | two (cos, signed sin) stages | quad partials (odd row stride)
   double2* cpb = lds;                // [2][ns_max] psi by rank
   double2* clb = lds + 2 * ns_max;   // [2][ns_max] lambda by rank
   uint32_t* blk = reinterpret_cast<uint32_t*>(lds + 4 * ns_max);
   uint16_t* rtab = reinterpret_cast<uint16_t*>(blk + ps.stage_len);
+  DevExc* sx = reinterpret_cast<DevExc*>(rtab + tileN);
+  double2* scs0 = reinterpret_cast<double2*>(sx + ps.count);
+  double* gq = reinterpret_cast<double*>(scs0 + 2 * ps.count);
+  const int gs = ps.count | 1;
+  auto scs = [&](int slot) { return scs0 + slot * ps.count; };
   const int item0 = blockIdx.x;
   if (item0 >= total) return;
   const int nb = total >> tb;
@@ -933,7 +939,7 @@ __global__ __launch_bounds__(T) LDS_BOUND_OCCUPANCY void k_rev2(
     const uint32_t base = base_of(it);
     if (!GONLY)
       for (int e = (int)tm.tid; e < ps.count; e += P)
-        scs[s][e] = signed_cs(cs[(size_t)ent(it) * K + sx[e].k], sx[e], base);
+        scs(s)[e] = signed_cs(cs[(size_t)ent(it) * K + sx[e].k], sx[e], base);
     typename TL::Buf r;
     tm.refresh();
     tm.fetch(r, psi + off_of(it), base);
@@ -957,20 +963,20 @@ __global__ __launch_bounds__(T) LDS_BOUND_OCCUPANCY void k_rev2(
     if (GONLY && !prod) {
       constexpr int NW = P / 64;
       const int lane = (int)threadIdx.x & 63, w = (int)threadIdx.x >> 6;
-      rev_partials_only<NW>(cpb + slot * ns_max, clb + slot * ns_max, blk, ps.count, gq, w, lane);
+      rev_partials_only<NW>(cpb + slot * ns_max, clb + slot * ns_max, blk, ps.count, gq, w, lane, gs);
       const uint32_t base = base_of(item);
       const int b = ent(item);
       const uint32_t t = item & tmask;
       for (int e = w + NW * lane; e < ps.count; e += NW * 64)
-        gpart[((size_t)b * L + sx[e].occ) * ntiles + t] = rev_partial(gq, e, sx[e], base);
+        gpart[((size_t)b * L + sx[e].occ) * ntiles + t] = rev_partial(gq, e, sx[e], base, gs);
     } else if (!GONLY && threadIdx.x < 64) {
-      rev_excitations<T>(cpb + slot * ns_max, clb + slot * ns_max, blk, scs[slot], ps.count, gq);
+      rev_excitations<T>(cpb + slot * ns_max, clb + slot * ns_max, blk, scs(slot), ps.count, gq, gs);
       // the chain's partials are this wave's own LDS writes: read back in issue order
       const uint32_t base = base_of(item);
       const int b = ent(item);
       const uint32_t t = item & tmask;
       for (int e = threadIdx.x; e < ps.count; e += 64)
-        gpart[((size_t)b * L + sx[e].occ) * ntiles + t] = rev_partial(gq, e, sx[e], base);
+        gpart[((size_t)b * L + sx[e].occ) * ntiles + t] = rev_partial(gq, e, sx[e], base, gs);
     } else if (prod) {
       if (!GONLY && j > 0) write_item(item - (int)gridDim.x, slot ^ 1);
       if (next < total) read_item(next, slot ^ 1);
@@ -1719,10 +1725,11 @@ hipError_t rev_overlapped(const LaunchArgs& a, int pidx, double2* psi, bool* use
     const DevPass& hp = a.hpasses[pidx];
     const int k = hp.k;
     const int ntiles = 1 << (a.n - k);
-    const size_t lds = sc_lds(hp, 4);
-    // static LDS: excitation records, two (cos, sin) stages, quad partials, the chain's sink
-    const size_t stat = sizeof(DevExc) * kMaxPassExc + 2 * 16 * kMaxPassExc + 8 * kGqWords + 16;
-    if (lds + stat > (size_t)kLdsBytes) return hipSuccess;
+    // the pass's records, two (cos, signed sin) stages and the quad partials behind the tiles,
+    // the class block and the rank table; the chain's sink is static
+    const size_t lds = sc_lds(hp, 4) + sizeof(DevExc) * hp.count + 2 * 16 * size_t(hp.count) +
+                       8 * 16 * size_t(hp.count | 1);
+    if (lds + 16 > (size_t)kLdsBytes) return hipSuccess;
     hipError_t e = set_lds(k_rev2<T, KT, WP, GONLY>, lds);
     if (e != hipSuccess) return e;
     const int total = a.B << (a.n - k);
