@@ -697,7 +697,6 @@ __global__ __launch_bounds__(T) LDS_BOUND_OCCUPANCY void k_fwd(
     const double2* __restrict__ cs, int K, const double2* src, double2* __restrict__ psi, int n,
     uint32_t hf, uint32_t amask, uint32_t bmask, int total, int flip) {
   extern __shared__ double2 lds[];
-  __shared__ PassStage st;
   using TL = Tile<T, KT>;
   using SC = Sector<T, KT>;
   constexpr bool RP = KT != 0;  // register-staged tiles
@@ -705,19 +704,23 @@ __global__ __launch_bounds__(T) LDS_BOUND_OCCUPANCY void k_fwd(
   const uint32_t tileN = 1u << ps.k;
   const int tb = n - ps.k;
   const uint32_t tmask = (1u << tb) - 1u;
-  double2* cp = lds;  // in-sector amplitudes by rank
+  // LDS, sized by the pass: in-sector amplitudes by rank | class block | rank table | the
+  // excitation records and their (cos, signed sin)
+  double2* cp = lds;
   uint32_t* blk = reinterpret_cast<uint32_t*>(lds + ps.ns_max);
   uint16_t* rtab = reinterpret_cast<uint16_t*>(blk + ps.stage_len);
+  DevExc* sx = reinterpret_cast<DevExc*>(rtab + tileN);
+  double2* scs = reinterpret_cast<double2*>(sx + ps.count);
   const TL tm(ps.lmask);
   const bool cst = (int)threadIdx.x < ps.count;
   int item = blockIdx.x;
   if (item >= total) return;
   const int nb = total >> tb;
   auto ent = [&](int it) { return flip ? nb - 1 - (it >> tb) : it >> tb; };  // batch entry
-  stage_records<T>(st, ps, exc);
+  for (int i = threadIdx.x; i < ps.count; i += T) sx[i] = exc[ps.first + i];
   typename TL::Buf r;
   int staged = -1;
-  auto cs_of = [&](int it) { return cs[(size_t)ent(it) * K + st.x[threadIdx.x].k]; };
+  auto cs_of = [&](int it) { return cs[(size_t)ent(it) * K + sx[threadIdx.x].k]; };
   auto base_of = [&](int it) { return dep(it & tmask, ps.gmask); };
   auto vec_of = [&](int it) { return psi + ((size_t)ent(it) << n); };
   auto src_of = [&](int it) { return src + ((size_t)ent(it) << n); };
@@ -746,7 +749,7 @@ __global__ __launch_bounds__(T) LDS_BOUND_OCCUPANCY void k_fwd(
   if (cst) csv = cs_of(item);
   if (RP && !INIT) tm.fetch(r, src_of(item), base_of(item));
   take(item);
-  if (cst) st.cs[threadIdx.x] = signed_cs(csv, st.x[threadIdx.x], base_of(item));
+  if (cst) scs[threadIdx.x] = signed_cs(csv, sx[threadIdx.x], base_of(item));
   for (;;) {
     const uint32_t base = base_of(item);
     double2* __restrict__ v = vec_of(item);
@@ -759,7 +762,7 @@ __global__ __launch_bounds__(T) LDS_BOUND_OCCUPANCY void k_fwd(
       tm.refresh();
       if (RP && !INIT) tm.fetch(r, src_of(next), base_of(next));
     }
-    fwd_excitations<T>(cp, blk, st.cs, ps.count);
+    fwd_excitations<T>(cp, blk, scs, ps.count);
     __syncthreads();  // the excitations are applied
     // the whole tile: a fixed number of stores per thread, so the next take waits for its
     // own loads only
@@ -773,7 +776,7 @@ __global__ __launch_bounds__(T) LDS_BOUND_OCCUPANCY void k_fwd(
     __syncthreads();  // cp, the table and the (cos, sin) stage are no longer read
     stage_class(base_of(next));
     take(next);
-    if (cst) st.cs[threadIdx.x] = signed_cs(csv, st.x[threadIdx.x], base_of(next));
+    if (cst) scs[threadIdx.x] = signed_cs(csv, sx[threadIdx.x], base_of(next));
     item = next;
   }
 }
@@ -1698,7 +1701,7 @@ template <int T, int KT, bool INIT>
 hipError_t fwd_ti(const LaunchArgs& a, int pidx, const double2* src, double2* dst) {
   const DevPass& hp = a.hpasses[pidx];
   const int k = hp.k;
-  const size_t lds = sc_lds(hp, 1);
+  const size_t lds = sc_lds(hp, 1) + (sizeof(DevExc) + 16) * size_t(hp.count);
   hipError_t e = set_lds(k_fwd<T, KT, INIT>, lds);
   if (e != hipSuccess) return e;
   const int total = a.B << (a.n - k);
