@@ -345,6 +345,19 @@ __device__ __forceinline__ void put_tile_loop(uint32_t lmask, uint32_t tileN, co
   }
 }
 
+// Producer side of the overlapped passes: the thread's tile elements in PD chunks of
+// H, each loaded into registers and then given to LDS by rank.
+template <int C, int PD, int H, class TL, class SC>
+__device__ __forceinline__ void read_chunks(const TL& tm, typename TL::Buf& r, const double2* v,
+                                            uint32_t base, double2* cv, const uint16_t* rtab) {
+  if constexpr (C < PD) {
+    tm.refresh();
+    tm.template fetch<C * H, (C + 1) * H>(r, v, base);
+    SC::template take<C * H, (C + 1) * H>(tm, r, cv, rtab);
+    read_chunks<C + 1, PD, H, TL, SC>(tm, r, v, base, cv, rtab);
+  }
+}
+
 // ---- pass bodies shared by the per-pass kernels and the whole-evaluation kernel
 
 // Forward excitations of a pass on the in-sector amplitudes cp of a tile (class block blk,
@@ -944,12 +957,17 @@ __global__ __launch_bounds__(T) LDS_BOUND_OCCUPANCY void k_rev2(
       for (int e = (int)tm.tid; e < ps.count; e += P)
         scs(s)[e] = signed_cs(cs[(size_t)ent(it) * K + sx[e].k], sx[e], base);
     typename TL::Buf r;
-    tm.refresh();
-    tm.fetch(r, psi + off_of(it), base);
-    SC::take(tm, r, cpb + s * ns_max, rtab);
-    tm.refresh();
-    tm.fetch(r, lam + off_of(it), base);
-    SC::take(tm, r, clb + s * ns_max, rtab);
+    if constexpr (TL::EPT > 16) {  // large tiles: chunks of 8 elements per thread
+      read_chunks<0, TL::EPT / 8, 8, TL, SC>(tm, r, psi + off_of(it), base, cpb + s * ns_max, rtab);
+      read_chunks<0, TL::EPT / 8, 8, TL, SC>(tm, r, lam + off_of(it), base, clb + s * ns_max, rtab);
+    } else {
+      tm.refresh();
+      tm.fetch(r, psi + off_of(it), base);
+      SC::take(tm, r, cpb + s * ns_max, rtab);
+      tm.refresh();
+      tm.fetch(r, lam + off_of(it), base);
+      SC::take(tm, r, clb + s * ns_max, rtab);
+    }
   };
   auto write_item = [&](int it, int s) {
     const uint32_t base = base_of(it);
@@ -1333,18 +1351,6 @@ __global__ __launch_bounds__(T) LDS_BOUND_OCCUPANCY void k_expv(
   }
 }
 
-// Producer side of the overlapped expectation pass: the thread's tile elements in PD chunks of
-// H, each loaded into registers and then given to LDS by rank.
-template <int C, int PD, int H, class TL, class SC>
-__device__ __forceinline__ void read_chunks(const TL& tm, typename TL::Buf& r, const double2* v,
-                                            uint32_t base, double2* cv, const uint16_t* rtab) {
-  if constexpr (C < PD) {
-    tm.refresh();
-    tm.template fetch<C * H, (C + 1) * H>(r, v, base);
-    SC::template take<C * H, (C + 1) * H>(tm, r, cv, rtab);
-    read_chunks<C + 1, PD, H, TL, SC>(tm, r, v, base, cv, rtab);
-  }
-}
 
 // Expectation / apply-H pass, overlapped form for light passes (few entries per row) whose
 // workgroups keep one tile and one value table: the lower (PD - 1) / PD of the workgroup walks
@@ -1754,15 +1760,18 @@ hipError_t rev_tw(const LaunchArgs& a, int pidx, double2* psi) {
   hipError_t e0 = a.gonly ? rev_overlapped<T, KT, false, true>(a, pidx, psi, &used)
                           : rev_overlapped<T, KT, WP>(a, pidx, psi, &used);
   if (e0 != hipSuccess || used) return e0;
+  // the non-overlapped pass keeps two vectors' tiles in registers: 14-qubit tiles take its loop
+  // form
+  constexpr int KR = KT == 14 ? 0 : KT;
   const DevPass& hp = a.hpasses[pidx];
   const int k = hp.k;
   const size_t lds = sc_lds(hp, 2);
-  hipError_t e = set_lds(k_rev<T, KT, WP>, lds);
+  hipError_t e = set_lds(k_rev<T, KR, WP>, lds);
   if (e != hipSuccess) return e;
   const int total = a.B << (a.n - k);
   const int grid =
-      pass_grid(total, resident_grid(k_rev<T, KT, WP>, T, lds, a.cu_share), 1 << (a.n - k));
-  hipLaunchKernelGGL((k_rev<T, KT, WP>), dim3(grid), dim3(T), lds, a.stream, a.passes, pidx,
+      pass_grid(total, resident_grid(k_rev<T, KR, WP>, T, lds, a.cu_share), 1 << (a.n - k));
+  hipLaunchKernelGGL((k_rev<T, KR, WP>), dim3(grid), dim3(T), lds, a.stream, a.passes, pidx,
                      a.exc, a.cls, a.pairs, a.cs, a.K, psi, a.lam, a.n, a.amask, a.bmask, a.gpart,
                      a.L, total, a.flip);
   return hipGetLastError();
@@ -1811,7 +1820,7 @@ hipError_t exp_overlapped(const LaunchArgs& a, int pidx, int eslot, int first, b
 
 // Passes with long rows over groups of batch entries (k_expv), where one Hamiltonian serves
 // the batch and the group's tiles fit beside the local value tables: four entries where they
-// fit, else two.
+// fit and the batch has four, else two.
 inline size_t expv_lds(const DevPass& hp, int V) {
   const int k = hp.k;
   const size_t nd = size_t((hp.n_slots + 1) & ~1) + size_t((hp.n_occ + 1) & ~1) + size_t((k + 2) & ~1) +
@@ -1838,9 +1847,11 @@ template <int T, int KT, bool APPLY>
 hipError_t exp_pairs(const LaunchArgs& a, int pidx, int eslot, int first, bool* used) {
   *used = false;
   const DevPass& hp = a.hpasses[pidx];
-  if (a.blob_stride != 0 || T < 64 + hp.k) return hipSuccess;
+  // a single entry takes k_exp: its sums are formed in the same order with the same operations,
+  // so an entry's result does not depend on the walk that serves it
+  if (a.B < 2 || a.blob_stride != 0 || T < 64 + hp.k) return hipSuccess;
   const size_t stat = 4 * 8 * (T / 64) + 256;
-  if (expv_lds(hp, 4) + stat <= (size_t)kLdsBytes) {
+  if (a.B >= 4 && expv_lds(hp, 4) + stat <= (size_t)kLdsBytes) {
     *used = true;
     return launch_expv<T, KT, APPLY, 4>(a, pidx, eslot, first, expv_lds(hp, 4));
   }
@@ -1932,8 +1943,10 @@ hipError_t fwd_k(const LaunchArgs& a, int pidx, int init, const double2* src, do
 template <int T>
 hipError_t rev_k(const LaunchArgs& a, int pidx, double2* psi, bool wp) {
   const int k = a.hpasses[pidx].k;
-  if constexpr (T >= 512)
+  if constexpr (T >= 512) {
+    if (k == 14) return rev_t<T, 14>(a, pidx, psi, wp);
     if (k == 13) return rev_t<T, 13>(a, pidx, psi, wp);
+  }
   if (k == 12) return rev_t<T, 12>(a, pidx, psi, wp);
   if (k == 11) return rev_t<T, 11>(a, pidx, psi, wp);
   return rev_t<T, 0>(a, pidx, psi, wp);
