@@ -811,6 +811,9 @@ __global__ __launch_bounds__(T) LDS_BOUND_OCCUPANCY void k_rev(
   using TL = Tile<T, KT>;
   using SC = Sector<T, KT>;
   constexpr bool RP = KT != 0;
+  // tiles of more than 16 elements per thread (two vectors would not fit the registers): read
+  // in chunks of 8 when taken, nothing requested ahead
+  constexpr bool CH = TL::EPT > 16;
   const DevPass ps = passes[pidx];
   const uint32_t tileN = 1u << ps.k;
   const int tb = n - ps.k;
@@ -841,7 +844,10 @@ __global__ __launch_bounds__(T) LDS_BOUND_OCCUPANCY void k_rev(
     }
   };
   auto take = [&](int it) {
-    if constexpr (RP) {
+    if constexpr (CH) {
+      read_chunks<0, TL::EPT / 8, 8, TL, SC>(tm, rp, psi + off_of(it), base_of(it), cp, rtab);
+      read_chunks<0, TL::EPT / 8, 8, TL, SC>(tm, rp, lam + off_of(it), base_of(it), cl, rtab);
+    } else if constexpr (RP) {
       SC::take(tm, rp, cp, rtab);
       SC::take(tm, rl, cl, rtab);
     } else {
@@ -852,7 +858,7 @@ __global__ __launch_bounds__(T) LDS_BOUND_OCCUPANCY void k_rev(
   stage_class(base_of(item));
   double2 csv = make_double2(1.0, 0.0);
   if (cst) csv = cs_of(item);
-  if (RP) {
+  if (RP && !CH) {
     tm.fetch(rp, psi + off_of(item), base_of(item));
     tm.fetch(rl, lam + off_of(item), base_of(item));
   }
@@ -868,7 +874,7 @@ __global__ __launch_bounds__(T) LDS_BOUND_OCCUPANCY void k_rev(
     const int next = item + gridDim.x;
     if (next < total) {
       if (cst) csv = cs_of(next);
-      if (RP) {
+      if (RP && !CH) {
         tm.refresh();
         tm.fetch(rp, psi + off_of(next), base_of(next));
         tm.fetch(rl, lam + off_of(next), base_of(next));
@@ -1760,18 +1766,15 @@ hipError_t rev_tw(const LaunchArgs& a, int pidx, double2* psi) {
   hipError_t e0 = a.gonly ? rev_overlapped<T, KT, false, true>(a, pidx, psi, &used)
                           : rev_overlapped<T, KT, WP>(a, pidx, psi, &used);
   if (e0 != hipSuccess || used) return e0;
-  // the non-overlapped pass keeps two vectors' tiles in registers: 14-qubit tiles take its loop
-  // form
-  constexpr int KR = KT == 14 ? 0 : KT;
   const DevPass& hp = a.hpasses[pidx];
   const int k = hp.k;
   const size_t lds = sc_lds(hp, 2);
-  hipError_t e = set_lds(k_rev<T, KR, WP>, lds);
+  hipError_t e = set_lds(k_rev<T, KT, WP>, lds);
   if (e != hipSuccess) return e;
   const int total = a.B << (a.n - k);
   const int grid =
-      pass_grid(total, resident_grid(k_rev<T, KR, WP>, T, lds, a.cu_share), 1 << (a.n - k));
-  hipLaunchKernelGGL((k_rev<T, KR, WP>), dim3(grid), dim3(T), lds, a.stream, a.passes, pidx,
+      pass_grid(total, resident_grid(k_rev<T, KT, WP>, T, lds, a.cu_share), 1 << (a.n - k));
+  hipLaunchKernelGGL((k_rev<T, KT, WP>), dim3(grid), dim3(T), lds, a.stream, a.passes, pidx,
                      a.exc, a.cls, a.pairs, a.cs, a.K, psi, a.lam, a.n, a.amask, a.bmask, a.gpart,
                      a.L, total, a.flip);
   return hipGetLastError();
