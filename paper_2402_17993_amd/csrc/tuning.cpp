@@ -52,7 +52,9 @@ Tuning choose_tuning(int n, int K, int batch, const ucc_options& o) {
   const int d = o.taper ? 2 : 0;
   t.kf = o.tile_qubits ? o.tile_qubits : std::min(n, 14 - d);
   t.ke = o.tile_qubits_exp ? o.tile_qubits_exp : std::min(n, 14 - d);
-  t.kr = o.tile_qubits_rev ? o.tile_qubits_rev : std::min(n, 13 - d);
+  // a recomputing sweep takes the forward sweep's tile size (its windows then mirror the
+  // forward ones); stored states need the overlapped pass's 13
+  t.kr = o.tile_qubits_rev ? o.tile_qubits_rev : std::min(n, 14 - d);
   if (t.ckpt) {  // one tile size for both sweeps, at most the reverse pass's 13
     const int k = o.tile_qubits ? o.tile_qubits : o.tile_qubits_rev ? o.tile_qubits_rev : 13 - d;
     t.kf = t.kr = std::min(n, k);
