@@ -315,7 +315,7 @@ def tapered(ucc, torch, h1, h2, exc, thetas, steps=20):
             "tile_qubits_fwd_exp_rev": [info["tile_qubits"], info["tile_qubits_exp"], info["tile_qubits_rev"]],
             "block_threads_fwd_exp_rev": [info["block_threads_fwd"], info["block_threads_exp"],
                                           info["block_threads_rev"]],
-            "store_states": info["store_states"],
+            "store_states": info["store_states"], "fuse_depth": info["fuse_depth"],
             "parity": {"max_abs_dE": de, "max_abs_dgrad": dg, "entries_checked": len(gold["entries"])}}
 
 
@@ -846,7 +846,7 @@ def main():
                                                  info["block_threads_exp"],
                                                  info["block_threads_rev"]],
                    "autotuned": bool(info["autotuned"]), "launch_mode": info["launch_mode"],
-                   "store_states": info["store_states"],
+                   "store_states": info["store_states"], "fuse_depth": info["fuse_depth"],
                    "integral_seed": ISEED, "theta_seeds": "1..64", "theta_scale": SCALE},
         "p50_ms": float(np.percentile(step_ms, 50)),
         "p99_ms": float(np.percentile(step_ms, 99)),

@@ -96,6 +96,9 @@ typedef struct {
                                 holds 2^(n_qubits - 2) amplitudes (4x fewer bytes per pass) and
                                 every energy and gradient is that of the untapered ansatz.
                                 Needs n_qubits >= 8; not with the Trotter-free calls. */
+  int32_t fuse_depth;        /* most excitation factors fused into one forward / reverse pass
+                                (1..256); 0 = as many as fit the tile (up to 256), or the
+                                autotuner's choice when autotune is set */
 } ucc_options;
 
 /* Fill *opt with defaults (all automatic, launch_mode 0, max_batch 1). */
@@ -244,6 +247,7 @@ typedef struct {
   int64_t job_footprint;     /* device bytes one server job on this context holds */
   int32_t state_qubits;      /* bits of the stored state index: n_qubits, or n_qubits - 2 tapered */
   int32_t taper;             /* the taper option in effect */
+  int32_t fuse_depth;        /* the fusion depth in effect (0: up to 256) */
 } ucc_plan_info;
 
 /* Sizes and choices made by ucc_build. */

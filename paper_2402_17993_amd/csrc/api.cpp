@@ -308,14 +308,14 @@ ucc_status resolve_launch_mode(ucc_ctx* c) {
   return UCC_OK;
 }
 
-ucc_status replan(ucc_ctx* c, int kf, int ke, int kr) {
+ucc_status replan(ucc_ctx* c, int kf, int ke, int kr, int fuse) {
   Plan& p = c->plan;
   if (p.ckpt) kr = kf;
-  if (p.kf == kf && p.ke == ke && p.kr == kr) return UCC_OK;
+  if (p.kf == kf && p.ke == ke && p.kr == kr && (fuse < 0 || fuse == p.fuse)) return UCC_OK;
   Plan np;
   const std::string msg = build_plan(np, p.nq, p.ne, p.h1.data(), p.h2.data(), p.exc.data(), p.K,
                                      kf, ke, kr, c->opt.contiguous_qubits, p.ckpt, p.M, p.order,
-                                     p.taper);
+                                     p.taper, fuse < 0 ? p.fuse : fuse);
   if (!msg.empty()) return fail(UCC_EINVAL, msg);
   np.tf = p.tf;
   np.te = p.te;
@@ -400,6 +400,8 @@ ucc_status ucc_build(int32_t n_qubits, int32_t n_elec, const double* h1, const d
   if (o.autotune && o.host_only) return fail(UCC_EINVAL, "autotune needs a device context");
   if (o.store_states < 0 || o.store_states > 2) return fail(UCC_EINVAL, "store_states must be 0..2");
   if (o.taper < 0 || o.taper > 1) return fail(UCC_EINVAL, "taper must be 0 or 1");
+  if (o.fuse_depth < 0 || o.fuse_depth > kMaxPassExc)
+    return fail(UCC_EINVAL, "fuse_depth must be 0 (automatic) or in [1, 256]");
   if (o.taper && n_qubits < 8) return fail(UCC_EINVAL, "taper needs n_qubits >= 8");
   if (o.store_states == 1 &&
       (o.tile_qubits > 13 || o.tile_qubits_rev > 13 ||
@@ -413,7 +415,7 @@ ucc_status ucc_build(int32_t n_qubits, int32_t n_elec, const double* h1, const d
   const Tuning tu = choose_tuning(n_qubits - (o.taper ? 2 : 0), n_exc, std::max(1, o.max_batch), o);
   msg = build_plan(c->plan, n_qubits, n_elec, h1, h2, exc, n_exc, tu.kf, tu.ke, tu.kr,
                    o.contiguous_qubits, tu.ckpt, std::max(1, o.trotter_steps),
-                   std::max(1, o.trotter_order), o.taper);
+                   std::max(1, o.trotter_order), o.taper, o.fuse_depth);
   if (!msg.empty()) {
     delete c;
     return fail(UCC_EINVAL, msg);
@@ -555,6 +557,7 @@ ucc_status ucc_get_plan_info(const ucc_ctx* c, ucc_plan_info* info) {
   info->n_qubits = p.nq;
   info->state_qubits = p.n;
   info->taper = p.taper;
+  info->fuse_depth = p.fuse;
   info->n_elec = p.ne;
   info->n_exc = p.K;
   info->n_pauli = (int32_t)p.pc.size();

@@ -46,6 +46,7 @@ struct Profiler {
 
 struct Tuning {
   int kf = 14, ke = 14, kr = 13, tf = 1024, te = 1024, tr = 512, launch_mode = 1;
+  int fuse = -1;  // fusion depth the autotuner chose (-1: the plan's)
   bool ckpt = false;  // stored forward states (then kr == kf)
 };
 
@@ -138,8 +139,9 @@ bool whole_launch_fits(const Plan& p, const Tables& t);
 ucc_status resolve_launch_mode(ucc_ctx* c);
 void free_tables(ucc_ctx* c);
 ucc_status upload_tables(ucc_ctx* c);
-// Re-plan for tile sizes (kf, ke, kr): new host and device tables, buffers re-allocated.
-ucc_status replan(ucc_ctx* c, int kf, int ke, int kr);
+// Re-plan for tile sizes (kf, ke, kr) and fusion depth (fuse < 0: keep the plan's): new host
+// and device tables, buffers re-allocated.
+ucc_status replan(ucc_ctx* c, int kf, int ke, int kr, int fuse = -1);
 void profile_sum(const Profiler& pr, ucc_kernel_stat* stats, hipError_t* err);
 // Time the automatic choices at batch B on this context's device and keep the fastest.
 ucc_status autotune(ucc_ctx* c, int B);

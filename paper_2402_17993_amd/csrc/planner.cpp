@@ -90,6 +90,7 @@ uint32_t pad_mask(uint32_t mask, int k, int n) {
 // factor left behind, stay for later windows in their order.
 std::vector<Plan::Pass> plan_windows(const Plan& p, int kind, int k, int c0) {
   const uint32_t F = (1u << c0) - 1u;
+  const int cap = p.fuse > 0 ? std::min(p.fuse, kMaxPassExc) : kMaxPassExc;  // fusion depth
   const int L = (int)p.seq.size();
   std::vector<int> rest(L);
   for (int t = 0; t < L; ++t) rest[t] = (kind == kRev) ? L - 1 - t : t;  // factor indices
@@ -107,7 +108,7 @@ std::vector<Plan::Pass> plan_windows(const Plan& p, int kind, int k, int c0) {
       // the spin orbitals the factor acts on: its stored support and, tapered, the tapered
       // orbitals it moves an electron into or out of (two factors sharing one do not commute)
       const uint32_t so = s | (x.tsupp << p.n);
-      if ((so & skipped) == 0 && pc32(cur.lmask | s) <= k && (int)cur.items.size() < kMaxPassExc) {
+      if ((so & skipped) == 0 && pc32(cur.lmask | s) <= k && (int)cur.items.size() < cap) {
         cur.items.push_back(e);
         cur.lmask |= s;
       } else {
@@ -367,8 +368,9 @@ inline void tapered_occ(const Plan& p, uint32_t ph, int ag, int bg, int& oa, int
 
 std::string build_plan(Plan& p, int n, int ne, const double* h1, const double* h2,
                        const int32_t* exc, int K, int kf, int ke, int kr, int c0, bool ckpt,
-                       int M, int order, int taper) {
+                       int M, int order, int taper, int fuse) {
   p = Plan();
+  p.fuse = std::max(0, fuse);
   if (taper && (n < 8 || ne > n - 2)) return "taper needs n_qubits >= 8 and two empty spin orbitals";
   p.n = n;
   p.nq = n;

@@ -96,7 +96,7 @@ ucc_status autotune(ucc_ctx* c, int B) {
     auto it = g_cache.find(key);
     if (it != g_cache.end()) {
       const Tuning tu = it->second;
-      ucc_status s = replan(c, tu.kf, tu.ke, tu.kr);
+      ucc_status s = replan(c, tu.kf, tu.ke, tu.kr, tu.fuse);
       if (s != UCC_OK) return s;
       apply_tuning(p, tu);
       p.autotuned = true;
@@ -179,6 +179,40 @@ ucc_status autotune(ucc_ctx* c, int B) {
   s = replan(c, tu.kf, tu.ke, tu.kr);
   if (s != UCC_OK) return s;
   apply_tuning(p, tu);
+  // fusion depth (when the option leaves it automatic): windows capped at fewer factors hold
+  // shorter excitation chains, which helps where a long chain outlasts its tile's traffic; the
+  // sweeps are timed with the chosen tiles and workgroups and the fastest cap kept
+  if (o.fuse_depth == 0) {
+    double best = 1e300;
+    int best_f = 0;
+    for (int F : {0, 96, 64, 40}) {
+      s = replan(c, tu.kf, tu.ke, tu.kr, F);
+      if (s == UCC_OK) s = ensure_buffers(c, c->buf, B, true);
+      if (s != UCC_OK) return s;
+      apply_tuning(p, tu);
+      p.launch_mode = 1;
+      std::vector<double> th(size_t(B) * p.K, 0.01);
+      hipError_t e = hipMemcpy(c->buf.theta, th.data(), th.size() * sizeof(double), hipMemcpyHostToDevice);
+      if (e != hipSuccess) return hip_fail(e, "autotune theta upload");
+      Profiler pr;
+      s = enqueue_eval(c, c->buf, c->buf.theta, B, true, nullptr, nullptr);  // warm-up
+      for (int rep = 0; rep < 2 && s == UCC_OK; ++rep)
+        s = enqueue_eval(c, c->buf, c->buf.theta, B, true, nullptr, &pr);
+      if (s != UCC_OK) return s;
+      ucc_kernel_stat st[UCC_KERNEL_KINDS];
+      profile_sum(pr, st, &e);
+      if (e != hipSuccess) return hip_fail(e, "autotune events");
+      const double ms = st[UCC_KERNEL_FWD].ms + st[UCC_KERNEL_REV].ms;
+      if (ms < best * 0.98) {  // a cap must win clearly over no cap
+        best = ms;
+        best_f = F;
+      }
+    }
+    tu.fuse = best_f;
+    s = replan(c, tu.kf, tu.ke, tu.kr, tu.fuse);
+    if (s != UCC_OK) return s;
+    apply_tuning(p, tu);
+  }
   p.autotuned = true;
   {
     std::lock_guard<std::mutex> lock(g_cache_mu);

@@ -119,6 +119,7 @@ struct Plan {
   int n = 0, ne = 0, ns = 0, K = 0;
   int nq = 0;     // spin orbitals (logical qubits); n = nq - 2 when tapered, else nq
   int taper = 0;  // 1: the two highest spin orbitals are tapered
+  int fuse = 0;   // most factors per forward / reverse window (0: kMaxPassExc)
   int nalpha = 0, nbeta = 0;
   uint64_t nsec = 0;  // basis states with N = ne, S_z = 0
   std::vector<double> h1, h2;
@@ -203,7 +204,7 @@ std::string validate_inputs(int n, int ne, const double* h1, const double* h2, c
 // taper: two-qubit tapering (see Plan); n is the number of spin orbitals either way.
 std::string build_plan(Plan& p, int n, int ne, const double* h1, const double* h2,
                        const int32_t* exc, int K, int kf, int ke, int kr, int c0, bool ckpt,
-                       int M = 1, int order = 1, int taper = 0);
+                       int M = 1, int order = 1, int taper = 0, int fuse = 0);
 void build_tables(const Plan& p, Tables& t);
 // Trotter-free evaluation (Sec. 3.2): the generator A = sum_k theta_k G_k written as x-groups,
 // one per excitation (x = its support, values +-sigma_k on the two patterns G_k connects, no

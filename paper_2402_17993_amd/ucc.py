@@ -44,7 +44,8 @@ class Options(ctypes.Structure):
                 ("launch_mode", _i32), ("host_only", _i32), ("device", _i32),
                 ("block_threads_fwd", _i32), ("block_threads_exp", _i32),
                 ("block_threads_rev", _i32), ("tile_qubits_exp", _i32), ("autotune", _i32),
-                ("store_states", _i32), ("trotter_order", _i32), ("taper", _i32)]
+                ("store_states", _i32), ("trotter_order", _i32), ("taper", _i32),
+                ("fuse_depth", _i32)]
 
 
 class PlanInfo(ctypes.Structure):
@@ -57,7 +58,7 @@ class PlanInfo(ctypes.Structure):
                 ("block_threads_rev", _i32), ("launch_mode", _i32), ("autotuned", _i32),
                 ("store_states", _i32), ("trotter_steps", _i32), ("trotter_order", _i32),
                 ("perm", _i32 * 32), ("job_footprint", ctypes.c_int64),
-                ("state_qubits", _i32), ("taper", _i32)]
+                ("state_qubits", _i32), ("taper", _i32), ("fuse_depth", _i32)]
 
 
 class KernelStat(ctypes.Structure):
@@ -146,7 +147,7 @@ class Context:
                  contiguous_qubits=0, block_threads=0, block_threads_fwd=0,
                  block_threads_exp=0, block_threads_rev=0, max_batch=1, launch_mode=0,
                  autotune=False, store_states=0, trotter_steps=1, trotter_order=1,
-                 taper=0, host_only=False, device=-1):
+                 taper=0, fuse_depth=0, host_only=False, device=-1):
         L = lib()
         self._h = None
         self.n_qubits, self.n_elec = int(n_qubits), int(n_elec)
@@ -165,6 +166,7 @@ class Context:
         o.store_states = store_states
         o.trotter_steps, o.trotter_order = trotter_steps, trotter_order
         o.taper = int(taper)
+        o.fuse_depth = int(fuse_depth)
         o.host_only, o.device = int(bool(host_only)), device
         h = _vp()
         check(L.ucc_build(self.n_qubits, self.n_elec, _ptr(h1), _ptr(h2), _ptr(exc),

@@ -500,3 +500,19 @@ def test_tapered_windows_keep_non_commuting_factors_in_order(n, ne, kw):
         K = len(exc)
         check_commuting_reorder(fwd, np.arange(K), orb[order])
         check_commuting_reorder(rev, np.arange(K)[::-1], orb[order])
+
+
+def test_fusion_depth_caps_the_windows():
+    """fuse_depth F: no forward or reverse window holds more than F factors, the windows still
+    cover the Trotter product in order, and the option is range-checked."""
+    n, ne = 18, 10
+    free = host_ctx(n, ne)[0]
+    capped, _, _, exc = host_ctx(n, ne, fuse_depth=16)
+    assert capped.plan_info()["fuse_depth"] == 16
+    counts = [len(p["items"]) for p in capped.pass_table() if p["kind"] != 1]
+    assert max(counts) <= 16 < max(len(p["items"]) for p in free.pass_table() if p["kind"] != 1)
+    fwd = np.concatenate([p["items"] for p in capped.pass_table() if p["kind"] == 0])
+    check_commuting_reorder(fwd, np.arange(len(exc)), capped.excitation_table()["supp"])
+    for bad in (-1, 257):
+        with pytest.raises(ucc.UCCError):
+            host_ctx(8, 4, fuse_depth=bad)
