@@ -135,9 +135,10 @@ def one_at_a_time(ctx, td):
     return td.shape[0] / (time.perf_counter() - t0)
 
 
-def served_same_workload(ucc, h1, h2, exc, thetas, iters=4):
-    """The workload's 64 theta vectors as 64 steepest-descent jobs on the server."""
-    ctx = ucc.Context(N, NE, h1, h2, exc, max_batch=0, device=0, autotune=True)
+def served_same_workload(ucc, h1, h2, exc, thetas, iters=20):
+    """The workload's 64 theta vectors as 64 steepest-descent jobs on the server (the context
+    tuned for the batch the server will form)."""
+    ctx = ucc.Context(N, NE, h1, h2, exc, max_batch=BATCH, device=0, autotune=True)
     with ucc.Server(slots=BATCH) as srv:
         t0 = time.perf_counter()
         tickets = [srv.submit(ctx, thetas[b], iters, 0.1) for b in range(BATCH)]

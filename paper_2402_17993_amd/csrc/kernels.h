@@ -67,6 +67,9 @@ hipError_t launch_gen(const LaunchArgs& a, int pidx, int first, const GenPassArg
 // Reverse pass pidx on (psi, a.lam); write_psi = 0: psi is a stored state, read only.
 hipError_t launch_rev(const LaunchArgs& a, int pidx, double2* psi, bool write_psi);
 hipError_t launch_reduce(const LaunchArgs& a, int ne, bool grad, int nt);
+// theta[b][k] -= lr[b] * G[b][k] (product rounded first) for B rows of K.
+hipError_t launch_sd_update(double* theta, const double* G, const double* lr, int B, int K,
+                            hipStream_t st);
 
 // Trotter-free evaluation (chebyshev.hip).  Chebyshev series of exp(A) with rho = max(sum_k
 // |theta_k|, kChebRhoMin) per entry, cut where the tail bound falls below kChebTol, at most

@@ -190,6 +190,18 @@ __global__ void k_trig(const double* __restrict__ theta, double2* __restrict__ c
   }
 }
 
+// One steepest-descent step on the device, theta <- theta - lr_b * grad for every entry b, with
+// the product rounded before the difference (no fused multiply-add), as the host does it.
+__global__ void k_sd_update(double* __restrict__ theta, const double* __restrict__ G,
+                            const double* __restrict__ lr, int B, int K) {
+#pragma clang fp contract(off)
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < B * K) {
+    const double step = lr[i / K] * G[i];
+    theta[i] = theta[i] - step;
+  }
+}
+
 // Shared-memory staging of a forward/reverse pass: its excitation records and their
 // (cos, sin) for the current batch entry.
 struct PassStage {
@@ -2038,6 +2050,13 @@ hipError_t launch_whole(const LaunchArgs& a, const double* theta, bool grad, int
     return hipGetLastError();
   };
   return grad ? go(k_whole<256, true>) : go(k_whole<256, false>);
+}
+
+hipError_t launch_sd_update(double* theta, const double* G, const double* lr, int B, int K,
+                            hipStream_t st) {
+  const int total = B * K;
+  hipLaunchKernelGGL(k_sd_update, dim3((total + 255) / 256), dim3(256), 0, st, theta, G, lr, B, K);
+  return hipGetLastError();
 }
 
 hipError_t launch_reduce(const LaunchArgs& a, int ne, bool grad, int nt) {

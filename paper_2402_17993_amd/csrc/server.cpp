@@ -11,10 +11,14 @@
 // the entry's row.
 //
 // Rounds are per group: each group has its own stream and iterates at its own pace (one
-// round = E and dE/dtheta for every member, then theta <- theta - lr * grad on the host), so
-// small fragments are not held back by large ones, and the groups' kernels overlap on the
-// device.  One worker thread launches idle groups and polls the in-flight ones; jobs join
-// and leave a group between its rounds.
+// round = E and dE/dtheta for every member, then theta <- theta - lr * grad), so small
+// fragments are not held back by large ones, and the groups' kernels overlap on the device.
+// The step is taken on the device right behind the round (and mirrored on the host, with the
+// same rounding, for the jobs' records), so while the membership stays the same -- nobody
+// joins, leaves or is cancelled at the next round -- the group's next round is enqueued
+// before this one finishes: two rounds in flight, no host round trip between them.  One
+// worker thread launches groups and polls the in-flight rounds; jobs join and leave a group
+// when it has no round in flight.
 //
 // Results do not depend on the mix: every batch entry is computed by the same kernels in the
 // same order whatever else is in the batch, and the host update is plain IEEE arithmetic.
@@ -105,12 +109,15 @@ struct Group {
   int bank_cap = 0;
   std::vector<const ucc_ctx*> bank_rows;
   double* h_theta = nullptr;  // pinned host staging
-  double* h_E = nullptr;
-  double* h_G = nullptr;
+  double* h_E[2] = {nullptr, nullptr};  // results of the (up to) two rounds in flight
+  double* h_G[2] = {nullptr, nullptr};
+  double* d_lr = nullptr;     // [cap] step size of each row (device)
+  double* h_lr = nullptr;     // its pinned staging
   int h_cap = 0;
   hipStream_t stream = nullptr;
-  hipEvent_t done_ev = nullptr;
-  bool in_flight = false;
+  hipEvent_t done_ev[2] = {nullptr, nullptr};
+  int queued = 0;  // rounds in flight
+  int head = 0;    // result slot of the oldest of them
 };
 
 void free_group(Group& g) {
@@ -118,9 +125,13 @@ void free_group(Group& g) {
   free_buffers(g.buf);
   if (g.bank) (void)hipFree(g.bank);
   if (g.h_theta) (void)hipHostFree(g.h_theta);
-  if (g.h_E) (void)hipHostFree(g.h_E);
-  if (g.h_G) (void)hipHostFree(g.h_G);
-  if (g.done_ev) (void)hipEventDestroy(g.done_ev);
+  for (int i = 0; i < 2; ++i) {
+    if (g.h_E[i]) (void)hipHostFree(g.h_E[i]);
+    if (g.h_G[i]) (void)hipHostFree(g.h_G[i]);
+    if (g.done_ev[i]) (void)hipEventDestroy(g.done_ev[i]);
+  }
+  if (g.d_lr) (void)hipFree(g.d_lr);
+  if (g.h_lr) (void)hipHostFree(g.h_lr);
   if (g.stream) (void)hipStreamDestroy(g.stream);
   g = Group();
 }
@@ -146,13 +157,23 @@ ucc_status prepare_group(Group& g, int B, int slots, bool mixed) {
   }
   if (B > g.h_cap) {
     if (g.h_theta) (void)hipHostFree(g.h_theta);
-    if (g.h_E) (void)hipHostFree(g.h_E);
-    if (g.h_G) (void)hipHostFree(g.h_G);
-    g.h_theta = g.h_E = g.h_G = nullptr;
+    g.h_theta = nullptr;
+    for (int i = 0; i < 2; ++i) {
+      if (g.h_E[i]) (void)hipHostFree(g.h_E[i]);
+      if (g.h_G[i]) (void)hipHostFree(g.h_G[i]);
+      g.h_E[i] = g.h_G[i] = nullptr;
+    }
+    if (g.d_lr) (void)hipFree(g.d_lr);
+    if (g.h_lr) (void)hipHostFree(g.h_lr);
+    g.d_lr = g.h_lr = nullptr;
     g.h_cap = 0;
     hipError_t e = hipHostMalloc(reinterpret_cast<void**>(&g.h_theta), size_t(cap) * p.K * 8);
-    if (e == hipSuccess) e = hipHostMalloc(reinterpret_cast<void**>(&g.h_E), size_t(cap) * 8);
-    if (e == hipSuccess) e = hipHostMalloc(reinterpret_cast<void**>(&g.h_G), size_t(cap) * p.K * 8);
+    for (int i = 0; i < 2 && e == hipSuccess; ++i) {
+      e = hipHostMalloc(reinterpret_cast<void**>(&g.h_E[i]), size_t(cap) * 8);
+      if (e == hipSuccess) e = hipHostMalloc(reinterpret_cast<void**>(&g.h_G[i]), size_t(cap) * p.K * 8);
+    }
+    if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&g.d_lr), size_t(cap) * 8);
+    if (e == hipSuccess) e = hipHostMalloc(reinterpret_cast<void**>(&g.h_lr), size_t(cap) * 8);
     if (e != hipSuccess) return hip_fail(e, "hipHostMalloc(server staging)");
     g.h_cap = cap;
   }
@@ -169,18 +190,26 @@ ucc_status prepare_group(Group& g, int B, int slots, bool mixed) {
   return UCC_OK;
 }
 
-// Enqueue one round of group g on its stream: theta rows in, E and grad out.  The pass
-// kernels fill at most cu_share compute units (0 = all).
-ucc_status launch_round(Group& g, int slots, int cu_share) {
+// Enqueue one round of group g on its stream: E and grad out into the next result slot, then
+// the step theta <- theta - lr * grad on the device.  fresh: the membership may have changed
+// since the last round, so the rows' theta, step sizes (and value tables) are uploaded first;
+// otherwise the device theta is the previous round's stepped one.  The pass kernels fill at
+// most cu_share compute units (0 = all).
+ucc_status launch_round(Group& g, int slots, int cu_share, bool fresh) {
   const int B = (int)g.jobs.size();
   const int K = g.proto->plan.K;
   bool mixed = false;
   for (Job* j : g.jobs) mixed |= j->ctx != g.proto;
-  ucc_status s = prepare_group(g, B, slots, mixed);
-  if (s != UCC_OK) return s;
-  for (int r = 0; r < B; ++r) std::memcpy(g.h_theta + size_t(r) * K, g.jobs[r]->theta.data(), size_t(K) * 8);
-  hipError_t e = hipMemcpyAsync(g.buf.theta, g.h_theta, size_t(B) * K * 8, hipMemcpyHostToDevice, g.stream);
-  if (e == hipSuccess && mixed) {
+  hipError_t e = hipSuccess;
+  if (fresh) {
+    ucc_status s = prepare_group(g, B, slots, mixed);
+    if (s != UCC_OK) return s;
+    for (int r = 0; r < B; ++r) std::memcpy(g.h_theta + size_t(r) * K, g.jobs[r]->theta.data(), size_t(K) * 8);
+    e = hipMemcpyAsync(g.buf.theta, g.h_theta, size_t(B) * K * 8, hipMemcpyHostToDevice, g.stream);
+    for (int r = 0; r < B; ++r) g.h_lr[r] = g.jobs[r]->lr;
+    if (e == hipSuccess) e = hipMemcpyAsync(g.d_lr, g.h_lr, size_t(B) * 8, hipMemcpyHostToDevice, g.stream);
+  }
+  if (e == hipSuccess && fresh && mixed) {
     const size_t words = g.proto->tab.blob.size();
     for (int r = 0; r < B && e == hipSuccess; ++r) {
       const ucc_ctx* c = g.jobs[r]->ctx;
@@ -193,13 +222,17 @@ ucc_status launch_round(Group& g, int slots, int cu_share) {
     std::fill(g.bank_rows.begin(), g.bank_rows.end(), nullptr);
     return hip_fail(e, "server copies");
   }
-  s = enqueue_eval(g.proto, g.buf, g.buf.theta, B, true, g.stream, nullptr, mixed ? g.bank : nullptr,
-                   cu_share);
+  ucc_status s = enqueue_eval(g.proto, g.buf, g.buf.theta, B, true, g.stream, nullptr,
+                              mixed ? g.bank : nullptr, cu_share);
   if (s != UCC_OK) return s;
-  e = hipMemcpyAsync(g.h_E, g.buf.E, size_t(B) * 8, hipMemcpyDeviceToHost, g.stream);
-  if (e == hipSuccess) e = hipMemcpyAsync(g.h_G, g.buf.G, size_t(B) * K * 8, hipMemcpyDeviceToHost, g.stream);
-  if (e == hipSuccess) e = hipEventRecord(g.done_ev, g.stream);
+  const int slot = (g.head + g.queued) & 1;
+  e = hipMemcpyAsync(g.h_E[slot], g.buf.E, size_t(B) * 8, hipMemcpyDeviceToHost, g.stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(g.h_G[slot], g.buf.G, size_t(B) * K * 8, hipMemcpyDeviceToHost, g.stream);
+  if (e == hipSuccess) e = hipEventRecord(g.done_ev[slot], g.stream);
+  if (e == hipSuccess) e = launch_sd_update(g.buf.theta, g.buf.G, g.d_lr, B, K, g.stream);
   if (e != hipSuccess) return hip_fail(e, "server result copies");
+  ++g.queued;
   return UCC_OK;
 }
 
@@ -251,7 +284,8 @@ Group* ucc_server::group_for(ucc_ctx* c) {
   std::unique_ptr<Group> g(new (std::nothrow) Group());
   if (!g) return nullptr;
   if (hipStreamCreateWithFlags(&g->stream, hipStreamNonBlocking) != hipSuccess ||
-      hipEventCreateWithFlags(&g->done_ev, hipEventDisableTiming) != hipSuccess) {
+      hipEventCreateWithFlags(&g->done_ev[0], hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&g->done_ev[1], hipEventDisableTiming) != hipSuccess) {
     (void)hipGetLastError();
     free_group(*g);
     return nullptr;
@@ -313,8 +347,20 @@ int ucc_server::cu_share_for(const Group& g) const {
 }
 
 // Results of a finished round: record E, update theta, retire completed/cancelled jobs.
+// Whether group g may enqueue its next round behind the one in flight: every member needs
+// that round too (the one in flight is not its last), nobody is cancelled and nobody waits
+// to join, so the rows stay as they are.
+static bool can_pipeline(const Group& g) {
+  if (g.queued != 1 || !g.joining.empty() || g.jobs.empty()) return false;
+  for (const Job* j : g.jobs)
+    if (j->cancel || (int)j->traj.size() + 2 > j->iters + 1) return false;
+  return true;
+}
+
 void ucc_server::finish_round_locked(Group& g, ucc_status st, const std::string& err) {
   const int K = g.proto->plan.K;
+  const double* hE = g.h_E[g.head];
+  const double* hG = g.h_G[g.head];
   std::vector<Job*> keep;
   for (size_t r = 0; r < g.jobs.size(); ++r) {
     Job* j = g.jobs[r];
@@ -324,14 +370,15 @@ void ucc_server::finish_round_locked(Group& g, ucc_status st, const std::string&
       continue;
     }
     j->rounds += 1;
-    j->traj.push_back(g.h_E[r]);
+    j->traj.push_back(hE[r]);
     if ((int)j->traj.size() == j->iters + 1) {
       retire_locked(j, UCC_OK);
       continue;
     }
-    const double* gr = g.h_G + r * size_t(K);
+    // the host record of the step the device took (same rounding: product, then difference)
+    const double* gr = hG + r * size_t(K);
     for (int k = 0; k < K; ++k) {
-      const double step = j->lr * gr[k];  // rounded product, then the difference
+      const double step = j->lr * gr[k];
       j->theta[k] = j->theta[k] - step;
     }
     keep.push_back(j);
@@ -346,27 +393,44 @@ void ucc_server::run() {
     if (stop) break;
     admit_locked();
     bool progress = false, any_done = false, in_flight = false;
-    // rounds that finished
+    // rounds that finished, oldest first
     for (auto& gp : groups) {
       Group& g = *gp;
-      if (!g.in_flight) continue;
-      const hipError_t e = hipEventQuery(g.done_ev);
-      if (e == hipErrorNotReady) {
-        in_flight = true;
+      while (g.queued > 0) {
+        const hipError_t e = hipEventQuery(g.done_ev[g.head]);
+        if (e == hipErrorNotReady) {
+          in_flight = true;
+          break;
+        }
+        progress = true;
+        const ucc_status st = e == hipSuccess ? UCC_OK : hip_fail(e, "server round");
+        const size_t before = g.jobs.size();
+        if (st != UCC_OK) (void)hipStreamSynchronize(g.stream);  // nothing may still run on the rows
+        finish_round_locked(g, st, g_last_error);
+        g.head ^= 1;
+        g.queued = st == UCC_OK ? g.queued - 1 : 0;
+        any_done |= g.jobs.size() != before;
+        if (g.jobs.size() != before) members_changed(g);
+      }
+    }
+    for (auto& gp : groups) {
+      Group& g = *gp;
+      if (g.queued >= 2) continue;
+      if (g.queued == 1) {  // the next round behind the one in flight, same rows
+        if (!can_pipeline(g)) continue;
+        const ucc_status st = launch_round(g, slots, cu_share_for(g), false);
+        progress = true;
+        if (st != UCC_OK) {
+          const size_t before = g.jobs.size();
+          (void)hipStreamSynchronize(g.stream);
+          finish_round_locked(g, st, g_last_error);
+          g.queued = 0;
+          any_done |= g.jobs.size() != before;
+          members_changed(g);
+        }
         continue;
       }
-      g.in_flight = false;
-      progress = true;
-      const ucc_status st = e == hipSuccess ? UCC_OK : hip_fail(e, "server round");
-      const size_t before = g.jobs.size();
-      finish_round_locked(g, st, g_last_error);
-      any_done |= g.jobs.size() != before;
-      if (g.jobs.size() != before) members_changed(g);
-    }
-    // idle groups: membership changes, then the next round
-    for (auto& gp : groups) {
-      Group& g = *gp;
-      if (g.in_flight) continue;
+      // no round in flight: membership changes, then the next round
       std::vector<Job*> keep;
       for (Job* j : g.jobs) {
         if (j->cancel) {
@@ -389,24 +453,24 @@ void ucc_server::run() {
       g.jobs.swap(keep);
       if (changed) members_changed(g);
       if (g.jobs.empty()) continue;
-      const ucc_status st = launch_round(g, slots, cu_share_for(g));
+      const ucc_status st = launch_round(g, slots, cu_share_for(g), true);
       progress = true;
       if (st != UCC_OK) {
         const size_t before = g.jobs.size();
         // nothing of this round may still be running on the stream before rows are reused
         (void)hipStreamSynchronize(g.stream);
         finish_round_locked(g, st, g_last_error);
+        g.queued = 0;
         any_done |= g.jobs.size() != before;
         members_changed(g);
       } else {
-        g.in_flight = true;
         in_flight = true;
       }
     }
     // empty groups give their memory back
     for (auto it = groups.begin(); it != groups.end();) {
       Group& g = **it;
-      if (!g.in_flight && g.jobs.empty() && g.joining.empty()) {
+      if (g.queued == 0 && g.jobs.empty() && g.joining.empty()) {
         free_group(g);
         it = groups.erase(it);
       } else {
