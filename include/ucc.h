@@ -63,7 +63,15 @@ typedef struct {
                                 batch's tiles); 2 the whole evaluation in one launch, one
                                 workgroup per theta vector holding the state's N/S_z sector in
                                 LDS -- only for states that are a single tile (n_qubits <= 12);
-                                auto picks 2 where it applies */
+                                auto picks 2 where it applies; 3 the evaluation graph: every
+                                pass of an energy + gradient call in one persistent launch
+                                (graph.hip), each (pass, batch entry, tile) item released when
+                                the previous pass has completed that entry's items (per-entry
+                                counters, bounded waits), results bit for bit those of mode 1
+                                with the same tiles; 512-thread workgroups, tiles of at most
+                                13 qubits, no taper; energy-only calls use the mode 1
+                                launches.  Contexts in mode 3 can also share one launch
+                                (ucc_energy_grad_jobs, server groups) */
   int32_t host_only;         /* 1: plan on the host only (no device memory, no evaluation);
                                 for introspection and tests on machines without a GPU */
   int32_t device;            /* HIP device ordinal; -1 = current device */
@@ -99,6 +107,9 @@ typedef struct {
   int32_t fuse_depth;        /* most excitation factors fused into one forward / reverse pass
                                 (1..256); 0 = as many as fit the tile (up to 256), or the
                                 autotuner's choice when autotune is set */
+  int32_t graph_wait_us;     /* launch_mode 3: longest time one item may wait for the items
+                                it depends on before the launch gives up (microseconds of wall
+                                clock; 0 = 2,000,000); see ucc_graph_status */
 } ucc_options;
 
 /* Fill *opt with defaults (all automatic, launch_mode 0, max_batch 1). */
@@ -149,6 +160,39 @@ ucc_status ucc_energy(ucc_ctx* ctx, const double* theta, int32_t B, double* ener
 ucc_status ucc_energy_grad(ucc_ctx* ctx, const double* theta, int32_t B, double* energy,
                            double* grad, void* stream);
 
+/*
+ * ucc_energy_grad_jobs -- ucc_energy_grad of several contexts (jobs of different sizes, e.g.
+ * the fragments and pairs of Eq. 1) in ONE launch of the evaluation graph (launch_mode 3):
+ * the jobs' passes run interleaved stage by stage, each job's items gated by its own per-entry
+ * counters, so a job does not wait for another's passes.  Every result equals that job's own
+ * ucc_energy_grad bit for bit.
+ *
+ *   ctx[j]     njobs distinct contexts built with launch_mode 3 on the current device
+ *   B[j]       batch of job j (as ucc_energy_grad)
+ *   theta[j], energy[j], grad[j]   as ucc_energy_grad, per job (host or device pointers)
+ *   njobs      1 .. 4
+ *   stream     as ucc_energy_grad
+ * Each job uses its context's buffers (the context holds the job's state afterwards, as after
+ * ucc_energy_grad).
+ * Errors: UCC_EINVAL (bad argument, a context not in mode 3, repeated contexts, a plan the
+ * graph cannot run: more than 512 passes or an overlapped pass at tiles other than 12 or 13
+ * qubits, or too little LDS or too few resident workgroups); UCC_EBUSY (a context held by a
+ * server job); UCC_EDEVICE (launch failure; for host outputs also a launch that gave up
+ * waiting, see ucc_graph_status); UCC_ENOMEM.
+ */
+ucc_status ucc_energy_grad_jobs(ucc_ctx* const* ctx, const int32_t* B, const double* const* theta,
+                                double* const* energy, double* const* grad, int32_t njobs,
+                                void* stream);
+
+/*
+ * ucc_graph_status -- whether an evaluation-graph launch of ctx gave up: a wait that outlasted
+ * graph_wait_us (e.g. a device hung by other work) makes every workgroup of the launch stop;
+ * the launch's energies and gradients are then NaN.  Synchronizes `stream` (the stream of the
+ * calls to check), returns UCC_EDEVICE if a launch of ctx gave up since the last check (and
+ * clears the mark), else UCC_OK.  Calls with host outputs check by themselves.
+ */
+ucc_status ucc_graph_status(ucc_ctx* ctx, void* stream);
+
 /* Device scratch held by the allocation-free entry point, per GPU, until the process ends. */
 #define UCC_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
 
@@ -171,7 +215,8 @@ ucc_status ucc_energy_grad(ucc_ctx* ctx, const double* theta, int32_t B, double*
  * must start at zero is cleared by a kernel on the stream): calls that overlap on one GPU
  * (different streams or threads, any contexts) race and must be serialized by the caller.
  * The context's own buffers are not touched, so ucc_get_state does not see this call's state.
- * Errors: UCC_EINVAL (NULL or host pointers, B out of range, host_only context),
+ * Errors: UCC_EINVAL (NULL or host pointers, B out of range, host_only context, a context in
+ *         launch_mode 3),
  *         UCC_ENOMEM (the call needs more than UCC_NOALLOC_SCRATCH_BYTES), UCC_EBUSY (a server
  *         job holds the context), UCC_EDEVICE (HIP errors, symbol lookup).
  */
@@ -248,6 +293,8 @@ typedef struct {
   int32_t state_qubits;      /* bits of the stored state index: n_qubits, or n_qubits - 2 tapered */
   int32_t taper;             /* the taper option in effect */
   int32_t fuse_depth;        /* the fusion depth in effect (0: up to 256) */
+  int32_t graph_grid;        /* launch_mode 3: workgroups of the last graph launch (0: none yet) */
+  int32_t graph_lds;         /* launch_mode 3: its dynamic LDS bytes per workgroup */
 } ucc_plan_info;
 
 /* Sizes and choices made by ucc_build. */
@@ -382,6 +429,7 @@ enum {
   UCC_KERNEL_WHOLE = 6,  /* whole evaluation of a one-tile state in one launch (launch_mode 2) */
   UCC_KERNEL_GEN = 7,    /* Trotter-free: generator product pass (y += (2/rho) A x) */
   UCC_KERNEL_CHEB = 8,   /* Trotter-free: series coefficients, value tables, start, sum update */
+  UCC_KERNEL_GRAPH = 9,  /* evaluation graph: every pass of one or more evaluations (mode 3) */
   UCC_KERNEL_KINDS = 10
 };
 

@@ -66,17 +66,26 @@ void free_buffers(Buffers& b) {
   free_ptr(b.gpart);
   free_ptr(b.E);
   free_ptr(b.G);
+  free_ptr(b.gctl);
   b = Buffers();
+}
+
+size_t graph_ctl_words(const ucc_ctx* c, int cap) {
+  const Plan& p = c->plan;
+  if (p.launch_mode != 3) return 0;
+  const size_t stages = size_t(p.nfwd + p.nexp + p.nrev) + 2;
+  return (8 + (stages - 1) * size_t(cap) + 3) & ~size_t(3);
 }
 
 ucc_status ensure_buffers(const ucc_ctx* c, Buffers& b, int B, bool need_lam) {
   const Plan& p = c->plan;
   const size_t S = size_t(1) << p.n;
-  if (B <= b.cap && (!need_lam || b.lam)) return UCC_OK;
+  const bool graph = c->plan.launch_mode == 3;
+  if (B <= b.cap && (!need_lam || b.lam) && (!graph || b.gctl)) return UCC_OK;
   hipError_t e = hipDeviceSynchronize();
   if (e != hipSuccess) return hip_fail(e, "hipDeviceSynchronize");
   const int cap = std::max(B, b.cap);
-  const bool lam = need_lam || b.lam != nullptr;
+  const bool lam = need_lam || b.lam != nullptr || graph;
   free_buffers(b);
   b.cap = cap;
   const size_t nte = size_t(1) << (p.n - p.ke);
@@ -94,6 +103,7 @@ ucc_status ensure_buffers(const ucc_ctx* c, Buffers& b, int B, bool need_lam) {
       {reinterpret_cast<void**>(&b.lam), lam ? cap * S * 16 : 0},
       {reinterpret_cast<void**>(&b.gpart), lam ? cap * p.seq.size() * ntr * 8 : 0},
       {reinterpret_cast<void**>(&b.ck), lam && p.ckpt ? size_t(p.nfwd - 1) * cap * S * 16 : 0},
+      {reinterpret_cast<void**>(&b.gctl), graph_ctl_words(c, cap) * 4},
   };
   for (auto& r : reqs) {
     if (r.bytes == 0) continue;
@@ -107,6 +117,7 @@ ucc_status ensure_buffers(const ucc_ctx* c, Buffers& b, int B, bool need_lam) {
   // N / S_z sector, which no kernel writes.
   e = hipMemset(b.psi, 0, cap * S * 16);
   if (e == hipSuccess && b.lam) e = hipMemset(b.lam, 0, cap * S * 16);
+  if (e == hipSuccess && b.gctl) e = hipMemset(b.gctl, 0, graph_ctl_words(c, cap) * 4);
   if (e != hipSuccess) {
     free_buffers(b);
     return hip_fail(e, "hipMemset(state buffers)");
@@ -172,8 +183,133 @@ Profiler::~Profiler() {
     if (e) (void)hipEventDestroy(e);
 }
 
+// Algorithmic HBM bytes of one energy + gradient evaluation (the per-kind model of
+// ucc_kernel_stat summed over the launch sequence).
+static double eval_bytes(const Plan& p, int B) {
+  const double S = 16.0 * double(size_t(1) << p.n) * B;
+  const double sec = 16.0 * double(p.nsec) * B;
+  const int nte = 1 << (p.n - p.ke);
+  double t = 24.0 * B * p.K + S + 2 * S * (p.nfwd - 1);
+  for (int j = 0; j < p.nexp; ++j) t += S + (j == 0 ? sec : 2 * sec);
+  t += (p.ckpt ? 3 : 4) * S * p.nrev;
+  t += 8.0 * B * (double(p.nexp) * nte + double(p.seq.size()) * (1 << (p.n - p.kr)));
+  return t;
+}
+
+ucc_status graph_job(const ucc_ctx* c, Buffers& b, const double* d_theta, int B,
+                     const uint32_t* blob_bank, GraphJob* job, size_t* lds, int* align) {
+  const Plan& p = c->plan;
+  if (p.launch_mode != 3) return fail(UCC_EINVAL, "the context was not built with launch_mode 3");
+  const int P = p.nfwd + p.nexp + p.nrev;
+  if (P > kMaxGraphPasses) return fail(UCC_EINVAL, "the evaluation graph takes at most 512 passes");
+  if (!b.gctl || B > b.cap) return fail(UCC_EINVAL, "graph buffers missing");
+  LaunchArgs a = make_args(c, b, B, nullptr);
+  if (blob_bank) {
+    a.blobs = reinterpret_cast<const uint4*>(blob_bank);
+    a.blob_stride = (int)(c->tab.blob.size() / 4);
+  }
+  GraphJob J;
+  J.passes = c->d_passes;
+  J.exc = c->d_exc;
+  J.cls = reinterpret_cast<const int2*>(c->d_cls);
+  J.pairs = c->d_pairs;
+  J.blobs = a.blobs;
+  J.occ = c->d_occ;
+  J.theta = d_theta;
+  J.cs = b.cs;
+  J.psi = b.psi;
+  J.lam = b.lam;
+  J.ck = p.ckpt ? b.ck : nullptr;
+  J.ckpt = p.ckpt ? 1 : 0;
+  J.epart = b.epart;
+  J.gpart = b.gpart;
+  J.E = b.E;
+  J.G = b.G;
+  J.cnt = b.gctl + 8;
+  J.scale = p.scale;
+  J.cstride = uint64_t(b.cap) << p.n;
+  J.n = p.n;
+  J.K = p.K;
+  J.B = B;
+  J.L = (int)p.seq.size();
+  J.nfwd = p.nfwd;
+  J.nexp = p.nexp;
+  J.nrev = p.nrev;
+  J.estride = p.nexp << (p.n - p.ke);
+  J.blob_stride = a.blob_stride;
+  J.stages = P + 2;
+  J.hf = p.hf;
+  J.amask = p.amask;
+  J.bmask = p.bmask;
+  size_t need = 64;
+  int al = 1;
+  for (int i = 0; i < P; ++i) {
+    const DevPass& hp = c->tab.passes[i];
+    const int v = hp.kind == kFwd ? kVarPlain : pass_variant(a, i, true, !p.ckpt);
+    const bool overlapped = (hp.kind == kRev && v == kVarRev2) || (hp.kind == kExp && v == kVarExp2);
+    if (overlapped && hp.k != 12 && hp.k != 13)
+      return fail(UCC_EINVAL, "the evaluation graph runs overlapped passes at 12- or 13-qubit tiles only");
+    if (overlapped) al = std::max(al, 1 << (p.n - hp.k));
+    J.var[i >> 4] |= uint32_t(v) << (2 * (i & 15));
+    need = std::max(need, pass_lds(hp, v, true) + graph_stage_extra(hp, v));
+  }
+  if (need + 256 > (size_t)kLdsBytes) return fail(UCC_EINVAL, "a pass of this plan needs more LDS than the evaluation graph has");
+  *job = J;
+  *lds = need;
+  *align = al;
+  return UCC_OK;
+}
+
+ucc_status enqueue_graph(const ucc_ctx* const* ctx, const GraphJob* jobs, int n, size_t lds, int align,
+                         hipStream_t st, Profiler* prof) {
+  double bytes = 0.0;
+  int wait_us = 0;
+  for (int j = 0; j < n; ++j) {
+    bytes += eval_bytes(ctx[j]->plan, jobs[j].B);
+    wait_us = std::max(wait_us, ctx[j]->opt.graph_wait_us);
+  }
+  const double us = wait_us > 0 ? double(wait_us) : 2e6;
+  const uint64_t ticks = (uint64_t)(us * wall_ticks_per_us());
+  int grid = 0;
+  hipError_t e = hipSuccess;
+  Profiler::Rec r{UCC_KERNEL_GRAPH, nullptr, nullptr, bytes};
+  if (prof) {
+    r.a = prof->get();
+    r.b = prof->get();
+    if (!r.a || !r.b) return hip_fail(hipErrorOutOfMemory, "profile events");
+    e = hipEventRecord(r.a, st);
+  }
+  if (e == hipSuccess) e = launch_graph(jobs, n, lds, align, ticks, st, &grid);
+  if (e == hipErrorInvalidValue && grid == 0)
+    return fail(UCC_EINVAL, "too few workgroups of the evaluation graph fit on the device at once");
+  if (e == hipSuccess && prof) e = hipEventRecord(r.b, st);
+  if (prof) prof->recs.push_back(r);
+  if (e != hipSuccess) return hip_fail(e, "launch k_graph");
+  for (int j = 0; j < n; ++j) {
+    ctx[j]->graph_grid = grid;
+    ctx[j]->graph_lds = (int)lds;
+  }
+  return UCC_OK;
+}
+
+ucc_status graph_check(Buffers& b) {
+  if (!b.gctl) return UCC_OK;
+  uint32_t w = 0;
+  hipError_t e = hipMemcpy(&w, b.gctl, 4, hipMemcpyDeviceToHost);
+  if (e == hipSuccess && w) {
+    const uint32_t zero = 0;
+    e = hipMemcpy(b.gctl, &zero, 4, hipMemcpyHostToDevice);
+  }
+  if (e != hipSuccess) return hip_fail(e, "graph status");
+  if (w)
+    return fail(UCC_EDEVICE, "an evaluation-graph launch gave up waiting (graph_wait_us); its "
+                             "energies and gradients are NaN");
+  return UCC_OK;
+}
+
 // The launch sequence of one call: cos/sin, forward passes (the first synthesizes |HF>),
-// expectation or apply-H passes, reverse passes (gradient), fixed-order reduction.
+// expectation or apply-H passes, reverse passes (gradient), fixed-order reduction.  In
+// launch_mode 3 an energy + gradient call is one evaluation-graph launch instead.
 ucc_status enqueue_eval(const ucc_ctx* c, Buffers& b, const double* d_theta, int B, bool grad,
                         hipStream_t st, Profiler* prof, const uint32_t* blob_bank, int cu_share) {
   const Plan& p = c->plan;
@@ -195,6 +331,14 @@ ucc_status enqueue_eval(const ucc_ctx* c, Buffers& b, const double* d_theta, int
     prof->recs.push_back(r);
     return e;
   };
+  if (p.launch_mode == 3 && grad) {
+    GraphJob job;
+    size_t lds = 0;
+    int align = 1;
+    ucc_status s = graph_job(c, b, d_theta, B, blob_bank, &job, &lds, &align);
+    if (s != UCC_OK) return s;
+    return enqueue_graph(&c, &job, 1, lds, align, st, prof);
+  }
   if (p.launch_mode == 2) {  // the whole evaluation in one launch: theta in, state, E and G out
     const double bytes = 8.0 * B * p.K + S + 8.0 * B * (1 + (grad ? p.K : 0));
     hipError_t e = timed(UCC_KERNEL_WHOLE, bytes,
@@ -305,6 +449,7 @@ ucc_status resolve_launch_mode(ucc_ctx* c) {
     return fail(UCC_EINVAL, "launch_mode 2 needs a state that is one tile whose tables fit in LDS "
                             "(n_qubits <= 12)");
   if (c->opt.launch_mode == 0) p.launch_mode = fits ? 2 : 1;
+  if (c->opt.launch_mode == 3) p.launch_mode = 3;
   return UCC_OK;
 }
 
@@ -395,7 +540,16 @@ ucc_status ucc_build(int32_t n_qubits, int32_t n_elec, const double* h1, const d
   for (int t : {o.block_threads, o.block_threads_fwd, o.block_threads_exp, o.block_threads_rev})
     if (t && t != 256 && t != 512 && t != 1024)
       return fail(UCC_EINVAL, "block_threads (any kind) must be 0, 256, 512 or 1024");
-  if (o.launch_mode < 0 || o.launch_mode > 2) return fail(UCC_EINVAL, "launch_mode must be 0..2");
+  if (o.launch_mode < 0 || o.launch_mode > 3) return fail(UCC_EINVAL, "launch_mode must be 0..3");
+  if (o.launch_mode == 3) {
+    if (o.taper) return fail(UCC_EINVAL, "launch_mode 3 does not take taper");
+    if (o.autotune) return fail(UCC_EINVAL, "launch_mode 3 does not take autotune (its workgroups are 512 threads)");
+    for (int t : {o.block_threads, o.block_threads_fwd, o.block_threads_exp, o.block_threads_rev})
+      if (t && t != 512) return fail(UCC_EINVAL, "launch_mode 3 runs 512-thread workgroups");
+    for (int k : {o.tile_qubits, o.tile_qubits_exp, o.tile_qubits_rev})
+      if (k > 13) return fail(UCC_EINVAL, "launch_mode 3 takes tiles of at most 13 qubits");
+  }
+  if (o.graph_wait_us < 0) return fail(UCC_EINVAL, "graph_wait_us must be >= 0");
   if (o.max_batch < 0) return fail(UCC_EINVAL, "max_batch must be >= 0");
   if (o.autotune && o.host_only) return fail(UCC_EINVAL, "autotune needs a device context");
   if (o.store_states < 0 || o.store_states > 2) return fail(UCC_EINVAL, "store_states must be 0..2");
@@ -493,9 +647,92 @@ static ucc_status eval_call(ucc_ctx* c, const double* theta, int32_t B, double* 
   if (host_e || host_g) {
     e = hipStreamSynchronize(st);
     if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+    if (want_grad && c->plan.launch_mode == 3) {
+      s = graph_check(c->buf);
+      if (s != UCC_OK) return s;
+    }
   }
   c->last_B = B;
   return UCC_OK;
+}
+
+ucc_status ucc_energy_grad_jobs(ucc_ctx* const* ctx, const int32_t* B, const double* const* theta,
+                                double* const* energy, double* const* grad, int32_t njobs,
+                                void* stream) {
+  g_last_error.clear();
+  if (!ctx || !B || !theta || !energy || !grad) return fail(UCC_EINVAL, "NULL argument");
+  if (njobs < 1 || njobs > kMaxGraphJobs) return fail(UCC_EINVAL, "njobs must be in [1, 4]");
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+  for (int j = 0; j < njobs; ++j) {
+    ucc_ctx* c = ctx[j];
+    if (!c || !theta[j] || !energy[j] || !grad[j]) return fail(UCC_EINVAL, "NULL job argument");
+    if (c->host_only) return fail(UCC_EINVAL, "context was built host_only");
+    if (c->plan.launch_mode != 3) return fail(UCC_EINVAL, "every job's context needs launch_mode 3");
+    if (c->device != dev) return fail(UCC_EINVAL, "every job's context must be on the current device");
+    if (B[j] < 1 || B[j] > 65535) return fail(UCC_EINVAL, "B must be in [1, 65535]");
+    if (c->busy) return fail(UCC_EBUSY, "context is in use by a server job");
+    for (int i = 0; i < j; ++i)
+      if (ctx[i] == c) return fail(UCC_EINVAL, "a context appears twice among the jobs");
+  }
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  GraphJob jobs[kMaxGraphJobs];
+  size_t lds = 0;
+  int align = 1;
+  for (int j = 0; j < njobs; ++j) {
+    ucc_ctx* c = ctx[j];
+    ucc_status s = ensure_buffers(c, c->buf, B[j], true);
+    if (s != UCC_OK) return s;
+    const double* d_theta = theta[j];
+    if (!is_device_ptr(theta[j])) {
+      e = hipMemcpyAsync(c->buf.theta, theta[j], size_t(B[j]) * c->plan.K * 8, hipMemcpyHostToDevice, st);
+      if (e != hipSuccess) return hip_fail(e, "copy theta");
+      d_theta = c->buf.theta;
+    }
+    size_t l = 0;
+    int a = 1;
+    s = graph_job(c, c->buf, d_theta, B[j], nullptr, &jobs[j], &l, &a);
+    if (s != UCC_OK) return s;
+    lds = std::max(lds, l);
+    align = std::max(align, a);
+  }
+  ucc_status s = enqueue_graph(ctx, jobs, njobs, lds, align, st, ctx[0]->prof.get());
+  if (s != UCC_OK) return s;
+  bool host = false;
+  for (int j = 0; j < njobs; ++j) {
+    ucc_ctx* c = ctx[j];
+    const bool he = !is_device_ptr(energy[j]), hg = !is_device_ptr(grad[j]);
+    host |= he || hg;
+    e = hipMemcpyAsync(energy[j], c->buf.E, size_t(B[j]) * 8,
+                       he ? hipMemcpyDeviceToHost : hipMemcpyDeviceToDevice, st);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(grad[j], c->buf.G, size_t(B[j]) * c->plan.K * 8,
+                         hg ? hipMemcpyDeviceToHost : hipMemcpyDeviceToDevice, st);
+    if (e != hipSuccess) return hip_fail(e, "copy results");
+    c->last_B = B[j];
+  }
+  if (host) {
+    e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+    ucc_status worst = UCC_OK;
+    for (int j = 0; j < njobs; ++j) {
+      const ucc_status sj = graph_check(ctx[j]->buf);
+      if (sj != UCC_OK) worst = sj;
+    }
+    return worst;
+  }
+  return UCC_OK;
+}
+
+ucc_status ucc_graph_status(ucc_ctx* c, void* stream) {
+  g_last_error.clear();
+  if (!c) return fail(UCC_EINVAL, "ctx is NULL");
+  if (c->host_only) return fail(UCC_EINVAL, "context was built host_only");
+  hipError_t e = hipSetDevice(c->device);
+  if (e == hipSuccess) e = hipStreamSynchronize(reinterpret_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+  return graph_check(c->buf);
 }
 
 ucc_status ucc_energy(ucc_ctx* c, const double* theta, int32_t B, double* energy, void* stream) {
@@ -557,6 +794,8 @@ ucc_status ucc_get_plan_info(const ucc_ctx* c, ucc_plan_info* info) {
   info->n_qubits = p.nq;
   info->state_qubits = p.n;
   info->taper = p.taper;
+  info->graph_grid = c->graph_grid;
+  info->graph_lds = c->graph_lds;
   info->fuse_depth = p.fuse;
   info->n_elec = p.ne;
   info->n_exc = p.K;

@@ -28,6 +28,9 @@ struct Buffers {
   double* gpart = nullptr; // [cap][L][reverse tiles] (L factors of the Trotter product)
   double* E = nullptr;     // [cap]
   double* G = nullptr;     // [cap][K]
+  // evaluation graph (launch_mode 3): word 0 status, word 4 abort, words 8 .. the per-(stage,
+  // entry) counters [stages - 1][cap] (kernels.h, launch_graph)
+  uint32_t* gctl = nullptr;
 };
 
 // Per-launch HIP-event timing (ucc_profile).
@@ -106,6 +109,8 @@ struct ucc_ctx {
   ucc::Buffers buf;
   ucc::GenSet gen;
   int last_B = 0;
+  mutable std::atomic<int> graph_grid{0};  // last evaluation-graph launch: workgroups, LDS
+  mutable std::atomic<int> graph_lds{0};
   std::atomic<int> busy{0};  // held by a server job
   std::unique_ptr<ucc::Profiler> prof;
 };
@@ -126,6 +131,19 @@ LaunchArgs make_args(const ucc_ctx* c, const Buffers& b, int B, hipStream_t st);
 ucc_status enqueue_eval(const ucc_ctx* c, Buffers& b, const double* d_theta, int B, bool grad,
                         hipStream_t st, Profiler* prof, const uint32_t* blob_bank = nullptr,
                         int cu_share = 0);
+// Evaluation graph (launch_mode 3): the launch argument of one job (an energy + gradient call
+// of c on buffers b), the dynamic LDS its stages need and the grid multiple its overlapped
+// passes need.  UCC_EINVAL for plans the graph cannot run.
+ucc_status graph_job(const ucc_ctx* c, Buffers& b, const double* d_theta, int B,
+                     const uint32_t* blob_bank, GraphJob* job, size_t* lds, int* align);
+// One graph launch of jobs[0 .. n) on st (profiled into prof if given); records the grid and
+// LDS in each context.
+ucc_status enqueue_graph(const ucc_ctx* const* ctx, const GraphJob* jobs, int n, size_t lds, int align,
+                         hipStream_t st, Profiler* prof);
+// Words of a graph control block for `cap` entries of c's plan (0: not in launch_mode 3).
+size_t graph_ctl_words(const ucc_ctx* c, int cap);
+// Reads and clears the status word of b (after the work that may have set it is complete).
+ucc_status graph_check(Buffers& b);
 // True if b's tables equal a's in everything but the expectation values, so entries built
 // from b can run in a batch launched with a's tables and a per-entry blob bank.
 bool batch_compatible(const ucc_ctx* a, const ucc_ctx* b);

@@ -67,6 +67,75 @@ hipError_t launch_gen(const LaunchArgs& a, int pidx, int first, const GenPassArg
 // Reverse pass pidx on (psi, a.lam); write_psi = 0: psi is a stored state, read only.
 hipError_t launch_rev(const LaunchArgs& a, int pidx, double2* psi, bool write_psi);
 hipError_t launch_reduce(const LaunchArgs& a, int ne, bool grad, int nt);
+
+// Pass bodies (pass_bodies.h): the per-pass launchers choose among them by tile size, LDS and
+// grid; the evaluation graph runs, for every pass, the body that choice gives.
+enum PassVariant : int {
+  kVarPlain = 0,   // k_fwd, k_exp, k_rev
+  kVarExpv2 = 1,   // k_expv, groups of 2 entries
+  kVarExpv4 = 2,   // k_expv, groups of 4 entries
+  kVarExp2 = 3,    // k_exp2 (overlapped light expectation pass)
+  kVarRev2 = 1,    // k_rev2 (overlapped reverse pass)
+};
+// The body a per-pass launch of pass pidx with these arguments runs (apply: gradient call;
+// wp: the reverse pass writes psi back, i.e. recomputes instead of reading stored states).
+int pass_variant(const LaunchArgs& a, int pidx, bool apply, bool wp);
+// Dynamic LDS bytes that body uses for pass hp (per-pass launch).
+size_t pass_lds(const DevPass& hp, int variant, bool apply);
+
+// ---- evaluation graph (graph.hip): every pass of one or more jobs in one launch
+//
+// Stages of a job: 0 = cos/sin, 1 .. P = its passes in order (forward, apply-H, reverse),
+// P + 1 = the fixed-order sums.  Items of a stage are those of the pass's per-pass launch;
+// workgroup w takes items w, w + grid, ... of every stage in stage order (jobs interleaved
+// stage by stage), and an item waits until every item of the previous stage that touched its
+// batch entries is complete (per-entry counters), instead of for the whole previous pass.
+constexpr int kMaxGraphJobs = 4;
+constexpr int kMaxGraphPasses = 512;
+constexpr int kGraphThreads = 512;
+
+struct GraphJob {
+  const DevPass* passes = nullptr;
+  const DevExc* exc = nullptr;
+  const int2* cls = nullptr;
+  const uint32_t* pairs = nullptr;
+  const uint4* blobs = nullptr;
+  const int32_t* occ = nullptr;
+  const double* theta = nullptr;  // [B][K]
+  double2* cs = nullptr;
+  double2* psi = nullptr;
+  double2* lam = nullptr;
+  double2* ck = nullptr;          // stored forward states 0 .. nfwd - 2 (the last is psi)
+  double* epart = nullptr;
+  double* gpart = nullptr;
+  double* E = nullptr;
+  double* G = nullptr;
+  uint32_t* cnt = nullptr;        // [stages - 1][B] completed items per entry, zero at launch
+  double scale = 1.0;
+  uint64_t cstride = 0;           // amplitudes between stored states
+  int n = 0, K = 0, B = 0, L = 0;
+  int nfwd = 0, nexp = 0, nrev = 0;
+  int estride = 0, blob_stride = 0;
+  int ckpt = 0;                   // 1: the reverse sweep reads stored states (psi not written)
+  int stages = 0;
+  uint32_t hf = 0, amask = 0, bmask = 0;
+  uint32_t var[kMaxGraphPasses / 16] = {};  // 2 bits per pass: its PassVariant
+};
+
+// Extra dynamic LDS the graph's copy of a body takes beside pass_lds (the statics of the
+// per-pass kernel).
+size_t graph_stage_extra(const DevPass& hp, int variant);
+// One launch of the stages of jobs[0 .. njobs), grid = the workgroups resident at once at
+// `lds` bytes of dynamic LDS, rounded down to a multiple of `align` (hipErrorInvalidValue
+// when fewer than `align` fit).  Each job's cnt points 8 words into its control block: word 0
+// is the job's status (set to 1 by a launch that gave up, never cleared here), word 4 the
+// abort word (job 0's is the launch's), words 8 .. the counters; words 4 .. are zeroed before
+// the launch.  A wait that outlasts limit_ticks (wall clock) makes the launch give up; the
+// jobs' E and G are then NaN.
+hipError_t launch_graph(const GraphJob* jobs, int njobs, size_t lds, int align, uint64_t limit_ticks,
+                        hipStream_t st, int* grid_out);
+// Wall-clock ticks per microsecond of the current device.
+double wall_ticks_per_us();
 // theta[b][k] -= lr[b] * G[b][k] (product rounded first) for B rows of K.
 hipError_t launch_sd_update(double* theta, const double* G, const double* lr, int B, int K,
                             hipStream_t st);

@@ -51,6 +51,8 @@ extern "C" ucc_status ucc_energy_grad_noalloc(ucc_ctx* c, const double* theta, i
   g_last_error.clear();
   if (!c) return fail(UCC_EINVAL, "ctx is NULL");
   if (c->host_only) return fail(UCC_EINVAL, "context was built host_only");
+  if (c->plan.launch_mode == 3)
+    return fail(UCC_EINVAL, "the allocation-free call runs the per-pass launches; the context is in launch_mode 3");
   if (B < 1 || B > 65535) return fail(UCC_EINVAL, "B must be in [1, 65535]");
   if (!theta || !energy || !grad) return fail(UCC_EINVAL, "NULL output or input");
   if (c->busy) return fail(UCC_EBUSY, "context is in use by a server job");

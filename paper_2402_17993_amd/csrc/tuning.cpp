@@ -67,6 +67,12 @@ Tuning choose_tuning(int n, int K, int batch, const ucc_options& o) {
   t.te = pick(o.block_threads_exp, o.block_threads, small ? 256 : 1024);
   t.tr = pick(o.block_threads_rev, o.block_threads, small ? 256 : 512);
   t.launch_mode = o.launch_mode ? o.launch_mode : 1;  // 0 is resolved once the tables exist
+  if (o.launch_mode == 3) {  // the evaluation graph: one workgroup size, tiles of at most 13
+    t.tf = t.te = t.tr = 512;
+    if (!o.tile_qubits) t.kf = std::min(t.kf, 13);
+    if (!o.tile_qubits_exp) t.ke = std::min(t.ke, 13);
+    if (!o.tile_qubits_rev) t.kr = std::min(t.kr, 13);
+  }
   return t;
 }
 

@@ -23,6 +23,7 @@ STATUS_CODES = {v: k for k, v in STATUS.items()}
 
 EXPORTED = [
     "ucc_default_options", "ucc_build", "ucc_energy", "ucc_energy_grad", "ucc_energy_grad_noalloc",
+    "ucc_energy_grad_jobs", "ucc_graph_status",
     "ucc_stream_probe",
     "ucc_energy_trotter_free", "ucc_energy_grad_trotter_free", "ucc_get_generator_passes",
     "ucc_get_partials_passes",
@@ -34,7 +35,7 @@ EXPORTED = [
     "ucc_server_create", "ucc_submit", "ucc_poll", "ucc_wait", "ucc_cancel", "ucc_server_destroy",
 ]
 
-KERNEL_KINDS = ["trig", "fwd", "exp", "applyh", "rev", "reduce", "whole", "gen", "cheb"]
+KERNEL_KINDS = ["trig", "fwd", "exp", "applyh", "rev", "reduce", "whole", "gen", "cheb", "graph"]
 N_KERNEL_KINDS = 10
 
 
@@ -45,7 +46,7 @@ class Options(ctypes.Structure):
                 ("block_threads_fwd", _i32), ("block_threads_exp", _i32),
                 ("block_threads_rev", _i32), ("tile_qubits_exp", _i32), ("autotune", _i32),
                 ("store_states", _i32), ("trotter_order", _i32), ("taper", _i32),
-                ("fuse_depth", _i32)]
+                ("fuse_depth", _i32), ("graph_wait_us", _i32)]
 
 
 class PlanInfo(ctypes.Structure):
@@ -58,7 +59,8 @@ class PlanInfo(ctypes.Structure):
                 ("block_threads_rev", _i32), ("launch_mode", _i32), ("autotuned", _i32),
                 ("store_states", _i32), ("trotter_steps", _i32), ("trotter_order", _i32),
                 ("perm", _i32 * 32), ("job_footprint", ctypes.c_int64),
-                ("state_qubits", _i32), ("taper", _i32), ("fuse_depth", _i32)]
+                ("state_qubits", _i32), ("taper", _i32), ("fuse_depth", _i32),
+                ("graph_grid", _i32), ("graph_lds", _i32)]
 
 
 class KernelStat(ctypes.Structure):
@@ -89,6 +91,8 @@ def lib():
         "ucc_energy": (_i32, [_vp, _vp, _i32, _vp, _vp]),
         "ucc_energy_grad": (_i32, [_vp, _vp, _i32, _vp, _vp, _vp]),
         "ucc_energy_grad_noalloc": (_i32, [_vp, _vp, _i32, _vp, _vp, _vp]),
+        "ucc_energy_grad_jobs": (_i32, [_P(_vp), _P(_i32), _P(_vp), _P(_vp), _P(_vp), _i32, _vp]),
+        "ucc_graph_status": (_i32, [_vp, _vp]),
         "ucc_stream_probe": (_i32, [_vp, _vp, ctypes.c_size_t, _i32, _vp]),
         "ucc_energy_trotter_free": (_i32, [_vp, _vp, _i32, _vp, _vp, _vp]),
         "ucc_energy_grad_trotter_free": (_i32, [_vp, _vp, _i32, _vp, _vp, _vp, _vp]),
@@ -131,6 +135,58 @@ def _ptr(a):
     return ctypes.c_void_p(a.ctypes.data) if a is not None else None
 
 
+def _torch_ready():
+    try:
+        import torch
+    except ImportError:
+        return False
+    return torch.cuda.is_available() and torch.cuda.is_initialized()
+
+
+def energy_grad_jobs(contexts, thetas, stream=None):
+    """ucc_energy_grad_jobs: (E, dE/dtheta) of each context at its theta ([K] or [B, K]), all
+    jobs in one evaluation-graph launch (contexts built with launch_mode=3).  numpy in ->
+    numpy out; torch CUDA in -> torch CUDA out (every theta of one kind)."""
+    L = lib()
+    n = len(contexts)
+    if n != len(thetas) or not 1 <= n <= 4:
+        raise ValueError("one theta per context, 1 to 4 jobs")
+    cuda = [_is_torch_cuda(t) for t in thetas]
+    if any(cuda) and not all(cuda):
+        raise ValueError("thetas must be all numpy or all torch CUDA tensors")
+    keep, th_p, e_p, g_p, Bs, outs = [], [], [], [], [], []
+    if all(cuda):
+        import torch
+        for c, t in zip(contexts, thetas):
+            th = t.detach().to(torch.float64).contiguous()
+            B = th.numel() // c.n_exc
+            if th.numel() != B * c.n_exc or B < 1:
+                raise ValueError("theta must hold B * n_exc amplitudes")
+            E = torch.empty(B, dtype=torch.float64, device=th.device)
+            G = torch.empty(B, c.n_exc, dtype=torch.float64, device=th.device)
+            keep += [th]
+            th_p.append(th.data_ptr()), e_p.append(E.data_ptr()), g_p.append(G.data_ptr())
+            Bs.append(B), outs.append((E, G))
+        st = stream if stream is not None else torch.cuda.current_stream(thetas[0].device).cuda_stream
+    else:
+        for c, t in zip(contexts, thetas):
+            th = np.ascontiguousarray(t, dtype=np.float64)
+            B = th.size // c.n_exc
+            if th.size != B * c.n_exc or B < 1:
+                raise ValueError("theta must hold B * n_exc amplitudes")
+            E = np.empty(B)
+            G = np.empty((B, c.n_exc))
+            keep += [th, E, G]
+            th_p.append(th.ctypes.data), e_p.append(E.ctypes.data), g_p.append(G.ctypes.data)
+            Bs.append(B), outs.append((E, G))
+        st = stream
+    arr = lambda xs: (_vp * n)(*[_vp(x) for x in xs])
+    check(L.ucc_energy_grad_jobs((_vp * n)(*[c._h for c in contexts]), (_i32 * n)(*Bs), arr(th_p),
+                                 arr(e_p), arr(g_p), n, _vp(st) if st is not None else None),
+          "ucc_energy_grad_jobs")
+    return outs
+
+
 def _is_torch_cuda(x):
     try:
         import torch
@@ -147,7 +203,7 @@ class Context:
                  contiguous_qubits=0, block_threads=0, block_threads_fwd=0,
                  block_threads_exp=0, block_threads_rev=0, max_batch=1, launch_mode=0,
                  autotune=False, store_states=0, trotter_steps=1, trotter_order=1,
-                 taper=0, fuse_depth=0, host_only=False, device=-1):
+                 taper=0, fuse_depth=0, graph_wait_us=0, host_only=False, device=-1):
         L = lib()
         self._h = None
         self.n_qubits, self.n_elec = int(n_qubits), int(n_elec)
@@ -167,6 +223,7 @@ class Context:
         o.trotter_steps, o.trotter_order = trotter_steps, trotter_order
         o.taper = int(taper)
         o.fuse_depth = int(fuse_depth)
+        o.graph_wait_us = int(graph_wait_us)
         o.host_only, o.device = int(bool(host_only)), device
         h = _vp()
         check(L.ucc_build(self.n_qubits, self.n_elec, _ptr(h1), _ptr(h2), _ptr(exc),
@@ -212,6 +269,15 @@ class Context:
     def energy_grad(self, theta, stream=None):
         """(E [B], dE/dtheta [B, K])."""
         return self._run(theta, True, stream)
+
+    def graph_status(self, stream=None):
+        """ucc_graph_status: raises UCCError (UCC_EDEVICE) if an evaluation-graph launch of this
+        context gave up waiting since the last check; synchronizes the stream first."""
+        if stream is None and _torch_ready():
+            import torch
+            stream = torch.cuda.current_stream().cuda_stream
+        check(lib().ucc_graph_status(self._h, _vp(stream) if stream is not None else None),
+              "ucc_graph_status")
 
     def energy_grad_noalloc(self, theta, energy, grad, stream=None):
         """ucc_energy_grad_noalloc: theta [B, K] in, energy [B] and grad [B, K] out, all
