@@ -320,6 +320,86 @@ def tapered(ucc, torch, h1, h2, exc, thetas, steps=20):
             "parity": {"max_abs_dE": de, "max_abs_dgrad": dg, "entries_checked": len(gold["entries"])}}
 
 
+def graph_launch(ucc, torch, h1, h2, exc, thetas, steps=20):
+    """The benchmark workload as ONE evaluation-graph launch per step (launch_mode 3: every pass
+    in one persistent kernel, items gated by per-entry counters) beside its twin, the per-pass
+    launches of the same tiles (13 qubits) and workgroups (512 threads): evals/s of both, the
+    twin's per-pass kernel times summed (HIP events) and the graph launch's own time, with the
+    two results compared bit for bit and all 64 stored oracle values checked.  Then a job mix
+    in one launch -- a 12-qubit batch of 16, the 18-qubit batch of 64 and one 24-qubit state --
+    against the same three jobs launched one after another (each its own graph launch)."""
+    from paper_2402_17993_amd.inputs import make_integrals, make_thetas, uccsd_excitations
+
+    gold = json.load(open(os.path.join(ROOT, "tests", "golden", "dimer_18q.json")))
+    td = torch.tensor(thetas, device="cuda:0", dtype=torch.float64)
+    g = ucc.Context(N, NE, h1, h2, exc, max_batch=BATCH, device=0, launch_mode=3)
+    tw = ucc.Context(N, NE, h1, h2, exc, max_batch=BATCH, device=0, launch_mode=1, block_threads=512,
+                     tile_qubits=13, tile_qubits_exp=13, tile_qubits_rev=13)
+    Eg, Gg = g.energy_grad(td)
+    Et, Gt = tw.energy_grad(td)
+    torch.cuda.synchronize()
+    same = bool(torch.equal(Eg, Et) and torch.equal(Gg, Gt))
+    En, Gn = Eg.cpu().numpy(), Gg.cpu().numpy()
+    de = max(abs(En[int(b)] - v["energy"]) for b, v in gold["entries"].items())
+    dg = max(float(np.max(np.abs(Gn[int(b)] - np.array(v["grad"])))) for b, v in gold["entries"].items())
+    if not same or de > 1e-10 or dg > 1e-9:
+        raise RuntimeError(f"graph parity failed: bitwise {same}, |dE| {de:.2e}, |dg| {dg:.2e}")
+
+    def wall_ms(fn):
+        for _ in range(3):
+            fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            fn()
+        torch.cuda.synchronize()
+        return 1e3 * (time.perf_counter() - t0) / steps
+
+    def kernel_ms(ctx):
+        ctx.profile(True)
+        ctx.profile_read(reset=True)
+        for _ in range(steps):
+            ctx.energy_grad(td)
+        st = ctx.profile_read(reset=True)
+        ctx.profile(False)
+        return {k: v["ms"] / steps for k, v in st.items() if v["launches"]}
+
+    ms_g = wall_ms(lambda: g.energy_grad(td))
+    ms_t = wall_ms(lambda: tw.energy_grad(td))
+    kg, kt = kernel_ms(g), kernel_ms(tw)
+    info = g.plan_info()
+    out = {"graph_evals_per_s": BATCH / (ms_g * 1e-3), "graph_ms_per_step": ms_g,
+           "per_pass_twin_evals_per_s": BATCH / (ms_t * 1e-3), "per_pass_twin_ms_per_step": ms_t,
+           "per_pass_twin_kernel_ms_sum": sum(kt.values()), "per_pass_twin_kernel_ms": kt,
+           "graph_kernel_ms": kg, "bitwise_equal": same, "max_abs_dE": de, "max_abs_dg": dg,
+           "graph_grid": info["graph_grid"], "graph_lds_bytes": info["graph_lds"],
+           "passes_fwd_exp_rev": [info["n_fwd_passes"], info["n_exp_passes"], info["n_rev_passes"]]}
+    # the job mix
+    jobs = []
+    for n, ne, seed, B in ((12, 8, 31, 16), (24, 14, 0, 1)):
+        a1, a2 = make_integrals(n // 2, seed)
+        ex = uccsd_excitations(n, ne)
+        c = ucc.Context(n, ne, a1, a2, ex, max_batch=B, device=0, launch_mode=3)
+        t = torch.tensor(make_thetas(len(ex), seed + 7, 0.05, batch=B), device="cuda:0")
+        jobs.append((c, t))
+    ctxs = [jobs[0][0], g, jobs[1][0]]
+    ths = [jobs[0][1], td, jobs[1][1]]
+    ms_mix = wall_ms(lambda: ucc.energy_grad_jobs(ctxs, ths))
+    ms_seq = wall_ms(lambda: [c.energy_grad(t) for c, t in zip(ctxs, ths)])
+    mix = ucc.energy_grad_jobs(ctxs, ths)
+    alone = [c.energy_grad(t) for c, t in zip(ctxs, ths)]
+    torch.cuda.synchronize()
+    out["mix_12q_b16_18q_b64_24q_b1"] = {
+        "one_launch_ms": ms_mix, "three_launches_ms": ms_seq,
+        "alone_equals_mix_bitwise": all(bool(torch.equal(a[0], m[0]) and torch.equal(a[1], m[1]))
+                                        for a, m in zip(alone, mix))}
+    for c, _ in jobs:
+        c.close()
+    g.close()
+    tw.close()
+    return out
+
+
 def trotter_variants(ucc, torch, h1, h2, exc, thetas, steps=5):
     """The benchmark workload (18 qubits, batch 64) under the other Trotter products of the
     paper: M slices of the first-order product (Eq. 5), the symmetric second-order product
@@ -699,7 +779,7 @@ def serving_trimers(ucc, jobs=4, iters=5, lr=0.1):
             "per_iteration_ms_p50": 1e3 * float(np.percentile(per_it, 50))}
 
 
-LEGS = ("all", "latency", "large_26q", "paper_shaped", "variants", "tapered", "trotter_free",
+LEGS = ("all", "latency", "large_26q", "paper_shaped", "variants", "tapered", "graph", "trotter_free",
         "size_consistency", "serving", "serving_sweep", "serving_trimers", "stream")
 
 
@@ -751,6 +831,7 @@ def main():
             "paper_shaped": lambda: paper_shaped(ucc, torch),
             "variants": lambda: trotter_variants(ucc, torch, h1, h2, exc, thetas),
             "tapered": lambda: tapered(ucc, torch, h1, h2, exc, thetas),
+            "graph": lambda: graph_launch(ucc, torch, h1, h2, exc, thetas),
             "trotter_free": lambda: trotter_free(ucc, torch, h1, h2, exc, thetas),
             "size_consistency": lambda: size_consistency(ucc),
             "serving": lambda: serving_mix(ucc, args.serve_arrivals),
@@ -761,7 +842,8 @@ def main():
         print(json.dumps({"leg": args.leg, "result": legs[args.leg]()}))
         return
     ctx = ucc.Context(N, NE, h1, h2, exc, max_batch=BATCH, device=0, launch_mode=args.launch_mode,
-                      autotune=not args.no_autotune, store_states=args.store_states)
+                      autotune=not args.no_autotune and args.launch_mode != 3,
+                      store_states=args.store_states)
     info = ctx.plan_info()
     td = torch.tensor(thetas, device=dev, dtype=torch.float64)
 
@@ -870,6 +952,7 @@ def main():
         out["large_26q"] = large_state(ucc, torch)
         out["paper_shaped_dimers"] = paper_shaped(ucc, torch)
         out["tapered_18q_b64"] = tapered(ucc, torch, h1, h2, exc, thetas)
+        out["graph_18q_b64"] = graph_launch(ucc, torch, h1, h2, exc, thetas)
         out["trotter_variants_18q_b64"] = trotter_variants(ucc, torch, h1, h2, exc, thetas)
         out["trotter_free_18q_b64"] = trotter_free(ucc, torch, h1, h2, exc, thetas)
         out["size_consistency_h8"] = size_consistency(ucc)
@@ -885,10 +968,13 @@ def main():
 
 
 def kernel_source_hash():
+    """Hash of the per-pass kernels' device code (their launchers and their bodies)."""
     import hashlib
 
-    p = os.path.join(ROOT, "paper_2402_17993_amd", "csrc", "kernels.hip")
-    return hashlib.sha256(open(p, "rb").read()).hexdigest()[:16]
+    h = hashlib.sha256()
+    for f in ("kernels.hip", "pass_bodies.h"):
+        h.update(open(os.path.join(ROOT, "paper_2402_17993_amd", "csrc", f), "rb").read())
+    return h.hexdigest()[:16]
 
 
 if __name__ == "__main__":
