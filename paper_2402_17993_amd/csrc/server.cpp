@@ -20,6 +20,13 @@
 // worker thread launches groups and polls the in-flight rounds; jobs join and leave a group
 // when it has no round in flight.
 //
+// Groups of contexts in launch_mode 3 (the evaluation graph) instead share ONE launch per
+// round: whenever none of them has a round in flight, every such group with members is staged
+// on one stream and all their evaluations run as jobs of one graph launch (up to four per
+// launch), each gated by its own counters, then each group's results are copied and its step
+// taken, as above.  Groups of different sizes (fragments and pairs of Eq. 1) thus advance in
+// the same launch.
+//
 // Results do not depend on the mix: every batch entry is computed by the same kernels in the
 // same order whatever else is in the batch, and the host update is plain IEEE arithmetic.
 #include <chrono>
@@ -118,10 +125,13 @@ struct Group {
   hipEvent_t done_ev[2] = {nullptr, nullptr};
   int queued = 0;  // rounds in flight
   int head = 0;    // result slot of the oldest of them
+  bool graph = false;  // launch_mode 3 contexts: rounds are jobs of the server's shared launch
 };
 
-void free_group(Group& g) {
+// (other: a further stream the group's rounds may run on, synchronized too)
+void free_group(Group& g, hipStream_t other = nullptr) {
   if (g.stream) (void)hipStreamSynchronize(g.stream);
+  if (other) (void)hipStreamSynchronize(other);
   free_buffers(g.buf);
   if (g.bank) (void)hipFree(g.bank);
   if (g.h_theta) (void)hipHostFree(g.h_theta);
@@ -195,26 +205,34 @@ ucc_status prepare_group(Group& g, int B, int slots, bool mixed) {
 // since the last round, so the rows' theta, step sizes (and value tables) are uploaded first;
 // otherwise the device theta is the previous round's stepped one.  The pass kernels fill at
 // most cu_share compute units (0 = all).
-ucc_status launch_round(Group& g, int slots, int cu_share, bool fresh) {
+bool group_mixed(const Group& g) {
+  for (const Job* j : g.jobs)
+    if (j->ctx != g.proto) return true;
+  return false;
+}
+
+// Before a round of group g on stream st.  fresh: the membership may have changed since the
+// last round, so the rows' theta, step sizes (and value tables) are uploaded first; otherwise
+// the device theta is the previous round's stepped one.
+ucc_status stage_round(Group& g, int slots, bool fresh, hipStream_t st) {
   const int B = (int)g.jobs.size();
   const int K = g.proto->plan.K;
-  bool mixed = false;
-  for (Job* j : g.jobs) mixed |= j->ctx != g.proto;
+  const bool mixed = group_mixed(g);
   hipError_t e = hipSuccess;
   if (fresh) {
     ucc_status s = prepare_group(g, B, slots, mixed);
     if (s != UCC_OK) return s;
     for (int r = 0; r < B; ++r) std::memcpy(g.h_theta + size_t(r) * K, g.jobs[r]->theta.data(), size_t(K) * 8);
-    e = hipMemcpyAsync(g.buf.theta, g.h_theta, size_t(B) * K * 8, hipMemcpyHostToDevice, g.stream);
+    e = hipMemcpyAsync(g.buf.theta, g.h_theta, size_t(B) * K * 8, hipMemcpyHostToDevice, st);
     for (int r = 0; r < B; ++r) g.h_lr[r] = g.jobs[r]->lr;
-    if (e == hipSuccess) e = hipMemcpyAsync(g.d_lr, g.h_lr, size_t(B) * 8, hipMemcpyHostToDevice, g.stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(g.d_lr, g.h_lr, size_t(B) * 8, hipMemcpyHostToDevice, st);
   }
   if (e == hipSuccess && fresh && mixed) {
     const size_t words = g.proto->tab.blob.size();
     for (int r = 0; r < B && e == hipSuccess; ++r) {
       const ucc_ctx* c = g.jobs[r]->ctx;
       if (g.bank_rows[r] == c) continue;
-      e = hipMemcpyAsync(g.bank + size_t(r) * words, c->d_blob, words * 4, hipMemcpyDeviceToDevice, g.stream);
+      e = hipMemcpyAsync(g.bank + size_t(r) * words, c->d_blob, words * 4, hipMemcpyDeviceToDevice, st);
       g.bank_rows[r] = c;
     }
   }
@@ -222,18 +240,58 @@ ucc_status launch_round(Group& g, int slots, int cu_share, bool fresh) {
     std::fill(g.bank_rows.begin(), g.bank_rows.end(), nullptr);
     return hip_fail(e, "server copies");
   }
-  ucc_status s = enqueue_eval(g.proto, g.buf, g.buf.theta, B, true, g.stream, nullptr,
-                              mixed ? g.bank : nullptr, cu_share);
-  if (s != UCC_OK) return s;
+  return UCC_OK;
+}
+
+// After group g's evaluation on stream st: E and grad out into the next result slot, the
+// slot's event, then the step theta <- theta - lr * grad on the device.
+ucc_status close_round(Group& g, hipStream_t st) {
+  const int B = (int)g.jobs.size();
+  const int K = g.proto->plan.K;
   const int slot = (g.head + g.queued) & 1;
-  e = hipMemcpyAsync(g.h_E[slot], g.buf.E, size_t(B) * 8, hipMemcpyDeviceToHost, g.stream);
-  if (e == hipSuccess)
-    e = hipMemcpyAsync(g.h_G[slot], g.buf.G, size_t(B) * K * 8, hipMemcpyDeviceToHost, g.stream);
-  if (e == hipSuccess) e = hipEventRecord(g.done_ev[slot], g.stream);
-  if (e == hipSuccess) e = launch_sd_update(g.buf.theta, g.buf.G, g.d_lr, B, K, g.stream);
+  hipError_t e = hipMemcpyAsync(g.h_E[slot], g.buf.E, size_t(B) * 8, hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess) e = hipMemcpyAsync(g.h_G[slot], g.buf.G, size_t(B) * K * 8, hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess) e = hipEventRecord(g.done_ev[slot], st);
+  if (e == hipSuccess) e = launch_sd_update(g.buf.theta, g.buf.G, g.d_lr, B, K, st);
   if (e != hipSuccess) return hip_fail(e, "server result copies");
   ++g.queued;
   return UCC_OK;
+}
+
+// Enqueue one round of group g on its stream (see stage_round); the pass kernels fill at most
+// cu_share compute units (0 = all).
+ucc_status launch_round(Group& g, int slots, int cu_share, bool fresh) {
+  ucc_status s = stage_round(g, slots, fresh, g.stream);
+  if (s != UCC_OK) return s;
+  s = enqueue_eval(g.proto, g.buf, g.buf.theta, (int)g.jobs.size(), true, g.stream, nullptr,
+                   group_mixed(g) ? g.bank : nullptr, cu_share);
+  if (s != UCC_OK) return s;
+  return close_round(g, g.stream);
+}
+
+// One round of the groups gs[0 .. n) (launch_mode 3, n <= kMaxGraphJobs) as jobs of one
+// evaluation-graph launch on stream st.
+ucc_status launch_graph_round(Group* const* gs, int n, int slots, hipStream_t st) {
+  GraphJob jobs[kMaxGraphJobs];
+  const ucc_ctx* ctxs[kMaxGraphJobs];
+  size_t lds = 0;
+  int align = 1;
+  for (int i = 0; i < n; ++i) {
+    Group& g = *gs[i];
+    ucc_status s = stage_round(g, slots, true, st);
+    if (s != UCC_OK) return s;
+    size_t l = 0;
+    int a = 1;
+    s = graph_job(g.proto, g.buf, g.buf.theta, (int)g.jobs.size(), group_mixed(g) ? g.bank : nullptr,
+                  &jobs[i], &l, &a);
+    if (s != UCC_OK) return s;
+    ctxs[i] = g.proto;
+    lds = std::max(lds, l);
+    align = std::max(align, a);
+  }
+  ucc_status s = enqueue_graph(ctxs, jobs, n, lds, align, st, nullptr);
+  for (int i = 0; i < n && s == UCC_OK; ++i) s = close_round(*gs[i], st);
+  return s;
 }
 
 }  // namespace
@@ -255,8 +313,11 @@ struct ucc_server {
   uint64_t next_id = 1;
   bool stop = false;
   std::thread worker;
+  hipStream_t graph_stream = nullptr;  // shared rounds of the launch_mode 3 groups
 
   void run();
+  void graph_rounds_locked(bool* progress, bool* any_done, bool* in_flight);
+  void update_members_locked(Group& g, bool* any_done);
   int cu_share_for(const Group& g) const;
   void admit_locked();
   Group* group_for(ucc_ctx* c);
@@ -291,6 +352,7 @@ Group* ucc_server::group_for(ucc_ctx* c) {
     return nullptr;
   }
   g->proto = c;
+  g->graph = c->plan.launch_mode == 3;
   groups.push_back(std::move(g));
   return groups.back().get();
 }
@@ -386,6 +448,77 @@ void ucc_server::finish_round_locked(Group& g, ucc_status st, const std::string&
   g.jobs.swap(keep);
 }
 
+// Cancelled members leave and admitted jobs join (the group has no round in flight).
+void ucc_server::update_members_locked(Group& g, bool* any_done) {
+  std::vector<Job*> keep;
+  for (Job* j : g.jobs) {
+    if (j->cancel) {
+      retire_locked(j, UCC_ECANCELED);
+      *any_done = true;
+    } else {
+      keep.push_back(j);
+    }
+  }
+  for (Job* j : g.joining) {
+    if (j->cancel) {
+      retire_locked(j, UCC_ECANCELED);
+      *any_done = true;
+    } else {
+      keep.push_back(j);
+    }
+  }
+  const bool changed = keep.size() != g.jobs.size() || !g.joining.empty();
+  g.joining.clear();
+  g.jobs.swap(keep);
+  if (changed) members_changed(g);
+}
+
+// The launch_mode 3 groups: when none has a round in flight, one shared graph launch (per
+// kMaxGraphJobs groups) for every such group with members.
+void ucc_server::graph_rounds_locked(bool* progress, bool* any_done, bool* in_flight) {
+  std::vector<Group*> gs;
+  for (auto& gp : groups)
+    if (gp->graph && gp->queued) {
+      *in_flight = true;
+      return;
+    }
+  for (auto& gp : groups) {
+    Group& g = *gp;
+    if (!g.graph) continue;
+    update_members_locked(g, any_done);
+    if (!g.jobs.empty()) gs.push_back(&g);
+  }
+  if (gs.empty()) return;
+  if (!graph_stream && hipStreamCreateWithFlags(&graph_stream, hipStreamNonBlocking) != hipSuccess) {
+    const ucc_status st = hip_fail(hipGetLastError(), "server graph stream");
+    for (Group* g : gs) {
+      finish_round_locked(*g, st, g_last_error);
+      members_changed(*g);
+    }
+    graph_stream = nullptr;
+    *any_done = true;
+    return;
+  }
+  for (size_t i = 0; i < gs.size(); i += kMaxGraphJobs) {
+    const int n = (int)std::min<size_t>(kMaxGraphJobs, gs.size() - i);
+    const ucc_status st = launch_graph_round(&gs[i], n, slots, graph_stream);
+    *progress = true;
+    if (st == UCC_OK) {
+      *in_flight = true;
+      continue;
+    }
+    const std::string err = g_last_error;
+    (void)hipStreamSynchronize(graph_stream);  // nothing of this round may still run on the rows
+    for (int k = 0; k < n; ++k) {
+      Group& g = *gs[i + k];
+      finish_round_locked(g, st, err);
+      g.queued = 0;
+      *any_done = true;
+      members_changed(g);
+    }
+  }
+}
+
 void ucc_server::run() {
   (void)hipSetDevice(device);
   std::unique_lock<std::mutex> lk(mu);
@@ -403,7 +536,9 @@ void ucc_server::run() {
           break;
         }
         progress = true;
-        const ucc_status st = e == hipSuccess ? UCC_OK : hip_fail(e, "server round");
+        ucc_status st = e == hipSuccess ? UCC_OK : hip_fail(e, "server round");
+        // a graph launch that gave up left NaN results and marked the group's status word
+        if (st == UCC_OK && g.graph) st = graph_check(g.buf);
         const size_t before = g.jobs.size();
         if (st != UCC_OK) (void)hipStreamSynchronize(g.stream);  // nothing may still run on the rows
         finish_round_locked(g, st, g_last_error);
@@ -415,6 +550,7 @@ void ucc_server::run() {
     }
     for (auto& gp : groups) {
       Group& g = *gp;
+      if (g.graph) continue;  // shared graph rounds (below)
       if (g.queued >= 2) continue;
       if (g.queued == 1) {  // the next round behind the one in flight, same rows
         if (!can_pipeline(g)) continue;
@@ -431,27 +567,7 @@ void ucc_server::run() {
         continue;
       }
       // no round in flight: membership changes, then the next round
-      std::vector<Job*> keep;
-      for (Job* j : g.jobs) {
-        if (j->cancel) {
-          retire_locked(j, UCC_ECANCELED);
-          any_done = true;
-        } else {
-          keep.push_back(j);
-        }
-      }
-      for (Job* j : g.joining) {
-        if (j->cancel) {
-          retire_locked(j, UCC_ECANCELED);
-          any_done = true;
-        } else {
-          keep.push_back(j);
-        }
-      }
-      const bool changed = keep.size() != g.jobs.size() || !g.joining.empty();
-      g.joining.clear();
-      g.jobs.swap(keep);
-      if (changed) members_changed(g);
+      update_members_locked(g, &any_done);
       if (g.jobs.empty()) continue;
       const ucc_status st = launch_round(g, slots, cu_share_for(g), true);
       progress = true;
@@ -467,11 +583,12 @@ void ucc_server::run() {
         in_flight = true;
       }
     }
+    graph_rounds_locked(&progress, &any_done, &in_flight);
     // empty groups give their memory back
     for (auto it = groups.begin(); it != groups.end();) {
       Group& g = **it;
       if (g.queued == 0 && g.jobs.empty() && g.joining.empty()) {
-        free_group(g);
+        free_group(g, g.graph ? graph_stream : nullptr);
         it = groups.erase(it);
       } else {
         ++it;
@@ -631,7 +748,8 @@ void ucc_server_destroy(ucc_server* s) {
   s->cv_work.notify_all();
   if (s->worker.joinable()) s->worker.join();
   (void)hipSetDevice(s->device);
-  for (auto& g : s->groups) free_group(*g);  // waits for rounds in flight
+  for (auto& g : s->groups) free_group(*g, s->graph_stream);  // waits for rounds in flight
+  if (s->graph_stream) (void)hipStreamDestroy(s->graph_stream);
   {
     std::lock_guard<std::mutex> lock(s->mu);
     for (auto& kv : s->jobs)
