@@ -395,6 +395,22 @@ def graph_launch(ucc, torch, h1, h2, exc, thetas, steps=20):
                                         for a, m in zip(alone, mix))}
     for c, _ in jobs:
         c.close()
+    # one evaluation (B = 1): the per-pass sequence pays a launch per pass
+    lat = {}
+    for n, ne in ((14, 6), (16, 8), (20, 10)):
+        a1, a2 = make_integrals(n // 2, 0)
+        ex = uccsd_excitations(n, ne)
+        t = torch.tensor(make_thetas(len(ex), 1, 0.05), device="cuda:0")
+        cg = ucc.Context(n, ne, a1, a2, ex, device=0, launch_mode=3)
+        k = min(n, 13)
+        ct = ucc.Context(n, ne, a1, a2, ex, device=0, launch_mode=1, block_threads=512,
+                         tile_qubits=k, tile_qubits_exp=k, tile_qubits_rev=k)
+        lat[f"{n}q"] = {"graph_ms": wall_ms(lambda: cg.energy_grad(t)),
+                        "per_pass_twin_ms": wall_ms(lambda: ct.energy_grad(t)),
+                        "passes": sum(cg.plan_info()[f"n_{x}_passes"] for x in ("fwd", "exp", "rev"))}
+        cg.close()
+        ct.close()
+    out["single_evaluation_B1"] = lat
     g.close()
     tw.close()
     return out
