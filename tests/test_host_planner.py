@@ -516,3 +516,32 @@ def test_fusion_depth_caps_the_windows():
     for bad in (-1, 257):
         with pytest.raises(ucc.UCCError):
             host_ctx(8, 4, fuse_depth=bad)
+
+
+def test_evaluation_graph_plan_and_rejections():
+    """launch_mode 3 (the evaluation graph): 512-thread workgroups and tiles of at most 13 qubits
+    for every kind, chosen without the autotuner; what the graph cannot take is refused."""
+    for n, ne in ((8, 4), (12, 8), (18, 10), (24, 14)):
+        h1, h2 = make_integrals(n // 2, 0)
+        c = ucc.Context(n, ne, h1, h2, uccsd_excitations(n, ne), launch_mode=3, host_only=True, max_batch=0)
+        i = c.plan_info()
+        assert i["launch_mode"] == 3
+        assert (i["block_threads_fwd"], i["block_threads_exp"], i["block_threads_rev"]) == (512, 512, 512)
+        k = min(n, 13)
+        assert (i["tile_qubits"], i["tile_qubits_exp"], i["tile_qubits_rev"]) == (k, k, k)
+        assert i["n_fwd_passes"] + i["n_exp_passes"] + i["n_rev_passes"] <= 512
+        assert i["graph_grid"] == 0  # no launch yet
+        c.close()
+    h1, h2 = make_integrals(9, 0)
+    exc = uccsd_excitations(18, 10)
+    for kw in (dict(taper=1), dict(tile_qubits=14), dict(tile_qubits_exp=14), dict(block_threads=1024),
+               dict(block_threads_rev=256), dict(graph_wait_us=-1), dict(launch_mode=4)):
+        opts = dict(launch_mode=3, host_only=True)
+        opts.update(kw)
+        with pytest.raises(ucc.UCCError) as e:
+            ucc.Context(18, 10, h1, h2, exc, **opts)
+        assert e.value.status == ucc.STATUS_CODES["UCC_EINVAL"], kw
+    # autotune needs a device context anyway; with launch_mode 3 it is refused before that
+    with pytest.raises(ucc.UCCError) as e:
+        ucc.Context(18, 10, h1, h2, exc, launch_mode=3, autotune=True)
+    assert "launch_mode 3" in str(e.value)
