@@ -71,7 +71,10 @@ typedef struct {
                                 with the same tiles; 512-thread workgroups, tiles of at most
                                 13 qubits, no taper; energy-only calls use the mode 1
                                 launches.  Contexts in mode 3 can also share one launch
-                                (ucc_energy_grad_jobs, server groups) */
+                                (ucc_energy_grad_jobs, server groups).  A graph launch needs
+                                every one of its workgroups resident: do not run two graph
+                                launches on one device at the same time (different streams);
+                                they may then give up waiting (see ucc_graph_status) */
   int32_t host_only;         /* 1: plan on the host only (no device memory, no evaluation);
                                 for introspection and tests on machines without a GPU */
   int32_t device;            /* HIP device ordinal; -1 = current device */
