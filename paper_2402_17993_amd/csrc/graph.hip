@@ -172,6 +172,7 @@ __device__ __forceinline__ bool sum_stage(const GraphJob& J, const Gate<T>& g, d
       const double gk = grad_component(J.gpart, b, J.L, nt, J.occ, J.K, k, lane, J.scale);
       if (lane == 0) J.G[(size_t)b * J.K + k] = gk;
     }
+    __syncthreads();  // the next wait may rewrite the gate's flag
   }
   return true;
 }
