@@ -138,6 +138,7 @@ LaunchArgs make_args(const ucc_ctx* c, const Buffers& b, int B, hipStream_t st) 
   a.hf = p.hf;
   a.amask = p.amask;
   a.bmask = p.bmask;
+  a.taper = p.taper;
   a.passes = c->d_passes;
   a.exc = c->d_exc;
   a.hpasses = c->tab.passes.data();
@@ -221,6 +222,7 @@ ucc_status graph_job(const ucc_ctx* c, Buffers& b, const double* d_theta, int B,
   J.lam = b.lam;
   J.ck = p.ckpt ? b.ck : nullptr;
   J.ckpt = p.ckpt ? 1 : 0;
+  J.taper = p.taper;
   J.epart = b.epart;
   J.gpart = b.gpart;
   J.E = b.E;
@@ -761,7 +763,15 @@ ucc_status ucc_get_state(ucc_ctx* c, int32_t b, double* re_im) {
   if (p.taper) std::memset(re_im, 0, sizeof(double) * 2 * (size_t(1) << p.nq));
   uint64_t la = 0, lb = 0;  // stored alpha / beta orbitals, logical
   for (int q = 0; q < n; ++q) (((p.iperm[q] & 1) ? lb : la) |= uint64_t(1) << p.iperm[q]);
+  // the kernels never write amplitudes outside the N / S_z sector (they are zero); the buffer
+  // may hold anything there, so those are reported as the zeros they are
+  const int na = __builtin_popcount(p.hf & p.amask), nb = __builtin_popcount(p.hf & p.bmask);
+  auto in_sector = [&](uint64_t P) {
+    const int da = na - __builtin_popcountll(P & p.amask), db = nb - __builtin_popcountll(P & p.bmask);
+    return p.taper ? (da == 0 || da == 1) && (db == 0 || db == 1) : da == 0 && db == 0;
+  };
   for (uint64_t P = 0; P < S; ++P) {
+    if (!in_sector(P)) tmp[2 * P] = tmp[2 * P + 1] = 0.0;
     uint64_t L = 0;
     for (int q = 0; q < n; ++q)
       if ((P >> q) & 1u) L |= uint64_t(1) << p.iperm[q];

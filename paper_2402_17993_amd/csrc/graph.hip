@@ -216,9 +216,9 @@ __device__ __forceinline__ bool run_stage(const GraphJob& J, int s, uint32_t* ab
       constexpr int KT = decltype(kt)::value;
       if (p == 0)
         return fwd_body<T, KT, true>(g, lds, J.passes, p, J.exc, J.cls, J.pairs, J.cs, J.K, src, dst,
-                                     J.n, J.hf, J.amask, J.bmask, total, 0, wg, grid);
+                                     J.n, J.hf, J.amask, J.bmask, total, 0, J.taper, wg, grid);
       return fwd_body<T, KT, false>(g, lds, J.passes, p, J.exc, J.cls, J.pairs, J.cs, J.K, src, dst, J.n,
-                                    J.hf, J.amask, J.bmask, total, 0, wg, grid);
+                                    J.hf, J.amask, J.bmask, total, 0, J.taper, wg, grid);
     });
   }
   if (p < J.nfwd + J.nexp) {
@@ -233,20 +233,20 @@ __device__ __forceinline__ bool run_stage(const GraphJob& J, int s, uint32_t* ab
         if constexpr (KT != 0)
           return exp2_body<T, KT, true, false, 2>(g, body, red, J.passes, p, J.blobs, J.cls, J.pairs,
                                                   J.psi, J.lam, J.n, J.amask, J.bmask, ep, J.estride,
-                                                  first, total, 0, GenPassArgs(), wg, grid);
+                                                  first, total, 0, GenPassArgs(), J.hf, J.taper, wg, grid);
         return false;
       }
       if (var == kVarExpv4)
         return expv_body<T, KT, true, 4>(g, body, red, J.passes, p, J.blobs, J.cls, J.pairs, J.psi, J.lam,
                                          J.n, J.amask, J.bmask, ep, J.estride, first, J.B,
-                                         ((J.B + 3) / 4) << (J.n - k), 0, wg, grid);
+                                         ((J.B + 3) / 4) << (J.n - k), 0, J.hf, J.taper, wg, grid);
       if (var == kVarExpv2)
         return expv_body<T, KT, true, 2>(g, body, red, J.passes, p, J.blobs, J.cls, J.pairs, J.psi, J.lam,
                                          J.n, J.amask, J.bmask, ep, J.estride, first, J.B,
-                                         ((J.B + 1) / 2) << (J.n - k), 0, wg, grid);
+                                         ((J.B + 1) / 2) << (J.n - k), 0, J.hf, J.taper, wg, grid);
       return exp_body<T, KT, true>(g, lds, J.passes, p, J.blobs, J.cls, J.pairs, J.psi, J.lam, J.n,
-                                   J.amask, J.bmask, ep, J.estride, first, total, J.blob_stride, 0, wg,
-                                   grid);
+                                   J.amask, J.bmask, ep, J.estride, first, total, J.blob_stride, 0, J.hf,
+                                   J.taper, wg, grid);
     });
   }
   const int j = p - J.nfwd - J.nexp;
@@ -257,10 +257,10 @@ __device__ __forceinline__ bool run_stage(const GraphJob& J, int s, uint32_t* ab
       if constexpr (KT != 0) {
         if (J.ckpt)
           return rev2_body<T, KT, false, false>(g, lds, J.passes, p, J.exc, J.cls, J.pairs, J.cs, J.K, psi,
-                                                J.lam, J.n, J.amask, J.bmask, J.gpart, J.L, total, 0, wg,
-                                                grid);
+                                                J.lam, J.n, J.amask, J.bmask, J.gpart, J.L, total, 0, J.hf,
+                                                J.taper, wg, grid);
         return rev2_body<T, KT, true, false>(g, lds, J.passes, p, J.exc, J.cls, J.pairs, J.cs, J.K, psi,
-                                             J.lam, J.n, J.amask, J.bmask, J.gpart, J.L, total, 0, wg, grid);
+                                             J.lam, J.n, J.amask, J.bmask, J.gpart, J.L, total, 0, J.hf, J.taper, wg, grid);
       }
       return false;
     }
@@ -269,9 +269,9 @@ __device__ __forceinline__ bool run_stage(const GraphJob& J, int s, uint32_t* ab
     double2* body = reinterpret_cast<double2*>(lb + sizeof(PassStage) + sizeof(double) * kGqWords);
     if (J.ckpt)
       return rev_body<T, KT, false>(g, body, st, gq, J.passes, p, J.exc, J.cls, J.pairs, J.cs, J.K, psi,
-                                    J.lam, J.n, J.amask, J.bmask, J.gpart, J.L, total, 0, wg, grid);
+                                    J.lam, J.n, J.amask, J.bmask, J.gpart, J.L, total, 0, J.hf, J.taper, wg, grid);
     return rev_body<T, KT, true>(g, body, st, gq, J.passes, p, J.exc, J.cls, J.pairs, J.cs, J.K, psi,
-                                 J.lam, J.n, J.amask, J.bmask, J.gpart, J.L, total, 0, wg, grid);
+                                 J.lam, J.n, J.amask, J.bmask, J.gpart, J.L, total, 0, J.hf, J.taper, wg, grid);
   });
 }
 

@@ -29,6 +29,7 @@ struct LaunchArgs {
   const int32_t* occ = nullptr;  // [K + 1] offsets, then the factors of each amplitude
   int tf = 512, te = 1024, tr = 256;  // workgroup size of forward, expectation, reverse passes
   uint32_t hf = 0, amask = 0, bmask = 0;
+  int taper = 0;  // tapered state (the sector admits one electron fewer per spin)
   const DevPass* passes = nullptr;
   const DevExc* exc = nullptr;
   const DevPass* hpasses = nullptr;  // host copy of the pass table (sizes for launches)
@@ -117,6 +118,7 @@ struct GraphJob {
   int nfwd = 0, nexp = 0, nrev = 0;
   int estride = 0, blob_stride = 0;
   int ckpt = 0;                   // 1: the reverse sweep reads stored states (psi not written)
+  int taper = 0;
   int stages = 0;
   uint32_t hf = 0, amask = 0, bmask = 0;
   uint32_t var[kMaxGraphPasses / 16] = {};  // 2 bits per pass: its PassVariant

@@ -2,11 +2,11 @@
 //
 // The pass kernels are persistent: each workgroup walks (batch entry, tile) items, a tile
 // being the 2^k amplitudes whose global bits equal the tile index.  A tile is streamed
-// through registers with coalesced 16-byte loads (the lowest physical bits are always local,
-// so consecutive lanes read consecutive addresses; the next tile's loads are in flight while
-// the current one is worked on); only its amplitudes inside the particle-number / S_z sector
-// go to LDS, by rank, all of the pass's work is applied there, and the tile is written back
-// (exact zeros outside the sector, the LDS values at their physical offsets inside).
+// through registers with 16-byte loads (the lowest physical bits are always local, so
+// consecutive lanes read consecutive addresses; the next tile's loads are in flight while the
+// current one is worked on), of its amplitudes inside the particle-number / S_z sector only
+// (the others are exactly zero and are never read or written); those go to LDS, by rank, all
+// of the pass's work is applied there, and they are written back to their physical offsets.
 //
 //   k_trig      cos/sin of every amplitude of every batch entry
 //   k_fwd       forward excitation pass: U_k = exp(theta_k G_k) for the pass's excitations
@@ -52,10 +52,10 @@ __global__ __launch_bounds__(T) LDS_BOUND_OCCUPANCY void k_fwd(
     const DevPass* __restrict__ passes, int pidx, const DevExc* __restrict__ exc,
     const int2* __restrict__ pcls, const uint32_t* __restrict__ pairs,
     const double2* __restrict__ cs, int K, const double2* src, double2* __restrict__ psi, int n,
-    uint32_t hf, uint32_t amask, uint32_t bmask, int total, int flip) {
+    uint32_t hf, uint32_t amask, uint32_t bmask, int total, int flip, int taper) {
   extern __shared__ double2 lds[];
   fwd_body<T, KT, INIT>(NoGate(), lds, passes, pidx, exc, pcls, pairs, cs, K, src, psi, n, hf, amask,
-                        bmask, total, flip, blockIdx.x, gridDim.x);
+                        bmask, total, flip, taper, blockIdx.x, gridDim.x);
 }
 
 template <int T, int KT, bool WP>
@@ -63,12 +63,13 @@ __global__ __launch_bounds__(T) LDS_BOUND_OCCUPANCY void k_rev(
     const DevPass* __restrict__ passes, int pidx, const DevExc* __restrict__ exc,
     const int2* __restrict__ pcls, const uint32_t* __restrict__ pairs,
     const double2* __restrict__ cs, int K, double2* __restrict__ psi, double2* __restrict__ lam,
-    int n, uint32_t amask, uint32_t bmask, double* __restrict__ gpart, int L, int total, int flip) {
+    int n, uint32_t amask, uint32_t bmask, double* __restrict__ gpart, int L, int total, int flip,
+    uint32_t hf, int taper) {
   extern __shared__ double2 lds[];
   __shared__ PassStage st;
   __shared__ double gq[kGqWords];  // quad partials of <lambda|G_k|psi>
   rev_body<T, KT, WP>(NoGate(), lds, st, gq, passes, pidx, exc, pcls, pairs, cs, K, psi, lam, n, amask,
-                      bmask, gpart, L, total, flip, blockIdx.x, gridDim.x);
+                      bmask, gpart, L, total, flip, hf, taper, blockIdx.x, gridDim.x);
 }
 
 template <int T, int KT, bool WP, bool GONLY = false>
@@ -76,10 +77,11 @@ __global__ __launch_bounds__(T) LDS_BOUND_OCCUPANCY void k_rev2(
     const DevPass* __restrict__ passes, int pidx, const DevExc* __restrict__ exc,
     const int2* __restrict__ pcls, const uint32_t* __restrict__ pairs,
     const double2* __restrict__ cs, int K, double2* __restrict__ psi, double2* __restrict__ lam,
-    int n, uint32_t amask, uint32_t bmask, double* __restrict__ gpart, int L, int total, int flip) {
+    int n, uint32_t amask, uint32_t bmask, double* __restrict__ gpart, int L, int total, int flip,
+    uint32_t hf, int taper) {
   extern __shared__ double2 lds[];
   rev2_body<T, KT, WP, GONLY>(NoGate(), lds, passes, pidx, exc, pcls, pairs, cs, K, psi, lam, n, amask,
-                              bmask, gpart, L, total, flip, blockIdx.x, gridDim.x);
+                              bmask, gpart, L, total, flip, hf, taper, blockIdx.x, gridDim.x);
 }
 
 template <int T, int KT, bool APPLY>
@@ -88,10 +90,10 @@ __global__ __launch_bounds__(T) LDS_BOUND_OCCUPANCY void k_exp(
     const int2* __restrict__ pcls, const uint32_t* __restrict__ blocks,
     const double2* __restrict__ psi, double2* __restrict__ lam, int n, uint32_t amask,
     uint32_t bmask, double* __restrict__ epart, int estride, int first, int total, int bstride,
-    int flip) {
+    int flip, uint32_t hf, int taper) {
   extern __shared__ double2 lds[];
   exp_body<T, KT, APPLY>(NoGate(), lds, passes, pidx, blobs, pcls, blocks, psi, lam, n, amask, bmask,
-                         epart, estride, first, total, bstride, flip, blockIdx.x, gridDim.x);
+                         epart, estride, first, total, bstride, flip, hf, taper, blockIdx.x, gridDim.x);
 }
 
 template <int T, int KT, bool APPLY, int V>
@@ -99,11 +101,12 @@ __global__ __launch_bounds__(T) LDS_BOUND_OCCUPANCY void k_expv(
     const DevPass* __restrict__ passes, int pidx, const uint4* __restrict__ blobs,
     const int2* __restrict__ pcls, const uint32_t* __restrict__ blocks,
     const double2* __restrict__ psi, double2* __restrict__ lam, int n, uint32_t amask,
-    uint32_t bmask, double* __restrict__ epart, int estride, int first, int B, int total, int flip) {
+    uint32_t bmask, double* __restrict__ epart, int estride, int first, int B, int total, int flip,
+    uint32_t hf, int taper) {
   extern __shared__ double2 lds[];
   __shared__ double red[V * (T / 64)];
   expv_body<T, KT, APPLY, V>(NoGate(), lds, red, passes, pidx, blobs, pcls, blocks, psi, lam, n, amask,
-                             bmask, epart, estride, first, B, total, flip, blockIdx.x, gridDim.x);
+                             bmask, epart, estride, first, B, total, flip, hf, taper, blockIdx.x, gridDim.x);
 }
 
 template <int T, int KT, bool APPLY, bool GEN = false, int PD = 2>
@@ -112,12 +115,12 @@ __global__ __launch_bounds__(T) LDS_BOUND_OCCUPANCY void k_exp2(
     const int2* __restrict__ pcls, const uint32_t* __restrict__ blocks,
     const double2* __restrict__ psi, double2* __restrict__ lam, int n, uint32_t amask,
     uint32_t bmask, double* __restrict__ epart, int estride, int first, int total, int flip,
-    GenPassArgs ga) {
+    GenPassArgs ga, uint32_t hf, int taper) {
   extern __shared__ double2 lds[];
   __shared__ double red[32];
   exp2_body<T, KT, APPLY, GEN, PD>(NoGate(), lds, red, passes, pidx, blobs, pcls, blocks, psi, lam, n,
-                                   amask, bmask, epart, estride, first, total, flip, ga, blockIdx.x,
-                                   gridDim.x);
+                                   amask, bmask, epart, estride, first, total, flip, ga, hf, taper,
+                                   blockIdx.x, gridDim.x);
 }
 
 
@@ -358,7 +361,7 @@ hipError_t fwd_ti(const LaunchArgs& a, int pidx, const double2* src, double2* ds
   const int grid = pass_grid(total, resident_grid(k_fwd<T, KT, INIT>, T, lds, a.cu_share), 1 << (a.n - k));
   hipLaunchKernelGGL((k_fwd<T, KT, INIT>), dim3(grid), dim3(T), lds, a.stream, a.passes, pidx,
                      a.exc, a.cls, a.pairs, a.cs, a.K, src, dst, a.n, a.hf, a.amask, a.bmask,
-                     total, a.flip);
+                     total, a.flip, a.taper);
   return hipGetLastError();
 }
 
@@ -393,7 +396,7 @@ hipError_t rev_overlapped(const LaunchArgs& a, int pidx, double2* psi, bool* use
     }
     hipLaunchKernelGGL((k_rev2<T, KT, WP, GONLY>), dim3(grid), dim3(T), lds, a.stream, a.passes, pidx,
                        a.exc, a.cls, a.pairs, a.cs, a.K, psi, a.lam, a.n, a.amask, a.bmask,
-                       a.gpart, a.L, total, a.flip);
+                       a.gpart, a.L, total, a.flip, a.hf, a.taper);
     *used = true;
     return hipGetLastError();
   }
@@ -416,7 +419,7 @@ hipError_t rev_tw(const LaunchArgs& a, int pidx, double2* psi) {
       pass_grid(total, resident_grid(k_rev<T, KT, WP>, T, lds, a.cu_share), 1 << (a.n - k));
   hipLaunchKernelGGL((k_rev<T, KT, WP>), dim3(grid), dim3(T), lds, a.stream, a.passes, pidx,
                      a.exc, a.cls, a.pairs, a.cs, a.K, psi, a.lam, a.n, a.amask, a.bmask, a.gpart,
-                     a.L, total, a.flip);
+                     a.L, total, a.flip, a.hf, a.taper);
   return hipGetLastError();
 }
 
@@ -458,7 +461,8 @@ hipError_t exp_overlapped(const LaunchArgs& a, int pidx, int eslot, int first, b
     }
     hipLaunchKernelGGL((k_exp2<T, KT, APPLY, false, PD>), dim3(grid), dim3(T), lds, a.stream, a.passes, pidx,
                        a.blobs, a.cls, a.pairs, a.psi, a.lam, a.n, a.amask, a.bmask,
-                       a.epart + (size_t)eslot, a.estride, first, total, a.flip, GenPassArgs());
+                       a.epart + (size_t)eslot, a.estride, first, total, a.flip, GenPassArgs(), a.hf,
+                       a.taper);
     *used = true;
     return hipGetLastError();
   }
@@ -485,7 +489,7 @@ hipError_t launch_expv(const LaunchArgs& a, int pidx, int eslot, int first, size
       pass_grid(total, resident_grid(k_expv<T, KT, APPLY, V>, T, lds, a.cu_share), 1 << (a.n - k));
   hipLaunchKernelGGL((k_expv<T, KT, APPLY, V>), dim3(grid), dim3(T), lds, a.stream, a.passes, pidx,
                      a.blobs, a.cls, a.pairs, a.psi, a.lam, a.n, a.amask, a.bmask,
-                     a.epart + (size_t)eslot, a.estride, first, a.B, total, a.flip);
+                     a.epart + (size_t)eslot, a.estride, first, a.B, total, a.flip, a.hf, a.taper);
   return hipGetLastError();
 }
 
@@ -535,7 +539,8 @@ hipError_t exp_t(const LaunchArgs& a, int pidx, int eslot, int first) {
       pass_grid(total, resident_grid(k_exp<T, KT, APPLY>, T, lds, a.cu_share), 1 << (a.n - k));
   hipLaunchKernelGGL((k_exp<T, KT, APPLY>), dim3(grid), dim3(T), lds, a.stream, a.passes, pidx,
                      a.blobs, a.cls, a.pairs, a.psi, a.lam, a.n, a.amask, a.bmask,
-                     a.epart + (size_t)eslot, a.estride, first, total, a.blob_stride, a.flip);
+                     a.epart + (size_t)eslot, a.estride, first, total, a.blob_stride, a.flip, a.hf,
+                     a.taper);
   return hipGetLastError();
 }
 
@@ -561,7 +566,7 @@ hipError_t gen_t(const LaunchArgs& a, int pidx, int first, const GenPassArgs& g,
       if (grid >= ntiles && grid % ntiles == 0) {
         hipLaunchKernelGGL((k_exp2<T, KT, true, true, PD>), dim3(grid), dim3(T), lds, a.stream, a.passes,
                            pidx, g.tmpl, a.cls, a.pairs, a.psi, a.lam, a.n, a.amask, a.bmask, a.epart,
-                           a.estride, first, total, a.flip, g);
+                           a.estride, first, total, a.flip, g, a.hf, a.taper);
         *fused = true;
         return hipGetLastError();
       }

@@ -119,6 +119,37 @@ __device__ __forceinline__ const dvec2& rget(const RegBuf<N>& r) {
     return rget<J - 1, N - 1>(r.tail);
 }
 
+// Which basis states lie in the N / S_z sector: popcount(v & amask) = na and
+// popcount(v & bmask) = nb (tapered states: the stored alpha / beta counts may also be one
+// less, the tapered orbital then holding the missing electron).  Amplitudes outside the
+// sector are exactly zero, so the tile loads read only the sector's: an element outside
+// loads the HF amplitude instead (one cached line per vector; the number of loads stays
+// fixed), and the cache lines that hold no sector state are never read.  The default
+// selector admits every state.
+struct SecSel {
+  uint32_t amask = 0, bmask = 0, hf = 0;
+  int na = 0, nb = 0, taper = 0;
+  bool all = true;
+  __device__ __forceinline__ static SecSel make(uint32_t amask, uint32_t bmask, uint32_t hf, int taper) {
+    SecSel s;
+    s.amask = amask;
+    s.bmask = bmask;
+    s.hf = hf;
+    s.na = __popc(hf & amask);
+    s.nb = __popc(hf & bmask);
+    s.taper = taper;
+    s.all = false;
+    return s;
+  }
+  __device__ __forceinline__ bool in(uint32_t ph) const {
+    if (all) return true;
+    const int da = na - __popc(ph & amask), db = nb - __popc(ph & bmask);
+    return taper ? ((unsigned)da <= 1u && (unsigned)db <= 1u) : (da == 0 && db == 0);
+  }
+  // the element to load for physical index ph
+  __device__ __forceinline__ uint32_t src(uint32_t ph) const { return in(ph) ? ph : hf; }
+};
+
 // Element c = threadIdx.x + j*T of a tile sits at base | dt | dj: dt deposits the thread's
 // low compact bits into the local mask, dj the bits of j into the next local bits (uniform).
 // KT = log2 of the tile size for the unrolled register-staged path (12, 13 or 14); KT = 0 is
@@ -134,7 +165,9 @@ struct Tile {
   uint32_t tid;  // the thread's index among the T threads that share the tile
   mutable uint32_t dt;
   uint32_t h0 = 0, h1 = 0, h2 = 0, h3 = 0, h4 = 0, h5 = 0;  // physical bits of j's bits 0..5
-  __device__ __forceinline__ explicit Tile(uint32_t lm, uint32_t t = threadIdx.x) : lmask(lm), tid(t) {
+  SecSel sel;  // the elements fetch reads (the others load the HF amplitude)
+  __device__ __forceinline__ explicit Tile(uint32_t lm, uint32_t t = threadIdx.x, SecSel s = SecSel())
+      : lmask(lm), tid(t), sel(s) {
     dt = dep(t, lm);
     uint32_t mm = lm;
 #pragma unroll
@@ -160,10 +193,10 @@ struct Tile {
            ((J & 8) ? h3 : 0u) | ((J & 16) ? h4 : 0u) | ((J & 32) ? h5 : 0u);
   }
   // fetch issues the loads of elements J .. JE - 1 of the thread into registers (waited on
-  // where they are used)
+  // where they are used); an element outside the sector loads the HF amplitude instead
   template <int J = 0, int JE = EPT>
   __device__ __forceinline__ void fetch(Buf& r, const double2* __restrict__ v, uint32_t base) const {
-    rget<J, EPT>(r) = ld16_stream(v + (base | off<J>()));
+    rget<J, EPT>(r) = ld16_stream(v + sel.src(base | off<J>()));
     if constexpr (J + 1 < JE) fetch<J + 1, JE>(r, v, base);
   }
 };
@@ -252,16 +285,15 @@ __device__ __forceinline__ uint32_t first_entry(const ExcRange& r, const uint32_
 
 // Tile elements of the thread (registers) and the tile's in-sector amplitudes (LDS, by rank).
 // Amplitudes outside the N / S_z sector are exactly zero and stay zero (the reference state is
-// in the sector and every factor conserves N and S_z).  A pass reads the whole tile and writes
-// the whole tile.
+// in the sector and every factor conserves N and S_z), so no pass reads or writes them: a
+// tile's loads fetch only its in-sector elements (Tile::fetch) and put_tile stores only those;
+// the cache lines that hold no sector state (65% of them at 18 qubits, 74% at 26) are never
+// touched, and the memory there is never read (ucc_get_state zeroes it when it copies a state
+// out).
 //   take:     in-sector values -> cv[rank]
-//   put_tile: every element of the thread, in tile order: cv[rank] inside the sector, zero
-//             outside.  One unconditional 16-byte store per element, so the number of stores
-//             a thread has in flight is known when the code is compiled and the next tile's
-//             take waits for that tile's loads only (vector-memory counters retire in issue
-//             order; a data-dependent store count would make it wait for every store).  The
-//             store data comes from LDS into fresh registers, never from the prefetch
-//             registers, so the next tile's loads do not wait for these stores either.
+//   put_tile: the thread's in-sector elements, in tile order: cv[rank] to its place.  The store
+//             data comes from LDS into fresh registers, never from the prefetch registers, so
+//             the next tile's loads do not wait for these stores.
 template <int T, int KT>
 struct Sector {
   using TL = Tile<T, KT>;
@@ -292,9 +324,7 @@ struct Sector {
                                                   const uint16_t* rtab, double2* __restrict__ v,
                                                   uint32_t base) {
     const uint32_t rk = rtab[tm.tid + J * T];
-    const bool in = rk != kNoRank;
-    const dvec2 d = ld16(cv + (in ? rk : 0u));
-    st16_stream(v + (base | tm.template off<J>()), in ? d : dvec2{0.0, 0.0});
+    if (rk != kNoRank) st16_stream(v + (base | tm.template off<J>()), ld16(cv + rk));
     if constexpr (J + 1 < EPT) put_tile<J + 1>(tm, cv, rtab, v, base);
   }
 };
@@ -303,10 +333,10 @@ struct Sector {
 template <int T, bool INIT>
 __device__ __forceinline__ void take_loop(uint32_t lmask, uint32_t tileN, double2* cv,
                                           const uint16_t* rtab, const double2* __restrict__ v,
-                                          uint32_t base, uint32_t hf) {
+                                          uint32_t base, uint32_t hf, const SecSel& sel) {
   for (uint32_t c = threadIdx.x; c < tileN; c += T) {
     const uint32_t ph = base | dep(c, lmask);
-    const double2 val = INIT ? make_double2(ph == hf ? 1.0 : 0.0, 0.0) : v[ph];
+    const double2 val = INIT ? make_double2(ph == hf ? 1.0 : 0.0, 0.0) : v[sel.src(ph)];
     // every amplitude of the tile is read (the load is not sunk into the branch below)
     if (!INIT) asm volatile("" : : "v"(val.x), "v"(val.y));
     const uint32_t rk = rtab[c];
@@ -320,7 +350,7 @@ __device__ __forceinline__ void put_tile_loop(uint32_t lmask, uint32_t tileN, co
                                               uint32_t base) {
   for (uint32_t c = threadIdx.x; c < tileN; c += T) {
     const uint32_t rk = rtab[c];
-    v[base | dep(c, lmask)] = rk != kNoRank ? cv[rk] : make_double2(0.0, 0.0);
+    if (rk != kNoRank) v[base | dep(c, lmask)] = cv[rk];
   }
 }
 
@@ -754,7 +784,7 @@ UCC_BODY bool fwd_body(
     const DevPass* __restrict__ passes, int pidx, const DevExc* __restrict__ exc,
     const int2* __restrict__ pcls, const uint32_t* __restrict__ pairs,
     const double2* __restrict__ cs, int K, const double2* src, double2* __restrict__ psi, int n,
-    uint32_t hf, uint32_t amask, uint32_t bmask, int total, int flip, int wg, int grid) {
+    uint32_t hf, uint32_t amask, uint32_t bmask, int total, int flip, int taper, int wg, int grid) {
   lds = in_lds(lds);
   passes = in_global(passes);
   exc = in_global(exc);
@@ -777,7 +807,7 @@ UCC_BODY bool fwd_body(
   uint16_t* rtab = reinterpret_cast<uint16_t*>(blk + ps.stage_len);
   DevExc* sx = reinterpret_cast<DevExc*>(rtab + tileN);
   double2* scs = reinterpret_cast<double2*>(sx + ps.count);
-  const TL tm(ps.lmask);
+  const TL tm(ps.lmask, threadIdx.x, SecSel::make(amask, bmask, hf, taper));
   const bool cst = (int)threadIdx.x < ps.count;
   int item = wg;
   if (item >= total) return true;
@@ -807,7 +837,7 @@ UCC_BODY bool fwd_body(
       else
         SC::take(tm, r, cp, rtab);
     } else {
-      take_loop<T, INIT>(ps.lmask, tileN, cp, rtab, src_of(it), base_of(it), hf);
+      take_loop<T, INIT>(ps.lmask, tileN, cp, rtab, src_of(it), base_of(it), hf, tm.sel);
     }
   };
   stage_class(base_of(item));
@@ -865,7 +895,7 @@ UCC_BODY bool rev_body(
     const int2* __restrict__ pcls, const uint32_t* __restrict__ pairs,
     const double2* __restrict__ cs, int K, double2* __restrict__ psi, double2* __restrict__ lam,
     int n, uint32_t amask, uint32_t bmask, double* __restrict__ gpart, int L, int total, int flip,
-    int wg, int grid) {
+    uint32_t hf, int taper, int wg, int grid) {
   lds = in_lds(lds);
   PassStage& st = *in_lds(&st_);
   gq = in_lds(gq);
@@ -892,7 +922,7 @@ UCC_BODY bool rev_body(
   double2* cl = lds + ps.ns_max;
   uint32_t* blk = reinterpret_cast<uint32_t*>(lds + 2 * ps.ns_max);
   uint16_t* rtab = reinterpret_cast<uint16_t*>(blk + ps.stage_len);
-  const TL tm(ps.lmask);
+  const TL tm(ps.lmask, threadIdx.x, SecSel::make(amask, bmask, hf, taper));
   const bool cst = (int)threadIdx.x < ps.count;
   int item = wg;
   if (item >= total) return true;
@@ -920,8 +950,8 @@ UCC_BODY bool rev_body(
       SC::take(tm, rp, cp, rtab);
       SC::take(tm, rl, cl, rtab);
     } else {
-      take_loop<T, false>(ps.lmask, tileN, cp, rtab, psi + off_of(it), base_of(it), 0u);
-      take_loop<T, false>(ps.lmask, tileN, cl, rtab, lam + off_of(it), base_of(it), 0u);
+      take_loop<T, false>(ps.lmask, tileN, cp, rtab, psi + off_of(it), base_of(it), 0u, tm.sel);
+      take_loop<T, false>(ps.lmask, tileN, cl, rtab, lam + off_of(it), base_of(it), 0u, tm.sel);
     }
   };
   stage_class(base_of(item));
@@ -998,7 +1028,7 @@ UCC_BODY bool rev2_body(
     const int2* __restrict__ pcls, const uint32_t* __restrict__ pairs,
     const double2* __restrict__ cs, int K, double2* __restrict__ psi, double2* __restrict__ lam,
     int n, uint32_t amask, uint32_t bmask, double* __restrict__ gpart, int L, int total, int flip,
-    int wg, int grid) {
+    uint32_t hf, int taper, int wg, int grid) {
   lds = in_lds(lds);
   passes = in_global(passes);
   exc = in_global(exc);
@@ -1040,7 +1070,7 @@ UCC_BODY bool rev2_body(
     stage_sc_class<T>(blk, rtab, pairs + bl.x, bl.y, tileN);  // its barriers publish sx too
   }
   const bool prod = (int)threadIdx.x >= P;
-  const TL tm(ps.lmask, prod ? threadIdx.x - P : 0u);
+  const TL tm(ps.lmask, prod ? threadIdx.x - P : 0u, SecSel::make(amask, bmask, hf, taper));
   // producers: item `it` into slot s (its (cos, signed sin), then psi, then lambda)
   auto read_item = [&](int it, int s) {
     const uint32_t base = base_of(it);
@@ -1125,7 +1155,7 @@ UCC_BODY bool exp_body(
     const int2* __restrict__ pcls, const uint32_t* __restrict__ blocks,
     const double2* __restrict__ psi, double2* __restrict__ lam, int n, uint32_t amask,
     uint32_t bmask, double* __restrict__ epart, int estride, int first, int total, int bstride,
-    int flip, int wg, int grid) {
+    int flip, uint32_t hf, int taper, int wg, int grid) {
   lds = in_lds(lds);
   passes = in_global(passes);
   blobs = in_global(blobs);
@@ -1153,7 +1183,7 @@ UCC_BODY bool exp_body(
   uint32_t* blk = reinterpret_cast<uint32_t*>(red + 16);
   uint16_t* rtab = reinterpret_cast<uint16_t*>(blk + ps.stage_len);
   const uint32_t* bw = reinterpret_cast<const uint32_t*>(lb);
-  const TL tm(ps.lmask);
+  const TL tm(ps.lmask, threadIdx.x, SecSel::make(amask, bmask, hf, taper));
   int item = wg;
   if (item >= total) return true;
   const int nb = total >> tb;
@@ -1197,7 +1227,7 @@ UCC_BODY bool exp_body(
     if constexpr (RP)
       SC::take(tm, r, cp, rtab);
     else
-      take_loop<T, false>(ps.lmask, tileN, cp, rtab, vec_of(item), base, 0u);
+      take_loop<T, false>(ps.lmask, tileN, cp, rtab, vec_of(item), base, 0u, tm.sel);
     exp_prep<T>(bw, t1, t2, dpre, ps.lmask, k, n, base);
     __syncthreads();  // cp and the per-tile values complete
     const int next = item + grid;
@@ -1353,7 +1383,7 @@ UCC_BODY bool expv_body(
     const int2* __restrict__ pcls, const uint32_t* __restrict__ blocks,
     const double2* __restrict__ psi, double2* __restrict__ lam, int n, uint32_t amask,
     uint32_t bmask, double* __restrict__ epart, int estride, int first, int B, int total, int flip,
-    int wg, int grid) {
+    uint32_t hf, int taper, int wg, int grid) {
   lds = in_lds(lds);
   red = in_lds(red);
   passes = in_global(passes);
@@ -1421,7 +1451,7 @@ UCC_BODY bool expv_body(
   stage_class(base_of(item));  // its barriers also publish the local tables
   auto g_end = [&](int g) { return min(V * g + V, B); };  // entries of group g inside the batch
   if (!gate.wait(V * group_of(item), g_end(group_of(item)))) return false;
-  const TL tm(ps.lmask);
+  const TL tm(ps.lmask, threadIdx.x, SecSel::make(amask, bmask, hf, taper));
   if (RP) tm.fetch(r, psi + ((size_t)entry(group_of(item), 0) << n), base_of(item));
   for (;;) {
     const int g = group_of(item);
@@ -1439,7 +1469,7 @@ UCC_BODY bool expv_body(
       }
     } else {
       for (int v = 0; v < V; ++v)
-        take_loop<T, false>(ps.lmask, tileN, cpb + v * ns_max, rtab, psi + ((size_t)entry(g, v) << n), base, 0u);
+        take_loop<T, false>(ps.lmask, tileN, cpb + v * ns_max, rtab, psi + ((size_t)entry(g, v) << n), base, 0u, tm.sel);
       exp_prep<T>(gb, t1, t2, dpre, ps.lmask, k, n, base);
     }
     __syncthreads();  // the tiles and the per-tile values complete
@@ -1498,7 +1528,7 @@ UCC_BODY bool exp2_body(
     const int2* __restrict__ pcls, const uint32_t* __restrict__ blocks,
     const double2* __restrict__ psi, double2* __restrict__ lam, int n, uint32_t amask,
     uint32_t bmask, double* __restrict__ epart, int estride, int first, int total, int flip,
-    const GenPassArgs& ga, int wg, int grid) {
+    const GenPassArgs& ga, uint32_t hf, int taper, int wg, int grid) {
   lds = in_lds(lds);
   red = in_lds(red);
   passes = in_global(passes);
@@ -1554,7 +1584,7 @@ UCC_BODY bool exp2_body(
   }
   exp_prep<T>(bw, t1, t2, dpre, ps.lmask, k, n, base);
   const bool prod = (int)threadIdx.x >= W;
-  const TL tm(ps.lmask, prod ? threadIdx.x - W : 0u);
+  const TL tm(ps.lmask, prod ? threadIdx.x - W : 0u, SecSel::make(amask, bmask, hf, taper));
   const int nsc = (int)blk[0];
   const uint32_t* sphys = blk + 2 + 2 * nsc + 1 + ((nsc + 1) >> 1);  // rows' local offsets
   // GEN: per-item slot values (two slots) and the slot -> excitation map, behind the rank table
