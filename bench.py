@@ -953,6 +953,12 @@ def main():
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "avg_launch_ms": avg_ms, "algorithmic_bytes_per_launch": bytes_per_launch,
+                     # the HBM bytes the counters saw, over the same live launch time: the
+                     # fraction of peak the kernel really moves (the dense-state model above
+                     # counts every amplitude of every tile, the kernels touch only the sector)
+                     "traffic_GBps": (traffic / (avg_ms * 1e-3) / 1e9) if traffic else None,
+                     "traffic_frac": (traffic / (avg_ms * 1e-3) / 1e9 / HBM_PEAK_GBS)
+                     if traffic else None,
                      "stream_ceiling": stream_rates(ucc, torch)},
         "kernels": {k: {"launches": v["launches"], "ms": v["ms"],
                         "GBps": (v["bytes"] / (v["ms"] * 1e-3) / 1e9) if v["ms"] else None}
