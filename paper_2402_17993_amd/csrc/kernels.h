@@ -38,6 +38,7 @@ struct LaunchArgs {
   int blob_stride = 0;  // uint4 per batch entry when entries have their own Hamiltonian
   int cu_share = 0;     // compute units the persistent pass kernels may fill (0 = all)
   int flip = 0;         // 1: pass kernels visit the batch entries in descending order
+  int rgroup = 0;       // batch entries per item of the overlapped reverse pass (0: default)
   // reverse passes whose rotations (cs) are all the identity: compute the gradient partials
   // only and write nothing back where the overlapped form applies (else the plain form runs)
   bool gonly = false;

@@ -72,7 +72,7 @@ __global__ __launch_bounds__(T) LDS_BOUND_OCCUPANCY void k_rev(
                       bmask, gpart, L, total, flip, hf, taper, blockIdx.x, gridDim.x);
 }
 
-template <int T, int KT, bool WP, bool GONLY = false>
+template <int T, int KT, bool WP, bool GONLY = false, int V = 1>
 __global__ __launch_bounds__(T) LDS_BOUND_OCCUPANCY void k_rev2(
     const DevPass* __restrict__ passes, int pidx, const DevExc* __restrict__ exc,
     const int2* __restrict__ pcls, const uint32_t* __restrict__ pairs,
@@ -80,8 +80,9 @@ __global__ __launch_bounds__(T) LDS_BOUND_OCCUPANCY void k_rev2(
     int n, uint32_t amask, uint32_t bmask, double* __restrict__ gpart, int L, int total, int flip,
     uint32_t hf, int taper) {
   extern __shared__ double2 lds[];
-  rev2_body<T, KT, WP, GONLY>(NoGate(), lds, passes, pidx, exc, pcls, pairs, cs, K, psi, lam, n, amask,
-                              bmask, gpart, L, total, flip, hf, taper, blockIdx.x, gridDim.x);
+  rev2_body<T, KT, WP, GONLY, NoGate, V>(NoGate(), lds, passes, pidx, exc, pcls, pairs, cs, K, psi,
+                                         lam, n, amask, bmask, gpart, L, total, flip, hf, taper,
+                                         blockIdx.x, gridDim.x);
 }
 
 template <int T, int KT, bool APPLY>
@@ -332,10 +333,12 @@ inline size_t sc_lds(const DevPass& hp, int vectors) {
   return 16 * size_t(vectors) * hp.ns_max + 4 * size_t(hp.stage_len) + (size_t(2) << hp.k);
 }
 inline size_t fwd_lds(const DevPass& hp) { return sc_lds(hp, 1) + (sizeof(DevExc) + 16) * size_t(hp.count); }
-// the overlapped reverse pass: the pass's records, two (cos, signed sin) stages and the quad
-// partials behind the tiles, the class block and the rank table; the chain's sink is static
-inline size_t rev2_lds(const DevPass& hp) {
-  return sc_lds(hp, 4) + sizeof(DevExc) * hp.count + 2 * 16 * size_t(hp.count) + 8 * 16 * size_t(hp.count | 1);
+// the overlapped reverse pass with V entries per item: two slots of V tiles of psi and
+// lambda, the class block and the rank table, the pass's records, a (cos, signed sin) stage
+// per slot and entry and the quad partials per entry; the chains' sink is static
+inline size_t rev2_lds(const DevPass& hp, int V = 1) {
+  return sc_lds(hp, 4 * V) + sizeof(DevExc) * hp.count + 2 * V * 16 * size_t(hp.count) +
+         V * 8 * 16 * size_t(hp.count | 1);
 }
 inline size_t exp2_lds(const DevPass& hp, bool apply) {
   const int k = hp.k;
@@ -371,35 +374,59 @@ hipError_t fwd_t(const LaunchArgs& a, int pidx, int init, const double2* src, do
 }
 
 // The overlapped reverse pass needs every workgroup to keep one tile (a grid that is a
-// multiple of the tile count), register staging and room for two LDS slots.
+// multiple of the tile count), register staging and room for two LDS slots.  V entries per
+// item (V chains at once); *fits tells whether this V could run.
 // dry: decide only (*used tells whether this form would run); nothing is launched.
-template <int T, int KT, bool WP, bool GONLY = false>
-hipError_t rev_overlapped(const LaunchArgs& a, int pidx, double2* psi, bool* used, bool dry = false) {
+template <int T, int KT, bool WP, bool GONLY, int V>
+hipError_t rev_overlapped_v(const LaunchArgs& a, int pidx, double2* psi, bool* used, bool dry) {
   *used = false;
-  if constexpr (T < 512 || KT == 0) {
+  if constexpr (T < 512 || KT == 0 || 128 * V > T || (GONLY && V > 1)) {
     return hipSuccess;
   } else {
     const DevPass& hp = a.hpasses[pidx];
     const int k = hp.k;
     const int ntiles = 1 << (a.n - k);
-    const size_t lds = rev2_lds(hp);
+    const size_t lds = rev2_lds(hp, V);
     if (lds + 16 > (size_t)kLdsBytes) return hipSuccess;
-    hipError_t e = set_lds(k_rev2<T, KT, WP, GONLY>, lds);
+    hipError_t e = set_lds(k_rev2<T, KT, WP, GONLY, V>, lds);
     if (e != hipSuccess) return e;
     const int total = a.B << (a.n - k);
+    const int items = ((a.B + V - 1) / V) << (a.n - k);
     const int grid =
-        pass_grid(total, resident_grid(k_rev2<T, KT, WP, GONLY>, T, lds, a.cu_share), ntiles);
+        pass_grid(items, resident_grid(k_rev2<T, KT, WP, GONLY, V>, T, lds, a.cu_share), ntiles);
     if (grid < ntiles || grid % ntiles != 0) return hipSuccess;
+    // groups only where every workgroup still overlaps several items and has V entries
+    if (V > 1 && (a.B < V || items < 2 * grid)) return hipSuccess;
     if (dry) {
       *used = true;
       return hipSuccess;
     }
-    hipLaunchKernelGGL((k_rev2<T, KT, WP, GONLY>), dim3(grid), dim3(T), lds, a.stream, a.passes, pidx,
-                       a.exc, a.cls, a.pairs, a.cs, a.K, psi, a.lam, a.n, a.amask, a.bmask,
+    hipLaunchKernelGGL((k_rev2<T, KT, WP, GONLY, V>), dim3(grid), dim3(T), lds, a.stream, a.passes,
+                       pidx, a.exc, a.cls, a.pairs, a.cs, a.K, psi, a.lam, a.n, a.amask, a.bmask,
                        a.gpart, a.L, total, a.flip, a.hf, a.taper);
     *used = true;
     return hipGetLastError();
   }
+}
+
+// Entries per item of the overlapped reverse pass: the chain of one entry bounds the pass
+// once the sector-only tile traffic is small, so a batch takes groups of rev_group entries
+// (one chain wave each), as long as every workgroup still gets several items to overlap.
+#ifndef UCC_REV_GROUP
+#define UCC_REV_GROUP 2
+#endif
+template <int T, int KT, bool WP, bool GONLY = false>
+hipError_t rev_overlapped(const LaunchArgs& a, int pidx, double2* psi, bool* used, bool dry = false) {
+  const int vg = a.rgroup > 0 ? a.rgroup : UCC_REV_GROUP;
+  if (!GONLY && vg >= 4) {
+    hipError_t e = rev_overlapped_v<T, KT, WP, GONLY, 4>(a, pidx, psi, used, dry);
+    if (e != hipSuccess || *used) return e;
+  }
+  if (!GONLY && vg >= 2) {
+    hipError_t e = rev_overlapped_v<T, KT, WP, GONLY, 2>(a, pidx, psi, used, dry);
+    if (e != hipSuccess || *used) return e;
+  }
+  return rev_overlapped_v<T, KT, WP, GONLY, 1>(a, pidx, psi, used, dry);
 }
 
 template <int T, int KT, bool WP>

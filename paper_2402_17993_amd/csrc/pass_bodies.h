@@ -492,16 +492,13 @@ __device__ __forceinline__ void fwd_excitations(double2* cp, const uint32_t* blk
 
 // Reverse excitations of a pass (descending k) on in-sector psi (cp) and lambda (cl): the
 // partial of <lambda|G_k|psi> over the tile's pairs (without the tile's sign, which
-// multiplies the sum exactly), then exp(-theta_k G_k) on both, applied by wave 0 alone as in
-// fwd_excitations.  Each quad's partial goes to gq (layout at kGqStride); rev_partial sums
-// them after the caller's workgroup barrier.
-template <int T>
-__device__ __forceinline__ void rev_excitations(double2* cp, double2* cl, const uint32_t* blk,
-                                                const double2* scs, int count, double* gq,
-                                                int gs = kGqStride) {
+// multiplies the sum exactly), then exp(-theta_k G_k) on both, applied by one wave alone as
+// in fwd_excitations (lane: the caller's lane in that wave).  Each quad's partial goes to gq
+// (layout at kGqStride); rev_partial sums them after the caller's workgroup barrier.  Several
+// waves may run chains at once on disjoint cp, cl and gq (they share only the sink).
+__device__ __forceinline__ void rev_chain(int lane, double2* cp, double2* cl, const uint32_t* blk,
+                                          const double2* scs, int count, double* gq, int gs) {
   __shared__ double2 sink[1];  // written and read by lanes without a pair; never used
-  if (threadIdx.x >= 64) return;
-  const int lane = threadIdx.x;
   const uint32_t* off = blk + 2;
   const int m = (int)blk[1], ns = (int)blk[0];
   const uint32_t* ent = blk + 3 + m + ((ns + 1) >> 1) + ns;
@@ -552,6 +549,15 @@ __device__ __forceinline__ void rev_excitations(double2* cp, double2* cl, const 
     nxt = nn;
     e0 = e0n;
   }
+}
+
+// rev_chain on wave 0; the other waves return at once.
+template <int T>
+__device__ __forceinline__ void rev_excitations(double2* cp, double2* cl, const uint32_t* blk,
+                                                const double2* scs, int count, double* gq,
+                                                int gs = kGqStride) {
+  if (threadIdx.x >= 64) return;
+  rev_chain((int)threadIdx.x, cp, cl, blk, scs, count, gq, gs);
 }
 
 // The per-quad partials of rev_excitations for a pass whose rotations are the identity, with
@@ -1007,21 +1013,26 @@ UCC_BODY bool rev_body(
 
 // Reverse pass, overlapped form, for workgroups whose items all have the same tile (the grid
 // is a multiple of the tile count): the in-sector amplitudes of two items live in two LDS
-// slots.  While wave 0 applies the excitations of item j (slot j & 1) and stores its gradient
-// partials, the upper half of the workgroup writes item j - 1 out of the other slot and reads
-// item j + 1 into it (its (cos, signed sin) included), so the tile traffic runs beside the
-// excitation chain instead of around it.  The same class block and rank table serve both
-// slots.  A producer thread writes and then reads the same tile elements, hence the same LDS
-// ranks, so the two steps need no synchronization between threads.
+// slots.  While the chain waves apply the excitations of item j (slot j & 1) and store its
+// gradient partials, the upper half of the workgroup writes item j - 1 out of the other slot
+// and reads item j + 1 into it (its (cos, signed sin) included), so the tile traffic runs
+// beside the excitation chain instead of around it.  The same class block and rank table
+// serve both slots.  A producer thread writes and then reads the same tile elements, hence
+// the same LDS ranks, so the two steps need no synchronization between threads.
+// V: batch entries per item.  An item is one tile of V consecutive entries (of the visiting
+// order; the last group may be short); wave v of the lower half runs the chain of entry v
+// in its own part of the slot, so V chains run at once.  Entries of one tile share the
+// class block and the excitation records, and each entry's arithmetic is that of V = 1.
+// total is always entries x tiles.
 // GONLY (a sweep whose rotations are all the identity, as in the adjoint of the Trotter-free
-// series): only the gradient partials are computed.  Every wave of the lower half takes
+// series; V = 1): only the gradient partials are computed.  Every wave of the lower half takes
 // excitations w, w + P/64, ... of the pass, its lanes take the pairs as the chain does and each
 // quad's partial goes to gq, so the partials are those of the chain with (cos, sin) = (1, 0);
 // a wave writes gpart for its own excitations only (its own LDS writes, read back in issue
 // order).  Nothing is written back to HBM.
 // Gating: an item is complete once it is written back, i.e. at the end of the next
 // iteration (GONLY: nothing is written back, so at the end of its own).
-template <int T, int KT, bool WP, bool GONLY, class GT>
+template <int T, int KT, bool WP, bool GONLY, class GT, int V = 1>
 UCC_BODY bool rev2_body(
     const GT& gate, double2* lds,
     const DevPass* __restrict__ passes, int pidx, const DevExc* __restrict__ exc,
@@ -1029,6 +1040,9 @@ UCC_BODY bool rev2_body(
     const double2* __restrict__ cs, int K, double2* __restrict__ psi, double2* __restrict__ lam,
     int n, uint32_t amask, uint32_t bmask, double* __restrict__ gpart, int L, int total, int flip,
     uint32_t hf, int taper, int wg, int grid) {
+  constexpr int P = T / 2;  // producer threads: the upper half of the workgroup
+  static_assert(V == 1 || !GONLY, "the partials-only form takes one entry per item");
+  static_assert(64 * V <= P, "the chain waves of an item fit the lower half");
   lds = in_lds(lds);
   passes = in_global(passes);
   exc = in_global(exc);
@@ -1038,7 +1052,6 @@ UCC_BODY bool rev2_body(
   psi = in_global(psi);
   lam = in_global(lam);
   gpart = in_global(gpart);
-  constexpr int P = T / 2;  // producer threads: the upper half of the workgroup
   using TL = Tile<P, KT>;
   using SC = Sector<P, KT>;
   const DevPass ps = passes[pidx];
@@ -1047,23 +1060,30 @@ UCC_BODY bool rev2_body(
   const uint32_t tmask = (1u << tb) - 1u;
   const int ntiles = 1 << tb;
   const int ns_max = ps.ns_max;
-  // LDS, all sized by the pass: psi and lambda of two slots by rank | class block | rank table |
-  // the excitation records | two (cos, signed sin) stages | quad partials (odd row stride)
-  double2* cpb = lds;                // [2][ns_max] psi by rank
-  double2* clb = lds + 2 * ns_max;   // [2][ns_max] lambda by rank
-  uint32_t* blk = reinterpret_cast<uint32_t*>(lds + 4 * ns_max);
+  // LDS, all sized by the pass: psi and lambda of two slots of V entries by rank | class
+  // block | rank table | the excitation records | (cos, signed sin) per slot and entry | quad
+  // partials per entry (odd row stride)
+  double2* cpb = lds;                    // [2][V][ns_max] psi by rank
+  double2* clb = lds + 2 * V * ns_max;   // [2][V][ns_max] lambda by rank
+  uint32_t* blk = reinterpret_cast<uint32_t*>(lds + 4 * V * ns_max);
   uint16_t* rtab = reinterpret_cast<uint16_t*>(blk + ps.stage_len);
   DevExc* sx = reinterpret_cast<DevExc*>(rtab + tileN);
   double2* scs0 = reinterpret_cast<double2*>(sx + ps.count);
-  double* gq = reinterpret_cast<double*>(scs0 + 2 * ps.count);
+  double* gq0 = reinterpret_cast<double*>(scs0 + 2 * V * ps.count);
   const int gs = ps.count | 1;
-  auto scs = [&](int slot) { return scs0 + slot * ps.count; };
+  auto scs = [&](int part) { return scs0 + part * ps.count; };  // part = slot * V + v
+  const int nb = total >> tb;                  // batch entries
+  const int items = ((nb + V - 1) / V) << tb;  // (group, tile) items
   const int item0 = wg;
-  if (item0 >= total) return true;
-  const int nb = total >> tb;
-  auto ent = [&](int it) { return flip ? nb - 1 - (it >> tb) : it >> tb; };  // batch entry
+  if (item0 >= items) return true;
+  auto ent = [&](int e) { return flip ? nb - 1 - e : e; };       // batch entry of visit e
+  auto vis = [&](int it, int v) { return (it >> tb) * V + v; };  // visit index of entry v
+  auto nv = [&](int it) { return min(V, nb - (it >> tb) * V); };  // entries of the item
+  // the batch entries of an item as a range [lo, hi)
+  auto lo_of = [&](int it) { return flip ? nb - (it >> tb) * V - nv(it) : (it >> tb) * V; };
+  auto hi_of = [&](int it) { return lo_of(it) + nv(it); };
   auto base_of = [&](int it) { return dep(it & tmask, ps.gmask); };
-  auto off_of = [&](int it) { return (size_t)ent(it) << n; };
+  auto off_of = [&](int it, int v) { return (size_t)ent(vis(it, v)) << n; };
   for (int i = threadIdx.x; i < ps.count; i += T) sx[i] = exc[ps.first + i];
   {
     const int2 bl = pcls[ps.cls_base + tile_class(base_of(item0), amask, bmask, ps.nbeta_g)];
@@ -1071,71 +1091,87 @@ UCC_BODY bool rev2_body(
   }
   const bool prod = (int)threadIdx.x >= P;
   const TL tm(ps.lmask, prod ? threadIdx.x - P : 0u, SecSel::make(amask, bmask, hf, taper));
-  // producers: item `it` into slot s (its (cos, signed sin), then psi, then lambda)
+  // producers: item `it` into slot s (per entry its (cos, signed sin), then psi, then lambda)
   auto read_item = [&](int it, int s) {
     const uint32_t base = base_of(it);
-    if (!GONLY)
-      for (int e = (int)tm.tid; e < ps.count; e += P)
-        scs(s)[e] = signed_cs(cs[(size_t)ent(it) * K + sx[e].k], sx[e], base);
-    typename TL::Buf r;
-    if constexpr (TL::EPT > 16) {  // large tiles: chunks of 8 elements per thread
-      read_chunks<0, TL::EPT / 8, 8, TL, SC>(tm, r, psi + off_of(it), base, cpb + s * ns_max, rtab);
-      read_chunks<0, TL::EPT / 8, 8, TL, SC>(tm, r, lam + off_of(it), base, clb + s * ns_max, rtab);
-    } else {
-      tm.refresh();
-      tm.fetch(r, psi + off_of(it), base);
-      SC::take(tm, r, cpb + s * ns_max, rtab);
-      tm.refresh();
-      tm.fetch(r, lam + off_of(it), base);
-      SC::take(tm, r, clb + s * ns_max, rtab);
+    const int m = nv(it);
+    for (int v = 0; v < m; ++v) {
+      const int part = s * V + v;
+      if (!GONLY) {
+        const double2* csb = cs + (size_t)ent(vis(it, v)) * K;
+        for (int e = (int)tm.tid; e < ps.count; e += P)
+          scs(part)[e] = signed_cs(csb[sx[e].k], sx[e], base);
+      }
+      typename TL::Buf r;
+      if constexpr (TL::EPT > 16) {  // large tiles: chunks of 8 elements per thread
+        read_chunks<0, TL::EPT / 8, 8, TL, SC>(tm, r, psi + off_of(it, v), base, cpb + part * ns_max, rtab);
+        read_chunks<0, TL::EPT / 8, 8, TL, SC>(tm, r, lam + off_of(it, v), base, clb + part * ns_max, rtab);
+      } else {
+        tm.refresh();
+        tm.fetch(r, psi + off_of(it, v), base);
+        SC::take(tm, r, cpb + part * ns_max, rtab);
+        tm.refresh();
+        tm.fetch(r, lam + off_of(it, v), base);
+        SC::take(tm, r, clb + part * ns_max, rtab);
+      }
     }
   };
   auto write_item = [&](int it, int s) {
     const uint32_t base = base_of(it);
-    tm.refresh();
-    if (WP) SC::put_tile(tm, cpb + s * ns_max, rtab, psi + off_of(it), base);
-    SC::put_tile(tm, clb + s * ns_max, rtab, lam + off_of(it), base);
+    const int m = nv(it);
+    for (int v = 0; v < m; ++v) {
+      const int part = s * V + v;
+      tm.refresh();
+      if (WP) SC::put_tile(tm, cpb + part * ns_max, rtab, psi + off_of(it, v), base);
+      SC::put_tile(tm, clb + part * ns_max, rtab, lam + off_of(it, v), base);
+    }
   };
-  if (!gate.wait(ent(item0), ent(item0) + 1)) return false;
+  if (!gate.wait(lo_of(item0), hi_of(item0))) return false;
   if (prod) read_item(item0, 0);
   __syncthreads();
   int item = item0, j = 0;
   for (;;) {
     const int slot = j & 1;
     const int next = item + grid;
-    if (next < total && !gate.wait(ent(next), ent(next) + 1)) return false;
+    if (next < items && !gate.wait(lo_of(next), hi_of(next))) return false;
     if (GONLY && !prod) {
       constexpr int NW = P / 64;
       const int lane = (int)threadIdx.x & 63, w = (int)threadIdx.x >> 6;
-      rev_partials_only<NW>(cpb + slot * ns_max, clb + slot * ns_max, blk, ps.count, gq, w, lane, gs);
+      rev_partials_only<NW>(cpb + slot * ns_max, clb + slot * ns_max, blk, ps.count, gq0, w, lane, gs);
       const uint32_t base = base_of(item);
-      const int b = ent(item);
+      const int b = ent(vis(item, 0));
       const uint32_t t = item & tmask;
       for (int e = w + NW * lane; e < ps.count; e += NW * 64)
-        gpart[((size_t)b * L + sx[e].occ) * ntiles + t] = rev_partial(gq, e, sx[e], base, gs);
-    } else if (!GONLY && threadIdx.x < 64) {
-      rev_excitations<T>(cpb + slot * ns_max, clb + slot * ns_max, blk, scs(slot), ps.count, gq, gs);
-      // the chain's partials are this wave's own LDS writes: read back in issue order
-      const uint32_t base = base_of(item);
-      const int b = ent(item);
-      const uint32_t t = item & tmask;
-      for (int e = threadIdx.x; e < ps.count; e += 64)
-        gpart[((size_t)b * L + sx[e].occ) * ntiles + t] = rev_partial(gq, e, sx[e], base, gs);
+        gpart[((size_t)b * L + sx[e].occ) * ntiles + t] = rev_partial(gq0, e, sx[e], base, gs);
+    } else if (!GONLY && (int)threadIdx.x < 64 * V) {
+      // chain wave v: entry v of the item, if the item has it
+      const int v = (int)threadIdx.x >> 6, lane = (int)threadIdx.x & 63;
+      if (v < nv(item)) {
+        const int part = slot * V + v;
+        double* gq = gq0 + v * 16 * gs;
+        rev_chain(lane, cpb + part * ns_max, clb + part * ns_max, blk, scs(part), ps.count, gq, gs);
+        // the chain's partials are this wave's own LDS writes: read back in issue order
+        const uint32_t base = base_of(item);
+        const int b = ent(vis(item, v));
+        const uint32_t t = item & tmask;
+        for (int e = lane; e < ps.count; e += 64)
+          gpart[((size_t)b * L + sx[e].occ) * ntiles + t] = rev_partial(gq, e, sx[e], base, gs);
+      }
     } else if (prod) {
       if (!GONLY && j > 0) write_item(item - grid, slot ^ 1);
-      if (next < total) read_item(next, slot ^ 1);
+      if (next < items) read_item(next, slot ^ 1);
     }
     __syncthreads();  // item j applied; item j + 1 read; item j - 1 written
     if (GONLY)
-      gate.done(ent(item), ent(item) + 1);
+      gate.done(lo_of(item), hi_of(item));
     else if (j > 0)
-      gate.done(ent(item - grid), ent(item - grid) + 1);
-    if (next >= total) break;
+      gate.done(lo_of(item - grid), hi_of(item - grid));
+    if (next >= items) break;
     item = next;
     ++j;
   }
   if (!GONLY && prod) write_item(item, j & 1);
-  if (!GONLY) gate.done(ent(item), ent(item) + 1);
+  if (!GONLY) gate.done(lo_of(item), hi_of(item));
   return true;
 }
 
