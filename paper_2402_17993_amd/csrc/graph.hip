@@ -205,6 +205,7 @@ __device__ __forceinline__ bool run_stage(const GraphJob& J, int s, uint32_t* ab
   if (s == P + 1) return sum_stage<T>(J, g, lds, wg, grid);
   const int p = s - 1;
   const int k = J.passes[p].k;
+  const int ks = J.n <= kBufMaxQubits ? k : 0;  // register-staged tile size (0: loop form)
   const int total = J.B << (J.n - k);
   const int var = (int)(J.var[p >> 4] >> (2 * (p & 15))) & 3;
   auto state = [&](int w) { return w == J.nfwd - 1 ? J.psi : J.ck + (size_t)w * J.cstride; };
@@ -212,7 +213,7 @@ __device__ __forceinline__ bool run_stage(const GraphJob& J, int s, uint32_t* ab
   if (p < J.nfwd) {
     double2* dst = J.ckpt ? state(p) : J.psi;
     const double2* src = J.ckpt && p > 0 ? state(p - 1) : dst;
-    return by_tile(k, [&](auto kt) {
+    return by_tile(ks, [&](auto kt) {
       constexpr int KT = decltype(kt)::value;
       if (p == 0)
         return fwd_body<T, KT, true>(g, lds, J.passes, p, J.exc, J.cls, J.pairs, J.cs, J.K, src, dst,
@@ -225,7 +226,7 @@ __device__ __forceinline__ bool run_stage(const GraphJob& J, int s, uint32_t* ab
     const int j = p - J.nfwd;
     double* ep = J.epart + (size_t)j * (1 << (J.n - k));
     const int first = j == 0;
-    return by_tile(k, [&](auto kt) {
+    return by_tile(ks, [&](auto kt) {
       constexpr int KT = decltype(kt)::value;
       double* red = reinterpret_cast<double*>(lds);
       double2* body = reinterpret_cast<double2*>(lb + 256);
@@ -251,7 +252,7 @@ __device__ __forceinline__ bool run_stage(const GraphJob& J, int s, uint32_t* ab
   }
   const int j = p - J.nfwd - J.nexp;
   double2* psi = J.ckpt ? state(J.nfwd - 1 - j) : J.psi;
-  return by_tile(k, [&](auto kt) {
+  return by_tile(ks, [&](auto kt) {
     constexpr int KT = decltype(kt)::value;
     if (var == kVarRev2) {
       if constexpr (KT != 0) {

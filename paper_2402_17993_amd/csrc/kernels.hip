@@ -602,9 +602,15 @@ hipError_t gen_t(const LaunchArgs& a, int pidx, int first, const GenPassArgs& g,
   return exp_t<T, KT, true>(a, pidx, 0, first);
 }
 
+// Tile size for the dispatch: register-staged tiles address the vector with 32-bit buffer
+// offsets, so larger states take the loop form (k = 0).
+inline int staged_k(const LaunchArgs& a, int pidx) {
+  return a.n <= kBufMaxQubits ? a.hpasses[pidx].k : 0;
+}
+
 template <int T>
 hipError_t gen_k(const LaunchArgs& a, int pidx, int first, const GenPassArgs& g, bool* fused) {
-  const int k = a.hpasses[pidx].k;
+  const int k = staged_k(a, pidx);
   if constexpr (T >= 512)
     if (k == 14) return gen_t<T, 14>(a, pidx, first, g, fused);
   if (k == 13) return gen_t<T, 13>(a, pidx, first, g, fused);
@@ -617,7 +623,7 @@ hipError_t gen_k(const LaunchArgs& a, int pidx, int first, const GenPassArgs& g,
 // 32 elements per thread, 16 for the two-vector reverse pass), a loop otherwise.
 template <int T>
 hipError_t fwd_k(const LaunchArgs& a, int pidx, int init, const double2* src, double2* dst) {
-  const int k = a.hpasses[pidx].k;
+  const int k = staged_k(a, pidx);
   if constexpr (T >= 512)
     if (k == 14) return fwd_t<T, 14>(a, pidx, init, src, dst);
   if (k == 13) return fwd_t<T, 13>(a, pidx, init, src, dst);
@@ -628,7 +634,7 @@ hipError_t fwd_k(const LaunchArgs& a, int pidx, int init, const double2* src, do
 
 template <int T>
 hipError_t rev_k(const LaunchArgs& a, int pidx, double2* psi, bool wp) {
-  const int k = a.hpasses[pidx].k;
+  const int k = staged_k(a, pidx);
   if constexpr (T >= 512) {
     if (k == 14) return rev_t<T, 14>(a, pidx, psi, wp);
     if (k == 13) return rev_t<T, 13>(a, pidx, psi, wp);
@@ -640,7 +646,7 @@ hipError_t rev_k(const LaunchArgs& a, int pidx, double2* psi, bool wp) {
 
 template <int T, bool APPLY>
 hipError_t exp_k(const LaunchArgs& a, int pidx, int eslot, int first) {
-  const int k = a.hpasses[pidx].k;
+  const int k = staged_k(a, pidx);
   if constexpr (T >= 512)
     if (k == 14) return exp_t<T, 14, APPLY>(a, pidx, eslot, first);
   if (k == 13) return exp_t<T, 13, APPLY>(a, pidx, eslot, first);
@@ -679,7 +685,7 @@ int variant_t(const LaunchArgs& a, int pidx, bool apply, bool wp) {
 
 template <int T>
 int variant_k(const LaunchArgs& a, int pidx, bool apply, bool wp) {
-  const int k = a.hpasses[pidx].k;
+  const int k = staged_k(a, pidx);
   if constexpr (T >= 512)
     if (k == 14) return variant_t<T, 14>(a, pidx, apply, wp);
   if (k == 13) return variant_t<T, 13>(a, pidx, apply, wp);

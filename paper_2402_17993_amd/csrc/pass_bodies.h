@@ -84,13 +84,30 @@ typedef double dvec2 __attribute__((ext_vector_type(2)));
 
 __device__ __forceinline__ dvec2 ld16(const double2* p) { return *reinterpret_cast<const dvec2*>(p); }
 __device__ __forceinline__ void st16(double2* p, dvec2 v) { *reinterpret_cast<dvec2*>(p) = v; }
-// Streaming (non-temporal) forms for the state tiles, which are read and written once per
-// pass: they then do not push the tables that every tile reads out of the L2 cache.
-__device__ __forceinline__ dvec2 ld16_stream(const double2* p) {
-  return __builtin_nontemporal_load(reinterpret_cast<const dvec2*>(p));
+// State tiles go through buffer instructions on a resource that spans one state vector:
+// the byte offset is 32 bits (states of at most kBufMaxQubits = 26 qubits: 1 GiB), an access at an offset
+// beyond the range (kBufOut) is dropped by the hardware (a load returns zero, a store writes
+// nothing, no memory is touched), so an element outside the sector costs neither traffic
+// nor a branch, and every thread issues the same number of memory instructions, which the
+// compiler can then wait for by count.  Streaming (non-temporal) hint: the tiles are read
+// and written once per pass and should not push the tables every tile reads out of the L2.
+// Larger states (up to the library's 30 qubits) take the loop forms of the passes, which
+// address the vector with 64-bit pointers.
+typedef uint32_t uvec4 __attribute__((ext_vector_type(4)));
+constexpr int kBufMaxQubits = 26;
+constexpr uint32_t kBufRecords = 0x7ffffff0u;  // the resource's size in bytes
+constexpr uint32_t kBufOut = 0x80000000u;      // an offset beyond it
+constexpr int kBufWord3 = 0x00020000;          // raw buffer, 32-bit data format
+constexpr int kBufNT = 2;                      // non-temporal
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t vec_rsrc(const double2* v) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<double2*>(v), (short)0, (int)kBufRecords,
+                                           kBufWord3);
 }
-__device__ __forceinline__ void st16_stream(double2* p, dvec2 v) {
-  __builtin_nontemporal_store(v, reinterpret_cast<dvec2*>(p));
+__device__ __forceinline__ dvec2 bld16_stream(__amdgpu_buffer_rsrc_t r, uint32_t off) {
+  return __builtin_bit_cast(dvec2, __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, kBufNT));
+}
+__device__ __forceinline__ void bst16_stream(__amdgpu_buffer_rsrc_t r, uint32_t off, dvec2 v) {
+  __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(uvec4, v), r, off, 0, kBufNT);
 }
 
 // Fixed-size register buffer of N complex values addressed by compile-time index (a nest
@@ -122,14 +139,15 @@ __device__ __forceinline__ const dvec2& rget(const RegBuf<N>& r) {
 // Which basis states lie in the N / S_z sector: popcount(v & amask) = na and
 // popcount(v & bmask) = nb (tapered states: the stored alpha / beta counts may also be one
 // less, the tapered orbital then holding the missing electron).  Amplitudes outside the
-// sector are exactly zero, so the tile loads read only the sector's: an element outside
-// loads the HF amplitude instead (one cached line per vector; the number of loads stays
-// fixed), and the cache lines that hold no sector state are never read.  The default
-// selector admits every state.
+// sector are exactly zero, so the tile loads and stores touch only the sector's (Tile::fetch,
+// Sector::put_tile), and the cache lines that hold no sector state are never read or
+// written.  The test is branch-free: na - popcount and nb - popcount, as unsigned numbers,
+// must not exceed lim (0 exact, 1 tapered; the default selector, lim = ~0, admits every
+// state).
 struct SecSel {
   uint32_t amask = 0, bmask = 0, hf = 0;
-  int na = 0, nb = 0, taper = 0;
-  bool all = true;
+  int na = 0, nb = 0;
+  uint32_t lim = ~0u;
   __device__ __forceinline__ static SecSel make(uint32_t amask, uint32_t bmask, uint32_t hf, int taper) {
     SecSel s;
     s.amask = amask;
@@ -137,14 +155,12 @@ struct SecSel {
     s.hf = hf;
     s.na = __popc(hf & amask);
     s.nb = __popc(hf & bmask);
-    s.taper = taper;
-    s.all = false;
+    s.lim = taper ? 1u : 0u;
     return s;
   }
   __device__ __forceinline__ bool in(uint32_t ph) const {
-    if (all) return true;
-    const int da = na - __popc(ph & amask), db = nb - __popc(ph & bmask);
-    return taper ? ((unsigned)da <= 1u && (unsigned)db <= 1u) : (da == 0 && db == 0);
+    const uint32_t da = (uint32_t)(na - __popc(ph & amask)), db = (uint32_t)(nb - __popc(ph & bmask));
+    return da <= lim && db <= lim;
   }
   // the element to load for physical index ph
   __device__ __forceinline__ uint32_t src(uint32_t ph) const { return in(ph) ? ph : hf; }
@@ -193,11 +209,16 @@ struct Tile {
            ((J & 8) ? h3 : 0u) | ((J & 16) ? h4 : 0u) | ((J & 32) ? h5 : 0u);
   }
   // fetch issues the loads of elements J .. JE - 1 of the thread into registers (waited on
-  // where they are used); an element outside the sector loads the HF amplitude instead
+  // where they are used); an element outside the sector reads nothing (its register is zero)
   template <int J = 0, int JE = EPT>
   __device__ __forceinline__ void fetch(Buf& r, const double2* __restrict__ v, uint32_t base) const {
-    rget<J, EPT>(r) = ld16_stream(v + sel.src(base | off<J>()));
-    if constexpr (J + 1 < JE) fetch<J + 1, JE>(r, v, base);
+    fetch_r<J, JE>(r, vec_rsrc(v), base);
+  }
+  template <int J, int JE>
+  __device__ __forceinline__ void fetch_r(Buf& r, __amdgpu_buffer_rsrc_t rs, uint32_t base) const {
+    const uint32_t ph = base | off<J>();
+    rget<J, EPT>(r) = bld16_stream(rs, sel.in(ph) ? ph << 4 : kBufOut);
+    if constexpr (J + 1 < JE) fetch_r<J + 1, JE>(r, rs, base);
   }
 };
 
@@ -319,13 +340,22 @@ struct Sector {
     }
     if constexpr (J + 1 < EPT) take_hf<J + 1>(tm, cv, rtab, base, hf);
   }
-  template <int J = 0>
   static __device__ __forceinline__ void put_tile(const TL& tm, const double2* cv,
                                                   const uint16_t* rtab, double2* __restrict__ v,
                                                   uint32_t base) {
+    put_tile_r<0>(tm, cv, rtab, vec_rsrc(v), base);
+  }
+  // every element issues its LDS read (rank 0 outside the sector) and its store (dropped
+  // outside the sector): no branch, a fixed count of each
+  template <int J>
+  static __device__ __forceinline__ void put_tile_r(const TL& tm, const double2* cv,
+                                                    const uint16_t* rtab, __amdgpu_buffer_rsrc_t rs,
+                                                    uint32_t base) {
     const uint32_t rk = rtab[tm.tid + J * T];
-    if (rk != kNoRank) st16_stream(v + (base | tm.template off<J>()), ld16(cv + rk));
-    if constexpr (J + 1 < EPT) put_tile<J + 1>(tm, cv, rtab, v, base);
+    const bool in = rk != kNoRank;
+    const dvec2 x = ld16(cv + (in ? rk : 0u));
+    bst16_stream(rs, in ? (base | tm.template off<J>()) << 4 : kBufOut, x);
+    if constexpr (J + 1 < EPT) put_tile_r<J + 1>(tm, cv, rtab, rs, base);
   }
 };
 
