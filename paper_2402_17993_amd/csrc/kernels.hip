@@ -58,6 +58,17 @@ __global__ __launch_bounds__(T) LDS_BOUND_OCCUPANCY void k_fwd(
                         bmask, total, flip, taper, blockIdx.x, gridDim.x);
 }
 
+template <int T, int KT, bool INIT, int V>
+__global__ __launch_bounds__(T) LDS_BOUND_OCCUPANCY void k_fwd2(
+    const DevPass* __restrict__ passes, int pidx, const DevExc* __restrict__ exc,
+    const int2* __restrict__ pcls, const uint32_t* __restrict__ pairs,
+    const double2* __restrict__ cs, int K, const double2* src, double2* __restrict__ psi, int n,
+    uint32_t hf, uint32_t amask, uint32_t bmask, int total, int flip, int taper) {
+  extern __shared__ double2 lds[];
+  fwd2_body<T, KT, INIT, V>(lds, passes, pidx, exc, pcls, pairs, cs, K, src, psi, n, hf, amask, bmask,
+                            total, flip, taper, blockIdx.x, gridDim.x);
+}
+
 template <int T, int KT, bool WP>
 __global__ __launch_bounds__(T) LDS_BOUND_OCCUPANCY void k_rev(
     const DevPass* __restrict__ passes, int pidx, const DevExc* __restrict__ exc,
@@ -353,10 +364,58 @@ inline size_t exp_lds(const DevPass& hp) {
          4 * size_t(hp.stage_len) + (size_t(2) << k);
 }
 
+// The overlapped forward pass with V entries per item (V chains at once): every workgroup
+// keeps one tile (a grid that is a multiple of the tile count), gets at least two items, and
+// the batch has V entries; *used tells whether it ran.
+inline size_t fwd2_lds(const DevPass& hp, int V) {
+  return 16 * 2 * size_t(V) * hp.ns_max + 4 * size_t(hp.stage_len) + (size_t(2) << hp.k) +
+         sizeof(DevExc) * hp.count + 2 * size_t(V) * 16 * hp.count;
+}
+template <int T, int KT, bool INIT, int V>
+hipError_t fwd_overlapped(const LaunchArgs& a, int pidx, const double2* src, double2* dst, bool* used) {
+  *used = false;
+  if constexpr (T < 512 || KT == 0 || 128 * V > T) {
+    return hipSuccess;
+  } else {
+    const DevPass& hp = a.hpasses[pidx];
+    const int k = hp.k;
+    const int ntiles = 1 << (a.n - k);
+    const size_t lds = fwd2_lds(hp, V);
+    if (lds + 16 > (size_t)kLdsBytes || a.B < V) return hipSuccess;
+    hipError_t e = set_lds(k_fwd2<T, KT, INIT, V>, lds);
+    if (e != hipSuccess) return e;
+    const int total = a.B << (a.n - k);
+    const int items = ((a.B + V - 1) / V) << (a.n - k);
+    const int grid =
+        pass_grid(items, resident_grid(k_fwd2<T, KT, INIT, V>, T, lds, a.cu_share), ntiles);
+    if (grid < ntiles || grid % ntiles != 0 || items < 2 * grid) return hipSuccess;
+    hipLaunchKernelGGL((k_fwd2<T, KT, INIT, V>), dim3(grid), dim3(T), lds, a.stream, a.passes, pidx,
+                       a.exc, a.cls, a.pairs, a.cs, a.K, src, dst, a.n, a.hf, a.amask, a.bmask,
+                       total, a.flip, a.taper);
+    *used = true;
+    return hipGetLastError();
+  }
+}
+
+// Entries per item of the overlapped forward pass, which 1024-thread workgroups take (512
+// producer threads hold a 2^13 tile in 16 registers each); smaller ones keep the one-wave
+// form (fwd_body), which measured faster there.  0: the one-wave form always.
+#ifndef UCC_FWD_GROUP
+#define UCC_FWD_GROUP 4
+#endif
+
 template <int T, int KT, bool INIT>
 hipError_t fwd_ti(const LaunchArgs& a, int pidx, const double2* src, double2* dst) {
   const DevPass& hp = a.hpasses[pidx];
   const int k = hp.k;
+  if constexpr (T == 1024) {
+    bool used = false;
+    hipError_t e0 = hipSuccess;
+    if (UCC_FWD_GROUP >= 4) e0 = fwd_overlapped<T, KT, INIT, 4>(a, pidx, src, dst, &used);
+    if (e0 != hipSuccess || used) return e0;
+    if (UCC_FWD_GROUP >= 2) e0 = fwd_overlapped<T, KT, INIT, 2>(a, pidx, src, dst, &used);
+    if (e0 != hipSuccess || used) return e0;
+  }
   const size_t lds = fwd_lds(hp);
   hipError_t e = set_lds(k_fwd<T, KT, INIT>, lds);
   if (e != hipSuccess) return e;

@@ -467,20 +467,18 @@ struct NoGate {
 
 // Forward excitations of a pass on the in-sector amplitudes cp of a tile (class block blk,
 // (cos, signed sin) of each excitation in scs): U_k = exp(theta_k G_k) in Trotter order, each
-// a Givens rotation on the excitation's pairs.  One wave (wave 0) applies them all: the LDS
-// operations of a wave take effect in issue order, so excitation e+1 reads what excitation e
-// wrote without a workgroup barrier, and the pairs of one excitation are disjoint, so no two
-// lanes touch the same amplitude within one excitation.  Every LDS operation of an excitation
-// is issued by all 64 lanes (lanes without a pair use a sink), so the number of operations
-// in flight is known when the code is compiled and the chain waits for its reads by count,
-// never for the previous excitation's writes.  The other waves return at once; the caller
-// synchronizes the workgroup before cp is read again.
-template <int T>
-__device__ __forceinline__ void fwd_excitations(double2* cp, const uint32_t* blk, const double2* scs,
-                                                int count) {
+// a Givens rotation on the excitation's pairs.  One wave (the caller's; lane: its lane)
+// applies them all: the LDS operations of a wave take effect in issue order, so excitation
+// e+1 reads what excitation e wrote without a workgroup barrier, and the pairs of one
+// excitation are disjoint, so no two lanes touch the same amplitude within one excitation.
+// Every LDS operation of an excitation is issued by all 64 lanes (lanes without a pair use a
+// sink), so the number of operations in flight is known when the code is compiled and the
+// chain waits for its reads by count, never for the previous excitation's writes.  Several
+// waves may run chains at once on disjoint amplitudes (they share only the sink); the caller
+// synchronizes the workgroup before cp is read by other waves.
+__device__ __forceinline__ void fwd_chain(int lane, double2* cp, const uint32_t* blk, const double2* scs,
+                                          int count) {
   __shared__ double2 sink[1];  // written and read by lanes without a pair; never used
-  if (threadIdx.x >= 64) return;
-  const int lane = threadIdx.x;
   const uint32_t* off = blk + 2;
   const int m = (int)blk[1], ns = (int)blk[0];
   const uint32_t* ent = blk + 3 + m + ((ns + 1) >> 1) + ns;
@@ -518,6 +516,14 @@ __device__ __forceinline__ void fwd_excitations(double2* cp, const uint32_t* blk
     nxt = nn;
     e0 = e0n;
   }
+}
+
+// fwd_chain on wave 0; the other waves return at once.
+template <int T>
+__device__ __forceinline__ void fwd_excitations(double2* cp, const uint32_t* blk, const double2* scs,
+                                                int count) {
+  if (threadIdx.x >= 64) return;
+  fwd_chain((int)threadIdx.x, cp, blk, scs, count);
 }
 
 // Reverse excitations of a pass (descending k) on in-sector psi (cp) and lambda (cl): the
@@ -806,7 +812,7 @@ __device__ __forceinline__ double exp_rows(const double2* cp, const uint32_t* bl
 //      during step 2;
 //   2. the pass's excitations run in order on the in-sector amplitudes in LDS (one wave,
 //      no barrier between excitations; the workgroup synchronizes once at the end);
-//   3. the whole tile is written (put_tile);
+//   3. the tile's in-sector amplitudes are written (put_tile);
 //   4. the next tile gives its in-sector amplitudes to LDS, by rank (take).
 // The take of step 4 sits at the end of the loop body, so the compiler sees the loads of
 // step 1 followed by exactly the stores of step 3 and waits for the loads alone.
@@ -915,6 +921,117 @@ UCC_BODY bool fwd_body(
     item = next;
   }
   return true;
+}
+
+// Forward pass, overlapped form, for workgroups whose items all have the same tile (the grid
+// is a multiple of the tile count): two LDS slots, each with the in-sector tiles of the V
+// batch entries of an item (V consecutive entries of the visiting order, the last group may
+// be short).  While wave v of the lower half applies the pass's excitations to entry v of
+// item j (slot j & 1), the upper half writes item j - 1 from the other slot to psi and reads
+// item j + 1 from src into it (INIT: the HF state, nothing read), its (cos, signed sin)
+// included.  Entries of one tile share the class block and the excitation records; each
+// entry's arithmetic is that of fwd_body, so the results are bitwise the same.  src and psi
+// may be the same vectors: an item is read before and written after its own iteration, and
+// the items of one iteration are different entries.  total is entries x tiles.
+template <int T, int KT, bool INIT, int V>
+__device__ __forceinline__ void fwd2_body(
+    double2* lds, const DevPass* __restrict__ passes, int pidx, const DevExc* __restrict__ exc,
+    const int2* __restrict__ pcls, const uint32_t* __restrict__ pairs,
+    const double2* __restrict__ cs, int K, const double2* src, double2* __restrict__ psi, int n,
+    uint32_t hf, uint32_t amask, uint32_t bmask, int total, int flip, int taper, int wg, int grid) {
+  constexpr int P = T / 2;  // producer threads: the upper half of the workgroup
+  static_assert(64 * V <= P, "the chain waves of an item fit the lower half");
+  static_assert(KT != 0, "register-staged tiles");
+  lds = in_lds(lds);
+  passes = in_global(passes);
+  exc = in_global(exc);
+  pcls = in_global(pcls);
+  pairs = in_global(pairs);
+  cs = in_global(cs);
+  src = in_global(src);
+  psi = in_global(psi);
+  using TL = Tile<P, KT>;
+  using SC = Sector<P, KT>;
+  const DevPass ps = passes[pidx];
+  const uint32_t tileN = 1u << ps.k;
+  const int tb = n - ps.k;
+  const uint32_t tmask = (1u << tb) - 1u;
+  const int ns_max = ps.ns_max;
+  // LDS, sized by the pass: [2][V][ns_max] in-sector amplitudes by rank | class block | rank
+  // table | the excitation records | (cos, signed sin) per slot and entry
+  double2* cpb = lds;
+  uint32_t* blk = reinterpret_cast<uint32_t*>(lds + 2 * V * ns_max);
+  uint16_t* rtab = reinterpret_cast<uint16_t*>(blk + ps.stage_len);
+  DevExc* sx = reinterpret_cast<DevExc*>(rtab + tileN);
+  double2* scs0 = reinterpret_cast<double2*>(sx + ps.count);
+  auto scs = [&](int part) { return scs0 + part * ps.count; };  // part = slot * V + v
+  const int nb = total >> tb;                  // batch entries
+  const int items = ((nb + V - 1) / V) << tb;  // (group, tile) items
+  const int item0 = wg;
+  if (item0 >= items) return;
+  auto ent = [&](int e) { return flip ? nb - 1 - e : e; };       // batch entry of visit e
+  auto vis = [&](int it, int v) { return (it >> tb) * V + v; };  // visit index of entry v
+  auto nv = [&](int it) { return min(V, nb - (it >> tb) * V); };  // entries of the item
+  auto base_of = [&](int it) { return dep(it & tmask, ps.gmask); };
+  auto off_of = [&](int it, int v) { return (size_t)ent(vis(it, v)) << n; };
+  for (int i = threadIdx.x; i < ps.count; i += T) sx[i] = exc[ps.first + i];
+  {
+    const int2 bl = pcls[ps.cls_base + tile_class(base_of(item0), amask, bmask, ps.nbeta_g)];
+    stage_sc_class<T>(blk, rtab, pairs + bl.x, bl.y, tileN);  // its barriers publish sx too
+  }
+  const bool prod = (int)threadIdx.x >= P;
+  const TL tm(ps.lmask, prod ? threadIdx.x - P : 0u, SecSel::make(amask, bmask, hf, taper));
+  // producers: item `it` into slot s (per entry its (cos, signed sin), then its tile)
+  auto read_item = [&](int it, int s) {
+    const uint32_t base = base_of(it);
+    const int m = nv(it);
+    for (int v = 0; v < m; ++v) {
+      const int part = s * V + v;
+      const double2* csb = cs + (size_t)ent(vis(it, v)) * K;
+      for (int e = (int)tm.tid; e < ps.count; e += P) scs(part)[e] = signed_cs(csb[sx[e].k], sx[e], base);
+      if constexpr (INIT) {
+        SC::take_hf(tm, cpb + part * ns_max, rtab, base, hf);
+      } else {
+        typename TL::Buf r;
+        if constexpr (TL::EPT > 16) {  // large tiles: chunks of 8 elements per thread
+          read_chunks<0, TL::EPT / 8, 8, TL, SC>(tm, r, src + off_of(it, v), base, cpb + part * ns_max, rtab);
+        } else {
+          tm.refresh();
+          tm.fetch(r, src + off_of(it, v), base);
+          SC::take(tm, r, cpb + part * ns_max, rtab);
+        }
+      }
+    }
+  };
+  auto write_item = [&](int it, int s) {
+    const uint32_t base = base_of(it);
+    const int m = nv(it);
+    for (int v = 0; v < m; ++v) {
+      tm.refresh();
+      SC::put_tile(tm, cpb + (s * V + v) * ns_max, rtab, psi + off_of(it, v), base);
+    }
+  };
+  if (prod) read_item(item0, 0);
+  __syncthreads();
+  int item = item0, j = 0;
+  for (;;) {
+    const int slot = j & 1;
+    const int next = item + grid;
+    if ((int)threadIdx.x < 64 * V) {
+      // chain wave v: entry v of the item, if the item has it
+      const int v = (int)threadIdx.x >> 6;
+      if (v < nv(item)) fwd_chain((int)threadIdx.x & 63, cpb + (slot * V + v) * ns_max, blk,
+                                  scs(slot * V + v), ps.count);
+    } else if (prod) {
+      if (j > 0) write_item(item - grid, slot ^ 1);
+      if (next < items) read_item(next, slot ^ 1);
+    }
+    __syncthreads();  // item j applied; item j + 1 read; item j - 1 written
+    if (next >= items) break;
+    item = next;
+    ++j;
+  }
+  if (prod) write_item(item, j & 1);
 }
 
 // Reverse pass: for each excitation (descending k) the partial of <lambda|G_k|psi> over the

@@ -61,11 +61,13 @@ Tuning choose_tuning(int n, int K, int batch, const ucc_options& o) {
   }
   // One-tile states are latency-bound: small workgroups.  Multi-tile states: large
   // workgroups keep a 2^14 tile in 16 registers per thread and give the apply-H rows their
-  // lanes; the two-vector reverse tile (and a 2^13 forward tile) takes 512.
+  // lanes; a 2^13 forward tile takes 512; the reverse pass over stored states takes 1024 (the
+  // overlapped form streams with half of it and runs a chain per batch entry of an item in
+  // the other), the recomputing one 512 (two vectors of a tile in registers).
   const bool small = n <= 12;
   t.tf = pick(o.block_threads_fwd, o.block_threads, small ? 256 : t.kf <= 13 ? 512 : 1024);
   t.te = pick(o.block_threads_exp, o.block_threads, small ? 256 : 1024);
-  t.tr = pick(o.block_threads_rev, o.block_threads, small ? 256 : 512);
+  t.tr = pick(o.block_threads_rev, o.block_threads, small ? 256 : t.ckpt ? 1024 : 512);
   t.launch_mode = o.launch_mode ? o.launch_mode : 1;  // 0 is resolved once the tables exist
   if (o.launch_mode == 3) {  // the evaluation graph: one workgroup size, tiles of at most 13
     t.tf = t.te = t.tr = 512;
