@@ -78,7 +78,7 @@ __global__ __launch_bounds__(T) LDS_BOUND_OCCUPANCY void k_rev(
     uint32_t hf, int taper) {
   extern __shared__ double2 lds[];
   __shared__ PassStage st;
-  __shared__ double gq[kGqWords];  // quad partials of <lambda|G_k|psi>
+  __shared__ double gq[kGqWords];  // row partials of <lambda|G_k|psi>
   rev_body<T, KT, WP>(NoGate(), lds, st, gq, passes, pidx, exc, pcls, pairs, cs, K, psi, lam, n, amask,
                       bmask, gpart, L, total, flip, hf, taper, blockIdx.x, gridDim.x);
 }
@@ -346,10 +346,10 @@ inline size_t sc_lds(const DevPass& hp, int vectors) {
 inline size_t fwd_lds(const DevPass& hp) { return sc_lds(hp, 1) + (sizeof(DevExc) + 16) * size_t(hp.count); }
 // the overlapped reverse pass with V entries per item: two slots of V tiles of psi and
 // lambda, the class block and the rank table, the pass's records, a (cos, signed sin) stage
-// per slot and entry and the quad partials per entry; the chains' sink is static
+// per slot and entry and the row partials per entry; the chains' sink is static
 inline size_t rev2_lds(const DevPass& hp, int V = 1) {
   return sc_lds(hp, 4 * V) + sizeof(DevExc) * hp.count + 2 * V * 16 * size_t(hp.count) +
-         V * 8 * 16 * size_t(hp.count | 1);
+         V * 8 * kGqRows * size_t(hp.count | 1);
 }
 inline size_t exp2_lds(const DevPass& hp, bool apply) {
   const int k = hp.k;

@@ -46,6 +46,17 @@ __device__ __forceinline__ double quad_sum(double v) {
   return v;
 }
 
+// Sum over the 16 lanes of a row (its quads' sums by pairs: row_half_mirror swaps quads 0 and
+// 1, 2 and 3; row_mirror swaps 0 and 3, 1 and 2).  Every step adds the same two values in
+// either order, and floating-point addition is commutative, so every lane of the row gets
+// the bitwise same sum ((q0 + q1) + (q2 + q3)).
+__device__ __forceinline__ double row_sum(double v) {
+  v = quad_sum(v);
+  v += dpp<0x141>(v);  // row_half_mirror
+  v += dpp<0x140>(v);  // row_mirror
+  return v;
+}
+
 // Sum over the 64 lanes of a wavefront in a fixed order (quads, row_shr 4 and 8 within each
 // row of 16, then row_bcast 15 and 31 across rows); every lane gets the result.
 __device__ __forceinline__ double wave_sum(double v) {
@@ -529,8 +540,9 @@ __device__ __forceinline__ void fwd_excitations(double2* cp, const uint32_t* blk
 // Reverse excitations of a pass (descending k) on in-sector psi (cp) and lambda (cl): the
 // partial of <lambda|G_k|psi> over the tile's pairs (without the tile's sign, which
 // multiplies the sum exactly), then exp(-theta_k G_k) on both, applied by one wave alone as
-// in fwd_excitations (lane: the caller's lane in that wave).  Each quad's partial goes to gq
-// (layout at kGqStride); rev_partial sums them after the caller's workgroup barrier.  Several
+// in fwd_excitations (lane: the caller's lane in that wave).  Each row's partial (16 lanes)
+// goes to gq (layout at kGqStride); rev_partial sums them after the caller's workgroup
+// barrier.  Several
 // waves may run chains at once on disjoint cp, cl and gq (they share only the sink).
 __device__ __forceinline__ void rev_chain(int lane, double2* cp, double2* cl, const uint32_t* blk,
                                           const double2* scs, int count, double* gq, int gs) {
@@ -578,9 +590,9 @@ __device__ __forceinline__ void rev_chain(int lane, double2* cp, double2* cl, co
       cl[qu] = make_double2(c * bu.x + sq * bw.x, c * bu.y + sq * bw.y);
       cl[qw] = make_double2(c * bw.x - sq * bu.x, c * bw.y - sq * bu.y);
     }
-    // the four lanes of a quad hold the same sum (the adds commute exactly) and all write it
-    g = quad_sum(g);
-    gq[(lane >> 2) * gs + e] = g;
+    // the 16 lanes of a row hold the same sum (the adds commute exactly) and all write it
+    g = row_sum(g);
+    gq[(lane >> 4) * gs + e] = g;
     cur = nxt;
     nxt = nn;
     e0 = e0n;
@@ -596,10 +608,10 @@ __device__ __forceinline__ void rev_excitations(double2* cp, double2* cl, const 
   rev_chain((int)threadIdx.x, cp, cl, blk, scs, count, gq, gs);
 }
 
-// The per-quad partials of rev_excitations for a pass whose rotations are the identity, with
+// The per-row partials of rev_excitations for a pass whose rotations are the identity, with
 // the excitations shared among NW waves (wave w: e = w, w + NW, ...) and cp, cl only read.
 // Lane l of a wave sums the pairs i0 + l, i0 + l + 64, ... of an excitation in the order the
-// chain does, so each quad's partial is the chain's.
+// chain does, so each row's partial is the chain's.
 template <int NW>
 __device__ __forceinline__ void rev_partials_only(const double2* cp, const double2* cl,
                                                   const uint32_t* blk, int count, double* gq, int w,
@@ -617,18 +629,18 @@ __device__ __forceinline__ void rev_partials_only(const double2* cp, const doubl
       const double t = (bw.x * au.x + bw.y * au.y) - (bu.x * aw.x + bu.y * aw.y);
       g += (en & 0x8000u) ? -t : t;
     }
-    g = quad_sum(g);
-    gq[(lane >> 2) * gs + e] = g;
+    g = row_sum(g);
+    gq[(lane >> 4) * gs + e] = g;
   }
 }
 
-// Tile partial of <lambda|G_k|psi> for the pass's excitation e: the 16 quad partials in a
+// Tile partial of <lambda|G_k|psi> for the pass's excitation e: the 4 row partials in a
 // fixed order, times the tile's sign of the excitation.
 __device__ __forceinline__ double rev_partial(const double* gq, int e, const DevExc& x, uint32_t base,
                                               int gs = kGqStride) {
   double s = 0.0;
 #pragma unroll
-  for (int q = 0; q < 16; ++q) s += gq[q * gs + e];
+  for (int q = 0; q < kGqRows; ++q) s += gq[q * gs + e];
   return exc_sign(x, base) * s;
 }
 
@@ -1039,7 +1051,7 @@ __device__ __forceinline__ void fwd2_body(
 // gradient partials collect in LDS and are stored with the tiles.  WP = false: psi is the
 // stored state the matching forward window left; it is read and never written (the state
 // this pass ends on is the previous stored state).
-// st: the pass's records and (cos, signed sin); gq: quad partials of <lambda|G_k|psi>
+// st: the pass's records and (cos, signed sin); gq: row partials of <lambda|G_k|psi>
 // (kGqWords doubles).
 template <int T, int KT, bool WP, class GT>
 UCC_BODY bool rev_body(
@@ -1174,7 +1186,7 @@ UCC_BODY bool rev_body(
 // GONLY (a sweep whose rotations are all the identity, as in the adjoint of the Trotter-free
 // series; V = 1): only the gradient partials are computed.  Every wave of the lower half takes
 // excitations w, w + P/64, ... of the pass, its lanes take the pairs as the chain does and each
-// quad's partial goes to gq, so the partials are those of the chain with (cos, sin) = (1, 0);
+// row's partial goes to gq, so the partials are those of the chain with (cos, sin) = (1, 0);
 // a wave writes gpart for its own excitations only (its own LDS writes, read back in issue
 // order).  Nothing is written back to HBM.
 // Gating: an item is complete once it is written back, i.e. at the end of the next
@@ -1208,7 +1220,7 @@ UCC_BODY bool rev2_body(
   const int ntiles = 1 << tb;
   const int ns_max = ps.ns_max;
   // LDS, all sized by the pass: psi and lambda of two slots of V entries by rank | class
-  // block | rank table | the excitation records | (cos, signed sin) per slot and entry | quad
+  // block | rank table | the excitation records | (cos, signed sin) per slot and entry | row
   // partials per entry (odd row stride)
   double2* cpb = lds;                    // [2][V][ns_max] psi by rank
   double2* clb = lds + 2 * V * ns_max;   // [2][V][ns_max] lambda by rank
@@ -1295,7 +1307,7 @@ UCC_BODY bool rev2_body(
       const int v = (int)threadIdx.x >> 6, lane = (int)threadIdx.x & 63;
       if (v < nv(item)) {
         const int part = slot * V + v;
-        double* gq = gq0 + v * 16 * gs;
+        double* gq = gq0 + v * kGqRows * gs;
         rev_chain(lane, cpb + part * ns_max, clb + part * ns_max, blk, scs(part), ps.count, gq, gs);
         // the chain's partials are this wave's own LDS writes: read back in issue order
         const uint32_t base = base_of(item);

@@ -39,10 +39,12 @@ struct DevExc {
 };
 
 constexpr int kMaxPassExc = 256;  // excitations per forward/reverse pass (staged in LDS)
-// Gradient partials of a reverse pass in LDS: quad q's partial of excitation e at
-// q * kGqStride + e (the stride spreads the 16 quads of one write over distinct banks).
+// Gradient partials of a reverse pass in LDS: the partial of row q (16 lanes of the chain
+// wave) for excitation e at q * kGqStride + e (the odd stride puts the rows of one write in
+// distinct banks).
+constexpr int kGqRows = 4;
 constexpr int kGqStride = kMaxPassExc + 1;
-constexpr int kGqWords = 16 * kGqStride;  // doubles
+constexpr int kGqWords = kGqRows * kGqStride;  // doubles
 
 // Class block of one forward/reverse pass for one tile class (the alpha and beta electron
 // counts of the tile's global bits): uint32 words
