@@ -44,7 +44,6 @@ bool stores_states(int n, const ucc_options& o) {
 
 Tuning choose_tuning(int n, int K, int batch, const ucc_options& o) {
   (void)K;
-  (void)batch;
   Tuning t;
   t.ckpt = stores_states(n, o);
   // n: stored qubits.  A tapered state keeps the same in-sector amplitudes in a quarter of the
@@ -61,13 +60,18 @@ Tuning choose_tuning(int n, int K, int batch, const ucc_options& o) {
   }
   // One-tile states are latency-bound: small workgroups.  Multi-tile states: large
   // workgroups keep a 2^14 tile in 16 registers per thread and give the apply-H rows their
-  // lanes; a 2^13 forward tile takes 512; the reverse pass over stored states takes 1024 (the
-  // overlapped form streams with half of it and runs a chain per batch entry of an item in
-  // the other), the recomputing one 512 (two vectors of a tile in registers).
+  // lanes; a 2^13 forward tile and the reverse tiles (two vectors) take 512.  Passes over
+  // stored states whose batch gives every workgroup of the chip (256 CUs, one 1024-thread
+  // workgroup each) at least two items of a group of entries (four forward, two reverse)
+  // take the overlapped forms at 1024 threads: half of the workgroup streams, the other
+  // half runs one excitation chain per entry of the item.
   const bool small = n <= 12;
-  t.tf = pick(o.block_threads_fwd, o.block_threads, small ? 256 : t.kf <= 13 ? 512 : 1024);
+  const bool fwd_groups = t.ckpt && (int64_t((batch + 3) / 4) << (n - t.kf)) >= 2 * 256;
+  const bool rev_groups = t.ckpt && (int64_t((batch + 1) / 2) << (n - t.kr)) >= 2 * 256;
+  t.tf = pick(o.block_threads_fwd, o.block_threads,
+              small ? 256 : t.kf <= 13 && !fwd_groups ? 512 : 1024);
   t.te = pick(o.block_threads_exp, o.block_threads, small ? 256 : 1024);
-  t.tr = pick(o.block_threads_rev, o.block_threads, small ? 256 : t.ckpt ? 1024 : 512);
+  t.tr = pick(o.block_threads_rev, o.block_threads, small ? 256 : rev_groups ? 1024 : 512);
   t.launch_mode = o.launch_mode ? o.launch_mode : 1;  // 0 is resolved once the tables exist
   if (o.launch_mode == 3) {  // the evaluation graph: one workgroup size, tiles of at most 13
     t.tf = t.te = t.tr = 512;
