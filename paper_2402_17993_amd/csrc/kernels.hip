@@ -58,14 +58,14 @@ __global__ __launch_bounds__(T) LDS_BOUND_OCCUPANCY void k_fwd(
                         bmask, total, flip, taper, blockIdx.x, gridDim.x);
 }
 
-template <int T, int KT, bool INIT, int V>
+template <int T, int KT, bool INIT, int V, int R>
 __global__ __launch_bounds__(T) LDS_BOUND_OCCUPANCY void k_fwd2(
     const DevPass* __restrict__ passes, int pidx, const DevExc* __restrict__ exc,
     const int2* __restrict__ pcls, const uint32_t* __restrict__ pairs,
     const double2* __restrict__ cs, int K, const double2* src, double2* __restrict__ psi, int n,
     uint32_t hf, uint32_t amask, uint32_t bmask, int total, int flip, int taper) {
   extern __shared__ double2 lds[];
-  fwd2_body<T, KT, INIT, V>(lds, passes, pidx, exc, pcls, pairs, cs, K, src, psi, n, hf, amask, bmask,
+  fwd2_body<T, KT, INIT, V, R>(lds, passes, pidx, exc, pcls, pairs, cs, K, src, psi, n, hf, amask, bmask,
                             total, flip, taper, blockIdx.x, gridDim.x);
 }
 
@@ -83,7 +83,7 @@ __global__ __launch_bounds__(T) LDS_BOUND_OCCUPANCY void k_rev(
                       bmask, gpart, L, total, flip, hf, taper, blockIdx.x, gridDim.x);
 }
 
-template <int T, int KT, bool WP, bool GONLY = false, int V = 1>
+template <int T, int KT, bool WP, bool GONLY = false, int V = 1, int R = 0>
 __global__ __launch_bounds__(T) LDS_BOUND_OCCUPANCY void k_rev2(
     const DevPass* __restrict__ passes, int pidx, const DevExc* __restrict__ exc,
     const int2* __restrict__ pcls, const uint32_t* __restrict__ pairs,
@@ -91,7 +91,7 @@ __global__ __launch_bounds__(T) LDS_BOUND_OCCUPANCY void k_rev2(
     int n, uint32_t amask, uint32_t bmask, double* __restrict__ gpart, int L, int total, int flip,
     uint32_t hf, int taper) {
   extern __shared__ double2 lds[];
-  rev2_body<T, KT, WP, GONLY, NoGate, V>(NoGate(), lds, passes, pidx, exc, pcls, pairs, cs, K, psi,
+  rev2_body<T, KT, WP, GONLY, NoGate, V, R>(NoGate(), lds, passes, pidx, exc, pcls, pairs, cs, K, psi,
                                          lam, n, amask, bmask, gpart, L, total, flip, hf, taper,
                                          blockIdx.x, gridDim.x);
 }
@@ -364,6 +364,12 @@ inline size_t exp_lds(const DevPass& hp) {
          4 * size_t(hp.stage_len) + (size_t(2) << k);
 }
 
+// The overlapped passes' producers move the in-sector ranks directly (RankIO, two per
+// thread) where the classes allow it, else the tile elements.
+#ifndef UCC_RANK_IO
+#define UCC_RANK_IO 1
+#endif
+
 // The overlapped forward pass with V entries per item (V chains at once): every workgroup
 // keeps one tile (a grid that is a multiple of the tile count), gets at least two items, and
 // the batch has V entries; *used tells whether it ran.
@@ -371,25 +377,32 @@ inline size_t fwd2_lds(const DevPass& hp, int V) {
   return 16 * 2 * size_t(V) * hp.ns_max + 4 * size_t(hp.stage_len) + (size_t(2) << hp.k) +
          sizeof(DevExc) * hp.count + 2 * size_t(V) * 16 * hp.count;
 }
-template <int T, int KT, bool INIT, int V>
+template <int T, int KT, bool INIT, int V, int R = 0>
 hipError_t fwd_overlapped(const LaunchArgs& a, int pidx, const double2* src, double2* dst, bool* used) {
   *used = false;
   if constexpr (T < 512 || KT == 0 || 128 * V > T) {
     return hipSuccess;
   } else {
+    if constexpr (R == 0 && !INIT) {  // the producers move ranks where the classes allow it
+      if (UCC_RANK_IO) {
+        hipError_t e0 = fwd_overlapped<T, KT, INIT, V, 2>(a, pidx, src, dst, used);
+        if (e0 != hipSuccess || *used) return e0;
+      }
+    }
     const DevPass& hp = a.hpasses[pidx];
     const int k = hp.k;
     const int ntiles = 1 << (a.n - k);
-    const size_t lds = fwd2_lds(hp, V);
+    if (R > 0 && hp.ns_max > R * (T / 2)) return hipSuccess;
+    const size_t lds = fwd2_lds(hp, V) + (R > 0 ? 4 * size_t(hp.ns_max) : 0);
     if (lds + 16 > (size_t)kLdsBytes || a.B < V) return hipSuccess;
-    hipError_t e = set_lds(k_fwd2<T, KT, INIT, V>, lds);
+    hipError_t e = set_lds(k_fwd2<T, KT, INIT, V, R>, lds);
     if (e != hipSuccess) return e;
     const int total = a.B << (a.n - k);
     const int items = ((a.B + V - 1) / V) << (a.n - k);
     const int grid =
-        pass_grid(items, resident_grid(k_fwd2<T, KT, INIT, V>, T, lds, a.cu_share), ntiles);
+        pass_grid(items, resident_grid(k_fwd2<T, KT, INIT, V, R>, T, lds, a.cu_share), ntiles);
     if (grid < ntiles || grid % ntiles != 0 || items < 2 * grid) return hipSuccess;
-    hipLaunchKernelGGL((k_fwd2<T, KT, INIT, V>), dim3(grid), dim3(T), lds, a.stream, a.passes, pidx,
+    hipLaunchKernelGGL((k_fwd2<T, KT, INIT, V, R>), dim3(grid), dim3(T), lds, a.stream, a.passes, pidx,
                        a.exc, a.cls, a.pairs, a.cs, a.K, src, dst, a.n, a.hf, a.amask, a.bmask,
                        total, a.flip, a.taper);
     *used = true;
@@ -436,8 +449,8 @@ hipError_t fwd_t(const LaunchArgs& a, int pidx, int init, const double2* src, do
 // multiple of the tile count), register staging and room for two LDS slots.  V entries per
 // item (V chains at once); *fits tells whether this V could run.
 // dry: decide only (*used tells whether this form would run); nothing is launched.
-template <int T, int KT, bool WP, bool GONLY, int V>
-hipError_t rev_overlapped_v(const LaunchArgs& a, int pidx, double2* psi, bool* used, bool dry) {
+template <int T, int KT, bool WP, bool GONLY, int V, int R>
+hipError_t rev_overlapped_vr(const LaunchArgs& a, int pidx, double2* psi, bool* used, bool dry) {
   *used = false;
   if constexpr (T < 512 || KT == 0 || 128 * V > T || (GONLY && V > 1)) {
     return hipSuccess;
@@ -445,14 +458,16 @@ hipError_t rev_overlapped_v(const LaunchArgs& a, int pidx, double2* psi, bool* u
     const DevPass& hp = a.hpasses[pidx];
     const int k = hp.k;
     const int ntiles = 1 << (a.n - k);
-    const size_t lds = rev2_lds(hp, V);
+    // R > 0: every rank of a class within R per producer thread, and the rank offsets in LDS
+    if (R > 0 && hp.ns_max > R * (T / 2)) return hipSuccess;
+    const size_t lds = rev2_lds(hp, V) + (R > 0 ? 4 * size_t(hp.ns_max) : 0);
     if (lds + 16 > (size_t)kLdsBytes) return hipSuccess;
-    hipError_t e = set_lds(k_rev2<T, KT, WP, GONLY, V>, lds);
+    hipError_t e = set_lds(k_rev2<T, KT, WP, GONLY, V, R>, lds);
     if (e != hipSuccess) return e;
     const int total = a.B << (a.n - k);
     const int items = ((a.B + V - 1) / V) << (a.n - k);
     const int grid =
-        pass_grid(items, resident_grid(k_rev2<T, KT, WP, GONLY, V>, T, lds, a.cu_share), ntiles);
+        pass_grid(items, resident_grid(k_rev2<T, KT, WP, GONLY, V, R>, T, lds, a.cu_share), ntiles);
     if (grid < ntiles || grid % ntiles != 0) return hipSuccess;
     // groups only where every workgroup still overlaps several items and has V entries
     if (V > 1 && (a.B < V || items < 2 * grid)) return hipSuccess;
@@ -460,12 +475,21 @@ hipError_t rev_overlapped_v(const LaunchArgs& a, int pidx, double2* psi, bool* u
       *used = true;
       return hipSuccess;
     }
-    hipLaunchKernelGGL((k_rev2<T, KT, WP, GONLY, V>), dim3(grid), dim3(T), lds, a.stream, a.passes,
+    hipLaunchKernelGGL((k_rev2<T, KT, WP, GONLY, V, R>), dim3(grid), dim3(T), lds, a.stream, a.passes,
                        pidx, a.exc, a.cls, a.pairs, a.cs, a.K, psi, a.lam, a.n, a.amask, a.bmask,
                        a.gpart, a.L, total, a.flip, a.hf, a.taper);
     *used = true;
     return hipGetLastError();
   }
+}
+
+template <int T, int KT, bool WP, bool GONLY, int V>
+hipError_t rev_overlapped_v(const LaunchArgs& a, int pidx, double2* psi, bool* used, bool dry) {
+  if (UCC_RANK_IO) {
+    hipError_t e = rev_overlapped_vr<T, KT, WP, GONLY, V, 2>(a, pidx, psi, used, dry);
+    if (e != hipSuccess || *used) return e;
+  }
+  return rev_overlapped_vr<T, KT, WP, GONLY, V, 0>(a, pidx, psi, used, dry);
 }
 
 // Entries per item of the overlapped reverse pass: the chain of one entry bounds the pass

@@ -370,6 +370,54 @@ struct Sector {
   }
 };
 
+// Rank-ordered streaming of a tile's in-sector amplitudes (the overlapped passes' producers):
+// rank r of the tile's class sits at physical offset pos[r] from the tile's base, so thread
+// t of the P producers moves ranks t, t + P, ... (at most R), and every load and store is
+// an in-sector amplitude: R loads per thread and vector instead of one per tile element, all
+// of an item's loads in flight before any is waited for, and no rank-table lookup.  Ranks
+// past the class's ns are addressed beyond the buffer's range (no access), so each thread
+// issues exactly R loads or stores per vector.
+template <int P, int R>
+struct RankIO {
+  static __device__ __forceinline__ void load(dvec2 (&x)[R], const uint32_t* pos, int ns,
+                                              const double2* v, uint32_t base, uint32_t tid) {
+    const __amdgpu_buffer_rsrc_t rs = vec_rsrc(v);
+#pragma unroll
+    for (int i = 0; i < R; ++i) {
+      const int r = (int)tid + i * P;
+      const bool in = r < ns;
+      x[i] = bld16_stream(rs, in ? (base | pos[in ? r : 0]) << 4 : kBufOut);
+    }
+  }
+  static __device__ __forceinline__ void take(const dvec2 (&x)[R], double2* cv, int ns, uint32_t tid) {
+#pragma unroll
+    for (int i = 0; i < R; ++i) {
+      const int r = (int)tid + i * P;
+      if (r < ns) st16(cv + r, x[i]);
+    }
+  }
+  static __device__ __forceinline__ void put(const double2* cv, const uint32_t* pos, int ns, double2* v,
+                                             uint32_t base, uint32_t tid) {
+    const __amdgpu_buffer_rsrc_t rs = vec_rsrc(v);
+#pragma unroll
+    for (int i = 0; i < R; ++i) {
+      const int r = (int)tid + i * P;
+      const bool in = r < ns;
+      const int rr = in ? r : 0;
+      bst16_stream(rs, in ? (base | pos[rr]) << 4 : kBufOut, ld16(cv + rr));
+    }
+  }
+};
+
+// pos[r] = physical offset of rank r of the staged class block blk (forward/reverse layout)
+// from the tile's base; the caller synchronizes before pos is read.
+template <int T>
+__device__ __forceinline__ void stage_rank_pos(uint32_t* pos, const uint32_t* blk, uint32_t lmask) {
+  const int ns = (int)blk[0];
+  const uint16_t* sl = reinterpret_cast<const uint16_t*>(blk + 3 + (int)blk[1]);
+  for (int i = threadIdx.x; i < ns; i += T) pos[i] = dep(sl[i], lmask);
+}
+
 // Loop forms for tiles without a register-staged variant (KT = 0).
 template <int T, bool INIT>
 __device__ __forceinline__ void take_loop(uint32_t lmask, uint32_t tileN, double2* cv,
@@ -945,7 +993,7 @@ UCC_BODY bool fwd_body(
 // entry's arithmetic is that of fwd_body, so the results are bitwise the same.  src and psi
 // may be the same vectors: an item is read before and written after its own iteration, and
 // the items of one iteration are different entries.  total is entries x tiles.
-template <int T, int KT, bool INIT, int V>
+template <int T, int KT, bool INIT, int V, int R = 0>
 __device__ __forceinline__ void fwd2_body(
     double2* lds, const DevPass* __restrict__ passes, int pidx, const DevExc* __restrict__ exc,
     const int2* __restrict__ pcls, const uint32_t* __restrict__ pairs,
@@ -976,6 +1024,7 @@ __device__ __forceinline__ void fwd2_body(
   uint16_t* rtab = reinterpret_cast<uint16_t*>(blk + ps.stage_len);
   DevExc* sx = reinterpret_cast<DevExc*>(rtab + tileN);
   double2* scs0 = reinterpret_cast<double2*>(sx + ps.count);
+  uint32_t* pos = reinterpret_cast<uint32_t*>(scs0 + 2 * V * ps.count);  // R > 0: [ns_max]
   auto scs = [&](int part) { return scs0 + part * ps.count; };  // part = slot * V + v
   const int nb = total >> tb;                  // batch entries
   const int items = ((nb + V - 1) / V) << tb;  // (group, tile) items
@@ -991,12 +1040,33 @@ __device__ __forceinline__ void fwd2_body(
     const int2 bl = pcls[ps.cls_base + tile_class(base_of(item0), amask, bmask, ps.nbeta_g)];
     stage_sc_class<T>(blk, rtab, pairs + bl.x, bl.y, tileN);  // its barriers publish sx too
   }
+  const int ns = (int)blk[0];
+  if constexpr (R > 0) {
+    stage_rank_pos<T>(pos, blk, ps.lmask);
+    __syncthreads();
+  }
   const bool prod = (int)threadIdx.x >= P;
   const TL tm(ps.lmask, prod ? threadIdx.x - P : 0u, SecSel::make(amask, bmask, hf, taper));
+  using RIO = RankIO<P, (R > 0 ? R : 1)>;
   // producers: item `it` into slot s (per entry its (cos, signed sin), then its tile)
   auto read_item = [&](int it, int s) {
     const uint32_t base = base_of(it);
     const int m = nv(it);
+    if constexpr (R > 0 && !INIT) {
+      for (int v = 0; v < m; ++v) {
+        const double2* csb = cs + (size_t)ent(vis(it, v)) * K;
+        for (int e = (int)tm.tid; e < ps.count; e += P)
+          scs(s * V + v)[e] = signed_cs(csb[sx[e].k], sx[e], base);
+      }
+      dvec2 x[V][R > 0 ? R : 1];  // every entry's tile requested before any is taken
+#pragma unroll
+      for (int v = 0; v < V; ++v)
+        if (v < m) RIO::load(x[v], pos, ns, src + off_of(it, v), base, tm.tid);
+#pragma unroll
+      for (int v = 0; v < V; ++v)
+        if (v < m) RIO::take(x[v], cpb + (s * V + v) * ns_max, ns, tm.tid);
+      return;
+    }
     for (int v = 0; v < m; ++v) {
       const int part = s * V + v;
       const double2* csb = cs + (size_t)ent(vis(it, v)) * K;
@@ -1019,8 +1089,12 @@ __device__ __forceinline__ void fwd2_body(
     const uint32_t base = base_of(it);
     const int m = nv(it);
     for (int v = 0; v < m; ++v) {
-      tm.refresh();
-      SC::put_tile(tm, cpb + (s * V + v) * ns_max, rtab, psi + off_of(it, v), base);
+      if constexpr (R > 0) {
+        RIO::put(cpb + (s * V + v) * ns_max, pos, ns, psi + off_of(it, v), base, tm.tid);
+      } else {
+        tm.refresh();
+        SC::put_tile(tm, cpb + (s * V + v) * ns_max, rtab, psi + off_of(it, v), base);
+      }
     }
   };
   if (prod) read_item(item0, 0);
@@ -1191,7 +1265,7 @@ UCC_BODY bool rev_body(
 // order).  Nothing is written back to HBM.
 // Gating: an item is complete once it is written back, i.e. at the end of the next
 // iteration (GONLY: nothing is written back, so at the end of its own).
-template <int T, int KT, bool WP, bool GONLY, class GT, int V = 1>
+template <int T, int KT, bool WP, bool GONLY, class GT, int V = 1, int R = 0>
 UCC_BODY bool rev2_body(
     const GT& gate, double2* lds,
     const DevPass* __restrict__ passes, int pidx, const DevExc* __restrict__ exc,
@@ -1230,6 +1304,7 @@ UCC_BODY bool rev2_body(
   double2* scs0 = reinterpret_cast<double2*>(sx + ps.count);
   double* gq0 = reinterpret_cast<double*>(scs0 + 2 * V * ps.count);
   const int gs = ps.count | 1;
+  uint32_t* pos = reinterpret_cast<uint32_t*>(gq0 + V * kGqRows * gs);  // R > 0: [ns_max]
   auto scs = [&](int part) { return scs0 + part * ps.count; };  // part = slot * V + v
   const int nb = total >> tb;                  // batch entries
   const int items = ((nb + V - 1) / V) << tb;  // (group, tile) items
@@ -1248,19 +1323,44 @@ UCC_BODY bool rev2_body(
     const int2 bl = pcls[ps.cls_base + tile_class(base_of(item0), amask, bmask, ps.nbeta_g)];
     stage_sc_class<T>(blk, rtab, pairs + bl.x, bl.y, tileN);  // its barriers publish sx too
   }
+  const int ns = (int)blk[0];
+  if constexpr (R > 0) {
+    stage_rank_pos<T>(pos, blk, ps.lmask);
+    __syncthreads();
+  }
   const bool prod = (int)threadIdx.x >= P;
   const TL tm(ps.lmask, prod ? threadIdx.x - P : 0u, SecSel::make(amask, bmask, hf, taper));
+  using RIO = RankIO<P, (R > 0 ? R : 1)>;
   // producers: item `it` into slot s (per entry its (cos, signed sin), then psi, then lambda)
   auto read_item = [&](int it, int s) {
     const uint32_t base = base_of(it);
     const int m = nv(it);
     for (int v = 0; v < m; ++v) {
-      const int part = s * V + v;
       if (!GONLY) {
         const double2* csb = cs + (size_t)ent(vis(it, v)) * K;
         for (int e = (int)tm.tid; e < ps.count; e += P)
-          scs(part)[e] = signed_cs(csb[sx[e].k], sx[e], base);
+          scs(s * V + v)[e] = signed_cs(csb[sx[e].k], sx[e], base);
       }
+    }
+    if constexpr (R > 0) {
+      // every entry's psi and lambda requested before any is taken
+      dvec2 xp[V][R > 0 ? R : 1], xl[V][R > 0 ? R : 1];
+#pragma unroll
+      for (int v = 0; v < V; ++v)
+        if (v < m) {
+          RIO::load(xp[v], pos, ns, psi + off_of(it, v), base, tm.tid);
+          RIO::load(xl[v], pos, ns, lam + off_of(it, v), base, tm.tid);
+        }
+#pragma unroll
+      for (int v = 0; v < V; ++v)
+        if (v < m) {
+          RIO::take(xp[v], cpb + (s * V + v) * ns_max, ns, tm.tid);
+          RIO::take(xl[v], clb + (s * V + v) * ns_max, ns, tm.tid);
+        }
+      return;
+    }
+    for (int v = 0; v < m; ++v) {
+      const int part = s * V + v;
       typename TL::Buf r;
       if constexpr (TL::EPT > 16) {  // large tiles: chunks of 8 elements per thread
         read_chunks<0, TL::EPT / 8, 8, TL, SC>(tm, r, psi + off_of(it, v), base, cpb + part * ns_max, rtab);
@@ -1280,9 +1380,14 @@ UCC_BODY bool rev2_body(
     const int m = nv(it);
     for (int v = 0; v < m; ++v) {
       const int part = s * V + v;
-      tm.refresh();
-      if (WP) SC::put_tile(tm, cpb + part * ns_max, rtab, psi + off_of(it, v), base);
-      SC::put_tile(tm, clb + part * ns_max, rtab, lam + off_of(it, v), base);
+      if constexpr (R > 0) {
+        if (WP) RIO::put(cpb + part * ns_max, pos, ns, psi + off_of(it, v), base, tm.tid);
+        RIO::put(clb + part * ns_max, pos, ns, lam + off_of(it, v), base, tm.tid);
+      } else {
+        tm.refresh();
+        if (WP) SC::put_tile(tm, cpb + part * ns_max, rtab, psi + off_of(it, v), base);
+        SC::put_tile(tm, clb + part * ns_max, rtab, lam + off_of(it, v), base);
+      }
     }
   };
   if (!gate.wait(lo_of(item0), hi_of(item0))) return false;
