@@ -356,6 +356,28 @@ def test_30q_largest_state_theta_zero_closed_forms(ucc):
     ctx.close()
 
 
+def test_18q_ragged_batch_grouped_passes(ucc):
+    # 63 entries: the grouped forward pass (four entries per item) ends on a group of three,
+    # the grouped reverse pass (two per item) on a group of one, in both visiting orders
+    say("case: 18q/10e batch 63 energy+grad, short last groups (stored oracle values)")
+    gold = json.load(open(os.path.join(HERE, "golden", "dimer_18q.json")))
+    n, ne = gold["n"], gold["ne"]
+    h1, h2 = make_integrals(n // 2, gold["integral_seed"])
+    exc = uccsd_excitations(n, ne)
+    th = make_thetas(len(exc), gold["theta_seed"], gold["theta_scale"], batch=gold["batch"])[:63]
+    ctx = ucc.Context(n, ne, h1, h2, exc, max_batch=63)
+    info = ctx.plan_info()
+    assert (info["block_threads_fwd"], info["block_threads_rev"]) == (1024, 1024)
+    e, gr = ctx.energy_grad(th)
+    assert np.max(np.abs(e - np.array(gold["energies"][:63]))) <= E_TOL
+    for b, ent in gold["entries"].items():
+        b = int(b)
+        if b < 63:
+            assert abs(e[b] - ent["energy"]) <= E_TOL, b
+            assert np.max(np.abs(gr[b] - np.array(ent["grad"]))) <= G_TOL, b
+    ctx.close()
+
+
 @pytest.mark.parametrize("n,ne,kw", [(12, 8, dict(tile_qubits=8, tile_qubits_rev=8)),
                                      (16, 8, dict(store_states=1)), (16, 8, dict(store_states=2))])
 def test_magnitude_ordered_excitations(ucc, n, ne, kw):

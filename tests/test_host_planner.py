@@ -518,6 +518,21 @@ def test_fusion_depth_caps_the_windows():
             host_ctx(8, 4, fuse_depth=bad)
 
 
+def test_fixed_tuning_takes_grouped_passes_where_the_batch_fills_the_chip():
+    """Without the autotuner, 18 qubits with stored states: a batch that gives every CU at
+    least two items of grouped entries (four forward, two reverse) takes 1024-thread forward and
+    reverse passes (the overlapped, grouped forms); a single vector keeps 512."""
+    n, ne = 18, 10
+    h1, h2 = make_integrals(n // 2, 0)
+    exc = uccsd_excitations(n, ne)
+    for batch, want in ((64, (1024, 1024, 1024)), (1, (512, 1024, 512))):
+        c = ucc.Context(n, ne, h1, h2, exc, host_only=True, max_batch=batch)
+        i = c.plan_info()
+        assert i["store_states"] == 1
+        assert (i["block_threads_fwd"], i["block_threads_exp"], i["block_threads_rev"]) == want, batch
+        c.close()
+
+
 def test_evaluation_graph_plan_and_rejections():
     """launch_mode 3 (the evaluation graph): 512-thread workgroups and tiles of at most 13 qubits
     for every kind, chosen without the autotuner; what the graph cannot take is refused."""
