@@ -953,6 +953,11 @@ def main():
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "avg_launch_ms": avg_ms, "algorithmic_bytes_per_launch": bytes_per_launch,
+                     "bytes_model": "algorithmic bytes: the dense-state pass model (every amplitude "
+                                    "of every tile; a reverse pass reads psi and lambda and writes "
+                                    "lambda, 3 x 16 x 2^n B per vector); the kernels move only the "
+                                    "cache lines holding N/S_z-sector amplitudes, so frac can pass 1; "
+                                    "traffic / traffic_frac are the HBM bytes the counters measured",
                      # the HBM bytes the counters saw, over the same live launch time: the
                      # fraction of peak the kernel really moves (the dense-state model above
                      # counts every amplitude of every tile, the kernels touch only the sector)
